@@ -1,0 +1,169 @@
+"""Oracle: variational two-site fit of W|psi> at bounded bond dimension (complex128).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+One time step (Sec. 2.2, Table 1 "(i)DMRG" row; Sec. 8.2: a variational sweeping optimisation
+of the time-evolved MPS in every step): find the MPS phi with bonds <= Dmax that maximises
+|<phi|W psi>|.  Readings of the paper (which leaves the details open), shared with the device
+path and listed in the design notes:
+  * guess phi = psi, brought to right-canonical form by QR from the last site to the second;
+  * a sweep is a left-to-right pass over the bonds (0,1) .. (L-2,L-1) followed by a
+    right-to-left pass over the same bonds; two sweeps per time step;
+  * at every bond the exact projection Theta of W|psi> onto the current left/right bases is
+    split by an SVD in FP64; k = min(Dmax, #{sigma_i > cutoff * sigma_1}) values are kept
+    (k >= 1); left-to-right: phi_i = U, phi_{i+1} = S V^dag; right-to-left: phi_i = U S,
+    phi_{i+1} = V^dag;
+  * after the last visit phi is normalised; the norm before normalisation is |<phi_hat|W psi>|.
+
+Tensor conventions: MPS site M[a, s, b]; MPO site W[alpha, s_out, s_in, beta]; environments
+E[bra, mpo, ket].  The bra is conjugated inside the environment contractions.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def env_left(Lenv, bra, W, ket):
+    """L'[b', beta, b] = sum conj(bra[a', s', b']) L[a', alpha, a] W[alpha, s', s, beta] ket[a, s, b]."""
+    return np.einsum('xay,xpu,apsb,ysv->ubv', Lenv, bra.conj(), W, ket, optimize=True)
+
+
+def env_right(Renv, bra, W, ket):
+    """R'[a', alpha, a] = sum conj(bra[a', s', b']) W[alpha, s', s, beta] ket[a, s, b] R[b', beta, b]."""
+    return np.einsum('xpu,apsb,ysv,ubv->xay', bra.conj(), W, ket, Renv, optimize=True)
+
+
+def theta_two_site(Lenv, M1, W1, M2, W2, Renv):
+    """Projected two-site tensor Theta[a', s', t', c'] =
+    sum L[a', alpha, a] M1[a, s, b] W1[alpha, s', s, beta] M2[b, t, c] W2[beta, t', t, gamma] R[c', gamma, c]."""
+    return np.einsum('xay,ysb,apsg,btc,gqtz,uzc->xpqu', Lenv, M1, W1, M2, W2, Renv, optimize=True)
+
+
+def svd_truncate(mat, Dmax: int, cutoff: float):
+    """FP64 SVD of a matrix, keeping k = min(Dmax, #{sigma > cutoff * sigma_1}) >= 1 values.
+    Returns U[:, :k], S[:k], Vh[:k], and the discarded weight sum_{i>=k} sigma_i^2 / sum sigma_i^2."""
+    U, S, Vh = np.linalg.svd(mat, full_matrices=False)
+    if S.size == 0:
+        raise ValueError("empty matrix")
+    if S[0] > 0:
+        k = int(np.count_nonzero(S > cutoff * S[0]))
+    else:
+        k = 1
+    k = max(1, min(Dmax, k))
+    tot = float(np.sum(S ** 2))
+    disc = float(np.sum(S[k:] ** 2)) / tot if tot > 0 else 0.0
+    return U[:, :k], S[:k], Vh[:k], disc
+
+
+def right_canonicalize(ms):
+    """Right-canonical copy of an MPS: QR of each site's adjoint from the last site to the second;
+    the triangular factor is absorbed into the site on the left. Bond i becomes
+    min(D_left, d * D_right) where that is smaller."""
+    out = [m.copy() for m in ms]
+    for i in range(len(out) - 1, 0, -1):
+        a, d, b = out[i].shape
+        Q, R = np.linalg.qr(out[i].reshape(a, d * b).conj().T)  # (d b) x k, k x a
+        k = Q.shape[1]
+        out[i] = Q.conj().T.reshape(k, d, b)
+        out[i - 1] = np.einsum('xsa,ka->xsk', out[i - 1], R.conj())
+    return out
+
+
+def boundary_env(w: int):
+    E = np.zeros((1, w, 1), dtype=np.complex128)
+    E[0, 0, 0] = 1.0
+    return E
+
+
+def fit_step(psi, Ws, Dmax: int, nsweeps: int = 2, cutoff: float = 1e-14):
+    """One time step: variational two-site fit of W|psi> at bonds <= Dmax (module docstring).
+
+    psi: list of L site tensors; Ws: one MPO tensor or a list of L; returns (phi, stats) with phi
+    normalised (unless W|psi> projects to zero) and stats = dict(norm, discarded (per visit),
+    bond_dims)."""
+    L = len(psi)
+    if not isinstance(Ws, (list, tuple)):
+        Ws = [Ws] * L
+    if L == 1:
+        phi0 = np.einsum('apsb,xsy->xpy', Ws[0][:1, :, :, :1], psi[0])  # boundary level 0 in and out
+        n = np.linalg.norm(phi0)
+        return [phi0 / n if n > 0 else phi0], dict(norm=float(n), discarded=[], bond_dims=[1, 1])
+    phi = right_canonicalize(psi)
+    Lenv = [None] * (L + 1)
+    Renv = [None] * (L + 1)
+    Lenv[0] = boundary_env(Ws[0].shape[0])
+    Renv[L] = boundary_env(Ws[-1].shape[3])
+    for i in range(L - 1, 1, -1):
+        Renv[i] = env_right(Renv[i + 1], phi[i], Ws[i], psi[i])
+    discarded = []
+    S = None
+    for _ in range(nsweeps):
+        for i in range(0, L - 1):  # left to right
+            th = theta_two_site(Lenv[i], psi[i], Ws[i], psi[i + 1], Ws[i + 1], Renv[i + 2])
+            a, p, q, c = th.shape
+            U, S, Vh, disc = svd_truncate(th.reshape(a * p, q * c), Dmax, cutoff)
+            discarded.append(disc)
+            k = S.size
+            phi[i] = U.reshape(a, p, k)
+            phi[i + 1] = (S[:, None] * Vh).reshape(k, q, c)
+            if i < L - 2:
+                Lenv[i + 1] = env_left(Lenv[i], phi[i], Ws[i], psi[i])
+        for i in range(L - 2, -1, -1):  # right to left
+            th = theta_two_site(Lenv[i], psi[i], Ws[i], psi[i + 1], Ws[i + 1], Renv[i + 2])
+            a, p, q, c = th.shape
+            U, S, Vh, disc = svd_truncate(th.reshape(a * p, q * c), Dmax, cutoff)
+            discarded.append(disc)
+            k = S.size
+            phi[i] = (U * S[None, :]).reshape(a, p, k)
+            phi[i + 1] = Vh.reshape(k, q, c)
+            if i > 0:
+                Renv[i + 1] = env_right(Renv[i + 2], phi[i + 1], Ws[i + 1], psi[i + 1])
+    norm = float(np.linalg.norm(S))
+    if norm > 0:
+        phi[0] = phi[0] / norm
+    dims = [1] + [phi[i].shape[2] for i in range(L)]
+    return phi, dict(norm=norm, discarded=discarded, bond_dims=dims)
+
+
+def overlap(bra, ket) -> complex:
+    """<bra|ket> of two open-boundary MPS (transfer-matrix contraction)."""
+    E = np.ones((1, 1), dtype=np.complex128)
+    for A, B in zip(bra, ket):
+        E = np.einsum('xy,xsu,ysv->uv', E, A.conj(), B, optimize=True)
+    return complex(E[0, 0])
+
+
+def norm(ms) -> float:
+    return float(np.sqrt(abs(overlap(ms, ms))))
+
+
+def expect_local(ms, op, site: int) -> complex:
+    """<psi| op_site |psi> / <psi|psi>."""
+    E = np.ones((1, 1), dtype=np.complex128)
+    for j, A in enumerate(ms):
+        if j == site:
+            E = np.einsum('xy,xpu,pq,yqv->uv', E, A.conj(), op, A, optimize=True)
+        else:
+            E = np.einsum('xy,xsu,ysv->uv', E, A.conj(), A, optimize=True)
+    return complex(E[0, 0]) / overlap(ms, ms)
+
+
+def mpo_expectation(ms, Wsites, left, right) -> complex:
+    """<psi| O |psi> for an MPO O = l . W_1 ... W_L . r."""
+    E = np.einsum('a,xy->xay', left, np.ones((1, 1), dtype=np.complex128))
+    for A, W in zip(ms, Wsites):
+        E = env_left(E, A, W, A)
+    return complex(np.einsum('xay,a->', E, right))
+
+
+def applied_norm2(psi, Ws) -> float:
+    """||W psi||^2 = <psi| W^dag W |psi> through a double-layer environment."""
+    L = len(psi)
+    if not isinstance(Ws, (list, tuple)):
+        Ws = [Ws] * L
+    w = Ws[0].shape[0]
+    E = np.zeros((1, w, w, 1), dtype=np.complex128)
+    E[0, 0, 0, 0] = 1.0  # [bra, mpo(dag), mpo, ket]; boundary level 0 on both MPO layers
+    for A, W in zip(psi, Ws):
+        E = np.einsum('xqay,xsu,qpsr,aptb,ytv->urbv', E, A.conj(), W.conj(), W, A, optimize=True)
+    return float(E[0, 0, 0, 0].real)

@@ -1,0 +1,167 @@
+"""Pins of the oracle's MPO construction against the paper's printed worked examples.
+
+Every fixture under tests/golden/ transcribes one printed table (Sec. 2.5, Sec. 3, Sec. 4,
+Sec. 5, Sec. 6, Appendix A) in a small text syntax. With chi = 1 and random complex
+non-commuting d x d blocks A, B, C, D, every block of the oracle's level matrix must equal
+the printed formula (and every unlisted block must vanish). A dropped term, a wrong sign, a
+wrong weight or a transposed product changes at least one entry.
+"""
+import glob
+import itertools
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import mpo
+from paper_2302_14181_amd.workloads import JordanBlocks
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+D_PHYS = 3
+TAU = 0.37 + 0.21j
+
+
+def _blocks(seed=11):
+    rng = np.random.default_rng(seed)
+    cn = lambda *s: (rng.standard_normal(s) + 1j * rng.standard_normal(s)) / np.sqrt(2)
+    mats = {k: cn(D_PHYS, D_PHYS) for k in "ABCD"}
+    H = JordanBlocks(A=mats["A"][None, None], B=mats["B"][None], C=mats["C"][None], Dloc=mats["D"])
+    mats["I"] = np.eye(D_PHYS, dtype=np.complex128)
+    return H, mats
+
+
+def _word(word, mats):
+    if word.startswith("{"):
+        letters = word.strip("{}")
+        perms = sorted(set(itertools.permutations(letters)))
+        return sum(_word("".join(p), mats) for p in perms)
+    out = np.eye(D_PHYS, dtype=np.complex128)
+    for ch in word:
+        out = out @ mats[ch]
+    return out
+
+
+def _expr(text, mats, tau):
+    total = np.zeros((D_PHYS, D_PHYS), dtype=np.complex128)
+    for term in text.replace(" - ", " + -").split(" + "):
+        term = term.strip()
+        sign = 1
+        if term.startswith("-"):
+            sign, term = -1, term[1:].strip()
+        coef, power, word = Fraction(1), 0, None
+        for tok in term.split():
+            if re.fullmatch(r"\d+(/\d+)?", tok):
+                coef *= Fraction(tok)
+            elif tok == "t":
+                power += 1
+            elif tok.startswith("t^"):
+                power += int(tok[2:])
+            else:
+                assert word is None, f"two words in term {term!r}"
+                word = tok
+        total += sign * float(coef) * tau ** power * _word(word, mats)
+    return total
+
+
+def _parse_level(s):
+    return tuple(int(x) for x in s.strip("()").split(","))
+
+
+def _load(path):
+    meta, entries = {}, {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        m = re.match(r"^(\([\d,]+\))\s+(\([\d,]+\)):\s*(.*)$", line)
+        if m:
+            entries[(_parse_level(m.group(1)), _parse_level(m.group(2)))] = m.group(3)
+            continue
+        key, val = line.split(":", 1)
+        meta[key.strip()] = val.strip()
+    meta["levels"] = [_parse_level(x) for x in meta["levels"].split()]
+    meta["order"] = int(meta["order"])
+    return meta, entries
+
+
+def _stage(stage, H, N, tau):
+    P = mpo.hamiltonian_power(H, N)
+    if stage == "power":
+        return P
+    if stage in ("alg1", "basis_transform"):
+        O = mpo.fold(P, tau)
+        if stage == "alg1":
+            return O
+        return _basis_transform(O)
+    if stage == "v1":
+        return mpo.exact_compress(mpo.fold(P, tau))
+    ext = mpo.exact_compress(mpo.fold(mpo.extend(P, H, tau), tau))
+    if stage == "extended":
+        return ext
+    if stage == "v2":
+        return mpo.approx_compress(ext, tau)
+    raise ValueError(stage)
+
+
+def _basis_transform(O):
+    """S O S^-1 with S = [[1, 1], [1, -1]] on the ((1,2), (2,1)) levels, identity elsewhere."""
+    p, q = (1, 2), (2, 1)
+    S = {(p, p): 1.0, (p, q): 1.0, (q, p): 1.0, (q, q): -1.0}
+    Sinv = {k: 0.5 * v for k, v in S.items()}
+
+    def coeff(mat, r, c):
+        if r in (p, q) or c in (p, q):
+            return mat.get((r, c), 0.0)
+        return 1.0 if r == c else 0.0
+
+    out = mpo.LevelMatrix(O.N, O.chi, O.d)
+    out.levels = list(O.levels)
+    for r in O.levels:
+        for c in O.levels:
+            acc = None
+            for x in O.levels:
+                sx = coeff(S, r, x) if (r in (p, q) or x in (p, q)) else (1.0 if r == x else 0.0)
+                if sx == 0.0:
+                    continue
+                for y in O.levels:
+                    blk = O.get(x, y)
+                    if blk is None:
+                        continue
+                    sy = coeff(Sinv, y, c) if (y in (p, q) or c in (p, q)) else (1.0 if y == c else 0.0)
+                    if sy == 0.0:
+                        continue
+                    term = sx * sy * blk
+                    acc = term if acc is None else acc + term
+            if acc is not None and np.max(np.abs(acc)) > 0:
+                out.blocks[(r, c)] = acc
+    return out
+
+
+FIXTURES = sorted(glob.glob(os.path.join(GOLDEN, "*.txt")))
+
+
+@pytest.mark.parametrize("path", FIXTURES, ids=[os.path.basename(p) for p in FIXTURES])
+def test_printed_table(path):
+    meta, entries = _load(path)
+    H, mats = _blocks()
+    O = _stage(meta["stage"], H, meta["order"], TAU)
+    assert sorted(O.levels) == sorted(meta["levels"]), "set of levels differs from the printed table"
+    scale = 1.0
+    for r in O.levels:
+        for c in O.levels:
+            blk = O.get(r, c)
+            got = np.zeros((D_PHYS, D_PHYS), dtype=np.complex128) if blk is None else blk[0, :, :, 0]
+            want = _expr(entries[(r, c)], mats, TAU) if (r, c) in entries else np.zeros_like(got)
+            err = np.max(np.abs(got - want))
+            assert err <= 1e-13 * max(scale, np.max(np.abs(want))), f"entry {r} -> {c}: |diff| = {err:.3e}"
+
+
+def test_fixture_parser_rejects_wrong_formula():
+    """The comparison is sensitive: a transposed product or a wrong weight is detected."""
+    H, mats = _blocks()
+    good = _expr("1/2 t^2 DB", mats, TAU)
+    assert np.max(np.abs(good - _expr("1/2 t^2 BD", mats, TAU))) > 1e-3
+    assert np.max(np.abs(good - _expr("1/3 t^2 DB", mats, TAU))) > 1e-3
+    assert np.max(np.abs(_expr("{ABB}", mats, TAU) - (mats["A"] @ mats["B"] @ mats["B"] + mats["B"] @ mats["A"] @ mats["B"] + mats["B"] @ mats["B"] @ mats["A"]))) < 1e-12
