@@ -1,0 +1,214 @@
+/*
+ * mpoevo: higher-order MPO time evolution on MI355X (gfx950).
+ *
+ * C ABI of the library libmpoevo.so. The method is that of "Efficient higher-order matrix
+ * product operators for time evolution" (Van Damme, Haegeman, McCulloch, Vanderstraeten):
+ *   - mpo_build   builds the order-N MPO approximation of exp(tau H) from the Jordan blocks of a
+ *                 first-degree Hamiltonian MPO (Sec. 2.3, Sec. 3 Alg. 1, Sec. 4 Alg. 2,
+ *                 Sec. 5 Alg. 3, Sec. 6 Alg. 4, boundary vectors of Sec. 3);
+ *   - env_update, local_apply, truncate are the three device operations of the variational
+ *                 fit of W|psi> at fixed maximal bond dimension (Sec. 2.2 and Table 1, the
+ *                 sweeping (DMRG-like) scheme used in every benchmark of Sec. 8);
+ *   - step        runs one complete time step of that fit (two-site updates, two sweeps).
+ *
+ * Conventions for every array argument:
+ *   - complex numbers are interleaved {re, im}: complex128 = 2 x double, complex64 = 2 x float;
+ *   - arrays are row-major, last index fastest;
+ *   - MPS site tensor M[a][s][b] (left bond, physical, right bond);
+ *   - MPO site tensor W[alpha][s_out][s_in][beta];
+ *   - environment E[bra][mpo][ket]; the bra tensor is conjugated inside the contractions.
+ * Precision: MPOEVO_FP64 contracts in double (complex128 inputs/outputs); MPOEVO_FP32 contracts
+ * in float on the matrix cores with float accumulation (complex64 inputs/outputs). The SVD,
+ * the truncation and all norms are FP64 in both modes.
+ *
+ * Ownership: the caller allocates every input, output and workspace buffer; the library never
+ * frees or reallocates them. A handle owns only its own small bookkeeping (error text, device
+ * id, a few device flags). Device calls are asynchronous on the given stream (hipStream_t,
+ * passed as void*; NULL = the default stream) unless stated otherwise. A handle is not
+ * thread-safe: use one per host thread.
+ *
+ * Errors: every call returns MPOEVO_OK (0) or a negative status; nothing is thrown across the
+ * ABI. mpoevo_last_error(h) returns the text of the last error of that handle (never NULL;
+ * with h == NULL the last error of the calling thread's handle-free calls).
+ */
+#ifndef MPOEVO_H
+#define MPOEVO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpoevo_ctx* mpoevo_handle;
+
+enum {
+  MPOEVO_OK = 0,
+  MPOEVO_EINVAL = -1,       /* bad argument: null pointer, unknown enum, order out of range */
+  MPOEVO_ESHAPE = -2,       /* inconsistent or unsupported dimensions */
+  MPOEVO_ENOMEM = -3,       /* workspace (or output capacity) too small */
+  MPOEVO_EHIP = -4,         /* a HIP runtime call failed */
+  MPOEVO_ESOLVER = -5,      /* the FP64 SVD did not converge or a device wait timed out */
+  MPOEVO_ENONFINITE = -6,   /* non-finite input (H blocks, tau) or non-finite matrix in truncate */
+  MPOEVO_EUNSUPPORTED = -7  /* valid request this build does not implement */
+};
+
+enum { MPOEVO_FP64 = 0, MPOEVO_FP32 = 1 };
+enum { MPOEVO_V1_EXACT = 0, MPOEVO_V2_EXTENDED = 1 };
+enum { MPOEVO_LEFT = 0, MPOEVO_RIGHT = 1 };
+
+/* Handle on HIP device `device` (made current by every call that uses it). */
+int mpoevo_create(mpoevo_handle* h, int device);
+int mpoevo_destroy(mpoevo_handle h);
+const char* mpoevo_last_error(mpoevo_handle h);
+const char* mpoevo_version(void);
+
+/*
+ * mpo_build -- HOST ONLY, synchronous, thread-safe.
+ * Order-N MPO for exp(tau H) (Sec. 3 Alg. 1; with variant V2 also Sec. 5 Alg. 3 on H^N before
+ * the fold and Sec. 6 Alg. 4 after Sec. 4 Alg. 2).
+ *   d, chi      physical dimension and the dimension of the middle level of H (Sec. 2.3).
+ *   A, B, C, D  complex128 Jordan blocks of H = [[I, C, D], [0, A, B], [0, 0, I]]:
+ *               A[chi][chi][d][d], B[chi][d][d], C[chi][d][d], D[d][d] (D is "Dloc").
+ *   order       1..4;  tau_re, tau_im: the complex step (tau = -i dt for exp(-i dt H)).
+ *   variant     MPOEVO_V1_EXACT (Alg. 1 + Alg. 2) or MPOEVO_V2_EXTENDED (Alg. 3, 1, 2, 4).
+ *   inner_charge[chi], phys_charge[d]: optional U(1) charges (both NULL or both set).
+ *   *w_out      receives the MPO bond dimension w.
+ *   W_out       complex128 W[w][d][d][w] or NULL (size query: only *w_out is written);
+ *               W_capacity = number of complex entries available at W_out.
+ *   level_charge_out[w]: optional (needs the charges); charge of every MPO bond index.
+ * Level (1,...,1) is bond index 0; the boundary vectors of a finite chain are l = r = e_0.
+ * Errors: EINVAL (null blocks, order outside 1..4, bad variant), ENONFINITE (non-finite block
+ * entry or tau), ENOMEM (W_capacity < w*d*d*w).
+ */
+int mpo_build(int d, int chi, const double* A, const double* B, const double* C, const double* D,
+              int order, double tau_re, double tau_im, int variant,
+              const int* inner_charge, const int* phys_charge,
+              int* w_out, double* W_out, size_t W_capacity, int* level_charge_out);
+
+/*
+ * Dimensions of one site of the fit (shared by env_update and the workspace query):
+ *   dims[0] Dbra_l, dims[1] Dket_l, dims[2] Dbra_r, dims[3] Dket_r, dims[4] d, dims[5] w_l,
+ *   dims[6] w_r.  bra[Dbra_l][d][Dbra_r], ket[Dket_l][d][Dket_r], W[w_l][d][d][w_r].
+ */
+
+/*
+ * env_update -- DEVICE, async on `stream`.
+ * One environment step of the sweep (Sec. 2.2; cost O(w d D^3) of Table 1):
+ *   side LEFT :  E_out[b'][beta][b]  = sum conj(bra[a'][s'][b']) E_in[a'][alpha][a]
+ *                                          W[alpha][s'][s][beta] ket[a][s][b]
+ *                E_in (Dbra_l, w_l, Dket_l) -> E_out (Dbra_r, w_r, Dket_r)
+ *   side RIGHT:  E_out[a'][alpha][a] = sum conj(bra[a'][s'][b']) W[alpha][s'][s][beta]
+ *                                          ket[a][s][b] E_in[b'][beta][b]
+ *                E_in (Dbra_r, w_r, Dket_r) -> E_out (Dbra_l, w_l, Dket_l)
+ * All tensors complex128 (prec FP64) or complex64 (prec FP32), device pointers. E_out must not
+ * alias an input. Workspace: mpoevo_workspace_size(MPOEVO_CALL_ENV_UPDATE, ...).
+ * Errors: EINVAL, ESHAPE (non-positive dims), ENOMEM (workspace too small), EHIP.
+ */
+int env_update(mpoevo_handle h, int side, int prec, const void* E_in, const void* bra,
+               const void* W, const void* ket, void* E_out, const int* dims,
+               void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * local_apply -- DEVICE, async on `stream`.
+ * Projected two-site tensor of the fit at bond (i, i+1) (the optimal two-site update):
+ *   Theta[a'][s'][t'][c'] = sum L[a'][alpha][a] M1[a][s][b] W1[alpha][s'][s][beta]
+ *                               M2[b][t][c] W2[beta][t'][t][gamma] R[c'][gamma][c]
+ * nsites must be 2. dims: [0] Dbra_l, [1] Dket_l, [2] Dket_m, [3] Dket_r, [4] Dbra_r, [5] d,
+ * [6] w_l, [7] w_m, [8] w_r.  L (Dbra_l, w_l, Dket_l), M1 (Dket_l, d, Dket_m),
+ * W1 (w_l, d, d, w_m), M2 (Dket_m, d, Dket_r), W2 (w_m, d, d, w_r), R (Dbra_r, w_r, Dket_r).
+ * Inputs complex128 (FP64) or complex64 (FP32); Theta is ALWAYS complex128 (the FP32 path
+ * accumulates in float and widens on store), shaped (Dbra_l*d) x (d*Dbra_r).
+ * Errors: EINVAL, ESHAPE, ENOMEM, EHIP.
+ */
+int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void* W1,
+                const void* W2, const void* M1, const void* M2, const void* R, void* Theta,
+                const int* dims, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * truncate -- DEVICE, async on `stream`. FP64 SVD Theta = U S V^dag of an m x n complex128
+ * matrix (row-major) by one-sided Jacobi, keeping k = min(Dmax, m, n, #{sigma_i > cutoff *
+ * sigma_1}) >= 1 singular values (the truncation of the two-site update).
+ *   direction LEFT  (left-to-right sweep): A_out = U_k (left-orthonormal), B_out = S_k V_k^dag
+ *   direction RIGHT (right-to-left sweep): A_out = U_k S_k, B_out = V_k^dag (right-orthonormal)
+ * Outputs have the static capacity kcap = min(Dmax, m, n): A_out is m x kcap, B_out is kcap x n
+ * (complex128, row-major); columns of A_out and rows of B_out at index >= k are zero.
+ * k_dev (int), discarded_dev (double: sum_{i>=k} sigma_i^2 / sum sigma_i^2) and norm_dev
+ * (double: ||S_k||) are DEVICE scalars (nullable); sigma_dev (double[min(m,n)], descending,
+ * nullable). Theta is not modified. If the SVD does not converge within its sweep limit the
+ * result is still written and *k_dev is negated (status is only visible on the device, or
+ * through mpoevo_check_solver after a stream synchronisation).
+ * Errors: EINVAL, ESHAPE (m or n outside 1..MPOEVO_SVD_MAX_DIM), ENOMEM, EHIP.
+ */
+#define MPOEVO_SVD_MAX_DIM 1024
+int truncate(mpoevo_handle h, const void* Theta, int m, int n, int Dmax, double cutoff,
+             int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
+             double* norm_dev, double* sigma_dev, void* workspace, size_t workspace_bytes,
+             void* stream);
+
+/* After a stream synchronisation: MPOEVO_OK, or ESOLVER if any truncate/step issued on this
+ * handle since the previous check did not converge (flag kept in device memory of the handle). */
+int mpoevo_check_solver(mpoevo_handle h);
+
+/*
+ * step -- one time step (Sec. 8.2: a variational sweeping optimisation of the time-evolved MPS
+ * in every step): the MPS psi is replaced by the normalised two-site variational fit of W|psi>
+ * with bonds <= Dmax.  Guess phi = psi brought to right-canonical form (FP64 SVD of each site
+ * from the last to the second; skipped if opts->input_right_canonical), then opts->nsweeps
+ * sweeps, each a left-to-right pass over the bonds (0,1)..(L-2,L-1) and a right-to-left pass
+ * over the same bonds; at every bond the projected two-site tensor is split by `truncate`.
+ * Synchronises `stream` once at the end (bond dimensions and statistics are read back).
+ *   mps   psi on entry, phi on exit. site[i] is a device pointer to complex128
+ *         [bond_dim[i]][d][bond_dim[i+1]] with capacity Dmax*d*Dmax entries; bond_dim (host,
+ *         L+1 entries, bond_dim[0] = bond_dim[L] = 1) is updated in place.
+ *   mpo   per-site complex128 W_i[w[i]][d][d][w[i+1]] (device); boundaries e_0 on bonds 0, L.
+ *   opts  nsweeps in 1..4, prec, cutoff (relative singular value cutoff, e.g. 1e-14),
+ *         input_right_canonical (1: psi is already right-canonical, skip the guess SVDs).
+ *   stats nullable; filled after the synchronisation.
+ * Workspace: mpoevo_workspace_size(MPOEVO_CALL_STEP, dims = {L, d, Dmax, wmax}, prec).
+ * Errors: EINVAL, ESHAPE (L < 2, Dmax < 1, Dmax > MPOEVO_SVD_MAX_DIM/d), ENOMEM, EHIP,
+ * ESOLVER (an SVD did not converge), ENONFINITE (the fitted norm is not finite).
+ */
+typedef struct {
+  int L, d, Dmax;
+  int* bond_dim;
+  void** site;
+} mpoevo_mps;
+
+typedef struct {
+  int L, d;
+  const int* w;
+  const void* const* site;
+} mpoevo_mpo;
+
+typedef struct {
+  int nsweeps;
+  int prec;
+  double cutoff;
+  int input_right_canonical;
+} mpoevo_step_opts;
+
+typedef struct {
+  double norm;              /* |<phi_hat|W psi>| = ||S|| at the last bond visit */
+  double discarded_max;     /* largest discarded weight of any bond visit */
+  double discarded_sum;     /* sum over the bond visits of the discarded weights */
+  int visits;               /* number of bond visits (4 (L-1) for two sweeps) */
+  int max_bond;             /* largest bond dimension of the result */
+  double gflop;             /* algorithmic contraction work of the step (8 flop per complex MAC) */
+} mpoevo_step_stats;
+
+int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
+         mpoevo_step_stats* stats, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace sizes in bytes for the device calls (dims as documented for each call). */
+enum { MPOEVO_CALL_ENV_UPDATE = 0, MPOEVO_CALL_LOCAL_APPLY = 1, MPOEVO_CALL_TRUNCATE = 2,
+       MPOEVO_CALL_STEP = 3 };
+/* dims: ENV_UPDATE -> the 7 env_update dims; LOCAL_APPLY -> the 9 local_apply dims;
+ * TRUNCATE -> {m, n}; STEP -> {L, d, Dmax, wmax}. */
+int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPOEVO_H */

@@ -24,19 +24,33 @@ import numpy as np
 
 
 def env_left(Lenv, bra, W, ket):
-    """L'[b', beta, b] = sum conj(bra[a', s', b']) L[a', alpha, a] W[alpha, s', s, beta] ket[a, s, b]."""
-    return np.einsum('xay,xpu,apsb,ysv->ubv', Lenv, bra.conj(), W, ket, optimize=True)
+    """L'[b', beta, b] = sum conj(bra[a', s', b']) L[a', alpha, a] W[alpha, s', s, beta] ket[a, s, b],
+    evaluated as three pairwise contractions (sum over a, then over alpha and s, then a' and s')."""
+    T = np.tensordot(Lenv, ket, axes=([2], [0]))             # [a', alpha, s, b]
+    T = np.tensordot(T, W, axes=([1, 2], [0, 2]))             # [a', b, s', beta]
+    T = np.tensordot(bra.conj(), T, axes=([0, 1], [0, 2]))    # [b', b, beta]
+    return np.ascontiguousarray(T.transpose(0, 2, 1))
 
 
 def env_right(Renv, bra, W, ket):
-    """R'[a', alpha, a] = sum conj(bra[a', s', b']) W[alpha, s', s, beta] ket[a, s, b] R[b', beta, b]."""
-    return np.einsum('xpu,apsb,ysv,ubv->xay', bra.conj(), W, ket, Renv, optimize=True)
+    """R'[a', alpha, a] = sum conj(bra[a', s', b']) W[alpha, s', s, beta] ket[a, s, b] R[b', beta, b],
+    evaluated as three pairwise contractions (sum over b, then over s and beta, then s' and b')."""
+    T = np.tensordot(ket, Renv, axes=([2], [2]))              # [a, s, b', beta]
+    T = np.tensordot(T, W, axes=([1, 3], [2, 3]))             # [a, b', alpha, s']
+    T = np.tensordot(bra.conj(), T, axes=([1, 2], [3, 1]))    # [a', a, alpha]
+    return np.ascontiguousarray(T.transpose(0, 2, 1))
 
 
 def theta_two_site(Lenv, M1, W1, M2, W2, Renv):
     """Projected two-site tensor Theta[a', s', t', c'] =
-    sum L[a', alpha, a] M1[a, s, b] W1[alpha, s', s, beta] M2[b, t, c] W2[beta, t', t, gamma] R[c', gamma, c]."""
-    return np.einsum('xay,ysb,apsg,btc,gqtz,uzc->xpqu', Lenv, M1, W1, M2, W2, Renv, optimize=True)
+    sum L[a', alpha, a] M1[a, s, b] W1[alpha, s', s, beta] M2[b, t, c] W2[beta, t', t, gamma] R[c', gamma, c],
+    evaluated as the left half (L M1 W1), the right half (M2 W2 R) and their contraction over b, beta."""
+    left = np.tensordot(Lenv, M1, axes=([2], [0]))            # [a', alpha, s, b]
+    left = np.tensordot(left, W1, axes=([1, 2], [0, 2]))      # [a', b, s', beta]
+    right = np.tensordot(M2, Renv, axes=([2], [2]))           # [b, t, c', gamma]
+    right = np.tensordot(right, W2, axes=([1, 3], [2, 3]))    # [b, c', beta, t']
+    th = np.tensordot(left, right, axes=([1, 3], [0, 2]))     # [a', s', c', t']
+    return np.ascontiguousarray(th.transpose(0, 1, 3, 2))
 
 
 def svd_truncate(mat, Dmax: int, cutoff: float):
@@ -129,7 +143,8 @@ def overlap(bra, ket) -> complex:
     """<bra|ket> of two open-boundary MPS (transfer-matrix contraction)."""
     E = np.ones((1, 1), dtype=np.complex128)
     for A, B in zip(bra, ket):
-        E = np.einsum('xy,xsu,ysv->uv', E, A.conj(), B, optimize=True)
+        E = np.tensordot(E, A.conj(), axes=([0], [0]))        # [y, s, u]
+        E = np.tensordot(E, B, axes=([0, 1], [0, 1]))         # [u, v]
     return complex(E[0, 0])
 
 
@@ -141,10 +156,9 @@ def expect_local(ms, op, site: int) -> complex:
     """<psi| op_site |psi> / <psi|psi>."""
     E = np.ones((1, 1), dtype=np.complex128)
     for j, A in enumerate(ms):
-        if j == site:
-            E = np.einsum('xy,xpu,pq,yqv->uv', E, A.conj(), op, A, optimize=True)
-        else:
-            E = np.einsum('xy,xsu,ysv->uv', E, A.conj(), A, optimize=True)
+        B = np.tensordot(op, A, axes=([1], [1])).transpose(1, 0, 2) if j == site else A
+        E = np.tensordot(E, A.conj(), axes=([0], [0]))
+        E = np.tensordot(E, B, axes=([0, 1], [0, 1]))
     return complex(E[0, 0]) / overlap(ms, ms)
 
 
@@ -157,13 +171,18 @@ def mpo_expectation(ms, Wsites, left, right) -> complex:
 
 
 def applied_norm2(psi, Ws) -> float:
-    """||W psi||^2 = <psi| W^dag W |psi> through a double-layer environment."""
+    """||W psi||^2 = <psi| W^dag W |psi> through a double-layer environment
+    E[bra, mpo (conjugated layer), mpo, ket]; boundary level 0 on both MPO layers."""
     L = len(psi)
     if not isinstance(Ws, (list, tuple)):
         Ws = [Ws] * L
     w = Ws[0].shape[0]
     E = np.zeros((1, w, w, 1), dtype=np.complex128)
-    E[0, 0, 0, 0] = 1.0  # [bra, mpo(dag), mpo, ket]; boundary level 0 on both MPO layers
+    E[0, 0, 0, 0] = 1.0
     for A, W in zip(psi, Ws):
-        E = np.einsum('xqay,xsu,qpsr,aptb,ytv->urbv', E, A.conj(), W.conj(), W, A, optimize=True)
+        T = np.tensordot(E, A, axes=([3], [0]))                    # [x, q, a, t, v]
+        T = np.tensordot(T, W, axes=([2, 3], [0, 2]))              # [x, q, v, p, b]
+        T = np.tensordot(T, W.conj(), axes=([1, 3], [0, 1]))       # [x, v, b, s, r]
+        E = np.tensordot(A.conj(), T, axes=([0, 1], [0, 3]))       # [u, v, b, r]
+        E = E.transpose(0, 3, 2, 1)
     return float(E[0, 0, 0, 0].real)

@@ -1,0 +1,175 @@
+// C ABI of libmpoevo.so: argument validation, error text, dispatch to the device layer.
+// This translation unit includes no HIP or POSIX headers (the ABI exports a function named
+// `truncate`, which must not meet the libc declaration of the same name).
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+thread_local std::string g_thread_err;
+
+int fail(mpoevo::Context* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_thread_err = msg;
+  return code;
+}
+}  // namespace
+
+extern "C" {
+
+const char* mpoevo_version(void) { return "mpoevo 0.1 (gfx950)"; }
+
+int mpoevo_create(mpoevo_handle* h, int device) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_create: h is NULL");
+  *h = nullptr;
+  auto* ctx = new (std::nothrow) mpoevo::Context();
+  if (!ctx) return fail(nullptr, MPOEVO_ENOMEM, "mpoevo_create: out of host memory");
+  ctx->device = device;
+  const int rc = mpoevo::device_init(*ctx);
+  if (rc != MPOEVO_OK) {
+    g_thread_err = ctx->err;
+    delete ctx;
+    return rc;
+  }
+  *h = reinterpret_cast<mpoevo_handle>(ctx);
+  return MPOEVO_OK;
+}
+
+int mpoevo_destroy(mpoevo_handle h) {
+  if (!h) return MPOEVO_OK;
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  mpoevo::device_fini(*ctx);
+  delete ctx;
+  return MPOEVO_OK;
+}
+
+const char* mpoevo_last_error(mpoevo_handle h) {
+  if (!h) return g_thread_err.c_str();
+  return reinterpret_cast<mpoevo::Context*>(h)->err.c_str();
+}
+
+int mpo_build(int d, int chi, const double* A, const double* B, const double* C, const double* D,
+              int order, double tau_re, double tau_im, int variant, const int* inner_charge,
+              const int* phys_charge, int* w_out, double* W_out, size_t W_capacity,
+              int* level_charge_out) {
+  std::string err;
+  const int rc = mpoevo::build_mpo_host(d, chi, A, B, C, D, order, tau_re, tau_im, variant,
+                                        inner_charge, phys_charge, w_out, W_out, W_capacity,
+                                        level_charge_out, err);
+  if (rc != MPOEVO_OK) g_thread_err = err;
+  return rc;
+}
+
+int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes) {
+  if (!dims || !bytes) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_workspace_size: NULL argument");
+  if (prec != MPOEVO_FP64 && prec != MPOEVO_FP32) return fail(nullptr, MPOEVO_EINVAL, "unknown precision");
+  switch (call_id) {
+    case MPOEVO_CALL_ENV_UPDATE:
+      for (int i = 0; i < 7; ++i) if (dims[i] < 1) return fail(nullptr, MPOEVO_ESHAPE, "non-positive dimension");
+      *bytes = mpoevo::env_update_ws(dims, prec);
+      return MPOEVO_OK;
+    case MPOEVO_CALL_LOCAL_APPLY:
+      for (int i = 0; i < 9; ++i) if (dims[i] < 1) return fail(nullptr, MPOEVO_ESHAPE, "non-positive dimension");
+      *bytes = mpoevo::local_apply_ws(dims, prec);
+      return MPOEVO_OK;
+    case MPOEVO_CALL_TRUNCATE:
+      if (dims[0] < 1 || dims[1] < 1 || dims[0] > MPOEVO_SVD_MAX_DIM || dims[1] > MPOEVO_SVD_MAX_DIM)
+        return fail(nullptr, MPOEVO_ESHAPE, "truncate: m, n must be in 1..MPOEVO_SVD_MAX_DIM");
+      *bytes = mpoevo::truncate_ws(dims[0], dims[1]);
+      return MPOEVO_OK;
+    case MPOEVO_CALL_STEP:
+      if (dims[0] < 2 || dims[1] < 1 || dims[2] < 1 || dims[3] < 1)
+        return fail(nullptr, MPOEVO_ESHAPE, "step: need L >= 2, d, Dmax, wmax >= 1");
+      if ((long)dims[1] * dims[2] > MPOEVO_SVD_MAX_DIM)
+        return fail(nullptr, MPOEVO_ESHAPE, "step: d * Dmax exceeds MPOEVO_SVD_MAX_DIM");
+      *bytes = mpoevo::step_ws(dims[0], dims[1], dims[2], dims[3], prec);
+      return MPOEVO_OK;
+    default:
+      return fail(nullptr, MPOEVO_EINVAL, "mpoevo_workspace_size: unknown call id");
+  }
+}
+
+int env_update(mpoevo_handle h, int side, int prec, const void* E_in, const void* bra,
+               const void* W, const void* ket, void* E_out, const int* dims, void* workspace,
+               size_t workspace_bytes, void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "env_update: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (side != MPOEVO_LEFT && side != MPOEVO_RIGHT) return fail(ctx, MPOEVO_EINVAL, "env_update: unknown side");
+  if (prec != MPOEVO_FP64 && prec != MPOEVO_FP32) return fail(ctx, MPOEVO_EINVAL, "env_update: unknown precision");
+  if (!E_in || !bra || !W || !ket || !E_out || !dims) return fail(ctx, MPOEVO_EINVAL, "env_update: NULL pointer");
+  for (int i = 0; i < 7; ++i) if (dims[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "env_update: non-positive dimension");
+  if (workspace_bytes < mpoevo::env_update_ws(dims, prec) || (!workspace && workspace_bytes))
+    return fail(ctx, MPOEVO_ENOMEM, "env_update: workspace too small");
+  return mpoevo::env_update_dev(*ctx, side, prec, E_in, bra, W, ket, E_out, dims, workspace,
+                                workspace_bytes, stream);
+}
+
+int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void* W1,
+                const void* W2, const void* M1, const void* M2, const void* R, void* Theta,
+                const int* dims, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "local_apply: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (nsites != 2) return fail(ctx, MPOEVO_EUNSUPPORTED, "local_apply: only the two-site tensor is built");
+  if (prec != MPOEVO_FP64 && prec != MPOEVO_FP32) return fail(ctx, MPOEVO_EINVAL, "local_apply: unknown precision");
+  if (!L || !W1 || !W2 || !M1 || !M2 || !R || !Theta || !dims) return fail(ctx, MPOEVO_EINVAL, "local_apply: NULL pointer");
+  for (int i = 0; i < 9; ++i) if (dims[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "local_apply: non-positive dimension");
+  if (workspace_bytes < mpoevo::local_apply_ws(dims, prec) || (!workspace && workspace_bytes))
+    return fail(ctx, MPOEVO_ENOMEM, "local_apply: workspace too small");
+  return mpoevo::local_apply_dev(*ctx, prec, L, W1, W2, M1, M2, R, Theta, dims, workspace,
+                                 workspace_bytes, stream);
+}
+
+int truncate(mpoevo_handle h, const void* Theta, int m, int n, int Dmax, double cutoff,
+             int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
+             double* norm_dev, double* sigma_dev, void* workspace, size_t workspace_bytes,
+             void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "truncate: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (!Theta || !A_out || !B_out) return fail(ctx, MPOEVO_EINVAL, "truncate: NULL pointer");
+  if (direction != MPOEVO_LEFT && direction != MPOEVO_RIGHT) return fail(ctx, MPOEVO_EINVAL, "truncate: unknown direction");
+  if (m < 1 || n < 1 || m > MPOEVO_SVD_MAX_DIM || n > MPOEVO_SVD_MAX_DIM || Dmax < 1)
+    return fail(ctx, MPOEVO_ESHAPE, "truncate: m, n must be in 1..MPOEVO_SVD_MAX_DIM and Dmax >= 1");
+  if (!(cutoff >= 0.0) || cutoff >= 1.0) return fail(ctx, MPOEVO_EINVAL, "truncate: cutoff must be in [0, 1)");
+  if (workspace_bytes < mpoevo::truncate_ws(m, n) || !workspace)
+    return fail(ctx, MPOEVO_ENOMEM, "truncate: workspace too small");
+  return mpoevo::truncate_dev(*ctx, Theta, m, n, Dmax, cutoff, direction, A_out, B_out, k_dev,
+                              discarded_dev, norm_dev, sigma_dev, workspace, workspace_bytes, stream);
+}
+
+int mpoevo_check_solver(mpoevo_handle h) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_check_solver: NULL handle");
+  return mpoevo::check_solver_dev(*reinterpret_cast<mpoevo::Context*>(h));
+}
+
+int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
+         mpoevo_step_stats* stats, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "step: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (!mps || !mpo || !opts || !mps->bond_dim || !mps->site || !mpo->w || !mpo->site)
+    return fail(ctx, MPOEVO_EINVAL, "step: NULL argument");
+  if (opts->prec != MPOEVO_FP64 && opts->prec != MPOEVO_FP32) return fail(ctx, MPOEVO_EINVAL, "step: unknown precision");
+  if (opts->nsweeps < 1 || opts->nsweeps > 4) return fail(ctx, MPOEVO_EINVAL, "step: nsweeps must be 1..4");
+  if (!(opts->cutoff >= 0.0) || opts->cutoff >= 1.0) return fail(ctx, MPOEVO_EINVAL, "step: cutoff must be in [0, 1)");
+  const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
+  if (L < 2 || d < 1 || Dmax < 1 || mpo->L != L || mpo->d != d)
+    return fail(ctx, MPOEVO_ESHAPE, "step: need L >= 2 and matching L, d of MPS and MPO");
+  if ((long)d * Dmax > MPOEVO_SVD_MAX_DIM) return fail(ctx, MPOEVO_ESHAPE, "step: d * Dmax exceeds MPOEVO_SVD_MAX_DIM");
+  if (mps->bond_dim[0] != 1 || mps->bond_dim[L] != 1) return fail(ctx, MPOEVO_ESHAPE, "step: boundary bonds must be 1");
+  int wmax = 0;
+  for (int i = 0; i <= L; ++i) {
+    if (i > 0 && i < L && (mps->bond_dim[i] < 1 || mps->bond_dim[i] > Dmax))
+      return fail(ctx, MPOEVO_ESHAPE, "step: MPS bond dimension outside 1..Dmax");
+    if (mpo->w[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "step: MPO bond dimension < 1");
+    if (mpo->w[i] > wmax) wmax = mpo->w[i];
+  }
+  for (int i = 0; i < L; ++i)
+    if (!mps->site[i] || !mpo->site[i]) return fail(ctx, MPOEVO_EINVAL, "step: NULL site pointer");
+  if (workspace_bytes < mpoevo::step_ws(L, d, Dmax, wmax, opts->prec) || !workspace)
+    return fail(ctx, MPOEVO_ENOMEM, "step: workspace too small");
+  return mpoevo::step_dev(*ctx, mps, mpo, opts, stats, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

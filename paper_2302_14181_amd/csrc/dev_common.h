@@ -1,0 +1,39 @@
+// Shared device-side definitions for the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace mpoevo {
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using type = float2; };
+template <> struct Cx<double> { using type = double2; };
+template <typename T> using cx_t = typename Cx<T>::type;
+
+// Arguments of a strided-batched complex product C = op(A) op(B) (complex elements, strides in
+// complex elements). A(m, k) at A + batch*bA + m*sAm + k*sAk, B(k, n) at B + batch*bB + k*sBk +
+// n*sBn, C(m, n) at C + batch*bC + m*sCm + n*sCn; conjA / conjB conjugate the operand.
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K, batch;
+  long long sAm, sAk, sBk, sBn, sCm, sCn;
+  long long bA, bB, bC;
+  bool conjA, conjB;
+};
+
+// Launch a complex product with real fp32 (T = float) or fp64 (T = double) matrix-core
+// arithmetic. out_fp64: store C as complex128 even when T = float. Returns a hipError_t.
+hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st);
+
+#define MPOEVO_HIP_TRY(expr)                                  \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return e_;                          \
+  } while (0)
+
+}  // namespace mpoevo

@@ -1,0 +1,547 @@
+// Device layer of the C ABI: environment updates, the projected two-site tensor, the FP64
+// truncation and one full time step of the variational fit (Sec. 2.2; Sec. 8.2).
+//
+// Data flow of a time step (i = site index, bond i is the left bond of site i):
+//   psi  (ket, caller's buffers, bonds Q_i)  and  phi (bra, the new state, bonds P_i).
+//   T_i  = Lenv_i . M_i                    (matrix product, K = Q_i)
+//   LB_i = T_i . W_i   [a'][s'][beta][b]   (short-leg contraction with the MPO)
+//   U_i  = M_i . Renv_{i+1}^T              (matrix product, K = Q_{i+1})
+//   RB_i = W_i . U_i   [beta][b][t'][c']
+//   Theta(i,i+1) = LB_i . RB_{i+1}         (matrix product, K = w Q_{i+1})
+//   Lenv_{i+1} = phi_i^dag . LB_i,  Renv_i = conj(phi_i) . RB_i^T
+// LB_i depends only on the sites left of i and RB_{i+1} only on the sites right of i+1, so the
+// left-to-right pass computes LB_i once per visit and reuses the RB_{i+1} of the previous
+// right-to-left pass (and vice versa): every visit costs one left (or right) block, one
+// environment product and the Theta product. All LB_i / RB_i of the chain stay resident in HBM.
+//
+// Bond dimensions of phi are static upper bounds min(Dmax, m, n) during a step (the kept rank
+// is decided on the device, discarded directions are exact zeros), so no visit waits for the
+// host; the host reads the kept ranks once at the end of the step and compacts the result.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dev_common.h"
+#include "internal.h"
+#include "svd.h"
+#include "wmix.h"
+
+namespace mpoevo {
+
+struct DeviceState {
+  int* status = nullptr;  // sticky status bits (device int)
+  int lds_max = 0;
+};
+
+namespace {
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+size_t csize(int prec) { return prec == MPOEVO_FP64 ? sizeof(double2) : sizeof(float2); }
+
+int hip_fail(Context& ctx, hipError_t e, const char* what) {
+  ctx.err = std::string(what) + ": " + hipGetErrorString(e);
+  return MPOEVO_EHIP;
+}
+
+// ----------------------------------------------------------------------------- small kernels
+__global__ void cast_c128_c64(const double2* __restrict__ in, float2* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = float2{(float)in[i].x, (float)in[i].y};
+}
+
+template <typename C2>
+__global__ void boundary_env(C2* E, int w) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i < w) E[i] = C2{i == 0 ? 1 : 0, 0};
+}
+
+__global__ void scale_by_inverse_norm(double2* x, long long n, const double* norm) {
+  const double s = *norm;
+  const double f = (s > 0.0 && isfinite(s)) ? 1.0 / s : 1.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = double2{x[i].x * f, x[i].y * f};
+}
+
+// dst[a][s][b] (Pa x d x Pb) <- src[a][s][b] with src row pitch (d, Pbs), a < Pa, b < Pb.
+__global__ void compact_site(const double2* __restrict__ src, double2* __restrict__ dst, int Pa,
+                             int d, int Pb, int Pbs) {
+  const long long n = (long long)Pa * d * Pb;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(i % Pb);
+    const long long as = i / Pb;
+    dst[i] = src[as * Pbs + b];
+  }
+}
+
+int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
+
+hipError_t cast_to_c64(const void* in, void* out, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cast_c128_c64, dim3(grid_for(n)), dim3(256), 0, st, (const double2*)in, (float2*)out, n);
+  return hipGetLastError();
+}
+
+hipError_t set_boundary(void* E, int w, bool fp64, hipStream_t st) {
+  if (fp64) hipLaunchKernelGGL(boundary_env<double2>, dim3((w + 255) / 256), dim3(256), 0, st, (double2*)E, w);
+  else hipLaunchKernelGGL(boundary_env<float2>, dim3((w + 255) / 256), dim3(256), 0, st, (float2*)E, w);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ contraction building blocks
+// LB[a'][s'][beta][b] = sum E[a'][alpha][a] ket[a][s][b] W[alpha][s'][s][beta]
+// E: (P, wl, Qa), ket: (Qa, d, Qb), W: (wl, d, d, wr). tmp holds P*wl*d*Qb complex.
+hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, void* tmp,
+                      void* LB, int P, int wl, int Qa, int d, int Qb, int wr, hipStream_t st) {
+  GemmDesc g{};
+  g.A = E; g.B = ket; g.C = tmp;
+  g.M = P * wl; g.N = d * Qb; g.K = Qa; g.batch = 1;
+  g.sAm = Qa; g.sAk = 1; g.sBk = (long long)d * Qb; g.sBn = 1; g.sCm = (long long)d * Qb; g.sCn = 1;
+  MPOEVO_HIP_TRY(gemm_launch(g, fp64, false, st));
+  return wmix_left(fp64, tmp, W, LB, P, Qb, wl, d, wr, st);
+}
+
+// RB[beta][b][t'][c'] = sum W[beta][t'][t][gamma] ket[b][t][c] E[c'][gamma][c]
+// ket: (Qa, d, Qb), E: (Pr, wr, Qb), W: (wl, d, d, wr). tmp holds Qa*d*Pr*wr complex.
+hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W, void* tmp,
+                       void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st) {
+  GemmDesc g{};
+  g.A = ket; g.B = E; g.C = tmp;
+  g.M = Qa * d; g.N = Pr * wr; g.K = Qb; g.batch = 1;
+  g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sBn = Qb; g.sCm = (long long)Pr * wr; g.sCn = 1;
+  MPOEVO_HIP_TRY(gemm_launch(g, fp64, false, st));
+  return wmix_right(fp64, tmp, W, RB, Qa, Pr, wl, d, wr, st);
+}
+
+// Lnew[b'][beta][b] = sum conj(bra[a'][s'][b']) LB[a'][s'][beta][b]; bra: (Pa, d, Pb).
+hipError_t left_env_from_block(bool fp64, const void* bra, const void* LB, void* Lnew, int Pa,
+                               int d, int Pb, int wr, int Qb, hipStream_t st) {
+  GemmDesc g{};
+  g.A = bra; g.B = LB; g.C = Lnew;
+  g.M = Pb; g.N = wr * Qb; g.K = Pa * d; g.batch = 1;
+  g.sAm = 1; g.sAk = Pb; g.conjA = true;
+  g.sBk = (long long)wr * Qb; g.sBn = 1; g.sCm = (long long)wr * Qb; g.sCn = 1;
+  return gemm_launch(g, fp64, false, st);
+}
+
+// Rnew[a'][alpha][a] = sum conj(bra[a'][t'][c']) RB[alpha][a][t'][c']; bra: (Pa, d, Pb).
+hipError_t right_env_from_block(bool fp64, const void* bra, const void* RB, void* Rnew, int Pa,
+                                int d, int Pb, int wl, int Qa, hipStream_t st) {
+  GemmDesc g{};
+  g.A = bra; g.B = RB; g.C = Rnew;
+  g.M = Pa; g.N = wl * Qa; g.K = d * Pb; g.batch = 1;
+  g.sAm = (long long)d * Pb; g.sAk = 1; g.conjA = true;
+  g.sBk = 1; g.sBn = (long long)d * Pb; g.sCm = (long long)wl * Qa; g.sCn = 1;
+  return gemm_launch(g, fp64, false, st);
+}
+
+// Theta[(a',s')][(t',c')] = sum LB[(a',s')][(beta,b)] RB[(beta,b)][(t',c')], complex128 out.
+hipError_t theta_product(bool fp64, const void* LB, const void* RB, void* theta, int Pa, int d,
+                         int wm, int Qm, int Pc, hipStream_t st) {
+  GemmDesc g{};
+  g.A = LB; g.B = RB; g.C = theta;
+  g.M = Pa * d; g.N = d * Pc; g.K = wm * Qm; g.batch = 1;
+  g.sAm = (long long)wm * Qm; g.sAk = 1; g.sBk = (long long)d * Pc; g.sBn = 1;
+  g.sCm = (long long)d * Pc; g.sCn = 1;
+  return gemm_launch(g, fp64, true, st);
+}
+
+// Site product site[a][s][b] <- sum_c site_in[a][s][c] R[c][b] (complex128), used to absorb
+// the U S factor of the right-canonicalisation into the site on the left.
+hipError_t absorb_right(const void* site_in, const void* R, void* site_out, int Pa, int d, int Pc,
+                        int Pb, hipStream_t st) {
+  GemmDesc g{};
+  g.A = site_in; g.B = R; g.C = site_out;
+  g.M = Pa * d; g.N = Pb; g.K = Pc; g.batch = 1;
+  g.sAm = Pc; g.sAk = 1; g.sBk = Pb; g.sBn = 1; g.sCm = Pb; g.sCn = 1;
+  return gemm_launch(g, true, true, st);
+}
+
+// ------------------------------------------------------------------------- step workspace map
+struct StepLayout {
+  size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
+  size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
+      off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, total;
+  SvdPlan plan;
+};
+
+StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
+  StepLayout s{};
+  const size_t cs = csize(prec);
+  const bool f32 = prec == MPOEVO_FP32;
+  s.sitecap = (size_t)Dmax * d * Dmax;
+  s.lbcap = (size_t)Dmax * d * wmax * Dmax;
+  s.envcap = (size_t)Dmax * wmax * Dmax;
+  s.tmpcap = (size_t)Dmax * wmax * d * Dmax;
+  s.wcap = (size_t)wmax * d * d * wmax;
+  s.thetacap = (size_t)d * Dmax * d * Dmax;
+  s.plan = svd_plan(d * Dmax, d * Dmax);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += a256(bytes); return at; };
+  s.off_phi = take(sizeof(double2) * s.sitecap * L);
+  s.off_ketc = take(f32 ? sizeof(float2) * s.sitecap * L : 0);
+  s.off_brac = take(f32 ? sizeof(float2) * s.sitecap * L : 0);
+  s.off_wc = take(f32 ? sizeof(float2) * s.wcap * L : 0);
+  s.off_lb = take(cs * s.lbcap * L);
+  s.off_rb = take(cs * s.lbcap * L);
+  s.off_env0 = take(cs * s.envcap);
+  s.off_env1 = take(cs * s.envcap);
+  s.off_tmp = take(cs * s.tmpcap);
+  s.off_theta = take(sizeof(double2) * s.thetacap);
+  s.off_svd = take(svd_ws_bound(d * Dmax));
+  s.off_kbuf = take(sizeof(int) * (size_t)8 * L);
+  s.off_dbuf = take(sizeof(double) * (size_t)8 * L);
+  s.off_nbuf = take(sizeof(double) * (size_t)8 * L);
+  s.off_site_tmp = take(sizeof(double2) * s.sitecap);
+  s.off_site_tmp2 = take(sizeof(double2) * s.sitecap);
+  s.total = o;
+  return s;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------ init / sizes
+int device_init(Context& ctx) {
+  hipError_t e = hipSetDevice(ctx.device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  int lds = 0, coop = 0;
+  e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx.device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceGetAttribute(shared memory)");
+  e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, ctx.device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceGetAttribute(cooperative launch)");
+  if (!coop) { ctx.err = "device does not support cooperative launches"; return MPOEVO_EUNSUPPORTED; }
+  if ((size_t)lds < kSvdLdsBytes) {
+    ctx.err = "device provides " + std::to_string(lds) + " bytes of LDS per workgroup; the SVD needs " +
+              std::to_string(kSvdLdsBytes);
+    return MPOEVO_EUNSUPPORTED;
+  }
+  e = svd_configure();
+  if (e != hipSuccess) return hip_fail(ctx, e, "svd_configure");
+  auto* ds = new DeviceState();
+  ds->lds_max = lds;
+  e = hipMalloc(&ds->status, sizeof(int));
+  if (e != hipSuccess) { delete ds; return hip_fail(ctx, e, "hipMalloc(status)"); }
+  e = hipMemset(ds->status, 0, sizeof(int));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) { (void)hipFree(ds->status); delete ds; return hip_fail(ctx, e, "status init"); }
+  ctx.dev = ds;
+  return MPOEVO_OK;
+}
+
+void device_fini(Context& ctx) {
+  if (!ctx.dev) return;
+  (void)hipSetDevice(ctx.device);
+  (void)hipFree(ctx.dev->status);
+  delete ctx.dev;
+  ctx.dev = nullptr;
+}
+
+size_t env_update_ws(const int* dims, int prec) {
+  const size_t Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4],
+               wl = dims[5], wr = dims[6];
+  const size_t cs = csize(prec);
+  const size_t left = a256(cs * Dbl * wl * d * Dkr) + a256(cs * Dbl * d * wr * Dkr);
+  const size_t right = a256(cs * Dkl * d * Dbr * wr) + a256(cs * wl * Dkl * d * Dbr);
+  return std::max(left, right);
+}
+
+size_t local_apply_ws(const int* dims, int prec) {
+  const size_t Dbl = dims[0], Dkm = dims[2], Dbr = dims[4], d = dims[5], wl = dims[6],
+               wm = dims[7], wr = dims[8];
+  const size_t cs = csize(prec);
+  const size_t tmp = std::max(cs * Dbl * wl * d * Dkm, cs * Dkm * d * Dbr * wr);
+  return a256(tmp) + a256(cs * Dbl * d * wm * Dkm) + a256(cs * wm * Dkm * d * Dbr);
+}
+
+size_t truncate_ws(int m, int n) { return svd_plan(m, n).ws; }
+
+size_t step_ws(int L, int d, int Dmax, int wmax, int prec) {
+  return step_layout(L, d, Dmax, wmax, prec).total;
+}
+
+int check_solver_dev(Context& ctx) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  int st = 0;
+  hipError_t e = hipMemcpy(&st, ctx.dev->status, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reading the solver status");
+  if (st) {
+    e = hipMemset(ctx.dev->status, 0, sizeof(int));
+    if (e != hipSuccess) return hip_fail(ctx, e, "clearing the solver status");
+    if (st & kStatusNonFinite) { ctx.err = "truncate: non-finite singular values"; return MPOEVO_ENONFINITE; }
+    if (st & kStatusBarrierTimeout) { ctx.err = "truncate: grid barrier timed out"; return MPOEVO_ESOLVER; }
+    ctx.err = "truncate: Jacobi SVD did not converge within its sweep limit";
+    return MPOEVO_ESOLVER;
+  }
+  return MPOEVO_OK;
+}
+
+// ------------------------------------------------------------------------------- ABI calls
+int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
+                   const void* W, const void* ket, void* E_out, const int* dims, void* ws,
+                   size_t, void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  const int Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4], wl = dims[5],
+            wr = dims[6];
+  if (!wmix_supported(wl, d, wr)) { ctx.err = "env_update: MPO bond too large for this build"; return MPOEVO_EUNSUPPORTED; }
+  const bool fp64 = prec == MPOEVO_FP64;
+  const size_t cs = csize(prec);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  hipError_t e;
+  if (side == MPOEVO_LEFT) {
+    void* tmp = base;
+    void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
+    e = left_block(fp64, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st);
+    if (e == hipSuccess) e = left_env_from_block(fp64, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st);
+  } else {
+    void* tmp = base;
+    void* RB = base + a256(cs * (size_t)Dkl * d * Dbr * wr);
+    e = right_block(fp64, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st);
+    if (e == hipSuccess) e = right_env_from_block(fp64, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st);
+  }
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "env_update");
+}
+
+int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const void* W2,
+                    const void* M1, const void* M2, const void* R, void* Theta, const int* dims,
+                    void* ws, size_t, void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  const int Dbl = dims[0], Dkl = dims[1], Dkm = dims[2], Dkr = dims[3], Dbr = dims[4], d = dims[5],
+            wl = dims[6], wm = dims[7], wr = dims[8];
+  if (!wmix_supported(wl, d, wm) || !wmix_supported(wm, d, wr)) {
+    ctx.err = "local_apply: MPO bond too large for this build";
+    return MPOEVO_EUNSUPPORTED;
+  }
+  const bool fp64 = prec == MPOEVO_FP64;
+  const size_t cs = csize(prec);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  const size_t tmpb = a256(std::max(cs * Dbl * wl * d * Dkm, cs * Dkm * d * Dbr * wr));
+  void* tmp = base;
+  void* LB = base + tmpb;
+  void* RB = base + tmpb + a256(cs * (size_t)Dbl * d * wm * Dkm);
+  hipError_t e = left_block(fp64, L, M1, W1, tmp, LB, Dbl, wl, Dkl, d, Dkm, wm, st);
+  if (e == hipSuccess) e = right_block(fp64, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st);
+  if (e == hipSuccess) e = theta_product(fp64, LB, RB, Theta, Dbl, d, wm, Dkm, Dbr, st);
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "local_apply");
+}
+
+int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double cutoff,
+                 int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
+                 double* norm_dev, double* sigma_dev, void* ws, size_t, void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  const SvdPlan p = svd_plan(m, n);
+  hipError_t e = svd_truncate(p, static_cast<const double2*>(Theta), Dmax, cutoff, direction,
+                              static_cast<double2*>(A_out), static_cast<double2*>(B_out), k_dev,
+                              discarded_dev, norm_dev, sigma_dev, ws, ctx.dev->status,
+                              static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "truncate");
+}
+
+// ---------------------------------------------------------------------------------- the step
+int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
+             mpoevo_step_stats* stats, void* ws, size_t, void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  const int L = mps->L, d = mps->d, Dmax = mps->Dmax, prec = opts->prec;
+  const bool fp64 = prec == MPOEVO_FP64;
+  int wmax = 0;
+  for (int i = 0; i <= L; ++i) wmax = std::max(wmax, mpo->w[i]);
+  for (int i = 0; i < L; ++i)
+    if (!wmix_supported(mpo->w[i], d, mpo->w[i + 1])) {
+      ctx.err = "step: MPO bond too large for this build";
+      return MPOEVO_EUNSUPPORTED;
+    }
+  const StepLayout lay = step_layout(L, d, Dmax, wmax, prec);
+  const size_t cs = csize(prec);
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto phi = [&](int i) { return reinterpret_cast<double2*>(base + lay.off_phi) + lay.sitecap * i; };
+  auto ket = [&](int i) -> const void* {
+    if (fp64) return mps->site[i];
+    return reinterpret_cast<float2*>(base + lay.off_ketc) + lay.sitecap * i;
+  };
+  auto bra = [&](int i) -> const void* {
+    if (fp64) return phi(i);
+    return reinterpret_cast<float2*>(base + lay.off_brac) + lay.sitecap * i;
+  };
+  auto wsite = [&](int i) -> const void* {
+    if (fp64) return mpo->site[i];
+    return reinterpret_cast<float2*>(base + lay.off_wc) + lay.wcap * i;
+  };
+  auto LB = [&](int i) { return base + lay.off_lb + cs * lay.lbcap * i; };
+  auto RB = [&](int i) { return base + lay.off_rb + cs * lay.lbcap * i; };
+  void* env0 = base + lay.off_env0;
+  void* env1 = base + lay.off_env1;
+  void* tmp = base + lay.off_tmp;
+  double2* theta = reinterpret_cast<double2*>(base + lay.off_theta);
+  void* svdws = base + lay.off_svd;
+  int* kbuf = reinterpret_cast<int*>(base + lay.off_kbuf);
+  double* dbuf = reinterpret_cast<double*>(base + lay.off_dbuf);
+  double* nbuf = reinterpret_cast<double*>(base + lay.off_nbuf);
+  double2* site_tmp = reinterpret_cast<double2*>(base + lay.off_site_tmp);
+  double2* site_tmp2 = reinterpret_cast<double2*>(base + lay.off_site_tmp2);
+  const int* w = mpo->w;
+
+  std::vector<int> Q(mps->bond_dim, mps->bond_dim + L + 1);  // ket bonds
+  std::vector<int> P(Q);                                       // bra bonds (upper bounds)
+  hipError_t e = hipSuccess;
+  double gflop = 0.0;
+  auto flop_gemm = [&](double M, double N, double K) { gflop += 8.0 * M * N * K * 1e-9; };
+  auto bra_refresh = [&](int i) -> hipError_t {  // fp32 copy of phi_i
+    if (fp64) return hipSuccess;
+    return cast_to_c64(phi(i), (void*)bra(i), (long long)P[i] * d * P[i + 1], st);
+  };
+#define STEP_TRY(x)                              \
+  do {                                           \
+    e = (x);                                     \
+    if (e != hipSuccess) return hip_fail(ctx, e, "step"); \
+  } while (0)
+
+  // inputs in contraction precision; phi <- psi
+  for (int i = 0; i < L; ++i) {
+    const long long ns = (long long)Q[i] * d * Q[i + 1];
+    STEP_TRY(hipMemcpyAsync(phi(i), mps->site[i], sizeof(double2) * ns, hipMemcpyDeviceToDevice, st));
+    if (!fp64) {
+      STEP_TRY(cast_to_c64(mps->site[i], (void*)ket(i), ns, st));
+      STEP_TRY(cast_to_c64(mpo->site[i], (void*)wsite(i), (long long)w[i] * d * d * w[i + 1], st));
+    }
+  }
+  // right-canonical guess: SVD of each site from the last to the second
+  if (!opts->input_right_canonical) {
+    for (int i = L - 1; i >= 1; --i) {
+      const int m = P[i], n = d * P[i + 1];
+      const SvdPlan pl = svd_plan(m, n);
+      const int kcap = std::min(m, n);
+      double2* A = theta;  // m x kcap   (U S)
+      double2* B = site_tmp;  // kcap x n (V^dag)
+      STEP_TRY(svd_truncate(pl, phi(i), kcap, opts->cutoff, MPOEVO_RIGHT, A, B, nullptr, nullptr,
+                            nullptr, nullptr, svdws, ctx.dev->status, st));
+      STEP_TRY(hipMemcpyAsync(phi(i), B, sizeof(double2) * (size_t)kcap * n, hipMemcpyDeviceToDevice, st));
+      // phi_{i-1} <- phi_{i-1} . (U S)
+      STEP_TRY(absorb_right(phi(i - 1), A, site_tmp2, P[i - 1], d, m, kcap, st));
+      STEP_TRY(hipMemcpyAsync(phi(i - 1), site_tmp2, sizeof(double2) * (size_t)P[i - 1] * d * kcap,
+                              hipMemcpyDeviceToDevice, st));
+      P[i] = kcap;
+    }
+  }
+  for (int i = 0; i < L; ++i) STEP_TRY(bra_refresh(i));
+
+  // right blocks RB_i, i = L-1 .. 1, from the canonical guess
+  STEP_TRY(set_boundary(env1, w[L], fp64, st));  // Renv_L
+  for (int i = L - 1; i >= 1; --i) {
+    STEP_TRY(right_block(fp64, ket(i), env1, wsite(i), tmp, RB(i), Q[i], d, Q[i + 1], P[i + 1],
+                         w[i], w[i + 1], st));
+    flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
+    if (i > 1) {
+      STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st));
+      flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
+    }
+  }
+
+  int visit = 0;
+  const int nvis = opts->nsweeps * 2 * (L - 1);
+  int last_visit_k_slot = 0;
+  std::vector<int> k_slot_of_bond(L, -1);
+  for (int sw = 0; sw < opts->nsweeps; ++sw) {
+    // left to right
+    for (int i = 0; i <= L - 2; ++i, ++visit) {
+      if (i == 0) STEP_TRY(set_boundary(env0, w[0], fp64, st));
+      else {
+        STEP_TRY(left_env_from_block(fp64, bra(i - 1), LB(i - 1), env0, P[i - 1], d, P[i],
+                                     w[i], Q[i], st));
+        flop_gemm(P[i], (double)w[i] * Q[i], (double)P[i - 1] * d);
+      }
+      STEP_TRY(left_block(fp64, env0, ket(i), wsite(i), tmp, LB(i), P[i], w[i], Q[i], d, Q[i + 1],
+                          w[i + 1], st));
+      flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
+      const int m = P[i] * d, n = d * P[i + 2];
+      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st));
+      flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
+      const int kcap = std::min(Dmax, std::min(m, n));
+      STEP_TRY(svd_truncate(svd_plan(m, n), theta, Dmax, opts->cutoff, MPOEVO_LEFT, phi(i),
+                            phi(i + 1), kbuf + visit, dbuf + visit, nbuf + visit, nullptr, svdws,
+                            ctx.dev->status, st));
+      P[i + 1] = kcap;
+      k_slot_of_bond[i + 1] = visit;
+      last_visit_k_slot = visit;
+      STEP_TRY(bra_refresh(i));
+      STEP_TRY(bra_refresh(i + 1));
+    }
+    // right to left
+    for (int i = L - 2; i >= 0; --i, ++visit) {
+      if (i < L - 2) {
+        STEP_TRY(right_env_from_block(fp64, bra(i + 2), RB(i + 2), env1, P[i + 2], d, P[i + 3],
+                                      w[i + 2], Q[i + 2], st));
+        flop_gemm(P[i + 2], (double)w[i + 2] * Q[i + 2], (double)d * P[i + 3]);
+        STEP_TRY(right_block(fp64, ket(i + 1), env1, wsite(i + 1), tmp, RB(i + 1), Q[i + 1], d,
+                             Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st));
+        flop_gemm((double)Q[i + 1] * d, (double)P[i + 2] * w[i + 2], Q[i + 2]);
+      }
+      const int m = P[i] * d, n = d * P[i + 2];
+      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st));
+      flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
+      const int kcap = std::min(Dmax, std::min(m, n));
+      STEP_TRY(svd_truncate(svd_plan(m, n), theta, Dmax, opts->cutoff, MPOEVO_RIGHT, phi(i),
+                            phi(i + 1), kbuf + visit, dbuf + visit, nbuf + visit, nullptr, svdws,
+                            ctx.dev->status, st));
+      P[i + 1] = kcap;
+      k_slot_of_bond[i + 1] = visit;
+      last_visit_k_slot = visit;
+      STEP_TRY(bra_refresh(i));
+      STEP_TRY(bra_refresh(i + 1));
+    }
+  }
+  // normalise with the norm of the last visit (phi_0 holds U S)
+  STEP_TRY([&] {
+    hipLaunchKernelGGL(scale_by_inverse_norm, dim3(grid_for((long long)P[0] * d * P[1])), dim3(256), 0,
+                       st, phi(0), (long long)P[0] * d * P[1], nbuf + last_visit_k_slot);
+    return hipGetLastError();
+  }());
+  // read back the kept ranks and statistics (one synchronisation per step)
+  std::vector<int> kh(nvis);
+  std::vector<double> dh(nvis), nh(nvis);
+  STEP_TRY(hipMemcpyAsync(kh.data(), kbuf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
+  STEP_TRY(hipMemcpyAsync(dh.data(), dbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
+  STEP_TRY(hipMemcpyAsync(nh.data(), nbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
+  STEP_TRY(hipStreamSynchronize(st));
+  const int sres = check_solver_dev(ctx);
+  if (sres != MPOEVO_OK) return sres;
+  std::vector<int> Pact(L + 1, 1);
+  for (int b = 1; b < L; ++b) Pact[b] = kh[k_slot_of_bond[b]];
+  // compact phi into the caller's site buffers
+  for (int i = 0; i < L; ++i) {
+    const long long n = (long long)Pact[i] * d * Pact[i + 1];
+    // rows beyond Pact[i] are zero; keep a' < Pact[i], b < Pact[i+1] of the padded (P[i], d, P[i+1])
+    hipLaunchKernelGGL(compact_site, dim3(grid_for(n)), dim3(256), 0, st, phi(i),
+                       static_cast<double2*>(mps->site[i]), Pact[i], d, Pact[i + 1], P[i + 1]);
+    STEP_TRY(hipGetLastError());
+  }
+  STEP_TRY(hipStreamSynchronize(st));
+  const double norm = nh[last_visit_k_slot];
+  int maxb = 1;
+  for (int b = 0; b <= L; ++b) {
+    mps->bond_dim[b] = Pact[b];
+    maxb = std::max(maxb, Pact[b]);
+  }
+  if (stats) {
+    stats->norm = norm;
+    stats->discarded_max = 0.0;
+    stats->discarded_sum = 0.0;
+    for (int v = 0; v < nvis; ++v) {
+      stats->discarded_max = std::max(stats->discarded_max, dh[v]);
+      stats->discarded_sum += dh[v];
+    }
+    stats->visits = nvis;
+    stats->max_bond = maxb;
+    stats->gflop = gflop;
+  }
+  if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
+#undef STEP_TRY
+  return MPOEVO_OK;
+}
+
+}  // namespace mpoevo

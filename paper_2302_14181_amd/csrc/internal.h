@@ -1,0 +1,46 @@
+// Internal interface between the C ABI layer (abi.cpp, no HIP headers) and the device code
+// (device.hip). Only plain C++ types cross this boundary.
+#pragma once
+
+#include <cstddef>
+#include <string>
+
+#include "../../include/mpoevo.h"
+
+namespace mpoevo {
+
+int build_mpo_host(int d, int chi, const double* A, const double* B, const double* C,
+                   const double* D, int order, double tau_re, double tau_im, int variant,
+                   const int* inner_charge, const int* phys_charge, int* w_out, double* W_out,
+                   size_t W_capacity, int* level_charge_out, std::string& err);
+
+struct DeviceState;  // defined in device.hip
+
+struct Context {
+  int device = 0;
+  std::string err;
+  DeviceState* dev = nullptr;
+};
+
+int device_init(Context& ctx);
+void device_fini(Context& ctx);
+
+size_t env_update_ws(const int* dims, int prec);
+size_t local_apply_ws(const int* dims, int prec);
+size_t truncate_ws(int m, int n);
+size_t step_ws(int L, int d, int Dmax, int wmax, int prec);
+
+int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
+                   const void* W, const void* ket, void* E_out, const int* dims, void* ws,
+                   size_t ws_bytes, void* stream);
+int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const void* W2,
+                    const void* M1, const void* M2, const void* R, void* Theta, const int* dims,
+                    void* ws, size_t ws_bytes, void* stream);
+int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double cutoff,
+                 int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
+                 double* norm_dev, double* sigma_dev, void* ws, size_t ws_bytes, void* stream);
+int check_solver_dev(Context& ctx);
+int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
+             mpoevo_step_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+}  // namespace mpoevo

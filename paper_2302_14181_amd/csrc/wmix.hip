@@ -1,0 +1,160 @@
+// Contractions with the MPO tensor W over its short legs (K = w d terms per output). These are
+// memory-bound: every thread keeps the K input values of one output column in registers and
+// produces all of its w d outputs, with W staged once per workgroup in LDS.
+//
+//   left : LB[a'][s'][beta][b]  = sum_{alpha, s} T[a'][alpha][s][b]  W[alpha][s'][s][beta]
+//   right: RB[beta][b][t'][c']  = sum_{t, gamma} W[beta][t'][t][gamma] U[b][t][c'][gamma]
+//
+// T = E_left . ket (first product of the left environment update), U = ket . E_right^T.
+
+#include "dev_common.h"
+#include "wmix.h"
+
+namespace mpoevo {
+namespace {
+
+template <typename T>
+__device__ inline cx_t<T> cmul_add(cx_t<T> acc, cx_t<T> a, cx_t<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+
+constexpr int kThreads = 256;
+
+// grid: (ceil(Q / 256), P). KMAX >= wl * d.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __restrict__ Tin,
+                                                             const cx_t<T>* __restrict__ W,
+                                                             cx_t<T>* __restrict__ out, int Q,
+                                                             int wl, int d, int wr) {
+  using C2 = cx_t<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C2* Ws = reinterpret_cast<C2*>(smem_raw);
+  const int nW = wl * d * d * wr;
+  for (int i = threadIdx.x; i < nW; i += kThreads) Ws[i] = W[i];
+  __syncthreads();
+  const int b = blockIdx.x * kThreads + threadIdx.x;
+  const int ap = blockIdx.y;
+  if (b >= Q) return;
+  const int K = wl * d;
+  const C2* src = Tin + (long long)ap * K * Q + b;
+  C2 in[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) in[k] = (k < K) ? src[(long long)k * Q] : C2{T(0), T(0)};
+  C2* dst = out + (long long)ap * d * wr * Q + b;
+  for (int sp = 0; sp < d; ++sp)
+    for (int be = 0; be < wr; ++be) {
+      C2 acc{T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < K) {
+          const int al = k / d, s = k % d;  // k = alpha * d + s
+          acc = cmul_add<T>(acc, in[k], Ws[((al * d + sp) * d + s) * wr + be]);
+        }
+      }
+      dst[(long long)(sp * wr + be) * Q] = acc;
+    }
+}
+
+// grid: (ceil(Pr / 256), Q). U[b][t][c'][gamma] with c' < Pr; out RB[beta][b][t'][c'].
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kThreads) void wmix_right_kernel(const cx_t<T>* __restrict__ U,
+                                                              const cx_t<T>* __restrict__ W,
+                                                              cx_t<T>* __restrict__ out, int Q,
+                                                              int Pr, int wl, int d, int wr) {
+  using C2 = cx_t<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C2* Ws = reinterpret_cast<C2*>(smem_raw);
+  const int nW = wl * d * d * wr;
+  for (int i = threadIdx.x; i < nW; i += kThreads) Ws[i] = W[i];
+  __syncthreads();
+  const int cp = blockIdx.x * kThreads + threadIdx.x;
+  const int b = blockIdx.y;
+  if (cp >= Pr) return;
+  const int K = d * wr;
+  C2 in[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    C2 v{T(0), T(0)};
+    if (k < K) {
+      const int t = k / wr, ga = k % wr;  // k = t * wr + gamma
+      v = U[(((long long)b * d + t) * Pr + cp) * wr + ga];
+    }
+    in[k] = v;
+  }
+  for (int be = 0; be < wl; ++be)
+    for (int tp = 0; tp < d; ++tp) {
+      C2 acc{T(0), T(0)};
+      const C2* wrow = Ws + (be * d + tp) * d * wr;  // W[beta][t'][t][gamma], (t, gamma) = k
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < K) acc = cmul_add<T>(acc, wrow[k], in[k]);
+      out[(((long long)be * Q + b) * d + tp) * Pr + cp] = acc;
+    }
+}
+
+template <typename T, int KMAX>
+hipError_t launch_left(const void* Tin, const void* W, void* out, int P, int Q, int wl, int d,
+                       int wr, hipStream_t st) {
+  const size_t sh = sizeof(cx_t<T>) * (size_t)wl * d * d * wr;
+  dim3 grid((Q + kThreads - 1) / kThreads, P);
+  hipLaunchKernelGGL((wmix_left_kernel<T, KMAX>), grid, dim3(kThreads), sh, st,
+                     (const cx_t<T>*)Tin, (const cx_t<T>*)W, (cx_t<T>*)out, Q, wl, d, wr);
+  return hipGetLastError();
+}
+
+template <typename T, int KMAX>
+hipError_t launch_right(const void* U, const void* W, void* out, int Q, int Pr, int wl, int d,
+                        int wr, hipStream_t st) {
+  const size_t sh = sizeof(cx_t<T>) * (size_t)wl * d * d * wr;
+  dim3 grid((Pr + kThreads - 1) / kThreads, Q);
+  hipLaunchKernelGGL((wmix_right_kernel<T, KMAX>), grid, dim3(kThreads), sh, st,
+                     (const cx_t<T>*)U, (const cx_t<T>*)W, (cx_t<T>*)out, Q, Pr, wl, d, wr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_left(const void* Tin, const void* W, void* out, int P, int Q, int wl, int d,
+                         int wr, hipStream_t st) {
+  const int K = wl * d;
+  if (K <= 4) return launch_left<T, 4>(Tin, W, out, P, Q, wl, d, wr, st);
+  if (K <= 8) return launch_left<T, 8>(Tin, W, out, P, Q, wl, d, wr, st);
+  if (K <= 16) return launch_left<T, 16>(Tin, W, out, P, Q, wl, d, wr, st);
+  if (K <= 32) return launch_left<T, 32>(Tin, W, out, P, Q, wl, d, wr, st);
+  return launch_left<T, 64>(Tin, W, out, P, Q, wl, d, wr, st);
+}
+
+template <typename T>
+hipError_t dispatch_right(const void* U, const void* W, void* out, int Q, int Pr, int wl, int d,
+                          int wr, hipStream_t st) {
+  const int K = wr * d;
+  if (K <= 4) return launch_right<T, 4>(U, W, out, Q, Pr, wl, d, wr, st);
+  if (K <= 8) return launch_right<T, 8>(U, W, out, Q, Pr, wl, d, wr, st);
+  if (K <= 16) return launch_right<T, 16>(U, W, out, Q, Pr, wl, d, wr, st);
+  if (K <= 32) return launch_right<T, 32>(U, W, out, Q, Pr, wl, d, wr, st);
+  return launch_right<T, 64>(U, W, out, Q, Pr, wl, d, wr, st);
+}
+
+}  // namespace
+
+bool wmix_supported(int wl, int d, int wr) {
+  return wl * d <= kWmixMaxK && wr * d <= kWmixMaxK &&
+         (size_t)wl * d * d * wr * sizeof(double2) <= 64 * 1024;
+}
+
+hipError_t wmix_left(bool fp64, const void* Tin, const void* W, void* out, int P, int Q, int wl,
+                     int d, int wr, hipStream_t st) {
+  if (fp64) return dispatch_left<double>(Tin, W, out, P, Q, wl, d, wr, st);
+  return dispatch_left<float>(Tin, W, out, P, Q, wl, d, wr, st);
+}
+
+hipError_t wmix_right(bool fp64, const void* U, const void* W, void* out, int Q, int Pr, int wl,
+                      int d, int wr, hipStream_t st) {
+  if (fp64) return dispatch_right<double>(U, W, out, Q, Pr, wl, d, wr, st);
+  return dispatch_right<float>(U, W, out, Q, Pr, wl, d, wr, st);
+}
+
+}  // namespace mpoevo

@@ -1,0 +1,310 @@
+"""Python binding of libmpoevo.so (ctypes): argument marshalling only.
+
+Every computation runs in the library (host C++ for `mpo_build`, HIP kernels for the device
+calls). PyTorch provides device memory and the current stream; the functions take torch
+tensors on the GPU (complex128 for the FP64 path, complex64 for the FP32 path, see the header
+include/mpoevo.h for layouts) and raise MpoevoError on any non-zero status.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpoevo.so")
+
+OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESOLVER, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, FP32 = 0, 1
+V1_EXACT, V2_EXTENDED = 0, 1
+LEFT, RIGHT = 0, 1
+CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP = 0, 1, 2, 3
+SVD_MAX_DIM = 1024
+
+
+class MpoevoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mpoevo error {code}: {msg}")
+        self.code = code
+
+
+class _MPS(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("d", ctypes.c_int), ("Dmax", ctypes.c_int),
+                ("bond_dim", ctypes.POINTER(ctypes.c_int)), ("site", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class _MPO(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("d", ctypes.c_int), ("w", ctypes.POINTER(ctypes.c_int)),
+                ("site", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("nsweeps", ctypes.c_int), ("prec", ctypes.c_int), ("cutoff", ctypes.c_double),
+                ("input_right_canonical", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double), ("discarded_max", ctypes.c_double),
+                ("discarded_sum", ctypes.c_double), ("visits", ctypes.c_int),
+                ("max_bond", ctypes.c_int), ("gflop", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library once (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MpoevoError(EUNSUPPORTED, f"{path} is missing: run paper_2302_14181_amd.build first")
+    lib = ctypes.CDLL(path, mode=os.RTLD_LOCAL | os.RTLD_NOW)
+    vp, ip, dp, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_size_t
+    lib.mpoevo_version.restype = ctypes.c_char_p
+    lib.mpoevo_last_error.restype = ctypes.c_char_p
+    lib.mpoevo_last_error.argtypes = [vp]
+    lib.mpoevo_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.mpoevo_destroy.argtypes = [vp]
+    lib.mpoevo_check_solver.argtypes = [vp]
+    lib.mpo_build.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_int, ip, ip, ip, dp, sz, ip]
+    lib.mpoevo_workspace_size.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.env_update.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, ip, vp, sz, vp]
+    lib.local_apply.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, ip, vp, sz, vp]
+    lib.truncate.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                             vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.step.argtypes = [vp, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO), ctypes.POINTER(_Opts),
+                         ctypes.POINTER(_Stats), vp, sz, vp]
+    for name in ("mpoevo_create", "mpoevo_destroy", "mpoevo_check_solver", "mpo_build",
+                 "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["mpoevo_create", "mpoevo_destroy", "mpoevo_last_error", "mpoevo_version", "mpo_build",
+            "env_update", "local_apply", "truncate", "mpoevo_check_solver", "step",
+            "mpoevo_workspace_size"]
+
+
+def _check(rc: int, handle=None):
+    if rc != OK:
+        lib = load()
+        msg = lib.mpoevo_last_error(handle.ptr if handle is not None else None)
+        raise MpoevoError(rc, msg.decode() if msg else "")
+
+
+def _iarr(values):
+    return (ctypes.c_int * len(values))(*[int(v) for v in values])
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ------------------------------------------------------------------------------------ host
+def mpo_build(A, B, C, Dloc, order: int, tau: complex, variant: int = V2_EXTENDED,
+              inner_charge=None, phys_charge=None):
+    """Order-N MPO W[w][d][d][w] (numpy complex128) and, with charges, the level charges."""
+    lib = load()
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    B = np.ascontiguousarray(B, dtype=np.complex128)
+    C = np.ascontiguousarray(C, dtype=np.complex128)
+    D = np.ascontiguousarray(Dloc, dtype=np.complex128)
+    d, chi = D.shape[0], B.shape[0]
+    qi = _iarr(inner_charge) if inner_charge is not None else None
+    qp = _iarr(phys_charge) if phys_charge is not None else None
+    w = ctypes.c_int(0)
+    args = (d, chi, _dptr(A.view(np.float64)), _dptr(B.view(np.float64)), _dptr(C.view(np.float64)),
+            _dptr(D.view(np.float64)), order, float(np.real(tau)), float(np.imag(tau)), variant, qi, qp)
+    _check(lib.mpo_build(*args, ctypes.byref(w), None, 0, None))
+    W = np.zeros((w.value, d, d, w.value), dtype=np.complex128)
+    lc = (ctypes.c_int * w.value)() if qi is not None else None
+    _check(lib.mpo_build(*args, ctypes.byref(w), _dptr(W.view(np.float64)), W.size, lc))
+    return W, (np.array(list(lc), dtype=np.int64) if lc is not None else None)
+
+
+def workspace_size(call_id: int, dims, prec: int) -> int:
+    lib = load()
+    out = ctypes.c_size_t(0)
+    _check(lib.mpoevo_workspace_size(call_id, _iarr(dims), prec, ctypes.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------------------------- device
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prec_of(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return FP64
+    if t.dtype == torch.complex64:
+        return FP32
+    raise MpoevoError(EINVAL, f"unsupported dtype {t.dtype}")
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Handle:
+    """Library handle on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        self.ptr = ctypes.c_void_p()
+        _check(lib.mpoevo_create(ctypes.byref(self.ptr), device))
+        self.device = device
+
+    def close(self):
+        if self.ptr:
+            load().mpoevo_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check_solver(self):
+        _check(load().mpoevo_check_solver(self.ptr), self)
+
+
+def env_update(h: Handle, side: int, E_in, bra, W, ket, E_out, workspace=None, stream=None):
+    """Environment update (see include/mpoevo.h). Tensors: E (Dbra, w, Dket), bra/ket
+    (D_l, d, D_r), W (w_l, d, d, w_r), all complex128 or all complex64 on the device."""
+    prec = _prec_of(E_in)
+    Dbl, d, Dbr = bra.shape
+    Dkl, _, Dkr = ket.shape
+    wl, _, _, wr = W.shape
+    dims = [Dbl, Dkl, Dbr, Dkr, d, wl, wr]
+    if workspace is None:
+        workspace = _workspace(workspace_size(CALL_ENV_UPDATE, dims, prec), E_in.device)
+    _check(load().env_update(h.ptr, side, prec, _ptr(E_in), _ptr(bra), _ptr(W), _ptr(ket), _ptr(E_out),
+                             _iarr(dims), _ptr(workspace), workspace.numel(), _stream(stream)), h)
+
+
+def local_apply(h: Handle, Lenv, W1, W2, M1, M2, Renv, Theta, workspace=None, stream=None):
+    """Projected two-site tensor into Theta (complex128, (Dbra_l*d) x (d*Dbra_r))."""
+    prec = _prec_of(Lenv)
+    Dbl, wl, Dkl = Lenv.shape
+    Dkm = M1.shape[2]
+    Dkr = M2.shape[2]
+    Dbr, wr, _ = Renv.shape
+    d = M1.shape[1]
+    wm = W1.shape[3]
+    dims = [Dbl, Dkl, Dkm, Dkr, Dbr, d, wl, wm, wr]
+    if workspace is None:
+        workspace = _workspace(workspace_size(CALL_LOCAL_APPLY, dims, prec), Lenv.device)
+    _check(load().local_apply(h.ptr, 2, prec, _ptr(Lenv), _ptr(W1), _ptr(W2), _ptr(M1), _ptr(M2),
+                              _ptr(Renv), _ptr(Theta), _iarr(dims), _ptr(workspace), workspace.numel(),
+                              _stream(stream)), h)
+
+
+def truncate(h: Handle, Theta, Dmax: int, cutoff: float, direction: int, A_out, B_out,
+             k=None, discarded=None, norm=None, sigma=None, workspace=None, stream=None):
+    """FP64 SVD truncation of Theta (m x n complex128); outputs A_out (m x kcap), B_out
+    (kcap x n); optional device scalars k (int32), discarded, norm (float64), sigma."""
+    m, n = Theta.shape
+    if workspace is None:
+        workspace = _workspace(workspace_size(CALL_TRUNCATE, [m, n], FP64), Theta.device)
+    _check(load().truncate(h.ptr, _ptr(Theta), m, n, Dmax, cutoff, direction, _ptr(A_out), _ptr(B_out),
+                           _ptr(k), _ptr(discarded), _ptr(norm), _ptr(sigma), _ptr(workspace),
+                           workspace.numel(), _stream(stream)), h)
+
+
+@dataclass
+class StepStats:
+    norm: float
+    discarded_max: float
+    discarded_sum: float
+    visits: int
+    max_bond: int
+    gflop: float
+
+
+class DeviceMPS:
+    """MPS on the device: complex128 site buffers of capacity Dmax * d * Dmax, bonds on the host."""
+
+    def __init__(self, sites, Dmax: int, device="cuda"):
+        torch = _torch()
+        self.L = len(sites)
+        self.d = sites[0].shape[1]
+        self.Dmax = Dmax
+        self.bond = [1] + [int(s.shape[2]) for s in sites]
+        cap = Dmax * self.d * Dmax
+        self.buf = []
+        for s in sites:
+            if s.shape[0] > Dmax or s.shape[2] > Dmax:
+                raise MpoevoError(ESHAPE, "site bond exceeds Dmax")
+            t = torch.zeros(cap, dtype=torch.complex128, device=device)
+            flat = torch.from_numpy(np.ascontiguousarray(s, dtype=np.complex128).reshape(-1))
+            t[: flat.numel()].copy_(flat)
+            self.buf.append(t)
+
+    def to_numpy(self):
+        out = []
+        for i, t in enumerate(self.buf):
+            a, b = self.bond[i], self.bond[i + 1]
+            out.append(t[: a * self.d * b].cpu().numpy().reshape(a, self.d, b).copy())
+        return out
+
+
+class DeviceMPO:
+    """Per-site MPO tensors on the device (complex128)."""
+
+    def __init__(self, Ws, device="cuda"):
+        torch = _torch()
+        self.L = len(Ws)
+        self.d = Ws[0].shape[1]
+        self.w = [int(Ws[0].shape[0])] + [int(W.shape[3]) for W in Ws]
+        cache = {}
+        self.buf = []
+        for W in Ws:
+            key = id(W)
+            if key not in cache:
+                cache[key] = torch.from_numpy(np.ascontiguousarray(W, dtype=np.complex128)).to(device)
+            self.buf.append(cache[key])
+
+
+def step_workspace(mps: DeviceMPS, mpo: DeviceMPO, prec: int):
+    dims = [mps.L, mps.d, mps.Dmax, max(mpo.w)]
+    return _workspace(workspace_size(CALL_STEP, dims, prec), mps.buf[0].device)
+
+
+def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int = FP64,
+         cutoff: float = 1e-14, input_right_canonical: bool = False, workspace=None,
+         stream=None) -> StepStats:
+    """One time step of the variational fit; mps is updated in place (see include/mpoevo.h)."""
+    if workspace is None:
+        workspace = step_workspace(mps, mpo, prec)
+    bond = _iarr(mps.bond)
+    sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
+    wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
+    cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
+    cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
+    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)))
+    st = _Stats()
+    _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
+                       _ptr(workspace), workspace.numel(), _stream(stream)), h)
+    mps.bond = [bond[i] for i in range(mps.L + 1)]
+    return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop)

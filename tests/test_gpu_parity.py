@@ -1,0 +1,260 @@
+"""GPU parity of the C ABI device calls against the CPU oracle (MI355X only).
+
+Every case prints its name, seed and shape before touching the GPU. Tolerances:
+  FP64 contractions: relative Frobenius error <= 1e-12;
+  FP32 contractions: relative Frobenius error <= 2e-5 (float accumulation over K <= 2048 terms);
+  FP64 SVD: singular values to 1e-12 relative to sigma_1, factors orthonormal to 1e-12,
+            the rank-k product equal to the optimal rank-k approximation to 1e-11.
+  Time step (gauge-invariant): infidelity against the oracle step from the same input
+            <= 1e-12 (FP64) / 1e-9 (FP32); |norm - oracle norm| <= 1e-10 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import dense, fit as ofit, mpo as ompo
+from paper_2302_14181_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mp():
+    from paper_2302_14181_amd import mpoevo
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mpoevo.load()
+    return mpoevo
+
+
+@pytest.fixture(scope="module")
+def handle(mp):
+    h = mp.Handle(0)
+    yield h
+    h.close()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _dev(x, prec64=True):
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128))
+    if not prec64:
+        t = t.to(torch.complex64)
+    return t.cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def _cn(rng, *shape):
+    return wl.complex_normal(rng, shape)
+
+
+ENV_CASES = [  # Dbra_l, Dket_l, Dbra_r, Dket_r, d, w_l, w_r
+    (1, 1, 2, 2, 2, 3, 3),
+    (37, 45, 29, 33, 2, 3, 3),
+    (64, 64, 64, 64, 2, 8, 8),
+    (100, 131, 140, 77, 3, 4, 5),
+    (130, 130, 130, 130, 2, 6, 6),
+]
+
+
+@pytest.mark.parametrize("prec64", [True, False], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("side", ["left", "right"])
+@pytest.mark.parametrize("dims", ENV_CASES, ids=[str(c) for c in ENV_CASES])
+def test_env_update_parity(mp, handle, dims, side, prec64):
+    Dbl, Dkl, Dbr, Dkr, d, wl_, wr = dims
+    rng = np.random.default_rng(sum(dims))
+    _say("env_update", side, "fp64" if prec64 else "fp32", dims)
+    bra, ket, W = _cn(rng, Dbl, d, Dbr), _cn(rng, Dkl, d, Dkr), _cn(rng, wl_, d, d, wr)
+    if side == "left":
+        E = _cn(rng, Dbl, wl_, Dkl)
+        ref = ofit.env_left(E, bra, W, ket)
+        out = torch.zeros((Dbr, wr, Dkr), dtype=torch.complex128 if prec64 else torch.complex64, device="cuda")
+        mp.env_update(handle, mp.LEFT, _dev(E, prec64), _dev(bra, prec64), _dev(W, prec64), _dev(ket, prec64), out)
+    else:
+        E = _cn(rng, Dbr, wr, Dkr)
+        ref = ofit.env_right(E, bra, W, ket)
+        out = torch.zeros((Dbl, wl_, Dkl), dtype=torch.complex128 if prec64 else torch.complex64, device="cuda")
+        mp.env_update(handle, mp.RIGHT, _dev(E, prec64), _dev(bra, prec64), _dev(W, prec64), _dev(ket, prec64), out)
+    torch.cuda.synchronize()
+    err = _rel(out.cpu().numpy().astype(np.complex128), ref)
+    assert err < (1e-12 if prec64 else 2e-5), err
+
+
+@pytest.mark.parametrize("prec64", [True, False], ids=["fp64", "fp32"])
+def test_env_update_microbench_shape(mp, handle, prec64):
+    """The D = 256, d = 2, w = 8 microbenchmark operands (seed 0), both sides; sampled full-size check."""
+    _say("env_update microbench D=256 w=8", "fp64" if prec64 else "fp32")
+    E, M, N, W = wl.env_microbench_inputs(0)
+    ref = ofit.env_left(E, N, W, M)
+    out = torch.zeros((256, 8, 256), dtype=torch.complex128 if prec64 else torch.complex64, device="cuda")
+    mp.env_update(handle, mp.LEFT, _dev(E, prec64), _dev(N, prec64), _dev(W, prec64), _dev(M, prec64), out)
+    torch.cuda.synchronize()
+    assert _rel(out.cpu().numpy().astype(np.complex128), ref) < (1e-12 if prec64 else 2e-5)
+    ref = ofit.env_right(E, N, W, M)
+    mp.env_update(handle, mp.RIGHT, _dev(E, prec64), _dev(N, prec64), _dev(W, prec64), _dev(M, prec64), out)
+    torch.cuda.synchronize()
+    assert _rel(out.cpu().numpy().astype(np.complex128), ref) < (1e-12 if prec64 else 2e-5)
+
+
+LA_CASES = [  # Dbra_l, Dket_l, Dket_m, Dket_r, Dbra_r, d, w_l, w_m, w_r
+    (1, 1, 2, 4, 4, 2, 3, 3, 3),
+    (33, 40, 47, 29, 35, 2, 3, 3, 3),
+    (64, 64, 64, 64, 64, 2, 6, 6, 6),
+    (20, 31, 27, 18, 22, 3, 4, 5, 4),
+]
+
+
+@pytest.mark.parametrize("prec64", [True, False], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("dims", LA_CASES, ids=[str(c) for c in LA_CASES])
+def test_local_apply_parity(mp, handle, dims, prec64):
+    Dbl, Dkl, Dkm, Dkr, Dbr, d, wl_, wm, wr = dims
+    rng = np.random.default_rng(7 + sum(dims))
+    _say("local_apply", "fp64" if prec64 else "fp32", dims)
+    L = _cn(rng, Dbl, wl_, Dkl)
+    M1, M2 = _cn(rng, Dkl, d, Dkm), _cn(rng, Dkm, d, Dkr)
+    W1, W2 = _cn(rng, wl_, d, d, wm), _cn(rng, wm, d, d, wr)
+    R = _cn(rng, Dbr, wr, Dkr)
+    ref = ofit.theta_two_site(L, M1, W1, M2, W2, R).reshape(Dbl * d, d * Dbr)
+    th = torch.zeros((Dbl * d, d * Dbr), dtype=torch.complex128, device="cuda")
+    mp.local_apply(handle, _dev(L, prec64), _dev(W1, prec64), _dev(W2, prec64), _dev(M1, prec64),
+                   _dev(M2, prec64), _dev(R, prec64), th)
+    torch.cuda.synchronize()
+    err = _rel(th.cpu().numpy(), ref)
+    assert err < (1e-12 if prec64 else 2e-5), err
+
+
+TR_CASES = [(1, 1), (2, 2), (2, 7), (9, 3), (32, 32), (64, 40), (40, 64), (130, 127), (256, 256), (300, 200)]
+
+
+def _graded(rng, m, n, decay):
+    """Random matrix with singular values decaying like exp(-decay * i)."""
+    r = min(m, n)
+    U, _ = np.linalg.qr(_cn(rng, m, r))
+    V, _ = np.linalg.qr(_cn(rng, n, r))
+    s = np.exp(-decay * np.arange(r))
+    return (U * s) @ V.conj().T
+
+
+@pytest.mark.parametrize("direction", [0, 1], ids=["left", "right"])
+@pytest.mark.parametrize("shape", TR_CASES, ids=[str(c) for c in TR_CASES])
+def test_truncate_parity(mp, handle, shape, direction):
+    m, n = shape
+    rng = np.random.default_rng(m * 1000 + n)
+    _say("truncate", shape, "dir", direction)
+    X = _cn(rng, m, n) if (m * n) % 2 == 0 else _graded(rng, m, n, 0.3)
+    Dmax = max(1, min(m, n) - 3)
+    kcap = min(Dmax, m, n)
+    A = torch.zeros((m, kcap), dtype=torch.complex128, device="cuda")
+    B = torch.zeros((kcap, n), dtype=torch.complex128, device="cuda")
+    k = torch.zeros(1, dtype=torch.int32, device="cuda")
+    disc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sig = torch.zeros(min(m, n), dtype=torch.float64, device="cuda")
+    mp.truncate(handle, _dev(X), Dmax, 1e-14, direction, A, B, k, disc, nrm, sig)
+    torch.cuda.synchronize()
+    handle.check_solver()
+    U, S, Vh = np.linalg.svd(X, full_matrices=False)
+    kk = int(k.item())
+    kref = max(1, min(Dmax, int(np.count_nonzero(S > 1e-14 * S[0]))))
+    assert kk == kref
+    assert np.max(np.abs(sig.cpu().numpy() - S)) < 1e-12 * S[0]
+    a, b = A.cpu().numpy(), B.cpu().numpy()
+    assert np.max(np.abs(a[:, kk:])) == 0 and np.max(np.abs(b[kk:])) == 0
+    approx = U[:, :kk] @ np.diag(S[:kk]) @ Vh[:kk]
+    assert np.max(np.abs(a @ b - approx)) < 1e-11 * S[0]
+    iso = a[:, :kk] if direction == 0 else b[:kk].conj().T
+    assert np.max(np.abs(iso.conj().T @ iso - np.eye(kk))) < 1e-12
+    tot = np.sum(S ** 2)
+    assert abs(disc.item() - np.sum(S[kk:] ** 2) / tot) < 1e-12
+    assert abs(nrm.item() - np.sqrt(np.sum(S[:kk] ** 2))) < 1e-12 * S[0]
+
+
+def test_truncate_rank_deficient(mp, handle):
+    _say("truncate rank-deficient 64x48 rank 5")
+    rng = np.random.default_rng(5)
+    X = _cn(rng, 64, 5) @ _cn(rng, 5, 48)
+    A = torch.zeros((64, 48), dtype=torch.complex128, device="cuda")
+    B = torch.zeros((48, 48), dtype=torch.complex128, device="cuda")
+    k = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mp.truncate(handle, _dev(X), 64, 1e-12, 0, A, B, k)
+    torch.cuda.synchronize()
+    assert int(k.item()) == 5
+    assert np.max(np.abs(A.cpu().numpy() @ B.cpu().numpy() - X)) < 1e-12 * np.linalg.norm(X, 2)
+
+
+def _normalise(ms):
+    n = ofit.norm(ms)
+    out = [m.copy() for m in ms]
+    out[0] = out[0] / n
+    return out
+
+
+def _gpu_step(mp, handle, psi, W, D, prec, nsweeps=2, canonical=False):
+    dm = mp.DeviceMPS(psi, Dmax=D)
+    dw = mp.DeviceMPO([W] * len(psi))
+    st = mp.step(handle, dm, dw, nsweeps=nsweeps, prec=prec, input_right_canonical=canonical)
+    return dm.to_numpy(), st
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", [(6, 4, 2, 8), (9, 6, 3, 16), (12, 8, 2, 24)], ids=str)
+def test_step_parity_random_state(mp, handle, case, prec):
+    L, D0, N, D = case
+    _say("step random", case, "fp64" if prec == 0 else "fp32")
+    rng = np.random.default_rng(L * 7 + D)
+    psi = _normalise(wl.random_mps(rng, L, 2, D0))
+    W, _ = mp.mpo_build(*[getattr(wl.tfim(1.0), k) for k in ("A", "B", "C", "Dloc")], N, -0.1j, mp.V2_EXTENDED)
+    ref, rst = ofit.fit_step(psi, W, Dmax=D, nsweeps=2)
+    out, st = _gpu_step(mp, handle, psi, W, D, prec)
+    infid = 1 - abs(ofit.overlap(out, ref)) ** 2
+    assert infid < (1e-12 if prec == 0 else 1e-9), infid
+    assert abs(st.norm - rst["norm"]) < 1e-10 * rst["norm"]
+    assert abs(ofit.norm(out) - 1) < 1e-12
+    assert st.visits == 4 * (L - 1)
+    assert abs(st.discarded_max - max(rst["discarded"])) < (1e-12 if prec == 0 else 1e-8)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_config1_trajectory(mp, handle, prec):
+    """Tiny TFIM configuration (L = 10, g = 1, order 2, dt = 0.05, all-up, D <= 16, 20 steps):
+    per-step fidelity against the oracle step from the same input, and the whole trajectory
+    against the oracle trajectory and the exact exp(-i t H)."""
+    _say("config1 trajectory", "fp64" if prec == 0 else "fp32")
+    L, D, dt = 10, 16, 0.05
+    H = wl.tfim(1.0)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -1j * dt, mp.V2_EXTENDED)
+    psi_gpu = wl.all_up(L)
+    psi_or = wl.all_up(L)
+    Hd = dense.dense_hamiltonian(ompo.hamiltonian_mpo(H), L)
+    v0 = dense.mps_to_dense(wl.all_up(L))
+    for step in range(20):
+        ref_same, _ = ofit.fit_step(psi_gpu, W, Dmax=D, nsweeps=2)
+        out, st = _gpu_step(mp, handle, psi_gpu, W, D, prec, canonical=step > 0)
+        delta = 1 - abs(ofit.overlap(out, ref_same)) ** 2
+        assert delta < (1e-12 if prec == 0 else 1e-9), (step, delta)
+        psi_gpu = out
+        psi_or, _ = ofit.fit_step(psi_or, W, Dmax=D, nsweeps=2)
+    assert 1 - abs(ofit.overlap(psi_gpu, psi_or)) ** 2 < (1e-11 if prec == 0 else 1e-8)
+    exact = dense.expm_hermitian(-1j * dt * 20, Hd) @ v0
+    assert 1 - abs(np.vdot(dense.mps_to_dense(psi_gpu), exact)) ** 2 < 1e-5
+
+
+def test_step_rejects_bad_arguments(mp, handle):
+    _say("step argument errors")
+    psi = wl.all_up(4)
+    H = wl.tfim(1.0)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    dm = mp.DeviceMPS(psi, Dmax=4)
+    dw = mp.DeviceMPO([W] * 4)
+    with pytest.raises(mp.MpoevoError) as e:
+        mp.step(handle, dm, dw, nsweeps=0)
+    assert e.value.code == mp.EINVAL
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mp.MpoevoError) as e:
+        mp.step(handle, dm, dw, workspace=ws)
+    assert e.value.code == mp.ENOMEM
