@@ -127,8 +127,9 @@ int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void
 
 /*
  * truncate -- DEVICE, async on `stream`. FP64 SVD Theta = U S V^dag of an m x n complex128
- * matrix (row-major) by one-sided Jacobi, keeping k = min(Dmax, m, n, #{sigma_i > cutoff *
- * sigma_1}) >= 1 singular values (the truncation of the two-site update).
+ * matrix (row-major) by one-sided Jacobi, keeping k = min(Dmax, m, n, #{sigma_i > max(cutoff *
+ * sigma_1, 8 eps sqrt(max(m, n)) ||Theta||_F)}) >= 1 singular values (the truncation of the
+ * two-site update; the second bound drops singular values at the rounding level of Theta).
  *   direction LEFT  (left-to-right sweep): A_out = U_k (left-orthonormal), B_out = S_k V_k^dag
  *   direction RIGHT (right-to-left sweep): A_out = U_k S_k, B_out = V_k^dag (right-orthonormal)
  * Outputs have the static capacity kcap = min(Dmax, m, n): A_out is m x kcap, B_out is kcap x n
@@ -195,6 +196,7 @@ typedef struct {
   int visits;               /* number of bond visits (4 (L-1) for two sweeps) */
   int max_bond;             /* largest bond dimension of the result */
   double gflop;             /* algorithmic contraction work of the step (8 flop per complex MAC) */
+  int svd_sweeps_max;       /* largest number of Jacobi sweeps any truncation of the step needed */
 } mpoevo_step_stats;
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,

@@ -223,9 +223,9 @@ int device_init(Context& ctx) {
   if (e != hipSuccess) return hip_fail(ctx, e, "svd_configure");
   auto* ds = new DeviceState();
   ds->lds_max = lds;
-  e = hipMalloc(&ds->status, sizeof(int));
+  e = hipMalloc(&ds->status, 4 * sizeof(int));
   if (e != hipSuccess) { delete ds; return hip_fail(ctx, e, "hipMalloc(status)"); }
-  e = hipMemset(ds->status, 0, sizeof(int));
+  e = hipMemset(ds->status, 0, 4 * sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) { (void)hipFree(ds->status); delete ds; return hip_fail(ctx, e, "status init"); }
   ctx.dev = ds;
@@ -265,15 +265,22 @@ size_t step_ws(int L, int d, int Dmax, int wmax, int prec) {
 
 int check_solver_dev(Context& ctx) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
-  int st = 0;
-  hipError_t e = hipMemcpy(&st, ctx.dev->status, sizeof(int), hipMemcpyDeviceToHost);
+  int stv[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpy(stv, ctx.dev->status, sizeof(stv), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "reading the solver status");
-  if (st) {
-    e = hipMemset(ctx.dev->status, 0, sizeof(int));
+  ctx.max_sweeps = std::max(ctx.max_sweeps, stv[1]);
+  const int st = stv[0];
+  if (st || stv[1] || stv[2]) {
+    e = hipMemset(ctx.dev->status, 0, sizeof(stv));
     if (e != hipSuccess) return hip_fail(ctx, e, "clearing the solver status");
+  }
+  if (st) {
     if (st & kStatusNonFinite) { ctx.err = "truncate: non-finite singular values"; return MPOEVO_ENONFINITE; }
     if (st & kStatusBarrierTimeout) { ctx.err = "truncate: grid barrier timed out"; return MPOEVO_ESOLVER; }
-    ctx.err = "truncate: Jacobi SVD did not converge within its sweep limit";
+    float rel;
+    std::memcpy(&rel, &stv[2], sizeof(float));
+    ctx.err = "truncate: Jacobi SVD did not converge within its sweep limit (last sweep's largest "
+              "relative inner product " + std::to_string(rel) + ")";
     return MPOEVO_ESOLVER;
   }
   return MPOEVO_OK;
@@ -386,6 +393,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   double2* site_tmp2 = reinterpret_cast<double2*>(base + lay.off_site_tmp2);
   const int* w = mpo->w;
 
+  ctx.max_sweeps = 0;
   std::vector<int> Q(mps->bond_dim, mps->bond_dim + L + 1);  // ket bonds
   std::vector<int> P(Q);                                       // bra bonds (upper bounds)
   hipError_t e = hipSuccess;
@@ -538,6 +546,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     stats->visits = nvis;
     stats->max_bond = maxb;
     stats->gflop = gflop;
+    stats->svd_sweeps_max = ctx.max_sweeps;
   }
   if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
 #undef STEP_TRY

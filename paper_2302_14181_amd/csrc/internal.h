@@ -19,6 +19,7 @@ struct DeviceState;  // defined in device.hip
 struct Context {
   int device = 0;
   std::string err;
+  int max_sweeps = 0;  // largest Jacobi sweep count seen by mpoevo_check_solver / step
   DeviceState* dev = nullptr;
 };
 

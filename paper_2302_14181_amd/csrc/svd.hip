@@ -1,12 +1,19 @@
 // FP64 SVD of the projected two-site tensor by one-sided (Hestenes) Jacobi, and the truncation
 // of the two-site update (keep k <= Dmax singular values, split as U | S V^dag or U S | V^dag).
 //
-// Jacobi runs on the columns of X = Theta (if n <= m) or X = Theta^dag (otherwise), so the
-// number of columns is min(m, n). Each column of the work buffer holds X[:, j] (mx rows)
-// followed by the j-th column of the accumulated unitary (np rows, starting as the identity):
-// every plane rotation is applied to the whole stacked column, so the accumulated factor is
-// unitary to rounding whatever the singular values are, and the normalised columns of X carry
-// the other factor with high relative accuracy.
+// Jacobi runs on the columns of X = Theta (if n < m) or X = Theta^dag (if m < n), so the number
+// of columns is min(m, n); a square Theta is taken in the orientation whose accumulated factor
+// is the isometry the sweep direction keeps (U for left-to-right, V for right-to-left). Each
+// column of the work buffer holds X[:, j] (mx rows) followed by the j-th column of the
+// accumulated unitary (np rows, starting as the identity): every plane rotation is applied to
+// the whole stacked column, so the accumulated factor is unitary to rounding.
+//
+// Numerically zero columns: a column whose norm is at the rounding level of the matrix,
+// floor = 8 eps sqrt(mx) ||Theta||_F, only carries cancellation noise; rotating it against a
+// large column regenerates noise of its own size, so pairs with such a column are not rotated
+// and those singular values are treated as zero (never kept). All other pairs are rotated
+// until |x^dag y| <= tol |x| |y| (relative orthogonality to working precision), so the
+// normalised columns of X that are kept are orthonormal to tol.
 //
 // Parallel schedule: the np columns are cut into nb blocks of b columns; a round pairs the
 // blocks (round-robin), one workgroup per block pair loads its 2b stacked columns into LDS and
@@ -26,7 +33,8 @@ namespace mpoevo {
 namespace {
 
 constexpr int kJacThreads = 256;
-constexpr int kMaxSweeps = 40;
+constexpr int kMaxSweeps = 60;
+constexpr double kAcceptOrthogonality = 1e-13;  // columns this orthogonal need no further sweep
 constexpr unsigned long long kBarrierTimeoutTicks = 300000000ull;  // 3 s of the 100 MHz clock
 
 struct SvdWs {  // carved from the caller's workspace
@@ -34,7 +42,7 @@ struct SvdWs {  // carved from the caller's workspace
   double* sigma;
   int* perm;
   unsigned* bar;      // [0] arrival count, [1] generation, [2] timeout flag
-  int* sweep_rot;     // [kMaxSweeps]
+  unsigned* sweep_max;  // [kMaxSweeps] bits of the largest |x^dag y| / (|x| |y|) seen in a sweep
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -51,7 +59,7 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   off += align256(sizeof(int) * p.np);
   w.bar = reinterpret_cast<unsigned*>(base + off);
   off += 256;
-  w.sweep_rot = reinterpret_cast<int*>(base + off);
+  w.sweep_max = reinterpret_cast<unsigned*>(base + off);
   return w;
 }
 
@@ -89,7 +97,7 @@ __global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, Sv
   }
   if (blockIdx.x == 0) {
     if (threadIdx.x < 3) w.bar[threadIdx.x] = 0u;
-    for (int i = threadIdx.x; i < kMaxSweeps; i += blockDim.x) w.sweep_rot[i] = 0;
+    for (int i = threadIdx.x; i < kMaxSweeps; i += blockDim.x) w.sweep_max[i] = 0u;
   }
 }
 
@@ -124,9 +132,18 @@ __device__ bool grid_barrier(unsigned* bar, unsigned nblocks) {
 }
 
 __global__ __launch_bounds__(kJacThreads) void svd_jacobi_kernel(SvdPlan p, SvdWs w, double tol,
-                                                                 int* status) {
+                                                                 double accept, int* status) {
   extern __shared__ double2 cols[];  // [2b][H]
-  __shared__ int rotated;
+  __shared__ unsigned wg_max;  // bits of a non-negative float: integer order = value order
+  __shared__ double floor2_sh;
+  if (threadIdx.x == 0) {  // squared rounding floor from the initial column norms (fixed order)
+    double fro2 = 0.0;
+    for (int j = 0; j < p.nx; ++j) fro2 += w.sigma[j];
+    const double fl = 8.0 * 2.220446049250313e-16 * sqrt((double)p.mx);
+    floor2_sh = fl * fl * fro2;
+  }
+  __syncthreads();
+  const double floor2 = floor2_sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = kJacThreads / 64;
   const int two_b = 2 * p.b, H = p.H;
@@ -142,7 +159,7 @@ __global__ __launch_bounds__(kJacThreads) void svd_jacobi_kernel(SvdPlan p, SvdW
         const int g = (c < p.b) ? bp * p.b + c : bq * p.b + (c - p.b);
         cols[idx] = w.Y[(long long)g * H + row];
       }
-      if (tid == 0) rotated = 0;
+      if (tid == 0) wg_max = 0u;
       __syncthreads();
       for (int ir = 0; ir < two_b - 1; ++ir) {
         for (int pk = wave; pk < p.b; pk += nwaves) {
@@ -163,7 +180,10 @@ __global__ __launch_bounds__(kJacThreads) void svd_jacobi_kernel(SvdPlan p, SvdW
           gr = wave_sum(gr);
           gi = wave_sum(gi);
           const double g = hypot(gr, gi);
-          if (g > 0.0 && g > tol * sqrt(a) * sqrt(bb)) {
+          const double nrm = sqrt(a) * sqrt(bb);
+          const bool live = fmin(a, bb) > floor2;  // both columns above the rounding floor
+          if (live && lane == 0) atomicMax(&wg_max, __float_as_uint((float)fmin(g / nrm, 1.0)));
+          if (live && g > tol * nrm) {
             const double zeta = (bb - a) / (2.0 * g);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
@@ -174,7 +194,6 @@ __global__ __launch_bounds__(kJacThreads) void svd_jacobi_kernel(SvdPlan p, SvdW
               cx[row] = double2{c * u.x - s * evx, c * u.y - s * evy};
               cy[row] = double2{s * u.x + c * evx, s * u.y + c * evy};
             }
-            if (lane == 0) rotated = 1;
           }
         }
         __syncthreads();
@@ -184,20 +203,28 @@ __global__ __launch_bounds__(kJacThreads) void svd_jacobi_kernel(SvdPlan p, SvdW
         const int g = (c < p.b) ? bp * p.b + c : bq * p.b + (c - p.b);
         w.Y[(long long)g * H + row] = cols[idx];
       }
-      if (tid == 0 && rotated) atomicOr(&w.sweep_rot[sweep], 1);
+      if (tid == 0 && wg_max) atomicMax(&w.sweep_max[sweep], wg_max);
       ok = grid_barrier(w.bar, nblk);
     }
     if (!ok) break;
-    if (__hip_atomic_load(&w.sweep_rot[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+    // stop when no pair needed a rotation, or every pair was already orthogonal to `accept`
+    // (plane rotations at the rounding floor of the inner products can otherwise repeat forever)
+    const float mx = __uint_as_float(
+        __hip_atomic_load(&w.sweep_max[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+    if ((double)mx <= tol || (double)mx <= accept) break;
   }
   if (blockIdx.x == 0 && tid == 0) {
+    atomicMax(&status[1], sweep + 1);
     if (!ok) atomicOr(status, kStatusBarrierTimeout);
-    else if (sweep >= kMaxSweeps) atomicOr(status, kStatusNotConverged);
+    else if (sweep >= kMaxSweeps) {
+      atomicOr(status, kStatusNotConverged);
+      atomicMax(reinterpret_cast<unsigned*>(&status[2]), w.sweep_max[kMaxSweeps - 1]);
+    }
   }
 }
 
-// sigma_j = |X[:, j]| for j < nx (one wave per column).
-__global__ void svd_norms_kernel(SvdPlan p, SvdWs w, int* status) {
+// sigma_j = |X[:, j]| (squared if `squared`) for j < nx (one wave per column).
+__global__ void svd_norms_kernel(SvdPlan p, SvdWs w, int* status, int squared) {
   const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j >= p.nx) return;
@@ -206,7 +233,7 @@ __global__ void svd_norms_kernel(SvdPlan p, SvdWs w, int* status) {
   for (int row = lane; row < p.mx; row += 64) s = fma(c[row].x, c[row].x, fma(c[row].y, c[row].y, s));
   s = wave_sum(s);
   if (lane == 0) {
-    const double sg = sqrt(s);
+    const double sg = squared ? s : sqrt(s);
     if (!isfinite(sg)) atomicOr(status, kStatusNonFinite);
     w.sigma[j] = sg;
   }
@@ -236,9 +263,14 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(SvdPlan p, SvdWs w, in
   }
   __syncthreads();
   // sigma_max and the count above the cutoff
-  double smax = 0.0;
-  for (int i = 0; i < r; ++i) smax = fmax(smax, sig[i]);
-  cnt[t] = (t < r && sig[t] > 0.0 && sig[t] > cutoff * smax) ? 1 : 0;
+  double smax = 0.0, fro2 = 0.0;
+  for (int i = 0; i < r; ++i) {
+    smax = fmax(smax, sig[i]);
+    fro2 += sig[i] * sig[i];
+  }
+  const double floor_abs = 8.0 * 2.220446049250313e-16 * sqrt((double)p.mx) * sqrt(fro2);
+  const double thr = fmax(cutoff * smax, floor_abs);
+  cnt[t] = (t < r && sig[t] > 0.0 && sig[t] > thr) ? 1 : 0;
   __syncthreads();
   for (int off = 512; off > 0; off >>= 1) {
     if (t < off) cnt[t] += cnt[t + off];
@@ -374,8 +406,14 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         int direction, double2* A_out, double2* B_out, int* k_dev,
                         double* disc_dev, double* norm_dev, double* sigma_dev, void* ws,
                         int* status, hipStream_t st) {
+  if (p.m == p.n && p.on_theta != (direction == 1)) {  // square: keep the isometry exact
+    SvdPlan q = p;
+    q.on_theta = (direction == 1);
+    return svd_truncate(q, theta, Dmax, cutoff, direction, A_out, B_out, k_dev, disc_dev, norm_dev,
+                        sigma_dev, ws, status, st);
+  }
   SvdWs w = carve(p, ws);
-  int* k_shared = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(w.sweep_rot) +
+  int* k_shared = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(w.sweep_max) +
                                          align256(sizeof(int) * kMaxSweeps));
   const int kcap = std::min(Dmax, std::min(p.m, p.n));
   {
@@ -384,23 +422,26 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     hipLaunchKernelGGL(svd_init_kernel, dim3(blocks), dim3(256), 0, st, theta, p, w);
     MPOEVO_HIP_TRY(hipGetLastError());
   }
+  const int wpb = 4;
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, w,
+                     status, 1);
+  MPOEVO_HIP_TRY(hipGetLastError());
   {
-    const double tol = 4.0 * 2.220446049250313e-16 * std::sqrt((double)p.mx);
+    // Above the rounding floor of a length-mx inner product (|err| <= mx eps |x| |y|), so the
+    // sweep stops once every pair is orthogonal to working precision.
+    const double tol = 2.220446049250313e-16 * std::max(16.0, (double)p.mx);
     const int nblk = p.nb / 2;
     SvdPlan pp = p;
     SvdWs ww = w;
-    double tt = tol;
+    double tt = tol, acc = kAcceptOrthogonality;
     int* stp = status;
-    void* args[] = {&pp, &ww, &tt, &stp};
+    void* args[] = {&pp, &ww, &tt, &acc, &stp};
     MPOEVO_HIP_TRY(hipLaunchCooperativeKernel((const void*)svd_jacobi_kernel, dim3(nblk),
                                               dim3(kJacThreads), args, (unsigned)p.lds, st));
   }
-  {
-    const int wpb = 4;
-    hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p,
-                       w, status);
-    MPOEVO_HIP_TRY(hipGetLastError());
-  }
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, w,
+                     status, 0);
+  MPOEVO_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, p, w, kcap, cutoff, k_dev,
                      disc_dev, norm_dev, sigma_dev, k_shared);
   MPOEVO_HIP_TRY(hipGetLastError());

@@ -48,7 +48,7 @@ class _Opts(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_double), ("discarded_max", ctypes.c_double),
                 ("discarded_sum", ctypes.c_double), ("visits", ctypes.c_int),
-                ("max_bond", ctypes.c_int), ("gflop", ctypes.c_double)]
+                ("max_bond", ctypes.c_int), ("gflop", ctypes.c_double), ("svd_sweeps_max", ctypes.c_int)]
 
 
 _lib = None
@@ -240,6 +240,7 @@ class StepStats:
     visits: int
     max_bond: int
     gflop: float
+    svd_sweeps_max: int
 
 
 class DeviceMPS:
@@ -307,4 +308,5 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
                        _ptr(workspace), workspace.numel(), _stream(stream)), h)
     mps.bond = [bond[i] for i in range(mps.L + 1)]
-    return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop)
+    return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
+                     st.svd_sweeps_max)

@@ -6,7 +6,8 @@ Every case prints its name, seed and shape before touching the GPU. Tolerances:
   FP64 SVD: singular values to 1e-12 relative to sigma_1, factors orthonormal to 1e-12,
             the rank-k product equal to the optimal rank-k approximation to 1e-11.
   Time step (gauge-invariant): infidelity against the oracle step from the same input
-            <= 1e-12 (FP64) / 1e-9 (FP32); |norm - oracle norm| <= 1e-10 relative.
+            <= 1e-12 (FP64) / 1e-9 (FP32); |norm - oracle norm| <= 1e-10 (FP64) / 1e-6 (FP32)
+            relative (the FP32 projection carries float rounding, ~1e-7 relative).
 """
 import numpy as np
 import pytest
@@ -160,11 +161,12 @@ def test_truncate_parity(mp, handle, shape, direction):
     handle.check_solver()
     U, S, Vh = np.linalg.svd(X, full_matrices=False)
     kk = int(k.item())
-    kref = max(1, min(Dmax, int(np.count_nonzero(S > 1e-14 * S[0]))))
+    floor = 8 * np.finfo(float).eps * np.sqrt(max(m, n)) * np.linalg.norm(X)
+    kref = max(1, min(Dmax, int(np.count_nonzero(S > max(1e-14 * S[0], floor)))))
     assert kk == kref
     assert np.max(np.abs(sig.cpu().numpy() - S)) < 1e-12 * S[0]
     a, b = A.cpu().numpy(), B.cpu().numpy()
-    assert np.max(np.abs(a[:, kk:])) == 0 and np.max(np.abs(b[kk:])) == 0
+    assert not np.any(a[:, kk:]) and not np.any(b[kk:])
     approx = U[:, :kk] @ np.diag(S[:kk]) @ Vh[:kk]
     assert np.max(np.abs(a @ b - approx)) < 1e-11 * S[0]
     iso = a[:, :kk] if direction == 0 else b[:kk].conj().T
@@ -213,7 +215,7 @@ def test_step_parity_random_state(mp, handle, case, prec):
     out, st = _gpu_step(mp, handle, psi, W, D, prec)
     infid = 1 - abs(ofit.overlap(out, ref)) ** 2
     assert infid < (1e-12 if prec == 0 else 1e-9), infid
-    assert abs(st.norm - rst["norm"]) < 1e-10 * rst["norm"]
+    assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]
     assert abs(ofit.norm(out) - 1) < 1e-12
     assert st.visits == 4 * (L - 1)
     assert abs(st.discarded_max - max(rst["discarded"])) < (1e-12 if prec == 0 else 1e-8)
@@ -235,6 +237,7 @@ def test_config1_trajectory(mp, handle, prec):
     for step in range(20):
         ref_same, _ = ofit.fit_step(psi_gpu, W, Dmax=D, nsweeps=2)
         out, st = _gpu_step(mp, handle, psi_gpu, W, D, prec, canonical=step > 0)
+        print(f"  step {step}: bonds {max(st.max_bond, 1)} sweeps {st.svd_sweeps_max}", flush=True)
         delta = 1 - abs(ofit.overlap(out, ref_same)) ** 2
         assert delta < (1e-12 if prec == 0 else 1e-9), (step, delta)
         psi_gpu = out
