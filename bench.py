@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64_MFMA = 78.6e12
 PEAK_FP64_VALU = 78.6e12
+PEAK_HBM = 8.0e12
 
 
 def env_microbench(mp, h, torch, prec64: bool, reps: int = 50):
@@ -106,6 +107,25 @@ def main():
     prec = mp.FP32 if args.prec == "fp32" else mp.FP64
     sec_step, wall_step, st = run(prec, args.steps, args.warmup)
     gflop = float(np.mean([x.gflop for x in st]))
+
+    # one extra (untimed) step with per-kernel-class HIP-event timing on the same stream
+    dmp = mp.DeviceMPS(psi0, Dmax=D)
+    mp.step(h, dmp, dw, prec=prec)
+    prof = mp.step(h, dmp, dw, prec=prec, input_right_canonical=True, profile=True).profile
+    classes = {
+        "jacobi_svd": {"ms": prof["t_jacobi_ms"], "launches": prof["n_jacobi"], "work": prof["jacobi_gflop"],
+                       "work_unit": "GFLOP", "bound": "alu", "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"},
+        "complex_gemm": {"ms": prof["t_gemm_ms"], "launches": prof["n_gemm"], "work": prof["gemm_gflop"],
+                         "work_unit": "GFLOP", "bound": "mfma",
+                         "peak": (PEAK_FP32_MFMA if prec == mp.FP32 else PEAK_FP64_MFMA) / 1e12, "unit": "TFLOP/s"},
+        "w_contraction": {"ms": prof["t_wmix_ms"], "launches": prof["n_wmix"], "work": prof["wmix_gbyte"],
+                          "work_unit": "GB", "bound": "hbm", "peak": PEAK_HBM / 1e9, "unit": "GB/s"},
+    }
+    for c in classes.values():
+        c["achieved"] = c["work"] / (c["ms"] * 1e-3) / (1e3 if c["unit"] == "TFLOP/s" else 1.0) if c["ms"] > 0 else 0.0
+        c["frac"] = c["achieved"] / c["peak"] if c["peak"] else 0.0
+        c["avg_launch_us"] = 1e3 * c["ms"] / max(c["launches"], 1)
+    dominant = max(classes, key=lambda k: classes[k]["ms"])
     fp64_sec = None
     if not args.no_fp64 and prec == mp.FP32:
         fp64_sec, _, _ = run(mp.FP64, max(1, args.steps // 2), args.warmup)
@@ -163,9 +183,11 @@ def main():
         "env_microbench": {"D": 256, "d": 2, "w": 8, "fp32_ms": mb32_ms, "fp64_ms": mb64_ms,
                            "fp32_tflops": mb_tflops, "fp64_tflops": mb_flop / (mb64_ms * 1e-3) / 1e12,
                            "fp32_frac_of_mfma_peak": mb_tflops * 1e12 / PEAK_FP32_MFMA},
-        "roofline": {"bound": "mfma", "kernel": "env_update chain at D=256 (complex GEMMs on FP32 MFMA)",
-                     "achieved": mb_tflops, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": mb_tflops * 1e12 / PEAK_FP32_MFMA, "traffic": None},
+        "roofline": {"bound": classes[dominant]["bound"], "kernel": dominant,
+                     "achieved": classes[dominant]["achieved"], "peak": classes[dominant]["peak"],
+                     "unit": classes[dominant]["unit"], "frac": classes[dominant]["frac"],
+                     "avg_launch_us": classes[dominant]["avg_launch_us"], "traffic": None},
+        "kernel_classes_one_step": classes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -148,8 +148,9 @@ int truncate(mpoevo_handle h, const void* Theta, int m, int n, int Dmax, double 
              void* stream);
 
 /* After a stream synchronisation: MPOEVO_OK, or ESOLVER if any truncate/step issued on this
- * handle since the previous check did not converge (flag kept in device memory of the handle). */
-int mpoevo_check_solver(mpoevo_handle h);
+ * handle since the previous check did not converge (flag kept in device memory of the handle).
+ * *max_sweeps (nullable) receives the largest number of Jacobi sweeps any of those SVDs took. */
+int mpoevo_check_solver(mpoevo_handle h, int* max_sweeps);
 
 /*
  * step -- one time step (Sec. 8.2: a variational sweeping optimisation of the time-evolved MPS
@@ -187,6 +188,7 @@ typedef struct {
   int prec;
   double cutoff;
   int input_right_canonical;
+  int profile;  /* nonzero: time the kernel classes with HIP events (adds host overhead) */
 } mpoevo_step_opts;
 
 typedef struct {
@@ -197,6 +199,14 @@ typedef struct {
   int max_bond;             /* largest bond dimension of the result */
   double gflop;             /* algorithmic contraction work of the step (8 flop per complex MAC) */
   int svd_sweeps_max;       /* largest number of Jacobi sweeps any truncation of the step needed */
+  /* filled when opts->profile: summed kernel durations (HIP events on the step's stream),
+     launch counts and algorithmic work of the three kernel classes of the step */
+  double t_jacobi_ms, jacobi_gflop;  /* one-sided Jacobi kernel; 36 mx flop per column pair visit */
+  int n_jacobi;
+  double t_gemm_ms, gemm_gflop;      /* complex matrix products (8 flop per complex MAC) */
+  int n_gemm;
+  double t_wmix_ms, wmix_gbyte;      /* short-leg contractions with W (bytes read + written) */
+  int n_wmix;
 } mpoevo_step_stats;
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,

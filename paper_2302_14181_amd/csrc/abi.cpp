@@ -139,9 +139,13 @@ int truncate(mpoevo_handle h, const void* Theta, int m, int n, int Dmax, double 
                               discarded_dev, norm_dev, sigma_dev, workspace, workspace_bytes, stream);
 }
 
-int mpoevo_check_solver(mpoevo_handle h) {
+int mpoevo_check_solver(mpoevo_handle h, int* max_sweeps) {
   if (!h) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_check_solver: NULL handle");
-  return mpoevo::check_solver_dev(*reinterpret_cast<mpoevo::Context*>(h));
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  ctx->max_sweeps = 0;
+  const int rc = mpoevo::check_solver_dev(*ctx);
+  if (max_sweeps) *max_sweeps = ctx->max_sweeps;
+  return rc;
 }
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,

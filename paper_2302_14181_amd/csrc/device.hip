@@ -31,8 +31,9 @@
 namespace mpoevo {
 
 struct DeviceState {
-  int* status = nullptr;  // sticky status bits (device int)
+  int* status = nullptr;  // sticky status words (device ints)
   int lds_max = 0;
+  std::vector<hipEvent_t> events;  // reused by profiled steps
 };
 
 namespace {
@@ -44,6 +45,44 @@ int hip_fail(Context& ctx, hipError_t e, const char* what) {
   ctx.err = std::string(what) + ": " + hipGetErrorString(e);
   return MPOEVO_EHIP;
 }
+
+// Optional per-kernel-class timing of a step with HIP events on its stream.
+struct Prof {
+  enum Kind { kJacobi = 0, kGemm = 1, kWmix = 2 };
+  DeviceState* ds = nullptr;
+  hipStream_t st = nullptr;
+  struct Rec { int kind; size_t e0; double work; };
+  std::vector<Rec> recs;
+  size_t next = 0;
+  hipError_t event(size_t i, hipEvent_t* out) {
+    while (ds->events.size() <= i) {
+      hipEvent_t e;
+      MPOEVO_HIP_TRY(hipEventCreate(&e));
+      ds->events.push_back(e);
+    }
+    *out = ds->events[i];
+    return hipSuccess;
+  }
+  // two fresh events; the caller records them around its launch
+  hipError_t pair(hipEvent_t* a, hipEvent_t* b, size_t* first) {
+    *first = next;
+    MPOEVO_HIP_TRY(event(next++, a));
+    return event(next++, b);
+  }
+  hipError_t begin(size_t* first) {
+    hipEvent_t a, b;
+    MPOEVO_HIP_TRY(pair(&a, &b, first));
+    return hipEventRecord(a, st);
+  }
+  hipError_t end(int kind, size_t first, double work) {
+    MPOEVO_HIP_TRY(hipEventRecord(ds->events[first + 1], st));
+    recs.push_back({kind, first, work});
+    return hipSuccess;
+  }
+};
+
+#define PROF_BEGIN(pr, tok) size_t tok = 0; if (pr) MPOEVO_HIP_TRY((pr)->begin(&tok))
+#define PROF_END(pr, tok, kind, work) if (pr) MPOEVO_HIP_TRY((pr)->end(kind, tok, work))
 
 // ----------------------------------------------------------------------------- small kernels
 __global__ void cast_c128_c64(const double2* __restrict__ in, float2* __restrict__ out, long long n) {
@@ -95,59 +134,81 @@ hipError_t set_boundary(void* E, int w, bool fp64, hipStream_t st) {
 // ------------------------------------------------------------------ contraction building blocks
 // LB[a'][s'][beta][b] = sum E[a'][alpha][a] ket[a][s][b] W[alpha][s'][s][beta]
 // E: (P, wl, Qa), ket: (Qa, d, Qb), W: (wl, d, d, wr). tmp holds P*wl*d*Qb complex.
+double gemm_flop(const GemmDesc& g) { return 8.0 * g.M * g.N * (double)g.K * g.batch; }
+
+hipError_t gemm_timed(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st, Prof* pr) {
+  PROF_BEGIN(pr, tok);
+  MPOEVO_HIP_TRY(gemm_launch(g, fp64, out_fp64, st));
+  PROF_END(pr, tok, Prof::kGemm, gemm_flop(g));
+  return hipSuccess;
+}
+
 hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, void* tmp,
-                      void* LB, int P, int wl, int Qa, int d, int Qb, int wr, hipStream_t st) {
+                      void* LB, int P, int wl, int Qa, int d, int Qb, int wr, hipStream_t st,
+                      Prof* pr = nullptr) {
   GemmDesc g{};
   g.A = E; g.B = ket; g.C = tmp;
   g.M = P * wl; g.N = d * Qb; g.K = Qa; g.batch = 1;
   g.sAm = Qa; g.sAk = 1; g.sBk = (long long)d * Qb; g.sBn = 1; g.sCm = (long long)d * Qb; g.sCn = 1;
-  MPOEVO_HIP_TRY(gemm_launch(g, fp64, false, st));
-  return wmix_left(fp64, tmp, W, LB, P, Qb, wl, d, wr, st);
+  MPOEVO_HIP_TRY(gemm_timed(g, fp64, false, st, pr));
+  PROF_BEGIN(pr, tok);
+  MPOEVO_HIP_TRY(wmix_left(fp64, tmp, W, LB, P, Qb, wl, d, wr, st));
+  const double cs = fp64 ? 16.0 : 8.0;
+  PROF_END(pr, tok, Prof::kWmix, cs * ((double)P * wl * d * Qb + (double)P * d * wr * Qb + wl * d * d * wr));
+  return hipSuccess;
 }
 
 // RB[beta][b][t'][c'] = sum W[beta][t'][t][gamma] ket[b][t][c] E[c'][gamma][c]
 // ket: (Qa, d, Qb), E: (Pr, wr, Qb), W: (wl, d, d, wr). tmp holds Qa*d*Pr*wr complex.
 hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W, void* tmp,
-                       void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st) {
+                       void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st,
+                       Prof* pr = nullptr) {
   GemmDesc g{};
   g.A = ket; g.B = E; g.C = tmp;
   g.M = Qa * d; g.N = Pr * wr; g.K = Qb; g.batch = 1;
   g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sBn = Qb; g.sCm = (long long)Pr * wr; g.sCn = 1;
-  MPOEVO_HIP_TRY(gemm_launch(g, fp64, false, st));
-  return wmix_right(fp64, tmp, W, RB, Qa, Pr, wl, d, wr, st);
+  MPOEVO_HIP_TRY(gemm_timed(g, fp64, false, st, pr));
+  PROF_BEGIN(pr, tok);
+  MPOEVO_HIP_TRY(wmix_right(fp64, tmp, W, RB, Qa, Pr, wl, d, wr, st));
+  const double cs = fp64 ? 16.0 : 8.0;
+  PROF_END(pr, tok, Prof::kWmix, cs * ((double)Qa * d * Pr * wr + (double)wl * Qa * d * Pr + wl * d * d * wr));
+  return hipSuccess;
 }
 
 // Lnew[b'][beta][b] = sum conj(bra[a'][s'][b']) LB[a'][s'][beta][b]; bra: (Pa, d, Pb).
 hipError_t left_env_from_block(bool fp64, const void* bra, const void* LB, void* Lnew, int Pa,
-                               int d, int Pb, int wr, int Qb, hipStream_t st) {
+                               int d, int Pb, int wr, int Qb, hipStream_t st,
+                         Prof* pr = nullptr) {
   GemmDesc g{};
   g.A = bra; g.B = LB; g.C = Lnew;
   g.M = Pb; g.N = wr * Qb; g.K = Pa * d; g.batch = 1;
   g.sAm = 1; g.sAk = Pb; g.conjA = true;
   g.sBk = (long long)wr * Qb; g.sBn = 1; g.sCm = (long long)wr * Qb; g.sCn = 1;
-  return gemm_launch(g, fp64, false, st);
+  return gemm_timed(g, fp64, false, st, pr);
 }
 
 // Rnew[a'][alpha][a] = sum conj(bra[a'][t'][c']) RB[alpha][a][t'][c']; bra: (Pa, d, Pb).
 hipError_t right_env_from_block(bool fp64, const void* bra, const void* RB, void* Rnew, int Pa,
-                                int d, int Pb, int wl, int Qa, hipStream_t st) {
+                                int d, int Pb, int wl, int Qa, hipStream_t st,
+                         Prof* pr = nullptr) {
   GemmDesc g{};
   g.A = bra; g.B = RB; g.C = Rnew;
   g.M = Pa; g.N = wl * Qa; g.K = d * Pb; g.batch = 1;
   g.sAm = (long long)d * Pb; g.sAk = 1; g.conjA = true;
   g.sBk = 1; g.sBn = (long long)d * Pb; g.sCm = (long long)wl * Qa; g.sCn = 1;
-  return gemm_launch(g, fp64, false, st);
+  return gemm_timed(g, fp64, false, st, pr);
 }
 
 // Theta[(a',s')][(t',c')] = sum LB[(a',s')][(beta,b)] RB[(beta,b)][(t',c')], complex128 out.
 hipError_t theta_product(bool fp64, const void* LB, const void* RB, void* theta, int Pa, int d,
-                         int wm, int Qm, int Pc, hipStream_t st) {
+                         int wm, int Qm, int Pc, hipStream_t st,
+                         Prof* pr = nullptr) {
   GemmDesc g{};
   g.A = LB; g.B = RB; g.C = theta;
   g.M = Pa * d; g.N = d * Pc; g.K = wm * Qm; g.batch = 1;
   g.sAm = (long long)wm * Qm; g.sAk = 1; g.sBk = (long long)d * Pc; g.sBn = 1;
   g.sCm = (long long)d * Pc; g.sCn = 1;
-  return gemm_launch(g, fp64, true, st);
+  return gemm_timed(g, fp64, true, st, pr);
 }
 
 // Site product site[a][s][b] <- sum_c site_in[a][s][c] R[c][b] (complex128), used to absorb
@@ -165,8 +226,8 @@ hipError_t absorb_right(const void* site_in, const void* R, void* site_out, int 
 struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
   size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
-      off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, total;
-  SvdPlan plan;
+      off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
+      total;
 };
 
 StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
@@ -179,7 +240,6 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.tmpcap = (size_t)Dmax * wmax * d * Dmax;
   s.wcap = (size_t)wmax * d * d * wmax;
   s.thetacap = (size_t)d * Dmax * d * Dmax;
-  s.plan = svd_plan(d * Dmax, d * Dmax);
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o += a256(bytes); return at; };
   s.off_phi = take(sizeof(double2) * s.sitecap * L);
@@ -198,6 +258,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_nbuf = take(sizeof(double) * (size_t)8 * L);
   s.off_site_tmp = take(sizeof(double2) * s.sitecap);
   s.off_site_tmp2 = take(sizeof(double2) * s.sitecap);
+  s.off_sweeps = take(sizeof(int) * (size_t)8 * L);
   s.total = o;
   return s;
 }
@@ -235,6 +296,7 @@ int device_init(Context& ctx) {
 void device_fini(Context& ctx) {
   if (!ctx.dev) return;
   (void)hipSetDevice(ctx.device);
+  for (hipEvent_t ev : ctx.dev->events) (void)hipEventDestroy(ev);
   (void)hipFree(ctx.dev->status);
   delete ctx.dev;
   ctx.dev = nullptr;
@@ -257,7 +319,9 @@ size_t local_apply_ws(const int* dims, int prec) {
   return a256(tmp) + a256(cs * Dbl * d * wm * Dkm) + a256(cs * wm * Dkm * d * Dbr);
 }
 
-size_t truncate_ws(int m, int n) { return svd_plan(m, n).ws; }
+size_t truncate_ws(int m, int n) {
+  return std::max(svd_plan(m, n, MPOEVO_LEFT).ws, svd_plan(m, n, MPOEVO_RIGHT).ws);
+}
 
 size_t step_ws(int L, int d, int Dmax, int wmax, int prec) {
   return step_layout(L, d, Dmax, wmax, prec).total;
@@ -341,8 +405,8 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
                  int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
                  double* norm_dev, double* sigma_dev, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
-  const SvdPlan p = svd_plan(m, n);
-  hipError_t e = svd_truncate(p, static_cast<const double2*>(Theta), Dmax, cutoff, direction,
+  const SvdPlan p = svd_plan(m, n, direction);
+  hipError_t e = svd_truncate(p, static_cast<const double2*>(Theta), Dmax, cutoff,
                               static_cast<double2*>(A_out), static_cast<double2*>(B_out), k_dev,
                               discarded_dev, norm_dev, sigma_dev, ws, ctx.dev->status,
                               static_cast<hipStream_t>(stream));
@@ -397,6 +461,16 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   std::vector<int> Q(mps->bond_dim, mps->bond_dim + L + 1);  // ket bonds
   std::vector<int> P(Q);                                       // bra bonds (upper bounds)
   hipError_t e = hipSuccess;
+  Prof prof_obj;
+  Prof* prof = nullptr;
+  if (opts->profile) {
+    prof_obj.ds = ctx.dev;
+    prof_obj.st = st;
+    prof = &prof_obj;
+  }
+  int* sweeps_buf = reinterpret_cast<int*>(base + lay.off_sweeps);
+  struct JacRec { size_t ev; double flop_per_sweep; int slot; };
+  std::vector<JacRec> jac_recs;
   double gflop = 0.0;
   auto flop_gemm = [&](double M, double N, double K) { gflop += 8.0 * M * N * K * 1e-9; };
   auto bra_refresh = [&](int i) -> hipError_t {  // fp32 copy of phi_i
@@ -422,11 +496,11 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   if (!opts->input_right_canonical) {
     for (int i = L - 1; i >= 1; --i) {
       const int m = P[i], n = d * P[i + 1];
-      const SvdPlan pl = svd_plan(m, n);
+      const SvdPlan pl = svd_plan(m, n, MPOEVO_RIGHT);
       const int kcap = std::min(m, n);
       double2* A = theta;  // m x kcap   (U S)
       double2* B = site_tmp;  // kcap x n (V^dag)
-      STEP_TRY(svd_truncate(pl, phi(i), kcap, opts->cutoff, MPOEVO_RIGHT, A, B, nullptr, nullptr,
+      STEP_TRY(svd_truncate(pl, phi(i), kcap, opts->cutoff, A, B, nullptr, nullptr,
                             nullptr, nullptr, svdws, ctx.dev->status, st));
       STEP_TRY(hipMemcpyAsync(phi(i), B, sizeof(double2) * (size_t)kcap * n, hipMemcpyDeviceToDevice, st));
       // phi_{i-1} <- phi_{i-1} . (U S)
@@ -442,10 +516,10 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   STEP_TRY(set_boundary(env1, w[L], fp64, st));  // Renv_L
   for (int i = L - 1; i >= 1; --i) {
     STEP_TRY(right_block(fp64, ket(i), env1, wsite(i), tmp, RB(i), Q[i], d, Q[i + 1], P[i + 1],
-                         w[i], w[i + 1], st));
+                         w[i], w[i + 1], st, prof));
     flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
     if (i > 1) {
-      STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st));
+      STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st, prof));
       flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
     }
   }
@@ -460,19 +534,26 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       if (i == 0) STEP_TRY(set_boundary(env0, w[0], fp64, st));
       else {
         STEP_TRY(left_env_from_block(fp64, bra(i - 1), LB(i - 1), env0, P[i - 1], d, P[i],
-                                     w[i], Q[i], st));
+                                     w[i], Q[i], st, prof));
         flop_gemm(P[i], (double)w[i] * Q[i], (double)P[i - 1] * d);
       }
       STEP_TRY(left_block(fp64, env0, ket(i), wsite(i), tmp, LB(i), P[i], w[i], Q[i], d, Q[i + 1],
-                          w[i + 1], st));
+                          w[i + 1], st, prof));
       flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
       const int m = P[i] * d, n = d * P[i + 2];
-      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st));
+      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
-      STEP_TRY(svd_truncate(svd_plan(m, n), theta, Dmax, opts->cutoff, MPOEVO_LEFT, phi(i),
-                            phi(i + 1), kbuf + visit, dbuf + visit, nbuf + visit, nullptr, svdws,
-                            ctx.dev->status, st));
+      {
+        const SvdPlan sp = svd_plan(m, n, MPOEVO_LEFT);
+        hipEvent_t j0 = nullptr, j1 = nullptr;
+        size_t jf = 0;
+        if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
+        STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
+                              dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
+                              j1, prof ? sweeps_buf + visit : nullptr));
+        if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
+      }
       P[i + 1] = kcap;
       k_slot_of_bond[i + 1] = visit;
       last_visit_k_slot = visit;
@@ -483,19 +564,26 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     for (int i = L - 2; i >= 0; --i, ++visit) {
       if (i < L - 2) {
         STEP_TRY(right_env_from_block(fp64, bra(i + 2), RB(i + 2), env1, P[i + 2], d, P[i + 3],
-                                      w[i + 2], Q[i + 2], st));
+                                      w[i + 2], Q[i + 2], st, prof));
         flop_gemm(P[i + 2], (double)w[i + 2] * Q[i + 2], (double)d * P[i + 3]);
         STEP_TRY(right_block(fp64, ket(i + 1), env1, wsite(i + 1), tmp, RB(i + 1), Q[i + 1], d,
-                             Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st));
+                             Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st, prof));
         flop_gemm((double)Q[i + 1] * d, (double)P[i + 2] * w[i + 2], Q[i + 2]);
       }
       const int m = P[i] * d, n = d * P[i + 2];
-      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st));
+      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
-      STEP_TRY(svd_truncate(svd_plan(m, n), theta, Dmax, opts->cutoff, MPOEVO_RIGHT, phi(i),
-                            phi(i + 1), kbuf + visit, dbuf + visit, nbuf + visit, nullptr, svdws,
-                            ctx.dev->status, st));
+      {
+        const SvdPlan sp = svd_plan(m, n, MPOEVO_RIGHT);
+        hipEvent_t j0 = nullptr, j1 = nullptr;
+        size_t jf = 0;
+        if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
+        STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
+                              dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
+                              j1, prof ? sweeps_buf + visit : nullptr));
+        if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
+      }
       P[i + 1] = kcap;
       k_slot_of_bond[i + 1] = visit;
       last_visit_k_slot = visit;
@@ -547,6 +635,33 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     stats->max_bond = maxb;
     stats->gflop = gflop;
     stats->svd_sweeps_max = ctx.max_sweeps;
+    stats->t_jacobi_ms = stats->jacobi_gflop = stats->t_gemm_ms = stats->gemm_gflop = 0.0;
+    stats->t_wmix_ms = stats->wmix_gbyte = 0.0;
+    stats->n_jacobi = stats->n_gemm = stats->n_wmix = 0;
+    if (prof) {
+      std::vector<int> sw(nvis);
+      STEP_TRY(hipMemcpy(sw.data(), sweeps_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost));
+      for (const auto& r : jac_recs) {
+        float ms = 0.f;
+        STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.ev], ctx.dev->events[r.ev + 1]));
+        stats->t_jacobi_ms += ms;
+        stats->jacobi_gflop += sw[r.slot] * r.flop_per_sweep * 1e-9;
+        stats->n_jacobi += 1;
+      }
+      for (const auto& r : prof->recs) {
+        float ms = 0.f;
+        STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.e0], ctx.dev->events[r.e0 + 1]));
+        if (r.kind == Prof::kGemm) {
+          stats->t_gemm_ms += ms;
+          stats->gemm_gflop += r.work * 1e-9;
+          stats->n_gemm += 1;
+        } else {
+          stats->t_wmix_ms += ms;
+          stats->wmix_gbyte += r.work * 1e-9;
+          stats->n_wmix += 1;
+        }
+      }
+    }
   }
   if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
 #undef STEP_TRY

@@ -11,10 +11,12 @@ enum : int { kStatusNotConverged = 1, kStatusBarrierTimeout = 2, kStatusNonFinit
 
 struct SvdPlan {
   int m, n;        // Theta is m x n
-  bool on_theta;   // one-sided Jacobi on the columns of Theta (n <= m) or of Theta^dag
-  int mx, nx;      // column length and number of columns of the Jacobi matrix X
+  int direction;   // 0: keep U (X = Theta); 1: keep V (X = Theta^dag)
+  int mx, nx;      // X is mx x nx (column length, number of columns)
+  int rank_max;    // min(m, n)
+  int rmax;        // rows per lane of the Jacobi kernel (mx <= 64 rmax)
   int b, nb, np;   // block width, number of blocks (even), padded column count
-  int H;           // column height in the work buffer: mx rows of X, then np rows of V
+  int threads;     // threads per Jacobi workgroup (one pair per wave)
   size_t lds;      // dynamic LDS bytes of the Jacobi kernel
   size_t ws;       // workspace bytes
 };
@@ -23,8 +25,8 @@ struct SvdPlan {
 // build constant rather than a device query (device_init checks that the device provides it).
 constexpr size_t kSvdLdsBytes = 128 * 1024;
 
-// Plan for an m x n truncation given the LDS capacity per workgroup.
-SvdPlan svd_plan(int m, int n, size_t lds_cap = kSvdLdsBytes);
+// Plan for an m x n truncation in the given direction.
+SvdPlan svd_plan(int m, int n, int direction, size_t lds_cap = kSvdLdsBytes);
 
 // Largest workspace of any plan with m, n <= maxdim (memoised).
 size_t svd_ws_bound(int maxdim);
@@ -33,10 +35,17 @@ size_t svd_ws_bound(int maxdim);
 hipError_t svd_configure();
 
 // FP64 SVD + truncation (see `truncate` in mpoevo.h). `status` points to the handle's device
-// status word. Writes A_out (m x kcap), B_out (kcap x n) with kcap = min(Dmax, m, n).
+// status words. Writes A_out (m x kcap), B_out (kcap x n) with kcap = min(Dmax, m, n).
+// Optional profiling: the Jacobi launch is bracketed by ev0 / ev1 (both or neither) and its
+// sweep count is stored at sweeps_dev (device int, nullable).
 hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double cutoff,
-                        int direction, double2* A_out, double2* B_out, int* k_dev,
-                        double* disc_dev, double* norm_dev, double* sigma_dev, void* ws,
-                        int* status, hipStream_t st);
+                        double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
+                        double* norm_dev, double* sigma_dev, void* ws, int* status,
+                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                        int* sweeps_dev = nullptr);
+
+// Algorithmic flops of one Jacobi sweep of a plan (36 mx per column pair visit: 16 mx for the
+// three inner products, 20 mx for the rotation of the two columns).
+double svd_sweep_flop(const SvdPlan& p);
 
 }  // namespace mpoevo

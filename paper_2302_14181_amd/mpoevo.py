@@ -42,13 +42,16 @@ class _MPO(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("nsweeps", ctypes.c_int), ("prec", ctypes.c_int), ("cutoff", ctypes.c_double),
-                ("input_right_canonical", ctypes.c_int)]
+                ("input_right_canonical", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_double), ("discarded_max", ctypes.c_double),
                 ("discarded_sum", ctypes.c_double), ("visits", ctypes.c_int),
-                ("max_bond", ctypes.c_int), ("gflop", ctypes.c_double), ("svd_sweeps_max", ctypes.c_int)]
+                ("max_bond", ctypes.c_int), ("gflop", ctypes.c_double), ("svd_sweeps_max", ctypes.c_int),
+                ("t_jacobi_ms", ctypes.c_double), ("jacobi_gflop", ctypes.c_double), ("n_jacobi", ctypes.c_int),
+                ("t_gemm_ms", ctypes.c_double), ("gemm_gflop", ctypes.c_double), ("n_gemm", ctypes.c_int),
+                ("t_wmix_ms", ctypes.c_double), ("wmix_gbyte", ctypes.c_double), ("n_wmix", ctypes.c_int)]
 
 
 _lib = None
@@ -68,7 +71,7 @@ def load(path: str = LIB_PATH):
     lib.mpoevo_last_error.argtypes = [vp]
     lib.mpoevo_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
     lib.mpoevo_destroy.argtypes = [vp]
-    lib.mpoevo_check_solver.argtypes = [vp]
+    lib.mpoevo_check_solver.argtypes = [vp, ip]
     lib.mpo_build.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_int, ip, ip, ip, dp, sz, ip]
     lib.mpoevo_workspace_size.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.POINTER(sz)]
@@ -185,8 +188,11 @@ class Handle:
         except Exception:
             pass
 
-    def check_solver(self):
-        _check(load().mpoevo_check_solver(self.ptr), self)
+    def check_solver(self) -> int:
+        """Raise if an SVD since the last check failed; return the largest Jacobi sweep count."""
+        sweeps = ctypes.c_int(0)
+        _check(load().mpoevo_check_solver(self.ptr, ctypes.byref(sweeps)), self)
+        return sweeps.value
 
 
 def env_update(h: Handle, side: int, E_in, bra, W, ket, E_out, workspace=None, stream=None):
@@ -241,6 +247,7 @@ class StepStats:
     max_bond: int
     gflop: float
     svd_sweeps_max: int
+    profile: dict | None = None
 
 
 class DeviceMPS:
@@ -294,7 +301,7 @@ def step_workspace(mps: DeviceMPS, mpo: DeviceMPO, prec: int):
 
 def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int = FP64,
          cutoff: float = 1e-14, input_right_canonical: bool = False, workspace=None,
-         stream=None) -> StepStats:
+         stream=None, profile: bool = False) -> StepStats:
     """One time step of the variational fit; mps is updated in place (see include/mpoevo.h)."""
     if workspace is None:
         workspace = step_workspace(mps, mpo, prec)
@@ -303,10 +310,14 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
     cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
     cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
-    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)))
+    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), int(bool(profile)))
     st = _Stats()
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
                        _ptr(workspace), workspace.numel(), _stream(stream)), h)
     mps.bond = [bond[i] for i in range(mps.L + 1)]
+    prof = None
+    if profile:
+        prof = {k: getattr(st, k) for k in ("t_jacobi_ms", "jacobi_gflop", "n_jacobi", "t_gemm_ms",
+                                            "gemm_gflop", "n_gemm", "t_wmix_ms", "wmix_gbyte", "n_wmix")}
     return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
-                     st.svd_sweeps_max)
+                     st.svd_sweeps_max, prof)

@@ -261,3 +261,21 @@ def test_step_rejects_bad_arguments(mp, handle):
     with pytest.raises(mp.MpoevoError) as e:
         mp.step(handle, dm, dw, workspace=ws)
     assert e.value.code == mp.ENOMEM
+
+
+def test_step_profile_mode_matches_plain_step(mp, handle):
+    """The event-timed step computes the same state and reports positive kernel-class times."""
+    _say("step profile mode L=8 D=8")
+    rng = np.random.default_rng(3)
+    psi = _normalise(wl.random_mps(rng, 8, 2, 4))
+    H = wl.tfim(1.0)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    a, sa = _gpu_step(mp, handle, psi, W, 8, 0)
+    dm = mp.DeviceMPS(psi, Dmax=8)
+    sb = mp.step(handle, dm, mp.DeviceMPO([W] * 8), prec=0, profile=True)
+    b = dm.to_numpy()
+    assert 1 - abs(ofit.overlap(a, b)) ** 2 < 1e-13
+    p = sb.profile
+    assert p["n_jacobi"] == sa.visits and p["t_jacobi_ms"] > 0 and p["jacobi_gflop"] > 0
+    assert p["n_gemm"] > 0 and p["t_gemm_ms"] > 0 and p["gemm_gflop"] > 0
+    assert p["n_wmix"] > 0 and p["wmix_gbyte"] > 0
