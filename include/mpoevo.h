@@ -189,6 +189,14 @@ typedef struct {
   double cutoff;
   int input_right_canonical;
   int profile;  /* nonzero: time the kernel classes with HIP events (adds host overhead) */
+  int svd_cold_start; /* nonzero: every truncation starts Jacobi from Theta itself. Zero (the
+                         default): a square bond matrix is first multiplied by the unitary the
+                         previous truncation of the same bond left in the workspace (its
+                         singular basis on the shared side), which leaves the same singular
+                         values and kept vectors and converges in a few sweeps. The unitaries
+                         persist in the workspace between step calls on one handle with the
+                         same workspace and chain shape; the caller must not modify that
+                         workspace between such calls. */
 } mpoevo_step_opts;
 
 typedef struct {
@@ -207,6 +215,8 @@ typedef struct {
   int n_gemm;
   double t_wmix_ms, wmix_gbyte;      /* short-leg contractions with W (bytes read + written) */
   int n_wmix;
+  int svd_sweeps_total;     /* Jacobi sweeps summed over the bond truncations of the step */
+  int svd_sweeps_hist[32];  /* number of bond truncations that took s sweeps (index min(s, 31)) */
 } mpoevo_step_stats;
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,

@@ -19,6 +19,7 @@
 // host; the host reads the kept ranks once at the end of the step and compacts the result.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -95,6 +96,14 @@ template <typename C2>
 __global__ void boundary_env(C2* E, int w) {
   const int i = threadIdx.x + blockIdx.x * blockDim.x;
   if (i < w) E[i] = C2{i == 0 ? 1 : 0, 0};
+}
+
+// out (n x n) = identity.
+__global__ void fill_identity(double2* out, int n) {
+  const long long total = (long long)n * n;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x)
+    out[idx] = double2{(idx / n == idx % n) ? 1.0 : 0.0, 0.0};
 }
 
 __global__ void scale_by_inverse_norm(double2* x, long long n, const double* norm) {
@@ -227,7 +236,7 @@ struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
   size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
-      total;
+      off_basis, basiscap, off_token, total;
 };
 
 StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
@@ -259,6 +268,10 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_site_tmp = take(sizeof(double2) * s.sitecap);
   s.off_site_tmp2 = take(sizeof(double2) * s.sitecap);
   s.off_sweeps = take(sizeof(int) * (size_t)8 * L);
+  // one unitary per bond (the Jacobi preconditioner carried between visits and steps)
+  s.basiscap = (size_t)d * Dmax * d * Dmax;
+  s.off_basis = take(sizeof(double2) * s.basiscap * (size_t)std::max(L - 1, 1));
+  s.off_token = take(sizeof(unsigned long long));  // which step last wrote the unitaries
   s.total = o;
   return s;
 }
@@ -456,6 +469,37 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   double2* site_tmp = reinterpret_cast<double2*>(base + lay.off_site_tmp);
   double2* site_tmp2 = reinterpret_cast<double2*>(base + lay.off_site_tmp2);
   const int* w = mpo->w;
+  auto basis = [&](int i) { return reinterpret_cast<double2*>(base + lay.off_basis) + lay.basiscap * i; };
+
+  // Jacobi preconditioners: kept in the workspace between steps of the same handle, valid while
+  // the workspace and the chain's shape stay the same; otherwise every bond restarts from the
+  // identity. warm_dim[i] is the order of the unitary stored for bond i (0: none).
+  const bool warm_on = opts->svd_cold_start == 0;
+  const int sig[5] = {L, d, Dmax, wmax, prec};
+  unsigned long long* token_dev = reinterpret_cast<unsigned long long*>(base + lay.off_token);
+  bool reuse = warm_on && ctx.warm_ws == ws && std::equal(sig, sig + 5, ctx.warm_sig) &&
+               (int)ctx.warm_dim.size() == L - 1;
+  if (reuse) {  // the workspace must still hold what this handle's last step left there
+    unsigned long long tok = 0;
+    hipError_t et = hipMemcpyAsync(&tok, token_dev, sizeof(tok), hipMemcpyDeviceToHost, st);
+    if (et == hipSuccess) et = hipStreamSynchronize(st);
+    if (et != hipSuccess) return hip_fail(ctx, et, "step: reading the workspace token");
+    reuse = tok == ctx.warm_token;
+  }
+  if (!reuse) ctx.warm_dim.assign(std::max(L - 1, 0), 0);
+  ctx.warm_ws = nullptr;  // re-armed when this step completes
+  // The unitary kept for bond i has the order of X's column count, min(m, n); a change of shape
+  // restarts it from the identity.
+  auto warm_for = [&](int i, int m, int n) -> double2* {
+    if (!warm_on) return nullptr;
+    const int nx = std::min(m, n);
+    if (ctx.warm_dim[i] != nx) {
+      hipLaunchKernelGGL(fill_identity, dim3(grid_for((long long)nx * nx)), dim3(256), 0, st, basis(i), nx);
+      if (hipGetLastError() != hipSuccess) return nullptr;
+      ctx.warm_dim[i] = nx;
+    }
+    return basis(i);
+  };
 
   ctx.max_sweeps = 0;
   std::vector<int> Q(mps->bond_dim, mps->bond_dim + L + 1);  // ket bonds
@@ -545,13 +589,14 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
-        const SvdPlan sp = svd_plan(m, n, MPOEVO_LEFT);
+        const SvdPlan sp = svd_plan(m, n, MPOEVO_LEFT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
+        double2* wb = warm_for(i, m, n);
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, prof ? sweeps_buf + visit : nullptr));
+                              j1, sweeps_buf + visit, wb, wb));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;
@@ -575,13 +620,14 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
-        const SvdPlan sp = svd_plan(m, n, MPOEVO_RIGHT);
+        const SvdPlan sp = svd_plan(m, n, MPOEVO_RIGHT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
+        double2* wb = warm_for(i, m, n);
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, prof ? sweeps_buf + visit : nullptr));
+                              j1, sweeps_buf + visit, wb, wb));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;
@@ -598,8 +644,9 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     return hipGetLastError();
   }());
   // read back the kept ranks and statistics (one synchronisation per step)
-  std::vector<int> kh(nvis);
+  std::vector<int> kh(nvis), swh(nvis);
   std::vector<double> dh(nvis), nh(nvis);
+  STEP_TRY(hipMemcpyAsync(swh.data(), sweeps_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(kh.data(), kbuf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(dh.data(), dbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(nh.data(), nbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
@@ -635,12 +682,17 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     stats->max_bond = maxb;
     stats->gflop = gflop;
     stats->svd_sweeps_max = ctx.max_sweeps;
+    stats->svd_sweeps_total = 0;
+    for (int& c : stats->svd_sweeps_hist) c = 0;
+    for (int v = 0; v < nvis; ++v) {
+      stats->svd_sweeps_total += swh[v];
+      stats->svd_sweeps_hist[std::min(std::max(swh[v], 0), 31)] += 1;
+    }
     stats->t_jacobi_ms = stats->jacobi_gflop = stats->t_gemm_ms = stats->gemm_gflop = 0.0;
     stats->t_wmix_ms = stats->wmix_gbyte = 0.0;
     stats->n_jacobi = stats->n_gemm = stats->n_wmix = 0;
     if (prof) {
-      std::vector<int> sw(nvis);
-      STEP_TRY(hipMemcpy(sw.data(), sweeps_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost));
+      const std::vector<int>& sw = swh;
       for (const auto& r : jac_recs) {
         float ms = 0.f;
         STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.ev], ctx.dev->events[r.ev + 1]));
@@ -664,6 +716,14 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     }
   }
   if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
+  if (warm_on) {
+    static std::atomic<unsigned long long> next_token{1};
+    ctx.warm_token = next_token.fetch_add(1);
+    STEP_TRY(hipMemcpyAsync(token_dev, &ctx.warm_token, sizeof(ctx.warm_token), hipMemcpyHostToDevice, st));
+    STEP_TRY(hipStreamSynchronize(st));
+    ctx.warm_ws = ws;
+    std::copy(sig, sig + 5, ctx.warm_sig);
+  }
 #undef STEP_TRY
   return MPOEVO_OK;
 }

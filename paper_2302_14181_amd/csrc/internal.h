@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <string>
+#include <vector>
 
 #include "../../include/mpoevo.h"
 
@@ -21,6 +22,12 @@ struct Context {
   std::string err;
   int max_sweeps = 0;  // largest Jacobi sweep count seen by mpoevo_check_solver / step
   DeviceState* dev = nullptr;
+  // Jacobi preconditioners left in a step workspace by the last completed step: the workspace,
+  // the chain's shape {L, d, Dmax, wmax, prec} and the order of the unitary stored per bond.
+  const void* warm_ws = nullptr;
+  int warm_sig[5] = {0, 0, 0, 0, 0};
+  unsigned long long warm_token = 0;  // also stored in the workspace by the step that wrote them
+  std::vector<int> warm_dim;
 };
 
 int device_init(Context& ctx);

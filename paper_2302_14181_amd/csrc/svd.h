@@ -11,7 +11,9 @@ enum : int { kStatusNotConverged = 1, kStatusBarrierTimeout = 2, kStatusNonFinit
 
 struct SvdPlan {
   int m, n;        // Theta is m x n
-  int direction;   // 0: keep U (X = Theta); 1: keep V (X = Theta^dag)
+  int direction;   // 0: keep U (A = U_k, B = S V_k^dag); 1: keep V (A = U_k S, B = V_k^dag)
+  int xconj;       // 0: X = Theta; 1: X = Theta^dag
+  int acc;         // accumulate the column rotations Q (nx x nx) of X
   int mx, nx;      // X is mx x nx (column length, number of columns)
   int rank_max;    // min(m, n)
   int rmax;        // rows per lane of the Jacobi kernel (mx <= 64 rmax)
@@ -25,8 +27,10 @@ struct SvdPlan {
 // build constant rather than a device query (device_init checks that the device provides it).
 constexpr size_t kSvdLdsBytes = 128 * 1024;
 
-// Plan for an m x n truncation in the given direction.
-SvdPlan svd_plan(int m, int n, int direction, size_t lds_cap = kSvdLdsBytes);
+// Plan for an m x n truncation in the given direction. want_basis: the call will ask for the
+// preconditioner of the next truncation (rectangular Theta then accumulates Q).
+SvdPlan svd_plan(int m, int n, int direction, bool want_basis = false,
+                 size_t lds_cap = kSvdLdsBytes);
 
 // Largest workspace of any plan with m, n <= maxdim (memoised).
 size_t svd_ws_bound(int maxdim);
@@ -34,7 +38,16 @@ size_t svd_ws_bound(int maxdim);
 // One-time kernel attribute setup (dynamic LDS above the default limit).
 hipError_t svd_configure();
 
-// FP64 SVD + truncation (see `truncate` in mpoevo.h). `status` points to the handle's device
+// FP64 SVD + truncation (see `truncate` in mpoevo.h). Preconditioning (square Theta, or a plan
+// made with want_basis; ignored otherwise): with `warm` (nx x nx unitary P, column j at
+// warm + j nx) Jacobi starts from X P instead of X, which has the same singular values and left
+// singular vectors; a P close to X's right singular vectors leaves X P nearly orthogonal and
+// saves most sweeps. With `basis_out` the unitary for the next truncation of the same bond is
+// written there in the same layout: for square Theta the normalised converged columns (or the
+// identity when some column is at the rounding floor), i.e. X's left singular vectors, which
+// precondition the opposite-direction visit; for rectangular Theta (same orientation on every
+// visit) the accumulated P Q, i.e. X's right singular vectors. `warm` and `basis_out` may be
+// the same buffer. `status` points to the handle's device
 // status words. Writes A_out (m x kcap), B_out (kcap x n) with kcap = min(Dmax, m, n).
 // Optional profiling: the Jacobi launch is bracketed by ev0 / ev1 (both or neither) and its
 // sweep count is stored at sweeps_dev (device int, nullable).
@@ -42,7 +55,8 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-                        int* sweeps_dev = nullptr);
+                        int* sweeps_dev = nullptr, const double2* warm = nullptr,
+                        double2* basis_out = nullptr);
 
 // Algorithmic flops of one Jacobi sweep of a plan (36 mx per column pair visit: 16 mx for the
 // three inner products, 20 mx for the rotation of the two columns).

@@ -1,10 +1,21 @@
 // FP64 SVD of the projected two-site tensor by one-sided (Hestenes) Jacobi, and the truncation
 // of the two-site update (keep k <= Dmax singular values, split as U | S V^dag or U S | V^dag).
 //
-// Orientation follows the sweep direction: left-to-right keeps U, so Jacobi orthogonalises the
-// columns of X = Theta (U_j = X_j / |X_j| after convergence) and the other factor is the exact
-// projection S V^dag = U^dag Theta; right-to-left keeps V, so X = Theta^dag (V_j = X_j / |X_j|)
-// and U S = Theta V. The two products run on the FP64 matrix cores.
+// Orientation. Jacobi orthogonalises the columns of X by plane rotations from the right,
+// X Q = (columns sigma_j x_j), Q unitary. A rectangular Theta is oriented so that X has
+// min(m, n) columns (X = Theta when m > n, X = Theta^dag when m < n); a square one by the sweep
+// direction (left-to-right keeps U: X = Theta; right-to-left keeps V: X = Theta^dag). The kept
+// factor is either the normalised converged columns of X, or, when it lies on the other side
+// (rectangular Theta), the accumulated rotation Q itself; both are orthonormal to rounding. The
+// other factor is the exact projection (S V^dag = U^dag Theta, or U S = Theta V) on the FP64
+// matrix cores.
+//
+// Preconditioning. Starting from X P instead of X, with P a unitary close to X's right singular
+// vectors, leaves the singular values and left singular vectors unchanged and X P nearly
+// orthogonal, so Jacobi ends in a few sweeps. The truncation of a bond leaves such a P for the
+// next truncation of the same bond: the normalised columns (square Theta; they are the singular
+// vectors on the side the next, opposite-direction visit multiplies) or the accumulated P Q
+// (rectangular Theta, same orientation every visit).
 //
 // Numerically zero columns: a column whose norm is at the rounding level of the matrix,
 // floor = 8 eps sqrt(mx) ||Theta||_F, only carries cancellation noise; rotating it against a
@@ -13,10 +24,12 @@
 // |x^dag y| <= tol |x| |y|, so the normalised kept columns are orthonormal to tol.
 //
 // Parallel schedule: the np columns are cut into nb blocks of b columns; a round pairs the
-// blocks (round-robin), one workgroup per block pair holds its 2b columns in LDS and performs one
-// cyclic sweep over all their column pairs, one wave per pair with both columns in registers.
-// Rounds are separated by a grid barrier of the cooperative launch; a sweep whose largest
-// relative inner product is below tol (or below kAccept) ends the iteration.
+// blocks (round-robin), one workgroup per block pair holds its 2b columns in LDS, one wave per
+// column pair with both columns in registers. The first round of a sweep visits every pair of
+// its 2b columns (so every pair inside a block is visited once per sweep), the other rounds
+// only the b x b pairs across their two blocks: each pair of columns is rotated exactly once
+// per sweep. Rounds are separated by a grid barrier of the cooperative launch; a sweep whose
+// largest relative inner product is below tol (or below kAccept) ends the iteration.
 
 #include <algorithm>
 #include <cmath>
@@ -30,20 +43,30 @@ namespace mpoevo {
 namespace {
 
 constexpr int kMaxSweeps = 60;
+constexpr int kMaxGrid = 256;      // workgroups of a Jacobi launch (nb / 2 <= 256)
 constexpr double kAccept = 1e-13;  // columns this orthogonal need no further sweep
 constexpr double kEps = 2.220446049250313e-16;
 constexpr unsigned long long kBarrierTimeoutTicks = 300000000ull;  // 3 s of the 100 MHz clock
 
 struct SvdWs {  // carved from the caller's workspace
   double2* X;           // [np][mx] column-major
+  double2* Q;           // [np][nx] accumulated rotation (plans with acc), else null
   double* sigma;        // [np]
   int* perm;            // [np]
-  unsigned* bar;        // [0] arrival count, [1] generation, [2] timeout flag
+  unsigned* bar;        // [2] timeout flag
+  unsigned* flags;      // [kMaxGrid] barrier generation reached by each workgroup
   unsigned* sweep_max;  // [kMaxSweeps] bits of the largest |x^dag y| / (|x| |y|) of a sweep
-  int* k_shared;
+  int* k_shared;        // [0] kept rank, [1] columns form a complete basis
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t ws_bytes(int mx, int nx, int np, bool acc) {
+  return align256(sizeof(double2) * (size_t)mx * np) +
+         (acc ? align256(sizeof(double2) * (size_t)nx * np) : 0) + align256(sizeof(double) * np) +
+         align256(sizeof(int) * np) + 256 + sizeof(unsigned) * kMaxGrid +
+         align256(sizeof(unsigned) * kMaxSweeps) + 256;
+}
 
 SvdWs carve(const SvdPlan& p, void* ws) {
   unsigned char* base = static_cast<unsigned char*>(ws);
@@ -51,12 +74,19 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   size_t off = 0;
   w.X = reinterpret_cast<double2*>(base + off);
   off += align256(sizeof(double2) * (size_t)p.mx * p.np);
+  w.Q = nullptr;
+  if (p.acc) {
+    w.Q = reinterpret_cast<double2*>(base + off);
+    off += align256(sizeof(double2) * (size_t)p.nx * p.np);
+  }
   w.sigma = reinterpret_cast<double*>(base + off);
   off += align256(sizeof(double) * p.np);
   w.perm = reinterpret_cast<int*>(base + off);
   off += align256(sizeof(int) * p.np);
   w.bar = reinterpret_cast<unsigned*>(base + off);
   off += 256;
+  w.flags = reinterpret_cast<unsigned*>(base + off);
+  off += sizeof(unsigned) * kMaxGrid;
   w.sweep_max = reinterpret_cast<unsigned*>(base + off);
   off += align256(sizeof(unsigned) * kMaxSweeps);
   w.k_shared = reinterpret_cast<int*>(base + off);
@@ -115,15 +145,20 @@ __device__ inline void rr_pair(int r, int k, int n, int& x, int& y) {
   y = (k == 0) ? (n - 1) : (r - k + n - 1) % (n - 1);
 }
 
-// X = Theta (direction 0) or Theta^dag (direction 1), zero padding columns; clear the state.
-__global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, SvdWs w) {
+// X = Theta (xconj 0) or Theta^dag (xconj 1), zero padding columns; Q = P (the preconditioner,
+// nx x nx, column j at P + j nx) or the identity, zero padding columns; clear the state.
+// With copy == 0 the first nx columns of X are left to the preconditioning product.
+__global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, SvdWs w, int copy,
+                                const double2* __restrict__ P) {
   const long long total = (long long)p.mx * p.np;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long first = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (long long idx = first; idx < total; idx += stride) {
     const int j = (int)(idx / p.mx), row = (int)(idx % p.mx);
+    if (j < p.nx && !copy) continue;
     double2 v{0.0, 0.0};
     if (j < p.nx) {
-      if (p.direction == 0) v = theta[(long long)row * p.n + j];
+      if (p.xconj == 0) v = theta[(long long)row * p.n + j];
       else {
         const double2 t = theta[(long long)j * p.n + row];
         v = double2{t.x, -t.y};
@@ -131,35 +166,54 @@ __global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, Sv
     }
     w.X[idx] = v;
   }
+  if (p.acc) {
+    const long long qtotal = (long long)p.nx * p.np;
+    for (long long idx = first; idx < qtotal; idx += stride) {
+      const int j = (int)(idx / p.nx), row = (int)(idx % p.nx);
+      double2 v{0.0, 0.0};
+      if (j < p.nx) v = P ? P[idx] : double2{row == j ? 1.0 : 0.0, 0.0};
+      w.Q[idx] = v;
+    }
+  }
   if (blockIdx.x == 0) {
     if (threadIdx.x < 3) w.bar[threadIdx.x] = 0u;
     for (int i = threadIdx.x; i < kMaxSweeps; i += blockDim.x) w.sweep_max[i] = 0u;
+    for (int i = threadIdx.x; i < kMaxGrid; i += blockDim.x) w.flags[i] = 0u;
   }
 }
 
-__device__ bool grid_barrier(unsigned* bar, unsigned nblocks) {
+// Grid barrier of the cooperative launch: workgroup g publishes the generation it reached in
+// flags[g] (release) and waits until every workgroup's flag has reached it (acquire), one lane
+// per flag. No shared counter, so arrivals do not serialise on one address. A wait longer than
+// the timeout (or another workgroup's timeout) sets bar[2] and makes every workgroup return
+// false; all workgroups then leave the sweep loop.
+__device__ bool grid_barrier(unsigned* flags, unsigned* bar, unsigned nblocks, unsigned gen) {
   __shared__ int timed_out;
   __syncthreads();
   if (threadIdx.x == 0) {
     timed_out = 0;
     __threadfence();
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const unsigned long long t0 = wall_clock64();
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-            wall_clock64() - t0 > kBarrierTimeoutTicks) {
-          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          timed_out = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+    __hip_atomic_store(&flags[blockIdx.x], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const unsigned long long t0 = wall_clock64();
+    bool fail = false;
+    while (true) {
+      int mine = 1;
+      for (unsigned j = lane; j < nblocks; j += 64)
+        mine &= __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+      if (__all(mine)) break;
+      if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 > kBarrierTimeoutTicks) {
+        fail = true;
+        break;
       }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (fail && lane == 0) {
+      __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      timed_out = 1;
     }
     __threadfence();
   }
@@ -167,18 +221,90 @@ __device__ bool grid_barrier(unsigned* bar, unsigned nblocks) {
   return timed_out == 0;
 }
 
-// One-sided Jacobi sweeps. RMAX = rows per lane (mx <= 64 RMAX). Launched cooperatively with
-// nb / 2 workgroups; dynamic LDS holds 2b columns of mx rows.
-template <int RMAX>
-__global__ __launch_bounds__(RMAX <= 8 ? 1024 : 512) void svd_jacobi_kernel(SvdPlan p, SvdWs w,
+// One Jacobi rotation of the column pair (u, v) held in registers (RMAX rows per lane): the
+// three inner products, the rotation that makes the pair orthogonal, applied in place (and to
+// the pair's columns of the accumulated rotation, qu and qv, when ACC). Returns whether the pair
+// was rotated; records the pair's relative inner product in *wg_max.
+template <int RMAX, bool ACC>
+__device__ inline bool jacobi_pair(double2 (&u)[RMAX], double2 (&v)[RMAX], double2 (&qu)[RMAX],
+                                   double2 (&qv)[RMAX], int lane, double floor2, double tol2,
+                                   unsigned* wg_max) {
+  double a = 0.0, bb = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+  for (int t = 0; t < RMAX; ++t) {
+    a = fma(u[t].x, u[t].x, fma(u[t].y, u[t].y, a));
+    bb = fma(v[t].x, v[t].x, fma(v[t].y, v[t].y, bb));
+    gr = fma(u[t].x, v[t].x, fma(u[t].y, v[t].y, gr));
+    gi = fma(u[t].x, v[t].y, fma(-u[t].y, v[t].x, gi));
+  }
+  wave_sum4(a, bb, gr, gi);
+  // Rotation parameters without divisions or square roots: |gamma|^2 = g2, r = 1/|gamma|,
+  // phase e = conj(gamma) r, zeta = (|v|^2 - |u|^2) / (2 |gamma|),
+  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = t c. Only c, s and e
+  // must be exact (a unitary rotation); t may carry rounding, which only leaves a slightly
+  // larger remainder for the next sweep.
+  const double g2 = fma(gr, gr, gi * gi);
+  const double ab = a * bb;
+  const bool live = fmin(a, bb) > floor2;
+  if (live && lane == 0 && ab > 0.0)
+    atomicMax(wg_max, __float_as_uint(sqrtf((float)fmin(g2 * rcp_d(ab), 1.0))));
+  if (!(live && g2 > tol2 * ab)) return false;
+  const double r = rsqrt_d(g2);
+  const double zeta = 0.5 * (bb - a) * r;
+  const double q = (zeta * zeta < 1e300) ? (1.0 + zeta * zeta) * rsqrt_d(1.0 + zeta * zeta) : fabs(zeta);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_d(fabs(zeta) + q);
+  const double c = rsqrt_d(1.0 + t * t), s = t * c;
+  const double er = gr * r, ei = -gi * r;  // conj(gamma) / |gamma|
+#pragma unroll
+  for (int tt = 0; tt < RMAX; ++tt) {
+    const double evx = er * v[tt].x - ei * v[tt].y, evy = er * v[tt].y + ei * v[tt].x;
+    const double2 un{c * u[tt].x - s * evx, c * u[tt].y - s * evy};
+    v[tt] = double2{s * u[tt].x + c * evx, s * u[tt].y + c * evy};
+    u[tt] = un;
+  }
+  if (ACC) {
+#pragma unroll
+    for (int tt = 0; tt < RMAX; ++tt) {
+      const double evx = er * qv[tt].x - ei * qv[tt].y, evy = er * qv[tt].y + ei * qv[tt].x;
+      const double2 un{c * qu[tt].x - s * evx, c * qu[tt].y - s * evy};
+      qv[tt] = double2{s * qu[tt].x + c * evx, s * qu[tt].y + c * evy};
+      qu[tt] = un;
+    }
+  }
+  return true;
+}
+
+template <int R>
+__device__ inline void load_col(double2 (&u)[R], const double2* c, int lane, int len) {
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int row = lane + 64 * t;
+    u[t] = row < len ? c[row] : double2{0.0, 0.0};
+  }
+}
+
+template <int R>
+__device__ inline void store_col(const double2 (&u)[R], double2* c, int lane, int len) {
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int row = lane + 64 * t;
+    if (row < len) c[row] = u[t];
+  }
+}
+
+// One-sided Jacobi sweeps. RMAX = rows per lane (mx <= 64 RMAX; with ACC also nx <= mx). Launched
+// cooperatively with nb / 2 workgroups of 64 b threads; dynamic LDS holds the 2b columns of X
+// (mx rows each) followed, with ACC, by the same 2b columns of Q (nx rows each).
+template <int RMAX, bool ACC>
+__global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPlan p, SvdWs w,
                                                                           double tol, int* status,
                                                                           int* sweeps_out) {
-  extern __shared__ double2 cols[];  // [2b][mx]
+  extern __shared__ double2 cols[];  // [2b][mx] then (ACC) [2b][nx]
   __shared__ unsigned wg_max;        // bits of a non-negative float: integer order = value order
   __shared__ double floor2_sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nwaves = blockDim.x >> 6;
-  const int two_b = 2 * p.b, mx = p.mx;
+  const int two_b = 2 * p.b, mx = p.mx, nx = p.nx;
+  double2* qcols = cols + two_b * mx;
   if (tid == 0) {  // squared rounding floor from the initial column norms (fixed order)
     double fro2 = 0.0;
     for (int j = 0; j < p.nx; ++j) fro2 += w.sigma[j];
@@ -191,78 +317,99 @@ __global__ __launch_bounds__(RMAX <= 8 ? 1024 : 512) void svd_jacobi_kernel(SvdP
   const unsigned nblk = gridDim.x;
   bool ok = true;
   int sweep = 0;
+  unsigned gen = 0;
   for (; sweep < kMaxSweeps && ok; ++sweep) {
     for (int r = 0; r < p.nb - 1 && ok; ++r) {
       int bp, bq;
       rr_pair(r, blockIdx.x, p.nb, bp, bq);
-      for (int idx = tid; idx < two_b * mx; idx += blockDim.x) {
-        const int c = idx / mx, row = idx - c * mx;
-        const int g = (c < p.b) ? bp * p.b + c : bq * p.b + (c - p.b);
-        cols[idx] = w.X[(long long)g * mx + row];
+      const int gx = bp * p.b + wave, gy = bq * p.b + wave;  // this wave's two global columns
+      // 2b columns global -> LDS: wave k moves column k of each block through its registers
+      if (wave < p.b) {
+        double2 u[RMAX], v[RMAX];
+        load_col(u, w.X + (long long)gx * mx, lane, mx);
+        load_col(v, w.X + (long long)gy * mx, lane, mx);
+        store_col(u, cols + wave * mx, lane, mx);
+        store_col(v, cols + (p.b + wave) * mx, lane, mx);
+        if (ACC) {
+          load_col(u, w.Q + (long long)gx * nx, lane, nx);
+          load_col(v, w.Q + (long long)gy * nx, lane, nx);
+          store_col(u, qcols + wave * nx, lane, nx);
+          store_col(v, qcols + (p.b + wave) * nx, lane, nx);
+        }
       }
       if (tid == 0) wg_max = 0u;
       __syncthreads();
-      for (int ir = 0; ir < two_b - 1; ++ir) {
-        for (int pk = wave; pk < p.b; pk += nwaves) {
-          int x, y;
-          rr_pair(ir, pk, two_b, x, y);
-          double2* cx = cols + x * mx;
-          double2* cy = cols + y * mx;
-          double2 u[RMAX], v[RMAX];
-          double a = 0.0, bb = 0.0, gr = 0.0, gi = 0.0;
-#pragma unroll
-          for (int t = 0; t < RMAX; ++t) {
-            const int row = lane + 64 * t;
-            if (row < mx) {
-              u[t] = cx[row];
-              v[t] = cy[row];
-            } else {
-              u[t] = double2{0.0, 0.0};
-              v[t] = double2{0.0, 0.0};
+      // One wave per pair (blockDim = 64 b). The first round of a sweep holds every block once:
+      // it also visits the pairs inside each block; later rounds visit only the b x b pairs
+      // across their two blocks, where wave k keeps column k of the first block in registers
+      // and meets the columns of the second block in turn.
+      const int pk = wave;
+      if (r == 0) {
+        for (int ir = 0; ir < two_b - 1; ++ir) {
+          if (pk < p.b) {
+            int x, y;
+            rr_pair(ir, pk, two_b, x, y);
+            double2 u[RMAX], v[RMAX], qu[RMAX], qv[RMAX];
+            load_col(u, cols + x * mx, lane, mx);
+            load_col(v, cols + y * mx, lane, mx);
+            if (ACC) {
+              load_col(qu, qcols + x * nx, lane, nx);
+              load_col(qv, qcols + y * nx, lane, nx);
             }
-            a = fma(u[t].x, u[t].x, fma(u[t].y, u[t].y, a));
-            bb = fma(v[t].x, v[t].x, fma(v[t].y, v[t].y, bb));
-            gr = fma(u[t].x, v[t].x, fma(u[t].y, v[t].y, gr));
-            gi = fma(u[t].x, v[t].y, fma(-u[t].y, v[t].x, gi));
-          }
-          wave_sum4(a, bb, gr, gi);
-          // Rotation parameters without divisions or square roots: |gamma|^2 = g2,
-          // r = 1/|gamma|, phase e = conj(gamma) r, zeta = (|y|^2 - |x|^2) / (2 |gamma|),
-          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = t c. Only c, s
-          // and e must be exact (a unitary rotation); t may carry rounding, which only leaves a
-          // slightly larger remainder for the next sweep.
-          const double g2 = fma(gr, gr, gi * gi);
-          const double ab = a * bb;
-          const bool live = fmin(a, bb) > floor2;
-          if (live && lane == 0 && ab > 0.0)
-            atomicMax(&wg_max, __float_as_uint(sqrtf((float)fmin(g2 * rcp_d(ab), 1.0))));
-          if (live && g2 > tol2 * ab) {
-            const double r = rsqrt_d(g2);
-            const double zeta = 0.5 * (bb - a) * r;
-            const double q = (zeta * zeta < 1e300) ? (1.0 + zeta * zeta) * rsqrt_d(1.0 + zeta * zeta) : fabs(zeta);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_d(fabs(zeta) + q);
-            const double c = rsqrt_d(1.0 + t * t), s = t * c;
-            const double er = gr * r, ei = -gi * r;  // conj(gamma) / |gamma|
-#pragma unroll
-            for (int tt = 0; tt < RMAX; ++tt) {
-              const int row = lane + 64 * tt;
-              if (row < mx) {
-                const double evx = er * v[tt].x - ei * v[tt].y, evy = er * v[tt].y + ei * v[tt].x;
-                cx[row] = double2{c * u[tt].x - s * evx, c * u[tt].y - s * evy};
-                cy[row] = double2{s * u[tt].x + c * evx, s * u[tt].y + c * evy};
+            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, lane, floor2, tol2, &wg_max)) {
+              store_col(u, cols + x * mx, lane, mx);
+              store_col(v, cols + y * mx, lane, mx);
+              if (ACC) {
+                store_col(qu, qcols + x * nx, lane, nx);
+                store_col(qv, qcols + y * nx, lane, nx);
               }
             }
           }
+          __syncthreads();
+        }
+      } else {
+        double2 u[RMAX], qu[RMAX];
+        bool dirty = false;
+        if (pk < p.b) {
+          load_col(u, cols + pk * mx, lane, mx);
+          if (ACC) load_col(qu, qcols + pk * nx, lane, nx);
+        }
+        for (int ir = 0; ir < p.b; ++ir) {
+          if (pk < p.b) {
+            int y = pk + ir;
+            y = p.b + (y >= p.b ? y - p.b : y);
+            double2 v[RMAX], qv[RMAX];
+            load_col(v, cols + y * mx, lane, mx);
+            if (ACC) load_col(qv, qcols + y * nx, lane, nx);
+            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, lane, floor2, tol2, &wg_max)) {
+              store_col(v, cols + y * mx, lane, mx);
+              if (ACC) store_col(qv, qcols + y * nx, lane, nx);
+              dirty = true;
+            }
+          }
+          __syncthreads();
+        }
+        if (pk < p.b && dirty) {
+          store_col(u, cols + pk * mx, lane, mx);
+          if (ACC) store_col(qu, qcols + pk * nx, lane, nx);
         }
         __syncthreads();
       }
-      for (int idx = tid; idx < two_b * mx; idx += blockDim.x) {
-        const int c = idx / mx, row = idx - c * mx;
-        const int g = (c < p.b) ? bp * p.b + c : bq * p.b + (c - p.b);
-        w.X[(long long)g * mx + row] = cols[idx];
+      if (wave < p.b) {  // LDS -> global
+        double2 u[RMAX], v[RMAX];
+        load_col(u, cols + wave * mx, lane, mx);
+        load_col(v, cols + (p.b + wave) * mx, lane, mx);
+        store_col(u, w.X + (long long)gx * mx, lane, mx);
+        store_col(v, w.X + (long long)gy * mx, lane, mx);
+        if (ACC) {
+          load_col(u, qcols + wave * nx, lane, nx);
+          load_col(v, qcols + (p.b + wave) * nx, lane, nx);
+          store_col(u, w.Q + (long long)gx * nx, lane, nx);
+          store_col(v, w.Q + (long long)gy * nx, lane, nx);
+        }
       }
       if (tid == 0 && wg_max) atomicMax(&w.sweep_max[sweep], wg_max);
-      ok = grid_barrier(w.bar, nblk);
+      ok = grid_barrier(w.flags, w.bar, nblk, ++gen);
     }
     if (!ok) break;
     const float mxr = __uint_as_float(
@@ -327,6 +474,16 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(SvdPlan p, SvdWs w, in
   }
   const double floor_abs = 8.0 * kEps * sqrt((double)p.mx) * sqrt(fro2);
   const double thr = fmax(cutoff * smax, floor_abs);
+  // every column clearly above the rounding floor: the normalised columns form a complete
+  // orthonormal basis (used to precondition the next truncation at the same bond)
+  cnt[t] = (t < r && !(sig[t] > 2.0 * floor_abs)) ? 1 : 0;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) cnt[t] += cnt[t + off];
+    __syncthreads();
+  }
+  const bool complete = cnt[0] == 0;
+  __syncthreads();
   cnt[t] = (t < r && sig[t] > 0.0 && sig[t] > thr) ? 1 : 0;
   red[t] = 0.0;
   __syncthreads();
@@ -348,32 +505,72 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(SvdPlan p, SvdWs w, in
   }
   if (t == 0) {
     const double tot = red[0], kept = kept_part[0];
-    *w.k_shared = k;
+    w.k_shared[0] = k;
+    w.k_shared[1] = complete ? 1 : 0;
     if (k_dev) *k_dev = k;
     if (disc_dev) *disc_dev = tot > 0.0 ? fmax(0.0, (tot - kept) / tot) : 0.0;
     if (norm_dev) *norm_dev = sqrt(kept);
   }
 }
 
-// The kept isometry: direction 0 -> A_out[i][r] = X[i][perm r] / sigma (m x kcap);
-// direction 1 -> B_out[r][c] = conj(X[c][perm r]) / sigma (kcap x n). Zero beyond k.
-__global__ void svd_isometry_kernel(SvdPlan p, SvdWs w, int kcap, double2* out) {
-  const int k = *w.k_shared;
-  const long long total = (long long)p.mx * kcap;
+// The kept isometry in descending order of sigma, zero beyond k. Source column j: the
+// normalised converged column X[:, j] / sigma_j (from_q 0, length mx) or the accumulated
+// rotation's column Q[:, j] (from_q 1, length nx); its length is m (direction 0) or n (1).
+// Direction 0 -> A_out[i][r] = src[perm r][i] (m x kcap); direction 1 -> B_out[r][c] =
+// conj(src[perm r][c]) (kcap x n).
+__global__ void svd_isometry_kernel(SvdPlan p, SvdWs w, int kcap, double2* out, int from_q) {
+  const int k = w.k_shared[0];
+  const int len = p.direction == 0 ? p.m : p.n;
+  const int ld = from_q ? p.nx : p.mx;
+  const double2* src = from_q ? w.Q : w.X;
+  const long long total = (long long)len * kcap;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     int i, rr;
     if (p.direction == 0) { i = (int)(idx / kcap); rr = (int)(idx % kcap); }
-    else { rr = (int)(idx / p.mx); i = (int)(idx % p.mx); }
+    else { rr = (int)(idx / len); i = (int)(idx % len); }
     double2 v{0.0, 0.0};
     if (rr < k) {
       const int j = w.perm[rr];
-      const double s = w.sigma[j];
-      const double2 x = w.X[(long long)j * p.mx + i];
-      if (s > 0.0) v = double2{x.x / s, (p.direction == 0 ? x.y : -x.y) / s};
+      const double2 x = src[(long long)j * ld + i];
+      if (from_q) v = x;
+      else {
+        const double s = w.sigma[j];
+        if (s > 0.0) v = double2{x.x / s, x.y / s};
+      }
+      if (p.direction == 1) v.y = -v.y;
     }
     out[idx] = v;
   }
+}
+
+// Complete unitary basis of the column space of X (square X only): out[j][row] = X[j][row] /
+// sigma_j when every column is above the rounding floor, otherwise the identity (which makes the
+// next preconditioning product an exact copy).
+__global__ void svd_basis_kernel(SvdPlan p, SvdWs w, double2* out) {
+  const int complete = w.k_shared[1];
+  const long long total = (long long)p.mx * p.nx;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / p.mx), row = (int)(idx % p.mx);
+    double2 v{row == j ? 1.0 : 0.0, 0.0};
+    if (complete) {
+      const double inv = 1.0 / w.sigma[j];
+      const double2 x = w.X[idx];
+      v = double2{x.x * inv, x.y * inv};
+    }
+    out[idx] = v;
+  }
+}
+
+template <int RMAX, bool ACC>
+const void* jacobi_fn() {
+  return reinterpret_cast<const void*>(svd_jacobi_kernel<RMAX, ACC>);
+}
+
+const void* jacobi_for(const SvdPlan& p) {
+  if (p.acc) return p.rmax == 4 ? jacobi_fn<4, true>() : p.rmax == 8 ? jacobi_fn<8, true>() : jacobi_fn<16, true>();
+  return p.rmax == 4 ? jacobi_fn<4, false>() : p.rmax == 8 ? jacobi_fn<8, false>() : jacobi_fn<16, false>();
 }
 
 }  // namespace
@@ -385,33 +582,46 @@ size_t svd_ws_bound(int maxdim) {
   auto it = memo.find(maxdim);
   if (it != memo.end()) return it->second;
   size_t best = 0;
-  for (int mx = 1; mx <= maxdim; ++mx)
-    for (int nx = 1; nx <= maxdim; ++nx) best = std::max(best, svd_plan(mx, nx, 0).ws);
+  for (int m = 1; m <= maxdim; ++m)
+    for (int n = 1; n <= maxdim; ++n)
+      for (int dir = 0; dir < 2; ++dir) best = std::max(best, svd_plan(m, n, dir, true).ws);
   memo[maxdim] = best;
   return best;
 }
 
 hipError_t svd_configure() {
-  MPOEVO_HIP_TRY(hipFuncSetAttribute((const void*)svd_jacobi_kernel<4>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSvdLdsBytes));
-  MPOEVO_HIP_TRY(hipFuncSetAttribute((const void*)svd_jacobi_kernel<8>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSvdLdsBytes));
-  return hipFuncSetAttribute((const void*)svd_jacobi_kernel<16>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSvdLdsBytes);
+  const void* fns[] = {jacobi_fn<4, false>(), jacobi_fn<8, false>(), jacobi_fn<16, false>(),
+                       jacobi_fn<4, true>(),  jacobi_fn<8, true>(),  jacobi_fn<16, true>()};
+  for (const void* f : fns)
+    MPOEVO_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSvdLdsBytes));
+  return hipSuccess;
 }
 
-SvdPlan svd_plan(int m, int n, int direction, size_t lds_cap) {
-  SvdPlan p;
+SvdPlan svd_plan(int m, int n, int direction, bool want_basis, size_t lds_cap) {
+  SvdPlan p{};
   p.m = m;
   p.n = n;
   p.direction = direction;
-  p.mx = direction == 0 ? m : n;
-  p.nx = direction == 0 ? n : m;
+  if (m == n) {
+    p.xconj = direction;
+    p.acc = 0;
+  } else if (m > n) {
+    p.xconj = 0;
+    p.acc = (direction == 1 || want_basis) ? 1 : 0;
+  } else {
+    p.xconj = 1;
+    p.acc = (direction == 0 || want_basis) ? 1 : 0;
+  }
+  p.mx = p.xconj == 0 ? m : n;
+  p.nx = p.xconj == 0 ? n : m;
   p.rank_max = std::min(m, n);
   p.rmax = p.mx <= 256 ? 4 : (p.mx <= 512 ? 8 : 16);
-  const int waves = p.rmax <= 8 ? 16 : 8;
-  const size_t col_cap = lds_cap / (sizeof(double2) * (size_t)p.mx);  // columns that fit in LDS
-  int b = std::min<int>((p.nx + 1) / 2, waves);                       // one pair per wave
+  // Block width: small blocks spread a sweep over more workgroups (compute units) at the price
+  // of more grid barriers per sweep; 8 columns (16 workgroups for 256 columns) balances the two.
+  const int bmax = p.rmax <= 8 ? 8 : 4;
+  const size_t col_bytes = sizeof(double2) * ((size_t)p.mx + (p.acc ? (size_t)p.nx : 0));
+  const size_t col_cap = lds_cap / col_bytes;  // columns that fit in LDS
+  int b = std::min<int>((p.nx + 1) / 2, bmax);   // one pair per wave
   b = std::max(1, std::min<int>(b, (int)(col_cap / 2)));
   int nb = (p.nx + b - 1) / b;
   if (nb < 2) nb = 2;
@@ -419,29 +629,48 @@ SvdPlan svd_plan(int m, int n, int direction, size_t lds_cap) {
   p.b = b;
   p.nb = nb;
   p.np = nb * b;
-  p.threads = waves * 64;
-  p.lds = sizeof(double2) * (size_t)2 * p.b * p.mx;
-  p.ws = align256(sizeof(double2) * (size_t)p.mx * p.np) + align256(sizeof(double) * p.np) +
-         align256(sizeof(int) * p.np) + 256 + align256(sizeof(unsigned) * kMaxSweeps) + 256;
+  p.threads = b * 64;
+  p.lds = col_bytes * (size_t)2 * p.b;
+  p.ws = ws_bytes(p.mx, p.nx, p.np, p.acc != 0);
   return p;
 }
 
 double svd_sweep_flop(const SvdPlan& p) {
-  const double pair_visits = (double)(p.nb - 1) * (p.nb / 2) * p.b * (2 * p.b - 1);
-  return pair_visits * 36.0 * p.mx;
+  // one full round (every pair inside a block pair) and nb - 2 cross rounds (b x b pairs)
+  const double pair_visits =
+      (double)(p.nb / 2) * (p.b * (2.0 * p.b - 1) + (double)(p.nb - 2) * p.b * p.b);
+  return pair_visits * (36.0 * p.mx + (p.acc ? 20.0 * p.nx : 0.0));
 }
 
 hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double cutoff,
                         double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
-                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev) {
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
+                        const double2* warm, double2* basis_out) {
+  if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx))
+    return hipErrorInvalidConfiguration;
   SvdWs w = carve(p, ws);
   const int kcap = std::min(Dmax, std::min(p.m, p.n));
+  const bool square = p.m == p.n;
+  // A preconditioner needs a complete basis to come back: the columns (square) or Q (rectangular).
+  if (!square && !p.acc) warm = nullptr, basis_out = nullptr;
   {
     const long long total = (long long)p.mx * p.np;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
-    hipLaunchKernelGGL(svd_init_kernel, dim3(blocks), dim3(256), 0, st, theta, p, w);
+    hipLaunchKernelGGL(svd_init_kernel, dim3(blocks), dim3(256), 0, st, theta, p, w, warm ? 0 : 1,
+                       p.acc ? warm : nullptr);
     MPOEVO_HIP_TRY(hipGetLastError());
+  }
+  if (warm) {  // X = Theta P (xconj 0) or Theta^dag P (xconj 1), column-major
+    GemmDesc g{};
+    g.batch = 1;
+    g.A = theta; g.B = warm; g.C = w.X;
+    g.M = p.mx; g.N = p.nx; g.K = p.nx;
+    if (p.xconj == 0) { g.sAm = p.n; g.sAk = 1; }
+    else { g.sAm = 1; g.sAk = p.n; g.conjA = true; }
+    g.sBk = 1; g.sBn = p.nx;
+    g.sCm = 1; g.sCn = p.mx;
+    MPOEVO_HIP_TRY(gemm_launch(g, true, true, st));
   }
   const int wpb = 4;
   hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, w,
@@ -456,11 +685,8 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     int* stp = status;
     int* swp = sweeps_dev;
     void* args[] = {&pp, &ww, &tt, &stp, &swp};
-    const void* fn = p.rmax == 4 ? (const void*)svd_jacobi_kernel<4>
-                     : p.rmax == 8 ? (const void*)svd_jacobi_kernel<8>
-                                   : (const void*)svd_jacobi_kernel<16>;
     if (ev0) MPOEVO_HIP_TRY(hipEventRecord(ev0, st));
-    MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.nb / 2), dim3(p.threads), args,
+    MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(jacobi_for(p), dim3(p.nb / 2), dim3(p.threads), args,
                                               (unsigned)p.lds, st));
     if (ev1) MPOEVO_HIP_TRY(hipEventRecord(ev1, st));
   }
@@ -470,12 +696,26 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, p, w, kcap, cutoff, k_dev,
                      disc_dev, norm_dev, sigma_dev);
   MPOEVO_HIP_TRY(hipGetLastError());
+  // the kept factor comes from the columns when it lies on X's column side, else from Q
+  const bool from_q = (p.direction == 0) != (p.xconj == 0);
   double2* iso = p.direction == 0 ? A_out : B_out;
   {
-    const long long total = (long long)p.mx * kcap;
+    const long long total = (long long)(p.direction == 0 ? p.m : p.n) * kcap;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(svd_isometry_kernel, dim3(blocks), dim3(256), 0, st, p, w, kcap, iso);
+    hipLaunchKernelGGL(svd_isometry_kernel, dim3(blocks), dim3(256), 0, st, p, w, kcap, iso,
+                       from_q ? 1 : 0);
     MPOEVO_HIP_TRY(hipGetLastError());
+  }
+  if (basis_out) {
+    if (square) {
+      const long long total = (long long)p.mx * p.nx;
+      const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
+      hipLaunchKernelGGL(svd_basis_kernel, dim3(blocks), dim3(256), 0, st, p, w, basis_out);
+      MPOEVO_HIP_TRY(hipGetLastError());
+    } else {  // the accumulated P Q (its first nx columns are contiguous)
+      MPOEVO_HIP_TRY(hipMemcpyAsync(basis_out, w.Q, sizeof(double2) * (size_t)p.nx * p.nx,
+                                    hipMemcpyDeviceToDevice, st));
+    }
   }
   GemmDesc g{};
   g.batch = 1;

@@ -42,7 +42,8 @@ class _MPO(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("nsweeps", ctypes.c_int), ("prec", ctypes.c_int), ("cutoff", ctypes.c_double),
-                ("input_right_canonical", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("input_right_canonical", ctypes.c_int), ("profile", ctypes.c_int),
+                ("svd_cold_start", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -51,7 +52,8 @@ class _Stats(ctypes.Structure):
                 ("max_bond", ctypes.c_int), ("gflop", ctypes.c_double), ("svd_sweeps_max", ctypes.c_int),
                 ("t_jacobi_ms", ctypes.c_double), ("jacobi_gflop", ctypes.c_double), ("n_jacobi", ctypes.c_int),
                 ("t_gemm_ms", ctypes.c_double), ("gemm_gflop", ctypes.c_double), ("n_gemm", ctypes.c_int),
-                ("t_wmix_ms", ctypes.c_double), ("wmix_gbyte", ctypes.c_double), ("n_wmix", ctypes.c_int)]
+                ("t_wmix_ms", ctypes.c_double), ("wmix_gbyte", ctypes.c_double), ("n_wmix", ctypes.c_int),
+                ("svd_sweeps_total", ctypes.c_int), ("svd_sweeps_hist", ctypes.c_int * 32)]
 
 
 _lib = None
@@ -248,6 +250,8 @@ class StepStats:
     gflop: float
     svd_sweeps_max: int
     profile: dict | None = None
+    svd_sweeps_total: int = 0
+    svd_sweeps_hist: tuple = ()
 
 
 class DeviceMPS:
@@ -301,7 +305,7 @@ def step_workspace(mps: DeviceMPS, mpo: DeviceMPO, prec: int):
 
 def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int = FP64,
          cutoff: float = 1e-14, input_right_canonical: bool = False, workspace=None,
-         stream=None, profile: bool = False) -> StepStats:
+         stream=None, profile: bool = False, svd_cold_start: bool = False) -> StepStats:
     """One time step of the variational fit; mps is updated in place (see include/mpoevo.h)."""
     if workspace is None:
         workspace = step_workspace(mps, mpo, prec)
@@ -310,7 +314,8 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
     cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
     cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
-    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), int(bool(profile)))
+    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), int(bool(profile)),
+                 int(bool(svd_cold_start)))
     st = _Stats()
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
                        _ptr(workspace), workspace.numel(), _stream(stream)), h)
@@ -320,4 +325,4 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
         prof = {k: getattr(st, k) for k in ("t_jacobi_ms", "jacobi_gflop", "n_jacobi", "t_gemm_ms",
                                             "gemm_gflop", "n_gemm", "t_wmix_ms", "wmix_gbyte", "n_wmix")}
     return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
-                     st.svd_sweeps_max, prof)
+                     st.svd_sweeps_max, prof, st.svd_sweeps_total, tuple(st.svd_sweeps_hist))

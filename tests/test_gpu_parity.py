@@ -279,3 +279,35 @@ def test_step_profile_mode_matches_plain_step(mp, handle):
     assert p["n_jacobi"] == sa.visits and p["t_jacobi_ms"] > 0 and p["jacobi_gflop"] > 0
     assert p["n_gemm"] > 0 and p["t_gemm_ms"] > 0 and p["gemm_gflop"] > 0
     assert p["n_wmix"] > 0 and p["wmix_gbyte"] > 0
+
+
+def test_step_warm_started_truncations_match_cold_and_oracle(mp, handle):
+    """Preconditioned Jacobi (the unitary the previous truncation of a bond left behind) gives the
+    same trajectory as cold starts and as the oracle, with fewer sweeps once the bases exist."""
+    _say("step warm start L=12 D=8 saturated random state, 4 steps")
+    L, D = 12, 8  # bonds 3..7 have square 16 x 16 bond matrices
+    rng = np.random.default_rng(11)
+    psi = _normalise(wl.random_mps(rng, L, 2, D))
+    H = wl.tfim(1.5)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    dw = mp.DeviceMPO([W] * L)
+    warm = mp.DeviceMPS(psi, Dmax=D)
+    cold = mp.DeviceMPS(psi, Dmax=D)
+    ws_w = mp.step_workspace(warm, dw, mp.FP64)
+    ws_c = torch.empty_like(ws_w)
+    ref = psi
+    tot_w, tot_c = [], []
+    for s in range(4):
+        sw = mp.step(handle, warm, dw, prec=mp.FP64, input_right_canonical=s > 0, workspace=ws_w)
+        sc = mp.step(handle, cold, dw, prec=mp.FP64, input_right_canonical=s > 0, workspace=ws_c,
+                     svd_cold_start=True)
+        ref, _ = ofit.fit_step(ref, W, Dmax=D, nsweeps=2)
+        a, b = warm.to_numpy(), cold.to_numpy()
+        assert 1 - abs(ofit.overlap(a, b)) ** 2 < 1e-12, s
+        assert 1 - abs(ofit.overlap(a, ref)) ** 2 < 1e-10, s
+        assert abs(sw.norm - sc.norm) < 1e-11 * sc.norm
+        tot_w.append(sw.svd_sweeps_total)
+        tot_c.append(sc.svd_sweeps_total)
+    print("total sweeps per step: warm", tot_w, "cold", tot_c, flush=True)
+    assert all(t > 0 for t in tot_w + tot_c)
+    assert sum(tot_w[1:]) < sum(tot_c[1:])
