@@ -24,7 +24,12 @@ struct GemmDesc {
   long long sAm, sAk, sBk, sBn, sCm, sCn;
   long long bA, bB, bC;
   bool conjA, conjB;
+  void* ws;         // optional scratch for split-K partial tiles (null: never split)
+  size_t ws_bytes;
 };
+
+// Scratch a caller gives gemm_launch for split-K partial results (the planner never needs more).
+constexpr size_t kGemmScratchBytes = size_t(32) << 20;
 
 // Launch a complex product with real fp32 (T = float) or fp64 (T = double) matrix-core
 // arithmetic. out_fp64: store C as complex128 even when T = float. Returns a hipError_t.

@@ -154,8 +154,10 @@ hipError_t gemm_timed(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t s
 
 hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, void* tmp,
                       void* LB, int P, int wl, int Qa, int d, int Qb, int wr, hipStream_t st,
-                      Prof* pr = nullptr) {
+                      Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = E; g.B = ket; g.C = tmp;
   g.M = P * wl; g.N = d * Qb; g.K = Qa; g.batch = 1;
   g.sAm = Qa; g.sAk = 1; g.sBk = (long long)d * Qb; g.sBn = 1; g.sCm = (long long)d * Qb; g.sCn = 1;
@@ -171,8 +173,10 @@ hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, 
 // ket: (Qa, d, Qb), E: (Pr, wr, Qb), W: (wl, d, d, wr). tmp holds Qa*d*Pr*wr complex.
 hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W, void* tmp,
                        void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st,
-                       Prof* pr = nullptr) {
+                       Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = ket; g.B = E; g.C = tmp;
   g.M = Qa * d; g.N = Pr * wr; g.K = Qb; g.batch = 1;
   g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sBn = Qb; g.sCm = (long long)Pr * wr; g.sCn = 1;
@@ -187,8 +191,10 @@ hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W,
 // Lnew[b'][beta][b] = sum conj(bra[a'][s'][b']) LB[a'][s'][beta][b]; bra: (Pa, d, Pb).
 hipError_t left_env_from_block(bool fp64, const void* bra, const void* LB, void* Lnew, int Pa,
                                int d, int Pb, int wr, int Qb, hipStream_t st,
-                         Prof* pr = nullptr) {
+                         Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = bra; g.B = LB; g.C = Lnew;
   g.M = Pb; g.N = wr * Qb; g.K = Pa * d; g.batch = 1;
   g.sAm = 1; g.sAk = Pb; g.conjA = true;
@@ -199,8 +205,10 @@ hipError_t left_env_from_block(bool fp64, const void* bra, const void* LB, void*
 // Rnew[a'][alpha][a] = sum conj(bra[a'][t'][c']) RB[alpha][a][t'][c']; bra: (Pa, d, Pb).
 hipError_t right_env_from_block(bool fp64, const void* bra, const void* RB, void* Rnew, int Pa,
                                 int d, int Pb, int wl, int Qa, hipStream_t st,
-                         Prof* pr = nullptr) {
+                         Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = bra; g.B = RB; g.C = Rnew;
   g.M = Pa; g.N = wl * Qa; g.K = d * Pb; g.batch = 1;
   g.sAm = (long long)d * Pb; g.sAk = 1; g.conjA = true;
@@ -211,8 +219,10 @@ hipError_t right_env_from_block(bool fp64, const void* bra, const void* RB, void
 // Theta[(a',s')][(t',c')] = sum LB[(a',s')][(beta,b)] RB[(beta,b)][(t',c')], complex128 out.
 hipError_t theta_product(bool fp64, const void* LB, const void* RB, void* theta, int Pa, int d,
                          int wm, int Qm, int Pc, hipStream_t st,
-                         Prof* pr = nullptr) {
+                         Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = LB; g.B = RB; g.C = theta;
   g.M = Pa * d; g.N = d * Pc; g.K = wm * Qm; g.batch = 1;
   g.sAm = (long long)wm * Qm; g.sAk = 1; g.sBk = (long long)d * Pc; g.sBn = 1;
@@ -223,8 +233,10 @@ hipError_t theta_product(bool fp64, const void* LB, const void* RB, void* theta,
 // Site product site[a][s][b] <- sum_c site_in[a][s][c] R[c][b] (complex128), used to absorb
 // the U S factor of the right-canonicalisation into the site on the left.
 hipError_t absorb_right(const void* site_in, const void* R, void* site_out, int Pa, int d, int Pc,
-                        int Pb, hipStream_t st) {
+                        int Pb, hipStream_t st, void* gws = nullptr) {
   GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = site_in; g.B = R; g.C = site_out;
   g.M = Pa * d; g.N = Pb; g.K = Pc; g.batch = 1;
   g.sAm = Pc; g.sAk = 1; g.sBk = Pb; g.sBn = 1; g.sCm = Pb; g.sCn = 1;
@@ -236,7 +248,7 @@ struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
   size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
-      off_basis, basiscap, off_token, total;
+      off_basis, basiscap, off_token, off_gemm, total;
 };
 
 StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
@@ -272,6 +284,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.basiscap = (size_t)d * Dmax * d * Dmax;
   s.off_basis = take(sizeof(double2) * s.basiscap * (size_t)std::max(L - 1, 1));
   s.off_token = take(sizeof(unsigned long long));  // which step last wrote the unitaries
+  s.off_gemm = take(kGemmScratchBytes);             // split-K partial products
   s.total = o;
   return s;
 }
@@ -315,7 +328,7 @@ void device_fini(Context& ctx) {
   ctx.dev = nullptr;
 }
 
-size_t env_update_ws(const int* dims, int prec) {
+size_t env_update_core(const int* dims, int prec) {
   const size_t Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4],
                wl = dims[5], wr = dims[6];
   const size_t cs = csize(prec);
@@ -324,12 +337,20 @@ size_t env_update_ws(const int* dims, int prec) {
   return std::max(left, right);
 }
 
-size_t local_apply_ws(const int* dims, int prec) {
+size_t env_update_ws(const int* dims, int prec) {
+  return env_update_core(dims, prec) + kGemmScratchBytes;  // split-K scratch at the end
+}
+
+size_t local_apply_core(const int* dims, int prec) {
   const size_t Dbl = dims[0], Dkm = dims[2], Dbr = dims[4], d = dims[5], wl = dims[6],
                wm = dims[7], wr = dims[8];
   const size_t cs = csize(prec);
   const size_t tmp = std::max(cs * Dbl * wl * d * Dkm, cs * Dkm * d * Dbr * wr);
   return a256(tmp) + a256(cs * Dbl * d * wm * Dkm) + a256(cs * wm * Dkm * d * Dbr);
+}
+
+size_t local_apply_ws(const int* dims, int prec) {
+  return local_apply_core(dims, prec) + kGemmScratchBytes;  // split-K scratch at the end
 }
 
 size_t truncate_ws(int m, int n) {
@@ -375,17 +396,20 @@ int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const voi
   const size_t cs = csize(prec);
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* base = static_cast<unsigned char*>(ws);
+  void* gws = base + env_update_core(dims, prec);
   hipError_t e;
   if (side == MPOEVO_LEFT) {
     void* tmp = base;
     void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
-    e = left_block(fp64, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st);
-    if (e == hipSuccess) e = left_env_from_block(fp64, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st);
+    e = left_block(fp64, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws);
+    if (e == hipSuccess)
+      e = left_env_from_block(fp64, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st, nullptr, gws);
   } else {
     void* tmp = base;
     void* RB = base + a256(cs * (size_t)Dkl * d * Dbr * wr);
-    e = right_block(fp64, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st);
-    if (e == hipSuccess) e = right_env_from_block(fp64, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st);
+    e = right_block(fp64, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st, nullptr, gws);
+    if (e == hipSuccess)
+      e = right_env_from_block(fp64, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st, nullptr, gws);
   }
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "env_update");
 }
@@ -408,9 +432,11 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
   void* tmp = base;
   void* LB = base + tmpb;
   void* RB = base + tmpb + a256(cs * (size_t)Dbl * d * wm * Dkm);
-  hipError_t e = left_block(fp64, L, M1, W1, tmp, LB, Dbl, wl, Dkl, d, Dkm, wm, st);
-  if (e == hipSuccess) e = right_block(fp64, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st);
-  if (e == hipSuccess) e = theta_product(fp64, LB, RB, Theta, Dbl, d, wm, Dkm, Dbr, st);
+  void* gws = base + local_apply_core(dims, prec);
+  hipError_t e = left_block(fp64, L, M1, W1, tmp, LB, Dbl, wl, Dkl, d, Dkm, wm, st, nullptr, gws);
+  if (e == hipSuccess)
+    e = right_block(fp64, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st, nullptr, gws);
+  if (e == hipSuccess) e = theta_product(fp64, LB, RB, Theta, Dbl, d, wm, Dkm, Dbr, st, nullptr, gws);
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "local_apply");
 }
 
@@ -470,6 +496,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   double2* site_tmp2 = reinterpret_cast<double2*>(base + lay.off_site_tmp2);
   const int* w = mpo->w;
   auto basis = [&](int i) { return reinterpret_cast<double2*>(base + lay.off_basis) + lay.basiscap * i; };
+  void* gws = base + lay.off_gemm;
 
   // Jacobi preconditioners: kept in the workspace between steps of the same handle, valid while
   // the workspace and the chain's shape stay the same; otherwise every bond restarts from the
@@ -548,7 +575,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                             nullptr, nullptr, svdws, ctx.dev->status, st));
       STEP_TRY(hipMemcpyAsync(phi(i), B, sizeof(double2) * (size_t)kcap * n, hipMemcpyDeviceToDevice, st));
       // phi_{i-1} <- phi_{i-1} . (U S)
-      STEP_TRY(absorb_right(phi(i - 1), A, site_tmp2, P[i - 1], d, m, kcap, st));
+      STEP_TRY(absorb_right(phi(i - 1), A, site_tmp2, P[i - 1], d, m, kcap, st, gws));
       STEP_TRY(hipMemcpyAsync(phi(i - 1), site_tmp2, sizeof(double2) * (size_t)P[i - 1] * d * kcap,
                               hipMemcpyDeviceToDevice, st));
       P[i] = kcap;
@@ -560,10 +587,10 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   STEP_TRY(set_boundary(env1, w[L], fp64, st));  // Renv_L
   for (int i = L - 1; i >= 1; --i) {
     STEP_TRY(right_block(fp64, ket(i), env1, wsite(i), tmp, RB(i), Q[i], d, Q[i + 1], P[i + 1],
-                         w[i], w[i + 1], st, prof));
+                         w[i], w[i + 1], st, prof, gws));
     flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
     if (i > 1) {
-      STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st, prof));
+      STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st, prof, gws));
       flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
     }
   }
@@ -578,14 +605,14 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       if (i == 0) STEP_TRY(set_boundary(env0, w[0], fp64, st));
       else {
         STEP_TRY(left_env_from_block(fp64, bra(i - 1), LB(i - 1), env0, P[i - 1], d, P[i],
-                                     w[i], Q[i], st, prof));
+                                     w[i], Q[i], st, prof, gws));
         flop_gemm(P[i], (double)w[i] * Q[i], (double)P[i - 1] * d);
       }
       STEP_TRY(left_block(fp64, env0, ket(i), wsite(i), tmp, LB(i), P[i], w[i], Q[i], d, Q[i + 1],
-                          w[i + 1], st, prof));
+                          w[i + 1], st, prof, gws));
       flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
       const int m = P[i] * d, n = d * P[i + 2];
-      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof));
+      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
@@ -609,14 +636,14 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     for (int i = L - 2; i >= 0; --i, ++visit) {
       if (i < L - 2) {
         STEP_TRY(right_env_from_block(fp64, bra(i + 2), RB(i + 2), env1, P[i + 2], d, P[i + 3],
-                                      w[i + 2], Q[i + 2], st, prof));
+                                      w[i + 2], Q[i + 2], st, prof, gws));
         flop_gemm(P[i + 2], (double)w[i + 2] * Q[i + 2], (double)d * P[i + 3]);
         STEP_TRY(right_block(fp64, ket(i + 1), env1, wsite(i + 1), tmp, RB(i + 1), Q[i + 1], d,
-                             Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st, prof));
+                             Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st, prof, gws));
         flop_gemm((double)Q[i + 1] * d, (double)P[i + 2] * w[i + 2], Q[i + 2]);
       }
       const int m = P[i] * d, n = d * P[i + 2];
-      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof));
+      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {

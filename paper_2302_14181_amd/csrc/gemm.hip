@@ -13,9 +13,17 @@
 //       lane l holds C'[(r/4)*8 + (l/32)*4 + r%4][l%32]).
 // fp64: v_mfma_f64_16x16x4f64 (lane l supplies A'[l%16][l/16], B'[l/16][l%16]; accumulator r of
 //       lane l holds C'[4r + l/16][l%16]).
-// A workgroup of 4 waves (2 x 2) owns a BM x BN complex tile, double-buffered in LDS with one
-// barrier per K step; global loads of the next K step are issued before the current step's
-// matrix instructions.
+// A workgroup of 4 waves (2 x 2, each wave WR x WC matrix-instruction tiles) owns a BM x BN
+// complex tile, double-buffered in LDS with one barrier per K step; global loads of the next K
+// step are issued before the current step's matrix instructions.
+//
+// Occupancy: the products of a sweep are small (M x N of a few hundred), so a planner picks the
+// largest tile that still gives every compute unit a workgroup, and when even the smallest tile
+// leaves most of the 256 compute units idle it splits K: each split writes its partial tile to
+// scratch and a second kernel sums the splits in a fixed order (results do not depend on
+// scheduling).
+
+#include <algorithm>
 
 #include "dev_common.h"
 
@@ -29,7 +37,6 @@ struct MfmaF32 {
   using T = float;
   using acc_t = f32x16;
   static constexpr int MT = 32, NT = 32, KT = 2, NACC = 16;
-  static constexpr int WR = 2, WC = 2;  // MFMA tiles per wave (rows, real cols)
   __device__ static acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
@@ -43,7 +50,6 @@ struct MfmaF64 {
   using T = double;
   using acc_t = f64x4;
   static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4;
-  static constexpr int WR = 2, WC = 4;
   __device__ static acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -54,13 +60,17 @@ struct MfmaF64 {
 };
 
 constexpr int kThreads = 256;
-constexpr int kBK = 8;  // complex K per stage
+constexpr int kBK = 8;          // complex K per stage
+constexpr int kMinWgs = 256;    // a tile giving at least this many workgroups is used as is
+constexpr int kTargetWgs = 512; // split K up to this many workgroups
+constexpr int kMaxSplits = 16;
+constexpr int kMinSplitK = 32;  // complex K per split, at least
 
-template <class Mf>
+template <class Mf, int WR, int WC>
 struct Tile {
   using T = typename Mf::T;
-  static constexpr int BM = 2 * Mf::WR * Mf::MT;      // complex rows per workgroup
-  static constexpr int BNR = 2 * Mf::WC * Mf::NT;     // real columns per workgroup
+  static constexpr int BM = 2 * WR * Mf::MT;          // complex rows per workgroup
+  static constexpr int BNR = 2 * WC * Mf::NT;         // real columns per workgroup
   static constexpr int BN = BNR / 2;                  // complex columns
   static constexpr int KR = 2 * kBK;                  // real k per stage
   static constexpr int LDA = BM + 4;                  // padded LDS row lengths (elements)
@@ -68,20 +78,27 @@ struct Tile {
   static constexpr int A_ELEMS = BM * kBK / kThreads;  // complex loads per thread
   static constexpr int B_ELEMS = BN * kBK / kThreads;
   static constexpr int LDS_ELEMS = KR * LDA + KR * LDB;
+  static_assert(A_ELEMS >= 1 && B_ELEMS >= 1, "tile too small for the staging scheme");
 };
 
-template <class Mf, typename TO, bool AKC, bool BNC>
-__global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g) {
+// splits > 1: the workgroup at blockIdx.z = batch * splits + s covers K in [s kchunk, (s+1)
+// kchunk) and writes its partial tile (precision T) to part[s][batch][M][N].
+template <class Mf, int WR, int WC, typename TO, bool AKC, bool BNC>
+__global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits, int kchunk,
+                                                         void* part) {
   using T = typename Mf::T;
   using C2 = cx_t<T>;
-  using TT = Tile<Mf>;
+  using TT = Tile<Mf, WR, WC>;
   __shared__ T lds[2 * TT::LDS_ELEMS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int bz = blockIdx.z;
+  const int bz = blockIdx.z / splits;
+  const int sk = blockIdx.z - bz * splits;
+  const int kbeg = sk * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
   const int m0 = blockIdx.y * TT::BM;
   const int n0 = blockIdx.x * TT::BN;
 
@@ -101,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g) {
       if (AKC) { m = e / kBK; k = e % kBK; } else { k = e / TT::BM; m = e % TT::BM; }
       const int gm = m0 + m, gk = k0 + k;
       C2 v{T(0), T(0)};
-      if (gm < g.M && gk < g.K) v = A[gm * g.sAm + gk * g.sAk];
+      if (gm < g.M && gk < kend) v = A[gm * g.sAm + gk * g.sAk];
       ra[i] = v;
     }
 #pragma unroll
@@ -111,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g) {
       if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / kBK; k = e % kBK; }
       const int gk = k0 + k, gn = n0 + n;
       C2 v{T(0), T(0)};
-      if (gk < g.K && gn < g.N) v = B[gk * g.sBk + gn * g.sBn];
+      if (gk < kend && gn < g.N) v = B[gk * g.sBk + gn * g.sBn];
       rb[i] = v;
     }
   };
@@ -141,75 +158,171 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g) {
     }
   };
 
-  typename Mf::acc_t acc[Mf::WR][Mf::WC];
+  typename Mf::acc_t acc[WR][WC];
 #pragma unroll
-  for (int i = 0; i < Mf::WR; ++i)
+  for (int i = 0; i < WR; ++i)
 #pragma unroll
-    for (int j = 0; j < Mf::WC; ++j)
+    for (int j = 0; j < WC; ++j)
 #pragma unroll
       for (int r = 0; r < Mf::NACC; ++r) acc[i][j][r] = T(0);
 
-  const int nk = (g.K + kBK - 1) / kBK;
-  load_tiles(0);
+  const int nk = (kend - kbeg + kBK - 1) / kBK;
+  load_tiles(kbeg);
   store_tiles(0);
   __syncthreads();
 
   const int arow = Mf::a_row(lane), ak = Mf::a_k(lane);
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load_tiles((kt + 1) * kBK);
+    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * kBK);
     const T* As = lds + cur * TT::LDS_ELEMS;
     const T* Bs = As + TT::KR * TT::LDA;
 #pragma unroll
     for (int kr = 0; kr < TT::KR; kr += Mf::KT) {
-      T af[Mf::WR], bf[Mf::WC];
+      T af[WR], bf[WC];
 #pragma unroll
-      for (int i = 0; i < Mf::WR; ++i)
-        af[i] = As[(kr + ak) * TT::LDA + wm * (Mf::WR * Mf::MT) + i * Mf::MT + arow];
+      for (int i = 0; i < WR; ++i)
+        af[i] = As[(kr + ak) * TT::LDA + wm * (WR * Mf::MT) + i * Mf::MT + arow];
 #pragma unroll
-      for (int j = 0; j < Mf::WC; ++j)
-        bf[j] = Bs[(kr + ak) * TT::LDB + wn * (Mf::WC * Mf::NT) + j * Mf::NT + arow];
+      for (int j = 0; j < WC; ++j)
+        bf[j] = Bs[(kr + ak) * TT::LDB + wn * (WC * Mf::NT) + j * Mf::NT + arow];
 #pragma unroll
-      for (int i = 0; i < Mf::WR; ++i)
+      for (int i = 0; i < WR; ++i)
 #pragma unroll
-        for (int j = 0; j < Mf::WC; ++j) acc[i][j] = Mf::mma(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < WC; ++j) acc[i][j] = Mf::mma(af[i], bf[j], acc[i][j]);
     }
     if (kt + 1 < nk) store_tiles(cur ^ 1);
     __syncthreads();
   }
 
+  if (splits == 1) {
+    TO* C = reinterpret_cast<TO*>(g.C);
+    const long long cbase = (long long)bz * g.bC;
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+#pragma unroll
+        for (int r = 0; r < Mf::NACC; ++r) {
+          const int row = m0 + wm * (WR * Mf::MT) + i * Mf::MT + Mf::out_row(lane, r);
+          const int rcol = wn * (WC * Mf::NT) + j * Mf::NT + Mf::out_col(lane);
+          const int col = n0 + (rcol >> 1);
+          if (row < g.M && col < g.N)
+            C[2 * (cbase + row * g.sCm + col * g.sCn) + (rcol & 1)] = TO(acc[i][j][r]);
+        }
+  } else {
+    T* P = reinterpret_cast<T*>(part);
+    const long long pbase = (long long)(sk * g.batch + bz) * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+#pragma unroll
+        for (int r = 0; r < Mf::NACC; ++r) {
+          const int row = m0 + wm * (WR * Mf::MT) + i * Mf::MT + Mf::out_row(lane, r);
+          const int rcol = wn * (WC * Mf::NT) + j * Mf::NT + Mf::out_col(lane);
+          const int col = n0 + (rcol >> 1);
+          if (row < g.M && col < g.N)
+            P[2 * (pbase + (long long)row * g.N + col) + (rcol & 1)] = acc[i][j][r];
+        }
+  }
+}
+
+// C[b][m][n] = sum over s = 0..splits-1 (in that order) of part[s][b][m][n].
+template <typename T, typename TO>
+__global__ void splitk_reduce(GemmDesc g, int splits, const T* __restrict__ part) {
+  const long long mn = (long long)g.M * g.N;
+  const long long total = mn * g.batch;
   TO* C = reinterpret_cast<TO*>(g.C);
-  const long long cbase = (long long)bz * g.bC;
-#pragma unroll
-  for (int i = 0; i < Mf::WR; ++i)
-#pragma unroll
-    for (int j = 0; j < Mf::WC; ++j)
-#pragma unroll
-      for (int r = 0; r < Mf::NACC; ++r) {
-        const int row = m0 + wm * (Mf::WR * Mf::MT) + i * Mf::MT + Mf::out_row(lane, r);
-        const int rcol = wn * (Mf::WC * Mf::NT) + j * Mf::NT + Mf::out_col(lane);
-        const int col = n0 + (rcol >> 1);
-        if (row < g.M && col < g.N)
-          C[2 * (cbase + row * g.sCm + col * g.sCn) + (rcol & 1)] = TO(acc[i][j][r]);
-      }
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    T re = T(0), im = T(0);
+    for (int s = 0; s < splits; ++s) {
+      re += part[2 * (s * total + idx)];
+      im += part[2 * (s * total + idx) + 1];
+    }
+    const long long b = idx / mn, rem = idx - b * mn;
+    const long long row = rem / g.N, col = rem - row * g.N;
+    const long long o = b * g.bC + row * g.sCm + col * g.sCn;
+    C[2 * o] = TO(re);
+    C[2 * o + 1] = TO(im);
+  }
 }
 
-template <class Mf, typename TO, bool AKC, bool BNC>
-hipError_t launch_one(const GemmDesc& g, hipStream_t st) {
-  using TT = Tile<Mf>;
-  dim3 grid((g.N + TT::BN - 1) / TT::BN, (g.M + TT::BM - 1) / TT::BM, g.batch);
-  hipLaunchKernelGGL((cgemm_kernel<Mf, TO, AKC, BNC>), grid, dim3(kThreads), 0, st, g);
-  return hipGetLastError();
+struct Plan {
+  int cfg;     // index into the precision's tile table
+  int bm, bn;  // complex tile
+  int splits, kchunk;
+};
+
+template <class Mf>
+Plan make_plan(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
+  auto tiles = [&](int c) {
+    return (long long)((g.M + cfgs[c][0] - 1) / cfgs[c][0]) * ((g.N + cfgs[c][1] - 1) / cfgs[c][1]) * g.batch;
+  };
+  Plan p{ncfg - 1, cfgs[ncfg - 1][0], cfgs[ncfg - 1][1], 1, g.K};
+  for (int c = 0; c < ncfg; ++c)
+    if (tiles(c) >= kMinWgs) {
+      p.cfg = c; p.bm = cfgs[c][0]; p.bn = cfgs[c][1];
+      return p;
+    }
+  const long long t = tiles(p.cfg);
+  if (!g.ws || t >= kTargetWgs) return p;
+  int s = (int)std::min<long long>((kTargetWgs + t - 1) / t, kMaxSplits);
+  s = std::min(s, g.K / kMinSplitK);
+  const size_t per = sizeof(typename Mf::T) * 2 * (size_t)g.M * g.N * g.batch;
+  s = (int)std::min<size_t>((size_t)s, per ? g.ws_bytes / per : 0);
+  if (s < 2) return p;
+  const int kc = ((g.K + s - 1) / s + kBK - 1) / kBK * kBK;
+  p.kchunk = kc;
+  p.splits = (g.K + kc - 1) / kc;
+  return p;
 }
 
-template <class Mf, typename TO>
-hipError_t launch_layout(const GemmDesc& g, hipStream_t st) {
+constexpr int kF32Cfg[3][2] = {{128, 64}, {64, 64}, {64, 32}};
+constexpr int kF64Cfg[2][2] = {{64, 64}, {32, 32}};
+
+template <class Mf, int WR, int WC, typename TO>
+hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
+  using TT = Tile<Mf, WR, WC>;
+  dim3 grid((g.N + TT::BN - 1) / TT::BN, (g.M + TT::BM - 1) / TT::BM, g.batch * pl.splits);
   const bool akc = (g.sAk == 1) || (g.K == 1);
   const bool bnc = (g.sBn == 1) || (g.N == 1);
-  if (akc && bnc) return launch_one<Mf, TO, true, true>(g, st);
-  if (akc && !bnc) return launch_one<Mf, TO, true, false>(g, st);
-  if (!akc && bnc) return launch_one<Mf, TO, false, true>(g, st);
-  return launch_one<Mf, TO, false, false>(g, st);
+  void* part = pl.splits > 1 ? g.ws : nullptr;
+  if (akc && bnc)
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, true, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else if (akc)
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, true, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else if (bnc)
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  MPOEVO_HIP_TRY(hipGetLastError());
+  if (pl.splits > 1) {
+    using T = typename Mf::T;
+    const long long total = (long long)g.M * g.N * g.batch;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL((splitk_reduce<T, TO>), dim3(blocks), dim3(256), 0, st, g, pl.splits,
+                       static_cast<const T*>(g.ws));
+    MPOEVO_HIP_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template <typename TO>
+hipError_t launch_f32(const GemmDesc& g, hipStream_t st) {
+  const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);
+  switch (pl.cfg) {
+    case 0: return launch_cfg<MfmaF32, 2, 2, TO>(g, pl, st);
+    case 1: return launch_cfg<MfmaF32, 1, 2, TO>(g, pl, st);
+    default: return launch_cfg<MfmaF32, 1, 1, TO>(g, pl, st);
+  }
+}
+
+hipError_t launch_f64(const GemmDesc& g, hipStream_t st) {
+  const Plan pl = make_plan<MfmaF64>(g, kF64Cfg, 2);
+  if (pl.cfg == 0) return launch_cfg<MfmaF64, 2, 4, double>(g, pl, st);
+  return launch_cfg<MfmaF64, 1, 2, double>(g, pl, st);
 }
 
 }  // namespace
@@ -217,9 +330,9 @@ hipError_t launch_layout(const GemmDesc& g, hipStream_t st) {
 hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
-  if (fp64) return launch_layout<MfmaF64, double>(g, st);
-  if (out_fp64) return launch_layout<MfmaF32, double>(g, st);
-  return launch_layout<MfmaF32, float>(g, st);
+  if (fp64) return launch_f64(g, st);
+  if (out_fp64) return launch_f32<double>(g, st);
+  return launch_f32<float>(g, st);
 }
 
 }  // namespace mpoevo

@@ -57,6 +57,7 @@ struct SvdWs {  // carved from the caller's workspace
   unsigned* flags;      // [kMaxGrid] barrier generation reached by each workgroup
   unsigned* sweep_max;  // [kMaxSweeps] bits of the largest |x^dag y| / (|x| |y|) of a sweep
   int* k_shared;        // [0] kept rank, [1] columns form a complete basis
+  void* gemm;           // split-K scratch of the products (kGemmScratchBytes)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -65,7 +66,7 @@ size_t ws_bytes(int mx, int nx, int np, bool acc) {
   return align256(sizeof(double2) * (size_t)mx * np) +
          (acc ? align256(sizeof(double2) * (size_t)nx * np) : 0) + align256(sizeof(double) * np) +
          align256(sizeof(int) * np) + 256 + sizeof(unsigned) * kMaxGrid +
-         align256(sizeof(unsigned) * kMaxSweeps) + 256;
+         align256(sizeof(unsigned) * kMaxSweeps) + 256 + kGemmScratchBytes;
 }
 
 SvdWs carve(const SvdPlan& p, void* ws) {
@@ -90,6 +91,8 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   w.sweep_max = reinterpret_cast<unsigned*>(base + off);
   off += align256(sizeof(unsigned) * kMaxSweeps);
   w.k_shared = reinterpret_cast<int*>(base + off);
+  off += 256;
+  w.gemm = base + off;
   return w;
 }
 
@@ -664,6 +667,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   if (warm) {  // X = Theta P (xconj 0) or Theta^dag P (xconj 1), column-major
     GemmDesc g{};
     g.batch = 1;
+    g.ws = w.gemm; g.ws_bytes = kGemmScratchBytes;
     g.A = theta; g.B = warm; g.C = w.X;
     g.M = p.mx; g.N = p.nx; g.K = p.nx;
     if (p.xconj == 0) { g.sAm = p.n; g.sAk = 1; }
@@ -719,6 +723,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   }
   GemmDesc g{};
   g.batch = 1;
+  g.ws = w.gemm; g.ws_bytes = kGemmScratchBytes;
   if (p.direction == 0) {  // B_out = U_k^dag Theta  (kcap x n)
     g.A = A_out; g.B = theta; g.C = B_out;
     g.M = kcap; g.N = p.n; g.K = p.m;
