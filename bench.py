@@ -1,16 +1,24 @@
 """Benchmark: seconds per time step of the variational higher-order MPO evolution on one MI355X.
 
-Workload (default): transverse-field Ising chain after the quench (g = 1.5), L = 64, order-2
-extended MPO (w = 3) for exp(-i tau H) with tau = 0.1, MPS bond dimension D = 128, two sweeps
-per step, FP32 matrix-core contractions with the FP64 SVD truncation. The input is a seeded
-complex-normal MPS with every bond at min(128, 2^i, 2^(L-i)) (the saturated regime the quench
-reaches); the first warm-up step brings it to right-canonical form and every timed step
-evolves the state further. Also reported: the same steps on the plain FP64 path, the
-environment-update microbenchmark at D = 256, d = 2, w = 8 (the matrix-core roofline target),
-per-kernel-class times of one profiled step, and the CPU oracle timed on one step of the same
-workload (its infidelity against the GPU step from the same input is the parity figure).
+Workload (default): the quench of the open transverse-field Ising chain H = -sum Z Z - g sum X,
+L = 64, from the ground state at g = 0.5 (tests/golden/tfim_g05_L64_ground.npz, prepared by the
+oracle) to g = 1.5, with the order-2 extended MPO (w = 3) of exp(-i tau H), tau = 0.1, bond
+dimension D <= 128, truncation cutoff 1e-14 sigma_1, two sweeps per step: K time steps from t = 0
+(default K = 100, the whole run). The bond dimension grows from about 24 to 128 during the first
+twenty steps and stays at 128 afterwards. Contractions run on the FP32 matrix cores, the SVD
+truncation in FP64. `value` is the mean seconds per step over the K timed steps (HIP events on
+the launch stream, bracketed by device synchronisation); W untimed warm-up steps run first on a
+separate copy of the initial state.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64] [--no-cpu]
+Also reported: the same opening steps on the plain FP64 path (FP32/FP64 time ratio on identical
+steps), one step at saturated bond dimension on a seeded random MPS (D = 128 on every bulk bond),
+the environment-update microbenchmark at D = 256, d = 2, w = 8 (the matrix-core roofline target),
+per-kernel-class times of one profiled step, per-step parity of the first step against the
+oracle from the same initial state (infidelity and <Z_32> error), and the CPU oracle timed on one
+saturated-bond step (the cpu_baseline).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64] [--fp64-steps N]
+                       [--no-cpu] [--no-fp64]
 """
 from __future__ import annotations
 
@@ -29,6 +37,8 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64_MFMA = 78.6e12
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
+GROUND = os.path.join(ROOT, "tests", "golden", "tfim_g05_L64_ground.npz")
+L, D, G_AFTER, ORDER, TAU = 64, 128, 1.5, 2, 0.1
 
 
 def env_microbench(mp, h, torch, prec64: bool, reps: int = 50):
@@ -50,28 +60,30 @@ def env_microbench(mp, h, torch, prec64: bool, reps: int = 50):
     e.record()
     torch.cuda.synchronize()
     ms = s.elapsed_time(e) / reps
-    D, d, w = 256, 2, 8
-    flop = 8.0 * (2 * D ** 3 * d * w + D ** 2 * d ** 2 * w ** 2)
+    Dm, d, w = 256, 2, 8
+    flop = 8.0 * (2 * Dm ** 3 * d * w + Dm ** 2 * d ** 2 * w ** 2)
     return ms, flop
+
+
+def load_ground():
+    z = np.load(GROUND)
+    return [z[f"site_{i:03d}"] for i in range(L)]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--L", type=int, default=64)
-    ap.add_argument("--D", type=int, default=128)
-    ap.add_argument("--order", type=int, default=2)
-    ap.add_argument("--tau", type=float, default=0.1)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the time step of a single chain is sequential across "
-              "bonds and this build has no multi-GPU path (see the design notes for how it would shard).",
-              file=sys.stderr)
+              "bonds and this build has no multi-GPU path (the design notes describe how it would "
+              "shard).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -80,38 +92,46 @@ def main():
 
     torch.cuda.set_device(0)
     h = mp.Handle(0)
-    L, D = args.L, args.D
-    H = wl.tfim(1.5)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, args.order, -1j * args.tau, mp.V2_EXTENDED)
-    psi0 = wl.random_mps(np.random.default_rng(0), L, 2, D)
+    prec = mp.FP32 if args.prec == "fp32" else mp.FP64
+    psi0 = load_ground()
+    H = wl.tfim(G_AFTER)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -1j * TAU, mp.V2_EXTENDED)
     dw = mp.DeviceMPO([W] * L)
 
-    def run(prec, steps, warmup):
+    def quench(p, steps, warmup, stats_out=None):
+        """Per-step milliseconds of `steps` quench steps from psi0 (events on the default stream)."""
+        if warmup:
+            dm = mp.DeviceMPS(psi0, Dmax=D)
+            wsw = mp.step_workspace(dm, dw, p)
+            for k in range(warmup):
+                mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=wsw)
+            torch.cuda.synchronize()
+            del wsw
         dm = mp.DeviceMPS(psi0, Dmax=D)
-        ws = mp.step_workspace(dm, dw, prec)
-        stats = []
-        for k in range(warmup):
-            stats.append(mp.step(h, dm, dw, prec=prec, input_right_canonical=k > 0, workspace=ws))
+        ws = torch.empty_like(mp.step_workspace(dm, dw, p))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        st = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        timed = []
+        ev[0].record()
         for k in range(steps):
-            timed.append(mp.step(h, dm, dw, prec=prec, input_right_canonical=(warmup + k) > 0, workspace=ws))
-        e.record()
+            st.append(mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=ws))
+            ev[k + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return s.elapsed_time(e) / 1e3 / steps, wall / steps, timed
+        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+        if stats_out is not None:
+            stats_out.update(dm=dm, ws=ws)
+        return ms, wall, st
 
-    prec = mp.FP32 if args.prec == "fp32" else mp.FP64
-    sec_step, wall_step, st = run(prec, args.steps, args.warmup)
+    keep = {}
+    ms, wall, st = quench(prec, args.steps, args.warmup, keep)
+    sec_step = float(np.sum(ms)) / 1e3 / args.steps
     gflop = float(np.mean([x.gflop for x in st]))
 
-    # one extra (untimed) step with per-kernel-class HIP-event timing on the same stream
-    dmp = mp.DeviceMPS(psi0, Dmax=D)
-    mp.step(h, dmp, dw, prec=prec)
-    prof = mp.step(h, dmp, dw, prec=prec, input_right_canonical=True, profile=True).profile
+    # one more (untimed) step of the same trajectory with per-kernel-class HIP-event timing
+    prof = mp.step(h, keep["dm"], dw, prec=prec, input_right_canonical=True, workspace=keep["ws"],
+                   profile=True).profile
     classes = {
         "jacobi_svd": {"ms": prof["t_jacobi_ms"], "launches": prof["n_jacobi"], "work": prof["jacobi_gflop"],
                        "work_unit": "GFLOP", "bound": "alu", "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"},
@@ -126,37 +146,70 @@ def main():
         c["frac"] = c["achieved"] / c["peak"] if c["peak"] else 0.0
         c["avg_launch_us"] = 1e3 * c["ms"] / max(c["launches"], 1)
     dominant = max(classes, key=lambda k: classes[k]["ms"])
-    fp64_sec = None
+    del keep
+
+    # the plain FP64 path on the same opening steps
+    fp64 = None
     if not args.no_fp64 and prec == mp.FP32:
-        fp64_sec, _, _ = run(mp.FP64, max(1, args.steps // 2), args.warmup)
+        n64 = max(1, min(args.fp64_steps, args.steps))
+        ms64, _, _ = quench(mp.FP64, n64, 0)
+        fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
+                "fp32_s_per_step": float(np.sum(ms[:n64])) / 1e3 / n64}
+        fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / fp64["fp32_s_per_step"]
+
+    # one step at saturated bond dimension (seeded random MPS, D = 128 on every bulk bond)
+    rnd = wl.random_mps(np.random.default_rng(0), L, 2, D)
+    dmr = mp.DeviceMPS(rnd, Dmax=D)
+    wsr = mp.step_workspace(dmr, dw, prec)
+    mp.step(h, dmr, dw, prec=prec, workspace=wsr)
+    mp.step(h, dmr, dw, prec=prec, input_right_canonical=True, workspace=wsr)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    mp.step(h, dmr, dw, prec=prec, input_right_canonical=True, workspace=wsr)
+    e.record()
+    torch.cuda.synchronize()
+    sat_s = s.elapsed_time(e) / 1e3
+    del wsr, dmr
 
     mb32_ms, mb_flop = env_microbench(mp, h, torch, prec64=False)
     mb64_ms, _ = env_microbench(mp, h, torch, prec64=True)
 
-    # parity of one step from the same (canonical) input against the oracle, and the CPU baseline
+    # parity of the first step from psi0 against the oracle, and the CPU baseline
     cpu = None
-    infid = None
+    parity = None
     if not args.no_cpu:
         from oracle import fit as ofit
         import threadpoolctl
-        # both sides start from the same seeded state and bring it to right-canonical form
-        # themselves, so no oracle input passes through the GPU path
-        dm2 = mp.DeviceMPS(psi0, Dmax=D)
-        mp.step(h, dm2, dw, prec=prec)
-        gpu_out = dm2.to_numpy()
-        with threadpoolctl.threadpool_limits() as _:
-            info = threadpoolctl.threadpool_info()
+        ref, rinfo = ofit.fit_step(psi0, W, Dmax=D, nsweeps=2)
+        parity = {}
+        for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64)):
+            dm1 = mp.DeviceMPS(psi0, Dmax=D)
+            s1 = mp.step(h, dm1, dw, prec=p)
+            out = dm1.to_numpy()
+            parity[name] = {
+                "step1_infidelity": float(1.0 - abs(ofit.overlap(out, ref)) ** 2),
+                "step1_Z32_error": float(abs(ofit.expect_local(out, wl.SZ, 31) - ofit.expect_local(ref, wl.SZ, 31))),
+                "step1_norm_rel_error": float(abs(s1.norm - rinfo["norm"]) / rinfo["norm"]),
+            }
+        info = threadpoolctl.threadpool_info()
         threads = max([i.get("num_threads", 1) for i in info] + [1])
         t0 = time.perf_counter()
-        ref, _ = ofit.fit_step(psi0, W, Dmax=D, nsweeps=2)
+        ofit.fit_step(rnd, W, Dmax=D, nsweeps=2)
         cpu_s = time.perf_counter() - t0
-        infid = float(1.0 - abs(ofit.overlap(gpu_out, ref)) ** 2)
         cpu = {"value": cpu_s, "unit": "s per time step", "cores": int(threads), "kind": "oracle",
-               "sample": f"one time step (L={L}, D={D}, order {args.order}, 2 sweeps, including the "
-                         f"right-canonicalisation of the seeded input) of the same workload, "
-                         f"numpy complex128 with {threads} BLAS threads on {os.cpu_count()} host cores"}
+               "sample": f"one time step at saturated bond dimension (seeded random MPS, L={L}, D={D} on "
+                         f"every bulk bond, order {ORDER}, 2 sweeps, including its right-canonicalisation), "
+                         f"numpy complex128 with {threads} BLAS threads on {os.cpu_count()} host cores; "
+                         f"the GPU takes gpu_saturated_step_s for the same step",
+               "gpu_saturated_step_s": sat_s}
 
     mb_tflops = mb_flop / (mb32_ms * 1e-3) / 1e12
+    phases = {}
+    for lo, hi in ((0, 20), (20, 40), (40, args.steps)):
+        if hi > lo and lo < args.steps:
+            seg = ms[lo:min(hi, args.steps)]
+            phases[f"steps_{lo + 1}_{min(hi, args.steps)}_ms"] = float(np.mean(seg))
     line = {
         "metric": "s per time step & TFLOP/s at D=256: FP32-MFMA grouped vs plain FP64, fidelity",
         "value": sec_step,
@@ -170,21 +223,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 contractions, f64 SVD" if prec == mp.FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"TFIM quench chain L={L}, g=1.5, order-{args.order} extended MPO (w={W.shape[0]}), "
-                               f"tau={args.tau}, D={D}, 2 sweeps per step, seeded random saturated MPS",
-                   "L": L, "D": D, "order": args.order, "tau": args.tau},
-        "step_gflop": gflop,
-        "step_tflops": gflop / sec_step / 1e3,
-        "wall_s_per_step": wall_step,
-        "fp64_path_s_per_step": fp64_sec,
-        "fp32_speedup_vs_fp64": (fp64_sec / sec_step) if fp64_sec else None,
-        "step_infidelity_vs_oracle": infid,
-        "svd_sweeps_max": int(max(x.svd_sweeps_max for x in st)),
+        "config": {"workload": f"TFIM quench L={L} from the g=0.5 ground state to g={G_AFTER}, order-{ORDER} "
+                               f"extended MPO (w={W.shape[0]}), tau={TAU}, D<={D}, 2 sweeps per step, "
+                               f"steps 1..{args.steps} from t=0",
+                   "L": L, "D": D, "order": ORDER, "tau": TAU},
+        "wall_s_per_step": wall / args.steps,
+        "phase_ms_per_step": phases,
+        "max_bond_last_step": int(st[-1].max_bond),
+        "discarded_sum_last_step": float(st[-1].discarded_sum),
+        "step_gflop_mean": gflop,
         "svd_sweeps_mean": float(np.mean([x.svd_sweeps_total / max(x.visits, 1) for x in st])),
-        "svd_sweeps_hist_last_step": list(st[-1].svd_sweeps_hist),
+        "fp64_path": fp64,
+        "gpu_saturated_step_s": sat_s,
+        "parity_vs_oracle": parity,
         "env_microbench": {"D": 256, "d": 2, "w": 8, "fp32_ms": mb32_ms, "fp64_ms": mb64_ms,
                            "fp32_tflops": mb_tflops, "fp64_tflops": mb_flop / (mb64_ms * 1e-3) / 1e12,
-                           "fp32_frac_of_mfma_peak": mb_tflops * 1e12 / PEAK_FP32_MFMA},
+                           "fp32_frac_of_mfma_peak": mb_tflops * 1e12 / PEAK_FP32_MFMA,
+                           "fp64_frac_of_mfma_peak": mb_flop / (mb64_ms * 1e-3) / PEAK_FP64_MFMA},
         "roofline": {"bound": classes[dominant]["bound"], "kernel": dominant,
                      "achieved": classes[dominant]["achieved"], "peak": classes[dominant]["peak"],
                      "unit": classes[dominant]["unit"], "frac": classes[dominant]["frac"],
