@@ -13,7 +13,7 @@ separate copy of the initial state.
 Also reported: the same opening steps on the plain FP64 path (FP32/FP64 time ratio on identical
 steps), one step at saturated bond dimension on a seeded random MPS (D = 128 on every bulk bond),
 the environment-update microbenchmark at D = 256, d = 2, w = 8 (the matrix-core roofline target),
-per-kernel-class times of one profiled step, per-step parity of the first step against the
+per-kernel-class times summed over the timed steps, per-step parity of the first step against the
 oracle from the same initial state (infidelity and <Z_32> error), and the CPU oracle timed on one
 saturated-bond step (the cpu_baseline).
 
@@ -98,8 +98,9 @@ def main():
     W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -1j * TAU, mp.V2_EXTENDED)
     dw = mp.DeviceMPO([W] * L)
 
-    def quench(p, steps, warmup, stats_out=None):
-        """Per-step milliseconds of `steps` quench steps from psi0 (events on the default stream)."""
+    def quench(p, steps, warmup, profile=False):
+        """Per-step milliseconds of `steps` quench steps from psi0 (events on the default stream);
+        with `profile` every step also times its kernel classes with HIP events."""
         if warmup:
             dm = mp.DeviceMPS(psi0, Dmax=D)
             wsw = mp.step_workspace(dm, dw, p)
@@ -115,23 +116,20 @@ def main():
         t0 = time.perf_counter()
         ev[0].record()
         for k in range(steps):
-            st.append(mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=ws))
+            st.append(mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=ws,
+                              profile=profile))
             ev[k + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
-        if stats_out is not None:
-            stats_out.update(dm=dm, ws=ws)
         return ms, wall, st
 
-    keep = {}
-    ms, wall, st = quench(prec, args.steps, args.warmup, keep)
+    ms, wall, st = quench(prec, args.steps, args.warmup, profile=True)
     sec_step = float(np.sum(ms)) / 1e3 / args.steps
     gflop = float(np.mean([x.gflop for x in st]))
 
-    # one more (untimed) step of the same trajectory with per-kernel-class HIP-event timing
-    prof = mp.step(h, keep["dm"], dw, prec=prec, input_right_canonical=True, workspace=keep["ws"],
-                   profile=True).profile
+    # kernel classes summed over the timed steps (HIP events on the launch stream)
+    prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile}
     classes = {
         "jacobi_svd": {"ms": prof["t_jacobi_ms"], "launches": prof["n_jacobi"], "work": prof["jacobi_gflop"],
                        "work_unit": "GFLOP", "bound": "alu", "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"},
@@ -146,13 +144,12 @@ def main():
         c["frac"] = c["achieved"] / c["peak"] if c["peak"] else 0.0
         c["avg_launch_us"] = 1e3 * c["ms"] / max(c["launches"], 1)
     dominant = max(classes, key=lambda k: classes[k]["ms"])
-    del keep
 
     # the plain FP64 path on the same opening steps
     fp64 = None
     if not args.no_fp64 and prec == mp.FP32:
         n64 = max(1, min(args.fp64_steps, args.steps))
-        ms64, _, _ = quench(mp.FP64, n64, 0)
+        ms64, _, _ = quench(mp.FP64, n64, 0, profile=True)
         fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
                 "fp32_s_per_step": float(np.sum(ms[:n64])) / 1e3 / n64}
         fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / fp64["fp32_s_per_step"]
@@ -244,7 +241,7 @@ def main():
                      "achieved": classes[dominant]["achieved"], "peak": classes[dominant]["peak"],
                      "unit": classes[dominant]["unit"], "frac": classes[dominant]["frac"],
                      "avg_launch_us": classes[dominant]["avg_launch_us"], "traffic": None},
-        "kernel_classes_one_step": classes,
+        "kernel_classes_timed_steps": classes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

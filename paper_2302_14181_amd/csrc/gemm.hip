@@ -14,8 +14,10 @@
 // fp64: v_mfma_f64_16x16x4f64 (lane l supplies A'[l%16][l/16], B'[l/16][l%16]; accumulator r of
 //       lane l holds C'[4r + l/16][l%16]).
 // A workgroup of 4 waves (2 x 2, each wave WR x WC matrix-instruction tiles) owns a BM x BN
-// complex tile, double-buffered in LDS with one barrier per K step; global loads of the next K
-// step are issued before the current step's matrix instructions.
+// complex tile, double-buffered in LDS with one barrier per K step of BK complex (8 for the large
+// tiles, 16 for the small ones, whose single workgroup per compute unit needs the longer step to
+// cover the latency of the next step's global loads, issued before the current step's matrix
+// instructions).
 //
 // Occupancy: the products of a sweep are small (M x N of a few hundred), so a planner picks the
 // largest tile that still gives every compute unit a workgroup, and when even the smallest tile
@@ -60,35 +62,36 @@ struct MfmaF64 {
 };
 
 constexpr int kThreads = 256;
-constexpr int kBK = 8;          // complex K per stage
+constexpr int kKGrain = 8;      // split-K chunks are multiples of this
 constexpr int kMinWgs = 256;    // a tile giving at least this many workgroups is used as is
 constexpr int kTargetWgs = 512; // split K up to this many workgroups
 constexpr int kMaxSplits = 16;
 constexpr int kMinSplitK = 32;  // complex K per split, at least
 
-template <class Mf, int WR, int WC>
+template <class Mf, int WR, int WC, int BK_>
 struct Tile {
+  static constexpr int BK = BK_;                      // complex K per stage
   using T = typename Mf::T;
   static constexpr int BM = 2 * WR * Mf::MT;          // complex rows per workgroup
   static constexpr int BNR = 2 * WC * Mf::NT;         // real columns per workgroup
   static constexpr int BN = BNR / 2;                  // complex columns
-  static constexpr int KR = 2 * kBK;                  // real k per stage
+  static constexpr int KR = 2 * BK;                   // real k per stage
   static constexpr int LDA = BM + 4;                  // padded LDS row lengths (elements)
   static constexpr int LDB = BNR + 4;
-  static constexpr int A_ELEMS = BM * kBK / kThreads;  // complex loads per thread
-  static constexpr int B_ELEMS = BN * kBK / kThreads;
+  static constexpr int A_ELEMS = BM * BK / kThreads;   // complex loads per thread
+  static constexpr int B_ELEMS = BN * BK / kThreads;
   static constexpr int LDS_ELEMS = KR * LDA + KR * LDB;
   static_assert(A_ELEMS >= 1 && B_ELEMS >= 1, "tile too small for the staging scheme");
 };
 
 // splits > 1: the workgroup at blockIdx.z = batch * splits + s covers K in [s kchunk, (s+1)
 // kchunk) and writes its partial tile (precision T) to part[s][batch][M][N].
-template <class Mf, int WR, int WC, typename TO, bool AKC, bool BNC>
+template <class Mf, int WR, int WC, int BK, typename TO, bool AKC, bool BNC>
 __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits, int kchunk,
                                                          void* part) {
   using T = typename Mf::T;
   using C2 = cx_t<T>;
-  using TT = Tile<Mf, WR, WC>;
+  using TT = Tile<Mf, WR, WC, BK>;
   __shared__ T lds[2 * TT::LDS_ELEMS];
 
   const int tid = threadIdx.x;
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
     for (int i = 0; i < TT::A_ELEMS; ++i) {
       const int e = tid + i * kThreads;
       int m, k;
-      if (AKC) { m = e / kBK; k = e % kBK; } else { k = e / TT::BM; m = e % TT::BM; }
+      if (AKC) { m = e / BK; k = e % BK; } else { k = e / TT::BM; m = e % TT::BM; }
       const int gm = m0 + m, gk = k0 + k;
       C2 v{T(0), T(0)};
       if (gm < g.M && gk < kend) v = A[gm * g.sAm + gk * g.sAk];
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
     for (int i = 0; i < TT::B_ELEMS; ++i) {
       const int e = tid + i * kThreads;
       int k, n;
-      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / kBK; k = e % kBK; }
+      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / BK; k = e % BK; }
       const int gk = k0 + k, gn = n0 + n;
       C2 v{T(0), T(0)};
       if (gk < kend && gn < g.N) v = B[gk * g.sBk + gn * g.sBn];
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
     for (int i = 0; i < TT::A_ELEMS; ++i) {
       const int e = tid + i * kThreads;
       int m, k;
-      if (AKC) { m = e / kBK; k = e % kBK; } else { k = e / TT::BM; m = e % TT::BM; }
+      if (AKC) { m = e / BK; k = e % BK; } else { k = e / TT::BM; m = e % TT::BM; }
       As[(2 * k) * TT::LDA + m] = ra[i].x;
       As[(2 * k + 1) * TT::LDA + m] = sgnA * ra[i].y;
     }
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
     for (int i = 0; i < TT::B_ELEMS; ++i) {
       const int e = tid + i * kThreads;
       int k, n;
-      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / kBK; k = e % kBK; }
+      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / BK; k = e % BK; }
       const T re = rb[i].x, im = sgnB * rb[i].y;
       T* r0 = Bs + (2 * k) * TT::LDB + 2 * n;
       T* r1 = r0 + TT::LDB;
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
 #pragma unroll
       for (int r = 0; r < Mf::NACC; ++r) acc[i][j][r] = T(0);
 
-  const int nk = (kend - kbeg + kBK - 1) / kBK;
+  const int nk = (kend - kbeg + BK - 1) / BK;
   load_tiles(kbeg);
   store_tiles(0);
   __syncthreads();
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
   const int arow = Mf::a_row(lane), ak = Mf::a_k(lane);
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * kBK);
+    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
     const T* As = lds + cur * TT::LDS_ELEMS;
     const T* Bs = As + TT::KR * TT::LDA;
 #pragma unroll
@@ -273,7 +276,7 @@ Plan make_plan(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
   const size_t per = sizeof(typename Mf::T) * 2 * (size_t)g.M * g.N * g.batch;
   s = (int)std::min<size_t>((size_t)s, per ? g.ws_bytes / per : 0);
   if (s < 2) return p;
-  const int kc = ((g.K + s - 1) / s + kBK - 1) / kBK * kBK;
+  const int kc = ((g.K + s - 1) / s + kKGrain - 1) / kKGrain * kKGrain;
   p.kchunk = kc;
   p.splits = (g.K + kc - 1) / kc;
   return p;
@@ -282,21 +285,21 @@ Plan make_plan(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
 constexpr int kF32Cfg[3][2] = {{128, 64}, {64, 64}, {64, 32}};
 constexpr int kF64Cfg[2][2] = {{64, 64}, {32, 32}};
 
-template <class Mf, int WR, int WC, typename TO>
+template <class Mf, int WR, int WC, int BK, typename TO>
 hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
-  using TT = Tile<Mf, WR, WC>;
+  using TT = Tile<Mf, WR, WC, BK>;
   dim3 grid((g.N + TT::BN - 1) / TT::BN, (g.M + TT::BM - 1) / TT::BM, g.batch * pl.splits);
   const bool akc = (g.sAk == 1) || (g.K == 1);
   const bool bnc = (g.sBn == 1) || (g.N == 1);
   void* part = pl.splits > 1 ? g.ws : nullptr;
   if (akc && bnc)
-    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, true, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, BK, TO, true, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
   else if (akc)
-    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, true, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, BK, TO, true, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
   else if (bnc)
-    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, BK, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
   else
-    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, BK, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
   MPOEVO_HIP_TRY(hipGetLastError());
   if (pl.splits > 1) {
     using T = typename Mf::T;
@@ -313,16 +316,16 @@ template <typename TO>
 hipError_t launch_f32(const GemmDesc& g, hipStream_t st) {
   const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);
   switch (pl.cfg) {
-    case 0: return launch_cfg<MfmaF32, 2, 2, TO>(g, pl, st);
-    case 1: return launch_cfg<MfmaF32, 1, 2, TO>(g, pl, st);
-    default: return launch_cfg<MfmaF32, 1, 1, TO>(g, pl, st);
+    case 0: return launch_cfg<MfmaF32, 2, 2, 8, TO>(g, pl, st);
+    case 1: return launch_cfg<MfmaF32, 1, 2, 16, TO>(g, pl, st);
+    default: return launch_cfg<MfmaF32, 1, 1, 16, TO>(g, pl, st);
   }
 }
 
 hipError_t launch_f64(const GemmDesc& g, hipStream_t st) {
   const Plan pl = make_plan<MfmaF64>(g, kF64Cfg, 2);
-  if (pl.cfg == 0) return launch_cfg<MfmaF64, 2, 4, double>(g, pl, st);
-  return launch_cfg<MfmaF64, 1, 2, double>(g, pl, st);
+  if (pl.cfg == 0) return launch_cfg<MfmaF64, 2, 4, 8, double>(g, pl, st);
+  return launch_cfg<MfmaF64, 1, 2, 16, double>(g, pl, st);
 }
 
 }  // namespace
