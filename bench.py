@@ -122,9 +122,9 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
-        return ms, wall, st
+        return ms, wall, st, dm
 
-    ms, wall, st = quench(prec, args.steps, args.warmup, profile=True)
+    ms, wall, st, dm_end = quench(prec, args.steps, args.warmup, profile=True)
     sec_step = float(np.sum(ms)) / 1e3 / args.steps
     gflop = float(np.mean([x.gflop for x in st]))
 
@@ -145,11 +145,30 @@ def main():
         c["avg_launch_us"] = 1e3 * c["ms"] / max(c["launches"], 1)
     dominant = max(classes, key=lambda k: classes[k]["ms"])
 
+    # diagnostics of the trajectory on the device (FP64): energy of H(g = 1.5), conserved by the
+    # exact evolution, and <Z_32>, at t = 0 and after the last timed step
+    Hm = np.zeros((3, 2, 2, 3), dtype=np.complex128)
+    Hm[0, :, :, 0] = Hm[2, :, :, 2] = np.eye(2)
+    Hm[0, :, :, 1], Hm[1, :, :, 2], Hm[0, :, :, 2] = H.C[0], H.B[0], H.Dloc
+    dH = mp.DeviceMPO([Hm] * L)
+    Id = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
+    zops = [Id] * L
+    zops[31] = wl.SZ.reshape(1, 2, 2, 1)
+    dZ = mp.DeviceMPO(zops)
+    dm0 = mp.DeviceMPS(psi0, Dmax=D)
+    diag = {"energy_t0": mp.expectation(h, dm0, dH, 0, 2).real,
+            "energy_end": mp.expectation(h, dm_end, dH, 0, 2).real,
+            "Z32_t0": mp.expectation(h, dm0, dZ).real,
+            "Z32_end": mp.expectation(h, dm_end, dZ).real,
+            "t_end": TAU * args.steps}
+    diag["energy_drift_per_site"] = (diag["energy_end"] - diag["energy_t0"]) / L
+    del dm0, dm_end
+
     # the plain FP64 path on the same opening steps
     fp64 = None
     if not args.no_fp64 and prec == mp.FP32:
         n64 = max(1, min(args.fp64_steps, args.steps))
-        ms64, _, _ = quench(mp.FP64, n64, 0, profile=True)
+        ms64, _, _, _ = quench(mp.FP64, n64, 0, profile=True)
         fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
                 "fp32_s_per_step": float(np.sum(ms[:n64])) / 1e3 / n64}
         fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / fp64["fp32_s_per_step"]
@@ -231,6 +250,7 @@ def main():
         "step_gflop_mean": gflop,
         "svd_sweeps_mean": float(np.mean([x.svd_sweeps_total / max(x.visits, 1) for x in st])),
         "fp64_path": fp64,
+        "diagnostics_device": diag,
         "gpu_saturated_step_s": sat_s,
         "parity_vs_oracle": parity,
         "env_microbench": {"D": 256, "d": 2, "w": 8, "fp32_ms": mb32_ms, "fp64_ms": mb64_ms,

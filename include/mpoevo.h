@@ -190,10 +190,10 @@ typedef struct {
   int input_right_canonical;
   int profile;  /* nonzero: time the kernel classes with HIP events (adds host overhead) */
   int svd_cold_start; /* nonzero: every truncation starts Jacobi from Theta itself. Zero (the
-                         default): a square bond matrix is first multiplied by the unitary the
-                         previous truncation of the same bond left in the workspace (its
-                         singular basis on the shared side), which leaves the same singular
-                         values and kept vectors and converges in a few sweeps. The unitaries
+                         default): the bond matrix is first multiplied by the unitary the
+                         previous truncation of the same bond left in the workspace (a singular
+                         basis of that matrix), which leaves the same singular values and kept
+                         vectors and converges in a few sweeps. The unitaries
                          persist in the workspace between step calls on one handle with the
                          same workspace and chain shape; the caller must not modify that
                          workspace between such calls. */
@@ -222,11 +222,28 @@ typedef struct {
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
          mpoevo_step_stats* stats, void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * expectation -- <psi| O |psi> for an MPO O = l . O_1 ... O_L . r with boundary vectors l = e_left
+ * on MPO bond 0 and r = e_right on MPO bond L: the diagnostics of a time step (Sec. 8.2) -- the
+ * energy through the Hamiltonian MPO of Sec. 2.3 (left = 0, right = w - 1), a local observable
+ * as a bond-1 MPO with the operator on one site, the norm with identities. FP64 throughout, by
+ * the left environment recursion of env_update (E <- E . psi_i . O_i . conj(psi_i)).
+ *   mps    as for step; not modified (bond_dim host, site[i] device complex128).
+ *   mpo    per-site complex128 O_i[w[i]][d][d][w[i+1]] (device); w[i] * d <= 64.
+ *   left, right  boundary levels, 0 <= left < w[0], 0 <= right < w[L].
+ *   out    device complex128 (two doubles), written on `stream`; no synchronisation.
+ * Workspace: mpoevo_workspace_size(MPOEVO_CALL_EXPECTATION, dims = {L, d, Dmax, wmax}, FP64).
+ * Errors: EINVAL (NULL arguments, levels out of range), ESHAPE, ENOMEM, EUNSUPPORTED (MPO bond
+ * too large), EHIP.
+ */
+int expectation(mpoevo_handle h, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
+                void* out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Workspace sizes in bytes for the device calls (dims as documented for each call). */
 enum { MPOEVO_CALL_ENV_UPDATE = 0, MPOEVO_CALL_LOCAL_APPLY = 1, MPOEVO_CALL_TRUNCATE = 2,
-       MPOEVO_CALL_STEP = 3 };
+       MPOEVO_CALL_STEP = 3, MPOEVO_CALL_EXPECTATION = 4 };
 /* dims: ENV_UPDATE -> the 7 env_update dims; LOCAL_APPLY -> the 9 local_apply dims;
- * TRUNCATE -> {m, n}; STEP -> {L, d, Dmax, wmax}. */
+ * TRUNCATE -> {m, n}; STEP and EXPECTATION -> {L, d, Dmax, wmax}. */
 int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes);
 
 #ifdef __cplusplus

@@ -87,6 +87,12 @@ int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes)
         return fail(nullptr, MPOEVO_ESHAPE, "step: d * Dmax exceeds MPOEVO_SVD_MAX_DIM");
       *bytes = mpoevo::step_ws(dims[0], dims[1], dims[2], dims[3], prec);
       return MPOEVO_OK;
+    case MPOEVO_CALL_EXPECTATION:
+      if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || dims[3] < 1)
+        return fail(nullptr, MPOEVO_ESHAPE, "expectation: need L, d, Dmax, wmax >= 1");
+      if (prec != MPOEVO_FP64) return fail(nullptr, MPOEVO_EINVAL, "expectation: FP64 only");
+      *bytes = mpoevo::expectation_ws(dims[0], dims[1], dims[2], dims[3]);
+      return MPOEVO_OK;
     default:
       return fail(nullptr, MPOEVO_EINVAL, "mpoevo_workspace_size: unknown call id");
   }
@@ -174,6 +180,33 @@ int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_s
   if (workspace_bytes < mpoevo::step_ws(L, d, Dmax, wmax, opts->prec) || !workspace)
     return fail(ctx, MPOEVO_ENOMEM, "step: workspace too small");
   return mpoevo::step_dev(*ctx, mps, mpo, opts, stats, workspace, workspace_bytes, stream);
+}
+
+int expectation(mpoevo_handle h, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
+                void* out, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "expectation: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (!mps || !mpo || !out || !mps->bond_dim || !mps->site || !mpo->w || !mpo->site)
+    return fail(ctx, MPOEVO_EINVAL, "expectation: NULL argument");
+  const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
+  if (L < 1 || d < 1 || Dmax < 1 || mpo->L != L || mpo->d != d)
+    return fail(ctx, MPOEVO_ESHAPE, "expectation: need L >= 1 and matching L, d of MPS and MPO");
+  if (mps->bond_dim[0] != 1 || mps->bond_dim[L] != 1)
+    return fail(ctx, MPOEVO_ESHAPE, "expectation: boundary bonds must be 1");
+  int wmax = 0;
+  for (int i = 0; i <= L; ++i) {
+    if (i > 0 && i < L && (mps->bond_dim[i] < 1 || mps->bond_dim[i] > Dmax))
+      return fail(ctx, MPOEVO_ESHAPE, "expectation: MPS bond dimension outside 1..Dmax");
+    if (mpo->w[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "expectation: MPO bond dimension < 1");
+    if (mpo->w[i] > wmax) wmax = mpo->w[i];
+  }
+  if (left < 0 || left >= mpo->w[0] || right < 0 || right >= mpo->w[L])
+    return fail(ctx, MPOEVO_EINVAL, "expectation: boundary level out of range");
+  for (int i = 0; i < L; ++i)
+    if (!mps->site[i] || !mpo->site[i]) return fail(ctx, MPOEVO_EINVAL, "expectation: NULL site pointer");
+  if (!workspace || workspace_bytes < mpoevo::expectation_ws(L, d, Dmax, wmax))
+    return fail(ctx, MPOEVO_ENOMEM, "expectation: workspace too small");
+  return mpoevo::expectation_dev(*ctx, mps, mpo, left, right, out, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -98,6 +98,16 @@ __global__ void boundary_env(C2* E, int w) {
   if (i < w) E[i] = C2{i == 0 ? 1 : 0, 0};
 }
 
+// E (1 x w x 1) = e_level.
+__global__ void boundary_level(double2* E, int w, int level) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i < w) E[i] = double2{i == level ? 1.0 : 0.0, 0.0};
+}
+
+__global__ void copy_entry(const double2* __restrict__ src, double2* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
 // out (n x n) = identity.
 __global__ void fill_identity(double2* out, int n) {
   const long long total = (long long)n * n;
@@ -450,6 +460,54 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
                               discarded_dev, norm_dev, sigma_dev, ws, ctx.dev->status,
                               static_cast<hipStream_t>(stream));
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "truncate");
+}
+
+// --------------------------------------------------------------------------- expectation
+size_t expectation_ws(int L, int d, int Dmax, int wmax) {
+  (void)L;
+  const size_t env = a256(sizeof(double2) * (size_t)Dmax * wmax * Dmax);
+  const size_t blk = a256(sizeof(double2) * (size_t)Dmax * wmax * d * Dmax);
+  return 2 * env + 2 * blk + kGemmScratchBytes;
+}
+
+// E <- E . psi_i . O_i . conj(psi_i), i = 0 .. L-1, from E = e_left; out = E[right].
+int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
+                    void* out, void* ws, size_t, void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
+  int wmax = 0;
+  for (int i = 0; i <= L; ++i) wmax = std::max(wmax, mpo->w[i]);
+  for (int i = 0; i < L; ++i)
+    if (!wmix_supported(mpo->w[i], d, mpo->w[i + 1])) {
+      ctx.err = "expectation: MPO bond too large for this build";
+      return MPOEVO_EUNSUPPORTED;
+    }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  const size_t env = a256(sizeof(double2) * (size_t)Dmax * wmax * Dmax);
+  const size_t blk = a256(sizeof(double2) * (size_t)Dmax * wmax * d * Dmax);
+  double2* E[2] = {reinterpret_cast<double2*>(base), reinterpret_cast<double2*>(base + env)};
+  void* tmp = base + 2 * env;
+  void* LB = base + 2 * env + blk;
+  void* gws = base + 2 * env + 2 * blk;
+  const int* D = mps->bond_dim;
+  const int* w = mpo->w;
+  hipLaunchKernelGGL(boundary_level, dim3((w[0] + 255) / 256), dim3(256), 0, st, E[0], w[0], left);
+  hipError_t e = hipGetLastError();
+  int cur = 0;
+  for (int i = 0; i < L && e == hipSuccess; ++i) {
+    e = left_block(true, E[cur], mps->site[i], mpo->site[i], tmp, LB, D[i], w[i], D[i], d, D[i + 1],
+                   w[i + 1], st, nullptr, gws);
+    if (e == hipSuccess)
+      e = left_env_from_block(true, mps->site[i], LB, E[cur ^ 1], D[i], d, D[i + 1], w[i + 1],
+                              D[i + 1], st, nullptr, gws);
+    cur ^= 1;
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(copy_entry, dim3(1), dim3(64), 0, st, E[cur] + right, static_cast<double2*>(out));
+    e = hipGetLastError();
+  }
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "expectation");
 }
 
 // ---------------------------------------------------------------------------------- the step

@@ -37,6 +37,7 @@ size_t env_update_ws(const int* dims, int prec);
 size_t local_apply_ws(const int* dims, int prec);
 size_t truncate_ws(int m, int n);
 size_t step_ws(int L, int d, int Dmax, int wmax, int prec);
+size_t expectation_ws(int L, int d, int Dmax, int wmax);
 
 int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
                    const void* W, const void* ket, void* E_out, const int* dims, void* ws,
@@ -50,5 +51,7 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
 int check_solver_dev(Context& ctx);
 int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
              mpoevo_step_stats* stats, void* ws, size_t ws_bytes, void* stream);
+int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
+                    void* out, void* ws, size_t ws_bytes, void* stream);
 
 }  // namespace mpoevo

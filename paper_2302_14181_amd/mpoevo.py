@@ -20,7 +20,7 @@ OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESOLVER, ENONFINITE, EUNSUPPORTED = 0, -1, -2,
 FP64, FP32 = 0, 1
 V1_EXACT, V2_EXTENDED = 0, 1
 LEFT, RIGHT = 0, 1
-CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP = 0, 1, 2, 3
+CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP, CALL_EXPECTATION = 0, 1, 2, 3, 4
 SVD_MAX_DIM = 1024
 
 
@@ -83,8 +83,10 @@ def load(path: str = LIB_PATH):
                              vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.step.argtypes = [vp, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO), ctypes.POINTER(_Opts),
                          ctypes.POINTER(_Stats), vp, sz, vp]
+    lib.expectation.argtypes = [vp, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO), ctypes.c_int, ctypes.c_int,
+                                vp, vp, sz, vp]
     for name in ("mpoevo_create", "mpoevo_destroy", "mpoevo_check_solver", "mpo_build",
-                 "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step"):
+                 "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step", "expectation"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -93,7 +95,7 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     return ["mpoevo_create", "mpoevo_destroy", "mpoevo_last_error", "mpoevo_version", "mpo_build",
             "env_update", "local_apply", "truncate", "mpoevo_check_solver", "step",
-            "mpoevo_workspace_size"]
+            "expectation", "mpoevo_workspace_size"]
 
 
 def _check(rc: int, handle=None):
@@ -326,3 +328,23 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
                                             "gemm_gflop", "n_gemm", "t_wmix_ms", "wmix_gbyte", "n_wmix")}
     return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
                      st.svd_sweeps_max, prof, st.svd_sweeps_total, tuple(st.svd_sweeps_hist))
+
+
+def expectation(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, left: int = 0, right: int = 0,
+                workspace=None, stream=None) -> complex:
+    """<psi| l.O_1...O_L.r |psi> on the device in FP64 (see include/mpoevo.h); waits for the result."""
+    torch = _torch()
+    dev = mps.buf[0].device
+    if workspace is None:
+        workspace = _workspace(workspace_size(CALL_EXPECTATION, [mps.L, mps.d, mps.Dmax, max(mpo.w)], FP64), dev)
+    bond = _iarr(mps.bond)
+    sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
+    wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
+    cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
+    cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    _check(load().expectation(h.ptr, ctypes.byref(cm), ctypes.byref(cw), left, right, _ptr(out),
+                              _ptr(workspace), workspace.numel(), _stream(stream)), h)
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+    v = out.cpu().numpy()
+    return complex(v[0], v[1])

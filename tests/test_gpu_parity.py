@@ -311,3 +311,62 @@ def test_step_warm_started_truncations_match_cold_and_oracle(mp, handle):
     print("total sweeps per step: warm", tot_w, "cold", tot_c, flush=True)
     assert all(t > 0 for t in tot_w + tot_c)
     assert sum(tot_w[1:]) < sum(tot_c[1:])
+
+
+def _hamiltonian_mpo_from_blocks(H):
+    """[[I, C, Dloc], [0, A, B], [0, 0, I]] assembled here from the Jordan blocks (Sec. 2.3)."""
+    d, chi = H.Dloc.shape[0], H.B.shape[0]
+    w = chi + 2
+    W = np.zeros((w, d, d, w), dtype=np.complex128)
+    W[0, :, :, 0] = np.eye(d)
+    W[w - 1, :, :, w - 1] = np.eye(d)
+    W[0, :, :, w - 1] = H.Dloc
+    for k in range(chi):
+        W[0, :, :, 1 + k] = H.C[k]
+        W[1 + k, :, :, w - 1] = H.B[k]
+        for l in range(chi):
+            W[1 + k, :, :, 1 + l] = H.A[k, l]
+    return W
+
+
+@pytest.mark.parametrize("L,D", [(8, 8), (11, 20)], ids=str)
+def test_expectation_energy_local_norm(mp, handle, L, D):
+    """<psi|O|psi> on the device (FP64) against the oracle: the TFIM energy through the Hamiltonian
+    MPO, <Z_3> through a bond-1 MPO, the norm, and <psi|W|psi> of the evolution MPO."""
+    _say("expectation", L, D)
+    rng = np.random.default_rng(L + D)
+    psi = wl.random_mps(rng, L, 2, D)
+    dm = mp.DeviceMPS(psi, Dmax=D)
+    H = wl.tfim(1.3)
+    Wh = _hamiltonian_mpo_from_blocks(H)
+    w = Wh.shape[0]
+    e0, e1 = np.zeros(w, complex), np.zeros(w, complex)
+    e0[0], e1[w - 1] = 1.0, 1.0
+    ref = ofit.mpo_expectation(psi, [Wh] * L, e0, e1)
+    got = mp.expectation(handle, dm, mp.DeviceMPO([Wh] * L), left=0, right=w - 1)
+    assert abs(got - ref) < 1e-12 * max(1.0, abs(ref)), (got, ref)
+    nrm = ofit.overlap(psi, psi)
+    Id = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
+    Z3 = [Id] * L
+    Z3[3] = wl.SZ.reshape(1, 2, 2, 1)
+    got = mp.expectation(handle, dm, mp.DeviceMPO(Z3))
+    ref = ofit.expect_local(psi, wl.SZ, 3) * nrm
+    assert abs(got - ref) < 1e-12 * abs(nrm)
+    got = mp.expectation(handle, dm, mp.DeviceMPO([Id] * L))
+    assert abs(got - nrm) < 1e-12 * abs(nrm)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    l0 = np.zeros(W.shape[0], complex)
+    l0[0] = 1.0
+    ref = ofit.mpo_expectation(psi, [W] * L, l0, l0)
+    got = mp.expectation(handle, dm, mp.DeviceMPO([W] * L))
+    assert abs(got - ref) < 1e-12 * abs(nrm)
+
+
+def test_expectation_rejects_bad_levels(mp, handle):
+    _say("expectation argument errors")
+    psi = wl.all_up(4)
+    dm = mp.DeviceMPS(psi, Dmax=2)
+    Wh = _hamiltonian_mpo_from_blocks(wl.tfim(1.0))
+    with pytest.raises(mp.MpoevoError) as e:
+        mp.expectation(handle, dm, mp.DeviceMPO([Wh] * 4), left=0, right=Wh.shape[0])
+    assert e.value.code == mp.EINVAL
