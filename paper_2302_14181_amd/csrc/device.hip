@@ -98,6 +98,38 @@ __global__ void boundary_env(C2* E, int w) {
   if (i < w) E[i] = C2{i == 0 ? 1 : 0, 0};
 }
 
+// Wt[(s' wr + beta)][(alpha d + s)] = W[alpha][s'][s][beta]: W as the left factor of the
+// short-leg contraction done as a product (large MPO bonds).
+template <typename C2>
+__global__ void permute_w_left(const C2* __restrict__ W, C2* __restrict__ Wt, int wl, int d, int wr) {
+  const long long n = (long long)wl * d * d * wr;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int beta = (int)(i % wr);
+    long long r = i / wr;
+    const int s = (int)(r % d);
+    r /= d;
+    const int sp = (int)(r % d);
+    const int alpha = (int)(r / d);
+    Wt[((long long)sp * wr + beta) * (wl * d) + alpha * d + s] = W[i];
+  }
+}
+
+// Up[b][t][gamma][c'] = U[b][t][c'][gamma] (Qt = Qa d leading pairs (b, t)).
+template <typename C2>
+__global__ void permute_u_right(const C2* __restrict__ U, C2* __restrict__ Up, long long Qt, int Pr,
+                                int wr) {
+  const long long n = Qt * Pr * wr;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(i % Pr);
+    long long r = i / Pr;
+    const int gamma = (int)(r % wr);
+    const long long bt = r / wr;
+    Up[i] = U[(bt * Pr + c) * wr + gamma];
+  }
+}
+
 // E (1 x w x 1) = e_level.
 __global__ void boundary_level(double2* E, int w, int level) {
   const int i = threadIdx.x + blockIdx.x * blockDim.x;
@@ -164,7 +196,7 @@ hipError_t gemm_timed(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t s
 
 hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, void* tmp,
                       void* LB, int P, int wl, int Qa, int d, int Qb, int wr, hipStream_t st,
-                      Prof* pr = nullptr, void* gws = nullptr) {
+                      Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr) {
   GemmDesc g{};
   g.ws = gws;
   g.ws_bytes = gws ? kGemmScratchBytes : 0;
@@ -172,18 +204,37 @@ hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, 
   g.M = P * wl; g.N = d * Qb; g.K = Qa; g.batch = 1;
   g.sAm = Qa; g.sAk = 1; g.sBk = (long long)d * Qb; g.sBn = 1; g.sCm = (long long)d * Qb; g.sCn = 1;
   MPOEVO_HIP_TRY(gemm_timed(g, fp64, false, st, pr));
-  PROF_BEGIN(pr, tok);
-  MPOEVO_HIP_TRY(wmix_left(fp64, tmp, W, LB, P, Qb, wl, d, wr, st));
-  const double cs = fp64 ? 16.0 : 8.0;
-  PROF_END(pr, tok, Prof::kWmix, cs * ((double)P * wl * d * Qb + (double)P * d * wr * Qb + wl * d * d * wr));
-  return hipSuccess;
+  if (wmix_supported(wl, d, wr)) {
+    PROF_BEGIN(pr, tok);
+    MPOEVO_HIP_TRY(wmix_left(fp64, tmp, W, LB, P, Qb, wl, d, wr, st));
+    const double cs = fp64 ? 16.0 : 8.0;
+    PROF_END(pr, tok, Prof::kWmix, cs * ((double)P * wl * d * Qb + (double)P * d * wr * Qb + wl * d * d * wr));
+    return hipSuccess;
+  }
+  // large MPO bond: LB_a'[(s', beta)][b] = sum Wt[(s', beta)][(alpha, s)] T_a'[(alpha, s)][b]
+  if (!xws) return hipErrorInvalidValue;
+  const long long nW = (long long)wl * d * d * wr;
+  if (fp64) hipLaunchKernelGGL(permute_w_left<double2>, dim3(grid_for(nW)), dim3(256), 0, st,
+                               (const double2*)W, (double2*)xws, wl, d, wr);
+  else hipLaunchKernelGGL(permute_w_left<float2>, dim3(grid_for(nW)), dim3(256), 0, st,
+                          (const float2*)W, (float2*)xws, wl, d, wr);
+  MPOEVO_HIP_TRY(hipGetLastError());
+  GemmDesc h{};
+  h.ws = gws;
+  h.ws_bytes = gws ? kGemmScratchBytes : 0;
+  h.A = xws; h.B = tmp; h.C = LB;
+  h.M = d * wr; h.N = Qb; h.K = wl * d; h.batch = P;
+  h.sAm = (long long)wl * d; h.sAk = 1; h.bA = 0;
+  h.sBk = Qb; h.sBn = 1; h.bB = (long long)wl * d * Qb;
+  h.sCm = Qb; h.sCn = 1; h.bC = (long long)d * wr * Qb;
+  return gemm_timed(h, fp64, false, st, pr);
 }
 
 // RB[beta][b][t'][c'] = sum W[beta][t'][t][gamma] ket[b][t][c] E[c'][gamma][c]
 // ket: (Qa, d, Qb), E: (Pr, wr, Qb), W: (wl, d, d, wr). tmp holds Qa*d*Pr*wr complex.
 hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W, void* tmp,
                        void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st,
-                       Prof* pr = nullptr, void* gws = nullptr) {
+                       Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr) {
   GemmDesc g{};
   g.ws = gws;
   g.ws_bytes = gws ? kGemmScratchBytes : 0;
@@ -191,10 +242,36 @@ hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W,
   g.M = Qa * d; g.N = Pr * wr; g.K = Qb; g.batch = 1;
   g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sBn = Qb; g.sCm = (long long)Pr * wr; g.sCn = 1;
   MPOEVO_HIP_TRY(gemm_timed(g, fp64, false, st, pr));
-  PROF_BEGIN(pr, tok);
-  MPOEVO_HIP_TRY(wmix_right(fp64, tmp, W, RB, Qa, Pr, wl, d, wr, st));
-  const double cs = fp64 ? 16.0 : 8.0;
-  PROF_END(pr, tok, Prof::kWmix, cs * ((double)Qa * d * Pr * wr + (double)wl * Qa * d * Pr + wl * d * d * wr));
+  if (wmix_supported(wl, d, wr)) {
+    PROF_BEGIN(pr, tok);
+    MPOEVO_HIP_TRY(wmix_right(fp64, tmp, W, RB, Qa, Pr, wl, d, wr, st));
+    const double cs = fp64 ? 16.0 : 8.0;
+    PROF_END(pr, tok, Prof::kWmix, cs * ((double)Qa * d * Pr * wr + (double)wl * Qa * d * Pr + wl * d * d * wr));
+    return hipSuccess;
+  }
+  // large MPO bond: Up[b][t][gamma][c'] = U[b][t][c'][gamma], then for each t':
+  // RB[beta][b][t'][c'] = sum_{(t, gamma)} W[beta][t'][t][gamma] Up_b[(t, gamma)][c']
+  if (!xws) return hipErrorInvalidValue;
+  const long long nU = (long long)Qa * d * Pr * wr;
+  if (fp64) hipLaunchKernelGGL(permute_u_right<double2>, dim3(grid_for(nU)), dim3(256), 0, st,
+                               (const double2*)tmp, (double2*)xws, (long long)Qa * d, Pr, wr);
+  else hipLaunchKernelGGL(permute_u_right<float2>, dim3(grid_for(nU)), dim3(256), 0, st,
+                          (const float2*)tmp, (float2*)xws, (long long)Qa * d, Pr, wr);
+  MPOEVO_HIP_TRY(hipGetLastError());
+  const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
+  for (int tp = 0; tp < d; ++tp) {
+    GemmDesc h{};
+    h.ws = gws;
+    h.ws_bytes = gws ? kGemmScratchBytes : 0;
+    h.A = static_cast<const unsigned char*>(W) + cs * (size_t)tp * d * wr;
+    h.B = xws;
+    h.C = static_cast<unsigned char*>(RB) + cs * (size_t)tp * Pr;
+    h.M = wl; h.N = Pr; h.K = d * wr; h.batch = Qa;
+    h.sAm = (long long)d * d * wr; h.sAk = 1; h.bA = 0;
+    h.sBk = Pr; h.sBn = 1; h.bB = (long long)d * wr * Pr;
+    h.sCm = (long long)Qa * d * Pr; h.sCn = 1; h.bC = (long long)d * Pr;
+    MPOEVO_HIP_TRY(gemm_timed(h, fp64, false, st, pr));
+  }
   return hipSuccess;
 }
 
@@ -253,12 +330,19 @@ hipError_t absorb_right(const void* site_in, const void* R, void* site_out, int 
   return gemm_launch(g, true, true, st);
 }
 
+// Scratch of the short-leg contraction done as a product (MPO bonds beyond the register kernels):
+// W permuted for the left side, the right intermediate transposed for the right side.
+size_t wcontract_xws(long long ket_rows, long long bra_cols, int d, int wl, int wr, size_t cs) {
+  if (wmix_supported(wl, d, wr)) return 0;
+  return std::max(a256(cs * (size_t)d * wr * wl * d), a256(cs * (size_t)(ket_rows * d * bra_cols * wr)));
+}
+
 // ------------------------------------------------------------------------- step workspace map
 struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
   size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
-      off_basis, basiscap, off_token, off_gemm, total;
+      off_basis, basiscap, off_token, off_gemm, off_xws, total;
 };
 
 StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
@@ -295,6 +379,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_basis = take(sizeof(double2) * s.basiscap * (size_t)std::max(L - 1, 1));
   s.off_token = take(sizeof(unsigned long long));  // which step last wrote the unitaries
   s.off_gemm = take(kGemmScratchBytes);             // split-K partial products
+  s.off_xws = take(wcontract_xws(Dmax, Dmax, d, wmax, wmax, cs));  // large MPO bonds
   s.total = o;
   return s;
 }
@@ -347,8 +432,12 @@ size_t env_update_core(const int* dims, int prec) {
   return std::max(left, right);
 }
 
+size_t env_update_xws(const int* dims, int prec) {
+  return wcontract_xws(dims[1], dims[2], dims[4], dims[5], dims[6], csize(prec));
+}
+
 size_t env_update_ws(const int* dims, int prec) {
-  return env_update_core(dims, prec) + kGemmScratchBytes;  // split-K scratch at the end
+  return env_update_core(dims, prec) + env_update_xws(dims, prec) + kGemmScratchBytes;
 }
 
 size_t local_apply_core(const int* dims, int prec) {
@@ -359,8 +448,14 @@ size_t local_apply_core(const int* dims, int prec) {
   return a256(tmp) + a256(cs * Dbl * d * wm * Dkm) + a256(cs * wm * Dkm * d * Dbr);
 }
 
+size_t local_apply_xws(const int* dims, int prec) {
+  const size_t cs = csize(prec);
+  return std::max(wcontract_xws(dims[1], dims[2], dims[5], dims[6], dims[7], cs),
+                  wcontract_xws(dims[2], dims[4], dims[5], dims[7], dims[8], cs));
+}
+
 size_t local_apply_ws(const int* dims, int prec) {
-  return local_apply_core(dims, prec) + kGemmScratchBytes;  // split-K scratch at the end
+  return local_apply_core(dims, prec) + local_apply_xws(dims, prec) + kGemmScratchBytes;
 }
 
 size_t truncate_ws(int m, int n) {
@@ -401,23 +496,23 @@ int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const voi
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   const int Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4], wl = dims[5],
             wr = dims[6];
-  if (!wmix_supported(wl, d, wr)) { ctx.err = "env_update: MPO bond too large for this build"; return MPOEVO_EUNSUPPORTED; }
   const bool fp64 = prec == MPOEVO_FP64;
   const size_t cs = csize(prec);
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* base = static_cast<unsigned char*>(ws);
-  void* gws = base + env_update_core(dims, prec);
+  void* xws = base + env_update_core(dims, prec);
+  void* gws = static_cast<unsigned char*>(xws) + env_update_xws(dims, prec);
   hipError_t e;
   if (side == MPOEVO_LEFT) {
     void* tmp = base;
     void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
-    e = left_block(fp64, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws);
+    e = left_block(fp64, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws, xws);
     if (e == hipSuccess)
       e = left_env_from_block(fp64, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st, nullptr, gws);
   } else {
     void* tmp = base;
     void* RB = base + a256(cs * (size_t)Dkl * d * Dbr * wr);
-    e = right_block(fp64, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st, nullptr, gws);
+    e = right_block(fp64, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st, nullptr, gws, xws);
     if (e == hipSuccess)
       e = right_env_from_block(fp64, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st, nullptr, gws);
   }
@@ -430,10 +525,6 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   const int Dbl = dims[0], Dkl = dims[1], Dkm = dims[2], Dkr = dims[3], Dbr = dims[4], d = dims[5],
             wl = dims[6], wm = dims[7], wr = dims[8];
-  if (!wmix_supported(wl, d, wm) || !wmix_supported(wm, d, wr)) {
-    ctx.err = "local_apply: MPO bond too large for this build";
-    return MPOEVO_EUNSUPPORTED;
-  }
   const bool fp64 = prec == MPOEVO_FP64;
   const size_t cs = csize(prec);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -442,10 +533,11 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
   void* tmp = base;
   void* LB = base + tmpb;
   void* RB = base + tmpb + a256(cs * (size_t)Dbl * d * wm * Dkm);
-  void* gws = base + local_apply_core(dims, prec);
-  hipError_t e = left_block(fp64, L, M1, W1, tmp, LB, Dbl, wl, Dkl, d, Dkm, wm, st, nullptr, gws);
+  void* xws = base + local_apply_core(dims, prec);
+  void* gws = static_cast<unsigned char*>(xws) + local_apply_xws(dims, prec);
+  hipError_t e = left_block(fp64, L, M1, W1, tmp, LB, Dbl, wl, Dkl, d, Dkm, wm, st, nullptr, gws, xws);
   if (e == hipSuccess)
-    e = right_block(fp64, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st, nullptr, gws);
+    e = right_block(fp64, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st, nullptr, gws, xws);
   if (e == hipSuccess) e = theta_product(fp64, LB, RB, Theta, Dbl, d, wm, Dkm, Dbr, st, nullptr, gws);
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "local_apply");
 }
@@ -467,7 +559,7 @@ size_t expectation_ws(int L, int d, int Dmax, int wmax) {
   (void)L;
   const size_t env = a256(sizeof(double2) * (size_t)Dmax * wmax * Dmax);
   const size_t blk = a256(sizeof(double2) * (size_t)Dmax * wmax * d * Dmax);
-  return 2 * env + 2 * blk + kGemmScratchBytes;
+  return 2 * env + 2 * blk + wcontract_xws(Dmax, Dmax, d, wmax, wmax, sizeof(double2)) + kGemmScratchBytes;
 }
 
 // E <- E . psi_i . O_i . conj(psi_i), i = 0 .. L-1, from E = e_left; out = E[right].
@@ -477,11 +569,6 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
   const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
   int wmax = 0;
   for (int i = 0; i <= L; ++i) wmax = std::max(wmax, mpo->w[i]);
-  for (int i = 0; i < L; ++i)
-    if (!wmix_supported(mpo->w[i], d, mpo->w[i + 1])) {
-      ctx.err = "expectation: MPO bond too large for this build";
-      return MPOEVO_EUNSUPPORTED;
-    }
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* base = static_cast<unsigned char*>(ws);
   const size_t env = a256(sizeof(double2) * (size_t)Dmax * wmax * Dmax);
@@ -489,7 +576,8 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
   double2* E[2] = {reinterpret_cast<double2*>(base), reinterpret_cast<double2*>(base + env)};
   void* tmp = base + 2 * env;
   void* LB = base + 2 * env + blk;
-  void* gws = base + 2 * env + 2 * blk;
+  void* xws = base + 2 * env + 2 * blk;
+  void* gws = static_cast<unsigned char*>(xws) + wcontract_xws(Dmax, Dmax, d, wmax, wmax, sizeof(double2));
   const int* D = mps->bond_dim;
   const int* w = mpo->w;
   hipLaunchKernelGGL(boundary_level, dim3((w[0] + 255) / 256), dim3(256), 0, st, E[0], w[0], left);
@@ -497,7 +585,7 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
   int cur = 0;
   for (int i = 0; i < L && e == hipSuccess; ++i) {
     e = left_block(true, E[cur], mps->site[i], mpo->site[i], tmp, LB, D[i], w[i], D[i], d, D[i + 1],
-                   w[i + 1], st, nullptr, gws);
+                   w[i + 1], st, nullptr, gws, xws);
     if (e == hipSuccess)
       e = left_env_from_block(true, mps->site[i], LB, E[cur ^ 1], D[i], d, D[i + 1], w[i + 1],
                               D[i + 1], st, nullptr, gws);
@@ -518,11 +606,6 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   const bool fp64 = prec == MPOEVO_FP64;
   int wmax = 0;
   for (int i = 0; i <= L; ++i) wmax = std::max(wmax, mpo->w[i]);
-  for (int i = 0; i < L; ++i)
-    if (!wmix_supported(mpo->w[i], d, mpo->w[i + 1])) {
-      ctx.err = "step: MPO bond too large for this build";
-      return MPOEVO_EUNSUPPORTED;
-    }
   const StepLayout lay = step_layout(L, d, Dmax, wmax, prec);
   const size_t cs = csize(prec);
   unsigned char* base = static_cast<unsigned char*>(ws);
@@ -555,6 +638,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   const int* w = mpo->w;
   auto basis = [&](int i) { return reinterpret_cast<double2*>(base + lay.off_basis) + lay.basiscap * i; };
   void* gws = base + lay.off_gemm;
+  void* xws = base + lay.off_xws;
 
   // Jacobi preconditioners: kept in the workspace between steps of the same handle, valid while
   // the workspace and the chain's shape stay the same; otherwise every bond restarts from the
@@ -645,7 +729,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   STEP_TRY(set_boundary(env1, w[L], fp64, st));  // Renv_L
   for (int i = L - 1; i >= 1; --i) {
     STEP_TRY(right_block(fp64, ket(i), env1, wsite(i), tmp, RB(i), Q[i], d, Q[i + 1], P[i + 1],
-                         w[i], w[i + 1], st, prof, gws));
+                         w[i], w[i + 1], st, prof, gws, xws));
     flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
     if (i > 1) {
       STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st, prof, gws));
@@ -667,7 +751,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         flop_gemm(P[i], (double)w[i] * Q[i], (double)P[i - 1] * d);
       }
       STEP_TRY(left_block(fp64, env0, ket(i), wsite(i), tmp, LB(i), P[i], w[i], Q[i], d, Q[i + 1],
-                          w[i + 1], st, prof, gws));
+                          w[i + 1], st, prof, gws, xws));
       flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
       const int m = P[i] * d, n = d * P[i + 2];
       STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
@@ -697,7 +781,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                                       w[i + 2], Q[i + 2], st, prof, gws));
         flop_gemm(P[i + 2], (double)w[i + 2] * Q[i + 2], (double)d * P[i + 3]);
         STEP_TRY(right_block(fp64, ket(i + 1), env1, wsite(i + 1), tmp, RB(i + 1), Q[i + 1], d,
-                             Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st, prof, gws));
+                             Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st, prof, gws, xws));
         flop_gemm((double)Q[i + 1] * d, (double)P[i + 2] * w[i + 2], Q[i + 2]);
       }
       const int m = P[i] * d, n = d * P[i + 2];

@@ -60,6 +60,8 @@ ENV_CASES = [  # Dbra_l, Dket_l, Dbra_r, Dket_r, d, w_l, w_r
     (64, 64, 64, 64, 2, 8, 8),
     (100, 131, 140, 77, 3, 4, 5),
     (130, 130, 130, 130, 2, 6, 6),
+    (20, 17, 23, 19, 2, 271, 271),  # the order-3 long-range Ising MPO bond: W contraction as a product
+    (9, 11, 13, 10, 2, 13, 40),     # one short (register kernel) and one long MPO leg
 ]
 
 
@@ -107,6 +109,7 @@ LA_CASES = [  # Dbra_l, Dket_l, Dket_m, Dket_r, Dbra_r, d, w_l, w_m, w_r
     (33, 40, 47, 29, 35, 2, 3, 3, 3),
     (64, 64, 64, 64, 64, 2, 6, 6, 6),
     (20, 31, 27, 18, 22, 3, 4, 5, 4),
+    (10, 12, 14, 11, 9, 2, 271, 271, 271),
 ]
 
 
@@ -370,3 +373,26 @@ def test_expectation_rejects_bad_levels(mp, handle):
     with pytest.raises(mp.MpoevoError) as e:
         mp.expectation(handle, dm, mp.DeviceMPO([Wh] * 4), left=0, right=Wh.shape[0])
     assert e.value.code == mp.EINVAL
+
+
+def _lr_blocks(g):
+    import json, os
+    fit = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lr_fit_K6.json")))
+    return wl.lr_ising(np.array(fit["coeffs"]), np.array(fit["lambdas"]), g)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_step_parity_long_range_order3(mp, handle, prec):
+    """Long-range Ising (J(r) = r^-2 as six exponentials, g = 1), order-3 extended MPO (w = 271):
+    one step against the oracle from the same random state."""
+    _say("step long-range order 3 w=271 L=6 D=8", "fp64" if prec == 0 else "fp32")
+    H = _lr_blocks(1.0)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 3, -0.1j, mp.V2_EXTENDED)
+    assert W.shape[0] == 271
+    rng = np.random.default_rng(31)
+    psi = _normalise(wl.random_mps(rng, 6, 2, 4))
+    ref, rst = ofit.fit_step(psi, W, Dmax=8, nsweeps=2)
+    out, st = _gpu_step(mp, handle, psi, W, 8, prec)
+    infid = 1 - abs(ofit.overlap(out, ref)) ** 2
+    assert infid < (1e-12 if prec == 0 else 1e-9), infid
+    assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]
