@@ -12,13 +12,21 @@ separate copy of the initial state.
 
 Also reported: the same opening steps on the plain FP64 path (FP32/FP64 time ratio on identical
 steps), one step at saturated bond dimension on a seeded random MPS (D = 128 on every bulk bond),
+one step of the long-range chain at D = 256 with the w = 271 order-3 MPO on both paths (step time
+and matrix-core rate of the contractions: the "TFLOP/s at D = 256" part of the metric),
 the environment-update microbenchmark at D = 256, d = 2, w = 8 (the matrix-core roofline target),
 per-kernel-class times summed over the timed steps, per-step parity of the first step against the
 oracle from the same initial state (infidelity and <Z_32> error), and the CPU oracle timed on one
 saturated-bond step (the cpu_baseline).
 
+With --workload lr3: the long-range Ising chain of the configuration with the largest MPO bond,
+J(r) = r^-2 as six exponentials (tests/golden/lr_fit_K6.json), g = 1, L = 100, order-3 extended MPO
+(w = 271), tau = 0.1, at saturated bond dimension D = 256 (seeded random MPS), K timed steps after
+W warm-up steps of the same trajectory (defaults K = 2, W = 1), FP32 and FP64 paths; the CPU oracle
+is timed on one bond visit of that workload and scaled to a step (labelled extrapolated).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64]
+                       [--no-cpu] [--no-fp64] [--workload quench|lr3]
 """
 from __future__ import annotations
 
@@ -70,6 +78,103 @@ def load_ground():
     return [z[f"site_{i:03d}"] for i in range(L)]
 
 
+def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
+    """K steps of the order-3 long-range Ising chain at D = 256 (w = 271), FP32 and FP64 paths.
+    embedded: return a summary dict (FP32 vs FP64 step time and product rate) instead of printing."""
+    import json as _json
+    Llr, Dlr, order, tau = 100, 256, 3, 0.1
+    if steps is None:
+        steps = args.steps if args.steps != 100 else 2
+    if warmup is None:
+        warmup = args.warmup
+    fit = _json.load(open(os.path.join(ROOT, "tests", "golden", "lr_fit_K6.json")))
+    H = wl.lr_ising(np.array(fit["coeffs"]), np.array(fit["lambdas"]), 1.0)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, order, -1j * tau, mp.V2_EXTENDED)
+    w = W.shape[0]
+    dw = mp.DeviceMPO([W] * Llr)
+    psi = wl.random_mps(np.random.default_rng(0), Llr, 2, Dlr)
+
+    def run(p, n):
+        dm = mp.DeviceMPS(psi, Dmax=Dlr)
+        ws = mp.step_workspace(dm, dw, p)
+        for k in range(warmup):
+            mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=ws)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        ev[0].record()
+        st = []
+        for k in range(n):
+            st.append(mp.step(h, dm, dw, prec=p, input_right_canonical=(warmup + k) > 0, workspace=ws,
+                              profile=True))
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(n)]
+        del ws, dm
+        torch.cuda.empty_cache()
+        return ms, st
+
+    prec = mp.FP32 if (args.prec == "fp32" or embedded) else mp.FP64
+    ms, st = run(prec, steps)
+    sec = float(np.sum(ms)) / 1e3 / steps
+    prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile}
+    peak = PEAK_FP32_MFMA if prec == mp.FP32 else PEAK_FP64_MFMA
+    gemm_tf = prof["gemm_gflop"] / prof["t_gemm_ms"] if prof["t_gemm_ms"] > 0 else 0.0
+    fp64 = None
+    if (embedded or not args.no_fp64) and prec == mp.FP32:
+        ms64, st64 = run(mp.FP64, steps)
+        p64 = {k: float(sum(x.profile[k] for x in st64)) for k in st64[0].profile}
+        fp64 = {"fp64_s_per_step": float(np.sum(ms64)) / 1e3 / steps,
+                "fp64_gemm_tflops": p64["gemm_gflop"] / p64["t_gemm_ms"] if p64["t_gemm_ms"] > 0 else 0.0}
+        fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / sec
+    if embedded:
+        return {"workload": f"long-range Ising L={Llr}, order-{order} extended MPO (w={w}), tau={tau}, "
+                            f"D={Dlr} saturated random MPS, {steps} step(s) after {warmup} warm-up",
+                "fp32_s_per_step": sec, "fp64_s_per_step": fp64["fp64_s_per_step"],
+                "fp32_speedup": fp64["fp32_speedup"], "step_tflop": float(np.mean([x.gflop for x in st])) / 1e3,
+                "fp32_gemm_tflops": gemm_tf, "fp32_gemm_frac_of_mfma_peak": gemm_tf * 1e12 / PEAK_FP32_MFMA,
+                "fp64_gemm_tflops": fp64["fp64_gemm_tflops"],
+                "fp64_gemm_frac_of_mfma_peak": fp64["fp64_gemm_tflops"] * 1e12 / PEAK_FP64_MFMA,
+                "jacobi_share_fp32": prof["t_jacobi_ms"] / max(float(np.sum(ms)), 1e-9)}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import fit as ofit
+        import threadpoolctl
+        rng = np.random.default_rng(1)
+        Lenv = wl.complex_normal(rng, (Dlr, w, Dlr))
+        M1, M2 = wl.complex_normal(rng, (Dlr, 2, Dlr)), wl.complex_normal(rng, (Dlr, 2, Dlr))
+        t0 = time.perf_counter()
+        ofit.env_left(Lenv, M1, W, M1)
+        ofit.theta_two_site(Lenv, M1, W, M2, W, Lenv)
+        visit = time.perf_counter() - t0
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] + [1])
+        cpu = {"value": visit * 4 * (Llr - 1), "unit": "s per time step (extrapolated)", "cores": int(threads),
+               "kind": "oracle",
+               "sample": f"one bond visit's contractions (one environment update and the projected two-site "
+                         f"tensor, D={Dlr}, w={w}) timed in the oracle ({visit:.2f} s, numpy complex128, "
+                         f"{threads} BLAS threads), times the {4 * (Llr - 1)} visits of a step; the SVDs "
+                         f"are not included"}
+    line = {
+        "metric": "s per time step & TFLOP/s at D=256: FP32-MFMA grouped vs plain FP64, fidelity",
+        "value": sec, "unit": "s per time step", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 contractions, f64 SVD" if prec == mp.FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"long-range Ising L={Llr}, J(r)=r^-2 as 6 exponentials, g=1, order-{order} "
+                               f"extended MPO (w={w}), tau={tau}, D={Dlr} saturated random MPS",
+                   "L": Llr, "D": Dlr, "order": order, "tau": tau},
+        "step_gflop": float(np.mean([x.gflop for x in st])),
+        "kernel_classes_timed_steps": {
+            "jacobi_svd_ms": prof["t_jacobi_ms"], "n_jacobi": prof["n_jacobi"],
+            "complex_gemm_ms": prof["t_gemm_ms"], "complex_gemm_gflop": prof["gemm_gflop"],
+            "complex_gemm_tflops": gemm_tf, "complex_gemm_frac_of_peak": gemm_tf * 1e12 / peak,
+            "w_contraction_ms": prof["t_wmix_ms"]},
+        "svd_sweeps_mean": float(np.mean([x.svd_sweeps_total / max(x.visits, 1) for x in st])),
+        "fp64_path": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +184,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--workload", choices=["quench", "lr3"], default="quench")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the time step of a single chain is sequential across "
@@ -92,6 +198,10 @@ def main():
 
     torch.cuda.set_device(0)
     h = mp.Handle(0)
+    if args.workload == "lr3":
+        run_lr3(args, torch, mp, wl, h)
+        h.close()
+        return
     prec = mp.FP32 if args.prec == "fp32" else mp.FP64
     psi0 = load_ground()
     H = wl.tfim(G_AFTER)
@@ -190,6 +300,7 @@ def main():
 
     mb32_ms, mb_flop = env_microbench(mp, h, torch, prec64=False)
     mb64_ms, _ = env_microbench(mp, h, torch, prec64=True)
+    d256 = None if args.no_fp64 else run_lr3(args, torch, mp, wl, h, steps=1, warmup=1, embedded=True)
 
     # parity of the first step from psi0 against the oracle, and the CPU baseline
     cpu = None
@@ -253,6 +364,7 @@ def main():
         "diagnostics_device": diag,
         "gpu_saturated_step_s": sat_s,
         "parity_vs_oracle": parity,
+        "d256_long_range": d256,
         "env_microbench": {"D": 256, "d": 2, "w": 8, "fp32_ms": mb32_ms, "fp64_ms": mb64_ms,
                            "fp32_tflops": mb_tflops, "fp64_tflops": mb_flop / (mb64_ms * 1e-3) / 1e12,
                            "fp32_frac_of_mfma_peak": mb_tflops * 1e12 / PEAK_FP32_MFMA,

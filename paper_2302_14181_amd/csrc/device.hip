@@ -731,6 +731,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     STEP_TRY(right_block(fp64, ket(i), env1, wsite(i), tmp, RB(i), Q[i], d, Q[i + 1], P[i + 1],
                          w[i], w[i + 1], st, prof, gws, xws));
     flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
+    flop_gemm((double)w[i] * d * Q[i], P[i + 1], (double)d * w[i + 1]);  // the W contraction
     if (i > 1) {
       STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st, prof, gws));
       flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
@@ -753,6 +754,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       STEP_TRY(left_block(fp64, env0, ket(i), wsite(i), tmp, LB(i), P[i], w[i], Q[i], d, Q[i + 1],
                           w[i + 1], st, prof, gws, xws));
       flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
+      flop_gemm((double)P[i] * d * w[i + 1], Q[i + 1], (double)w[i] * d);  // the W contraction
       const int m = P[i] * d, n = d * P[i + 2];
       STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
@@ -783,6 +785,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         STEP_TRY(right_block(fp64, ket(i + 1), env1, wsite(i + 1), tmp, RB(i + 1), Q[i + 1], d,
                              Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st, prof, gws, xws));
         flop_gemm((double)Q[i + 1] * d, (double)P[i + 2] * w[i + 2], Q[i + 2]);
+        flop_gemm((double)w[i + 1] * d * Q[i + 1], P[i + 2], (double)d * w[i + 2]);  // the W contraction
       }
       const int m = P[i] * d, n = d * P[i + 2];
       STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
