@@ -128,6 +128,23 @@ __device__ inline void wave_sum4(double& a, double& b, double& c, double& d) {
   }
 }
 
+__device__ inline void wave_sum2(double& a, double& b) {
+  a += dpp_move<0xB1>(a); b += dpp_move<0xB1>(b);
+  a += dpp_move<0x4E>(a); b += dpp_move<0x4E>(b);
+  a += dpp_move<0x141>(a); b += dpp_move<0x141>(b);
+  a += dpp_move<0x140>(a); b += dpp_move<0x140>(b);
+  a += __shfl_xor(a, 16, 64); b += __shfl_xor(b, 16, 64);
+  a += __shfl_xor(a, 32, 64); b += __shfl_xor(b, 32, 64);
+}
+
+template <int R>
+__device__ inline double sq_norm_part(const double2 (&u)[R]) {
+  double a = 0.0;
+#pragma unroll
+  for (int t = 0; t < R; ++t) a = fma(u[t].x, u[t].x, fma(u[t].y, u[t].y, a));
+  return a;
+}
+
 // 1/sqrt(x) and 1/x to full double precision: hardware estimate plus Newton steps.
 __device__ inline double rsqrt_d(double x) {
   double r = __builtin_amdgcn_rsq(x);
@@ -224,28 +241,27 @@ __device__ bool grid_barrier(unsigned* flags, unsigned* bar, unsigned nblocks, u
   return timed_out == 0;
 }
 
-// One Jacobi rotation of the column pair (u, v) held in registers (RMAX rows per lane): the
-// three inner products, the rotation that makes the pair orthogonal, applied in place (and to
-// the pair's columns of the accumulated rotation, qu and qv, when ACC). Returns whether the pair
-// was rotated; records the pair's relative inner product in *wg_max.
+// One Jacobi rotation of the column pair (u, v) held in registers (RMAX rows per lane), given
+// their squared norms a = |u|^2, bb = |v|^2: the inner product, the rotation that makes the pair
+// orthogonal, applied in place (and to the pair's columns of the accumulated rotation, qu and
+// qv, when ACC). The norms follow the rotation exactly in exact arithmetic, |u'|^2 = a - t |g|,
+// |v'|^2 = bb + t |g|; when either loses more than 31/32 of its value (cancellation) both are
+// recomputed from the columns. Returns whether the pair was rotated; records the pair's relative
+// inner product in *wg_max.
 template <int RMAX, bool ACC>
 __device__ inline bool jacobi_pair(double2 (&u)[RMAX], double2 (&v)[RMAX], double2 (&qu)[RMAX],
-                                   double2 (&qv)[RMAX], int lane, double floor2, double tol2,
-                                   unsigned* wg_max) {
-  double a = 0.0, bb = 0.0, gr = 0.0, gi = 0.0;
+                                   double2 (&qv)[RMAX], double& a, double& bb, int lane,
+                                   double floor2, double tol2, unsigned* wg_max) {
+  double gr = 0.0, gi = 0.0;
 #pragma unroll
   for (int t = 0; t < RMAX; ++t) {
-    a = fma(u[t].x, u[t].x, fma(u[t].y, u[t].y, a));
-    bb = fma(v[t].x, v[t].x, fma(v[t].y, v[t].y, bb));
     gr = fma(u[t].x, v[t].x, fma(u[t].y, v[t].y, gr));
     gi = fma(u[t].x, v[t].y, fma(-u[t].y, v[t].x, gi));
   }
-  wave_sum4(a, bb, gr, gi);
+  wave_sum2(gr, gi);
   // Rotation parameters without divisions or square roots: |gamma|^2 = g2, r = 1/|gamma|,
   // phase e = conj(gamma) r, zeta = (|v|^2 - |u|^2) / (2 |gamma|),
-  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = t c. Only c, s and e
-  // must be exact (a unitary rotation); t may carry rounding, which only leaves a slightly
-  // larger remainder for the next sweep.
+  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = t c.
   const double g2 = fma(gr, gr, gi * gi);
   const double ab = a * bb;
   const bool live = fmin(a, bb) > floor2;
@@ -273,6 +289,17 @@ __device__ inline bool jacobi_pair(double2 (&u)[RMAX], double2 (&v)[RMAX], doubl
       qv[tt] = double2{s * qu[tt].x + c * evx, s * qu[tt].y + c * evy};
       qu[tt] = un;
     }
+  }
+  const double tg = t * (g2 * r);  // t |gamma|
+  const double an = a - tg, bn = bb + tg;
+  if (an < 0.03125 * a || bn < 0.03125 * bb) {  // wave-uniform: all lanes hold the same values
+    double x = sq_norm_part(u), y = sq_norm_part(v);
+    wave_sum2(x, y);
+    a = x;
+    bb = y;
+  } else {
+    a = an;
+    bb = bn;
   }
   return true;
 }
@@ -305,6 +332,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   extern __shared__ double2 cols[];  // [2b][mx] then (ACC) [2b][nx]
   __shared__ unsigned wg_max;        // bits of a non-negative float: integer order = value order
   __shared__ double floor2_sh;
+  __shared__ double nrm[2 * 16];     // squared norms of the 2b columns held in LDS (b <= 16)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int two_b = 2 * p.b, mx = p.mx, nx = p.nx;
   double2* qcols = cols + two_b * mx;
@@ -333,6 +361,12 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
         load_col(v, w.X + (long long)gy * mx, lane, mx);
         store_col(u, cols + wave * mx, lane, mx);
         store_col(v, cols + (p.b + wave) * mx, lane, mx);
+        double na = sq_norm_part(u), nb = sq_norm_part(v);
+        wave_sum2(na, nb);
+        if (lane == 0) {
+          nrm[wave] = na;
+          nrm[p.b + wave] = nb;
+        }
         if (ACC) {
           load_col(u, w.Q + (long long)gx * nx, lane, nx);
           load_col(v, w.Q + (long long)gy * nx, lane, nx);
@@ -359,9 +393,14 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
               load_col(qu, qcols + x * nx, lane, nx);
               load_col(qv, qcols + y * nx, lane, nx);
             }
-            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, lane, floor2, tol2, &wg_max)) {
+            double na = nrm[x], nb = nrm[y];
+            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, na, nb, lane, floor2, tol2, &wg_max)) {
               store_col(u, cols + x * mx, lane, mx);
               store_col(v, cols + y * mx, lane, mx);
+              if (lane == 0) {
+                nrm[x] = na;
+                nrm[y] = nb;
+              }
               if (ACC) {
                 store_col(qu, qcols + x * nx, lane, nx);
                 store_col(qv, qcols + y * nx, lane, nx);
@@ -373,7 +412,9 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
       } else {
         double2 u[RMAX], qu[RMAX];
         bool dirty = false;
+        double na = 0.0;
         if (pk < p.b) {
+          na = nrm[pk];
           load_col(u, cols + pk * mx, lane, mx);
           if (ACC) load_col(qu, qcols + pk * nx, lane, nx);
         }
@@ -384,9 +425,11 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
             double2 v[RMAX], qv[RMAX];
             load_col(v, cols + y * mx, lane, mx);
             if (ACC) load_col(qv, qcols + y * nx, lane, nx);
-            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, lane, floor2, tol2, &wg_max)) {
+            double nb = nrm[y];
+            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, na, nb, lane, floor2, tol2, &wg_max)) {
               store_col(v, cols + y * mx, lane, mx);
               if (ACC) store_col(qv, qcols + y * nx, lane, nx);
+              if (lane == 0) nrm[y] = nb;
               dirty = true;
             }
           }
