@@ -28,8 +28,10 @@
 // column pair with both columns in registers. The first round of a sweep visits every pair of
 // its 2b columns (so every pair inside a block is visited once per sweep), the other rounds
 // only the b x b pairs across their two blocks: each pair of columns is rotated exactly once
-// per sweep. Rounds are separated by a grid barrier of the cooperative launch; a sweep whose
-// largest relative inner product is below tol (or below kAccept) ends the iteration.
+// per sweep. A workgroup starts a round once the two workgroups that wrote its blocks in the
+// previous round have published (point-to-point flags of the cooperative launch); every sweep
+// ends with a wait for all workgroups, after which a sweep whose largest relative inner product
+// is below tol (or below kAccept) ends the iteration.
 
 #include <algorithm>
 #include <cmath>
@@ -202,27 +204,38 @@ __global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, Sv
   }
 }
 
-// Grid barrier of the cooperative launch: workgroup g publishes the generation it reached in
-// flags[g] (release) and waits until every workgroup's flag has reached it (acquire), one lane
-// per flag. No shared counter, so arrivals do not serialise on one address. A wait longer than
-// the timeout (or another workgroup's timeout) sets bar[2] and makes every workgroup return
-// false; all workgroups then leave the sweep loop.
-__device__ bool grid_barrier(unsigned* flags, unsigned* bar, unsigned nblocks, unsigned gen) {
-  __shared__ int timed_out;
+// Synchronisation between the workgroups of the cooperative launch, without a shared counter
+// (whose atomics serialise): workgroup g publishes in flags[g] the number of rounds it has
+// completed (release); a workgroup that needs the blocks written in the previous round waits
+// for the flags of the two workgroups that wrote them (acquire), and at the end of a sweep every
+// workgroup waits for all flags. A wait longer than the timeout (or another workgroup's timeout)
+// sets bar[2] and makes every waiting workgroup return false; all workgroups then leave the sweep
+// loop.
+__device__ void publish_round(unsigned* flags, unsigned gen) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    timed_out = 0;
     __threadfence();
     __hip_atomic_store(&flags[blockIdx.x], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// Waits until flags[j] >= gen for j = f0, f1 (nblocks < 0) or for every j < nblocks.
+__device__ bool wait_flags(unsigned* flags, unsigned* bar, int f0, int f1, int nblocks, unsigned gen) {
+  __shared__ int timed_out;
+  if (threadIdx.x == 0) timed_out = 0;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     const unsigned long long t0 = wall_clock64();
     bool fail = false;
     while (true) {
       int mine = 1;
-      for (unsigned j = lane; j < nblocks; j += 64)
-        mine &= __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+      if (nblocks < 0) {
+        if (lane == 0) mine = __hip_atomic_load(&flags[f0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+        if (lane == 1) mine = __hip_atomic_load(&flags[f1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+      } else {
+        for (int j = lane; j < nblocks; j += 64)
+          mine &= __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+      }
       if (__all(mine)) break;
       if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
           wall_clock64() - t0 > kBarrierTimeoutTicks) {
@@ -239,6 +252,14 @@ __device__ bool grid_barrier(unsigned* flags, unsigned* bar, unsigned nblocks, u
   }
   __syncthreads();
   return timed_out == 0;
+}
+
+// The pair index of round r of the round-robin over n blocks that holds block blk.
+__device__ inline int rr_owner(int r, int blk, int n) {
+  if (blk == n - 1) return 0;
+  const int k1 = ((blk - r) % (n - 1) + (n - 1)) % (n - 1);  // blk in the first slot
+  if (k1 < n / 2) return k1;
+  return ((r - blk) % (n - 1) + (n - 1)) % (n - 1);          // blk in the second slot
 }
 
 // One Jacobi rotation of the column pair (u, v) held in registers (RMAX rows per lane), given
@@ -353,6 +374,10 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
     for (int r = 0; r < p.nb - 1 && ok; ++r) {
       int bp, bq;
       rr_pair(r, blockIdx.x, p.nb, bp, bq);
+      // the two blocks were written in the previous round by the workgroups that held them
+      if (r > 0 && !(ok = wait_flags(w.flags, w.bar, rr_owner(r - 1, bp, p.nb), rr_owner(r - 1, bq, p.nb),
+                                     -1, gen)))
+        break;
       const int gx = bp * p.b + wave, gy = bq * p.b + wave;  // this wave's two global columns
       // 2b columns global -> LDS: wave k moves column k of each block through its registers
       if (wave < p.b) {
@@ -455,9 +480,9 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
         }
       }
       if (tid == 0 && wg_max) atomicMax(&w.sweep_max[sweep], wg_max);
-      ok = grid_barrier(w.flags, w.bar, nblk, ++gen);
+      publish_round(w.flags, ++gen);
     }
-    if (!ok) break;
+    if (!ok || !(ok = wait_flags(w.flags, w.bar, 0, 0, (int)nblk, gen))) break;
     const float mxr = __uint_as_float(
         __hip_atomic_load(&w.sweep_max[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
     if ((double)mxr <= tol || (double)mxr <= kAccept) break;
