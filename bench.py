@@ -12,11 +12,12 @@ separate copy of the initial state.
 
 Also reported: the same opening steps on the plain FP64 path (FP32/FP64 time ratio on identical
 steps), one step at saturated bond dimension on a seeded random MPS (D = 128 on every bulk bond),
-one step of the long-range chain at D = 256 with the w = 271 order-3 MPO on both paths (step time
-and matrix-core rate of the contractions: the "TFLOP/s at D = 256" part of the metric),
+one step of the long-range chain at D = 256 with the w = 271 order-3 MPO on the FP32, FP64 and
+split-BF16x3 paths (step time and matrix-core rate of the contractions: the "TFLOP/s at D = 256"
+part of the metric),
 the environment-update microbenchmark at D = 256, d = 2, w = 8 (the matrix-core roofline target),
 per-kernel-class times summed over the timed steps, per-step parity of the first step against the
-oracle from the same initial state (infidelity and <Z_32> error), and the CPU oracle timed on one
+oracle from the same initial state on each path (infidelity and <Z_32> error), and the CPU oracle timed on one
 saturated-bond step (the cpu_baseline).
 
 With --workload lr3: the long-range Ising chain of the configuration with the largest MPO bond,
@@ -25,7 +26,7 @@ J(r) = r^-2 as six exponentials (tests/golden/lr_fit_K6.json), g = 1, L = 100, o
 W warm-up steps of the same trajectory (defaults K = 2, W = 1), FP32 and FP64 paths; the CPU oracle
 is timed on one bond visit of that workload and scaled to a step (labelled extrapolated).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64] [--fp64-steps N]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
                        [--no-cpu] [--no-fp64] [--workload quench|lr3]
 """
 from __future__ import annotations
@@ -43,28 +44,37 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64_MFMA = 78.6e12
+PEAK_BF16_MFMA = 2.5e15
+# split-BF16x3 issues three bf16 products per algorithmic one
+CEIL_BF16X3 = PEAK_BF16_MFMA / 3
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
+DTYPES = {"fp32": "f32 contractions, f64 SVD", "fp64": "f64",
+          "bf16x3": "split-bf16x3 contractions (f32 storage, f32 accumulation), f64 SVD"}
 GROUND = os.path.join(ROOT, "tests", "golden", "tfim_g05_L64_ground.npz")
 L, D, G_AFTER, ORDER, TAU = 64, 128, 1.5, 2, 0.1
 
 
-def env_microbench(mp, h, torch, prec64: bool, reps: int = 50):
+def prec_of(mp, name: str) -> int:
+    return {"fp32": mp.FP32, "fp64": mp.FP64, "bf16x3": mp.BF16X3}[name]
+
+
+def env_microbench(mp, h, torch, prec: int, reps: int = 50):
     """Time env_update (left) at D = 256, d = 2, w = 8 with HIP events on the launch stream."""
     from paper_2302_14181_amd import workloads as wl
     E, M, N, W = wl.env_microbench_inputs(0)
-    dt = torch.complex128 if prec64 else torch.complex64
+    dt = torch.complex128 if prec == mp.FP64 else torch.complex64
     t = {k: torch.from_numpy(v).to(dt).cuda() for k, v in dict(E=E, M=M, N=N, W=W).items()}
     out = torch.empty((256, 8, 256), dtype=dt, device="cuda")
-    ws = torch.empty(mp.workspace_size(mp.CALL_ENV_UPDATE, [256, 256, 256, 256, 2, 8, 8],
-                                       mp.FP64 if prec64 else mp.FP32), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(mp.workspace_size(mp.CALL_ENV_UPDATE, [256, 256, 256, 256, 2, 8, 8], prec),
+                     dtype=torch.uint8, device="cuda")
     for _ in range(3):
-        mp.env_update(h, mp.LEFT, t["E"], t["N"], t["W"], t["M"], out, workspace=ws)
+        mp.env_update(h, mp.LEFT, t["E"], t["N"], t["W"], t["M"], out, workspace=ws, prec=prec)
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
     for _ in range(reps):
-        mp.env_update(h, mp.LEFT, t["E"], t["N"], t["W"], t["M"], out, workspace=ws)
+        mp.env_update(h, mp.LEFT, t["E"], t["N"], t["W"], t["M"], out, workspace=ws, prec=prec)
     e.record()
     torch.cuda.synchronize()
     ms = s.elapsed_time(e) / reps
@@ -79,8 +89,9 @@ def load_ground():
 
 
 def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
-    """K steps of the order-3 long-range Ising chain at D = 256 (w = 271), FP32 and FP64 paths.
-    embedded: return a summary dict (FP32 vs FP64 step time and product rate) instead of printing."""
+    """K steps of the order-3 long-range Ising chain at D = 256 (w = 271): the chosen path, and
+    with an FP32 path also plain FP64 and split-BF16x3 on the same steps.
+    embedded: return a summary dict (FP32 vs FP64 vs BF16X3 step time and product rate)."""
     import json as _json
     Llr, Dlr, order, tau = 100, 256, 3, 0.1
     if steps is None:
@@ -113,19 +124,25 @@ def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
         torch.cuda.empty_cache()
         return ms, st
 
-    prec = mp.FP32 if (args.prec == "fp32" or embedded) else mp.FP64
+    prec = mp.FP32 if embedded else prec_of(mp, args.prec)
     ms, st = run(prec, steps)
     sec = float(np.sum(ms)) / 1e3 / steps
     prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile}
-    peak = PEAK_FP32_MFMA if prec == mp.FP32 else PEAK_FP64_MFMA
+    peak = {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA, mp.BF16X3: CEIL_BF16X3}[prec]
     gemm_tf = prof["gemm_gflop"] / prof["t_gemm_ms"] if prof["t_gemm_ms"] > 0 else 0.0
-    fp64 = None
+    fp64 = bf = None
     if (embedded or not args.no_fp64) and prec == mp.FP32:
         ms64, st64 = run(mp.FP64, steps)
         p64 = {k: float(sum(x.profile[k] for x in st64)) for k in st64[0].profile}
         fp64 = {"fp64_s_per_step": float(np.sum(ms64)) / 1e3 / steps,
                 "fp64_gemm_tflops": p64["gemm_gflop"] / p64["t_gemm_ms"] if p64["t_gemm_ms"] > 0 else 0.0}
         fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / sec
+        msb, stb = run(mp.BF16X3, steps)
+        pb = {k: float(sum(x.profile[k] for x in stb)) for k in stb[0].profile}
+        bf = {"bf16x3_s_per_step": float(np.sum(msb)) / 1e3 / steps,
+              "bf16x3_gemm_tflops": pb["gemm_gflop"] / pb["t_gemm_ms"] if pb["t_gemm_ms"] > 0 else 0.0}
+        bf["bf16x3_frac_of_ceiling"] = bf["bf16x3_gemm_tflops"] * 1e12 / CEIL_BF16X3
+        bf["bf16x3_speedup_vs_fp64"] = fp64["fp64_s_per_step"] / bf["bf16x3_s_per_step"]
     if embedded:
         return {"workload": f"long-range Ising L={Llr}, order-{order} extended MPO (w={w}), tau={tau}, "
                             f"D={Dlr} saturated random MPS, {steps} step(s) after {warmup} warm-up",
@@ -134,7 +151,8 @@ def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
                 "fp32_gemm_tflops": gemm_tf, "fp32_gemm_frac_of_mfma_peak": gemm_tf * 1e12 / PEAK_FP32_MFMA,
                 "fp64_gemm_tflops": fp64["fp64_gemm_tflops"],
                 "fp64_gemm_frac_of_mfma_peak": fp64["fp64_gemm_tflops"] * 1e12 / PEAK_FP64_MFMA,
-                "jacobi_share_fp32": prof["t_jacobi_ms"] / max(float(np.sum(ms)), 1e-9)}
+                "jacobi_share_fp32": prof["t_jacobi_ms"] / max(float(np.sum(ms)), 1e-9),
+                "bf16x3": bf}
     cpu = None
     if not args.no_cpu:
         from oracle import fit as ofit
@@ -158,7 +176,7 @@ def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
         "metric": "s per time step & TFLOP/s at D=256: FP32-MFMA grouped vs plain FP64, fidelity",
         "value": sec, "unit": "s per time step", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 contractions, f64 SVD" if prec == mp.FP32 else "f64", "data": "synthetic",
+        "dtype": DTYPES[args.prec], "data": "synthetic",
         "config": {"workload": f"long-range Ising L={Llr}, J(r)=r^-2 as 6 exponentials, g=1, order-{order} "
                                f"extended MPO (w={w}), tau={tau}, D={Dlr} saturated random MPS",
                    "L": Llr, "D": Dlr, "order": order, "tau": tau},
@@ -170,6 +188,7 @@ def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
             "w_contraction_ms": prof["t_wmix_ms"]},
         "svd_sweeps_mean": float(np.mean([x.svd_sweeps_total / max(x.visits, 1) for x in st])),
         "fp64_path": fp64,
+        "bf16x3_path": bf,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
@@ -180,7 +199,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--prec", choices=["fp32", "fp64", "bf16x3"], default="fp32")
     ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
@@ -202,7 +221,7 @@ def main():
         run_lr3(args, torch, mp, wl, h)
         h.close()
         return
-    prec = mp.FP32 if args.prec == "fp32" else mp.FP64
+    prec = prec_of(mp, args.prec)
     psi0 = load_ground()
     H = wl.tfim(G_AFTER)
     W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -1j * TAU, mp.V2_EXTENDED)
@@ -245,7 +264,8 @@ def main():
                        "work_unit": "GFLOP", "bound": "alu", "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"},
         "complex_gemm": {"ms": prof["t_gemm_ms"], "launches": prof["n_gemm"], "work": prof["gemm_gflop"],
                          "work_unit": "GFLOP", "bound": "mfma",
-                         "peak": (PEAK_FP32_MFMA if prec == mp.FP32 else PEAK_FP64_MFMA) / 1e12, "unit": "TFLOP/s"},
+                         "peak": {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA,
+                                  mp.BF16X3: CEIL_BF16X3}[prec] / 1e12, "unit": "TFLOP/s"},
         "w_contraction": {"ms": prof["t_wmix_ms"], "launches": prof["n_wmix"], "work": prof["wmix_gbyte"],
                           "work_unit": "GB", "bound": "hbm", "peak": PEAK_HBM / 1e9, "unit": "GB/s"},
     }
@@ -298,8 +318,9 @@ def main():
     sat_s = s.elapsed_time(e) / 1e3
     del wsr, dmr
 
-    mb32_ms, mb_flop = env_microbench(mp, h, torch, prec64=False)
-    mb64_ms, _ = env_microbench(mp, h, torch, prec64=True)
+    mb32_ms, mb_flop = env_microbench(mp, h, torch, mp.FP32)
+    mb64_ms, _ = env_microbench(mp, h, torch, mp.FP64)
+    mbbf_ms, _ = env_microbench(mp, h, torch, mp.BF16X3)
     d256 = None if args.no_fp64 else run_lr3(args, torch, mp, wl, h, steps=1, warmup=1, embedded=True)
 
     # parity of the first step from psi0 against the oracle, and the CPU baseline
@@ -310,7 +331,7 @@ def main():
         import threadpoolctl
         ref, rinfo = ofit.fit_step(psi0, W, Dmax=D, nsweeps=2)
         parity = {}
-        for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64)):
+        for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64), ("bf16x3", mp.BF16X3)):
             dm1 = mp.DeviceMPS(psi0, Dmax=D)
             s1 = mp.step(h, dm1, dw, prec=p)
             out = dm1.to_numpy()
@@ -348,7 +369,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 contractions, f64 SVD" if prec == mp.FP32 else "f64",
+        "dtype": DTYPES[args.prec],
         "data": "synthetic",
         "config": {"workload": f"TFIM quench L={L} from the g=0.5 ground state to g={G_AFTER}, order-{ORDER} "
                                f"extended MPO (w={W.shape[0]}), tau={TAU}, D<={D}, 2 sweeps per step, "
@@ -368,7 +389,9 @@ def main():
         "env_microbench": {"D": 256, "d": 2, "w": 8, "fp32_ms": mb32_ms, "fp64_ms": mb64_ms,
                            "fp32_tflops": mb_tflops, "fp64_tflops": mb_flop / (mb64_ms * 1e-3) / 1e12,
                            "fp32_frac_of_mfma_peak": mb_tflops * 1e12 / PEAK_FP32_MFMA,
-                           "fp64_frac_of_mfma_peak": mb_flop / (mb64_ms * 1e-3) / PEAK_FP64_MFMA},
+                           "fp64_frac_of_mfma_peak": mb_flop / (mb64_ms * 1e-3) / PEAK_FP64_MFMA,
+                           "bf16x3_ms": mbbf_ms, "bf16x3_tflops": mb_flop / (mbbf_ms * 1e-3) / 1e12,
+                           "bf16x3_frac_of_ceiling": mb_flop / (mbbf_ms * 1e-3) / CEIL_BF16X3},
         "roofline": {"bound": classes[dominant]["bound"], "kernel": dominant,
                      "achieved": classes[dominant]["achieved"], "peak": classes[dominant]["peak"],
                      "unit": classes[dominant]["unit"], "frac": classes[dominant]["frac"],

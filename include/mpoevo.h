@@ -18,8 +18,12 @@
  *   - MPO site tensor W[alpha][s_out][s_in][beta];
  *   - environment E[bra][mpo][ket]; the bra tensor is conjugated inside the contractions.
  * Precision: MPOEVO_FP64 contracts in double (complex128 inputs/outputs); MPOEVO_FP32 contracts
- * in float on the matrix cores with float accumulation (complex64 inputs/outputs). The SVD,
- * the truncation and all norms are FP64 in both modes.
+ * in float on the matrix cores with float accumulation (complex64 inputs/outputs);
+ * MPOEVO_BF16X3 takes the same complex64 inputs/outputs as MPOEVO_FP32 but multiplies on the
+ * bf16 matrix cores: each float operand is split into a bf16 head and a bf16 tail, the three
+ * products head*head + head*tail + tail*head are accumulated in float (relative error of each
+ * product about 2^-16 against about 2^-24 for FP32, at a higher matrix-core rate). The SVD,
+ * the truncation and all norms are FP64 in every mode.
  *
  * Ownership: the caller allocates every input, output and workspace buffer; the library never
  * frees or reallocates them. A handle owns only its own small bookkeeping (error text, device
@@ -53,7 +57,7 @@ enum {
   MPOEVO_EUNSUPPORTED = -7  /* valid request this build does not implement */
 };
 
-enum { MPOEVO_FP64 = 0, MPOEVO_FP32 = 1 };
+enum { MPOEVO_FP64 = 0, MPOEVO_FP32 = 1, MPOEVO_BF16X3 = 2 };
 enum { MPOEVO_V1_EXACT = 0, MPOEVO_V2_EXTENDED = 1 };
 enum { MPOEVO_LEFT = 0, MPOEVO_RIGHT = 1 };
 

@@ -16,6 +16,8 @@ int fail(mpoevo::Context* ctx, int code, const std::string& msg) {
   else g_thread_err = msg;
   return code;
 }
+
+bool valid_prec(int prec) { return prec == MPOEVO_FP64 || prec == MPOEVO_FP32 || prec == MPOEVO_BF16X3; }
 }  // namespace
 
 extern "C" {
@@ -65,7 +67,7 @@ int mpo_build(int d, int chi, const double* A, const double* B, const double* C,
 
 int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes) {
   if (!dims || !bytes) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_workspace_size: NULL argument");
-  if (prec != MPOEVO_FP64 && prec != MPOEVO_FP32) return fail(nullptr, MPOEVO_EINVAL, "unknown precision");
+  if (!valid_prec(prec)) return fail(nullptr, MPOEVO_EINVAL, "unknown precision");
   switch (call_id) {
     case MPOEVO_CALL_ENV_UPDATE:
       for (int i = 0; i < 7; ++i) if (dims[i] < 1) return fail(nullptr, MPOEVO_ESHAPE, "non-positive dimension");
@@ -104,7 +106,7 @@ int env_update(mpoevo_handle h, int side, int prec, const void* E_in, const void
   if (!h) return fail(nullptr, MPOEVO_EINVAL, "env_update: NULL handle");
   auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
   if (side != MPOEVO_LEFT && side != MPOEVO_RIGHT) return fail(ctx, MPOEVO_EINVAL, "env_update: unknown side");
-  if (prec != MPOEVO_FP64 && prec != MPOEVO_FP32) return fail(ctx, MPOEVO_EINVAL, "env_update: unknown precision");
+  if (!valid_prec(prec)) return fail(ctx, MPOEVO_EINVAL, "env_update: unknown precision");
   if (!E_in || !bra || !W || !ket || !E_out || !dims) return fail(ctx, MPOEVO_EINVAL, "env_update: NULL pointer");
   for (int i = 0; i < 7; ++i) if (dims[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "env_update: non-positive dimension");
   if (workspace_bytes < mpoevo::env_update_ws(dims, prec) || (!workspace && workspace_bytes))
@@ -119,7 +121,7 @@ int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void
   if (!h) return fail(nullptr, MPOEVO_EINVAL, "local_apply: NULL handle");
   auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
   if (nsites != 2) return fail(ctx, MPOEVO_EUNSUPPORTED, "local_apply: only the two-site tensor is built");
-  if (prec != MPOEVO_FP64 && prec != MPOEVO_FP32) return fail(ctx, MPOEVO_EINVAL, "local_apply: unknown precision");
+  if (!valid_prec(prec)) return fail(ctx, MPOEVO_EINVAL, "local_apply: unknown precision");
   if (!L || !W1 || !W2 || !M1 || !M2 || !R || !Theta || !dims) return fail(ctx, MPOEVO_EINVAL, "local_apply: NULL pointer");
   for (int i = 0; i < 9; ++i) if (dims[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "local_apply: non-positive dimension");
   if (workspace_bytes < mpoevo::local_apply_ws(dims, prec) || (!workspace && workspace_bytes))
@@ -160,7 +162,7 @@ int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_s
   auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
   if (!mps || !mpo || !opts || !mps->bond_dim || !mps->site || !mpo->w || !mpo->site)
     return fail(ctx, MPOEVO_EINVAL, "step: NULL argument");
-  if (opts->prec != MPOEVO_FP64 && opts->prec != MPOEVO_FP32) return fail(ctx, MPOEVO_EINVAL, "step: unknown precision");
+  if (!valid_prec(opts->prec)) return fail(ctx, MPOEVO_EINVAL, "step: unknown precision");
   if (opts->nsweeps < 1 || opts->nsweeps > 4) return fail(ctx, MPOEVO_EINVAL, "step: nsweeps must be 1..4");
   if (!(opts->cutoff >= 0.0) || opts->cutoff >= 1.0) return fail(ctx, MPOEVO_EINVAL, "step: cutoff must be in [0, 1)");
   const int L = mps->L, d = mps->d, Dmax = mps->Dmax;

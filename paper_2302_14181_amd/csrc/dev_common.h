@@ -26,6 +26,7 @@ struct GemmDesc {
   bool conjA, conjB;
   void* ws;         // optional scratch for split-K partial tiles (null: never split)
   size_t ws_bytes;
+  bool bf16x3;      // fp32 operands: split-BF16x3 products on the bf16 matrix cores
 };
 
 // Scratch a caller gives gemm_launch for split-K partial results (the planner never needs more).

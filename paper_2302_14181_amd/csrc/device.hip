@@ -187,23 +187,33 @@ hipError_t set_boundary(void* E, int w, bool fp64, hipStream_t st) {
 // E: (P, wl, Qa), ket: (Qa, d, Qb), W: (wl, d, d, wr). tmp holds P*wl*d*Qb complex.
 double gemm_flop(const GemmDesc& g) { return 8.0 * g.M * g.N * (double)g.K * g.batch; }
 
-hipError_t gemm_timed(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st, Prof* pr) {
+// Arithmetic of the contraction products: FP64, FP32, or FP32 operands multiplied as split-BF16x3.
+struct Arith {
+  bool fp64;
+  bool bf16x3;
+};
+Arith arith_of(int prec) { return Arith{prec == MPOEVO_FP64, prec == MPOEVO_BF16X3}; }
+
+hipError_t gemm_timed(const GemmDesc& g, Arith ar, bool out_fp64, hipStream_t st, Prof* pr) {
+  GemmDesc h = g;
+  h.bf16x3 = ar.bf16x3 && !ar.fp64;
   PROF_BEGIN(pr, tok);
-  MPOEVO_HIP_TRY(gemm_launch(g, fp64, out_fp64, st));
-  PROF_END(pr, tok, Prof::kGemm, gemm_flop(g));
+  MPOEVO_HIP_TRY(gemm_launch(h, ar.fp64, out_fp64, st));
+  PROF_END(pr, tok, Prof::kGemm, gemm_flop(h));
   return hipSuccess;
 }
 
-hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, void* tmp,
+hipError_t left_block(Arith ar, const void* E, const void* ket, const void* W, void* tmp,
                       void* LB, int P, int wl, int Qa, int d, int Qb, int wr, hipStream_t st,
                       Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr) {
+  const bool fp64 = ar.fp64;
   GemmDesc g{};
   g.ws = gws;
   g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = E; g.B = ket; g.C = tmp;
   g.M = P * wl; g.N = d * Qb; g.K = Qa; g.batch = 1;
   g.sAm = Qa; g.sAk = 1; g.sBk = (long long)d * Qb; g.sBn = 1; g.sCm = (long long)d * Qb; g.sCn = 1;
-  MPOEVO_HIP_TRY(gemm_timed(g, fp64, false, st, pr));
+  MPOEVO_HIP_TRY(gemm_timed(g, ar, false, st, pr));
   if (wmix_supported(wl, d, wr)) {
     PROF_BEGIN(pr, tok);
     MPOEVO_HIP_TRY(wmix_left(fp64, tmp, W, LB, P, Qb, wl, d, wr, st));
@@ -227,21 +237,22 @@ hipError_t left_block(bool fp64, const void* E, const void* ket, const void* W, 
   h.sAm = (long long)wl * d; h.sAk = 1; h.bA = 0;
   h.sBk = Qb; h.sBn = 1; h.bB = (long long)wl * d * Qb;
   h.sCm = Qb; h.sCn = 1; h.bC = (long long)d * wr * Qb;
-  return gemm_timed(h, fp64, false, st, pr);
+  return gemm_timed(h, ar, false, st, pr);
 }
 
 // RB[beta][b][t'][c'] = sum W[beta][t'][t][gamma] ket[b][t][c] E[c'][gamma][c]
 // ket: (Qa, d, Qb), E: (Pr, wr, Qb), W: (wl, d, d, wr). tmp holds Qa*d*Pr*wr complex.
-hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W, void* tmp,
+hipError_t right_block(Arith ar, const void* ket, const void* E, const void* W, void* tmp,
                        void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st,
                        Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr) {
+  const bool fp64 = ar.fp64;
   GemmDesc g{};
   g.ws = gws;
   g.ws_bytes = gws ? kGemmScratchBytes : 0;
   g.A = ket; g.B = E; g.C = tmp;
   g.M = Qa * d; g.N = Pr * wr; g.K = Qb; g.batch = 1;
   g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sBn = Qb; g.sCm = (long long)Pr * wr; g.sCn = 1;
-  MPOEVO_HIP_TRY(gemm_timed(g, fp64, false, st, pr));
+  MPOEVO_HIP_TRY(gemm_timed(g, ar, false, st, pr));
   if (wmix_supported(wl, d, wr)) {
     PROF_BEGIN(pr, tok);
     MPOEVO_HIP_TRY(wmix_right(fp64, tmp, W, RB, Qa, Pr, wl, d, wr, st));
@@ -270,13 +281,13 @@ hipError_t right_block(bool fp64, const void* ket, const void* E, const void* W,
     h.sAm = (long long)d * d * wr; h.sAk = 1; h.bA = 0;
     h.sBk = Pr; h.sBn = 1; h.bB = (long long)d * wr * Pr;
     h.sCm = (long long)Qa * d * Pr; h.sCn = 1; h.bC = (long long)d * Pr;
-    MPOEVO_HIP_TRY(gemm_timed(h, fp64, false, st, pr));
+    MPOEVO_HIP_TRY(gemm_timed(h, ar, false, st, pr));
   }
   return hipSuccess;
 }
 
 // Lnew[b'][beta][b] = sum conj(bra[a'][s'][b']) LB[a'][s'][beta][b]; bra: (Pa, d, Pb).
-hipError_t left_env_from_block(bool fp64, const void* bra, const void* LB, void* Lnew, int Pa,
+hipError_t left_env_from_block(Arith ar, const void* bra, const void* LB, void* Lnew, int Pa,
                                int d, int Pb, int wr, int Qb, hipStream_t st,
                          Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
@@ -286,11 +297,11 @@ hipError_t left_env_from_block(bool fp64, const void* bra, const void* LB, void*
   g.M = Pb; g.N = wr * Qb; g.K = Pa * d; g.batch = 1;
   g.sAm = 1; g.sAk = Pb; g.conjA = true;
   g.sBk = (long long)wr * Qb; g.sBn = 1; g.sCm = (long long)wr * Qb; g.sCn = 1;
-  return gemm_timed(g, fp64, false, st, pr);
+  return gemm_timed(g, ar, false, st, pr);
 }
 
 // Rnew[a'][alpha][a] = sum conj(bra[a'][t'][c']) RB[alpha][a][t'][c']; bra: (Pa, d, Pb).
-hipError_t right_env_from_block(bool fp64, const void* bra, const void* RB, void* Rnew, int Pa,
+hipError_t right_env_from_block(Arith ar, const void* bra, const void* RB, void* Rnew, int Pa,
                                 int d, int Pb, int wl, int Qa, hipStream_t st,
                          Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
@@ -300,11 +311,11 @@ hipError_t right_env_from_block(bool fp64, const void* bra, const void* RB, void
   g.M = Pa; g.N = wl * Qa; g.K = d * Pb; g.batch = 1;
   g.sAm = (long long)d * Pb; g.sAk = 1; g.conjA = true;
   g.sBk = 1; g.sBn = (long long)d * Pb; g.sCm = (long long)wl * Qa; g.sCn = 1;
-  return gemm_timed(g, fp64, false, st, pr);
+  return gemm_timed(g, ar, false, st, pr);
 }
 
 // Theta[(a',s')][(t',c')] = sum LB[(a',s')][(beta,b)] RB[(beta,b)][(t',c')], complex128 out.
-hipError_t theta_product(bool fp64, const void* LB, const void* RB, void* theta, int Pa, int d,
+hipError_t theta_product(Arith ar, const void* LB, const void* RB, void* theta, int Pa, int d,
                          int wm, int Qm, int Pc, hipStream_t st,
                          Prof* pr = nullptr, void* gws = nullptr) {
   GemmDesc g{};
@@ -314,7 +325,7 @@ hipError_t theta_product(bool fp64, const void* LB, const void* RB, void* theta,
   g.M = Pa * d; g.N = d * Pc; g.K = wm * Qm; g.batch = 1;
   g.sAm = (long long)wm * Qm; g.sAk = 1; g.sBk = (long long)d * Pc; g.sBn = 1;
   g.sCm = (long long)d * Pc; g.sCn = 1;
-  return gemm_timed(g, fp64, true, st, pr);
+  return gemm_timed(g, ar, true, st, pr);
 }
 
 // Site product site[a][s][b] <- sum_c site_in[a][s][c] R[c][b] (complex128), used to absorb
@@ -348,7 +359,7 @@ struct StepLayout {
 StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   StepLayout s{};
   const size_t cs = csize(prec);
-  const bool f32 = prec == MPOEVO_FP32;
+  const bool f32 = prec != MPOEVO_FP64;  // complex64 copies of the operands
   s.sitecap = (size_t)Dmax * d * Dmax;
   s.lbcap = (size_t)Dmax * d * wmax * Dmax;
   s.envcap = (size_t)Dmax * wmax * Dmax;
@@ -496,7 +507,7 @@ int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const voi
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   const int Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4], wl = dims[5],
             wr = dims[6];
-  const bool fp64 = prec == MPOEVO_FP64;
+  const Arith ar = arith_of(prec);
   const size_t cs = csize(prec);
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* base = static_cast<unsigned char*>(ws);
@@ -506,15 +517,15 @@ int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const voi
   if (side == MPOEVO_LEFT) {
     void* tmp = base;
     void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
-    e = left_block(fp64, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws, xws);
+    e = left_block(ar, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws, xws);
     if (e == hipSuccess)
-      e = left_env_from_block(fp64, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st, nullptr, gws);
+      e = left_env_from_block(ar, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st, nullptr, gws);
   } else {
     void* tmp = base;
     void* RB = base + a256(cs * (size_t)Dkl * d * Dbr * wr);
-    e = right_block(fp64, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st, nullptr, gws, xws);
+    e = right_block(ar, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st, nullptr, gws, xws);
     if (e == hipSuccess)
-      e = right_env_from_block(fp64, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st, nullptr, gws);
+      e = right_env_from_block(ar, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st, nullptr, gws);
   }
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "env_update");
 }
@@ -525,7 +536,7 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   const int Dbl = dims[0], Dkl = dims[1], Dkm = dims[2], Dkr = dims[3], Dbr = dims[4], d = dims[5],
             wl = dims[6], wm = dims[7], wr = dims[8];
-  const bool fp64 = prec == MPOEVO_FP64;
+  const Arith ar = arith_of(prec);
   const size_t cs = csize(prec);
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* base = static_cast<unsigned char*>(ws);
@@ -535,10 +546,10 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
   void* RB = base + tmpb + a256(cs * (size_t)Dbl * d * wm * Dkm);
   void* xws = base + local_apply_core(dims, prec);
   void* gws = static_cast<unsigned char*>(xws) + local_apply_xws(dims, prec);
-  hipError_t e = left_block(fp64, L, M1, W1, tmp, LB, Dbl, wl, Dkl, d, Dkm, wm, st, nullptr, gws, xws);
+  hipError_t e = left_block(ar, L, M1, W1, tmp, LB, Dbl, wl, Dkl, d, Dkm, wm, st, nullptr, gws, xws);
   if (e == hipSuccess)
-    e = right_block(fp64, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st, nullptr, gws, xws);
-  if (e == hipSuccess) e = theta_product(fp64, LB, RB, Theta, Dbl, d, wm, Dkm, Dbr, st, nullptr, gws);
+    e = right_block(ar, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st, nullptr, gws, xws);
+  if (e == hipSuccess) e = theta_product(ar, LB, RB, Theta, Dbl, d, wm, Dkm, Dbr, st, nullptr, gws);
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "local_apply");
 }
 
@@ -584,10 +595,10 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
   hipError_t e = hipGetLastError();
   int cur = 0;
   for (int i = 0; i < L && e == hipSuccess; ++i) {
-    e = left_block(true, E[cur], mps->site[i], mpo->site[i], tmp, LB, D[i], w[i], D[i], d, D[i + 1],
+    e = left_block(Arith{true, false}, E[cur], mps->site[i], mpo->site[i], tmp, LB, D[i], w[i], D[i], d, D[i + 1],
                    w[i + 1], st, nullptr, gws, xws);
     if (e == hipSuccess)
-      e = left_env_from_block(true, mps->site[i], LB, E[cur ^ 1], D[i], d, D[i + 1], w[i + 1],
+      e = left_env_from_block(Arith{true, false}, mps->site[i], LB, E[cur ^ 1], D[i], d, D[i + 1], w[i + 1],
                               D[i + 1], st, nullptr, gws);
     cur ^= 1;
   }
@@ -604,6 +615,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   const int L = mps->L, d = mps->d, Dmax = mps->Dmax, prec = opts->prec;
   const bool fp64 = prec == MPOEVO_FP64;
+  const Arith ar = arith_of(prec);
   int wmax = 0;
   for (int i = 0; i <= L; ++i) wmax = std::max(wmax, mpo->w[i]);
   const StepLayout lay = step_layout(L, d, Dmax, wmax, prec);
@@ -728,12 +740,12 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   // right blocks RB_i, i = L-1 .. 1, from the canonical guess
   STEP_TRY(set_boundary(env1, w[L], fp64, st));  // Renv_L
   for (int i = L - 1; i >= 1; --i) {
-    STEP_TRY(right_block(fp64, ket(i), env1, wsite(i), tmp, RB(i), Q[i], d, Q[i + 1], P[i + 1],
+    STEP_TRY(right_block(ar, ket(i), env1, wsite(i), tmp, RB(i), Q[i], d, Q[i + 1], P[i + 1],
                          w[i], w[i + 1], st, prof, gws, xws));
     flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
     flop_gemm((double)w[i] * d * Q[i], P[i + 1], (double)d * w[i + 1]);  // the W contraction
     if (i > 1) {
-      STEP_TRY(right_env_from_block(fp64, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st, prof, gws));
+      STEP_TRY(right_env_from_block(ar, bra(i), RB(i), env1, P[i], d, P[i + 1], w[i], Q[i], st, prof, gws));
       flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
     }
   }
@@ -747,16 +759,16 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     for (int i = 0; i <= L - 2; ++i, ++visit) {
       if (i == 0) STEP_TRY(set_boundary(env0, w[0], fp64, st));
       else {
-        STEP_TRY(left_env_from_block(fp64, bra(i - 1), LB(i - 1), env0, P[i - 1], d, P[i],
+        STEP_TRY(left_env_from_block(ar, bra(i - 1), LB(i - 1), env0, P[i - 1], d, P[i],
                                      w[i], Q[i], st, prof, gws));
         flop_gemm(P[i], (double)w[i] * Q[i], (double)P[i - 1] * d);
       }
-      STEP_TRY(left_block(fp64, env0, ket(i), wsite(i), tmp, LB(i), P[i], w[i], Q[i], d, Q[i + 1],
+      STEP_TRY(left_block(ar, env0, ket(i), wsite(i), tmp, LB(i), P[i], w[i], Q[i], d, Q[i + 1],
                           w[i + 1], st, prof, gws, xws));
       flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
       flop_gemm((double)P[i] * d * w[i + 1], Q[i + 1], (double)w[i] * d);  // the W contraction
       const int m = P[i] * d, n = d * P[i + 2];
-      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
+      STEP_TRY(theta_product(ar, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
@@ -779,16 +791,16 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     // right to left
     for (int i = L - 2; i >= 0; --i, ++visit) {
       if (i < L - 2) {
-        STEP_TRY(right_env_from_block(fp64, bra(i + 2), RB(i + 2), env1, P[i + 2], d, P[i + 3],
+        STEP_TRY(right_env_from_block(ar, bra(i + 2), RB(i + 2), env1, P[i + 2], d, P[i + 3],
                                       w[i + 2], Q[i + 2], st, prof, gws));
         flop_gemm(P[i + 2], (double)w[i + 2] * Q[i + 2], (double)d * P[i + 3]);
-        STEP_TRY(right_block(fp64, ket(i + 1), env1, wsite(i + 1), tmp, RB(i + 1), Q[i + 1], d,
+        STEP_TRY(right_block(ar, ket(i + 1), env1, wsite(i + 1), tmp, RB(i + 1), Q[i + 1], d,
                              Q[i + 2], P[i + 2], w[i + 1], w[i + 2], st, prof, gws, xws));
         flop_gemm((double)Q[i + 1] * d, (double)P[i + 2] * w[i + 2], Q[i + 2]);
         flop_gemm((double)w[i + 1] * d * Q[i + 1], P[i + 2], (double)d * w[i + 2]);  // the W contraction
       }
       const int m = P[i] * d, n = d * P[i + 2];
-      STEP_TRY(theta_product(fp64, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
+      STEP_TRY(theta_product(ar, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {

@@ -19,6 +19,14 @@
 // cover the latency of the next step's global loads, issued before the current step's matrix
 // instructions).
 //
+// split-BF16x3 (fp32 operands): each real value x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+// (round to nearest), and A B ~ hi_A hi_B + hi_A lo_B + lo_A hi_B with fp32 accumulation on
+// v_mfma_f32_32x32x16_bf16 (lane l supplies A'[l%32][8(l/32) + j] and B'[8(l/32) + j][l%32],
+// j = 0..7; accumulators as for the fp32 instruction). The dropped lo lo term leaves about
+// 2^-16 relative error per product. A tiles are staged as bf16 rows [m][k], B tiles as bf16
+// columns [n][k] of the real expanded B', so that each lane reads its eight k values with one
+// 16-byte LDS load.
+//
 // Occupancy: the products of a sweep are small (M x N of a few hundred), so a planner picks the
 // largest tile that still gives every compute unit a workgroup, and when even the smallest tile
 // leaves most of the 256 compute units idle it splits K: each split writes its partial tile to
@@ -231,6 +239,184 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
   }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__device__ inline unsigned pack_bf16(__bf16 a, __bf16 b) {
+  return (unsigned)__builtin_bit_cast(unsigned short, a) |
+         ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
+}
+
+template <int WR, int WC, int BK, typename TO, bool AKC, bool BNC>
+__global__ __launch_bounds__(kThreads) void cgemm_bf16x3_kernel(GemmDesc g, int splits, int kchunk,
+                                                                void* part) {
+  using C2 = float2;
+  using Mf = MfmaF32;  // output layout of the 32 x 32 instructions
+  constexpr int BM = 2 * WR * 32, BNR = 2 * WC * 32, BN = BNR / 2;
+  constexpr int KR = 2 * BK;     // real k per stage, a multiple of 16
+  constexpr int PITCH = KR + 8;  // bf16 per LDS row: 16-byte aligned rows, shifted banks
+  constexpr int A_ELEMS = BM * BK / kThreads, B_ELEMS = BN * BK / kThreads;
+  constexpr int A_PLANE = BM * PITCH, B_PLANE = BNR * PITCH;
+  constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;  // hi and lo planes of A and B
+  static_assert(KR % 16 == 0 && A_ELEMS >= 1 && B_ELEMS >= 1, "bf16x3 tile");
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int bz = blockIdx.z / splits;
+  const int sk = blockIdx.z - bz * splits;
+  const int kbeg = sk * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  const C2* A = reinterpret_cast<const C2*>(g.A) + bz * g.bA;
+  const C2* B = reinterpret_cast<const C2*>(g.B) + bz * g.bB;
+  const float sgnA = g.conjA ? -1.f : 1.f;
+  const float sgnB = g.conjB ? -1.f : 1.f;
+
+  C2 ra[A_ELEMS];
+  C2 rb[B_ELEMS];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < A_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int m, k;
+      if (AKC) { m = e / BK; k = e % BK; } else { k = e / BM; m = e % BM; }
+      const int gm = m0 + m, gk = k0 + k;
+      C2 v{0.f, 0.f};
+      if (gm < g.M && gk < kend) v = A[gm * g.sAm + gk * g.sAk];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < B_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int k, n;
+      if (BNC) { k = e / BN; n = e % BN; } else { n = e / BK; k = e % BK; }
+      const int gk = k0 + k, gn = n0 + n;
+      C2 v{0.f, 0.f};
+      if (gk < kend && gn < g.N) v = B[gk * g.sBk + gn * g.sBn];
+      rb[i] = v;
+    }
+  };
+  auto store_tiles = [&](int buf) {
+    __bf16* Ah = lds + buf * STAGE;
+    __bf16* Al = Ah + A_PLANE;
+    __bf16* Bh = Al + A_PLANE;
+    __bf16* Bl = Bh + B_PLANE;
+#pragma unroll
+    for (int i = 0; i < A_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int m, k;
+      if (AKC) { m = e / BK; k = e % BK; } else { k = e / BM; m = e % BM; }
+      __bf16 h0, l0, h1, l1;
+      split_bf16(ra[i].x, h0, l0);
+      split_bf16(sgnA * ra[i].y, h1, l1);
+      *reinterpret_cast<unsigned*>(Ah + m * PITCH + 2 * k) = pack_bf16(h0, h1);
+      *reinterpret_cast<unsigned*>(Al + m * PITCH + 2 * k) = pack_bf16(l0, l1);
+    }
+#pragma unroll
+    for (int i = 0; i < B_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int k, n;
+      if (BNC) { k = e / BN; n = e % BN; } else { n = e / BK; k = e % BK; }
+      __bf16 hr, lr, hi_, li;
+      split_bf16(rb[i].x, hr, lr);
+      split_bf16(sgnB * rb[i].y, hi_, li);
+      // real column 2n: (re, -im) at k' = 2k, 2k+1; real column 2n+1: (im, re)
+      *reinterpret_cast<unsigned*>(Bh + (2 * n) * PITCH + 2 * k) = pack_bf16(hr, -hi_);
+      *reinterpret_cast<unsigned*>(Bl + (2 * n) * PITCH + 2 * k) = pack_bf16(lr, -li);
+      *reinterpret_cast<unsigned*>(Bh + (2 * n + 1) * PITCH + 2 * k) = pack_bf16(hi_, hr);
+      *reinterpret_cast<unsigned*>(Bl + (2 * n + 1) * PITCH + 2 * k) = pack_bf16(li, lr);
+    }
+  };
+
+  f32x16 acc[WR][WC];
+#pragma unroll
+  for (int i = 0; i < WR; ++i)
+#pragma unroll
+    for (int j = 0; j < WC; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int nk = (kend - kbeg + BK - 1) / BK;
+  load_tiles(kbeg);
+  store_tiles(0);
+  __syncthreads();
+  const int lrow = lane & 31, lk = 8 * (lane >> 5);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
+    const __bf16* Ah = lds + cur * STAGE;
+    const __bf16* Al = Ah + A_PLANE;
+    const __bf16* Bh = Al + A_PLANE;
+    const __bf16* Bl = Bh + B_PLANE;
+#pragma unroll
+    for (int ks = 0; ks < KR; ks += 16) {
+      bf16x8 ah[WR], al[WR], bh[WC], bl[WC];
+#pragma unroll
+      for (int i = 0; i < WR; ++i) {
+        const int off = (wm * (WR * 32) + i * 32 + lrow) * PITCH + ks + lk;
+        ah[i] = *reinterpret_cast<const bf16x8*>(Ah + off);
+        al[i] = *reinterpret_cast<const bf16x8*>(Al + off);
+      }
+#pragma unroll
+      for (int j = 0; j < WC; ++j) {
+        const int off = (wn * (WC * 32) + j * 32 + lrow) * PITCH + ks + lk;
+        bh[j] = *reinterpret_cast<const bf16x8*>(Bh + off);
+        bl[j] = *reinterpret_cast<const bf16x8*>(Bl + off);
+      }
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+
+  if (splits == 1) {
+    TO* C = reinterpret_cast<TO*>(g.C);
+    const long long cbase = (long long)bz * g.bC;
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = m0 + wm * (WR * 32) + i * 32 + Mf::out_row(lane, r);
+          const int rcol = wn * (WC * 32) + j * 32 + Mf::out_col(lane);
+          const int col = n0 + (rcol >> 1);
+          if (row < g.M && col < g.N)
+            C[2 * (cbase + row * g.sCm + col * g.sCn) + (rcol & 1)] = TO(acc[i][j][r]);
+        }
+  } else {
+    float* P = reinterpret_cast<float*>(part);
+    const long long pbase = (long long)(sk * g.batch + bz) * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = m0 + wm * (WR * 32) + i * 32 + Mf::out_row(lane, r);
+          const int rcol = wn * (WC * 32) + j * 32 + Mf::out_col(lane);
+          const int col = n0 + (rcol >> 1);
+          if (row < g.M && col < g.N)
+            P[2 * (pbase + (long long)row * g.N + col) + (rcol & 1)] = acc[i][j][r];
+        }
+  }
+}
+
 // C[b][m][n] = sum over s = 0..splits-1 (in that order) of part[s][b][m][n].
 template <typename T, typename TO>
 __global__ void splitk_reduce(GemmDesc g, int splits, const T* __restrict__ part) {
@@ -322,6 +508,42 @@ hipError_t launch_f32(const GemmDesc& g, hipStream_t st) {
   }
 }
 
+template <int WR, int WC, int BK, typename TO>
+hipError_t launch_bf16x3_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
+  constexpr int BM = 2 * WR * 32, BN = WC * 32;
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * pl.splits);
+  const bool akc = (g.sAk == 1) || (g.K == 1);
+  const bool bnc = (g.sBn == 1) || (g.N == 1);
+  void* part = pl.splits > 1 ? g.ws : nullptr;
+  if (akc && bnc)
+    hipLaunchKernelGGL((cgemm_bf16x3_kernel<WR, WC, BK, TO, true, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else if (akc)
+    hipLaunchKernelGGL((cgemm_bf16x3_kernel<WR, WC, BK, TO, true, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else if (bnc)
+    hipLaunchKernelGGL((cgemm_bf16x3_kernel<WR, WC, BK, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else
+    hipLaunchKernelGGL((cgemm_bf16x3_kernel<WR, WC, BK, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  MPOEVO_HIP_TRY(hipGetLastError());
+  if (pl.splits > 1) {
+    const long long total = (long long)g.M * g.N * g.batch;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL((splitk_reduce<float, TO>), dim3(blocks), dim3(256), 0, st, g, pl.splits,
+                       static_cast<const float*>(g.ws));
+    MPOEVO_HIP_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template <typename TO>
+hipError_t launch_bf16x3(const GemmDesc& g, hipStream_t st) {
+  const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);  // same tiles and split-K scratch as fp32
+  switch (pl.cfg) {
+    case 0: return launch_bf16x3_cfg<2, 2, 16, TO>(g, pl, st);
+    case 1: return launch_bf16x3_cfg<1, 2, 16, TO>(g, pl, st);
+    default: return launch_bf16x3_cfg<1, 1, 16, TO>(g, pl, st);
+  }
+}
+
 hipError_t launch_f64(const GemmDesc& g, hipStream_t st) {
   const Plan pl = make_plan<MfmaF64>(g, kF64Cfg, 2);
   if (pl.cfg == 0) return launch_cfg<MfmaF64, 2, 4, 8, double>(g, pl, st);
@@ -334,6 +556,7 @@ hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t 
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
   if (fp64) return launch_f64(g, st);
+  if (g.bf16x3) return out_fp64 ? launch_bf16x3<double>(g, st) : launch_bf16x3<float>(g, st);
   if (out_fp64) return launch_f32<double>(g, st);
   return launch_f32<float>(g, st);
 }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpoevo.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESOLVER, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
 V1_EXACT, V2_EXTENDED = 0, 1
 LEFT, RIGHT = 0, 1
 CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP, CALL_EXPECTATION = 0, 1, 2, 3, 4
@@ -158,12 +158,18 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _prec_of(t) -> int:
+def _prec_of(t, prec=None) -> int:
+    """Precision of a call on tensors of t's dtype: complex128 -> FP64; complex64 -> FP32, or
+    BF16X3 when asked for (the same complex64 storage, split-bf16 products)."""
     torch = _torch()
     if t.dtype == torch.complex128:
+        if prec not in (None, FP64):
+            raise MpoevoError(EINVAL, "complex128 tensors take the FP64 path")
         return FP64
     if t.dtype == torch.complex64:
-        return FP32
+        if prec not in (None, FP32, BF16X3):
+            raise MpoevoError(EINVAL, "complex64 tensors take the FP32 or BF16X3 path")
+        return FP32 if prec is None else prec
     raise MpoevoError(EINVAL, f"unsupported dtype {t.dtype}")
 
 
@@ -199,10 +205,12 @@ class Handle:
         return sweeps.value
 
 
-def env_update(h: Handle, side: int, E_in, bra, W, ket, E_out, workspace=None, stream=None):
+def env_update(h: Handle, side: int, E_in, bra, W, ket, E_out, workspace=None, stream=None,
+               prec=None):
     """Environment update (see include/mpoevo.h). Tensors: E (Dbra, w, Dket), bra/ket
-    (D_l, d, D_r), W (w_l, d, d, w_r), all complex128 or all complex64 on the device."""
-    prec = _prec_of(E_in)
+    (D_l, d, D_r), W (w_l, d, d, w_r), all complex128 or all complex64 on the device;
+    prec=BF16X3 selects split-bf16 products for complex64 tensors."""
+    prec = _prec_of(E_in, prec)
     Dbl, d, Dbr = bra.shape
     Dkl, _, Dkr = ket.shape
     wl, _, _, wr = W.shape
@@ -213,9 +221,11 @@ def env_update(h: Handle, side: int, E_in, bra, W, ket, E_out, workspace=None, s
                              _iarr(dims), _ptr(workspace), workspace.numel(), _stream(stream)), h)
 
 
-def local_apply(h: Handle, Lenv, W1, W2, M1, M2, Renv, Theta, workspace=None, stream=None):
-    """Projected two-site tensor into Theta (complex128, (Dbra_l*d) x (d*Dbra_r))."""
-    prec = _prec_of(Lenv)
+def local_apply(h: Handle, Lenv, W1, W2, M1, M2, Renv, Theta, workspace=None, stream=None,
+                prec=None):
+    """Projected two-site tensor into Theta (complex128, (Dbra_l*d) x (d*Dbra_r)); prec as for
+    env_update."""
+    prec = _prec_of(Lenv, prec)
     Dbl, wl, Dkl = Lenv.shape
     Dkm = M1.shape[2]
     Dkr = M2.shape[2]
