@@ -227,27 +227,50 @@ int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_s
          mpoevo_step_stats* stats, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * step_batched -- one time step of each of n independent chains (the method of `step`, Sec. 8.2,
+ * applied to every chain), advanced concurrently: data parallelism across chains, each chain's
+ * sweep staying sequential over its bonds.
+ *   mps[c], mpo[c]  chain c as for step (own L, d, Dmax, MPO); no two chains (and no two sites)
+ *                   may share a site buffer or a bond_dim array. Updated in place as by step.
+ *   opts            shared by all chains (as for step).
+ *   stats           nullable, else n entries (chain order), as for step.
+ * Result for each chain: the same as `step` on that chain alone with a fresh workspace (the same
+ * kernels run; only their interleaving across chains differs). The per-chain truncation
+ * preconditioners persist per chain index in the workspace, as for step.
+ * Synchronous: synchronises `stream` on entry (the inputs may have been written on it), runs the
+ * chains on the handle's own worker streams and returns when every chain is done.
+ * Workspace: mpoevo_workspace_size(MPOEVO_CALL_STEP_BATCHED, dims = {n, then L, d, Dmax, wmax of
+ * each chain}, prec): the chains' step workspaces, 256-byte aligned, in chain order.
+ * Errors: as for step (the message names the chain); EINVAL also for n outside
+ * 1..MPOEVO_MAX_CHAINS or shared site buffers / bond arrays.
+ */
+#define MPOEVO_MAX_CHAINS 4096
+int step_batched(mpoevo_handle h, int n, mpoevo_mps* mps, const mpoevo_mpo* mpo,
+                 const mpoevo_step_opts* opts, mpoevo_step_stats* stats, void* workspace,
+                 size_t workspace_bytes, void* stream);
+
+/*
  * expectation -- <psi| O |psi> for an MPO O = l . O_1 ... O_L . r with boundary vectors l = e_left
  * on MPO bond 0 and r = e_right on MPO bond L: the diagnostics of a time step (Sec. 8.2) -- the
  * energy through the Hamiltonian MPO of Sec. 2.3 (left = 0, right = w - 1), a local observable
  * as a bond-1 MPO with the operator on one site, the norm with identities. FP64 throughout, by
  * the left environment recursion of env_update (E <- E . psi_i . O_i . conj(psi_i)).
  *   mps    as for step; not modified (bond_dim host, site[i] device complex128).
- *   mpo    per-site complex128 O_i[w[i]][d][d][w[i+1]] (device); w[i] * d <= 64.
+ *   mpo    per-site complex128 O_i[w[i]][d][d][w[i+1]] (device).
  *   left, right  boundary levels, 0 <= left < w[0], 0 <= right < w[L].
  *   out    device complex128 (two doubles), written on `stream`; no synchronisation.
  * Workspace: mpoevo_workspace_size(MPOEVO_CALL_EXPECTATION, dims = {L, d, Dmax, wmax}, FP64).
- * Errors: EINVAL (NULL arguments, levels out of range), ESHAPE, ENOMEM, EUNSUPPORTED (MPO bond
- * too large), EHIP.
+ * Errors: EINVAL (NULL arguments, levels out of range), ESHAPE, ENOMEM, EHIP.
  */
 int expectation(mpoevo_handle h, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
                 void* out, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Workspace sizes in bytes for the device calls (dims as documented for each call). */
 enum { MPOEVO_CALL_ENV_UPDATE = 0, MPOEVO_CALL_LOCAL_APPLY = 1, MPOEVO_CALL_TRUNCATE = 2,
-       MPOEVO_CALL_STEP = 3, MPOEVO_CALL_EXPECTATION = 4 };
+       MPOEVO_CALL_STEP = 3, MPOEVO_CALL_EXPECTATION = 4, MPOEVO_CALL_STEP_BATCHED = 5 };
 /* dims: ENV_UPDATE -> the 7 env_update dims; LOCAL_APPLY -> the 9 local_apply dims;
- * TRUNCATE -> {m, n}; STEP and EXPECTATION -> {L, d, Dmax, wmax}. */
+ * TRUNCATE -> {m, n}; STEP and EXPECTATION -> {L, d, Dmax, wmax};
+ * STEP_BATCHED -> {n, L_0, d_0, Dmax_0, wmax_0, ..., L_{n-1}, d_{n-1}, Dmax_{n-1}, wmax_{n-1}}. */
 int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes);
 
 #ifdef __cplusplus

@@ -8,6 +8,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -21,7 +22,7 @@ HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # no packed fp32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-result",
+    "-Wall", "-Wno-unused-result", "-pthread",
 ]
 HOSTFLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall"]
 
@@ -48,17 +49,19 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libmpoevo.so (always rebuilds). Returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    objs = []
+    cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *HIPFLAGS, "-c", "-o", obj, os.path.join(CSRC, src)])
+        cmds.append([hipcc, *HIPFLAGS, "-c", "-o", obj, os.path.join(CSRC, src)])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *HOSTFLAGS, "-c", "-o", obj, os.path.join(CSRC, src)])
+        cmds.append(["g++", *HOSTFLAGS, "-c", "-o", obj, os.path.join(CSRC, src)])
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        list(ex.map(_run, cmds))  # re-raises the first failure
     tmp = OUT + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs,
           "-Wl,-Bsymbolic", "-Wl,--no-undefined"])
     os.replace(tmp, OUT)
     if verbose:

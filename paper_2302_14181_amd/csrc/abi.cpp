@@ -5,6 +5,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_set>
+#include <vector>
 
 #include "internal.h"
 
@@ -89,6 +91,19 @@ int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes)
         return fail(nullptr, MPOEVO_ESHAPE, "step: d * Dmax exceeds MPOEVO_SVD_MAX_DIM");
       *bytes = mpoevo::step_ws(dims[0], dims[1], dims[2], dims[3], prec);
       return MPOEVO_OK;
+    case MPOEVO_CALL_STEP_BATCHED: {
+      const int n = dims[0];
+      if (n < 1 || n > MPOEVO_MAX_CHAINS) return fail(nullptr, MPOEVO_EINVAL, "step_batched: n must be in 1..MPOEVO_MAX_CHAINS");
+      for (int c = 0; c < n; ++c) {
+        const int* dc = dims + 1 + 4 * c;
+        if (dc[0] < 2 || dc[1] < 1 || dc[2] < 1 || dc[3] < 1)
+          return fail(nullptr, MPOEVO_ESHAPE, "step_batched: need L >= 2, d, Dmax, wmax >= 1 per chain");
+        if ((long)dc[1] * dc[2] > MPOEVO_SVD_MAX_DIM)
+          return fail(nullptr, MPOEVO_ESHAPE, "step_batched: d * Dmax exceeds MPOEVO_SVD_MAX_DIM");
+      }
+      *bytes = mpoevo::step_batched_ws(n, dims + 1, prec);
+      return MPOEVO_OK;
+    }
     case MPOEVO_CALL_EXPECTATION:
       if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || dims[3] < 1)
         return fail(nullptr, MPOEVO_ESHAPE, "expectation: need L, d, Dmax, wmax >= 1");
@@ -156,32 +171,72 @@ int mpoevo_check_solver(mpoevo_handle h, int* max_sweeps) {
   return rc;
 }
 
+namespace {
+// Checks one chain's arguments of step / step_batched; on success *wmax is its largest MPO bond.
+int check_chain(mpoevo::Context* ctx, const std::string& who, const mpoevo_mps* mps,
+                const mpoevo_mpo* mpo, int* wmax) {
+  if (!mps || !mpo || !mps->bond_dim || !mps->site || !mpo->w || !mpo->site)
+    return fail(ctx, MPOEVO_EINVAL, who + ": NULL argument");
+  const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
+  if (L < 2 || d < 1 || Dmax < 1 || mpo->L != L || mpo->d != d)
+    return fail(ctx, MPOEVO_ESHAPE, who + ": need L >= 2 and matching L, d of MPS and MPO");
+  if ((long)d * Dmax > MPOEVO_SVD_MAX_DIM) return fail(ctx, MPOEVO_ESHAPE, who + ": d * Dmax exceeds MPOEVO_SVD_MAX_DIM");
+  if (mps->bond_dim[0] != 1 || mps->bond_dim[L] != 1) return fail(ctx, MPOEVO_ESHAPE, who + ": boundary bonds must be 1");
+  *wmax = 0;
+  for (int i = 0; i <= L; ++i) {
+    if (i > 0 && i < L && (mps->bond_dim[i] < 1 || mps->bond_dim[i] > Dmax))
+      return fail(ctx, MPOEVO_ESHAPE, who + ": MPS bond dimension outside 1..Dmax");
+    if (mpo->w[i] < 1) return fail(ctx, MPOEVO_ESHAPE, who + ": MPO bond dimension < 1");
+    if (mpo->w[i] > *wmax) *wmax = mpo->w[i];
+  }
+  for (int i = 0; i < L; ++i)
+    if (!mps->site[i] || !mpo->site[i]) return fail(ctx, MPOEVO_EINVAL, who + ": NULL site pointer");
+  return MPOEVO_OK;
+}
+
+int check_opts(mpoevo::Context* ctx, const std::string& who, const mpoevo_step_opts* opts) {
+  if (!opts) return fail(ctx, MPOEVO_EINVAL, who + ": NULL argument");
+  if (!valid_prec(opts->prec)) return fail(ctx, MPOEVO_EINVAL, who + ": unknown precision");
+  if (opts->nsweeps < 1 || opts->nsweeps > 4) return fail(ctx, MPOEVO_EINVAL, who + ": nsweeps must be 1..4");
+  if (!(opts->cutoff >= 0.0) || opts->cutoff >= 1.0) return fail(ctx, MPOEVO_EINVAL, who + ": cutoff must be in [0, 1)");
+  return MPOEVO_OK;
+}
+}  // namespace
+
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
          mpoevo_step_stats* stats, void* workspace, size_t workspace_bytes, void* stream) {
   if (!h) return fail(nullptr, MPOEVO_EINVAL, "step: NULL handle");
   auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
-  if (!mps || !mpo || !opts || !mps->bond_dim || !mps->site || !mpo->w || !mpo->site)
-    return fail(ctx, MPOEVO_EINVAL, "step: NULL argument");
-  if (!valid_prec(opts->prec)) return fail(ctx, MPOEVO_EINVAL, "step: unknown precision");
-  if (opts->nsweeps < 1 || opts->nsweeps > 4) return fail(ctx, MPOEVO_EINVAL, "step: nsweeps must be 1..4");
-  if (!(opts->cutoff >= 0.0) || opts->cutoff >= 1.0) return fail(ctx, MPOEVO_EINVAL, "step: cutoff must be in [0, 1)");
-  const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
-  if (L < 2 || d < 1 || Dmax < 1 || mpo->L != L || mpo->d != d)
-    return fail(ctx, MPOEVO_ESHAPE, "step: need L >= 2 and matching L, d of MPS and MPO");
-  if ((long)d * Dmax > MPOEVO_SVD_MAX_DIM) return fail(ctx, MPOEVO_ESHAPE, "step: d * Dmax exceeds MPOEVO_SVD_MAX_DIM");
-  if (mps->bond_dim[0] != 1 || mps->bond_dim[L] != 1) return fail(ctx, MPOEVO_ESHAPE, "step: boundary bonds must be 1");
   int wmax = 0;
-  for (int i = 0; i <= L; ++i) {
-    if (i > 0 && i < L && (mps->bond_dim[i] < 1 || mps->bond_dim[i] > Dmax))
-      return fail(ctx, MPOEVO_ESHAPE, "step: MPS bond dimension outside 1..Dmax");
-    if (mpo->w[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "step: MPO bond dimension < 1");
-    if (mpo->w[i] > wmax) wmax = mpo->w[i];
-  }
-  for (int i = 0; i < L; ++i)
-    if (!mps->site[i] || !mpo->site[i]) return fail(ctx, MPOEVO_EINVAL, "step: NULL site pointer");
-  if (workspace_bytes < mpoevo::step_ws(L, d, Dmax, wmax, opts->prec) || !workspace)
+  if (int rc = check_opts(ctx, "step", opts); rc != MPOEVO_OK) return rc;
+  if (int rc = check_chain(ctx, "step", mps, mpo, &wmax); rc != MPOEVO_OK) return rc;
+  if (workspace_bytes < mpoevo::step_ws(mps->L, mps->d, mps->Dmax, wmax, opts->prec) || !workspace)
     return fail(ctx, MPOEVO_ENOMEM, "step: workspace too small");
   return mpoevo::step_dev(*ctx, mps, mpo, opts, stats, workspace, workspace_bytes, stream);
+}
+
+int step_batched(mpoevo_handle h, int n, mpoevo_mps* mps, const mpoevo_mpo* mpo,
+                 const mpoevo_step_opts* opts, mpoevo_step_stats* stats, void* workspace,
+                 size_t workspace_bytes, void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "step_batched: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (n < 1 || n > MPOEVO_MAX_CHAINS) return fail(ctx, MPOEVO_EINVAL, "step_batched: n must be in 1..MPOEVO_MAX_CHAINS");
+  if (!mps || !mpo) return fail(ctx, MPOEVO_EINVAL, "step_batched: NULL argument");
+  if (int rc = check_opts(ctx, "step_batched", opts); rc != MPOEVO_OK) return rc;
+  std::vector<int> dims(4 * (size_t)n);
+  std::unordered_set<const void*> seen;  // every site buffer and bond array belongs to one chain
+  for (int c = 0; c < n; ++c) {
+    int wmax = 0;
+    const std::string who = "step_batched: chain " + std::to_string(c);
+    if (int rc = check_chain(ctx, who, &mps[c], &mpo[c], &wmax); rc != MPOEVO_OK) return rc;
+    bool fresh = seen.insert(mps[c].bond_dim).second;
+    for (int i = 0; i < mps[c].L; ++i) fresh = seen.insert(mps[c].site[i]).second && fresh;
+    if (!fresh) return fail(ctx, MPOEVO_EINVAL, who + ": shares a site buffer or its bond array");
+    dims[4 * c] = mps[c].L; dims[4 * c + 1] = mps[c].d; dims[4 * c + 2] = mps[c].Dmax; dims[4 * c + 3] = wmax;
+  }
+  if (!workspace || workspace_bytes < mpoevo::step_batched_ws(n, dims.data(), opts->prec))
+    return fail(ctx, MPOEVO_ENOMEM, "step_batched: workspace too small");
+  return mpoevo::step_batched_dev(*ctx, n, mps, mpo, opts, stats, workspace, workspace_bytes, stream);
 }
 
 int expectation(mpoevo_handle h, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,

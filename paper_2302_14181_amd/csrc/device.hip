@@ -22,6 +22,8 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <thread>
 #include <vector>
 
 #include "dev_common.h"
@@ -426,8 +428,12 @@ int device_init(Context& ctx) {
 }
 
 void device_fini(Context& ctx) {
+  for (auto& c : ctx.chains) device_fini(*c);
+  ctx.chains.clear();
   if (!ctx.dev) return;
   (void)hipSetDevice(ctx.device);
+  for (void* s : ctx.streams) (void)hipStreamDestroy(static_cast<hipStream_t>(s));
+  ctx.streams.clear();
   for (hipEvent_t ev : ctx.dev->events) (void)hipEventDestroy(ev);
   (void)hipFree(ctx.dev->status);
   delete ctx.dev;
@@ -726,7 +732,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       double2* A = theta;  // m x kcap   (U S)
       double2* B = site_tmp;  // kcap x n (V^dag)
       STEP_TRY(svd_truncate(pl, phi(i), kcap, opts->cutoff, A, B, nullptr, nullptr,
-                            nullptr, nullptr, svdws, ctx.dev->status, st));
+                            nullptr, nullptr, svdws, ctx.dev->status, st, nullptr, nullptr,
+                            nullptr, nullptr, nullptr, ctx.coop_jacobi));
       STEP_TRY(hipMemcpyAsync(phi(i), B, sizeof(double2) * (size_t)kcap * n, hipMemcpyDeviceToDevice, st));
       // phi_{i-1} <- phi_{i-1} . (U S)
       STEP_TRY(absorb_right(phi(i - 1), A, site_tmp2, P[i - 1], d, m, kcap, st, gws));
@@ -779,7 +786,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         double2* wb = warm_for(i, m, n);
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, sweeps_buf + visit, wb, wb));
+                              j1, sweeps_buf + visit, wb, wb, ctx.coop_jacobi));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;
@@ -811,7 +818,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         double2* wb = warm_for(i, m, n);
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, sweeps_buf + visit, wb, wb));
+                              j1, sweeps_buf + visit, wb, wb, ctx.coop_jacobi));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;
@@ -909,6 +916,96 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     std::copy(sig, sig + 5, ctx.warm_sig);
   }
 #undef STEP_TRY
+  return MPOEVO_OK;
+}
+
+// ------------------------------------------------------------------------- batched chains
+namespace {
+constexpr int kBatchStreams = 4;  // worker streams (the hardware queues a process gets by default)
+
+size_t chain_ws(const int* dims, int prec) {  // dims = {L, d, Dmax, wmax}
+  return a256(step_ws(dims[0], dims[1], dims[2], dims[3], prec));
+}
+}  // namespace
+
+size_t step_batched_ws(int n, const int* dims, int prec) {
+  size_t total = 0;
+  for (int c = 0; c < n; ++c) total += chain_ws(dims + 4 * c, prec);
+  return total;
+}
+
+// Independent chains share nothing but the device: each chain runs the single-chain step on
+// one of a few worker streams (host thread per stream, chains taken largest first), so the
+// latency-bound truncations of different chains overlap. Their Jacobi launches are ordinary
+// launches; the number of streams is bounded so that the Jacobi workgroups of all streams fit
+// on three quarters of the compute units at once.
+int step_batched_dev(Context& ctx, int n, mpoevo_mps* mps, const mpoevo_mpo* mpo,
+                     const mpoevo_step_opts* opts, mpoevo_step_stats* stats, void* ws, size_t,
+                     void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  // the chains' inputs may have been written on the caller's stream
+  if (hipError_t e0 = hipStreamSynchronize(static_cast<hipStream_t>(stream)); e0 != hipSuccess)
+    return hip_fail(ctx, e0, "step_batched: stream synchronisation");
+  while ((int)ctx.chains.size() < n) {
+    auto c = std::make_unique<Context>();
+    c->device = ctx.device;
+    c->coop_jacobi = false;
+    const int rc = device_init(*c);
+    if (rc != MPOEVO_OK) {
+      ctx.err = "step_batched: " + c->err;
+      return rc;
+    }
+    ctx.chains.push_back(std::move(c));
+  }
+  int cus = 0;
+  if (hipError_t e0 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx.device);
+      e0 != hipSuccess)
+    return hip_fail(ctx, e0, "hipDeviceGetAttribute(compute units)");
+  std::vector<size_t> off(n + 1, 0);
+  std::vector<double> cost(n);
+  int maxgrid = 1;
+  for (int c = 0; c < n; ++c) {
+    int wmax = 0;
+    for (int i = 0; i <= mpo[c].L; ++i) wmax = std::max(wmax, mpo[c].w[i]);
+    const int dims[4] = {mps[c].L, mps[c].d, mps[c].Dmax, wmax};
+    off[c + 1] = off[c] + chain_ws(dims, opts->prec);
+    const int side = mps[c].d * mps[c].Dmax;
+    maxgrid = std::max(maxgrid, svd_grid(svd_plan(side, side, MPOEVO_LEFT, true)));
+    cost[c] = (double)mps[c].L * side * side * side;
+  }
+  const int nstreams = std::max(1, std::min({kBatchStreams, n, (3 * cus / 4) / maxgrid}));
+  while ((int)ctx.streams.size() < nstreams) {
+    hipStream_t s = nullptr;
+    if (hipError_t e0 = hipStreamCreateWithFlags(&s, hipStreamNonBlocking); e0 != hipSuccess)
+      return hip_fail(ctx, e0, "hipStreamCreateWithFlags");
+    ctx.streams.push_back(s);
+  }
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::atomic<int> next{0};
+  std::vector<int> rc(n, MPOEVO_OK);
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  auto worker = [&](int t) {
+    for (;;) {
+      const int j = next.fetch_add(1);
+      if (j >= n) break;
+      const int c = order[j];
+      rc[c] = step_dev(*ctx.chains[c], &mps[c], &mpo[c], opts, stats ? &stats[c] : nullptr,
+                       base + off[c], off[c + 1] - off[c], ctx.streams[t]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nstreams; ++t) pool.emplace_back(worker, t);
+  worker(0);
+  for (auto& th : pool) th.join();
+  ctx.max_sweeps = 0;
+  for (int c = 0; c < n; ++c) ctx.max_sweeps = std::max(ctx.max_sweeps, ctx.chains[c]->max_sweeps);
+  for (int c = 0; c < n; ++c)
+    if (rc[c] != MPOEVO_OK) {
+      ctx.err = "step_batched: chain " + std::to_string(c) + ": " + ctx.chains[c]->err;
+      return rc[c];
+    }
   return MPOEVO_OK;
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstddef>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,13 @@ struct Context {
   int warm_sig[5] = {0, 0, 0, 0, 0};
   unsigned long long warm_token = 0;  // also stored in the workspace by the step that wrote them
   std::vector<int> warm_dim;
+  // Jacobi launches: cooperative on a handle; ordinary (overlapping other streams) on the
+  // per-chain contexts of step_batched, which bound the workgroups in flight themselves.
+  bool coop_jacobi = true;
+  // step_batched: one context per chain index (own status words and preconditioner state) and
+  // the worker streams (hipStream_t, default priority), created on first use.
+  std::vector<std::unique_ptr<Context>> chains;
+  std::vector<void*> streams;
 };
 
 int device_init(Context& ctx);
@@ -53,5 +61,9 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
              mpoevo_step_stats* stats, void* ws, size_t ws_bytes, void* stream);
 int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
                     void* out, void* ws, size_t ws_bytes, void* stream);
+size_t step_batched_ws(int n, const int* dims, int prec);  // dims: {L, d, Dmax, wmax} per chain
+int step_batched_dev(Context& ctx, int n, mpoevo_mps* mps, const mpoevo_mpo* mpo,
+                     const mpoevo_step_opts* opts, mpoevo_step_stats* stats, void* ws,
+                     size_t ws_bytes, void* stream);
 
 }  // namespace mpoevo

@@ -51,12 +51,20 @@ hipError_t svd_configure();
 // status words. Writes A_out (m x kcap), B_out (kcap x n) with kcap = min(Dmax, m, n).
 // Optional profiling: the Jacobi launch is bracketed by ev0 / ev1 (both or neither) and its
 // sweep count is stored at sweeps_dev (device int, nullable).
+// coop: launch the Jacobi kernel cooperatively (the runtime then guarantees that its workgroups
+// are resident together, and runs it alone on the device). With coop false it is an ordinary
+// launch that can overlap work on other streams; the caller must keep the workgroups of all
+// Jacobi launches in flight at once within what the device holds together (one per compute
+// unit), and the kernel's bounded waits turn a violation into a barrier-timeout status.
 hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double cutoff,
                         double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                         int* sweeps_dev = nullptr, const double2* warm = nullptr,
-                        double2* basis_out = nullptr);
+                        double2* basis_out = nullptr, bool coop = true);
+
+// Workgroups of the Jacobi launch of a plan.
+inline int svd_grid(const SvdPlan& p) { return p.nb / 2; }
 
 // Algorithmic flops of one Jacobi sweep of a plan (36 mx per column pair visit: 16 mx for the
 // three inner products, 20 mx for the rotation of the two columns).

@@ -116,20 +116,6 @@ __device__ inline double dpp_move(double v) {
 
 // Sum over the 64 lanes, identical in every lane (each step adds the same two numbers in both
 // partner lanes): pair lanes within quads, then halves of 8, rows of 16, then across rows.
-__device__ inline void wave_sum4(double& a, double& b, double& c, double& d) {
-  a += dpp_move<0xB1>(a); b += dpp_move<0xB1>(b); c += dpp_move<0xB1>(c); d += dpp_move<0xB1>(d);
-  a += dpp_move<0x4E>(a); b += dpp_move<0x4E>(b); c += dpp_move<0x4E>(c); d += dpp_move<0x4E>(d);
-  a += dpp_move<0x141>(a); b += dpp_move<0x141>(b); c += dpp_move<0x141>(c); d += dpp_move<0x141>(d);
-  a += dpp_move<0x140>(a); b += dpp_move<0x140>(b); c += dpp_move<0x140>(c); d += dpp_move<0x140>(d);
-#pragma unroll
-  for (int off = 16; off <= 32; off <<= 1) {
-    a += __shfl_xor(a, off, 64);
-    b += __shfl_xor(b, off, 64);
-    c += __shfl_xor(c, off, 64);
-    d += __shfl_xor(d, off, 64);
-  }
-}
-
 __device__ inline void wave_sum2(double& a, double& b) {
   a += dpp_move<0xB1>(a); b += dpp_move<0xB1>(b);
   a += dpp_move<0x4E>(a); b += dpp_move<0x4E>(b);
@@ -717,7 +703,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
-                        const double2* warm, double2* basis_out) {
+                        const double2* warm, double2* basis_out, bool coop) {
   if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx))
     return hipErrorInvalidConfiguration;
   SvdWs w = carve(p, ws);
@@ -758,8 +744,11 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     int* swp = sweeps_dev;
     void* args[] = {&pp, &ww, &tt, &stp, &swp};
     if (ev0) MPOEVO_HIP_TRY(hipEventRecord(ev0, st));
-    MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(jacobi_for(p), dim3(p.nb / 2), dim3(p.threads), args,
-                                              (unsigned)p.lds, st));
+    if (coop)
+      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(jacobi_for(p), dim3(p.nb / 2), dim3(p.threads), args,
+                                                (unsigned)p.lds, st));
+    else
+      MPOEVO_HIP_TRY(hipLaunchKernel(jacobi_for(p), dim3(p.nb / 2), dim3(p.threads), args, p.lds, st));
     if (ev1) MPOEVO_HIP_TRY(hipEventRecord(ev1, st));
   }
   hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, w,

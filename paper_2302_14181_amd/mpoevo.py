@@ -20,7 +20,8 @@ OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESOLVER, ENONFINITE, EUNSUPPORTED = 0, -1, -2,
 FP64, FP32, BF16X3 = 0, 1, 2
 V1_EXACT, V2_EXTENDED = 0, 1
 LEFT, RIGHT = 0, 1
-CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP, CALL_EXPECTATION = 0, 1, 2, 3, 4
+CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP, CALL_EXPECTATION, CALL_STEP_BATCHED = 0, 1, 2, 3, 4, 5
+MAX_CHAINS = 4096
 SVD_MAX_DIM = 1024
 
 
@@ -85,8 +86,11 @@ def load(path: str = LIB_PATH):
                          ctypes.POINTER(_Stats), vp, sz, vp]
     lib.expectation.argtypes = [vp, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO), ctypes.c_int, ctypes.c_int,
                                 vp, vp, sz, vp]
+    lib.step_batched.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO),
+                                 ctypes.POINTER(_Opts), ctypes.POINTER(_Stats), vp, sz, vp]
     for name in ("mpoevo_create", "mpoevo_destroy", "mpoevo_check_solver", "mpo_build",
-                 "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step", "expectation"):
+                 "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step", "expectation",
+                 "step_batched"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -95,7 +99,7 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     return ["mpoevo_create", "mpoevo_destroy", "mpoevo_last_error", "mpoevo_version", "mpo_build",
             "env_update", "local_apply", "truncate", "mpoevo_check_solver", "step",
-            "expectation", "mpoevo_workspace_size"]
+            "expectation", "step_batched", "mpoevo_workspace_size"]
 
 
 def _check(rc: int, handle=None):
@@ -332,12 +336,54 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
                        _ptr(workspace), workspace.numel(), _stream(stream)), h)
     mps.bond = [bond[i] for i in range(mps.L + 1)]
+    return _stats_of(st, profile)
+
+
+def _stats_of(st, profile: bool) -> StepStats:
     prof = None
     if profile:
         prof = {k: getattr(st, k) for k in ("t_jacobi_ms", "jacobi_gflop", "n_jacobi", "t_gemm_ms",
                                             "gemm_gflop", "n_gemm", "t_wmix_ms", "wmix_gbyte", "n_wmix")}
     return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
                      st.svd_sweeps_max, prof, st.svd_sweeps_total, tuple(st.svd_sweeps_hist))
+
+
+def step_batched_workspace(chains, mpos, prec: int):
+    dims = [len(chains)]
+    for mps, mpo in zip(chains, mpos):
+        dims += [mps.L, mps.d, mps.Dmax, max(mpo.w)]
+    return _workspace(workspace_size(CALL_STEP_BATCHED, dims, prec), chains[0].buf[0].device)
+
+
+def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cutoff: float = 1e-14,
+                 input_right_canonical: bool = False, workspace=None, stream=None, profile: bool = False,
+                 svd_cold_start: bool = False):
+    """One time step of every chain (lists of DeviceMPS and DeviceMPO of equal length), advanced
+    concurrently by the library; each MPS is updated in place. Returns one StepStats per chain."""
+    if len(chains) != len(mpos) or not chains:
+        raise MpoevoError(EINVAL, "step_batched: need equal, non-empty lists of chains and MPOs")
+    if workspace is None:
+        workspace = step_batched_workspace(chains, mpos, prec)
+    n = len(chains)
+    keep = []  # ctypes arrays referenced by the structures
+    cms = (_MPS * n)()
+    cws = (_MPO * n)()
+    for c, (mps, mpo) in enumerate(zip(chains, mpos)):
+        bond = _iarr(mps.bond)
+        sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
+        w = _iarr(mpo.w)
+        wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
+        keep += [bond, sites, w, wsites]
+        cms[c] = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
+        cws[c] = _MPO(mpo.L, mpo.d, w, wsites)
+    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), int(bool(profile)),
+                 int(bool(svd_cold_start)))
+    st = (_Stats * n)()
+    _check(load().step_batched(h.ptr, n, cms, cws, ctypes.byref(opts), st, _ptr(workspace),
+                               workspace.numel(), _stream(stream)), h)
+    for c, mps in enumerate(chains):
+        mps.bond = [keep[4 * c][i] for i in range(mps.L + 1)]
+    return [_stats_of(st[c], profile) for c in range(n)]
 
 
 def expectation(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, left: int = 0, right: int = 0,

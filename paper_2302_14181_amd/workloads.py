@@ -159,3 +159,17 @@ def env_microbench_inputs(seed: int = 0, D: int = 256, d: int = 2, w: int = 8):
     N = complex_normal(rng, (D, d, D))
     W = complex_normal(rng, (w, d, d, w))
     return E, M, N, W
+
+
+def batched_tfim_chains(seed: int = 2, n: int = 64):
+    """The independent-chain batch: per chain (g, L, D) with g ~ U(0.5, 1.5), L drawn from
+    {32, 64, 96, 128} and D from {32, 64, 128, 256}, uniformly and independently, drawn per chain
+    in that order from numpy's default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        g = float(rng.uniform(0.5, 1.5))
+        L = int(rng.choice([32, 64, 96, 128]))
+        D = int(rng.choice([32, 64, 128, 256]))
+        out.append((g, L, D))
+    return out
