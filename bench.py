@@ -26,8 +26,13 @@ J(r) = r^-2 as six exponentials (tests/golden/lr_fit_K6.json), g = 1, L = 100, o
 W warm-up steps of the same trajectory (defaults K = 2, W = 1), FP32 and FP64 paths; the CPU oracle
 is timed on one bond visit of that workload and scaled to a step (labelled extrapolated).
 
+With --workload batched: 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128},
+D in {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up, K steps (default 3)
+advanced together by step_batched, against the same steps taken chain by chain; the oracle checks
+and times the first step of the first four chains.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64] [--workload quench|lr3]
+                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched]
 """
 from __future__ import annotations
 
@@ -194,6 +199,86 @@ def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
     print(json.dumps(line))
 
 
+def run_batched(args, torch, mp, wl, h):
+    """K steps of 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128}, D in
+    {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up: step_batched
+    against the same chains stepped one by one, and the oracle on the first chains' first step."""
+    chains = wl.batched_tfim_chains(2, 64)
+    steps = args.steps if args.steps != 100 else 3
+    prec = prec_of(mp, args.prec)
+    mpos = {}
+    for g, Lc, _ in chains:
+        if g not in mpos:
+            H = wl.tfim(g)
+            mpos[g] = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -1j * TAU, mp.V2_EXTENDED)[0]
+    dws = [mp.DeviceMPO([mpos[g]] * Lc) for g, Lc, _ in chains]
+
+    def trajectory(batched):
+        dms = [mp.DeviceMPS(wl.all_up(Lc), Dmax=Dc) for _, Lc, Dc in chains]
+        if batched:
+            ws = mp.step_batched_workspace(dms, dws, prec)
+        else:
+            ws = [mp.step_workspace(dm, dw, prec) for dm, dw in zip(dms, dws)]
+        torch.cuda.synchronize()
+        ms, first = [], None
+        for k in range(steps):
+            t0 = time.perf_counter()
+            if batched:
+                st = mp.step_batched(h, dms, dws, prec=prec, workspace=ws, input_right_canonical=k > 0)
+            else:
+                st = [mp.step(h, dm, dw, prec=prec, workspace=w_, input_right_canonical=k > 0)
+                      for dm, dw, w_ in zip(dms, dws, ws)]
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            if k == 0:
+                first = [dm.to_numpy() for dm in dms[:4]]
+        bonds = [max(dm.bond) for dm in dms]
+        gflop = sum(x.gflop for x in st)
+        del ws, dms
+        torch.cuda.empty_cache()
+        return ms, first, bonds, gflop
+
+    ms_b, first_b, bonds, gflop = trajectory(True)
+    ms_1, first_1, _, _ = trajectory(False)
+    sec = float(np.sum(ms_b)) / 1e3 / steps
+    parity, cpu = None, None
+    if not args.no_cpu:
+        from oracle import fit as ofit
+        import threadpoolctl
+        parity = []
+        t0 = time.perf_counter()
+        for c in range(4):
+            g, Lc, Dc = chains[c]
+            ref, _ = ofit.fit_step(wl.all_up(Lc), mpos[g], Dmax=Dc, nsweeps=2)
+            parity.append({"chain": c, "L": Lc, "D": Dc, "g": g,
+                           "step1_infidelity": float(1.0 - abs(ofit.overlap(first_b[c], ref)) ** 2),
+                           "batched_vs_one_by_one_max_abs": float(max(np.max(np.abs(a - b)) for a, b in
+                                                                      zip(first_b[c], first_1[c])))})
+        cpu_s = time.perf_counter() - t0
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] + [1])
+        cpu = {"value": cpu_s, "unit": "s for step 1 of chains 0-3", "cores": int(threads), "kind": "oracle",
+               "sample": f"the oracle's first step (from all-up) of the first four chains, numpy complex128 with "
+                         f"{threads} BLAS threads; the GPU batch takes steps_ms[0] for all 64 chains"}
+    line = {
+        "metric": "s per time step & TFLOP/s at D=256: FP32-MFMA grouped vs plain FP64, fidelity",
+        "value": sec, "unit": "s per time step (64 chains)", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[args.prec], "data": "synthetic",
+        "config": {"workload": "64 independent TFIM chains, g ~ U(0.5,1.5), L in {32,64,96,128}, "
+                               "D in {32,64,128,256} (seed 2), order-2 extended MPO (w=3), tau=0.1, "
+                               f"2 sweeps, all-up start, steps 1..{steps}",
+                   "chains": len(chains), "tau": TAU, "order": 2},
+        "steps_ms_batched": ms_b, "steps_ms_one_by_one": ms_1,
+        "batched_speedup": float(np.sum(ms_1) / np.sum(ms_b)),
+        "chain_steps_per_s": len(chains) * steps / (float(np.sum(ms_b)) / 1e3),
+        "last_step_gflop": gflop, "max_bond_per_chain_end": bonds,
+        "parity_vs_oracle": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,7 +288,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--workload", choices=["quench", "lr3"], default="quench")
+    ap.add_argument("--workload", choices=["quench", "lr3", "batched"], default="quench")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the time step of a single chain is sequential across "
@@ -217,8 +302,8 @@ def main():
 
     torch.cuda.set_device(0)
     h = mp.Handle(0)
-    if args.workload == "lr3":
-        run_lr3(args, torch, mp, wl, h)
+    if args.workload in ("lr3", "batched"):
+        (run_lr3 if args.workload == "lr3" else run_batched)(args, torch, mp, wl, h)
         h.close()
         return
     prec = prec_of(mp, args.prec)

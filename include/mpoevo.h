@@ -238,7 +238,10 @@ int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_s
  * kernels run; only their interleaving across chains differs). The per-chain truncation
  * preconditioners persist per chain index in the workspace, as for step.
  * Synchronous: synchronises `stream` on entry (the inputs may have been written on it), runs the
- * chains on the handle's own worker streams and returns when every chain is done.
+ * chains on the handle's own worker streams and returns when every chain is done. The number of
+ * worker streams is 4 (the hardware queues a process gets by default), or MPOEVO_BATCH_STREAMS
+ * (1..16) from the environment, lowered if needed so that the truncation kernels of all streams
+ * fit on three quarters of the device's compute units at once.
  * Workspace: mpoevo_workspace_size(MPOEVO_CALL_STEP_BATCHED, dims = {n, then L, d, Dmax, wmax of
  * each chain}, prec): the chains' step workspaces, 256-byte aligned, in chain order.
  * Errors: as for step (the message names the chain); EINVAL also for n outside

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -921,7 +922,13 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
 
 // ------------------------------------------------------------------------- batched chains
 namespace {
-constexpr int kBatchStreams = 4;  // worker streams (the hardware queues a process gets by default)
+// Worker streams: by default the number of hardware queues a process gets (4); the environment
+// variable MPOEVO_BATCH_STREAMS (1..16) overrides it.
+int batch_streams() {
+  const char* v = std::getenv("MPOEVO_BATCH_STREAMS");
+  const int n = v ? std::atoi(v) : 0;
+  return (n >= 1 && n <= 16) ? n : 4;
+}
 
 size_t chain_ws(const int* dims, int prec) {  // dims = {L, d, Dmax, wmax}
   return a256(step_ws(dims[0], dims[1], dims[2], dims[3], prec));
@@ -973,7 +980,7 @@ int step_batched_dev(Context& ctx, int n, mpoevo_mps* mps, const mpoevo_mpo* mpo
     maxgrid = std::max(maxgrid, svd_grid(svd_plan(side, side, MPOEVO_LEFT, true)));
     cost[c] = (double)mps[c].L * side * side * side;
   }
-  const int nstreams = std::max(1, std::min({kBatchStreams, n, (3 * cus / 4) / maxgrid}));
+  const int nstreams = std::max(1, std::min({batch_streams(), n, (3 * cus / 4) / maxgrid}));
   while ((int)ctx.streams.size() < nstreams) {
     hipStream_t s = nullptr;
     if (hipError_t e0 = hipStreamCreateWithFlags(&s, hipStreamNonBlocking); e0 != hipSuccess)

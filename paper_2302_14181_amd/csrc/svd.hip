@@ -116,13 +116,34 @@ __device__ inline double dpp_move(double v) {
 
 // Sum over the 64 lanes, identical in every lane (each step adds the same two numbers in both
 // partner lanes): pair lanes within quads, then halves of 8, rows of 16, then across rows.
+// x + (x of the partner row, rows paired 0-1 and 2-3) in every lane: v_permlane16_swap exchanges
+// the odd rows of one operand with the even rows of the other, so swapping x with itself leaves
+// the two rows of a pair in the two results, whose sum is the pair's sum.
+__device__ inline double row_pair_sum(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = static_cast<unsigned>(b), hi = static_cast<unsigned>(b >> 32);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h[0]) << 32) | l[0])) +
+         __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h[1]) << 32) | l[1]));
+}
+// x + (x of the other half of the wave) in every lane (v_permlane32_swap, the same way).
+__device__ inline double half_pair_sum(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = static_cast<unsigned>(b), hi = static_cast<unsigned>(b >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h[0]) << 32) | l[0])) +
+         __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h[1]) << 32) | l[1]));
+}
+
 __device__ inline void wave_sum2(double& a, double& b) {
   a += dpp_move<0xB1>(a); b += dpp_move<0xB1>(b);
   a += dpp_move<0x4E>(a); b += dpp_move<0x4E>(b);
   a += dpp_move<0x141>(a); b += dpp_move<0x141>(b);
   a += dpp_move<0x140>(a); b += dpp_move<0x140>(b);
-  a += __shfl_xor(a, 16, 64); b += __shfl_xor(b, 16, 64);
-  a += __shfl_xor(a, 32, 64); b += __shfl_xor(b, 32, 64);
+  a = row_pair_sum(a); b = row_pair_sum(b);
+  a = half_pair_sum(a); b = half_pair_sum(b);
 }
 
 template <int R>
@@ -133,17 +154,11 @@ __device__ inline double sq_norm_part(const double2 (&u)[R]) {
   return a;
 }
 
-// 1/sqrt(x) and 1/x to full double precision: hardware estimate plus Newton steps.
+// 1/sqrt(x) to full double precision: the hardware estimate plus two Newton steps.
 __device__ inline double rsqrt_d(double x) {
   double r = __builtin_amdgcn_rsq(x);
   r = r * fma(-0.5 * x * r, r, 1.5);
   r = r * fma(-0.5 * x * r, r, 1.5);
-  return r;
-}
-__device__ inline double rcp_d(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = r * fma(-x, r, 2.0);
-  r = r * fma(-x, r, 2.0);
   return r;
 }
 
@@ -249,16 +264,16 @@ __device__ inline int rr_owner(int r, int blk, int n) {
 }
 
 // One Jacobi rotation of the column pair (u, v) held in registers (RMAX rows per lane), given
-// their squared norms a = |u|^2, bb = |v|^2: the inner product, the rotation that makes the pair
-// orthogonal, applied in place (and to the pair's columns of the accumulated rotation, qu and
-// qv, when ACC). The norms follow the rotation exactly in exact arithmetic, |u'|^2 = a - t |g|,
-// |v'|^2 = bb + t |g|; when either loses more than 31/32 of its value (cancellation) both are
-// recomputed from the columns. Returns whether the pair was rotated; records the pair's relative
-// inner product in *wg_max.
+// their squared norms a = |u|^2, bb = |v|^2: the inner product g = u^dag v, the rotation that
+// makes the pair orthogonal, applied in place (and to the pair's columns of the accumulated
+// rotation, qu and qv, when ACC). The norms follow the rotation exactly in exact arithmetic,
+// |u'|^2 = a - t |g|, |v'|^2 = bb + t |g|; when either loses more than 31/32 of its value
+// (cancellation) both are recomputed from the columns. Returns whether the pair was rotated;
+// raises wave_max (wave-uniform) to the pair's squared relative inner product |g|^2 / (a bb).
 template <int RMAX, bool ACC>
 __device__ inline bool jacobi_pair(double2 (&u)[RMAX], double2 (&v)[RMAX], double2 (&qu)[RMAX],
                                    double2 (&qv)[RMAX], double& a, double& bb, int lane,
-                                   double floor2, double tol2, unsigned* wg_max) {
+                                   double floor2, double tol2, double& wave_max) {
   double gr = 0.0, gi = 0.0;
 #pragma unroll
   for (int t = 0; t < RMAX; ++t) {
@@ -266,38 +281,37 @@ __device__ inline bool jacobi_pair(double2 (&u)[RMAX], double2 (&v)[RMAX], doubl
     gi = fma(u[t].x, v[t].y, fma(-u[t].y, v[t].x, gi));
   }
   wave_sum2(gr, gi);
-  // Rotation parameters without divisions or square roots: |gamma|^2 = g2, r = 1/|gamma|,
-  // phase e = conj(gamma) r, zeta = (|v|^2 - |u|^2) / (2 |gamma|),
-  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = t c.
-  const double g2 = fma(gr, gr, gi * gi);
+  const double g2 = fma(gr, gr, gi * gi);  // |g|^2
   const double ab = a * bb;
   const bool live = fmin(a, bb) > floor2;
-  if (live && lane == 0 && ab > 0.0)
-    atomicMax(wg_max, __float_as_uint(sqrtf((float)fmin(g2 * rcp_d(ab), 1.0))));
+  if (live && ab > 0.0) wave_max = fmax(wave_max, g2 * __builtin_amdgcn_rcp(ab));
   if (!(live && g2 > tol2 * ab)) return false;
-  const double r = rsqrt_d(g2);
-  const double zeta = 0.5 * (bb - a) * r;
-  const double q = (zeta * zeta < 1e300) ? (1.0 + zeta * zeta) * rsqrt_d(1.0 + zeta * zeta) : fabs(zeta);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_d(fabs(zeta) + q);
-  const double c = rsqrt_d(1.0 + t * t), s = t * c;
-  const double er = gr * r, ei = -gi * r;  // conj(gamma) / |gamma|
+  // The rotation [[c, -s e], [s conj(e), c]] (e = conj(g) / |g|) with tan(2 theta) =
+  // 2 |g| / (bb - a), |theta| <= pi/4, from two reciprocal square roots and no division:
+  // rho = sqrt((bb - a)^2 + 4 |g|^2), cos^2 = (1 + |bb - a| / rho) / 2,
+  // s e = sr conj(g) and s conj(e) = sr g with sr = sign(bb - a) / (rho cos), t |g| = sr |g|^2 / cos.
+  const double dab = bb - a;
+  const double r1 = rsqrt_d(fma(dab, dab, 4.0 * g2));
+  const double c2 = fma(0.5 * fabs(dab), r1, 0.5);
+  const double rc = rsqrt_d(c2);
+  const double c = c2 * rc;
+  const double sr = (dab >= 0.0 ? r1 : -r1) * rc;
+  const double pr = sr * gr, pi = sr * gi;
 #pragma unroll
   for (int tt = 0; tt < RMAX; ++tt) {
-    const double evx = er * v[tt].x - ei * v[tt].y, evy = er * v[tt].y + ei * v[tt].x;
-    const double2 un{c * u[tt].x - s * evx, c * u[tt].y - s * evy};
-    v[tt] = double2{s * u[tt].x + c * evx, s * u[tt].y + c * evy};
+    const double2 un{c * u[tt].x - (pr * v[tt].x + pi * v[tt].y), c * u[tt].y - (pr * v[tt].y - pi * v[tt].x)};
+    v[tt] = double2{(pr * u[tt].x - pi * u[tt].y) + c * v[tt].x, (pr * u[tt].y + pi * u[tt].x) + c * v[tt].y};
     u[tt] = un;
   }
   if (ACC) {
 #pragma unroll
     for (int tt = 0; tt < RMAX; ++tt) {
-      const double evx = er * qv[tt].x - ei * qv[tt].y, evy = er * qv[tt].y + ei * qv[tt].x;
-      const double2 un{c * qu[tt].x - s * evx, c * qu[tt].y - s * evy};
-      qv[tt] = double2{s * qu[tt].x + c * evx, s * qu[tt].y + c * evy};
+      const double2 un{c * qu[tt].x - (pr * qv[tt].x + pi * qv[tt].y), c * qu[tt].y - (pr * qv[tt].y - pi * qv[tt].x)};
+      qv[tt] = double2{(pr * qu[tt].x - pi * qu[tt].y) + c * qv[tt].x, (pr * qu[tt].y + pi * qu[tt].x) + c * qv[tt].y};
       qu[tt] = un;
     }
   }
-  const double tg = t * (g2 * r);  // t |gamma|
+  const double tg = sr * g2 * rc;  // t |g|
   const double an = a - tg, bn = bb + tg;
   if (an < 0.03125 * a || bn < 0.03125 * bb) {  // wave-uniform: all lanes hold the same values
     double x = sq_norm_part(u), y = sq_norm_part(v);
@@ -387,6 +401,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
       }
       if (tid == 0) wg_max = 0u;
       __syncthreads();
+      double wave_max = 0.0;  // largest squared relative inner product this wave met (uniform)
       // One wave per pair (blockDim = 64 b). The first round of a sweep holds every block once:
       // it also visits the pairs inside each block; later rounds visit only the b x b pairs
       // across their two blocks, where wave k keeps column k of the first block in registers
@@ -405,7 +420,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
               load_col(qv, qcols + y * nx, lane, nx);
             }
             double na = nrm[x], nb = nrm[y];
-            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, na, nb, lane, floor2, tol2, &wg_max)) {
+            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, na, nb, lane, floor2, tol2, wave_max)) {
               store_col(u, cols + x * mx, lane, mx);
               store_col(v, cols + y * mx, lane, mx);
               if (lane == 0) {
@@ -437,7 +452,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
             load_col(v, cols + y * mx, lane, mx);
             if (ACC) load_col(qv, qcols + y * nx, lane, nx);
             double nb = nrm[y];
-            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, na, nb, lane, floor2, tol2, &wg_max)) {
+            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, na, nb, lane, floor2, tol2, wave_max)) {
               store_col(v, cols + y * mx, lane, mx);
               if (ACC) store_col(qv, qcols + y * nx, lane, nx);
               if (lane == 0) nrm[y] = nb;
@@ -452,6 +467,9 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
         }
         __syncthreads();
       }
+      if (lane == 0 && wave_max > 0.0)
+        atomicMax(&wg_max, __float_as_uint(sqrtf((float)fmin(wave_max, 1.0))));
+      __syncthreads();
       if (wave < p.b) {  // LDS -> global
         double2 u[RMAX], v[RMAX];
         load_col(u, cols + wave * mx, lane, mx);
