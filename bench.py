@@ -272,6 +272,8 @@ def run_batched(args, torch, mp, wl, h):
         "steps_ms_batched": ms_b, "steps_ms_one_by_one": ms_1,
         "batched_speedup": float(np.sum(ms_1) / np.sum(ms_b)),
         "chain_steps_per_s": len(chains) * steps / (float(np.sum(ms_b)) / 1e3),
+        "worker_streams_requested": int(os.environ.get("MPOEVO_BATCH_STREAMS", "4")),
+        "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
         "last_step_gflop": gflop, "max_bond_per_chain_end": bonds,
         "parity_vs_oracle": parity,
         "cpu_baseline": cpu,
@@ -290,6 +292,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--workload", choices=["quench", "lr3", "batched"], default="quench")
     args = ap.parse_args()
+    if args.workload == "batched":
+        # more hardware queues and worker streams let more chains' truncations overlap (read by
+        # the HIP runtime at initialisation and by the library at each batched step)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+        os.environ.setdefault("MPOEVO_BATCH_STREAMS", "8")
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the time step of a single chain is sequential across "
               "bonds and this build has no multi-GPU path (the design notes describe how it would "

@@ -76,6 +76,12 @@ constexpr int kTargetWgs = 512; // split K up to this many workgroups
 constexpr int kMaxSplits = 16;
 constexpr int kMinSplitK = 32;  // complex K per split, at least
 
+// LDS staging: A as rows [m][k] and the expanded B as columns [n][k] (real k), each row of
+// KR values plus 16 bytes of padding (an odd number of 16-byte units, so the 16-byte reads of
+// 16 consecutive rows hit distinct banks). Within each group of G = KT * V real k the values are
+// stored in the order the matrix instruction consumes them: a lane with k offset a (0..KT-1)
+// uses k = KT q + a in its q-th instruction of the group, so position a V + q holds it and the
+// lane fetches the operands of V instructions with one 16-byte read.
 template <class Mf, int WR, int WC, int BK_>
 struct Tile {
   static constexpr int BK = BK_;                      // complex K per stage
@@ -84,12 +90,19 @@ struct Tile {
   static constexpr int BNR = 2 * WC * Mf::NT;         // real columns per workgroup
   static constexpr int BN = BNR / 2;                  // complex columns
   static constexpr int KR = 2 * BK;                   // real k per stage
-  static constexpr int LDA = BM + 4;                  // padded LDS row lengths (elements)
-  static constexpr int LDB = BNR + 4;
+  static constexpr int V = 16 / (int)sizeof(T);       // values per 16-byte read
+  static constexpr int G = Mf::KT * V;                // real k per group (8)
+  static constexpr int PITCH = KR + V;                // LDS row length (elements)
   static constexpr int A_ELEMS = BM * BK / kThreads;   // complex loads per thread
   static constexpr int B_ELEMS = BN * BK / kThreads;
-  static constexpr int LDS_ELEMS = KR * LDA + KR * LDB;
+  static constexpr int LDS_ELEMS = (BM + BNR) * PITCH;
   static_assert(A_ELEMS >= 1 && B_ELEMS >= 1, "tile too small for the staging scheme");
+  static_assert(KR % G == 0 && ((PITCH * (int)sizeof(T) / 16) & 1), "staging layout");
+  // position of real k within its row
+  __device__ static int kpos(int kr) {
+    const int w = kr % G;
+    return kr - w + (w % Mf::KT) * V + w / Mf::KT;
+  }
 };
 
 // splits > 1: the workgroup at blockIdx.z = batch * splits + s covers K in [s kchunk, (s+1)
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
   using T = typename Mf::T;
   using C2 = cx_t<T>;
   using TT = Tile<Mf, WR, WC, BK>;
-  __shared__ T lds[2 * TT::LDS_ELEMS];
+  __shared__ __attribute__((aligned(16))) T lds[2 * TT::LDS_ELEMS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -143,16 +156,19 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
       rb[i] = v;
     }
   };
+  // A' = [re, sgnA im] over real k = 2k, 2k+1; B' holds 2 x 2 real blocks per complex entry:
+  // column 2n = (re, -im'), column 2n+1 = (im', re) over real k = 2k, 2k+1 (im' = sgnB im).
   auto store_tiles = [&](int buf) {
     T* As = lds + buf * TT::LDS_ELEMS;
-    T* Bs = As + TT::KR * TT::LDA;
+    T* Bs = As + TT::BM * TT::PITCH;
 #pragma unroll
     for (int i = 0; i < TT::A_ELEMS; ++i) {
       const int e = tid + i * kThreads;
       int m, k;
       if (AKC) { m = e / BK; k = e % BK; } else { k = e / TT::BM; m = e % TT::BM; }
-      As[(2 * k) * TT::LDA + m] = ra[i].x;
-      As[(2 * k + 1) * TT::LDA + m] = sgnA * ra[i].y;
+      T* row = As + m * TT::PITCH;
+      row[TT::kpos(2 * k)] = ra[i].x;
+      row[TT::kpos(2 * k + 1)] = sgnA * ra[i].y;
     }
 #pragma unroll
     for (int i = 0; i < TT::B_ELEMS; ++i) {
@@ -160,12 +176,13 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
       int k, n;
       if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / BK; k = e % BK; }
       const T re = rb[i].x, im = sgnB * rb[i].y;
-      T* r0 = Bs + (2 * k) * TT::LDB + 2 * n;
-      T* r1 = r0 + TT::LDB;
-      r0[0] = re;
-      r0[1] = im;
-      r1[0] = -im;
-      r1[1] = re;
+      T* c0 = Bs + (2 * n) * TT::PITCH;
+      T* c1 = c0 + TT::PITCH;
+      const int p0 = TT::kpos(2 * k), p1 = TT::kpos(2 * k + 1);
+      c0[p0] = re;
+      c0[p1] = -im;
+      c1[p0] = im;
+      c1[p1] = re;
     }
   };
 
@@ -183,24 +200,29 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
   __syncthreads();
 
   const int arow = Mf::a_row(lane), ak = Mf::a_k(lane);
+  using VecT = T __attribute__((ext_vector_type(TT::V)));
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
     const T* As = lds + cur * TT::LDS_ELEMS;
-    const T* Bs = As + TT::KR * TT::LDA;
+    const T* Bs = As + TT::BM * TT::PITCH;
 #pragma unroll
-    for (int kr = 0; kr < TT::KR; kr += Mf::KT) {
-      T af[WR], bf[WC];
+    for (int kg = 0; kg < TT::KR; kg += TT::G) {
+      VecT af[WR], bf[WC];
 #pragma unroll
       for (int i = 0; i < WR; ++i)
-        af[i] = As[(kr + ak) * TT::LDA + wm * (WR * Mf::MT) + i * Mf::MT + arow];
+        af[i] = *reinterpret_cast<const VecT*>(
+            As + (wm * (WR * Mf::MT) + i * Mf::MT + arow) * TT::PITCH + kg + ak * TT::V);
 #pragma unroll
       for (int j = 0; j < WC; ++j)
-        bf[j] = Bs[(kr + ak) * TT::LDB + wn * (WC * Mf::NT) + j * Mf::NT + arow];
+        bf[j] = *reinterpret_cast<const VecT*>(
+            Bs + (wn * (WC * Mf::NT) + j * Mf::NT + arow) * TT::PITCH + kg + ak * TT::V);
 #pragma unroll
-      for (int i = 0; i < WR; ++i)
+      for (int q = 0; q < TT::V; ++q)
 #pragma unroll
-        for (int j = 0; j < WC; ++j) acc[i][j] = Mf::mma(af[i], bf[j], acc[i][j]);
+        for (int i = 0; i < WR; ++i)
+#pragma unroll
+          for (int j = 0; j < WC; ++j) acc[i][j] = Mf::mma(af[i][q], bf[j][q], acc[i][j]);
     }
     if (kt + 1 < nk) store_tiles(cur ^ 1);
     __syncthreads();
@@ -502,9 +524,9 @@ template <typename TO>
 hipError_t launch_f32(const GemmDesc& g, hipStream_t st) {
   const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);
   switch (pl.cfg) {
-    case 0: return launch_cfg<MfmaF32, 2, 2, 8, TO>(g, pl, st);
-    case 1: return launch_cfg<MfmaF32, 1, 2, 16, TO>(g, pl, st);
-    default: return launch_cfg<MfmaF32, 1, 1, 16, TO>(g, pl, st);
+    case 0: return launch_cfg<MfmaF32, 2, 2, 16, TO>(g, pl, st);
+    case 1: return launch_cfg<MfmaF32, 1, 2, 32, TO>(g, pl, st);
+    default: return launch_cfg<MfmaF32, 1, 1, 32, TO>(g, pl, st);
   }
 }
 

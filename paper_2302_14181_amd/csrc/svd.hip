@@ -344,7 +344,8 @@ __device__ inline void store_col(const double2 (&u)[R], double2* c, int lane, in
 }
 
 // One-sided Jacobi sweeps. RMAX = rows per lane (mx <= 64 RMAX; with ACC also nx <= mx). Launched
-// cooperatively with nb / 2 workgroups of 64 b threads; dynamic LDS holds the 2b columns of X
+// with nb / 2 workgroups of 64 b threads that must all be resident together (a cooperative
+// launch, or an ordinary one whose caller bounds the load); dynamic LDS holds the 2b columns of X
 // (mx rows each) followed, with ACC, by the same 2b columns of Q (nx rows each).
 template <int RMAX, bool ACC>
 __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPlan p, SvdWs w,
@@ -692,7 +693,9 @@ SvdPlan svd_plan(int m, int n, int direction, bool want_basis, size_t lds_cap) {
   p.rank_max = std::min(m, n);
   p.rmax = p.mx <= 256 ? 4 : (p.mx <= 512 ? 8 : 16);
   // Block width: small blocks spread a sweep over more workgroups (compute units) at the price
-  // of more grid barriers per sweep; 8 columns (16 workgroups for 256 columns) balances the two.
+  // of more grid barriers per sweep; 8 columns (16 workgroups for 256 columns) balances the two
+  // (16 columns in 1024-thread workgroups, half the barriers, measured 15 % slower: four waves
+  // per SIMD then contend for issue).
   const int bmax = p.rmax <= 8 ? 8 : 4;
   const size_t col_bytes = sizeof(double2) * ((size_t)p.mx + (p.acc ? (size_t)p.nx : 0));
   const size_t col_cap = lds_cap / col_bytes;  // columns that fit in LDS
