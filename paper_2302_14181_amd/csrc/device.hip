@@ -564,7 +564,8 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
                  int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
                  double* norm_dev, double* sigma_dev, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
-  const SvdPlan p = svd_plan(m, n, direction);
+  // square: Jacobi on R^dag of the column-pivoted QR (a cold start needs few sweeps that way)
+  const SvdPlan p = (m == n && svd_qr_ok(m)) ? svd_plan_qr(m, direction) : svd_plan(m, n, direction);
   hipError_t e = svd_truncate(p, static_cast<const double2*>(Theta), Dmax, cutoff,
                               static_cast<double2*>(A_out), static_cast<double2*>(B_out), k_dev,
                               discarded_dev, norm_dev, sigma_dev, ws, ctx.dev->status,
@@ -688,6 +689,11 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     }
     return basis(i);
   };
+  // the slot a truncation that starts without a preconditioner writes its unitary to
+  auto basis_slot = [&](int i, int nx) -> double2* {
+    ctx.warm_dim[i] = nx;
+    return basis(i);
+  };
 
   ctx.max_sweeps = 0;
   std::vector<int> Q(mps->bond_dim, mps->bond_dim + L + 1);  // ket bonds
@@ -780,14 +786,17 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
-        const SvdPlan sp = svd_plan(m, n, MPOEVO_LEFT, warm_on);
+        // the first visit of a bond in a step has no fresh preconditioner (Theta moved by a
+        // whole time step since the last one): square Theta then goes through the pivoted QR
+        const bool qr = warm_on && m == n && svd_qr_ok(m) && (sw == 0 || ctx.warm_dim[i] != m);
+        const SvdPlan sp = qr ? svd_plan_qr(m, MPOEVO_LEFT) : svd_plan(m, n, MPOEVO_LEFT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = warm_for(i, m, n);
+        double2* wb = qr ? basis_slot(i, m) : warm_for(i, m, n);
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, sweeps_buf + visit, wb, wb, ctx.coop_jacobi));
+                              j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;
@@ -812,14 +821,15 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
-        const SvdPlan sp = svd_plan(m, n, MPOEVO_RIGHT, warm_on);
+        const bool qr = warm_on && m == n && svd_qr_ok(m) && ctx.warm_dim[i] != m;
+        const SvdPlan sp = qr ? svd_plan_qr(m, MPOEVO_RIGHT) : svd_plan(m, n, MPOEVO_RIGHT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = warm_for(i, m, n);
+        double2* wb = qr ? basis_slot(i, m) : warm_for(i, m, n);
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, sweeps_buf + visit, wb, wb, ctx.coop_jacobi));
+                              j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;

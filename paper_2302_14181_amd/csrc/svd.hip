@@ -48,6 +48,8 @@ constexpr int kMaxSweeps = 60;
 constexpr int kMaxGrid = 256;      // workgroups of a Jacobi launch (nb / 2 <= 256)
 constexpr double kAccept = 1e-13;  // columns this orthogonal need no further sweep
 constexpr double kEps = 2.220446049250313e-16;
+constexpr int kMaxDim = 1024;      // largest m, n of a truncation
+constexpr int kQrMaxDim = 512;     // largest n of a truncation preconditioned by the pivoted QR
 constexpr unsigned long long kBarrierTimeoutTicks = 300000000ull;  // 3 s of the 100 MHz clock
 
 struct SvdWs {  // carved from the caller's workspace
@@ -59,16 +61,21 @@ struct SvdWs {  // carved from the caller's workspace
   unsigned* flags;      // [kMaxGrid] barrier generation reached by each workgroup
   unsigned* sweep_max;  // [kMaxSweeps] bits of the largest |x^dag y| / (|x| |y|) of a sweep
   int* k_shared;        // [0] kept rank, [1] columns form a complete basis
+  double2* aux;         // [np][mx] (plans with qr) Jacobi input R^dag after the pivoted QR of X
+  int* qperm;           // [np] (qr) column pivots: column j of X Pi is column qperm[j] of X
+  int* pinv;            // [np] (qr) inverse pivots
   void* gemm;           // split-K scratch of the products (kGemmScratchBytes)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t ws_bytes(int mx, int nx, int np, bool acc) {
+size_t ws_bytes(int mx, int nx, int np, bool acc, bool qr) {
   return align256(sizeof(double2) * (size_t)mx * np) +
          (acc ? align256(sizeof(double2) * (size_t)nx * np) : 0) + align256(sizeof(double) * np) +
          align256(sizeof(int) * np) + 256 + sizeof(unsigned) * kMaxGrid +
-         align256(sizeof(unsigned) * kMaxSweeps) + 256 + kGemmScratchBytes;
+         align256(sizeof(unsigned) * kMaxSweeps) + 256 +
+         (qr ? align256(sizeof(double2) * (size_t)mx * np) + 2 * align256(sizeof(int) * np) : 0) +
+         kGemmScratchBytes;
 }
 
 SvdWs carve(const SvdPlan& p, void* ws) {
@@ -94,6 +101,16 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   off += align256(sizeof(unsigned) * kMaxSweeps);
   w.k_shared = reinterpret_cast<int*>(base + off);
   off += 256;
+  w.aux = nullptr;
+  w.qperm = w.pinv = nullptr;
+  if (p.qr) {
+    w.aux = reinterpret_cast<double2*>(base + off);
+    off += align256(sizeof(double2) * (size_t)p.mx * p.np);
+    w.qperm = reinterpret_cast<int*>(base + off);
+    off += align256(sizeof(int) * p.np);
+    w.pinv = reinterpret_cast<int*>(base + off);
+    off += align256(sizeof(int) * p.np);
+  }
   w.gemm = base + off;
   return w;
 }
@@ -608,7 +625,7 @@ __global__ void svd_isometry_kernel(SvdPlan p, SvdWs w, int kcap, double2* out, 
     double2 v{0.0, 0.0};
     if (rr < k) {
       const int j = w.perm[rr];
-      const double2 x = src[(long long)j * ld + i];
+      const double2 x = src[(long long)j * ld + (w.pinv ? w.pinv[i] : i)];
       if (from_q) v = x;
       else {
         const double s = w.sigma[j];
@@ -620,22 +637,352 @@ __global__ void svd_isometry_kernel(SvdPlan p, SvdWs w, int kcap, double2* out, 
   }
 }
 
-// Complete unitary basis of the column space of X (square X only): out[j][row] = X[j][row] /
-// sigma_j when every column is above the rounding floor, otherwise the identity (which makes the
-// next preconditioning product an exact copy).
+// Unitary basis of the column space of X (square X only) when every column is above the
+// rounding floor: out[j][row] = X[j][row] / sigma_j. Otherwise left to svd_complete_kernel.
 __global__ void svd_basis_kernel(SvdPlan p, SvdWs w, double2* out) {
-  const int complete = w.k_shared[1];
+  if (!w.k_shared[1]) return;
   const long long total = (long long)p.mx * p.nx;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(idx / p.mx), row = (int)(idx % p.mx);
-    double2 v{row == j ? 1.0 : 0.0, 0.0};
-    if (complete) {
+    const double inv = 1.0 / w.sigma[j];
+    const double2 x = w.X[(long long)j * p.mx + (w.pinv ? w.pinv[row] : row)];
+    out[idx] = double2{x.x * inv, x.y * inv};
+  }
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) b
+  return double2{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+
+// Sum of a complex value over the 64 lanes of a wave, in every lane.
+__device__ inline double2 wave_csum(double2 v) {
+  wave_sum2(v.x, v.y);
+  return v;
+}
+
+// One wave applies I - f v v^dag (v[j] = 1, v[i] = a[i] below) to the columns c0 .. cend-1 (at
+// most four, processed together so that their loads overlap) of the n-row matrix at base.
+__device__ inline void reflect_cols(const double2* a, double2 f, int j, int n, double2* base, int c0,
+                                    int cend, int lane) {
+  constexpr int G = 4;
+  double2* col[G];
+  double2 acc[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    col[q] = base + (long long)(c0 + q) * n;
+    acc[q] = (c0 + q < cend && lane == 0) ? col[q][j] : double2{0.0, 0.0};
+  }
+  for (int i = j + 1 + lane; i < n; i += 64) {
+    const double2 v = a[i];
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+      if (c0 + q < cend) {
+        const double2 pr = cmulc(v, col[q][i]);
+        acc[q].x += pr.x;
+        acc[q].y += pr.y;
+      }
+  }
+  double2 fq[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) fq[q] = (c0 + q < cend) ? cmul(f, wave_csum(acc[q])) : double2{0.0, 0.0};
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+      if (c0 + q < cend) col[q][j] = double2{col[q][j].x - fq[q].x, col[q][j].y - fq[q].y};
+  }
+  for (int i = j + 1 + lane; i < n; i += 64) {
+    const double2 v = a[i];
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+      if (c0 + q < cend) {
+        const double2 d = cmul(v, fq[q]);
+        col[q][i] = double2{col[q][i].x - d.x, col[q][i].y - d.y};
+      }
+  }
+}
+
+// The square case with columns at the rounding floor (X numerically rank-deficient, rank r < n):
+// a complete unitary whose first r columns are the normalised columns above the floor, U_r, and
+// whose other n - r columns are an orthonormal basis of the orthogonal complement of span(U_r),
+// taken from the Householder QR U_r = Q R (U_r = H_0 ... H_{r-1} [R; 0], the complement being
+// Q's columns r .. n-1, built by applying H_{r-1}, ..., H_0 to the last n - r unit vectors).
+// X's storage holds U_r during the factorisation (X is no longer needed). One workgroup of 1024
+// threads; each wave takes whole columns.
+constexpr int kCompleteThreads = 1024;
+__global__ __launch_bounds__(kCompleteThreads) void svd_complete_kernel(SvdPlan p, SvdWs w, double2* out) {
+  if (w.k_shared[1]) return;
+  const int n = p.nx;  // == p.mx
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kCompleteThreads / 64;
+  __shared__ int pos[kMaxDim];      // output column of X's column j
+  __shared__ int scan[kCompleteThreads];
+  __shared__ double2 tau[kMaxDim];
+  __shared__ double floor_sh;
+  if (tid == 0) {
+    double fro2 = 0.0;
+    for (int j = 0; j < n; ++j) fro2 += w.sigma[j] * w.sigma[j];
+    floor_sh = 8.0 * kEps * sqrt((double)p.mx) * sqrt(fro2);
+  }
+  __syncthreads();
+  // rank of each good column among the good ones (columns j = tid, tid + 1024 never needed: n <= 1024)
+  const bool good = tid < n && w.sigma[tid] > 2.0 * floor_sh;
+  scan[tid] = good ? 1 : 0;
+  __syncthreads();
+  for (int off = 1; off < kCompleteThreads; off <<= 1) {  // inclusive scan
+    const int v = tid >= off ? scan[tid - off] : 0;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
+  }
+  const int r = scan[kCompleteThreads - 1];
+  if (tid < n) pos[tid] = good ? scan[tid] - 1 : r + (tid + 1 - scan[tid]) - 1;
+  __syncthreads();
+  if (r == 0) {  // nothing above the floor: the identity
+    for (long long idx = tid; idx < (long long)n * n; idx += kCompleteThreads)
+      out[idx] = double2{(idx / n) == (idx % n) ? 1.0 : 0.0, 0.0};
+    return;
+  }
+  // U_r -> A (column-major n x r in X's storage, column pos[j]); also the first r output columns
+  double2* A = w.X;
+  for (long long idx = tid; idx < (long long)n * n; idx += kCompleteThreads) {
+    const int j = (int)(idx / n), row = (int)(idx % n);
+    if (w.sigma[j] > 2.0 * floor_sh) {
       const double inv = 1.0 / w.sigma[j];
-      const double2 x = w.X[idx];
-      v = double2{x.x * inv, x.y * inv};
+      const double2 x = w.X[(long long)j * n + (w.pinv ? w.pinv[row] : row)];
+      const double2 u{x.x * inv, x.y * inv};
+      out[(long long)pos[j] * n + row] = u;
     }
-    out[idx] = v;
+  }
+  __syncthreads();
+  for (long long idx = tid; idx < (long long)n * r; idx += kCompleteThreads) A[idx] = out[idx];
+  __syncthreads();
+  // Householder QR of A: reflector j (v_j = 1 at row j, A[i][j] below), A := H_j^dag A
+  for (int j = 0; j < r; ++j) {
+    double2* a = A + (long long)j * n;
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < n; i += 64) s = fma(a[i].x, a[i].x, fma(a[i].y, a[i].y, s));
+      double dummy = 0.0;
+      wave_sum2(s, dummy);
+      const double2 al = a[j];
+      double2 t{0.0, 0.0};
+      if (s > 0.0 || al.y != 0.0) {
+        const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, s)));
+        const double beta = al.x >= 0.0 ? -xn : xn;
+        t = double2{(beta - al.x) / beta, -al.y / beta};
+        // scale = 1 / (alpha - beta)
+        const double2 d{al.x - beta, al.y};
+        const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
+        const double2 sc{d.x * dn, -d.y * dn};
+        for (int i = j + 1 + lane; i < n; i += 64) a[i] = cmul(a[i], sc);
+        if (lane == 0) a[j] = double2{beta, 0.0};
+      }
+      if (lane == 0) tau[j] = t;
+    }
+    __syncthreads();
+    const double2 tj = tau[j];
+    if (tj.x != 0.0 || tj.y != 0.0)  // H_j^dag = I - conj(tau) v v^dag
+      for (int c = j + 1 + 4 * wave; c < r; c += 4 * nwaves)
+        reflect_cols(a, double2{tj.x, -tj.y}, j, n, A, c, r, lane);
+    __syncthreads();
+  }
+  // complement: E = [0; I_{n-r}] in output columns r .. n-1, then E := H_{r-1} ... then H_0
+  for (long long idx = tid; idx < (long long)n * (n - r); idx += kCompleteThreads) {
+    const int c = (int)(idx / n), row = (int)(idx % n);
+    out[(long long)(r + c) * n + row] = double2{row == r + c ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int j = r - 1; j >= 0; --j) {
+    const double2 tj = tau[j];
+    if (tj.x != 0.0 || tj.y != 0.0)  // H_j = I - tau v v^dag
+      for (int c = r + 4 * wave; c < n; c += 4 * nwaves)
+        reflect_cols(A + (long long)j * n, tj, j, n, out, c, n, lane);
+    __syncthreads();
+  }
+}
+
+// Largest value over the 64 lanes, in every lane (the lane-exchange pattern of wave_sum2).
+__device__ inline double wave_max1(double a) {
+  a = fmax(a, dpp_move<0xB1>(a));
+  a = fmax(a, dpp_move<0x4E>(a));
+  a = fmax(a, dpp_move<0x141>(a));
+  a = fmax(a, dpp_move<0x140>(a));
+  const unsigned long long b1 = static_cast<unsigned long long>(__double_as_longlong(a));
+  auto l1 = __builtin_amdgcn_permlane16_swap(static_cast<unsigned>(b1), static_cast<unsigned>(b1), false, false);
+  auto h1 = __builtin_amdgcn_permlane16_swap(static_cast<unsigned>(b1 >> 32), static_cast<unsigned>(b1 >> 32), false, false);
+  a = fmax(__longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h1[0]) << 32) | l1[0])),
+           __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h1[1]) << 32) | l1[1])));
+  const unsigned long long b2 = static_cast<unsigned long long>(__double_as_longlong(a));
+  auto l2 = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(b2), static_cast<unsigned>(b2), false, false);
+  auto h2 = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(b2 >> 32), static_cast<unsigned>(b2 >> 32), false, false);
+  return fmax(__longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h2[0]) << 32) | l2[0])),
+              __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h2[1]) << 32) | l2[1])));
+}
+
+// Householder QR with column pivoting of X (mx x nx, mx >= nx, column-major, in place): at
+// step j the remaining column of largest norm becomes column j (pivots kept as a permutation,
+// columns never moved), its reflector H_j = I - tau v v^dag (v_j = 1) zeroes it below row j, and
+// H_j^dag is applied to the remaining columns, whose norms below row j are then recomputed
+// exactly (the updated rows are in registers). Afterwards R(r, c) (r <= c) is X[qperm[c]][r].
+// One workgroup of 1024 threads; a lane holds rows lane + 64 t (t < RM) of a column, a wave
+// updates G columns at a time.
+constexpr int kQrThreads = 1024;
+template <int RM>
+__global__ __launch_bounds__(kQrThreads) void svd_qrcp_kernel(SvdPlan p, SvdWs w) {
+  constexpr int G = RM <= 4 ? 4 : (RM <= 8 ? 2 : 1);
+  const int m = p.mx, n = p.nx;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kQrThreads / 64;
+  __shared__ int perm[kMaxDim];
+  __shared__ double nrm2[kMaxDim];
+  __shared__ double red_v[kQrThreads / 64];
+  __shared__ int red_i[kQrThreads / 64];
+  __shared__ double2 tau_sh;
+  double2* X = w.X;
+  for (int c = wave; c < n; c += nwaves) {
+    const double2* col = X + (long long)c * m;
+    double sq = 0.0, dummy = 0.0;
+    for (int i = lane; i < m; i += 64) sq = fma(col[i].x, col[i].x, fma(col[i].y, col[i].y, sq));
+    wave_sum2(sq, dummy);
+    if (lane == 0) nrm2[c] = sq;
+  }
+  for (int c = tid; c < n; c += kQrThreads) perm[c] = c;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    // pivot: the largest remaining norm, ties to the smallest position (n <= 1024: one per thread)
+    const double mine = (tid >= j && tid < n) ? nrm2[tid] : -1.0;
+    const double wmax = wave_max1(mine);
+    const unsigned long long hit = __ballot(mine == wmax);
+    if (lane == 0) {
+      red_v[wave] = wmax;
+      red_i[wave] = wave * 64 + __builtin_ctzll(hit);
+    }
+    __syncthreads();
+    double bv = red_v[0];
+    int bi = red_i[0];
+    for (int k = 1; k < nwaves; ++k)
+      if (red_v[k] > bv) { bv = red_v[k]; bi = red_i[k]; }
+    if (!(bv > 0.0)) break;  // every remaining column is exactly zero below row j (uniform)
+    const int pcol = perm[bi];
+    double2* a = X + (long long)pcol * m;
+    if (wave == 0) {  // reflector of the pivot column, and the swap of the pivot into position j
+      double2 x[RM];
+      double sq = 0.0, dummy = 0.0;
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        const int i = lane + 64 * t;
+        x[t] = i < m ? a[i] : double2{0.0, 0.0};
+        if (i > j) sq = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, sq));
+      }
+      wave_sum2(sq, dummy);
+      const double2 al = a[j];
+      double2 tv{0.0, 0.0};
+      if (sq > 0.0 || al.y != 0.0) {
+        const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
+        const double beta = al.x >= 0.0 ? -xn : xn;
+        tv = double2{(beta - al.x) / beta, -al.y / beta};
+        const double2 d{al.x - beta, al.y};
+        const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
+        const double2 sc{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
+#pragma unroll
+        for (int t = 0; t < RM; ++t) {
+          const int i = lane + 64 * t;
+          if (i > j && i < m) a[i] = cmul(x[t], sc);
+          else if (i == j) a[i] = double2{beta, 0.0};
+        }
+      }
+      if (lane == 0) {
+        tau_sh = tv;
+        perm[bi] = perm[j];
+        perm[j] = pcol;
+        nrm2[bi] = nrm2[j];
+      }
+    }
+    __syncthreads();
+    const double2 tc{tau_sh.x, -tau_sh.y};  // H_j^dag = I - conj(tau) v v^dag
+    const bool refl = tc.x != 0.0 || tc.y != 0.0;
+    if (j + 1 + G * wave < n) {
+      double2 v[RM];  // the reflector (v_j = 1, zero above j)
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        const int i = lane + 64 * t;
+        v[t] = (i > j && i < m) ? a[i] : (i == j ? double2{1.0, 0.0} : double2{0.0, 0.0});
+      }
+      for (int c0 = j + 1 + G * wave; c0 < n; c0 += G * nwaves) {
+        double2 x[G][RM];
+        double2 acc[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          acc[q] = double2{0.0, 0.0};
+          const double2* col = X + (long long)perm[c0 + q < n ? c0 + q : c0] * m;
+#pragma unroll
+          for (int t = 0; t < RM; ++t) {
+            const int i = lane + 64 * t;
+            x[q][t] = (c0 + q < n && i >= j && i < m) ? col[i] : double2{0.0, 0.0};
+            const double2 pr = cmulc(v[t], x[q][t]);
+            acc[q].x += pr.x;
+            acc[q].y += pr.y;
+          }
+        }
+        double nq[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          if (refl) {
+            const double2 f = cmul(tc, wave_csum(acc[q]));
+#pragma unroll
+            for (int t = 0; t < RM; ++t) {
+              const double2 d = cmul(v[t], f);
+              x[q][t] = double2{x[q][t].x - d.x, x[q][t].y - d.y};
+            }
+          }
+          nq[q] = 0.0;
+#pragma unroll
+          for (int t = 0; t < RM; ++t)
+            if (lane + 64 * t > j) nq[q] = fma(x[q][t].x, x[q][t].x, fma(x[q][t].y, x[q][t].y, nq[q]));
+        }
+#pragma unroll
+        for (int q = 0; q < G; q += 2) {
+          double b2 = q + 1 < G ? nq[q + 1] : 0.0;
+          wave_sum2(nq[q], b2);
+          if (q + 1 < G) nq[q + 1] = b2;
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          if (c0 + q >= n) break;
+          double2* col = X + (long long)perm[c0 + q] * m;
+          if (refl) {
+#pragma unroll
+            for (int t = 0; t < RM; ++t) {
+              const int i = lane + 64 * t;
+              if (i >= j && i < m) col[i] = x[q][t];
+            }
+          }
+          if (lane == 0) nrm2[c0 + q] = nq[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < n; c += kQrThreads) {
+    w.qperm[c] = perm[c];
+    w.pinv[perm[c]] = c;
+  }
+}
+
+// Y = R^dag into dst (nx x np column-major, padding columns zero): Y(i, c) = conj(R(c, i)) for
+// c <= i, R(c, i) = X[qperm[i]][c].
+__global__ void svd_rdag_kernel(SvdPlan p, SvdWs w, double2* __restrict__ dst) {
+  const int n = p.nx, m = p.mx;
+  const long long total = (long long)n * p.np;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / n), i = (int)(idx % n);
+    double2 v{0.0, 0.0};
+    if (c < n && c <= i) {
+      const double2 r = w.X[(long long)w.qperm[i] * m + c];
+      v = double2{r.x, -r.y};
+    }
+    dst[idx] = v;
   }
 }
 
@@ -660,7 +1007,10 @@ size_t svd_ws_bound(int maxdim) {
   size_t best = 0;
   for (int m = 1; m <= maxdim; ++m)
     for (int n = 1; n <= maxdim; ++n)
-      for (int dir = 0; dir < 2; ++dir) best = std::max(best, svd_plan(m, n, dir, true).ws);
+      for (int dir = 0; dir < 2; ++dir) {
+        best = std::max(best, svd_plan(m, n, dir, true).ws);
+        if (m == n && svd_qr_ok(m)) best = std::max(best, svd_plan_qr(m, dir).ws);
+      }
   memo[maxdim] = best;
   return best;
 }
@@ -709,7 +1059,20 @@ SvdPlan svd_plan(int m, int n, int direction, bool want_basis, size_t lds_cap) {
   p.np = nb * b;
   p.threads = b * 64;
   p.lds = col_bytes * (size_t)2 * p.b;
-  p.ws = ws_bytes(p.mx, p.nx, p.np, p.acc != 0);
+  p.ws = ws_bytes(p.mx, p.nx, p.np, p.acc != 0, false);
+  return p;
+}
+
+bool svd_qr_ok(int n) { return n <= kQrMaxDim; }
+
+SvdPlan svd_plan_qr(int n, int direction, size_t lds_cap) {
+  // the factor to keep is X's right singular vectors: U of Theta from X = Theta^dag (direction 0),
+  // V of Theta from X = Theta (direction 1)
+  SvdPlan p = svd_plan(n, n, direction, false, lds_cap);
+  p.xconj = direction == 0 ? 1 : 0;
+  p.acc = 0;
+  p.qr = 1;
+  p.ws = ws_bytes(p.mx, p.nx, p.np, false, true);
   return p;
 }
 
@@ -725,8 +1088,10 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
                         const double2* warm, double2* basis_out, bool coop) {
-  if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx))
+  if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx) ||
+      (p.qr && (p.m != p.n || p.acc || p.mx > kQrMaxDim)))
     return hipErrorInvalidConfiguration;
+  if (p.qr) warm = nullptr;
   SvdWs w = carve(p, ws);
   const int kcap = std::min(Dmax, std::min(p.m, p.n));
   const bool square = p.m == p.n;
@@ -751,15 +1116,26 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     g.sCm = 1; g.sCn = p.mx;
     MPOEVO_HIP_TRY(gemm_launch(g, true, true, st));
   }
+  SvdWs wj = w;  // what Jacobi rotates: X itself, or R^dag of the column-pivoted QR of X
+  if (p.qr) {
+    if (p.mx <= 256) hipLaunchKernelGGL(svd_qrcp_kernel<4>, dim3(1), dim3(kQrThreads), 0, st, p, w);
+    else hipLaunchKernelGGL(svd_qrcp_kernel<8>, dim3(1), dim3(kQrThreads), 0, st, p, w);
+    MPOEVO_HIP_TRY(hipGetLastError());
+    const long long total = (long long)p.nx * p.np;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
+    hipLaunchKernelGGL(svd_rdag_kernel, dim3(blocks), dim3(256), 0, st, p, w, w.aux);
+    MPOEVO_HIP_TRY(hipGetLastError());
+    wj.X = w.aux;
+  }
   const int wpb = 4;
-  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, w,
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, wj,
                      status, 1);
   MPOEVO_HIP_TRY(hipGetLastError());
   {
     // above the rounding floor of a length-mx inner product (|err| <= mx eps |x| |y|)
     const double tol = kEps * std::max(16.0, (double)p.mx);
     SvdPlan pp = p;
-    SvdWs ww = w;
+    SvdWs ww = wj;
     double tt = tol;
     int* stp = status;
     int* swp = sweeps_dev;
@@ -772,19 +1148,20 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
       MPOEVO_HIP_TRY(hipLaunchKernel(jacobi_for(p), dim3(p.nb / 2), dim3(p.threads), args, p.lds, st));
     if (ev1) MPOEVO_HIP_TRY(hipEventRecord(ev1, st));
   }
-  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, w,
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, wj,
                      status, 0);
   MPOEVO_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, p, w, kcap, cutoff, k_dev,
+  hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, p, wj, kcap, cutoff, k_dev,
                      disc_dev, norm_dev, sigma_dev);
   MPOEVO_HIP_TRY(hipGetLastError());
-  // the kept factor comes from the columns when it lies on X's column side, else from Q
-  const bool from_q = (p.direction == 0) != (p.xconj == 0);
+  // the kept factor comes from the columns when it lies on X's column side, else from Q (with
+  // the pivoted QR it is always the columns, i.e. X's right singular vectors)
+  const bool from_q = !p.qr && ((p.direction == 0) != (p.xconj == 0));
   double2* iso = p.direction == 0 ? A_out : B_out;
   {
     const long long total = (long long)(p.direction == 0 ? p.m : p.n) * kcap;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(svd_isometry_kernel, dim3(blocks), dim3(256), 0, st, p, w, kcap, iso,
+    hipLaunchKernelGGL(svd_isometry_kernel, dim3(blocks), dim3(256), 0, st, p, wj, kcap, iso,
                        from_q ? 1 : 0);
     MPOEVO_HIP_TRY(hipGetLastError());
   }
@@ -792,7 +1169,9 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     if (square) {
       const long long total = (long long)p.mx * p.nx;
       const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
-      hipLaunchKernelGGL(svd_basis_kernel, dim3(blocks), dim3(256), 0, st, p, w, basis_out);
+      hipLaunchKernelGGL(svd_basis_kernel, dim3(blocks), dim3(256), 0, st, p, wj, basis_out);
+      MPOEVO_HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(svd_complete_kernel, dim3(1), dim3(kCompleteThreads), 0, st, p, wj, basis_out);
       MPOEVO_HIP_TRY(hipGetLastError());
     } else {  // the accumulated P Q (its first nx columns are contiguous)
       MPOEVO_HIP_TRY(hipMemcpyAsync(basis_out, w.Q, sizeof(double2) * (size_t)p.nx * p.nx,
