@@ -131,7 +131,9 @@ int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void
 
 /*
  * truncate -- DEVICE, async on `stream`. FP64 SVD Theta = U S V^dag of an m x n complex128
- * matrix (row-major) by one-sided Jacobi, keeping k = min(Dmax, m, n, #{sigma_i > max(cutoff *
+ * matrix (row-major) by one-sided Jacobi (for square Theta with m <= 512 on R^dag of a
+ * column-pivoted Householder QR of Theta or Theta^dag, which converges in few sweeps even when
+ * the singular values spread over many decades), keeping k = min(Dmax, m, n, #{sigma_i > max(cutoff *
  * sigma_1, 8 eps sqrt(max(m, n)) ||Theta||_F)}) >= 1 singular values (the truncation of the
  * two-site update; the second bound drops singular values at the rounding level of Theta).
  *   direction LEFT  (left-to-right sweep): A_out = U_k (left-orthonormal), B_out = S_k V_k^dag
@@ -196,8 +198,12 @@ typedef struct {
   int svd_cold_start; /* nonzero: every truncation starts Jacobi from Theta itself. Zero (the
                          default): the bond matrix is first multiplied by the unitary the
                          previous truncation of the same bond left in the workspace (a singular
-                         basis of that matrix), which leaves the same singular values and kept
-                         vectors and converges in a few sweeps. The unitaries
+                         basis of that matrix, completed to a unitary when the matrix is
+                         numerically rank-deficient), which leaves the same singular values and
+                         kept vectors and converges in a few sweeps; the first truncation of a
+                         square bond matrix in a step (Theta has moved by a whole time step
+                         since the last one) instead runs Jacobi on R^dag of its
+                         column-pivoted QR. The unitaries
                          persist in the workspace between step calls on one handle with the
                          same workspace and chain shape; the caller must not modify that
                          workspace between such calls. */

@@ -410,9 +410,10 @@ int device_init(Context& ctx) {
   e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, ctx.device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceGetAttribute(cooperative launch)");
   if (!coop) { ctx.err = "device does not support cooperative launches"; return MPOEVO_EUNSUPPORTED; }
-  if ((size_t)lds < kSvdLdsBytes) {
+  const size_t lds_need = std::max(kSvdLdsBytes, kQrLdsBytes + 1024);
+  if ((size_t)lds < lds_need) {
     ctx.err = "device provides " + std::to_string(lds) + " bytes of LDS per workgroup; the SVD needs " +
-              std::to_string(kSvdLdsBytes);
+              std::to_string(lds_need);
     return MPOEVO_EUNSUPPORTED;
   }
   e = svd_configure();

@@ -27,6 +27,8 @@ struct SvdPlan {
 // LDS budget of the Jacobi kernel (bytes); the workspace size depends on it, so it is a
 // build constant rather than a device query (device_init checks that the device provides it).
 constexpr size_t kSvdLdsBytes = 128 * 1024;
+// Dynamic LDS of the pivoted-QR factorisation at its largest size: 17 columns of 512 rows.
+constexpr size_t kQrLdsBytes = 16 * 17 * 512;
 
 // Plan for an m x n truncation in the given direction. want_basis: the call will ask for the
 // preconditioner of the next truncation (rectangular Theta then accumulates Q).
@@ -40,7 +42,7 @@ SvdPlan svd_plan(int m, int n, int direction, bool want_basis = false,
 // truncation of a bond in a time step) this converges in about 8 sweeps where Jacobi on X
 // needs 25-40.
 SvdPlan svd_plan_qr(int n, int direction, size_t lds_cap = kSvdLdsBytes);
-// Whether an n x n truncation can take the pivoted-QR plan (n <= 512).
+// Whether an n x n truncation takes the pivoted-QR plan (n <= 512).
 bool svd_qr_ok(int n);
 
 // Largest workspace of any plan with m, n <= maxdim (memoised).

@@ -49,7 +49,8 @@ constexpr int kMaxGrid = 256;      // workgroups of a Jacobi launch (nb / 2 <= 2
 constexpr double kAccept = 1e-13;  // columns this orthogonal need no further sweep
 constexpr double kEps = 2.220446049250313e-16;
 constexpr int kMaxDim = 1024;      // largest m, n of a truncation
-constexpr int kQrMaxDim = 512;     // largest n of a truncation preconditioned by the pivoted QR
+// Largest n of a truncation preconditioned by the pivoted QR.
+constexpr int kQrMaxDim = 512;
 constexpr unsigned long long kBarrierTimeoutTicks = 300000000ull;  // 3 s of the 100 MHz clock
 
 struct SvdWs {  // carved from the caller's workspace
@@ -64,6 +65,11 @@ struct SvdWs {  // carved from the caller's workspace
   double2* aux;         // [np][mx] (plans with qr) Jacobi input R^dag after the pivoted QR of X
   int* qperm;           // [np] (qr) column pivots: column j of X Pi is column qperm[j] of X
   int* pinv;            // [np] (qr) inverse pivots
+  unsigned* qflags;     // [kMaxGrid + 1] (qr) per-workgroup step reached; [kMaxGrid] reflector ready
+  double* qcand_v;      // [2][kMaxGrid] (qr) each workgroup's pivot candidate: norm^2 ...
+  int* qcand_i;         // [2][kMaxGrid] ... and column
+  double2* qcol;        // [2][nb / 2][mx] (qr) each workgroup's candidate column
+  int* qsteps;          // [1] (qr) steps taken (fewer than nx when the rest is exactly zero)
   void* gemm;           // split-K scratch of the products (kGemmScratchBytes)
 };
 
@@ -74,7 +80,10 @@ size_t ws_bytes(int mx, int nx, int np, bool acc, bool qr) {
          (acc ? align256(sizeof(double2) * (size_t)nx * np) : 0) + align256(sizeof(double) * np) +
          align256(sizeof(int) * np) + 256 + sizeof(unsigned) * kMaxGrid +
          align256(sizeof(unsigned) * kMaxSweeps) + 256 +
-         (qr ? align256(sizeof(double2) * (size_t)mx * np) + 2 * align256(sizeof(int) * np) : 0) +
+         (qr ? align256(sizeof(double2) * (size_t)mx * np) + 2 * align256(sizeof(int) * np) +
+                   align256(sizeof(unsigned) * (kMaxGrid + 1)) + align256(2 * sizeof(double) * kMaxGrid) +
+                   align256(2 * sizeof(int) * kMaxGrid) + align256(2 * sizeof(double2) * (size_t)mx * np) + 256
+              : 0) +
          kGemmScratchBytes;
 }
 
@@ -103,6 +112,11 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   off += 256;
   w.aux = nullptr;
   w.qperm = w.pinv = nullptr;
+  w.qflags = nullptr;
+  w.qcand_v = nullptr;
+  w.qcand_i = nullptr;
+  w.qcol = nullptr;
+  w.qsteps = nullptr;
   if (p.qr) {
     w.aux = reinterpret_cast<double2*>(base + off);
     off += align256(sizeof(double2) * (size_t)p.mx * p.np);
@@ -110,6 +124,16 @@ SvdWs carve(const SvdPlan& p, void* ws) {
     off += align256(sizeof(int) * p.np);
     w.pinv = reinterpret_cast<int*>(base + off);
     off += align256(sizeof(int) * p.np);
+    w.qflags = reinterpret_cast<unsigned*>(base + off);
+    off += align256(sizeof(unsigned) * (kMaxGrid + 1));
+    w.qcand_v = reinterpret_cast<double*>(base + off);
+    off += align256(2 * sizeof(double) * kMaxGrid);
+    w.qcand_i = reinterpret_cast<int*>(base + off);
+    off += align256(2 * sizeof(int) * kMaxGrid);
+    w.qcol = reinterpret_cast<double2*>(base + off);
+    off += align256(2 * sizeof(double2) * (size_t)p.mx * p.np);  // nb / 2 <= np columns
+    w.qsteps = reinterpret_cast<int*>(base + off);
+    off += 256;
   }
   w.gemm = base + off;
   return w;
@@ -216,6 +240,10 @@ __global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, Sv
     }
   }
   if (blockIdx.x == 0) {
+    if (p.qr) {
+      for (int i = threadIdx.x; i <= kMaxGrid; i += blockDim.x) w.qflags[i] = 0u;
+      if (threadIdx.x == 0) *w.qsteps = 0;
+    }
     if (threadIdx.x < 3) w.bar[threadIdx.x] = 0u;
     for (int i = threadIdx.x; i < kMaxSweeps; i += blockDim.x) w.sweep_max[i] = 0u;
     for (int i = threadIdx.x; i < kMaxGrid; i += blockDim.x) w.flags[i] = 0u;
@@ -820,152 +848,184 @@ __device__ inline double wave_max1(double a) {
               __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h2[1]) << 32) | l2[1])));
 }
 
-// Householder QR with column pivoting of X (mx x nx, mx >= nx, column-major, in place): at
-// step j the remaining column of largest norm becomes column j (pivots kept as a permutation,
-// columns never moved), its reflector H_j = I - tau v v^dag (v_j = 1) zeroes it below row j, and
-// H_j^dag is applied to the remaining columns, whose norms below row j are then recomputed
-// exactly (the updated rows are in registers). Afterwards R(r, c) (r <= c) is X[qperm[c]][r].
-// One workgroup of 1024 threads; a lane holds rows lane + 64 t (t < RM) of a column, a wave
-// updates G columns at a time.
-constexpr int kQrThreads = 1024;
-template <int RM>
-__global__ __launch_bounds__(kQrThreads) void svd_qrcp_kernel(SvdPlan p, SvdWs w) {
-  constexpr int G = RM <= 4 ? 4 : (RM <= 8 ? 2 : 1);
-  const int m = p.mx, n = p.nx;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kQrThreads / 64;
-  __shared__ int perm[kMaxDim];
-  __shared__ double nrm2[kMaxDim];
-  __shared__ double red_v[kQrThreads / 64];
-  __shared__ int red_i[kQrThreads / 64];
+// Householder QR with column pivoting of X (mx x nx, mx >= nx, column-major): at step j the
+// remaining column of largest norm becomes column j (pivots kept as a permutation), its reflector
+// H_j = I - tau v v^dag (v_j = 1) zeroes it below row j, and H_j^dag is applied to the remaining
+// columns. Spread over the Jacobi grid's workgroups (launched together, like the Jacobi
+// kernel): workgroup g keeps columns [g C, g C + C) (C = 2b) of X in LDS. Per step j every
+// workgroup publishes its remaining column of largest norm (the column itself, its norm and
+// index; flag = j + 1) and waits for all others; each then takes the overall largest (ties: the
+// smallest index), forms its reflector itself (the same arithmetic on the same data everywhere,
+// so one exchange per step suffices), applies H_j^dag to its remaining columns in LDS and
+// recomputes their norms below row j; the owner records the pivot and R(j, j). Two buffers (by
+// the parity of j) keep consecutive steps apart. At the end each workgroup writes its columns
+// back: R(r, c) = X[qperm[c]][r] for r <= c. Waits are bounded (barrier-timeout status).
+__global__ __launch_bounds__(256) void svd_qrcp_grid_kernel(SvdPlan p, SvdWs w, int* status) {
+  extern __shared__ double2 slab[];  // [C][mx] columns, then [mx] the reflector
+  __shared__ double nrm2[2 * 16];
+  __shared__ int done[2 * 16];
+  __shared__ double best_v;
+  __shared__ int best_c, best_g, mine_k;
   __shared__ double2 tau_sh;
+  __shared__ double beta_sh;
+  const int m = p.mx, n = p.nx, C = 2 * p.b, nwg = gridDim.x, g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c_lo = g * C;
+  double2* vsh = slab + (long long)C * m;
   double2* X = w.X;
-  for (int c = wave; c < n; c += nwaves) {
-    const double2* col = X + (long long)c * m;
-    double sq = 0.0, dummy = 0.0;
-    for (int i = lane; i < m; i += 64) sq = fma(col[i].x, col[i].x, fma(col[i].y, col[i].y, sq));
-    wave_sum2(sq, dummy);
-    if (lane == 0) nrm2[c] = sq;
+  for (long long idx = tid; idx < (long long)C * m; idx += blockDim.x) {
+    const int k = (int)(idx / m), i = (int)(idx % m);
+    slab[idx] = c_lo + k < n ? X[(long long)(c_lo + k) * m + i] : double2{0.0, 0.0};
   }
-  for (int c = tid; c < n; c += kQrThreads) perm[c] = c;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    // pivot: the largest remaining norm, ties to the smallest position (n <= 1024: one per thread)
-    const double mine = (tid >= j && tid < n) ? nrm2[tid] : -1.0;
-    const double wmax = wave_max1(mine);
-    const unsigned long long hit = __ballot(mine == wmax);
+  for (int k = wave; k < C; k += 4) {
+    double sq = 0.0, dummy = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double2 x = slab[(long long)k * m + i];
+      sq = fma(x.x, x.x, fma(x.y, x.y, sq));
+    }
+    wave_sum2(sq, dummy);
     if (lane == 0) {
-      red_v[wave] = wmax;
-      red_i[wave] = wave * 64 + __builtin_ctzll(hit);
+      nrm2[k] = sq;
+      done[k] = c_lo + k < n ? 0 : 1;
+    }
+  }
+  __syncthreads();
+  bool ok = true;
+  int j = 0;
+  for (; j < n && ok; ++j) {
+    const int par = j & 1;
+    if (wave == 0) {  // this workgroup's candidate
+      const double mine = (lane < C && !done[lane]) ? nrm2[lane] : -1.0;
+      const double wmax = wave_max1(mine);
+      const unsigned long long hit = __ballot(mine == wmax);
+      if (lane == 0) {
+        mine_k = __builtin_ctzll(hit);
+        w.qcand_v[par * kMaxGrid + g] = wmax;
+        w.qcand_i[par * kMaxGrid + g] = c_lo + mine_k;
+      }
     }
     __syncthreads();
-    double bv = red_v[0];
-    int bi = red_i[0];
-    for (int k = 1; k < nwaves; ++k)
-      if (red_v[k] > bv) { bv = red_v[k]; bi = red_i[k]; }
-    if (!(bv > 0.0)) break;  // every remaining column is exactly zero below row j (uniform)
-    const int pcol = perm[bi];
-    double2* a = X + (long long)pcol * m;
-    if (wave == 0) {  // reflector of the pivot column, and the swap of the pivot into position j
-      double2 x[RM];
-      double sq = 0.0, dummy = 0.0;
-#pragma unroll
-      for (int t = 0; t < RM; ++t) {
-        const int i = lane + 64 * t;
-        x[t] = i < m ? a[i] : double2{0.0, 0.0};
-        if (i > j) sq = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, sq));
+    {
+      const double2* src = slab + (long long)mine_k * m;
+      double2* dst = w.qcol + ((long long)par * nwg + g) * m;
+      for (int i = j + tid; i < m; i += blockDim.x) dst[i] = src[i];
+    }
+    publish_round(w.qflags, (unsigned)(j + 1));
+    if (!(ok = wait_flags(w.qflags, w.bar, 0, 0, nwg, (unsigned)(j + 1)))) break;
+    if (wave == 0) {  // the overall pivot (every workgroup computes the same)
+      double v = -1.0;
+      int c = n, gg = 0;
+      for (int k = lane; k < nwg; k += 64) {
+        const double kv = __hip_atomic_load(&w.qcand_v[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int kc = __hip_atomic_load(&w.qcand_i[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (kv > v || (kv == v && kc < c)) { v = kv; c = kc; gg = k; }
       }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oc = __shfl_xor(c, off, 64);
+        const int og = __shfl_xor(gg, off, 64);
+        if (ov > v || (ov == v && oc < c)) { v = ov; c = oc; gg = og; }
+      }
+      if (lane == 0) { best_v = v; best_c = c; best_g = gg; }
+    }
+    __syncthreads();
+    if (!(best_v > 0.0)) break;  // the remaining columns are exactly zero below row j
+    {  // the pivot column (rows j..) into LDS
+      const double2* src = w.qcol + ((long long)par * nwg + best_g) * m;
+      for (int i = j + tid; i < m; i += blockDim.x) vsh[i] = src[i];
+    }
+    __syncthreads();
+    if (wave == 0) {  // its reflector, v into vsh (v_j = 1)
+      double sq = 0.0, dummy = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) sq = fma(vsh[i].x, vsh[i].x, fma(vsh[i].y, vsh[i].y, sq));
       wave_sum2(sq, dummy);
-      const double2 al = a[j];
+      const double2 al = vsh[j];
       double2 tv{0.0, 0.0};
+      double beta = al.x;
       if (sq > 0.0 || al.y != 0.0) {
         const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
-        const double beta = al.x >= 0.0 ? -xn : xn;
+        beta = al.x >= 0.0 ? -xn : xn;
         tv = double2{(beta - al.x) / beta, -al.y / beta};
         const double2 d{al.x - beta, al.y};
         const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
         const double2 sc{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
-#pragma unroll
-        for (int t = 0; t < RM; ++t) {
-          const int i = lane + 64 * t;
-          if (i > j && i < m) a[i] = cmul(x[t], sc);
-          else if (i == j) a[i] = double2{beta, 0.0};
-        }
+        for (int i = j + 1 + lane; i < m; i += 64) vsh[i] = cmul(vsh[i], sc);
       }
       if (lane == 0) {
         tau_sh = tv;
-        perm[bi] = perm[j];
-        perm[j] = pcol;
-        nrm2[bi] = nrm2[j];
+        beta_sh = beta;
+        vsh[j] = double2{1.0, 0.0};
       }
+    }
+    __syncthreads();
+    if (best_g == g && tid == 0) {  // the owner: R(j, j) and the pivot
+      const int k = best_c - c_lo;
+      slab[(long long)k * m + j] = double2{beta_sh, 0.0};
+      done[k] = 1;
+      w.qperm[j] = best_c;
     }
     __syncthreads();
     const double2 tc{tau_sh.x, -tau_sh.y};  // H_j^dag = I - conj(tau) v v^dag
     const bool refl = tc.x != 0.0 || tc.y != 0.0;
-    if (j + 1 + G * wave < n) {
-      double2 v[RM];  // the reflector (v_j = 1, zero above j)
-#pragma unroll
-      for (int t = 0; t < RM; ++t) {
-        const int i = lane + 64 * t;
-        v[t] = (i > j && i < m) ? a[i] : (i == j ? double2{1.0, 0.0} : double2{0.0, 0.0});
-      }
-      for (int c0 = j + 1 + G * wave; c0 < n; c0 += G * nwaves) {
-        double2 x[G][RM];
-        double2 acc[G];
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
-          acc[q] = double2{0.0, 0.0};
-          const double2* col = X + (long long)perm[c0 + q < n ? c0 + q : c0] * m;
-#pragma unroll
-          for (int t = 0; t < RM; ++t) {
-            const int i = lane + 64 * t;
-            x[q][t] = (c0 + q < n && i >= j && i < m) ? col[i] : double2{0.0, 0.0};
-            const double2 pr = cmulc(v[t], x[q][t]);
-            acc[q].x += pr.x;
-            acc[q].y += pr.y;
-          }
+    for (int k = wave; k < C; k += 4) {
+      if (done[k]) continue;
+      double2* col = slab + (long long)k * m;
+      if (refl) {
+        double2 acc{0.0, 0.0};
+        for (int i = j + lane; i < m; i += 64) {
+          const double2 pr = cmulc(vsh[i], col[i]);
+          acc.x += pr.x;
+          acc.y += pr.y;
         }
-        double nq[G];
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
-          if (refl) {
-            const double2 f = cmul(tc, wave_csum(acc[q]));
-#pragma unroll
-            for (int t = 0; t < RM; ++t) {
-              const double2 d = cmul(v[t], f);
-              x[q][t] = double2{x[q][t].x - d.x, x[q][t].y - d.y};
-            }
-          }
-          nq[q] = 0.0;
-#pragma unroll
-          for (int t = 0; t < RM; ++t)
-            if (lane + 64 * t > j) nq[q] = fma(x[q][t].x, x[q][t].x, fma(x[q][t].y, x[q][t].y, nq[q]));
-        }
-#pragma unroll
-        for (int q = 0; q < G; q += 2) {
-          double b2 = q + 1 < G ? nq[q + 1] : 0.0;
-          wave_sum2(nq[q], b2);
-          if (q + 1 < G) nq[q + 1] = b2;
-        }
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
-          if (c0 + q >= n) break;
-          double2* col = X + (long long)perm[c0 + q] * m;
-          if (refl) {
-#pragma unroll
-            for (int t = 0; t < RM; ++t) {
-              const int i = lane + 64 * t;
-              if (i >= j && i < m) col[i] = x[q][t];
-            }
-          }
-          if (lane == 0) nrm2[c0 + q] = nq[q];
+        const double2 f = cmul(tc, wave_csum(acc));
+        for (int i = j + lane; i < m; i += 64) {
+          const double2 d = cmul(vsh[i], f);
+          col[i] = double2{col[i].x - d.x, col[i].y - d.y};
         }
       }
+      double sq = 0.0, dummy = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) sq = fma(col[i].x, col[i].x, fma(col[i].y, col[i].y, sq));
+      wave_sum2(sq, dummy);
+      if (lane == 0) nrm2[k] = sq;
     }
     __syncthreads();
   }
-  for (int c = tid; c < n; c += kQrThreads) {
-    w.qperm[c] = perm[c];
-    w.pinv[perm[c]] = c;
+  if (!ok) {
+    if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
+    return;
+  }
+  for (long long idx = tid; idx < (long long)C * m; idx += blockDim.x) {
+    const int k = (int)(idx / m), i = (int)(idx % m);
+    if (c_lo + k < n) X[(long long)(c_lo + k) * m + i] = slab[idx];
+  }
+  if (g == 0 && tid == 0) *w.qsteps = j;
+}
+
+// Pivots of the columns never chosen (all exactly zero below the last step) in increasing order,
+// and the inverse permutation. One workgroup.
+__global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
+  __shared__ int used[kMaxDim];
+  const int n = p.nx, j0 = min(max(*w.qsteps, 0), n);
+  for (int c = threadIdx.x; c < n; c += blockDim.x) used[c] = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < j0; j += blockDim.x) {
+    const int q = w.qperm[j];
+    if (q >= 0 && q < n) used[q] = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int j = j0;
+    for (int c = 0; c < n && j < n; ++c)
+      if (!used[c]) w.qperm[j++] = c;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) w.pinv[c] = c;  // (a complete permutation overwrites all)
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const int q = w.qperm[j];
+    if (q >= 0 && q < n) w.pinv[q] = j;
   }
 }
 
@@ -1020,6 +1080,8 @@ hipError_t svd_configure() {
                        jacobi_fn<4, true>(),  jacobi_fn<8, true>(),  jacobi_fn<16, true>()};
   for (const void* f : fns)
     MPOEVO_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSvdLdsBytes));
+  MPOEVO_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(svd_qrcp_grid_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsBytes));
   return hipSuccess;
 }
 
@@ -1118,8 +1180,17 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   }
   SvdWs wj = w;  // what Jacobi rotates: X itself, or R^dag of the column-pivoted QR of X
   if (p.qr) {
-    if (p.mx <= 256) hipLaunchKernelGGL(svd_qrcp_kernel<4>, dim3(1), dim3(kQrThreads), 0, st, p, w);
-    else hipLaunchKernelGGL(svd_qrcp_kernel<8>, dim3(1), dim3(kQrThreads), 0, st, p, w);
+    SvdPlan pp = p;
+    SvdWs ww = w;
+    int* stp = status;
+    void* args[] = {&pp, &ww, &stp};
+    const size_t lds = sizeof(double2) * (size_t)(2 * p.b + 1) * p.mx;
+    const void* fn = reinterpret_cast<const void*>(svd_qrcp_grid_kernel);
+    if (coop)
+      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.nb / 2), dim3(256), args, (unsigned)lds, st));
+    else
+      MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(p.nb / 2), dim3(256), args, lds, st));
+    hipLaunchKernelGGL(svd_qrperm_kernel, dim3(1), dim3(1024), 0, st, p, w);
     MPOEVO_HIP_TRY(hipGetLastError());
     const long long total = (long long)p.nx * p.np;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);

@@ -132,7 +132,8 @@ def test_local_apply_parity(mp, handle, dims, prec64):
     assert err < (1e-12 if prec64 else 2e-5), err
 
 
-TR_CASES = [(1, 1), (2, 2), (2, 7), (9, 3), (32, 32), (64, 40), (40, 64), (130, 127), (256, 256), (300, 200)]
+TR_CASES = [(1, 1), (2, 2), (2, 7), (9, 3), (32, 32), (64, 40), (40, 64), (130, 127), (256, 256), (300, 200),
+            (384, 384), (512, 512)]
 
 
 def _graded(rng, m, n, decay):
@@ -151,7 +152,29 @@ def test_truncate_parity(mp, handle, shape, direction):
     rng = np.random.default_rng(m * 1000 + n)
     _say("truncate", shape, "dir", direction)
     X = _cn(rng, m, n) if (m * n) % 2 == 0 else _graded(rng, m, n, 0.3)
-    Dmax = max(1, min(m, n) - 3)
+    _check_truncate(mp, handle, X, max(1, min(m, n) - 3), direction)
+
+
+# square matrices take the pivoted-QR preconditioned path: spectra over many decades (graded),
+# and exactly rank-deficient ones (the factorisation stops at the zero remainder)
+GRADED_SQ = [(64, 0.5, None), (256, 0.12, None), (512, 0.06, None), (200, 0.0, 120), (512, 0.0, 300)]
+
+
+@pytest.mark.parametrize("direction", [0, 1], ids=["left", "right"])
+@pytest.mark.parametrize("case", GRADED_SQ, ids=[str(c) for c in GRADED_SQ])
+def test_truncate_square_graded_and_deficient(mp, handle, case, direction):
+    n, decay, rank = case
+    rng = np.random.default_rng(n + 17 * (rank or 0))
+    _say("truncate square", case, "dir", direction)
+    if rank is None:
+        X = _graded(rng, n, n, decay)
+    else:
+        X = _cn(rng, n, rank) @ _cn(rng, rank, n)
+    _check_truncate(mp, handle, X, n // 2, direction)
+
+
+def _check_truncate(mp, handle, X, Dmax, direction):
+    m, n = X.shape
     kcap = min(Dmax, m, n)
     A = torch.zeros((m, kcap), dtype=torch.complex128, device="cuda")
     B = torch.zeros((kcap, n), dtype=torch.complex128, device="cuda")
