@@ -698,6 +698,10 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
 
   ctx.max_sweeps = 0;
   std::vector<int> Q(mps->bond_dim, mps->bond_dim + L + 1);  // ket bonds
+  // bonds the last step kept at Dmax: below it the spectrum fell under the cutoff, the bond
+  // matrices are numerically rank-deficient and their truncations take the pivoted QR
+  std::vector<char> saturated(L + 1);
+  for (int b = 0; b <= L; ++b) saturated[b] = Q[b] >= Dmax;
   std::vector<int> P(Q);                                       // bra bonds (upper bounds)
   hipError_t e = hipSuccess;
   Prof prof_obj;
@@ -788,13 +792,17 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       const int kcap = std::min(Dmax, std::min(m, n));
       {
         // the first visit of a bond in a step has no fresh preconditioner (Theta moved by a
-        // whole time step since the last one): square Theta then goes through the pivoted QR
-        const bool qr = warm_on && m == n && svd_qr_ok(m) && (sw == 0 || ctx.warm_dim[i] != m);
+        // whole time step since the last one), and a bond below Dmax is numerically
+        // rank-deficient (its basis would need completing): square Theta then goes through the
+        // pivoted QR, handing on a basis only where the next visit can use it
+        const bool qr = warm_on && m == n && svd_qr_ok(m) &&
+                        (sw == 0 || ctx.warm_dim[i] != m || !saturated[i + 1]);
         const SvdPlan sp = qr ? svd_plan_qr(m, MPOEVO_LEFT) : svd_plan(m, n, MPOEVO_LEFT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = qr ? basis_slot(i, m) : warm_for(i, m, n);
+        double2* wb = qr ? (saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
+        if (qr && !wb) ctx.warm_dim[i] = 0;
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
                               j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi));
@@ -822,12 +830,13 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
-        const bool qr = warm_on && m == n && svd_qr_ok(m) && ctx.warm_dim[i] != m;
+        const bool qr = warm_on && m == n && svd_qr_ok(m) && (ctx.warm_dim[i] != m || !saturated[i + 1]);
         const SvdPlan sp = qr ? svd_plan_qr(m, MPOEVO_RIGHT) : svd_plan(m, n, MPOEVO_RIGHT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = qr ? basis_slot(i, m) : warm_for(i, m, n);
+        double2* wb = qr ? (saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
+        if (qr && !wb) ctx.warm_dim[i] = 0;
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
                               j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi));
