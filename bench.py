@@ -291,6 +291,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--workload", choices=["quench", "lr3", "batched"], default="quench")
+    ap.add_argument("--progress", action="store_true", help="print a line to stderr every 10 timed steps")
     args = ap.parse_args()
     if args.workload == "batched":
         # more hardware queues and worker streams let more chains' truncations overlap (read by
@@ -340,6 +341,8 @@ def main():
             st.append(mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=ws,
                               profile=profile))
             ev[k + 1].record()
+            if args.progress and k % 10 == 9:
+                print(f"[bench] step {k + 1}/{steps}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
