@@ -131,9 +131,10 @@ int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void
 
 /*
  * truncate -- DEVICE, async on `stream`. FP64 SVD Theta = U S V^dag of an m x n complex128
- * matrix (row-major) by one-sided Jacobi (for square Theta with m <= 512 on R^dag of a
- * column-pivoted Householder QR of Theta or Theta^dag, which converges in few sweeps even when
- * the singular values spread over many decades), keeping k = min(Dmax, m, n, #{sigma_i > max(cutoff *
+ * matrix (row-major) by one-sided Jacobi (when the kept factor lies on the longer side -- m <= n
+ * for LEFT, m >= n for RIGHT -- and max(m, n) <= 512, on R^dag of a column-pivoted Householder
+ * QR of Theta^dag or Theta, which converges in few sweeps even when the singular values spread
+ * over many decades), keeping k = min(Dmax, m, n, #{sigma_i > max(cutoff *
  * sigma_1, 8 eps sqrt(max(m, n)) ||Theta||_F)}) >= 1 singular values (the truncation of the
  * two-site update; the second bound drops singular values at the rounding level of Theta).
  *   direction LEFT  (left-to-right sweep): A_out = U_k (left-orthonormal), B_out = S_k V_k^dag

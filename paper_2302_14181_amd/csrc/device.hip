@@ -566,7 +566,7 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
                  double* norm_dev, double* sigma_dev, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   // square: Jacobi on R^dag of the column-pivoted QR (a cold start needs few sweeps that way)
-  const SvdPlan p = (m == n && svd_qr_ok(m)) ? svd_plan_qr(m, direction) : svd_plan(m, n, direction);
+  const SvdPlan p = svd_qr_ok(m, n, direction) ? svd_plan_qr(m, n, direction) : svd_plan(m, n, direction);
   hipError_t e = svd_truncate(p, static_cast<const double2*>(Theta), Dmax, cutoff,
                               static_cast<double2*>(A_out), static_cast<double2*>(B_out), k_dev,
                               discarded_dev, norm_dev, sigma_dev, ws, ctx.dev->status,
@@ -795,13 +795,16 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         // whole time step since the last one), and a bond below Dmax is numerically
         // rank-deficient (its basis would need completing): square Theta then goes through the
         // pivoted QR, handing on a basis only where the next visit can use it
-        const bool qr = warm_on && m == n && svd_qr_ok(m) &&
-                        (sw == 0 || ctx.warm_dim[i] != m || !saturated[i + 1]);
-        const SvdPlan sp = qr ? svd_plan_qr(m, MPOEVO_LEFT) : svd_plan(m, n, MPOEVO_LEFT, warm_on);
+        // (rectangular Theta: when no basis of its size is at hand and the orientation the QR
+        // needs is the tall one)
+        const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_LEFT) &&
+                        (m == n ? (sw == 0 || ctx.warm_dim[i] != m || !saturated[i + 1])
+                                : ctx.warm_dim[i] != std::min(m, n));
+        const SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_LEFT) : svd_plan(m, n, MPOEVO_LEFT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = qr ? (saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
+        double2* wb = qr ? (m == n && saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
         if (qr && !wb) ctx.warm_dim[i] = 0;
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
@@ -830,12 +833,14 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
-        const bool qr = warm_on && m == n && svd_qr_ok(m) && (ctx.warm_dim[i] != m || !saturated[i + 1]);
-        const SvdPlan sp = qr ? svd_plan_qr(m, MPOEVO_RIGHT) : svd_plan(m, n, MPOEVO_RIGHT, warm_on);
+        const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_RIGHT) &&
+                        (m == n ? (ctx.warm_dim[i] != m || !saturated[i + 1])
+                                : ctx.warm_dim[i] != std::min(m, n));
+        const SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_RIGHT) : svd_plan(m, n, MPOEVO_RIGHT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = qr ? (saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
+        double2* wb = qr ? (m == n && saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
         if (qr && !wb) ctx.warm_dim[i] = 0;
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,

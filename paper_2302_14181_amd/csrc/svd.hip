@@ -406,7 +406,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   if (tid == 0) {  // squared rounding floor from the initial column norms (fixed order)
     double fro2 = 0.0;
     for (int j = 0; j < p.nx; ++j) fro2 += w.sigma[j];
-    const double fl = 8.0 * kEps * sqrt((double)mx);
+    const double fl = 8.0 * kEps * sqrt((double)p.frows);
     floor2_sh = fl * fl * fro2;
   }
   __syncthreads();
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(SvdPlan p, SvdWs w, in
     smax = fmax(smax, sig[i]);
     fro2 += sig[i] * sig[i];
   }
-  const double floor_abs = 8.0 * kEps * sqrt((double)p.mx) * sqrt(fro2);
+  const double floor_abs = 8.0 * kEps * sqrt((double)p.frows) * sqrt(fro2);
   const double thr = fmax(cutoff * smax, floor_abs);
   // every column clearly above the rounding floor: the normalised columns form a complete
   // orthonormal basis (used to precondition the next truncation at the same bond)
@@ -750,7 +750,7 @@ __global__ __launch_bounds__(kCompleteThreads) void svd_complete_kernel(SvdPlan 
   if (tid == 0) {
     double fro2 = 0.0;
     for (int j = 0; j < n; ++j) fro2 += w.sigma[j] * w.sigma[j];
-    floor_sh = 8.0 * kEps * sqrt((double)p.mx) * sqrt(fro2);
+    floor_sh = 8.0 * kEps * sqrt((double)p.frows) * sqrt(fro2);
   }
   __syncthreads();
   // rank of each good column among the good ones (columns j = tid, tid + 1024 never needed: n <= 1024)
@@ -1069,7 +1069,7 @@ size_t svd_ws_bound(int maxdim) {
     for (int n = 1; n <= maxdim; ++n)
       for (int dir = 0; dir < 2; ++dir) {
         best = std::max(best, svd_plan(m, n, dir, true).ws);
-        if (m == n && svd_qr_ok(m)) best = std::max(best, svd_plan_qr(m, dir).ws);
+        if (svd_qr_ok(m, n, dir)) best = std::max(best, svd_plan_qr(m, n, dir).ws);
       }
   memo[maxdim] = best;
   return best;
@@ -1084,6 +1084,8 @@ hipError_t svd_configure() {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsBytes));
   return hipSuccess;
 }
+
+void finish_plan(SvdPlan& p, size_t lds_cap);
 
 SvdPlan svd_plan(int m, int n, int direction, bool want_basis, size_t lds_cap) {
   SvdPlan p{};
@@ -1102,7 +1104,14 @@ SvdPlan svd_plan(int m, int n, int direction, bool want_basis, size_t lds_cap) {
   }
   p.mx = p.xconj == 0 ? m : n;
   p.nx = p.xconj == 0 ? n : m;
+  p.frows = p.mx;
   p.rank_max = std::min(m, n);
+  finish_plan(p, lds_cap);
+  return p;
+}
+
+// Block layout of the Jacobi kernel for the plan's mx, nx, acc.
+void finish_plan(SvdPlan& p, size_t lds_cap) {
   p.rmax = p.mx <= 256 ? 4 : (p.mx <= 512 ? 8 : 16);
   // Block width: small blocks spread a sweep over more workgroups (compute units) at the price
   // of more grid barriers per sweep; 8 columns (16 workgroups for 256 columns) balances the two
@@ -1122,20 +1131,38 @@ SvdPlan svd_plan(int m, int n, int direction, bool want_basis, size_t lds_cap) {
   p.threads = b * 64;
   p.lds = col_bytes * (size_t)2 * p.b;
   p.ws = ws_bytes(p.mx, p.nx, p.np, p.acc != 0, false);
-  return p;
 }
 
-bool svd_qr_ok(int n) { return n <= kQrMaxDim; }
+bool svd_qr_ok(int m, int n, int direction) {
+  return std::max(m, n) <= kQrMaxDim && (direction == 0 ? n >= m : m >= n);
+}
 
-SvdPlan svd_plan_qr(int n, int direction, size_t lds_cap) {
+SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap) {
   // the factor to keep is X's right singular vectors: U of Theta from X = Theta^dag (direction 0),
-  // V of Theta from X = Theta (direction 1)
-  SvdPlan p = svd_plan(n, n, direction, false, lds_cap);
+  // V of Theta from X = Theta (direction 1); X is tall (mx >= nx)
+  SvdPlan p{};
+  p.m = m;
+  p.n = n;
+  p.direction = direction;
   p.xconj = direction == 0 ? 1 : 0;
   p.acc = 0;
   p.qr = 1;
+  p.mx = p.xconj == 0 ? m : n;
+  p.nx = p.xconj == 0 ? n : m;
+  p.frows = p.mx;
+  p.rank_max = std::min(m, n);
+  finish_plan(p, lds_cap);
   p.ws = ws_bytes(p.mx, p.nx, p.np, false, true);
   return p;
+}
+
+// The plan of the Jacobi phase of a pivoted-QR plan: R^dag is nx x nx (the same column blocks).
+static SvdPlan rdag_plan(const SvdPlan& p) {
+  SvdPlan q = p;
+  q.mx = p.nx;
+  q.rmax = q.mx <= 256 ? 4 : (q.mx <= 512 ? 8 : 16);
+  q.lds = sizeof(double2) * (size_t)q.mx * 2 * q.b;
+  return q;
 }
 
 double svd_sweep_flop(const SvdPlan& p) {
@@ -1151,7 +1178,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
                         const double2* warm, double2* basis_out, bool coop) {
   if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx) ||
-      (p.qr && (p.m != p.n || p.acc || p.mx > kQrMaxDim)))
+      (p.qr && (p.mx < p.nx || p.acc || p.mx > kQrMaxDim)))
     return hipErrorInvalidConfiguration;
   if (p.qr) warm = nullptr;
   SvdWs w = carve(p, ws);
@@ -1198,14 +1225,15 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     MPOEVO_HIP_TRY(hipGetLastError());
     wj.X = w.aux;
   }
+  const SvdPlan pj = p.qr ? rdag_plan(p) : p;  // the plan of the Jacobi phase (R^dag: nx x nx)
   const int wpb = 4;
-  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, wj,
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, pj, wj,
                      status, 1);
   MPOEVO_HIP_TRY(hipGetLastError());
   {
     // above the rounding floor of a length-mx inner product (|err| <= mx eps |x| |y|)
     const double tol = kEps * std::max(16.0, (double)p.mx);
-    SvdPlan pp = p;
+    SvdPlan pp = pj;
     SvdWs ww = wj;
     double tt = tol;
     int* stp = status;
@@ -1213,16 +1241,16 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     void* args[] = {&pp, &ww, &tt, &stp, &swp};
     if (ev0) MPOEVO_HIP_TRY(hipEventRecord(ev0, st));
     if (coop)
-      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(jacobi_for(p), dim3(p.nb / 2), dim3(p.threads), args,
-                                                (unsigned)p.lds, st));
+      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(jacobi_for(pj), dim3(pj.nb / 2), dim3(pj.threads), args,
+                                                (unsigned)pj.lds, st));
     else
-      MPOEVO_HIP_TRY(hipLaunchKernel(jacobi_for(p), dim3(p.nb / 2), dim3(p.threads), args, p.lds, st));
+      MPOEVO_HIP_TRY(hipLaunchKernel(jacobi_for(pj), dim3(pj.nb / 2), dim3(pj.threads), args, pj.lds, st));
     if (ev1) MPOEVO_HIP_TRY(hipEventRecord(ev1, st));
   }
-  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, p, wj,
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, pj, wj,
                      status, 0);
   MPOEVO_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, p, wj, kcap, cutoff, k_dev,
+  hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, pj, wj, kcap, cutoff, k_dev,
                      disc_dev, norm_dev, sigma_dev);
   MPOEVO_HIP_TRY(hipGetLastError());
   // the kept factor comes from the columns when it lies on X's column side, else from Q (with
@@ -1232,7 +1260,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   {
     const long long total = (long long)(p.direction == 0 ? p.m : p.n) * kcap;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(svd_isometry_kernel, dim3(blocks), dim3(256), 0, st, p, wj, kcap, iso,
+    hipLaunchKernelGGL(svd_isometry_kernel, dim3(blocks), dim3(256), 0, st, pj, wj, kcap, iso,
                        from_q ? 1 : 0);
     MPOEVO_HIP_TRY(hipGetLastError());
   }
@@ -1240,9 +1268,9 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     if (square) {
       const long long total = (long long)p.mx * p.nx;
       const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
-      hipLaunchKernelGGL(svd_basis_kernel, dim3(blocks), dim3(256), 0, st, p, wj, basis_out);
+      hipLaunchKernelGGL(svd_basis_kernel, dim3(blocks), dim3(256), 0, st, pj, wj, basis_out);
       MPOEVO_HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(svd_complete_kernel, dim3(1), dim3(kCompleteThreads), 0, st, p, wj, basis_out);
+      hipLaunchKernelGGL(svd_complete_kernel, dim3(1), dim3(kCompleteThreads), 0, st, pj, wj, basis_out);
       MPOEVO_HIP_TRY(hipGetLastError());
     } else {  // the accumulated P Q (its first nx columns are contiguous)
       MPOEVO_HIP_TRY(hipMemcpyAsync(basis_out, w.Q, sizeof(double2) * (size_t)p.nx * p.nx,
