@@ -478,7 +478,10 @@ size_t local_apply_ws(const int* dims, int prec) {
 }
 
 size_t truncate_ws(int m, int n) {
-  return std::max(svd_plan(m, n, MPOEVO_LEFT).ws, svd_plan(m, n, MPOEVO_RIGHT).ws);
+  size_t ws = 0;
+  for (int dir : {MPOEVO_LEFT, MPOEVO_RIGHT})
+    ws = std::max(ws, svd_qr_ok(m, n, dir) ? svd_plan_qr(m, n, dir).ws : svd_plan(m, n, dir).ws);
+  return ws;
 }
 
 size_t step_ws(int L, int d, int Dmax, int wmax, int prec) {
@@ -565,7 +568,7 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
                  int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
                  double* norm_dev, double* sigma_dev, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
-  // square: Jacobi on R^dag of the column-pivoted QR (a cold start needs few sweeps that way)
+  // up to 512: Jacobi on R^dag of the column-pivoted QR (a cold start needs few sweeps that way)
   const SvdPlan p = svd_qr_ok(m, n, direction) ? svd_plan_qr(m, n, direction) : svd_plan(m, n, direction);
   hipError_t e = svd_truncate(p, static_cast<const double2*>(Theta), Dmax, cutoff,
                               static_cast<double2*>(A_out), static_cast<double2*>(B_out), k_dev,
@@ -795,8 +798,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         // whole time step since the last one), and a bond below Dmax is numerically
         // rank-deficient (its basis would need completing): square Theta then goes through the
         // pivoted QR, handing on a basis only where the next visit can use it
-        // (rectangular Theta: when no basis of its size is at hand and the orientation the QR
-        // needs is the tall one)
+        // (rectangular Theta: when no basis of its size is at hand)
         const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_LEFT) &&
                         (m == n ? (sw == 0 || ctx.warm_dim[i] != m || !saturated[i + 1])
                                 : ctx.warm_dim[i] != std::min(m, n));

@@ -18,8 +18,10 @@ struct SvdPlan {
   int rank_max;    // min(m, n)
   int rmax;        // rows per lane of the Jacobi kernel (mx <= 64 rmax)
   int b, nb, np;   // block width, number of blocks (even), padded column count
-  int qr;          // Jacobi runs on R^dag of the column-pivoted QR X Pi = Q R (X tall)
-  int frows;       // rows in the rounding floor 8 eps sqrt(frows) ||X||_F: X's rows (max(m, n))
+  int qr;          // Jacobi runs on R^dag of the column-pivoted QR X Pi = Q R
+  int frows;       // rows in the rounding floor 8 eps sqrt(frows) ||X||_F: X's rows
+  int np_alloc;    // columns of the per-column arrays (>= np, and >= the Jacobi phase's np with qr)
+  size_t aux_elems;  // (qr) elements of the buffer holding R^dag
   int threads;     // threads per Jacobi workgroup (one pair per wave)
   size_t lds;      // dynamic LDS bytes of the Jacobi kernel
   size_t ws;       // workspace bytes
@@ -37,14 +39,13 @@ SvdPlan svd_plan(int m, int n, int direction, bool want_basis = false,
                  size_t lds_cap = kSvdLdsBytes);
 
 // Plan for an m x n truncation preconditioned by a column-pivoted QR: X = Theta^dag
-// (direction 0) or Theta (direction 1), X Pi = Q R, one-sided Jacobi on R^dag, whose normalised
-// converged columns with rows permuted by Pi are X's right singular vectors, i.e. the factor
-// the direction keeps. For Theta whose singular values spread over many decades (the first
-// truncation of a bond in a time step) this converges in about 8 sweeps where Jacobi on X
-// needs 25-40.
+// (direction 0) or Theta (direction 1), X Pi = Q R (R upper trapezoidal, min(rows, cols) x
+// cols), one-sided Jacobi on R^dag, whose normalised converged columns with rows permuted by Pi
+// are X's right singular vectors, i.e. the factor the direction keeps. For Theta whose singular
+// values spread over many decades (the first truncation of a bond in a time step) this converges
+// in about 8 sweeps where Jacobi on X needs 25-40.
 SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap = kSvdLdsBytes);
-// Whether the pivoted-QR plan applies: X tall (n >= m for direction 0, m >= n for direction
-// 1) and max(m, n) <= 512.
+// Whether the pivoted-QR plan applies: max(m, n) <= 512.
 bool svd_qr_ok(int m, int n, int direction);
 
 // Largest workspace of any plan with m, n <= maxdim (memoised).

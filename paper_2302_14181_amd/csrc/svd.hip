@@ -69,18 +69,18 @@ struct SvdWs {  // carved from the caller's workspace
   double* qcand_v;      // [2][kMaxGrid] (qr) each workgroup's pivot candidate: norm^2 ...
   int* qcand_i;         // [2][kMaxGrid] ... and column
   double2* qcol;        // [2][nb / 2][mx] (qr) each workgroup's candidate column
-  int* qsteps;          // [1] (qr) steps taken (fewer than nx when the rest is exactly zero)
+  int* qsteps;          // [1] (qr) steps taken (fewer than min(mx, nx) when the rest is exactly zero)
   void* gemm;           // split-K scratch of the products (kGemmScratchBytes)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t ws_bytes(int mx, int nx, int np, bool acc, bool qr) {
+size_t ws_bytes(int mx, int nx, int np, bool acc, bool qr, int np_alloc, size_t aux_elems) {
   return align256(sizeof(double2) * (size_t)mx * np) +
-         (acc ? align256(sizeof(double2) * (size_t)nx * np) : 0) + align256(sizeof(double) * np) +
-         align256(sizeof(int) * np) + 256 + sizeof(unsigned) * kMaxGrid +
+         (acc ? align256(sizeof(double2) * (size_t)nx * np) : 0) + align256(sizeof(double) * np_alloc) +
+         align256(sizeof(int) * np_alloc) + 256 + sizeof(unsigned) * kMaxGrid +
          align256(sizeof(unsigned) * kMaxSweeps) + 256 +
-         (qr ? align256(sizeof(double2) * (size_t)mx * np) + 2 * align256(sizeof(int) * np) +
+         (qr ? align256(sizeof(double2) * aux_elems) + 2 * align256(sizeof(int) * np) +
                    align256(sizeof(unsigned) * (kMaxGrid + 1)) + align256(2 * sizeof(double) * kMaxGrid) +
                    align256(2 * sizeof(int) * kMaxGrid) + align256(2 * sizeof(double2) * (size_t)mx * np) + 256
               : 0) +
@@ -99,9 +99,9 @@ SvdWs carve(const SvdPlan& p, void* ws) {
     off += align256(sizeof(double2) * (size_t)p.nx * p.np);
   }
   w.sigma = reinterpret_cast<double*>(base + off);
-  off += align256(sizeof(double) * p.np);
+  off += align256(sizeof(double) * p.np_alloc);
   w.perm = reinterpret_cast<int*>(base + off);
-  off += align256(sizeof(int) * p.np);
+  off += align256(sizeof(int) * p.np_alloc);
   w.bar = reinterpret_cast<unsigned*>(base + off);
   off += 256;
   w.flags = reinterpret_cast<unsigned*>(base + off);
@@ -119,7 +119,7 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   w.qsteps = nullptr;
   if (p.qr) {
     w.aux = reinterpret_cast<double2*>(base + off);
-    off += align256(sizeof(double2) * (size_t)p.mx * p.np);
+    off += align256(sizeof(double2) * p.aux_elems);
     w.qperm = reinterpret_cast<int*>(base + off);
     off += align256(sizeof(int) * p.np);
     w.pinv = reinterpret_cast<int*>(base + off);
@@ -848,7 +848,7 @@ __device__ inline double wave_max1(double a) {
               __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h2[1]) << 32) | l2[1])));
 }
 
-// Householder QR with column pivoting of X (mx x nx, mx >= nx, column-major): at step j the
+// Householder QR with column pivoting of X (mx x nx, column-major; min(mx, nx) steps): at step j the
 // remaining column of largest norm becomes column j (pivots kept as a permutation), its reflector
 // H_j = I - tau v v^dag (v_j = 1) zeroes it below row j, and H_j^dag is applied to the remaining
 // columns. Spread over the Jacobi grid's workgroups (launched together, like the Jacobi
@@ -893,7 +893,8 @@ __global__ __launch_bounds__(256) void svd_qrcp_grid_kernel(SvdPlan p, SvdWs w, 
   __syncthreads();
   bool ok = true;
   int j = 0;
-  for (; j < n && ok; ++j) {
+  const int jmax = min(m, n);  // a wide X has rank <= mx
+  for (; j < jmax && ok; ++j) {
     const int par = j & 1;
     if (wave == 0) {  // this workgroup's candidate
       const double mine = (lane < C && !done[lane]) ? nrm2[lane] : -1.0;
@@ -1029,16 +1030,17 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
   }
 }
 
-// Y = R^dag into dst (nx x np column-major, padding columns zero): Y(i, c) = conj(R(c, i)) for
-// c <= i, R(c, i) = X[qperm[i]][c].
-__global__ void svd_rdag_kernel(SvdPlan p, SvdWs w, double2* __restrict__ dst) {
-  const int n = p.nx, m = p.mx;
-  const long long total = (long long)n * p.np;
+// Y = R^dag into dst (q.mx = nx rows, q.np columns, column-major, columns from q.nx = min(mx, nx)
+// on zero): Y(i, c) = conj(R(c, i)) for c <= i, R(c, i) = X[qperm[i]][c] (p: X's plan, q: the
+// Jacobi phase's).
+__global__ void svd_rdag_kernel(SvdPlan p, SvdPlan q, SvdWs w, double2* __restrict__ dst) {
+  const int n = p.nx, m = p.mx, r = q.nx;
+  const long long total = (long long)n * q.np;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     const int c = (int)(idx / n), i = (int)(idx % n);
     double2 v{0.0, 0.0};
-    if (c < n && c <= i) {
+    if (c < r && c <= i) {
       const double2 r = w.X[(long long)w.qperm[i] * m + c];
       v = double2{r.x, -r.y};
     }
@@ -1130,16 +1132,32 @@ void finish_plan(SvdPlan& p, size_t lds_cap) {
   p.np = nb * b;
   p.threads = b * 64;
   p.lds = col_bytes * (size_t)2 * p.b;
-  p.ws = ws_bytes(p.mx, p.nx, p.np, p.acc != 0, false);
+  p.np_alloc = p.np;
+  p.aux_elems = 0;
+  p.ws = ws_bytes(p.mx, p.nx, p.np, p.acc != 0, false, p.np_alloc, 0);
 }
 
 bool svd_qr_ok(int m, int n, int direction) {
-  return std::max(m, n) <= kQrMaxDim && (direction == 0 ? n >= m : m >= n);
+  (void)direction;
+  return std::max(m, n) <= kQrMaxDim;
+}
+
+// The plan of the Jacobi phase of a pivoted-QR plan: R^dag is nx x min(mx, nx).
+static SvdPlan rdag_plan(const SvdPlan& p) {
+  SvdPlan q = p;
+  q.mx = p.nx;
+  q.nx = std::min(p.mx, p.nx);
+  finish_plan(q, kSvdLdsBytes);
+  q.frows = p.frows;
+  q.qr = 1;
+  q.np_alloc = std::max(p.np, q.np);
+  q.aux_elems = p.aux_elems;
+  return q;
 }
 
 SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap) {
   // the factor to keep is X's right singular vectors: U of Theta from X = Theta^dag (direction 0),
-  // V of Theta from X = Theta (direction 1); X is tall (mx >= nx)
+  // V of Theta from X = Theta (direction 1)
   SvdPlan p{};
   p.m = m;
   p.n = n;
@@ -1149,20 +1167,14 @@ SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap) {
   p.qr = 1;
   p.mx = p.xconj == 0 ? m : n;
   p.nx = p.xconj == 0 ? n : m;
-  p.frows = p.mx;
+  p.frows = std::max(p.mx, p.nx);
   p.rank_max = std::min(m, n);
   finish_plan(p, lds_cap);
-  p.ws = ws_bytes(p.mx, p.nx, p.np, false, true);
+  const SvdPlan q = rdag_plan(p);
+  p.np_alloc = std::max(p.np, q.np);
+  p.aux_elems = std::max((size_t)p.mx * p.np, (size_t)q.mx * q.np);
+  p.ws = ws_bytes(p.mx, p.nx, p.np, false, true, p.np_alloc, p.aux_elems);
   return p;
-}
-
-// The plan of the Jacobi phase of a pivoted-QR plan: R^dag is nx x nx (the same column blocks).
-static SvdPlan rdag_plan(const SvdPlan& p) {
-  SvdPlan q = p;
-  q.mx = p.nx;
-  q.rmax = q.mx <= 256 ? 4 : (q.mx <= 512 ? 8 : 16);
-  q.lds = sizeof(double2) * (size_t)q.mx * 2 * q.b;
-  return q;
 }
 
 double svd_sweep_flop(const SvdPlan& p) {
@@ -1178,7 +1190,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
                         const double2* warm, double2* basis_out, bool coop) {
   if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx) ||
-      (p.qr && (p.mx < p.nx || p.acc || p.mx > kQrMaxDim)))
+      (p.qr && (p.acc || std::max(p.mx, p.nx) > kQrMaxDim)))
     return hipErrorInvalidConfiguration;
   if (p.qr) warm = nullptr;
   SvdWs w = carve(p, ws);
@@ -1206,6 +1218,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     MPOEVO_HIP_TRY(gemm_launch(g, true, true, st));
   }
   SvdWs wj = w;  // what Jacobi rotates: X itself, or R^dag of the column-pivoted QR of X
+  const SvdPlan pj = p.qr ? rdag_plan(p) : p;  // the plan of the Jacobi phase (R^dag: nx x min(mx, nx))
   if (p.qr) {
     SvdPlan pp = p;
     SvdWs ww = w;
@@ -1219,20 +1232,19 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
       MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(p.nb / 2), dim3(256), args, lds, st));
     hipLaunchKernelGGL(svd_qrperm_kernel, dim3(1), dim3(1024), 0, st, p, w);
     MPOEVO_HIP_TRY(hipGetLastError());
-    const long long total = (long long)p.nx * p.np;
+    const long long total = (long long)pj.mx * pj.np;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
-    hipLaunchKernelGGL(svd_rdag_kernel, dim3(blocks), dim3(256), 0, st, p, w, w.aux);
+    hipLaunchKernelGGL(svd_rdag_kernel, dim3(blocks), dim3(256), 0, st, p, pj, w, w.aux);
     MPOEVO_HIP_TRY(hipGetLastError());
     wj.X = w.aux;
   }
-  const SvdPlan pj = p.qr ? rdag_plan(p) : p;  // the plan of the Jacobi phase (R^dag: nx x nx)
   const int wpb = 4;
-  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, pj, wj,
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((pj.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, pj, wj,
                      status, 1);
   MPOEVO_HIP_TRY(hipGetLastError());
   {
     // above the rounding floor of a length-mx inner product (|err| <= mx eps |x| |y|)
-    const double tol = kEps * std::max(16.0, (double)p.mx);
+    const double tol = kEps * std::max(16.0, (double)std::max(p.mx, pj.mx));
     SvdPlan pp = pj;
     SvdWs ww = wj;
     double tt = tol;
@@ -1247,7 +1259,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
       MPOEVO_HIP_TRY(hipLaunchKernel(jacobi_for(pj), dim3(pj.nb / 2), dim3(pj.threads), args, pj.lds, st));
     if (ev1) MPOEVO_HIP_TRY(hipEventRecord(ev1, st));
   }
-  hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, pj, wj,
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((pj.nx + wpb - 1) / wpb), dim3(64 * wpb), 0, st, pj, wj,
                      status, 0);
   MPOEVO_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, pj, wj, kcap, cutoff, k_dev,

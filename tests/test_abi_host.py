@@ -87,6 +87,11 @@ def test_mpo_build_errors():
 
 def test_workspace_queries():
     assert mpoevo.workspace_size(mpoevo.CALL_TRUNCATE, [512, 512], mpoevo.FP64) > 512 * 512 * 16
+    # up to 512 the truncation goes through the pivoted QR: besides the 32 MiB product scratch its
+    # workspace holds X, R^dag and two candidate columns per workgroup (at least 4 x 512^2 complex)
+    for m, n in [(512, 512), (256, 512), (512, 130)]:
+        need = (32 << 20) + 4 * max(m, n) * min(m, n) * 16
+        assert mpoevo.workspace_size(mpoevo.CALL_TRUNCATE, [m, n], mpoevo.FP64) >= need, (m, n)
     s64 = mpoevo.workspace_size(mpoevo.CALL_STEP, [16, 2, 32, 3], mpoevo.FP64)
     s32 = mpoevo.workspace_size(mpoevo.CALL_STEP, [16, 2, 32, 3], mpoevo.FP32)
     assert s64 > 0 and s32 > 0
