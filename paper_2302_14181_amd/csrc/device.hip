@@ -356,7 +356,7 @@ struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
   size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
-      off_basis, basiscap, off_token, off_gemm, off_xws, total;
+      off_cplt, off_basis, basiscap, off_token, off_gemm, off_xws, total;
 };
 
 StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
@@ -388,6 +388,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_site_tmp = take(sizeof(double2) * s.sitecap);
   s.off_site_tmp2 = take(sizeof(double2) * s.sitecap);
   s.off_sweeps = take(sizeof(int) * (size_t)8 * L);
+  s.off_cplt = take(sizeof(int) * (size_t)8 * L);  // per visit: the bond matrix had full rank
   // one unitary per bond (the Jacobi preconditioner carried between visits and steps)
   s.basiscap = (size_t)d * Dmax * d * Dmax;
   s.off_basis = take(sizeof(double2) * s.basiscap * (size_t)std::max(L - 1, 1));
@@ -671,7 +672,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   const int sig[5] = {L, d, Dmax, wmax, prec};
   unsigned long long* token_dev = reinterpret_cast<unsigned long long*>(base + lay.off_token);
   bool reuse = warm_on && ctx.warm_ws == ws && std::equal(sig, sig + 5, ctx.warm_sig) &&
-               (int)ctx.warm_dim.size() == L - 1;
+               (int)ctx.warm_dim.size() == L - 1 && (int)ctx.warm_deficient.size() == L - 1;
   if (reuse) {  // the workspace must still hold what this handle's last step left there
     unsigned long long tok = 0;
     hipError_t et = hipMemcpyAsync(&tok, token_dev, sizeof(tok), hipMemcpyDeviceToHost, st);
@@ -679,7 +680,10 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     if (et != hipSuccess) return hip_fail(ctx, et, "step: reading the workspace token");
     reuse = tok == ctx.warm_token;
   }
-  if (!reuse) ctx.warm_dim.assign(std::max(L - 1, 0), 0);
+  if (!reuse) {
+    ctx.warm_dim.assign(std::max(L - 1, 0), 0);
+    ctx.warm_deficient.assign(std::max(L - 1, 0), 0);
+  }
   ctx.warm_ws = nullptr;  // re-armed when this step completes
   // The unitary kept for bond i has the order of X's column count, min(m, n); a change of shape
   // restarts it from the identity.
@@ -715,6 +719,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     prof = &prof_obj;
   }
   int* sweeps_buf = reinterpret_cast<int*>(base + lay.off_sweeps);
+  int* cplt_buf = reinterpret_cast<int*>(base + lay.off_cplt);
   struct JacRec { size_t ev; double flop_per_sweep; int slot; };
   std::vector<JacRec> jac_recs;
   double gflop = 0.0;
@@ -776,6 +781,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   const int nvis = opts->nsweeps * 2 * (L - 1);
   int last_visit_k_slot = 0;
   std::vector<int> k_slot_of_bond(L, -1);
+  std::vector<int> bond_of_visit(nvis, 0);
   for (int sw = 0; sw < opts->nsweeps; ++sw) {
     // left to right
     for (int i = 0; i <= L - 2; ++i, ++visit) {
@@ -795,22 +801,25 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       const int kcap = std::min(Dmax, std::min(m, n));
       {
         // the first visit of a bond in a step has no fresh preconditioner (Theta moved by a
-        // whole time step since the last one), and a bond below Dmax is numerically
-        // rank-deficient (its basis would need completing): square Theta then goes through the
-        // pivoted QR, handing on a basis only where the next visit can use it
-        // (rectangular Theta: when no basis of its size is at hand)
+        // whole time step since the last one), and a bond below Dmax, or one whose matrix the
+        // last step found numerically rank-deficient, would need its basis completed: square
+        // Theta then goes through the pivoted QR, handing on a basis only where the next visit
+        // can use it (rectangular Theta: when no basis of its size is at hand)
+        const bool deficient = !saturated[i + 1] || ctx.warm_deficient[i];
         const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_LEFT) &&
-                        (m == n ? (sw == 0 || ctx.warm_dim[i] != m || !saturated[i + 1])
+                        (m == n ? (sw == 0 || ctx.warm_dim[i] != m || deficient)
                                 : ctx.warm_dim[i] != std::min(m, n));
         const SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_LEFT) : svd_plan(m, n, MPOEVO_LEFT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = qr ? (m == n && saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
+        double2* wb = qr ? (m == n && !deficient ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
         if (qr && !wb) ctx.warm_dim[i] = 0;
+        bond_of_visit[visit] = i;
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi));
+                              j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi,
+                              cplt_buf + visit));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;
@@ -835,18 +844,24 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
       const int kcap = std::min(Dmax, std::min(m, n));
       {
+        const bool deficient = !saturated[i + 1] || ctx.warm_deficient[i];
         const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_RIGHT) &&
-                        (m == n ? (ctx.warm_dim[i] != m || !saturated[i + 1])
+                        (m == n ? (ctx.warm_dim[i] != m || deficient)
                                 : ctx.warm_dim[i] != std::min(m, n));
         const SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_RIGHT) : svd_plan(m, n, MPOEVO_RIGHT, warm_on);
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
-        double2* wb = qr ? (m == n && saturated[i + 1] ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
+        // the last visit of a square bond in the step hands on no basis: the next step's first
+        // visit starts from the pivoted QR (a warm start keeps its input unitary in the slot)
+        const bool last = sw + 1 == opts->nsweeps && m == n && svd_qr_ok(m, n, MPOEVO_LEFT);
+        double2* wb = qr ? (m == n && !deficient && !last ? basis_slot(i, m) : nullptr) : warm_for(i, m, n);
         if (qr && !wb) ctx.warm_dim[i] = 0;
+        bond_of_visit[visit] = i;
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
-                              j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi));
+                              j1, sweeps_buf + visit, qr ? nullptr : wb, last ? nullptr : wb,
+                              ctx.coop_jacobi, cplt_buf + visit));
         if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
       }
       P[i + 1] = kcap;
@@ -863,9 +878,10 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     return hipGetLastError();
   }());
   // read back the kept ranks and statistics (one synchronisation per step)
-  std::vector<int> kh(nvis), swh(nvis);
+  std::vector<int> kh(nvis), swh(nvis), ch(nvis);
   std::vector<double> dh(nvis), nh(nvis);
   STEP_TRY(hipMemcpyAsync(swh.data(), sweeps_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
+  STEP_TRY(hipMemcpyAsync(ch.data(), cplt_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(kh.data(), kbuf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(dh.data(), dbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(nh.data(), nbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
@@ -874,6 +890,12 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   if (sres != MPOEVO_OK) return sres;
   std::vector<int> Pact(L + 1, 1);
   for (int b = 1; b < L; ++b) Pact[b] = kh[k_slot_of_bond[b]];
+  // a bond is taken as rank-deficient when any of its truncations in this step was (near the
+  // onset of the rank deficiency the visits of one bond disagree, and a needless QR costs less
+  // than a completion)
+  std::fill(ctx.warm_deficient.begin(), ctx.warm_deficient.end(), 0);
+  for (int v = 0; v < nvis; ++v)
+    if (ch[v] == 0) ctx.warm_deficient[bond_of_visit[v]] = 1;
   // compact phi into the caller's site buffers
   for (int i = 0; i < L; ++i) {
     const long long n = (long long)Pact[i] * d * Pact[i + 1];

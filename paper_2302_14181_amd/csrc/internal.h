@@ -29,6 +29,9 @@ struct Context {
   int warm_sig[5] = {0, 0, 0, 0, 0};
   unsigned long long warm_token = 0;  // also stored in the workspace by the step that wrote them
   std::vector<int> warm_dim;
+  // per bond: a truncation of the last step found the bond matrix numerically rank-deficient
+  // (its columns would need completing to hand on a basis)
+  std::vector<char> warm_deficient;
   // Jacobi launches: cooperative on a handle; ordinary (overlapping other streams) on the
   // per-chain contexts of step_batched, which bound the workgroups in flight themselves.
   bool coop_jacobi = true;

@@ -72,12 +72,15 @@ hipError_t svd_configure();
 // launch that can overlap work on other streams; the caller must keep the workgroups of all
 // Jacobi launches in flight at once within what the device holds together (one per compute
 // unit), and the kernel's bounded waits turn a violation into a barrier-timeout status.
+// complete_dev (device int, nullable): 1 when every singular value lies clearly above the
+// rounding floor (X numerically of full column rank), else 0; a square basis_out then needs
+// the costly completion of its columns.
 hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double cutoff,
                         double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                         int* sweeps_dev = nullptr, const double2* warm = nullptr,
-                        double2* basis_out = nullptr, bool coop = true);
+                        double2* basis_out = nullptr, bool coop = true, int* complete_dev = nullptr);
 
 // Workgroups of the Jacobi launch of a plan.
 inline int svd_grid(const SvdPlan& p) { return p.nb / 2; }

@@ -569,7 +569,7 @@ __global__ void svd_norms_kernel(SvdPlan p, SvdWs w, int* status, int squared) {
 __global__ __launch_bounds__(1024) void svd_select_kernel(SvdPlan p, SvdWs w, int kcap,
                                                           double cutoff, int* k_dev,
                                                           double* disc_dev, double* norm_dev,
-                                                          double* sigma_dev) {
+                                                          double* sigma_dev, int* complete_dev) {
   __shared__ double sig[1024];
   __shared__ int rank_of[1024];
   __shared__ double red[1024];
@@ -628,6 +628,7 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(SvdPlan p, SvdWs w, in
     const double tot = red[0], kept = kept_part[0];
     w.k_shared[0] = k;
     w.k_shared[1] = complete ? 1 : 0;
+    if (complete_dev) *complete_dev = complete ? 1 : 0;
     if (k_dev) *k_dev = k;
     if (disc_dev) *disc_dev = tot > 0.0 ? fmax(0.0, (tot - kept) / tot) : 0.0;
     if (norm_dev) *norm_dev = sqrt(kept);
@@ -1188,7 +1189,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
-                        const double2* warm, double2* basis_out, bool coop) {
+                        const double2* warm, double2* basis_out, bool coop, int* complete_dev) {
   if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx) ||
       (p.qr && (p.acc || std::max(p.mx, p.nx) > kQrMaxDim)))
     return hipErrorInvalidConfiguration;
@@ -1263,7 +1264,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                      status, 0);
   MPOEVO_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(svd_select_kernel, dim3(1), dim3(1024), 0, st, pj, wj, kcap, cutoff, k_dev,
-                     disc_dev, norm_dev, sigma_dev);
+                     disc_dev, norm_dev, sigma_dev, complete_dev);
   MPOEVO_HIP_TRY(hipGetLastError());
   // the kept factor comes from the columns when it lies on X's column side, else from Q (with
   // the pivoted QR it is always the columns, i.e. X's right singular vectors)
