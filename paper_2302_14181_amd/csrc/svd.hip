@@ -256,13 +256,12 @@ __global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, Sv
 // for the flags of the two workgroups that wrote them (acquire), and at the end of a sweep every
 // workgroup waits for all flags. A wait longer than the timeout (or another workgroup's timeout)
 // sets bar[2] and makes every waiting workgroup return false; all workgroups then leave the sweep
-// loop.
+// loop. The waits poll with relaxed loads and acquire once, by a fence after the flags are seen
+// (an acquiring load in the poll would invalidate the L2 cache on every iteration).
 __device__ void publish_round(unsigned* flags, unsigned gen) {
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
+  if (threadIdx.x == 0)
     __hip_atomic_store(&flags[blockIdx.x], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
 }
 
 // Waits until flags[j] >= gen for j = f0, f1 (nblocks < 0) or for every j < nblocks.
@@ -276,11 +275,11 @@ __device__ bool wait_flags(unsigned* flags, unsigned* bar, int f0, int f1, int n
     while (true) {
       int mine = 1;
       if (nblocks < 0) {
-        if (lane == 0) mine = __hip_atomic_load(&flags[f0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
-        if (lane == 1) mine = __hip_atomic_load(&flags[f1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+        if (lane == 0) mine = __hip_atomic_load(&flags[f0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+        if (lane == 1) mine = __hip_atomic_load(&flags[f1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gen;
       } else {
         for (int j = lane; j < nblocks; j += 64)
-          mine &= __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen;
+          mine &= __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gen;
       }
       if (__all(mine)) break;
       if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
