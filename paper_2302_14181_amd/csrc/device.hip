@@ -809,7 +809,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_LEFT) &&
                         (m == n ? (sw == 0 || ctx.warm_dim[i] != m || deficient)
                                 : ctx.warm_dim[i] != std::min(m, n));
-        const SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_LEFT) : svd_plan(m, n, MPOEVO_LEFT, warm_on);
+        SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_LEFT) : svd_plan(m, n, MPOEVO_LEFT, warm_on);
+        if (!fp64) sp.accept = kSvdAcceptFp32;
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));
@@ -848,7 +849,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_RIGHT) &&
                         (m == n ? (ctx.warm_dim[i] != m || deficient)
                                 : ctx.warm_dim[i] != std::min(m, n));
-        const SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_RIGHT) : svd_plan(m, n, MPOEVO_RIGHT, warm_on);
+        SvdPlan sp = qr ? svd_plan_qr(m, n, MPOEVO_RIGHT) : svd_plan(m, n, MPOEVO_RIGHT, warm_on);
+        if (!fp64) sp.accept = kSvdAcceptFp32;
         hipEvent_t j0 = nullptr, j1 = nullptr;
         size_t jf = 0;
         if (prof) STEP_TRY(prof->pair(&j0, &j1, &jf));

@@ -22,10 +22,18 @@ struct SvdPlan {
   int frows;       // rows in the rounding floor 8 eps sqrt(frows) ||X||_F: X's rows
   int np_alloc;    // columns of the per-column arrays (>= np, and >= the Jacobi phase's np with qr)
   size_t aux_elems;  // (qr) elements of the buffer holding R^dag
+  double accept;   // a sweep whose largest relative inner product is at most this is the last
+                   // (0: only the sweep that finds every pair below the rounding tolerance)
   int threads;     // threads per Jacobi workgroup (one pair per wave)
   size_t lds;      // dynamic LDS bytes of the Jacobi kernel
   size_t ws;       // workspace bytes
 };
+
+// Early end of the Jacobi iteration for bond matrices formed by FP32 contractions (relative
+// rounding about 1e-7): cyclic Jacobi converges quadratically, so after a sweep whose largest
+// relative inner product was mu the columns are orthogonal to about mu^2 <= 1e-9, far below what
+// the input determines, and the sweep that would only confirm it is skipped.
+constexpr double kSvdAcceptFp32 = 3e-5;
 
 // LDS budget of the Jacobi kernel (bytes); the workspace size depends on it, so it is a
 // build constant rather than a device query (device_init checks that the device provides it).

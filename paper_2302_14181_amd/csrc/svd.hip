@@ -534,7 +534,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
     if (!ok || !(ok = wait_flags(w.flags, w.bar, 0, 0, (int)nblk, gen))) break;
     const float mxr = __uint_as_float(
         __hip_atomic_load(&w.sweep_max[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-    if ((double)mxr <= tol || (double)mxr <= kAccept) break;
+    if ((double)mxr <= tol || (double)mxr <= kAccept || (double)mxr <= p.accept) break;
   }
   if (blockIdx.x == 0 && tid == 0) {
     atomicMax(&status[1], sweep + 1);

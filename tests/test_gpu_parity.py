@@ -339,6 +339,40 @@ def test_step_warm_started_truncations_match_cold_and_oracle(mp, handle):
     assert sum(tot_w[1:]) < sum(tot_c[1:])
 
 
+def test_fp32_step_sweep_end_keeps_fidelity_and_isometries(mp, handle):
+    """FP32 steps end the Jacobi iteration after the sweep whose largest relative inner product is
+    below kSvdAcceptFp32 (quadratic convergence leaves about its square). On a saturated state
+    (square 128 x 128 bond matrices, warm-started visits), three chained FP32 steps each stay within
+    infidelity 1e-10 of the FP64 step from the same input, and the right-canonical sites stay
+    isometric to 1e-9."""
+    _say("fp32 sweep end L=14 D=64 saturated, 3 steps")
+    L, D = 14, 64
+    rng = np.random.default_rng(23)
+    psi = _normalise(wl.random_mps(rng, L, 2, D))
+    H = wl.tfim(1.5)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    dw = mp.DeviceMPO([W] * L)
+    d32 = mp.DeviceMPS(psi, Dmax=D)
+    ws32 = mp.step_workspace(d32, dw, mp.FP32)
+    sw32, sw64 = [], []
+    for s in range(3):
+        before = d32.to_numpy()
+        st32 = mp.step(handle, d32, dw, prec=mp.FP32, input_right_canonical=s > 0, workspace=ws32)
+        d64 = mp.DeviceMPS(before, Dmax=D)
+        st64 = mp.step(handle, d64, dw, prec=mp.FP64, input_right_canonical=s > 0)
+        a, b = d32.to_numpy(), d64.to_numpy()
+        infid = 1 - abs(ofit.overlap(a, b)) ** 2
+        iso = max(float(np.max(np.abs(B.reshape(B.shape[0], -1) @ B.reshape(B.shape[0], -1).conj().T
+                                      - np.eye(B.shape[0])))) for B in a[1:])
+        print(f"  step {s}: infidelity {infid:.2e} isometry {iso:.1e} sweeps fp32 {st32.svd_sweeps_total}"
+              f" fp64 {st64.svd_sweeps_total}", flush=True)
+        assert infid < 1e-10, (s, infid)
+        assert iso < 1e-9, (s, iso)
+        sw32.append(st32.svd_sweeps_total)
+        sw64.append(st64.svd_sweeps_total)
+    assert all(t > 0 for t in sw32 + sw64)
+
+
 def _hamiltonian_mpo_from_blocks(H):
     """[[I, C, Dloc], [0, A, B], [0, 0, I]] assembled here from the Jordan blocks (Sec. 2.3)."""
     d, chi = H.Dloc.shape[0], H.B.shape[0]
