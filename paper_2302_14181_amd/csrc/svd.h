@@ -38,8 +38,8 @@ constexpr double kSvdAcceptFp32 = 3e-5;
 // LDS budget of the Jacobi kernel (bytes); the workspace size depends on it, so it is a
 // build constant rather than a device query (device_init checks that the device provides it).
 constexpr size_t kSvdLdsBytes = 128 * 1024;
-// Dynamic LDS of the pivoted-QR factorisation at its largest size: 17 columns of 512 rows.
-constexpr size_t kQrLdsBytes = 16 * 17 * 512;
+// Dynamic LDS of the pivoted-QR factorisation at its largest size: 16 columns of 512 rows.
+constexpr size_t kQrLdsBytes = 16 * 16 * 512;
 
 // Plan for an m x n truncation in the given direction. want_basis: the call will ask for the
 // preconditioner of the next truncation (rectangular Theta then accumulates Q).

@@ -852,151 +852,158 @@ __device__ inline double wave_max1(double a) {
 // remaining column of largest norm becomes column j (pivots kept as a permutation), its reflector
 // H_j = I - tau v v^dag (v_j = 1) zeroes it below row j, and H_j^dag is applied to the remaining
 // columns. Spread over the Jacobi grid's workgroups (launched together, like the Jacobi
-// kernel): workgroup g keeps columns [g C, g C + C) (C = 2b) of X in LDS. Per step j every
-// workgroup publishes its remaining column of largest norm (the column itself, its norm and
-// index; flag = j + 1) and waits for all others; each then takes the overall largest (ties: the
-// smallest index), forms its reflector itself (the same arithmetic on the same data everywhere,
-// so one exchange per step suffices), applies H_j^dag to its remaining columns in LDS and
-// recomputes their norms below row j; the owner records the pivot and R(j, j). Two buffers (by
-// the parity of j) keep consecutive steps apart. At the end each workgroup writes its columns
-// back: R(r, c) = X[qperm[c]][r] for r <= c. Waits are bounded (barrier-timeout status).
-__global__ __launch_bounds__(256) void svd_qrcp_grid_kernel(SvdPlan p, SvdWs w, int* status) {
-  extern __shared__ double2 slab[];  // [C][mx] columns, then [mx] the reflector
-  __shared__ double nrm2[2 * 16];
-  __shared__ int done[2 * 16];
-  __shared__ double best_v;
-  __shared__ int best_c, best_g, mine_k;
-  __shared__ double2 tau_sh;
-  __shared__ double beta_sh;
+// kernel): workgroup g keeps columns [g C, g C + C) (C = 2b <= 16) of X in LDS, one wave per
+// column. Per step j wave 0 publishes the workgroup's remaining column of largest norm (the
+// column itself, its norm and index; flag = j + 1) and waits for all others; then every wave
+// takes the overall largest (ties: the smallest index), loads the pivot column into registers,
+// forms its reflector itself (the same arithmetic on the same data everywhere, so one exchange
+// per step suffices and no wave waits for another), applies H_j^dag to its own column and
+// recomputes its norm below row j; the owner's wave records the pivot and R(j, j). Two buffers
+// (by the parity of j) keep consecutive steps apart. At the end each workgroup writes its
+// columns back: R(r, c) = X[qperm[c]][r] for r <= c. Waits are bounded (barrier-timeout status).
+// RM: rows per lane (mx <= 64 RM).
+constexpr int kQrThreads = 1024;
+template <int RM>
+__global__ __launch_bounds__(kQrThreads) void svd_qrcp_grid_kernel(SvdPlan p, SvdWs w, int* status) {
+  extern __shared__ double2 slab[];  // [C][mx] columns
+  __shared__ double nrm2[16];
+  __shared__ int done[16];
   const int m = p.mx, n = p.nx, C = 2 * p.b, nwg = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c_lo = g * C;
-  double2* vsh = slab + (long long)C * m;
   double2* X = w.X;
   for (long long idx = tid; idx < (long long)C * m; idx += blockDim.x) {
     const int k = (int)(idx / m), i = (int)(idx % m);
     slab[idx] = c_lo + k < n ? X[(long long)(c_lo + k) * m + i] : double2{0.0, 0.0};
   }
   __syncthreads();
-  for (int k = wave; k < C; k += 4) {
+  if (wave < C) {
     double sq = 0.0, dummy = 0.0;
     for (int i = lane; i < m; i += 64) {
-      const double2 x = slab[(long long)k * m + i];
+      const double2 x = slab[(long long)wave * m + i];
       sq = fma(x.x, x.x, fma(x.y, x.y, sq));
     }
     wave_sum2(sq, dummy);
     if (lane == 0) {
-      nrm2[k] = sq;
-      done[k] = c_lo + k < n ? 0 : 1;
+      nrm2[wave] = sq;
+      done[wave] = c_lo + wave < n ? 0 : 1;
     }
   }
-  __syncthreads();
   bool ok = true;
   int j = 0;
   const int jmax = min(m, n);  // a wide X has rank <= mx
   for (; j < jmax && ok; ++j) {
     const int par = j & 1;
-    if (wave == 0) {  // this workgroup's candidate
+    __syncthreads();  // norms and done flags of the previous step
+    if (wave == 0) {  // this workgroup's candidate, published with its column (rows j..)
       const double mine = (lane < C && !done[lane]) ? nrm2[lane] : -1.0;
       const double wmax = wave_max1(mine);
       const unsigned long long hit = __ballot(mine == wmax);
-      if (lane == 0) {
-        mine_k = __builtin_ctzll(hit);
-        w.qcand_v[par * kMaxGrid + g] = wmax;
-        w.qcand_i[par * kMaxGrid + g] = c_lo + mine_k;
-      }
-    }
-    __syncthreads();
-    {
-      const double2* src = slab + (long long)mine_k * m;
+      const int kk = hit ? __builtin_ctzll(hit) : 0;  // (no hit only for a NaN norm)
+      const double2* src = slab + (long long)kk * m;
       double2* dst = w.qcol + ((long long)par * nwg + g) * m;
-      for (int i = j + tid; i < m; i += blockDim.x) dst[i] = src[i];
+      for (int i = j + lane; i < m; i += 64) dst[i] = src[i];
+      if (lane == 0) {
+        w.qcand_v[par * kMaxGrid + g] = wmax;
+        w.qcand_i[par * kMaxGrid + g] = c_lo + kk;
+      }
     }
     publish_round(w.qflags, (unsigned)(j + 1));
     if (!(ok = wait_flags(w.qflags, w.bar, 0, 0, nwg, (unsigned)(j + 1)))) break;
-    if (wave == 0) {  // the overall pivot (every workgroup computes the same)
-      double v = -1.0;
-      int c = n, gg = 0;
-      for (int k = lane; k < nwg; k += 64) {
-        const double kv = __hip_atomic_load(&w.qcand_v[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int kc = __hip_atomic_load(&w.qcand_i[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (kv > v || (kv == v && kc < c)) { v = kv; c = kc; gg = k; }
-      }
+    // the overall pivot (every wave computes the same)
+    double v = -1.0;
+    int c = n, gg = 0;
+    for (int k = lane; k < nwg; k += 64) {
+      const double kv = __hip_atomic_load(&w.qcand_v[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int kc = __hip_atomic_load(&w.qcand_i[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (kv > v || (kv == v && kc < c)) { v = kv; c = kc; gg = k; }
+    }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oc = __shfl_xor(c, off, 64);
-        const int og = __shfl_xor(gg, off, 64);
-        if (ov > v || (ov == v && oc < c)) { v = ov; c = oc; gg = og; }
-      }
-      if (lane == 0) { best_v = v; best_c = c; best_g = gg; }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int oc = __shfl_xor(c, off, 64);
+      const int og = __shfl_xor(gg, off, 64);
+      if (ov > v || (ov == v && oc < c)) { v = ov; c = oc; gg = og; }
     }
-    __syncthreads();
-    if (!(best_v > 0.0)) break;  // the remaining columns are exactly zero below row j
-    {  // the pivot column (rows j..) into LDS
-      const double2* src = w.qcol + ((long long)par * nwg + best_g) * m;
-      for (int i = j + tid; i < m; i += blockDim.x) vsh[i] = src[i];
+    if (!(v > 0.0)) break;  // the remaining columns are exactly zero below row j (uniform)
+    if (wave >= C) continue;
+    // the pivot column (rows j..) and its reflector: v_j = 1, v_i = x_i sc below, tau
+    const double2* pc = w.qcol + ((long long)par * nwg + gg) * m;
+    double2 x[RM];
+    double sq = 0.0;
+#pragma unroll
+    for (int t = 0; t < RM; ++t) {
+      const int row = lane + 64 * t;
+      x[t] = (row > j && row < m) ? pc[row] : double2{0.0, 0.0};
+      sq = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, sq));
     }
-    __syncthreads();
-    if (wave == 0) {  // its reflector, v into vsh (v_j = 1)
-      double sq = 0.0, dummy = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) sq = fma(vsh[i].x, vsh[i].x, fma(vsh[i].y, vsh[i].y, sq));
-      wave_sum2(sq, dummy);
-      const double2 al = vsh[j];
-      double2 tv{0.0, 0.0};
-      double beta = al.x;
-      if (sq > 0.0 || al.y != 0.0) {
-        const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
-        beta = al.x >= 0.0 ? -xn : xn;
-        tv = double2{(beta - al.x) / beta, -al.y / beta};
-        const double2 d{al.x - beta, al.y};
-        const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
-        const double2 sc{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
-        for (int i = j + 1 + lane; i < m; i += 64) vsh[i] = cmul(vsh[i], sc);
+    const double2 al = pc[j];
+    const int k = wave;
+    const bool mine_pivot = gg == g && c - c_lo == k;
+    const bool live = !done[k] && !mine_pivot;
+    // this wave's column (rows j..) and its product with the pivot column below row j
+    double2 col[RM];
+    double dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int t = 0; t < RM; ++t) {
+      const int row = lane + 64 * t;
+      col[t] = (live && row >= j && row < m) ? slab[(long long)k * m + row] : double2{0.0, 0.0};
+      if (row > j) {  // conj(x) col
+        dr = fma(x[t].x, col[t].x, fma(x[t].y, col[t].y, dr));
+        di = fma(x[t].x, col[t].y, fma(-x[t].y, col[t].x, di));
       }
+    }
+    double dummy = 0.0;
+    wave_sum2(sq, dummy);
+    wave_sum2(dr, di);
+    double2 tv{0.0, 0.0}, sc{0.0, 0.0};
+    double beta = al.x;
+    if (sq > 0.0 || al.y != 0.0) {
+      const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
+      beta = al.x >= 0.0 ? -xn : xn;
+      tv = double2{(beta - al.x) / beta, -al.y / beta};
+      const double2 d{al.x - beta, al.y};
+      const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
+      sc = double2{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
+    }
+    if (mine_pivot) {  // R(j, j) and the pivot
       if (lane == 0) {
-        tau_sh = tv;
-        beta_sh = beta;
-        vsh[j] = double2{1.0, 0.0};
+        slab[(long long)k * m + j] = double2{beta, 0.0};
+        done[k] = 1;
+        w.qperm[j] = c;
+      }
+      continue;
+    }
+    if (!live) continue;
+    // s = v^dag col = col_j + conj(sc) sum_{i>j} conj(x_i) col_i;  H_j^dag col = col - v conj(tau) s
+    const double2 cj = slab[(long long)k * m + j];
+    const double2 s{cj.x + sc.x * dr + sc.y * di, cj.y + sc.x * di - sc.y * dr};
+    const double2 f = cmul(double2{tv.x, -tv.y}, s);
+    const double2 fs = cmul(sc, f);  // v_i conj(tau) s = x_i (sc f) below row j
+    double nq = 0.0;
+#pragma unroll
+    for (int t = 0; t < RM; ++t) {
+      const int row = lane + 64 * t;
+      if (row == j) col[t] = double2{col[t].x - f.x, col[t].y - f.y};
+      else if (row > j && row < m) {
+        const double2 d = cmul(x[t], fs);
+        col[t] = double2{col[t].x - d.x, col[t].y - d.y};
+        nq = fma(col[t].x, col[t].x, fma(col[t].y, col[t].y, nq));
       }
     }
-    __syncthreads();
-    if (best_g == g && tid == 0) {  // the owner: R(j, j) and the pivot
-      const int k = best_c - c_lo;
-      slab[(long long)k * m + j] = double2{beta_sh, 0.0};
-      done[k] = 1;
-      w.qperm[j] = best_c;
+#pragma unroll
+    for (int t = 0; t < RM; ++t) {
+      const int row = lane + 64 * t;
+      if (row >= j && row < m) slab[(long long)k * m + row] = col[t];
     }
-    __syncthreads();
-    const double2 tc{tau_sh.x, -tau_sh.y};  // H_j^dag = I - conj(tau) v v^dag
-    const bool refl = tc.x != 0.0 || tc.y != 0.0;
-    for (int k = wave; k < C; k += 4) {
-      if (done[k]) continue;
-      double2* col = slab + (long long)k * m;
-      if (refl) {
-        double2 acc{0.0, 0.0};
-        for (int i = j + lane; i < m; i += 64) {
-          const double2 pr = cmulc(vsh[i], col[i]);
-          acc.x += pr.x;
-          acc.y += pr.y;
-        }
-        const double2 f = cmul(tc, wave_csum(acc));
-        for (int i = j + lane; i < m; i += 64) {
-          const double2 d = cmul(vsh[i], f);
-          col[i] = double2{col[i].x - d.x, col[i].y - d.y};
-        }
-      }
-      double sq = 0.0, dummy = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) sq = fma(col[i].x, col[i].x, fma(col[i].y, col[i].y, sq));
-      wave_sum2(sq, dummy);
-      if (lane == 0) nrm2[k] = sq;
-    }
-    __syncthreads();
+    wave_sum2(nq, dummy);
+    if (lane == 0) nrm2[k] = nq;
   }
   if (!ok) {
     if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
     return;
   }
+  __syncthreads();
   for (long long idx = tid; idx < (long long)C * m; idx += blockDim.x) {
     const int k = (int)(idx / m), i = (int)(idx % m);
     if (c_lo + k < n) X[(long long)(c_lo + k) * m + i] = slab[idx];
@@ -1082,8 +1089,9 @@ hipError_t svd_configure() {
                        jacobi_fn<4, true>(),  jacobi_fn<8, true>(),  jacobi_fn<16, true>()};
   for (const void* f : fns)
     MPOEVO_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSvdLdsBytes));
-  MPOEVO_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(svd_qrcp_grid_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsBytes));
+  for (const void* f : {reinterpret_cast<const void*>(svd_qrcp_grid_kernel<4>),
+                        reinterpret_cast<const void*>(svd_qrcp_grid_kernel<8>)})
+    MPOEVO_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsBytes));
   return hipSuccess;
 }
 
@@ -1190,7 +1198,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
                         const double2* warm, double2* basis_out, bool coop, int* complete_dev) {
   if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx) ||
-      (p.qr && (p.acc || std::max(p.mx, p.nx) > kQrMaxDim)))
+      (p.qr && (p.acc || std::max(p.mx, p.nx) > kQrMaxDim || 2 * p.b > kQrThreads / 64)))
     return hipErrorInvalidConfiguration;
   if (p.qr) warm = nullptr;
   SvdWs w = carve(p, ws);
@@ -1224,12 +1232,13 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     SvdWs ww = w;
     int* stp = status;
     void* args[] = {&pp, &ww, &stp};
-    const size_t lds = sizeof(double2) * (size_t)(2 * p.b + 1) * p.mx;
-    const void* fn = reinterpret_cast<const void*>(svd_qrcp_grid_kernel);
+    const size_t lds = sizeof(double2) * (size_t)(2 * p.b) * p.mx;
+    const void* fn = p.mx <= 256 ? reinterpret_cast<const void*>(svd_qrcp_grid_kernel<4>)
+                                 : reinterpret_cast<const void*>(svd_qrcp_grid_kernel<8>);
     if (coop)
-      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.nb / 2), dim3(256), args, (unsigned)lds, st));
+      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.nb / 2), dim3(kQrThreads), args, (unsigned)lds, st));
     else
-      MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(p.nb / 2), dim3(256), args, lds, st));
+      MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(p.nb / 2), dim3(kQrThreads), args, lds, st));
     hipLaunchKernelGGL(svd_qrperm_kernel, dim3(1), dim3(1024), 0, st, p, w);
     MPOEVO_HIP_TRY(hipGetLastError());
     const long long total = (long long)pj.mx * pj.np;
