@@ -293,7 +293,7 @@ __device__ bool wait_flags(unsigned* flags, unsigned* bar, int f0, int f1, int n
       __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       timed_out = 1;
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // pairs with the release stores seen
   }
   __syncthreads();
   return timed_out == 0;
@@ -424,71 +424,69 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
                                      -1, gen)))
         break;
       const int gx = bp * p.b + wave, gy = bq * p.b + wave;  // this wave's two global columns
-      // 2b columns global -> LDS: wave k moves column k of each block through its registers
-      if (wave < p.b) {
-        double2 u[RMAX], v[RMAX];
+      const int pk = wave;
+      // Cross rounds (r > 0): wave k keeps column k of the first block in registers from its
+      // global load to its global store and meets the columns of the second block (in LDS) in
+      // turn. The first round of a sweep holds every column in LDS and also visits the pairs
+      // inside each block.
+      double2 u[RMAX], qu[RMAX];
+      double na = 0.0;
+      if (wave < p.b) {  // global -> registers (own column) / LDS (the second block's column)
+        double2 v[RMAX];
         load_col(u, w.X + (long long)gx * mx, lane, mx);
         load_col(v, w.X + (long long)gy * mx, lane, mx);
-        store_col(u, cols + wave * mx, lane, mx);
+        if (r == 0) store_col(u, cols + wave * mx, lane, mx);
         store_col(v, cols + (p.b + wave) * mx, lane, mx);
-        double na = sq_norm_part(u), nb = sq_norm_part(v);
+        double nb = sq_norm_part(v);
+        na = sq_norm_part(u);
         wave_sum2(na, nb);
         if (lane == 0) {
           nrm[wave] = na;
           nrm[p.b + wave] = nb;
         }
         if (ACC) {
-          load_col(u, w.Q + (long long)gx * nx, lane, nx);
+          load_col(qu, w.Q + (long long)gx * nx, lane, nx);
           load_col(v, w.Q + (long long)gy * nx, lane, nx);
-          store_col(u, qcols + wave * nx, lane, nx);
+          if (r == 0) store_col(qu, qcols + wave * nx, lane, nx);
           store_col(v, qcols + (p.b + wave) * nx, lane, nx);
         }
       }
       if (tid == 0) wg_max = 0u;
       __syncthreads();
       double wave_max = 0.0;  // largest squared relative inner product this wave met (uniform)
-      // One wave per pair (blockDim = 64 b). The first round of a sweep holds every block once:
-      // it also visits the pairs inside each block; later rounds visit only the b x b pairs
-      // across their two blocks, where wave k keeps column k of the first block in registers
-      // and meets the columns of the second block in turn.
-      const int pk = wave;
       if (r == 0) {
         for (int ir = 0; ir < two_b - 1; ++ir) {
           if (pk < p.b) {
             int x, y;
             rr_pair(ir, pk, two_b, x, y);
-            double2 u[RMAX], v[RMAX], qu[RMAX], qv[RMAX];
-            load_col(u, cols + x * mx, lane, mx);
+            double2 uu[RMAX], v[RMAX], quu[RMAX], qv[RMAX];
+            load_col(uu, cols + x * mx, lane, mx);
             load_col(v, cols + y * mx, lane, mx);
             if (ACC) {
-              load_col(qu, qcols + x * nx, lane, nx);
+              load_col(quu, qcols + x * nx, lane, nx);
               load_col(qv, qcols + y * nx, lane, nx);
             }
-            double na = nrm[x], nb = nrm[y];
-            if (jacobi_pair<RMAX, ACC>(u, v, qu, qv, na, nb, lane, floor2, tol2, wave_max)) {
-              store_col(u, cols + x * mx, lane, mx);
+            double a = nrm[x], bb = nrm[y];
+            if (jacobi_pair<RMAX, ACC>(uu, v, quu, qv, a, bb, lane, floor2, tol2, wave_max)) {
+              store_col(uu, cols + x * mx, lane, mx);
               store_col(v, cols + y * mx, lane, mx);
               if (lane == 0) {
-                nrm[x] = na;
-                nrm[y] = nb;
+                nrm[x] = a;
+                nrm[y] = bb;
               }
               if (ACC) {
-                store_col(qu, qcols + x * nx, lane, nx);
+                store_col(quu, qcols + x * nx, lane, nx);
                 store_col(qv, qcols + y * nx, lane, nx);
               }
             }
           }
           __syncthreads();
         }
-      } else {
-        double2 u[RMAX], qu[RMAX];
-        bool dirty = false;
-        double na = 0.0;
-        if (pk < p.b) {
-          na = nrm[pk];
+        if (pk < p.b) {  // the first block's columns back into registers for the store below
           load_col(u, cols + pk * mx, lane, mx);
           if (ACC) load_col(qu, qcols + pk * nx, lane, nx);
         }
+      } else {
         for (int ir = 0; ir < p.b; ++ir) {
           if (pk < p.b) {
             int y = pk + ir;
@@ -501,35 +499,31 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
               store_col(v, cols + y * mx, lane, mx);
               if (ACC) store_col(qv, qcols + y * nx, lane, nx);
               if (lane == 0) nrm[y] = nb;
-              dirty = true;
             }
           }
           __syncthreads();
         }
-        if (pk < p.b && dirty) {
-          store_col(u, cols + pk * mx, lane, mx);
-          if (ACC) store_col(qu, qcols + pk * nx, lane, nx);
-        }
-        __syncthreads();
       }
       if (lane == 0 && wave_max > 0.0)
         atomicMax(&wg_max, __float_as_uint(sqrtf((float)fmin(wave_max, 1.0))));
-      __syncthreads();
-      if (wave < p.b) {  // LDS -> global
-        double2 u[RMAX], v[RMAX];
-        load_col(u, cols + wave * mx, lane, mx);
-        load_col(v, cols + (p.b + wave) * mx, lane, mx);
+      if (wave < p.b) {  // registers / LDS -> global (the LDS columns are final after the last barrier)
+        double2 v[RMAX];
         store_col(u, w.X + (long long)gx * mx, lane, mx);
+        load_col(v, cols + (p.b + wave) * mx, lane, mx);
         store_col(v, w.X + (long long)gy * mx, lane, mx);
         if (ACC) {
-          load_col(u, qcols + wave * nx, lane, nx);
+          store_col(qu, w.Q + (long long)gx * nx, lane, nx);
           load_col(v, qcols + (p.b + wave) * nx, lane, nx);
-          store_col(u, w.Q + (long long)gx * nx, lane, nx);
           store_col(v, w.Q + (long long)gy * nx, lane, nx);
         }
       }
-      if (tid == 0 && wg_max) atomicMax(&w.sweep_max[sweep], wg_max);
-      publish_round(w.flags, ++gen);
+      __syncthreads();  // every wave's share of wg_max (and of the global stores, for the release)
+      if (tid == 0) {
+        if (wg_max) atomicMax(&w.sweep_max[sweep], wg_max);
+        __hip_atomic_store(&w.flags[blockIdx.x], ++gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ++gen;
+      }
     }
     if (!ok || !(ok = wait_flags(w.flags, w.bar, 0, 0, (int)nblk, gen))) break;
     const float mxr = __uint_as_float(
