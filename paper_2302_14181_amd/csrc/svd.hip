@@ -65,9 +65,8 @@ struct SvdWs {  // carved from the caller's workspace
   double2* aux;         // [np][mx] (plans with qr) Jacobi input R^dag after the pivoted QR of X
   int* qperm;           // [np] (qr) column pivots: column j of X Pi is column qperm[j] of X
   int* pinv;            // [np] (qr) inverse pivots
-  unsigned* qflags;     // [kMaxGrid + 1] (qr) per-workgroup step reached; [kMaxGrid] reflector ready
-  double* qcand_v;      // [2][kMaxGrid] (qr) each workgroup's pivot candidate: norm^2 ...
-  int* qcand_i;         // [2][kMaxGrid] ... and column
+  unsigned long long* qkeys;  // [2][kMaxGrid] (qr) each workgroup's published candidate (step, norm, column)
+  double* qrefl;        // [2][kMaxGrid][8] (qr) each candidate's reflector: tau, 1 / (alpha - beta), beta
   double2* qcol;        // [2][nb / 2][mx] (qr) each workgroup's candidate column
   int* qsteps;          // [1] (qr) steps taken (fewer than min(mx, nx) when the rest is exactly zero)
   void* gemm;           // split-K scratch of the products (kGemmScratchBytes)
@@ -81,8 +80,8 @@ size_t ws_bytes(int mx, int nx, int np, bool acc, bool qr, int np_alloc, size_t 
          align256(sizeof(int) * np_alloc) + 256 + sizeof(unsigned) * kMaxGrid +
          align256(sizeof(unsigned) * kMaxSweeps) + 256 +
          (qr ? align256(sizeof(double2) * aux_elems) + 2 * align256(sizeof(int) * np) +
-                   align256(sizeof(unsigned) * (kMaxGrid + 1)) + align256(2 * sizeof(double) * kMaxGrid) +
-                   align256(2 * sizeof(int) * kMaxGrid) + align256(2 * sizeof(double2) * (size_t)mx * np) + 256
+                   align256(2 * sizeof(unsigned long long) * kMaxGrid) + align256(16 * sizeof(double) * kMaxGrid) +
+                   align256(2 * sizeof(double2) * (size_t)mx * np) + 256
               : 0) +
          kGemmScratchBytes;
 }
@@ -112,9 +111,8 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   off += 256;
   w.aux = nullptr;
   w.qperm = w.pinv = nullptr;
-  w.qflags = nullptr;
-  w.qcand_v = nullptr;
-  w.qcand_i = nullptr;
+  w.qkeys = nullptr;
+  w.qrefl = nullptr;
   w.qcol = nullptr;
   w.qsteps = nullptr;
   if (p.qr) {
@@ -124,12 +122,10 @@ SvdWs carve(const SvdPlan& p, void* ws) {
     off += align256(sizeof(int) * p.np);
     w.pinv = reinterpret_cast<int*>(base + off);
     off += align256(sizeof(int) * p.np);
-    w.qflags = reinterpret_cast<unsigned*>(base + off);
-    off += align256(sizeof(unsigned) * (kMaxGrid + 1));
-    w.qcand_v = reinterpret_cast<double*>(base + off);
-    off += align256(2 * sizeof(double) * kMaxGrid);
-    w.qcand_i = reinterpret_cast<int*>(base + off);
-    off += align256(2 * sizeof(int) * kMaxGrid);
+    w.qkeys = reinterpret_cast<unsigned long long*>(base + off);
+    off += align256(2 * sizeof(unsigned long long) * kMaxGrid);
+    w.qrefl = reinterpret_cast<double*>(base + off);
+    off += align256(16 * sizeof(double) * kMaxGrid);
     w.qcol = reinterpret_cast<double2*>(base + off);
     off += align256(2 * sizeof(double2) * (size_t)p.mx * p.np);  // nb / 2 <= np columns
     w.qsteps = reinterpret_cast<int*>(base + off);
@@ -241,7 +237,7 @@ __global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, Sv
   }
   if (blockIdx.x == 0) {
     if (p.qr) {
-      for (int i = threadIdx.x; i <= kMaxGrid; i += blockDim.x) w.qflags[i] = 0u;
+      for (int i = threadIdx.x; i < 2 * kMaxGrid; i += blockDim.x) w.qkeys[i] = 0ull;
       if (threadIdx.x == 0) *w.qsteps = 0;
     }
     if (threadIdx.x < 3) w.bar[threadIdx.x] = 0u;
@@ -258,11 +254,6 @@ __global__ void svd_init_kernel(const double2* __restrict__ theta, SvdPlan p, Sv
 // sets bar[2] and makes every waiting workgroup return false; all workgroups then leave the sweep
 // loop. The waits poll with relaxed loads and acquire once, by a fence after the flags are seen
 // (an acquiring load in the poll would invalidate the L2 cache on every iteration).
-__device__ void publish_round(unsigned* flags, unsigned gen) {
-  __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&flags[blockIdx.x], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Waits until flags[j] >= gen for j = f0, f1 (nblocks < 0) or for every j < nblocks.
 __device__ bool wait_flags(unsigned* flags, unsigned* bar, int f0, int f1, int nblocks, unsigned gen) {
@@ -842,19 +833,70 @@ __device__ inline double wave_max1(double a) {
               __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h2[1]) << 32) | l2[1])));
 }
 
+// Candidate keys of the pivoted QR, one 64-bit word per workgroup and step: bits 63..44 the step
+// (plus one), 43..12 the high word of the candidate's squared norm (a non-negative double, so its
+// bit pattern orders like its value; 20 mantissa bits decide the pivot), 11..0 4095 minus its
+// column. The largest key below the step field is the pivot: largest norm, ties to the smallest
+// column; a key with norm field 0 offers no candidate.
+__device__ inline unsigned long long qr_key(unsigned step, double norm2, int column) {
+  const unsigned hi = norm2 > 0.0 ? (unsigned)((unsigned long long)__double_as_longlong(norm2) >> 32) : 0u;
+  return ((unsigned long long)step << 44) | ((unsigned long long)hi << 12) | (unsigned long long)(4095 - column);
+}
+constexpr unsigned long long kQrKeyMask = (1ull << 44) - 1;
+
+// Waits until every workgroup's key carries step `step` (or later) and returns in every thread the
+// largest key (step field removed), or ~0 on a timeout (bounded like wait_flags).
+__device__ unsigned long long wait_keys(unsigned long long* keys, unsigned* bar, int nblocks, unsigned step) {
+  __shared__ unsigned long long best_sh;
+  __shared__ int timed_out;
+  if (threadIdx.x == 0) timed_out = 0;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const unsigned long long t0 = wall_clock64();
+    unsigned long long best = 0;
+    bool fail = false;
+    while (true) {
+      int mine = 1;
+      best = 0;
+      for (int k = lane; k < nblocks; k += 64) {
+        const unsigned long long key = __hip_atomic_load(&keys[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        mine &= (unsigned)(key >> 44) >= step;
+        best = max(best, key & kQrKeyMask);
+      }
+      if (__all(mine)) break;
+      if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 > kBarrierTimeoutTicks) {
+        fail = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) best = max(best, (unsigned long long)__shfl_xor((long long)best, off, 64));
+    if (fail && lane == 0) {
+      __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      timed_out = 1;
+    }
+    if (lane == 0) best_sh = best;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // pairs with the release stores seen
+  }
+  __syncthreads();
+  return timed_out ? ~0ull : best_sh;
+}
+
 // Householder QR with column pivoting of X (mx x nx, column-major; min(mx, nx) steps): at step j the
 // remaining column of largest norm becomes column j (pivots kept as a permutation), its reflector
 // H_j = I - tau v v^dag (v_j = 1) zeroes it below row j, and H_j^dag is applied to the remaining
 // columns. Spread over the Jacobi grid's workgroups (launched together, like the Jacobi
 // kernel): workgroup g keeps columns [g C, g C + C) (C = 2b <= 16) of X in LDS, one wave per
-// column. Per step j wave 0 publishes the workgroup's remaining column of largest norm (the
-// column itself, its norm and index; flag = j + 1) and waits for all others; then every wave
-// takes the overall largest (ties: the smallest index), loads the pivot column into registers,
-// forms its reflector itself (the same arithmetic on the same data everywhere, so one exchange
-// per step suffices and no wave waits for another), applies H_j^dag to its own column and
-// recomputes its norm below row j; the owner's wave records the pivot and R(j, j). Two buffers
-// (by the parity of j) keep consecutive steps apart. At the end each workgroup writes its
-// columns back: R(r, c) = X[qperm[c]][r] for r <= c. Waits are bounded (barrier-timeout status).
+// column. Per step j wave 0 takes the workgroup's remaining column of largest norm, forms its
+// reflector, publishes the column (rows j..) and the reflector, then a key with its norm and
+// index (release), and waits for all other keys; the largest key names the pivot, whose column and
+// reflector every wave then loads to apply H_j^dag to its own column and recompute its norm below
+// row j; the owner's wave records the pivot and R(j, j). One exchange per step, and the keys
+// carry the choice, so no wave reads the candidates separately. Two buffers (by the parity of j)
+// keep consecutive steps apart. At the end each workgroup writes its columns back:
+// R(r, c) = X[qperm[c]][r] for r <= c. Waits are bounded (barrier-timeout status).
 // RM: rows per lane (mx <= 64 RM).
 constexpr int kQrThreads = 1024;
 template <int RM>
@@ -862,6 +904,7 @@ __global__ __launch_bounds__(kQrThreads) void svd_qrcp_grid_kernel(SvdPlan p, Sv
   extern __shared__ double2 slab[];  // [C][mx] columns
   __shared__ double nrm2[16];
   __shared__ int done[16];
+  __shared__ unsigned long long key_sh;
   const int m = p.mx, n = p.nx, C = 2 * p.b, nwg = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c_lo = g * C;
@@ -889,92 +932,88 @@ __global__ __launch_bounds__(kQrThreads) void svd_qrcp_grid_kernel(SvdPlan p, Sv
   for (; j < jmax && ok; ++j) {
     const int par = j & 1;
     __syncthreads();  // norms and done flags of the previous step
-    if (wave == 0) {  // this workgroup's candidate, published with its column (rows j..)
+    if (wave == 0) {  // this workgroup's candidate: its column (rows j..), reflector and key
       const double mine = (lane < C && !done[lane]) ? nrm2[lane] : -1.0;
       const double wmax = wave_max1(mine);
       const unsigned long long hit = __ballot(mine == wmax);
       const int kk = hit ? __builtin_ctzll(hit) : 0;  // (no hit only for a NaN norm)
       const double2* src = slab + (long long)kk * m;
       double2* dst = w.qcol + ((long long)par * nwg + g) * m;
-      for (int i = j + lane; i < m; i += 64) dst[i] = src[i];
+      double sq = 0.0, dummy = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const double2 x = src[i];
+        dst[i] = x;
+        if (i > j) sq = fma(x.x, x.x, fma(x.y, x.y, sq));
+      }
+      wave_sum2(sq, dummy);
       if (lane == 0) {
-        w.qcand_v[par * kMaxGrid + g] = wmax;
-        w.qcand_i[par * kMaxGrid + g] = c_lo + kk;
+        const double2 al = src[j];
+        double2 tv{0.0, 0.0}, sc{0.0, 0.0};
+        double beta = al.x;
+        if (sq > 0.0 || al.y != 0.0) {
+          const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
+          beta = al.x >= 0.0 ? -xn : xn;
+          const double rb = 1.0 / beta;
+          tv = double2{(beta - al.x) * rb, -al.y * rb};
+          const double2 d{al.x - beta, al.y};
+          const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
+          sc = double2{d.x * dn, -d.y * dn};  // 1 / (alpha - beta): v_i = x_i sc below row j
+        }
+        double* r = w.qrefl + ((long long)par * kMaxGrid + g) * 8;
+        r[0] = tv.x;
+        r[1] = tv.y;
+        r[2] = sc.x;
+        r[3] = sc.y;
+        r[4] = beta;
+        key_sh = qr_key((unsigned)(j + 1), wmax, c_lo + kk);
       }
     }
-    publish_round(w.qflags, (unsigned)(j + 1));
-    if (!(ok = wait_flags(w.qflags, w.bar, 0, 0, nwg, (unsigned)(j + 1)))) break;
-    // the overall pivot (every wave computes the same)
-    double v = -1.0;
-    int c = n, gg = 0;
-    for (int k = lane; k < nwg; k += 64) {
-      const double kv = __hip_atomic_load(&w.qcand_v[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int kc = __hip_atomic_load(&w.qcand_i[par * kMaxGrid + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (kv > v || (kv == v && kc < c)) { v = kv; c = kc; gg = k; }
+    // keys by parity too: a workgroup writes this slot again only after every workgroup has
+    // published the next step, i.e. has finished reading this one
+    unsigned long long* keys = w.qkeys + par * kMaxGrid;
+    __syncthreads();  // wave 0's stores before the release
+    if (tid == 0) __hip_atomic_store(&keys[g], key_sh, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long best = wait_keys(keys, w.bar, nwg, (unsigned)(j + 1));
+    if (best == ~0ull) {
+      ok = false;
+      break;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off, 64);
-      const int oc = __shfl_xor(c, off, 64);
-      const int og = __shfl_xor(gg, off, 64);
-      if (ov > v || (ov == v && oc < c)) { v = ov; c = oc; gg = og; }
-    }
-    if (!(v > 0.0)) break;  // the remaining columns are exactly zero below row j (uniform)
+    if ((best >> 12) == 0) break;  // the remaining columns are exactly zero below row j (uniform)
     if (wave >= C) continue;
-    // the pivot column (rows j..) and its reflector: v_j = 1, v_i = x_i sc below, tau
-    const double2* pc = w.qcol + ((long long)par * nwg + gg) * m;
-    double2 x[RM];
-    double sq = 0.0;
-#pragma unroll
-    for (int t = 0; t < RM; ++t) {
-      const int row = lane + 64 * t;
-      x[t] = (row > j && row < m) ? pc[row] : double2{0.0, 0.0};
-      sq = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, sq));
-    }
-    const double2 al = pc[j];
+    const int c = 4095 - (int)(best & 4095), gg = c / C;  // the pivot and its workgroup
     const int k = wave;
     const bool mine_pivot = gg == g && c - c_lo == k;
-    const bool live = !done[k] && !mine_pivot;
-    // this wave's column (rows j..) and its product with the pivot column below row j
-    double2 col[RM];
-    double dr = 0.0, di = 0.0;
-#pragma unroll
-    for (int t = 0; t < RM; ++t) {
-      const int row = lane + 64 * t;
-      col[t] = (live && row >= j && row < m) ? slab[(long long)k * m + row] : double2{0.0, 0.0};
-      if (row > j) {  // conj(x) col
-        dr = fma(x[t].x, col[t].x, fma(x[t].y, col[t].y, dr));
-        di = fma(x[t].x, col[t].y, fma(-x[t].y, col[t].x, di));
-      }
-    }
-    double dummy = 0.0;
-    wave_sum2(sq, dummy);
-    wave_sum2(dr, di);
-    double2 tv{0.0, 0.0}, sc{0.0, 0.0};
-    double beta = al.x;
-    if (sq > 0.0 || al.y != 0.0) {
-      const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
-      beta = al.x >= 0.0 ? -xn : xn;
-      tv = double2{(beta - al.x) / beta, -al.y / beta};
-      const double2 d{al.x - beta, al.y};
-      const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
-      sc = double2{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
-    }
+    const double* r = w.qrefl + ((long long)par * kMaxGrid + gg) * 8;
     if (mine_pivot) {  // R(j, j) and the pivot
       if (lane == 0) {
-        slab[(long long)k * m + j] = double2{beta, 0.0};
+        slab[(long long)k * m + j] = double2{r[4], 0.0};
         done[k] = 1;
         w.qperm[j] = c;
       }
       continue;
     }
-    if (!live) continue;
+    if (done[k]) continue;
+    const double2 tv{r[0], r[1]}, sc{r[2], r[3]};
+    // the pivot column below row j and this wave's column (rows j..)
+    const double2* pc = w.qcol + ((long long)par * nwg + gg) * m;
+    double2 x[RM], col[RM];
+    double dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int t = 0; t < RM; ++t) {
+      const int row = lane + 64 * t;
+      x[t] = (row > j && row < m) ? pc[row] : double2{0.0, 0.0};
+      col[t] = (row >= j && row < m) ? slab[(long long)k * m + row] : double2{0.0, 0.0};
+      // conj(x) col
+      dr = fma(x[t].x, col[t].x, fma(x[t].y, col[t].y, dr));
+      di = fma(x[t].x, col[t].y, fma(-x[t].y, col[t].x, di));
+    }
+    wave_sum2(dr, di);
     // s = v^dag col = col_j + conj(sc) sum_{i>j} conj(x_i) col_i;  H_j^dag col = col - v conj(tau) s
     const double2 cj = slab[(long long)k * m + j];
     const double2 s{cj.x + sc.x * dr + sc.y * di, cj.y + sc.x * di - sc.y * dr};
     const double2 f = cmul(double2{tv.x, -tv.y}, s);
     const double2 fs = cmul(sc, f);  // v_i conj(tau) s = x_i (sc f) below row j
-    double nq = 0.0;
+    double nq = 0.0, dummy = 0.0;
 #pragma unroll
     for (int t = 0; t < RM; ++t) {
       const int row = lane + 64 * t;
