@@ -146,8 +146,10 @@ template <int CTRL>
 __device__ inline double dpp_move(double v) {
   const long long b = __double_as_longlong(v);
   int lo = static_cast<int>(b & 0xffffffffll), hi = static_cast<int>(b >> 32);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  // every lane reads a lane of its own row (quad permutations, row mirrors), so no lane keeps its
+  // old value and none needs initialising
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
