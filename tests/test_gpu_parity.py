@@ -173,6 +173,26 @@ def test_truncate_square_graded_and_deficient(mp, handle, case, direction):
     _check_truncate(mp, handle, X, n // 2, direction)
 
 
+# rectangular matrices up to 512 take the pivoted QR too, in either orientation (X = Theta^dag for
+# direction 0, Theta for 1, so each shape below gives a tall X in one direction and a wide X, whose
+# factorisation stops after min(m, n) steps, in the other): graded spectra and exact rank deficiency
+GRADED_RECT = [(96, 320, 0.2, None), (320, 96, 0.2, None), (500, 130, 0.05, None),
+               (130, 500, 0.0, 40), (300, 180, 0.0, 60)]
+
+
+@pytest.mark.parametrize("direction", [0, 1], ids=["left", "right"])
+@pytest.mark.parametrize("case", GRADED_RECT, ids=[str(c) for c in GRADED_RECT])
+def test_truncate_rect_graded_and_deficient(mp, handle, case, direction):
+    m, n, decay, rank = case
+    rng = np.random.default_rng(m + 3 * n + 17 * (rank or 0))
+    _say("truncate rectangular", case, "dir", direction)
+    if rank is None:
+        X = _graded(rng, m, n, decay)
+    else:
+        X = _cn(rng, m, rank) @ _cn(rng, rank, n)
+    _check_truncate(mp, handle, X, min(m, n) // 2, direction)
+
+
 def _check_truncate(mp, handle, X, Dmax, direction):
     m, n = X.shape
     kcap = min(Dmax, m, n)
