@@ -408,14 +408,36 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   bool ok = true;
   int sweep = 0;
   unsigned gen = 0;
-  for (; sweep < kMaxSweeps && ok; ++sweep) {
-    for (int r = 0; r < p.nb - 1 && ok; ++r) {
+  // The verdict on sweep s is read in round 1 of sweep s + 1, after a wait for every workgroup
+  // to have finished sweep s: by then the slower workgroups have mostly caught up, so no
+  // workgroup idles at the end of each sweep. A converged sweep thus keeps the rotations of the
+  // next sweep's first round (pairs below tol are not rotated; the others only further). With a
+  // single round per sweep, and after the last allowed sweep, the verdict is read at once.
+  const int rounds = p.nb - 1;
+  auto converged = [&](int s) {
+    const double mxr = (double)__uint_as_float(
+        __hip_atomic_load(&w.sweep_max[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    return mxr <= tol || mxr <= kAccept || mxr <= p.accept;
+  };
+  bool conv = false;
+  int done_sweeps = 0;
+  for (; sweep < kMaxSweeps && ok && !conv; ++sweep) {
+    for (int r = 0; r < rounds && ok; ++r) {
       int bp, bq;
       rr_pair(r, blockIdx.x, p.nb, bp, bq);
       // the two blocks were written in the previous round by the workgroups that held them
-      if (r > 0 && !(ok = wait_flags(w.flags, w.bar, rr_owner(r - 1, bp, p.nb), rr_owner(r - 1, bq, p.nb),
-                                     -1, gen)))
-        break;
+      if (r > 0 || sweep > 0) {
+        const int rp = r > 0 ? r - 1 : rounds - 1;
+        if (!(ok = wait_flags(w.flags, w.bar, rr_owner(rp, bp, p.nb), rr_owner(rp, bq, p.nb), -1, gen)))
+          break;
+      }
+      if (r == 1 && sweep > 0) {  // the previous sweep's verdict
+        if (!(ok = wait_flags(w.flags, w.bar, 0, 0, (int)nblk, (unsigned)(sweep * rounds)))) break;
+        if (converged(sweep - 1)) {
+          conv = true;
+          break;
+        }
+      }
       const int gx = bp * p.b + wave, gy = bq * p.b + wave;  // this wave's two global columns
       const int pk = wave;
       // Cross rounds (r > 0): wave k keeps column k of the first block in registers from its
@@ -518,16 +540,18 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
         ++gen;
       }
     }
-    if (!ok || !(ok = wait_flags(w.flags, w.bar, 0, 0, (int)nblk, gen))) break;
-    const float mxr = __uint_as_float(
-        __hip_atomic_load(&w.sweep_max[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-    if ((double)mxr <= tol || (double)mxr <= kAccept || (double)mxr <= p.accept) break;
+    if (!ok || conv) break;
+    done_sweeps = sweep + 1;
+    if (rounds == 1 || sweep + 1 == kMaxSweeps) {  // the verdict at once
+      if (!(ok = wait_flags(w.flags, w.bar, 0, 0, (int)nblk, gen))) break;
+      conv = converged(sweep);
+    }
   }
   if (blockIdx.x == 0 && tid == 0) {
-    atomicMax(&status[1], sweep + 1);
-    if (sweeps_out) *sweeps_out = sweep + 1;
+    atomicMax(&status[1], done_sweeps);
+    if (sweeps_out) *sweeps_out = done_sweeps;
     if (!ok) atomicOr(status, kStatusBarrierTimeout);
-    else if (sweep >= kMaxSweeps) {
+    else if (!conv) {
       atomicOr(status, kStatusNotConverged);
       atomicMax(reinterpret_cast<unsigned*>(&status[2]), w.sweep_max[kMaxSweeps - 1]);
     }
