@@ -391,6 +391,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   extern __shared__ double2 cols[];  // [2b][mx] then (ACC) [2b][nx]
   __shared__ unsigned wg_max;        // bits of a non-negative float: integer order = value order
   __shared__ double floor2_sh;
+  __shared__ int nbe_sh;
   __shared__ double nrm[2 * 16];     // squared norms of the 2b columns held in LDS (b <= 16)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int two_b = 2 * p.b, mx = p.mx, nx = p.nx;
@@ -403,8 +404,28 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   }
   __syncthreads();
   const double floor2 = floor2_sh;
+  // A column at the rounding floor is never rotated (a pair needs both columns above it), so its
+  // norm never changes: trailing blocks made only of columns clearly below it (half the floor,
+  // so that no column the pair test would take is left out; the tail of R^dag after the pivoted
+  // QR of a numerically rank-deficient matrix) are left out of the rounds altogether, with the
+  // same result. Every workgroup finds the same block count nbe.
+  if (wave == 0) {
+    int last = -1;
+    for (int j = lane; j < nx; j += 64)
+      if (w.sigma[j] > 0.5 * floor2) last = j;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off, 64));
+    if (lane == 0) {
+      int nbe = max((last + p.b) / p.b, 2);
+      nbe += nbe & 1;
+      nbe_sh = min(nbe, p.nb);
+    }
+  }
+  __syncthreads();
+  const int nbe = nbe_sh;
+  const unsigned nblk = nbe / 2;
+  if (blockIdx.x >= nblk) return;  // (block 0 always takes part and reports)
   const double tol2 = tol * tol;
-  const unsigned nblk = gridDim.x;
   bool ok = true;
   int sweep = 0;
   unsigned gen = 0;
@@ -413,7 +434,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   // workgroup idles at the end of each sweep. A converged sweep thus keeps the rotations of the
   // next sweep's first round (pairs below tol are not rotated; the others only further). With a
   // single round per sweep, and after the last allowed sweep, the verdict is read at once.
-  const int rounds = p.nb - 1;
+  const int rounds = nbe - 1;
   auto converged = [&](int s) {
     const double mxr = (double)__uint_as_float(
         __hip_atomic_load(&w.sweep_max[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -424,11 +445,11 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   for (; sweep < kMaxSweeps && ok && !conv; ++sweep) {
     for (int r = 0; r < rounds && ok; ++r) {
       int bp, bq;
-      rr_pair(r, blockIdx.x, p.nb, bp, bq);
+      rr_pair(r, blockIdx.x, nbe, bp, bq);
       // the two blocks were written in the previous round by the workgroups that held them
       if (r > 0 || sweep > 0) {
         const int rp = r > 0 ? r - 1 : rounds - 1;
-        if (!(ok = wait_flags(w.flags, w.bar, rr_owner(rp, bp, p.nb), rr_owner(rp, bq, p.nb), -1, gen)))
+        if (!(ok = wait_flags(w.flags, w.bar, rr_owner(rp, bp, nbe), rr_owner(rp, bq, nbe), -1, gen)))
           break;
       }
       if (r == 1 && sweep > 0) {  // the previous sweep's verdict
