@@ -952,10 +952,17 @@ __global__ __launch_bounds__(kQrThreads) void svd_qrcp_grid_kernel(SvdPlan p, Sv
   __shared__ double nrm2[16];
   __shared__ int done[16];
   __shared__ unsigned long long key_sh;
+  __shared__ double stop2_sh;
   const int m = p.mx, n = p.nx, C = 2 * p.b, nwg = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c_lo = g * C;
   double2* X = w.X;
+  if (tid == 0) {  // from the squared column norms of X (w.sigma), summed in a fixed order
+    double fro2 = 0.0;
+    for (int c = 0; c < n; ++c) fro2 += w.sigma[c];
+    const double fl = 4.0 * kEps * sqrt((double)p.frows);  // half the Jacobi rounding floor
+    stop2_sh = fl * fl * fro2;
+  }
   for (long long idx = tid; idx < (long long)C * m; idx += blockDim.x) {
     const int k = (int)(idx / m), i = (int)(idx % m);
     slab[idx] = c_lo + k < n ? X[(long long)(c_lo + k) * m + i] : double2{0.0, 0.0};
@@ -1025,7 +1032,14 @@ __global__ __launch_bounds__(kQrThreads) void svd_qrcp_grid_kernel(SvdPlan p, Sv
       ok = false;
       break;
     }
-    if ((best >> 12) == 0) break;  // the remaining columns are exactly zero below row j (uniform)
+    // The remaining columns (at most n - j, each of squared norm at most the largest, which the
+    // key holds to 20 mantissa bits) together below half the rounding floor: their part below
+    // row j is left out of R (a change of X below the floor, which the Jacobi iteration does
+    // not resolve) and the factorisation ends. The same test everywhere; exact zeros included.
+    {
+      const double bn = __longlong_as_double((long long)(((best >> 12) & 0xffffffffull) << 32));
+      if (bn * (double)(n - j) <= stop2_sh) break;
+    }
     if (wave >= C) continue;
     const int c = 4095 - (int)(best & 4095), gg = c / C;  // the pivot and its workgroup
     const int k = wave;
@@ -1308,6 +1322,12 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   SvdWs wj = w;  // what Jacobi rotates: X itself, or R^dag of the column-pivoted QR of X
   const SvdPlan pj = p.qr ? rdag_plan(p) : p;  // the plan of the Jacobi phase (R^dag: nx x min(mx, nx))
   if (p.qr) {
+    {  // squared column norms of X for the factorisation's stopping test
+      const int wpb0 = 4;
+      hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb0 - 1) / wpb0), dim3(64 * wpb0), 0, st, p, w,
+                         status, 1);
+      MPOEVO_HIP_TRY(hipGetLastError());
+    }
     SvdPlan pp = p;
     SvdWs ww = w;
     int* stp = status;
