@@ -11,7 +11,8 @@ the launch stream, bracketed by device synchronisation); W untimed warm-up steps
 separate copy of the initial state.
 
 Also reported: the same opening steps on the plain FP64 path (FP32/FP64 time ratio on identical
-steps), one step at saturated bond dimension on a seeded random MPS (D = 128 on every bulk bond),
+steps), one step at saturated bond dimension on a seeded random MPS (D = 128 on every bulk bond;
+also on the FP64 path, for the ratio at saturation),
 one step of the long-range chain at D = 256 with the w = 271 order-3 MPO on the FP32, FP64 and
 split-BF16x3 paths (step time and matrix-core rate of the contractions: the "TFLOP/s at D = 256"
 part of the metric),
@@ -398,20 +399,27 @@ def main():
                 "fp32_s_per_step": float(np.sum(ms[:n64])) / 1e3 / n64}
         fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / fp64["fp32_s_per_step"]
 
-    # one step at saturated bond dimension (seeded random MPS, D = 128 on every bulk bond)
-    rnd = wl.random_mps(np.random.default_rng(0), L, 2, D)
-    dmr = mp.DeviceMPS(rnd, Dmax=D)
-    wsr = mp.step_workspace(dmr, dw, prec)
-    mp.step(h, dmr, dw, prec=prec, workspace=wsr)
-    mp.step(h, dmr, dw, prec=prec, input_right_canonical=True, workspace=wsr)
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    mp.step(h, dmr, dw, prec=prec, input_right_canonical=True, workspace=wsr)
-    e.record()
-    torch.cuda.synchronize()
-    sat_s = s.elapsed_time(e) / 1e3
-    del wsr, dmr
+    # one step at saturated bond dimension (seeded random MPS, D = 128 on every bulk bond), after
+    # two steps that leave the truncations' preconditioners in the workspace
+    def saturated_step(p):
+        rnd = wl.random_mps(np.random.default_rng(0), L, 2, D)
+        dmr = mp.DeviceMPS(rnd, Dmax=D)
+        wsr = mp.step_workspace(dmr, dw, p)
+        mp.step(h, dmr, dw, prec=p, workspace=wsr)
+        mp.step(h, dmr, dw, prec=p, input_right_canonical=True, workspace=wsr)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        mp.step(h, dmr, dw, prec=p, input_right_canonical=True, workspace=wsr)
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / 1e3
+
+    sat_s = saturated_step(prec)
+    if fp64 is not None:  # the same saturated step on the plain FP64 path
+        fp64["saturated_fp64_s_per_step"] = saturated_step(mp.FP64)
+        fp64["saturated_fp32_s_per_step"] = sat_s
+        fp64["saturated_fp32_speedup"] = fp64["saturated_fp64_s_per_step"] / sat_s
 
     mb32_ms, mb_flop = env_microbench(mp, h, torch, mp.FP32)
     mb64_ms, _ = env_microbench(mp, h, torch, mp.FP64)
