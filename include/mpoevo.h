@@ -131,10 +131,10 @@ int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void
 
 /*
  * truncate -- DEVICE, async on `stream`. FP64 SVD Theta = U S V^dag of an m x n complex128
- * matrix (row-major) by one-sided Jacobi (when the kept factor lies on the longer side -- m <= n
- * for LEFT, m >= n for RIGHT -- and max(m, n) <= 512, on R^dag of a column-pivoted Householder
- * QR of Theta^dag or Theta, which converges in few sweeps even when the singular values spread
- * over many decades), keeping k = min(Dmax, m, n, #{sigma_i > max(cutoff *
+ * matrix (row-major) by one-sided Jacobi (for max(m, n) <= 512 on R^dag of a column-pivoted
+ * Householder QR of X = Theta^dag for LEFT, Theta for RIGHT, whose right singular vectors are the
+ * kept factor; this converges in few sweeps even when the singular values spread over many
+ * decades), keeping k = min(Dmax, m, n, #{sigma_i > max(cutoff *
  * sigma_1, 8 eps sqrt(max(m, n)) ||Theta||_F)}) >= 1 singular values (the truncation of the
  * two-site update; the second bound drops singular values at the rounding level of Theta).
  *   direction LEFT  (left-to-right sweep): A_out = U_k (left-orthonormal), B_out = S_k V_k^dag
@@ -197,17 +197,21 @@ typedef struct {
   int input_right_canonical;
   int profile;  /* nonzero: time the kernel classes with HIP events (adds host overhead) */
   int svd_cold_start; /* nonzero: every truncation starts Jacobi from Theta itself. Zero (the
-                         default): the bond matrix is first multiplied by the unitary the
+                         default): a square bond matrix is first multiplied by the unitary the
                          previous truncation of the same bond left in the workspace (a singular
-                         basis of that matrix, completed to a unitary when the matrix is
-                         numerically rank-deficient), which leaves the same singular values and
-                         kept vectors and converges in a few sweeps; the first truncation of a
-                         square bond matrix in a step (Theta has moved by a whole time step
-                         since the last one) instead runs Jacobi on R^dag of its
-                         column-pivoted QR. The unitaries
-                         persist in the workspace between step calls on one handle with the
-                         same workspace and chain shape; the caller must not modify that
-                         workspace between such calls. */
+                         basis of that matrix), which leaves the same singular values and kept
+                         vectors and converges in a few sweeps. The first truncation of a bond
+                         in a step (Theta has moved by a whole time step since the last one),
+                         rectangular bond matrices, and bonds below Dmax or found numerically
+                         rank-deficient by the previous step (whose basis would need
+                         completing) instead run Jacobi on R^dag of a column-pivoted QR (up to
+                         512). The unitaries persist in the workspace between step calls on one
+                         handle with the same workspace and chain shape; the caller must not
+                         modify that workspace between such calls. With FP32 or BF16X3
+                         contractions the Jacobi iteration ends after the sweep whose largest
+                         relative inner product is at most 3e-5 (the next would leave about its
+                         square, far below the contraction rounding); with FP64, after a sweep
+                         that finds every pair below the rounding tolerance. */
 } mpoevo_step_opts;
 
 typedef struct {
