@@ -1,6 +1,7 @@
 // Contractions with the MPO tensor W over its short legs (K = w d terms per output). These are
 // memory-bound: every thread keeps the K input values of one output column in registers and
-// produces all of its w d outputs, with W staged once per workgroup in LDS.
+// produces a group of kIlp of its w d outputs (one group per workgroup along the grid's z
+// dimension), with W staged once per workgroup in LDS.
 //
 //   left : LB[a'][s'][beta][b]  = sum_{alpha, s} T[a'][alpha][s][b]  W[alpha][s'][s][beta]
 //   right: RB[beta][b][t'][c']  = sum_{t, gamma} W[beta][t'][t][gamma] U[b][t][c'][gamma]
@@ -23,8 +24,9 @@ __device__ inline cx_t<T> cmul_add(cx_t<T> acc, cx_t<T> a, cx_t<T> b) {
 }
 
 constexpr int kThreads = 256;
+constexpr int kIlp = 8;  // outputs per thread computed together
 
-// grid: (ceil(Q / 256), P). KMAX >= wl * d.
+// grid: (ceil(Q / 256), P, ceil(d wr / kIlp)). KMAX >= wl * d.
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __restrict__ Tin,
                                                              const cx_t<T>* __restrict__ W,
@@ -45,21 +47,36 @@ __global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __re
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) in[k] = (k < K) ? src[(long long)k * Q] : C2{T(0), T(0)};
   C2* dst = out + (long long)ap * d * wr * Q + b;
-  for (int sp = 0; sp < d; ++sp)
-    for (int be = 0; be < wr; ++be) {
-      C2 acc{T(0), T(0)};
+  // outputs o = s' wr + beta: workgroup z computes the group [z kIlp, z kIlp + kIlp) with
+  // independent accumulators (more waves and independent multiply-add chains to cover latency;
+  // the inputs are read once per group, mostly from cache)
+  const int nout = d * wr;
+  {
+    const int o0 = blockIdx.z * kIlp;
+    C2 acc[kIlp];
+    int wo[kIlp];  // offset of (s', beta) in W[alpha][s'][s][beta]
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < K) {
-          const int al = k / d, s = k % d;  // k = alpha * d + s
-          acc = cmul_add<T>(acc, in[k], Ws[((al * d + sp) * d + s) * wr + be]);
-        }
-      }
-      dst[(long long)(sp * wr + be) * Q] = acc;
+    for (int j = 0; j < kIlp; ++j) {
+      acc[j] = C2{T(0), T(0)};
+      const int o = min(o0 + j, nout - 1), sp = o / wr, be = o % wr;
+      wo[j] = sp * d * wr + be;
     }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < K) {
+        const int al = k / d, s = k % d;  // k = alpha * d + s
+        const int base = (al * d * d + s) * wr;
+#pragma unroll
+        for (int j = 0; j < kIlp; ++j) acc[j] = cmul_add<T>(acc[j], in[k], Ws[base + wo[j]]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kIlp; ++j)
+      if (o0 + j < nout) dst[(long long)(o0 + j) * Q] = acc[j];
+  }
 }
 
-// grid: (ceil(Pr / 256), Q). U[b][t][c'][gamma] with c' < Pr; out RB[beta][b][t'][c'].
+// grid: (ceil(Pr / 256), Q, ceil(wl d / kIlp)). U[b][t][c'][gamma] with c' < Pr; out RB[beta][b][t'][c'].
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kThreads) void wmix_right_kernel(const cx_t<T>* __restrict__ U,
                                                               const cx_t<T>* __restrict__ W,
@@ -85,22 +102,34 @@ __global__ __launch_bounds__(kThreads) void wmix_right_kernel(const cx_t<T>* __r
     }
     in[k] = v;
   }
-  for (int be = 0; be < wl; ++be)
-    for (int tp = 0; tp < d; ++tp) {
-      C2 acc{T(0), T(0)};
-      const C2* wrow = Ws + (be * d + tp) * d * wr;  // W[beta][t'][t][gamma], (t, gamma) = k
+  // outputs o = beta d + t' (W row o: W[beta][t'][t][gamma], (t, gamma) = k): workgroup z
+  // computes the group [z kIlp, z kIlp + kIlp)
+  const int nout = wl * d;
+  {
+    const int o0 = blockIdx.z * kIlp;
+    C2 acc[kIlp];
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (k < K) acc = cmul_add<T>(acc, wrow[k], in[k]);
-      out[(((long long)be * Q + b) * d + tp) * Pr + cp] = acc;
+    for (int j = 0; j < kIlp; ++j) acc[j] = C2{T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < K) {
+#pragma unroll
+        for (int j = 0; j < kIlp; ++j) acc[j] = cmul_add<T>(acc[j], Ws[min(o0 + j, nout - 1) * K + k], in[k]);
+      }
     }
+#pragma unroll
+    for (int j = 0; j < kIlp; ++j) {
+      const int o = o0 + j;
+      if (o < nout) out[(((long long)(o / d) * Q + b) * d + o % d) * Pr + cp] = acc[j];
+    }
+  }
 }
 
 template <typename T, int KMAX>
 hipError_t launch_left(const void* Tin, const void* W, void* out, int P, int Q, int wl, int d,
                        int wr, hipStream_t st) {
   const size_t sh = sizeof(cx_t<T>) * (size_t)wl * d * d * wr;
-  dim3 grid((Q + kThreads - 1) / kThreads, P);
+  dim3 grid((Q + kThreads - 1) / kThreads, P, (d * wr + kIlp - 1) / kIlp);
   hipLaunchKernelGGL((wmix_left_kernel<T, KMAX>), grid, dim3(kThreads), sh, st,
                      (const cx_t<T>*)Tin, (const cx_t<T>*)W, (cx_t<T>*)out, Q, wl, d, wr);
   return hipGetLastError();
@@ -110,7 +139,7 @@ template <typename T, int KMAX>
 hipError_t launch_right(const void* U, const void* W, void* out, int Q, int Pr, int wl, int d,
                         int wr, hipStream_t st) {
   const size_t sh = sizeof(cx_t<T>) * (size_t)wl * d * d * wr;
-  dim3 grid((Pr + kThreads - 1) / kThreads, Q);
+  dim3 grid((Pr + kThreads - 1) / kThreads, Q, (wl * d + kIlp - 1) / kIlp);
   hipLaunchKernelGGL((wmix_right_kernel<T, KMAX>), grid, dim3(kThreads), sh, st,
                      (const cx_t<T>*)U, (const cx_t<T>*)W, (cx_t<T>*)out, Q, Pr, wl, d, wr);
   return hipGetLastError();
