@@ -17,7 +17,8 @@ one step of the long-range chain at D = 256 with the w = 271 order-3 MPO on the 
 split-BF16x3 paths (step time and matrix-core rate of the contractions: the "TFLOP/s at D = 256"
 part of the metric),
 the environment-update microbenchmark at D = 256, d = 2, w = 8 (the matrix-core roofline target),
-per-kernel-class times summed over the timed steps, per-step parity of the first step against the
+the Jacobi kernel's time summed over the timed steps (HIP events around its launches only, the
+roofline line) and every kernel class on one extra saturated step, per-step parity of the first step against the
 oracle from the same initial state on each path (infidelity and <Z_32> error), and the CPU oracle timed on one
 saturated-bond step (the cpu_baseline).
 
@@ -349,27 +350,33 @@ def main():
         ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
         return ms, wall, st, dm
 
-    ms, wall, st, dm_end = quench(prec, args.steps, args.warmup, profile=True)
+    # the timed steps time the Jacobi kernel only (HIP events around each launch, on its stream):
+    # events around every kernel class would add a few per cent of host work to the steps
+    ms, wall, st, dm_end = quench(prec, args.steps, args.warmup, profile=mp.PROFILE_JACOBI)
     sec_step = float(np.sum(ms)) / 1e3 / args.steps
     gflop = float(np.mean([x.gflop for x in st]))
 
-    # kernel classes summed over the timed steps (HIP events on the launch stream)
+    def class_table(prof):
+        classes = {
+            "jacobi_svd": {"ms": prof["t_jacobi_ms"], "launches": prof["n_jacobi"], "work": prof["jacobi_gflop"],
+                           "work_unit": "GFLOP", "bound": "alu", "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"},
+            "complex_gemm": {"ms": prof["t_gemm_ms"], "launches": prof["n_gemm"], "work": prof["gemm_gflop"],
+                             "work_unit": "GFLOP", "bound": "mfma",
+                             "peak": {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA,
+                                      mp.BF16X3: CEIL_BF16X3}[prec] / 1e12, "unit": "TFLOP/s"},
+            "w_contraction": {"ms": prof["t_wmix_ms"], "launches": prof["n_wmix"], "work": prof["wmix_gbyte"],
+                              "work_unit": "GB", "bound": "hbm", "peak": PEAK_HBM / 1e9, "unit": "GB/s"},
+        }
+        for c in classes.values():
+            c["achieved"] = c["work"] / (c["ms"] * 1e-3) / (1e3 if c["unit"] == "TFLOP/s" else 1.0) if c["ms"] > 0 else 0.0
+            c["frac"] = c["achieved"] / c["peak"] if c["peak"] else 0.0
+            c["avg_launch_us"] = 1e3 * c["ms"] / max(c["launches"], 1)
+        return classes
+
+    # the Jacobi kernel summed over the timed steps (the dominant kernel: the roofline below)
     prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile}
-    classes = {
-        "jacobi_svd": {"ms": prof["t_jacobi_ms"], "launches": prof["n_jacobi"], "work": prof["jacobi_gflop"],
-                       "work_unit": "GFLOP", "bound": "alu", "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"},
-        "complex_gemm": {"ms": prof["t_gemm_ms"], "launches": prof["n_gemm"], "work": prof["gemm_gflop"],
-                         "work_unit": "GFLOP", "bound": "mfma",
-                         "peak": {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA,
-                                  mp.BF16X3: CEIL_BF16X3}[prec] / 1e12, "unit": "TFLOP/s"},
-        "w_contraction": {"ms": prof["t_wmix_ms"], "launches": prof["n_wmix"], "work": prof["wmix_gbyte"],
-                          "work_unit": "GB", "bound": "hbm", "peak": PEAK_HBM / 1e9, "unit": "GB/s"},
-    }
-    for c in classes.values():
-        c["achieved"] = c["work"] / (c["ms"] * 1e-3) / (1e3 if c["unit"] == "TFLOP/s" else 1.0) if c["ms"] > 0 else 0.0
-        c["frac"] = c["achieved"] / c["peak"] if c["peak"] else 0.0
-        c["avg_launch_us"] = 1e3 * c["ms"] / max(c["launches"], 1)
-    dominant = max(classes, key=lambda k: classes[k]["ms"])
+    classes = {"jacobi_svd": class_table(prof)["jacobi_svd"]}
+    dominant = "jacobi_svd"
 
     # diagnostics of the trajectory on the device (FP64): energy of H(g = 1.5), conserved by the
     # exact evolution, and <Z_32>, at t = 0 and after the last timed step
@@ -401,7 +408,8 @@ def main():
 
     # one step at saturated bond dimension (seeded random MPS, D = 128 on every bulk bond), after
     # two steps that leave the truncations' preconditioners in the workspace
-    def saturated_step(p):
+    # (a fourth step, timing every kernel class, gives the breakdown of a saturated step)
+    def saturated_step(p, breakdown=False):
         rnd = wl.random_mps(np.random.default_rng(0), L, 2, D)
         dmr = mp.DeviceMPS(rnd, Dmax=D)
         wsr = mp.step_workspace(dmr, dw, p)
@@ -413,11 +421,16 @@ def main():
         mp.step(h, dmr, dw, prec=p, input_right_canonical=True, workspace=wsr)
         e.record()
         torch.cuda.synchronize()
-        return s.elapsed_time(e) / 1e3
+        t = s.elapsed_time(e) / 1e3
+        if not breakdown:
+            return t, None
+        sp = mp.step(h, dmr, dw, prec=p, input_right_canonical=True, workspace=wsr, profile=True)
+        torch.cuda.synchronize()
+        return t, class_table(sp.profile)
 
-    sat_s = saturated_step(prec)
+    sat_s, sat_classes = saturated_step(prec, breakdown=True)
     if fp64 is not None:  # the same saturated step on the plain FP64 path
-        fp64["saturated_fp64_s_per_step"] = saturated_step(mp.FP64)
+        fp64["saturated_fp64_s_per_step"] = saturated_step(mp.FP64)[0]
         fp64["saturated_fp32_s_per_step"] = sat_s
         fp64["saturated_fp32_speedup"] = fp64["saturated_fp64_s_per_step"] / sat_s
 
@@ -500,6 +513,7 @@ def main():
                      "unit": classes[dominant]["unit"], "frac": classes[dominant]["frac"],
                      "avg_launch_us": classes[dominant]["avg_launch_us"], "traffic": None},
         "kernel_classes_timed_steps": classes,
+        "kernel_classes_saturated_step": sat_classes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -195,7 +195,8 @@ typedef struct {
   int prec;
   double cutoff;
   int input_right_canonical;
-  int profile;  /* nonzero: time the kernel classes with HIP events (adds host overhead) */
+  int profile;  /* 1: time the kernel classes with HIP events (adds host overhead); 2: time the
+                   Jacobi kernel only (the other classes report zero); 0: none */
   int svd_cold_start; /* nonzero: every truncation starts Jacobi from Theta itself. Zero (the
                          default): a square bond matrix is first multiplied by the unitary the
                          previous truncation of the same bond left in the workspace (a singular

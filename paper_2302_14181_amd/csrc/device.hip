@@ -55,6 +55,7 @@ struct Prof {
   enum Kind { kJacobi = 0, kGemm = 1, kWmix = 2 };
   DeviceState* ds = nullptr;
   hipStream_t st = nullptr;
+  bool all = true;  // time the products and W contractions too (else the Jacobi kernel only)
   struct Rec { int kind; size_t e0; double work; };
   std::vector<Rec> recs;
   size_t next = 0;
@@ -85,8 +86,8 @@ struct Prof {
   }
 };
 
-#define PROF_BEGIN(pr, tok) size_t tok = 0; if (pr) MPOEVO_HIP_TRY((pr)->begin(&tok))
-#define PROF_END(pr, tok, kind, work) if (pr) MPOEVO_HIP_TRY((pr)->end(kind, tok, work))
+#define PROF_BEGIN(pr, tok) size_t tok = 0; if (pr && (pr)->all) MPOEVO_HIP_TRY((pr)->begin(&tok))
+#define PROF_END(pr, tok, kind, work) if (pr && (pr)->all) MPOEVO_HIP_TRY((pr)->end(kind, tok, work))
 
 // ----------------------------------------------------------------------------- small kernels
 __global__ void cast_c128_c64(const double2* __restrict__ in, float2* __restrict__ out, long long n) {
@@ -356,7 +357,7 @@ struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
   size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
-      off_cplt, off_basis, basiscap, off_token, off_gemm, off_xws, total;
+      off_cplt, off_blocks, off_basis, basiscap, off_token, off_gemm, off_xws, total;
 };
 
 StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
@@ -389,6 +390,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_site_tmp2 = take(sizeof(double2) * s.sitecap);
   s.off_sweeps = take(sizeof(int) * (size_t)8 * L);
   s.off_cplt = take(sizeof(int) * (size_t)8 * L);  // per visit: the bond matrix had full rank
+  s.off_blocks = take(sizeof(int) * (size_t)8 * L);  // per visit: column blocks of the Jacobi rounds
   // one unitary per bond (the Jacobi preconditioner carried between visits and steps)
   s.basiscap = (size_t)d * Dmax * d * Dmax;
   s.off_basis = take(sizeof(double2) * s.basiscap * (size_t)std::max(L - 1, 1));
@@ -716,11 +718,13 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   if (opts->profile) {
     prof_obj.ds = ctx.dev;
     prof_obj.st = st;
+    prof_obj.all = opts->profile != 2;
     prof = &prof_obj;
   }
   int* sweeps_buf = reinterpret_cast<int*>(base + lay.off_sweeps);
   int* cplt_buf = reinterpret_cast<int*>(base + lay.off_cplt);
-  struct JacRec { size_t ev; double flop_per_sweep; int slot; };
+  int* blocks_buf = reinterpret_cast<int*>(base + lay.off_blocks);
+  struct JacRec { size_t ev; SvdPlan plan; int slot; };
   std::vector<JacRec> jac_recs;
   double gflop = 0.0;
   auto flop_gemm = [&](double M, double N, double K) { gflop += 8.0 * M * N * K * 1e-9; };
@@ -820,8 +824,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
                               j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi,
-                              cplt_buf + visit));
-        if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
+                              cplt_buf + visit, blocks_buf + visit));
+        if (prof) jac_recs.push_back({jf, sp, visit});
       }
       P[i + 1] = kcap;
       k_slot_of_bond[i + 1] = visit;
@@ -863,8 +867,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         STEP_TRY(svd_truncate(sp, theta, Dmax, opts->cutoff, phi(i), phi(i + 1), kbuf + visit,
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
                               j1, sweeps_buf + visit, qr ? nullptr : wb, last ? nullptr : wb,
-                              ctx.coop_jacobi, cplt_buf + visit));
-        if (prof) jac_recs.push_back({jf, svd_sweep_flop(sp), visit});
+                              ctx.coop_jacobi, cplt_buf + visit, blocks_buf + visit));
+        if (prof) jac_recs.push_back({jf, sp, visit});
       }
       P[i + 1] = kcap;
       k_slot_of_bond[i + 1] = visit;
@@ -884,6 +888,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   std::vector<double> dh(nvis), nh(nvis);
   STEP_TRY(hipMemcpyAsync(swh.data(), sweeps_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(ch.data(), cplt_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
+  std::vector<int> bh(nvis, 0);
+  if (prof) STEP_TRY(hipMemcpyAsync(bh.data(), blocks_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(kh.data(), kbuf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(dh.data(), dbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(nh.data(), nbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
@@ -940,7 +946,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         float ms = 0.f;
         STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.ev], ctx.dev->events[r.ev + 1]));
         stats->t_jacobi_ms += ms;
-        stats->jacobi_gflop += sw[r.slot] * r.flop_per_sweep * 1e-9;
+        stats->jacobi_gflop += sw[r.slot] * svd_sweep_flop(svd_jacobi_plan(r.plan), bh[r.slot]) * 1e-9;
         stats->n_jacobi += 1;
       }
       for (const auto& r : prof->recs) {

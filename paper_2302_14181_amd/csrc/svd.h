@@ -80,6 +80,8 @@ hipError_t svd_configure();
 // launch that can overlap work on other streams; the caller must keep the workgroups of all
 // Jacobi launches in flight at once within what the device holds together (one per compute
 // unit), and the kernel's bounded waits turn a violation into a barrier-timeout status.
+// blocks_dev (device int, nullable): the number of column blocks the Jacobi rounds took (trailing
+// blocks of columns at the rounding floor are left out; see svd_sweep_flop).
 // complete_dev (device int, nullable): 1 when every singular value lies clearly above the
 // rounding floor (X numerically of full column rank), else 0; a square basis_out then needs
 // the costly completion of its columns.
@@ -88,13 +90,18 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                         int* sweeps_dev = nullptr, const double2* warm = nullptr,
-                        double2* basis_out = nullptr, bool coop = true, int* complete_dev = nullptr);
+                        double2* basis_out = nullptr, bool coop = true, int* complete_dev = nullptr,
+                        int* blocks_dev = nullptr);
 
 // Workgroups of the Jacobi launch of a plan.
 inline int svd_grid(const SvdPlan& p) { return p.nb / 2; }
 
-// Algorithmic flops of one Jacobi sweep of a plan (36 mx per column pair visit: 16 mx for the
-// three inner products, 20 mx for the rotation of the two columns).
-double svd_sweep_flop(const SvdPlan& p);
+// Algorithmic flops of one Jacobi sweep of a plan over nb column blocks (the plan's own when
+// nb <= 0), 36 mx per column pair visit: 16 mx for the three inner products, 20 mx for the
+// rotation of the two columns.
+double svd_sweep_flop(const SvdPlan& p, int nb = 0);
+// The plan the Jacobi iteration of a truncation runs on: the plan itself, or for the pivoted-QR
+// plan that of R^dag (nx x min(mx, nx)).
+SvdPlan svd_jacobi_plan(const SvdPlan& p);
 
 }  // namespace mpoevo

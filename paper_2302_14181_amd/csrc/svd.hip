@@ -387,7 +387,7 @@ __device__ inline void store_col(const double2 (&u)[R], double2* c, int lane, in
 template <int RMAX, bool ACC>
 __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPlan p, SvdWs w,
                                                                           double tol, int* status,
-                                                                          int* sweeps_out) {
+                                                                          int* sweeps_out, int* blocks_out) {
   extern __shared__ double2 cols[];  // [2b][mx] then (ACC) [2b][nx]
   __shared__ unsigned wg_max;        // bits of a non-negative float: integer order = value order
   __shared__ double floor2_sh;
@@ -571,6 +571,7 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   if (blockIdx.x == 0 && tid == 0) {
     atomicMax(&status[1], done_sweeps);
     if (sweeps_out) *sweeps_out = done_sweeps;
+    if (blocks_out) *blocks_out = nbe;
     if (!ok) atomicOr(status, kStatusBarrierTimeout);
     else if (!conv) {
       atomicOr(status, kStatusNotConverged);
@@ -1279,10 +1280,13 @@ SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap) {
   return p;
 }
 
-double svd_sweep_flop(const SvdPlan& p) {
+SvdPlan svd_jacobi_plan(const SvdPlan& p) { return p.qr ? rdag_plan(p) : p; }
+
+double svd_sweep_flop(const SvdPlan& p, int nb) {
   // one full round (every pair inside a block pair) and nb - 2 cross rounds (b x b pairs)
+  if (nb <= 0) nb = p.nb;
   const double pair_visits =
-      (double)(p.nb / 2) * (p.b * (2.0 * p.b - 1) + (double)(p.nb - 2) * p.b * p.b);
+      (double)(nb / 2) * (p.b * (2.0 * p.b - 1) + (double)(nb - 2) * p.b * p.b);
   return pair_visits * (36.0 * p.mx + (p.acc ? 20.0 * p.nx : 0.0));
 }
 
@@ -1290,7 +1294,8 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         double2* A_out, double2* B_out, int* k_dev, double* disc_dev,
                         double* norm_dev, double* sigma_dev, void* ws, int* status,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int* sweeps_dev,
-                        const double2* warm, double2* basis_out, bool coop, int* complete_dev) {
+                        const double2* warm, double2* basis_out, bool coop, int* complete_dev,
+                        int* blocks_dev) {
   if (p.nb / 2 > kMaxGrid || p.threads != 64 * p.b || (p.acc && p.nx > p.mx) ||
       (p.qr && (p.acc || std::max(p.mx, p.nx) > kQrMaxDim || 2 * p.b > kQrThreads / 64)))
     return hipErrorInvalidConfiguration;
@@ -1359,7 +1364,8 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     double tt = tol;
     int* stp = status;
     int* swp = sweeps_dev;
-    void* args[] = {&pp, &ww, &tt, &stp, &swp};
+    int* bkp = blocks_dev;
+    void* args[] = {&pp, &ww, &tt, &stp, &swp, &bkp};
     if (ev0) MPOEVO_HIP_TRY(hipEventRecord(ev0, st));
     if (coop)
       MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(jacobi_for(pj), dim3(pj.nb / 2), dim3(pj.threads), args,

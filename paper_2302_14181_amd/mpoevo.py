@@ -321,8 +321,9 @@ def step_workspace(mps: DeviceMPS, mpo: DeviceMPO, prec: int):
 
 def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int = FP64,
          cutoff: float = 1e-14, input_right_canonical: bool = False, workspace=None,
-         stream=None, profile: bool = False, svd_cold_start: bool = False) -> StepStats:
-    """One time step of the variational fit; mps is updated in place (see include/mpoevo.h)."""
+         stream=None, profile=False, svd_cold_start: bool = False) -> StepStats:
+    """One time step of the variational fit; mps is updated in place (see include/mpoevo.h).
+    profile: False, True (time every kernel class) or PROFILE_JACOBI (the Jacobi kernel only)."""
     if workspace is None:
         workspace = step_workspace(mps, mpo, prec)
     bond = _iarr(mps.bond)
@@ -330,7 +331,7 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
     cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
     cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
-    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), int(bool(profile)),
+    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
                  int(bool(svd_cold_start)))
     st = _Stats()
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
@@ -339,7 +340,20 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     return _stats_of(st, profile)
 
 
-def _stats_of(st, profile: bool) -> StepStats:
+PROFILE_JACOBI = 2  # step option: time the Jacobi kernel only (least host overhead)
+
+
+def _profile_code(profile) -> int:
+    if profile is True or profile == 1:
+        return 1
+    if profile == PROFILE_JACOBI:
+        return PROFILE_JACOBI
+    if not profile:
+        return 0
+    raise ValueError("profile must be False, True or PROFILE_JACOBI")
+
+
+def _stats_of(st, profile) -> StepStats:
     prof = None
     if profile:
         prof = {k: getattr(st, k) for k in ("t_jacobi_ms", "jacobi_gflop", "n_jacobi", "t_gemm_ms",
@@ -376,7 +390,7 @@ def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cu
         keep += [bond, sites, w, wsites]
         cms[c] = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
         cws[c] = _MPO(mpo.L, mpo.d, w, wsites)
-    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), int(bool(profile)),
+    opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
                  int(bool(svd_cold_start)))
     st = (_Stats * n)()
     _check(load().step_batched(h.ptr, n, cms, cws, ctypes.byref(opts), st, _ptr(workspace),
