@@ -409,8 +409,9 @@ def main():
     # one step at saturated bond dimension (seeded random MPS, D = 128 on every bulk bond), after
     # two steps that leave the truncations' preconditioners in the workspace
     # (a fourth step, timing every kernel class, gives the breakdown of a saturated step)
+    rnd = wl.random_mps(np.random.default_rng(0), L, 2, D)
+
     def saturated_step(p, breakdown=False):
-        rnd = wl.random_mps(np.random.default_rng(0), L, 2, D)
         dmr = mp.DeviceMPS(rnd, Dmax=D)
         wsr = mp.step_workspace(dmr, dw, p)
         mp.step(h, dmr, dw, prec=p, workspace=wsr)
