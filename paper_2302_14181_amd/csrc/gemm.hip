@@ -1,6 +1,7 @@
 // Complex strided-batched matrix products on the gfx950 matrix cores.
 //
-// A complex product C = A B (M x N x K complex multiply-adds) is computed as the real product
+// FP32 operands: three real products per complex multiply-add (cgemm3m_kernel, below). FP64:
+// a complex product C = A B (M x N x K complex multiply-adds) is computed as the real product
 // C' = A' B' of size M x 2N x 2K with
 //   A'[m][2k + p]          = (re, im)[p] of A[m][k]            (the interleaved storage itself)
 //   B'[2k + p][2n + q]     = [[re, im], [-im, re]][p][q] of B[k][n]
@@ -9,8 +10,9 @@
 // multiply-add) and needs no extra pass over memory: A tiles are stored to LDS planar by real
 // k, B tiles are expanded to their real 2x2 form while they are staged.
 //
-// fp32: v_mfma_f32_32x32x2f32 (lane l supplies A'[l%32][l/32], B'[l/32][l%32]; accumulator r of
-//       lane l holds C'[(r/4)*8 + (l/32)*4 + r%4][l%32]).
+// fp32 (the three-product kernel, on each real operand plane): v_mfma_f32_32x32x2f32 (lane l
+//       supplies A[l%32][l/32], B[l/32][l%32]; accumulator r of lane l holds
+//       C[(r/4)*8 + (l/32)*4 + r%4][l%32]).
 // fp64: v_mfma_f64_16x16x4f64 (lane l supplies A'[l%16][l/16], B'[l/16][l%16]; accumulator r of
 //       lane l holds C'[4r + l/16][l%16]).
 // A workgroup of 4 waves (2 x 2, each wave WR x WC matrix-instruction tiles) owns a BM x BN
@@ -43,15 +45,10 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// fp32 32 x 32 instructions (the three-product and split-BF16x3 kernels): element type of the
+// plans, and the output layout of an accumulator.
 struct MfmaF32 {
   using T = float;
-  using acc_t = f32x16;
-  static constexpr int MT = 32, NT = 32, KT = 2, NACC = 16;
-  __device__ static acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static int a_row(int l) { return l & 31; }
-  __device__ static int a_k(int l) { return l >> 5; }
   __device__ static int out_row(int l, int r) { return (r >> 2) * 8 + (l >> 5) * 4 + (r & 3); }
   __device__ static int out_col(int l) { return l & 31; }
 };
@@ -259,6 +256,196 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
             P[2 * (pbase + (long long)row * g.N + col) + (rcol & 1)] = acc[i][j][r];
         }
   }
+}
+
+// FP32 complex product with three real products per complex multiply-add (Gauss):
+//   P1 = Re A Re B,  P2 = Im A Im B,  P3 = (Re A + Im A)(Re B + Im B),
+//   Re C = P1 - P2,  Im C = P3 - P1 - P2,
+// three v_mfma_f32_32x32x2f32 accumulators per 32 x 32 complex block instead of the four real
+// products of the expanded form (the algorithmic count stays 8 flops per complex multiply-add).
+// A and B are staged in LDS as three k-contiguous planes each (real part, imaginary part, their
+// sum, formed while staging), rows [m][k] and [n][k], in the consumption order of the fp32
+// instruction (kpos below), so that each lane fetches the operands of four instructions with one
+// 16-byte read per plane. A workgroup of 4 waves (2 x 2, each wave WR x WC blocks of 32 x 32
+// complex outputs) owns a BM x BN complex tile, double-buffered with one barrier per K step of BK.
+// Rounding: the sums carry one more rounding and Im C a difference of products, so its error
+// bound is about twice that of the expanded form, normwise.
+template <int WR, int WC, int BK_>
+struct Tile3 {
+  static constexpr int BK = BK_;               // complex K per stage
+  static constexpr int BM = 2 * WR * 32;       // complex rows per workgroup
+  static constexpr int BN = 2 * WC * 32;       // complex columns per workgroup
+  static constexpr int V = 4, KT = 2, G = KT * V;
+  static constexpr int PITCH = BK + V;         // LDS row length (floats)
+  static constexpr int A_ELEMS = BM * BK / kThreads;
+  static constexpr int B_ELEMS = BN * BK / kThreads;
+  static constexpr int PLANE_A = BM * PITCH, PLANE_B = BN * PITCH;
+  static constexpr int STAGE = 3 * (PLANE_A + PLANE_B);
+  static_assert(A_ELEMS >= 1 && B_ELEMS >= 1, "tile too small for the staging scheme");
+  static_assert(BK % G == 0 && ((PITCH * 4 / 16) & 1), "staging layout");
+  __device__ static int kpos(int k) {
+    const int w = k % G;
+    return k - w + (w % KT) * V + w / KT;
+  }
+};
+
+template <int WR, int WC, int BK, typename TO, bool AKC, bool BNC>
+__global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int splits, int kchunk,
+                                                           void* part) {
+  using TT = Tile3<WR, WC, BK>;
+  using C2 = float2;
+  __shared__ __attribute__((aligned(16))) float lds[2 * TT::STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int bz = blockIdx.z / splits;
+  const int sk = blockIdx.z - bz * splits;
+  const int kbeg = sk * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+  const int m0 = blockIdx.y * TT::BM;
+  const int n0 = blockIdx.x * TT::BN;
+
+  const C2* A = reinterpret_cast<const C2*>(g.A) + bz * g.bA;
+  const C2* B = reinterpret_cast<const C2*>(g.B) + bz * g.bB;
+  const float sgnA = g.conjA ? -1.f : 1.f;
+  const float sgnB = g.conjB ? -1.f : 1.f;
+
+  C2 ra[TT::A_ELEMS];
+  C2 rb[TT::B_ELEMS];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < TT::A_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int m, k;
+      if (AKC) { m = e / BK; k = e % BK; } else { k = e / TT::BM; m = e % TT::BM; }
+      const int gm = m0 + m, gk = k0 + k;
+      C2 v{0.f, 0.f};
+      if (gm < g.M && gk < kend) v = A[gm * g.sAm + gk * g.sAk];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < TT::B_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int k, n;
+      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / BK; k = e % BK; }
+      const int gk = k0 + k, gn = n0 + n;
+      C2 v{0.f, 0.f};
+      if (gk < kend && gn < g.N) v = B[gk * g.sBk + gn * g.sBn];
+      rb[i] = v;
+    }
+  };
+  auto store_tiles = [&](int buf) {
+    float* Ar = lds + buf * TT::STAGE;
+    float* Ai = Ar + TT::PLANE_A;
+    float* As = Ai + TT::PLANE_A;
+    float* Br = As + TT::PLANE_A;
+    float* Bi = Br + TT::PLANE_B;
+    float* Bs = Bi + TT::PLANE_B;
+#pragma unroll
+    for (int i = 0; i < TT::A_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int m, k;
+      if (AKC) { m = e / BK; k = e % BK; } else { k = e / TT::BM; m = e % TT::BM; }
+      const int pp = m * TT::PITCH + TT::kpos(k);
+      const float re = ra[i].x, im = sgnA * ra[i].y;
+      Ar[pp] = re;
+      Ai[pp] = im;
+      As[pp] = re + im;
+    }
+#pragma unroll
+    for (int i = 0; i < TT::B_ELEMS; ++i) {
+      const int e = tid + i * kThreads;
+      int k, n;
+      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / BK; k = e % BK; }
+      const int pp = n * TT::PITCH + TT::kpos(k);
+      const float re = rb[i].x, im = sgnB * rb[i].y;
+      Br[pp] = re;
+      Bi[pp] = im;
+      Bs[pp] = re + im;
+    }
+  };
+
+  f32x16 p1[WR][WC], p2[WR][WC], p3[WR][WC];
+#pragma unroll
+  for (int i = 0; i < WR; ++i)
+#pragma unroll
+    for (int j = 0; j < WC; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) p1[i][j][r] = p2[i][j][r] = p3[i][j][r] = 0.f;
+
+  const int nk = (kend - kbeg + BK - 1) / BK;
+  load_tiles(kbeg);
+  store_tiles(0);
+  __syncthreads();
+
+  const int arow = lane & 31, ak = lane >> 5;
+  using VecT = float __attribute__((ext_vector_type(4)));
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
+    const float* Ar = lds + cur * TT::STAGE;
+    const float* Ai = Ar + TT::PLANE_A;
+    const float* As = Ai + TT::PLANE_A;
+    const float* Br = As + TT::PLANE_A;
+    const float* Bi = Br + TT::PLANE_B;
+    const float* Bs = Bi + TT::PLANE_B;
+#pragma unroll
+    for (int kg = 0; kg < BK; kg += TT::G) {
+      VecT ar_[WR], ai_[WR], as_[WR], br_[WC], bi_[WC], bs_[WC];
+#pragma unroll
+      for (int i = 0; i < WR; ++i) {
+        const int o = (wm * (WR * 32) + i * 32 + arow) * TT::PITCH + kg + ak * TT::V;
+        ar_[i] = *reinterpret_cast<const VecT*>(Ar + o);
+        ai_[i] = *reinterpret_cast<const VecT*>(Ai + o);
+        as_[i] = *reinterpret_cast<const VecT*>(As + o);
+      }
+#pragma unroll
+      for (int j = 0; j < WC; ++j) {
+        const int o = (wn * (WC * 32) + j * 32 + arow) * TT::PITCH + kg + ak * TT::V;
+        br_[j] = *reinterpret_cast<const VecT*>(Br + o);
+        bi_[j] = *reinterpret_cast<const VecT*>(Bi + o);
+        bs_[j] = *reinterpret_cast<const VecT*>(Bs + o);
+      }
+#pragma unroll
+      for (int q = 0; q < TT::V; ++q)
+#pragma unroll
+        for (int i = 0; i < WR; ++i)
+#pragma unroll
+          for (int j = 0; j < WC; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar_[i][q], br_[j][q], p1[i][j], 0, 0, 0);
+            p2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai_[i][q], bi_[j][q], p2[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as_[i][q], bs_[j][q], p3[i][j], 0, 0, 0);
+          }
+    }
+    if (kt + 1 < nk) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < WR; ++i)
+#pragma unroll
+    for (int j = 0; j < WC; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * (WR * 32) + i * 32 + MfmaF32::out_row(lane, r);
+        const int col = n0 + wn * (WC * 32) + j * 32 + MfmaF32::out_col(lane);
+        if (row >= g.M || col >= g.N) continue;
+        const float a = p1[i][j][r], b = p2[i][j][r];
+        const float re = a - b, im = p3[i][j][r] - a - b;
+        if (splits == 1) {
+          TO* C = reinterpret_cast<TO*>(g.C);
+          const long long o = (long long)bz * g.bC + (long long)row * g.sCm + (long long)col * g.sCn;
+          C[2 * o] = TO(re);
+          C[2 * o + 1] = TO(im);
+        } else {
+          float* P = reinterpret_cast<float*>(part);
+          const long long o = (long long)(sk * g.batch + bz) * g.M * g.N + (long long)row * g.N + col;
+          P[2 * o] = re;
+          P[2 * o + 1] = im;
+        }
+      }
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -490,7 +677,7 @@ Plan make_plan(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
   return p;
 }
 
-constexpr int kF32Cfg[3][2] = {{128, 64}, {64, 64}, {64, 32}};
+constexpr int kF32Cfg[3][2] = {{128, 64}, {64, 64}, {64, 32}};  // split-BF16x3 tiles
 constexpr int kF64Cfg[2][2] = {{64, 64}, {32, 32}};
 
 template <class Mf, int WR, int WC, int BK, typename TO>
@@ -520,15 +707,41 @@ hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   return hipSuccess;
 }
 
-template <typename TO>
-hipError_t launch_f32(const GemmDesc& g, hipStream_t st) {
-  const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);
-  switch (pl.cfg) {
-    case 0: return launch_cfg<MfmaF32, 2, 2, 16, TO>(g, pl, st);
-    case 1: return launch_cfg<MfmaF32, 1, 2, 32, TO>(g, pl, st);
-    default: return launch_cfg<MfmaF32, 1, 1, 32, TO>(g, pl, st);
+constexpr int k3mCfg[2][2] = {{128, 64}, {64, 64}};
+
+template <int WR, int WC, int BK, typename TO>
+hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
+  using TT = Tile3<WR, WC, BK>;
+  dim3 grid((g.N + TT::BN - 1) / TT::BN, (g.M + TT::BM - 1) / TT::BM, g.batch * pl.splits);
+  const bool akc = (g.sAk == 1) || (g.K == 1);
+  const bool bnc = (g.sBn == 1) || (g.N == 1);
+  void* part = pl.splits > 1 ? g.ws : nullptr;
+  if (akc && bnc)
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, true, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else if (akc)
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, true, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else if (bnc)
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  else
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  MPOEVO_HIP_TRY(hipGetLastError());
+  if (pl.splits > 1) {
+    const long long total = (long long)g.M * g.N * g.batch;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL((splitk_reduce<float, TO>), dim3(blocks), dim3(256), 0, st, g, pl.splits,
+                       static_cast<const float*>(part));
+    MPOEVO_HIP_TRY(hipGetLastError());
   }
+  return hipSuccess;
 }
+
+template <typename TO>
+hipError_t launch_3m(const GemmDesc& g, hipStream_t st) {
+  const Plan pl = make_plan<MfmaF32>(g, k3mCfg, 2);
+  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, TO>(g, pl, st);
+  return launch_3m_cfg<1, 1, 32, TO>(g, pl, st);
+}
+
 
 template <int WR, int WC, int BK, typename TO>
 hipError_t launch_bf16x3_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
@@ -558,7 +771,7 @@ hipError_t launch_bf16x3_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) 
 
 template <typename TO>
 hipError_t launch_bf16x3(const GemmDesc& g, hipStream_t st) {
-  const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);  // same tiles and split-K scratch as fp32
+  const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);
   switch (pl.cfg) {
     case 0: return launch_bf16x3_cfg<2, 2, 16, TO>(g, pl, st);
     case 1: return launch_bf16x3_cfg<1, 2, 16, TO>(g, pl, st);
@@ -579,8 +792,7 @@ hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t 
   if (g.K <= 0) return hipErrorInvalidValue;
   if (fp64) return launch_f64(g, st);
   if (g.bf16x3) return out_fp64 ? launch_bf16x3<double>(g, st) : launch_bf16x3<float>(g, st);
-  if (out_fp64) return launch_f32<double>(g, st);
-  return launch_f32<float>(g, st);
+  return out_fp64 ? launch_3m<double>(g, st) : launch_3m<float>(g, st);
 }
 
 }  // namespace mpoevo
