@@ -69,7 +69,8 @@ struct MfmaF64 {
 constexpr int kThreads = 256;
 constexpr int kKGrain = 8;      // split-K chunks are multiples of this
 constexpr int kMinWgs = 256;    // a tile giving at least this many workgroups is used as is
-constexpr int kTargetWgs = 512; // split K up to this many workgroups
+constexpr int kTargetWgs = 256; // split K up to this many workgroups (one per compute unit:
+                                // more splits cost more in the reduction than they gain)
 constexpr int kMaxSplits = 16;
 constexpr int kMinSplitK = 32;  // complex K per split, at least
 
