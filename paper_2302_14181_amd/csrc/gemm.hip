@@ -630,21 +630,30 @@ __global__ __launch_bounds__(kThreads) void cgemm_bf16x3_kernel(GemmDesc g, int 
 // C[b][m][n] = sum over s = 0..splits-1 (in that order) of part[s][b][m][n].
 template <typename T, typename TO>
 __global__ void splitk_reduce(GemmDesc g, int splits, const T* __restrict__ part) {
+  using C2 = cx_t<T>;
+  using CO = cx_t<TO>;
   const long long mn = (long long)g.M * g.N;
   const long long total = mn * g.batch;
-  TO* C = reinterpret_cast<TO*>(g.C);
+  const C2* pc = reinterpret_cast<const C2*>(part);
+  CO* C = reinterpret_cast<CO*>(g.C);
+  // a row-major output packed like the partial tiles needs no index arithmetic (no 64-bit
+  // divisions, which would set the pace here)
+  const bool packed = g.sCn == 1 && g.sCm == g.N && (g.batch == 1 || g.bC == mn);
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    T re = T(0), im = T(0);
-    for (int s = 0; s < splits; ++s) {
-      re += part[2 * (s * total + idx)];
-      im += part[2 * (s * total + idx) + 1];
+    C2 acc{T(0), T(0)};
+    for (int s = 0; s < splits; ++s) {  // one complex load per split
+      const C2 v = pc[s * total + idx];
+      acc.x += v.x;
+      acc.y += v.y;
     }
-    const long long b = idx / mn, rem = idx - b * mn;
-    const long long row = rem / g.N, col = rem - row * g.N;
-    const long long o = b * g.bC + row * g.sCm + col * g.sCn;
-    C[2 * o] = TO(re);
-    C[2 * o + 1] = TO(im);
+    long long o = idx;
+    if (!packed) {
+      const long long b = idx / mn, rem = idx - b * mn;
+      const long long row = rem / g.N, col = rem - row * g.N;
+      o = b * g.bC + row * g.sCm + col * g.sCn;
+    }
+    C[o] = CO{TO(acc.x), TO(acc.y)};
   }
 }
 
