@@ -429,11 +429,12 @@ __global__ __launch_bounds__(RMAX <= 8 ? 512 : 256) void svd_jacobi_kernel(SvdPl
   bool ok = true;
   int sweep = 0;
   unsigned gen = 0;
-  // The verdict on sweep s is read in round 1 of sweep s + 1, after a wait for every workgroup
-  // to have finished sweep s: by then the slower workgroups have mostly caught up, so no
-  // workgroup idles at the end of each sweep. A converged sweep thus keeps the rotations of the
-  // next sweep's first round (pairs below tol are not rotated; the others only further). With a
-  // single round per sweep, and after the last allowed sweep, the verdict is read at once.
+  // The verdict on sweep s is read in the second pairing step (r = 1) of sweep s + 1, after a
+  // wait for every workgroup to have finished sweep s: by then the slower workgroups have mostly
+  // caught up, so no workgroup idles at the end of each sweep. A converged sweep thus keeps the
+  // rotations of the next sweep's first pairing step (pairs below tol are not rotated; the others
+  // only further). With a single pairing step per sweep, and after the last allowed sweep, the
+  // verdict is read at once.
   const int rounds = nbe - 1;
   auto converged = [&](int s) {
     const double mxr = (double)__uint_as_float(
