@@ -267,40 +267,50 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
 // A and B are staged in LDS as three k-contiguous planes each (real part, imaginary part, their
 // sum, formed while staging), rows [m][k] and [n][k], in the consumption order of the fp32
 // instruction (kpos below), so that each lane fetches the operands of four instructions with one
-// 16-byte read per plane. A workgroup of 4 waves (2 x 2, each wave WR x WC blocks of 32 x 32
-// complex outputs) owns a BM x BN complex tile, double-buffered with one barrier per K step of BK.
+// 16-byte read per plane. A workgroup of KW groups of 4 waves (2 x 2, each wave WR x WC blocks of
+// 32 x 32 complex outputs) owns a BM x BN complex tile, double-buffered with one barrier per K
+// step of BK; with KW = 2 the two groups take the two halves of every step (two waves per SIMD,
+// so that one wave's staging and barrier wait overlap the other's matrix instructions) and their
+// partial sums meet in LDS at the end.
 // Rounding: the sums carry one more rounding and Im C a difference of products, so its error
 // bound is about twice that of the expanded form, normwise.
-template <int WR, int WC, int BK_>
+template <int WR, int WC, int BK_, int KW_>
 struct Tile3 {
   static constexpr int BK = BK_;               // complex K per stage
+  static constexpr int KW = KW_;               // wave groups along K
+  static constexpr int NT = kThreads * KW;     // threads per workgroup
   static constexpr int BM = 2 * WR * 32;       // complex rows per workgroup
   static constexpr int BN = 2 * WC * 32;       // complex columns per workgroup
   static constexpr int V = 4, KT = 2, G = KT * V;
+  static constexpr int KG = BK / KW;           // complex K per wave group and stage
   static constexpr int PITCH = BK + V;         // LDS row length (floats)
-  static constexpr int A_ELEMS = BM * BK / kThreads;
-  static constexpr int B_ELEMS = BN * BK / kThreads;
+  static constexpr int A_ELEMS = BM * BK / NT;
+  static constexpr int B_ELEMS = BN * BK / NT;
   static constexpr int PLANE_A = BM * PITCH, PLANE_B = BN * PITCH;
   static constexpr int STAGE = 3 * (PLANE_A + PLANE_B);
-  static_assert(A_ELEMS >= 1 && B_ELEMS >= 1, "tile too small for the staging scheme");
-  static_assert(BK % G == 0 && ((PITCH * 4 / 16) & 1), "staging layout");
+  static_assert(A_ELEMS >= 4 && B_ELEMS >= 4 && A_ELEMS % 4 == 0 && B_ELEMS % 4 == 0,
+                "tile too small for the staging scheme");
+  static_assert(BK % G == 0 && KG % G == 0 && ((PITCH * 4 / 16) & 1), "staging layout");
+  static_assert(KW == 1 || 2 * BM * BN <= 2 * STAGE, "LDS too small for the wave-group sum");
+  static_assert(KW == 1 || KW == 2, "one or two wave groups along K");
   __device__ static int kpos(int k) {
     const int w = k % G;
     return k - w + (w % KT) * V + w / KT;
   }
 };
 
-template <int WR, int WC, int BK, typename TO, bool AKC, bool BNC>
-__global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int splits, int kchunk,
-                                                           void* part) {
-  using TT = Tile3<WR, WC, BK>;
+template <int WR, int WC, int BK, int KW, typename TO, bool AKC, bool BNC>
+__global__ __launch_bounds__(kThreads * KW) void cgemm3m_kernel(GemmDesc g, int splits,
+                                                                int kchunk, void* part) {
+  using TT = Tile3<WR, WC, BK, KW>;
   using C2 = float2;
   __shared__ __attribute__((aligned(16))) float lds[2 * TT::STAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int kw = wave >> 2;  // wave group: the K slice [kw KG, (kw+1) KG) of every stage
+  const int wm = (wave >> 1) & 1, wn = wave & 1;
   const int bz = blockIdx.z / splits;
   const int sk = blockIdx.z - bz * splits;
   const int kbeg = sk * kchunk;
@@ -313,30 +323,77 @@ __global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int split
   const float sgnA = g.conjA ? -1.f : 1.f;
   const float sgnB = g.conjB ? -1.f : 1.f;
 
+  // An operand whose rows are not contiguous in k (A not k-contiguous, B not n-major) is
+  // staged in quads: a thread loads k = kb, kb + 2, kb + 4, kb + 6 of one row (each load
+  // coalesced across the lanes, which take consecutive rows) and writes them, adjacent in the
+  // instruction order, with one 16-byte LDS store per plane (conflict-free: the row pitch is an
+  // odd number of 16-byte units). A k-contiguous operand is staged element by element, the lanes
+  // running along k.
   C2 ra[TT::A_ELEMS];
   C2 rb[TT::B_ELEMS];
-  auto load_tiles = [&](int k0) {
+  auto quad = [](int q, int rows, int& r, int& kb, int& pos) {
+    r = q % rows;
+    const int kk = q / rows;  // (group of 8 k, parity)
+    kb = 8 * (kk >> 1) + (kk & 1);
+    pos = 8 * (kk >> 1) + 4 * (kk & 1);
+  };
+  // Per-thread load addresses, set up once and advanced by one stage (BK k) per load_tiles call;
+  // an element is loaded when its row is inside the matrix and its k below kend. Rows past the
+  // edge address the last row (never read).
+  const C2* pa[TT::A_ELEMS];
+  const C2* pb[TT::B_ELEMS];
+  int ka[TT::A_ELEMS], kb_[TT::B_ELEMS];
+  bool va[TT::A_ELEMS], vb[TT::B_ELEMS];
+#pragma unroll
+  for (int i = 0; i < TT::A_ELEMS; ++i) {
+    int m, k;
+    if (AKC) {
+      const int e = tid + i * TT::NT;
+      m = e / BK; k = e % BK;
+    } else {
+      int kb, pos;
+      quad(tid + (i / 4) * TT::NT, TT::BM, m, kb, pos);
+      k = kb + 2 * (i % 4);
+    }
+    va[i] = m0 + m < g.M;
+    ka[i] = k;
+    pa[i] = A + (long long)min(m0 + m, g.M - 1) * g.sAm + (long long)(kbeg + k) * g.sAk;
+  }
+#pragma unroll
+  for (int i = 0; i < TT::B_ELEMS; ++i) {
+    int n, k;
+    if (!BNC) {
+      const int e = tid + i * TT::NT;
+      n = e / BK; k = e % BK;
+    } else {
+      int kb, pos;
+      quad(tid + (i / 4) * TT::NT, TT::BN, n, kb, pos);
+      k = kb + 2 * (i % 4);
+    }
+    vb[i] = n0 + n < g.N;
+    kb_[i] = k;
+    pb[i] = B + (long long)(kbeg + k) * g.sBk + (long long)min(n0 + n, g.N - 1) * g.sBn;
+  }
+  const long long stepA = (long long)BK * g.sAk, stepB = (long long)BK * g.sBk;
+  int krem = kend - kbeg;  // k left from the next stage to load on
+  auto load_tiles = [&]() {
 #pragma unroll
     for (int i = 0; i < TT::A_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int m, k;
-      if (AKC) { m = e / BK; k = e % BK; } else { k = e / TT::BM; m = e % TT::BM; }
-      const int gm = m0 + m, gk = k0 + k;
       C2 v{0.f, 0.f};
-      if (gm < g.M && gk < kend) v = A[gm * g.sAm + gk * g.sAk];
+      if (va[i] && ka[i] < krem) v = *pa[i];
       ra[i] = v;
+      pa[i] += stepA;
     }
 #pragma unroll
     for (int i = 0; i < TT::B_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int k, n;
-      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / BK; k = e % BK; }
-      const int gk = k0 + k, gn = n0 + n;
       C2 v{0.f, 0.f};
-      if (gk < kend && gn < g.N) v = B[gk * g.sBk + gn * g.sBn];
+      if (vb[i] && kb_[i] < krem) v = *pb[i];
       rb[i] = v;
+      pb[i] += stepB;
     }
+    krem -= BK;
   };
+  using V4 = float __attribute__((ext_vector_type(4)));
   auto store_tiles = [&](int buf) {
     float* Ar = lds + buf * TT::STAGE;
     float* Ai = Ar + TT::PLANE_A;
@@ -344,27 +401,59 @@ __global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int split
     float* Br = As + TT::PLANE_A;
     float* Bi = Br + TT::PLANE_B;
     float* Bs = Bi + TT::PLANE_B;
+    if (AKC) {
 #pragma unroll
-    for (int i = 0; i < TT::A_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int m, k;
-      if (AKC) { m = e / BK; k = e % BK; } else { k = e / TT::BM; m = e % TT::BM; }
-      const int pp = m * TT::PITCH + TT::kpos(k);
-      const float re = ra[i].x, im = sgnA * ra[i].y;
-      Ar[pp] = re;
-      Ai[pp] = im;
-      As[pp] = re + im;
+      for (int i = 0; i < TT::A_ELEMS; ++i) {
+        const int e = tid + i * TT::NT;
+        const int pp = (e / BK) * TT::PITCH + TT::kpos(e % BK);
+        const float re = ra[i].x, im = sgnA * ra[i].y;
+        Ar[pp] = re;
+        Ai[pp] = im;
+        As[pp] = re + im;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < TT::A_ELEMS / 4; ++i) {
+        int m, kb, pos;
+        quad(tid + i * TT::NT, TT::BM, m, kb, pos);
+        const int pp = m * TT::PITCH + pos;
+        V4 re, im;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          re[j] = ra[4 * i + j].x;
+          im[j] = sgnA * ra[4 * i + j].y;
+        }
+        *reinterpret_cast<V4*>(Ar + pp) = re;
+        *reinterpret_cast<V4*>(Ai + pp) = im;
+        *reinterpret_cast<V4*>(As + pp) = re + im;
+      }
     }
+    if (!BNC) {
 #pragma unroll
-    for (int i = 0; i < TT::B_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int k, n;
-      if (BNC) { k = e / TT::BN; n = e % TT::BN; } else { n = e / BK; k = e % BK; }
-      const int pp = n * TT::PITCH + TT::kpos(k);
-      const float re = rb[i].x, im = sgnB * rb[i].y;
-      Br[pp] = re;
-      Bi[pp] = im;
-      Bs[pp] = re + im;
+      for (int i = 0; i < TT::B_ELEMS; ++i) {
+        const int e = tid + i * TT::NT;
+        const int pp = (e / BK) * TT::PITCH + TT::kpos(e % BK);
+        const float re = rb[i].x, im = sgnB * rb[i].y;
+        Br[pp] = re;
+        Bi[pp] = im;
+        Bs[pp] = re + im;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < TT::B_ELEMS / 4; ++i) {
+        int n, kb, pos;
+        quad(tid + i * TT::NT, TT::BN, n, kb, pos);
+        const int pp = n * TT::PITCH + pos;
+        V4 re, im;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          re[j] = rb[4 * i + j].x;
+          im[j] = sgnB * rb[4 * i + j].y;
+        }
+        *reinterpret_cast<V4*>(Br + pp) = re;
+        *reinterpret_cast<V4*>(Bi + pp) = im;
+        *reinterpret_cast<V4*>(Bs + pp) = re + im;
+      }
     }
   };
 
@@ -376,16 +465,23 @@ __global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int split
 #pragma unroll
       for (int r = 0; r < 16; ++r) p1[i][j][r] = p2[i][j][r] = p3[i][j][r] = 0.f;
 
+  // Software pipeline: the tile of stage kt + 1, loaded into registers during stage kt - 1, is
+  // stored to the other LDS buffer at the top of stage kt, then the loads of stage kt + 2 are
+  // issued, then stage kt's matrix instructions run; one barrier per stage.
   const int nk = (kend - kbeg + BK - 1) / BK;
-  load_tiles(kbeg);
+  load_tiles();
   store_tiles(0);
+  if (nk > 1) load_tiles();
   __syncthreads();
 
   const int arow = lane & 31, ak = lane >> 5;
   using VecT = float __attribute__((ext_vector_type(4)));
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
+    if (kt + 1 < nk) {
+      store_tiles(cur ^ 1);  // its readers finished at the previous barrier
+      if (kt + 2 < nk) load_tiles();
+    }
     const float* Ar = lds + cur * TT::STAGE;
     const float* Ai = Ar + TT::PLANE_A;
     const float* As = Ai + TT::PLANE_A;
@@ -393,7 +489,7 @@ __global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int split
     const float* Bi = Br + TT::PLANE_B;
     const float* Bs = Bi + TT::PLANE_B;
 #pragma unroll
-    for (int kg = 0; kg < BK; kg += TT::G) {
+    for (int kg = kw * TT::KG; kg < (kw + 1) * TT::KG; kg += TT::G) {
       VecT ar_[WR], ai_[WR], as_[WR], br_[WC], bi_[WC], bs_[WC];
 #pragma unroll
       for (int i = 0; i < WR; ++i) {
@@ -420,10 +516,29 @@ __global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int split
             p3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as_[i][q], bs_[j][q], p3[i][j], 0, 0, 0);
           }
     }
-    if (kt + 1 < nk) store_tiles(cur ^ 1);
     __syncthreads();
   }
 
+  // KW = 2: wave group 1 hands its partial (Re C, Im C) to group 0 through LDS (the stage buffers
+  // are free after the last barrier of the K loop), and group 0 adds them to its own.
+  const float2* red = reinterpret_cast<const float2*>(lds);
+  const int slot = (wave & 3) * 64 + lane;
+  if (KW > 1) {
+    if (kw == 1) {
+      float2* wr = reinterpret_cast<float2*>(lds);
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float a = p1[i][j][r], b = p2[i][j][r];
+            wr[((i * WC + j) * 16 + r) * 256 + slot] = float2{a - b, p3[i][j][r] - a - b};
+          }
+    }
+    __syncthreads();
+    if (kw == 1) return;
+  }
 #pragma unroll
   for (int i = 0; i < WR; ++i)
 #pragma unroll
@@ -434,7 +549,12 @@ __global__ __launch_bounds__(kThreads) void cgemm3m_kernel(GemmDesc g, int split
         const int col = n0 + wn * (WC * 32) + j * 32 + MfmaF32::out_col(lane);
         if (row >= g.M || col >= g.N) continue;
         const float a = p1[i][j][r], b = p2[i][j][r];
-        const float re = a - b, im = p3[i][j][r] - a - b;
+        float re = a - b, im = p3[i][j][r] - a - b;
+        if (KW > 1) {
+          const float2 o = red[((i * WC + j) * 16 + r) * 256 + slot];
+          re += o.x;
+          im += o.y;
+        }
         if (splits == 1) {
           TO* C = reinterpret_cast<TO*>(g.C);
           const long long o = (long long)bz * g.bC + (long long)row * g.sCm + (long long)col * g.sCn;
@@ -719,21 +839,21 @@ hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
 
 constexpr int k3mCfg[2][2] = {{128, 64}, {64, 64}};
 
-template <int WR, int WC, int BK, typename TO>
+template <int WR, int WC, int BK, int KW, typename TO>
 hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
-  using TT = Tile3<WR, WC, BK>;
+  using TT = Tile3<WR, WC, BK, KW>;
   dim3 grid((g.N + TT::BN - 1) / TT::BN, (g.M + TT::BM - 1) / TT::BM, g.batch * pl.splits);
   const bool akc = (g.sAk == 1) || (g.K == 1);
   const bool bnc = (g.sBn == 1) || (g.N == 1);
   void* part = pl.splits > 1 ? g.ws : nullptr;
   if (akc && bnc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, true, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, true, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else if (akc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, true, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, true, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else if (bnc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, false, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, false, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   MPOEVO_HIP_TRY(hipGetLastError());
   if (pl.splits > 1) {
     const long long total = (long long)g.M * g.N * g.batch;
@@ -748,8 +868,8 @@ hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
 template <typename TO>
 hipError_t launch_3m(const GemmDesc& g, hipStream_t st) {
   const Plan pl = make_plan<MfmaF32>(g, k3mCfg, 2);
-  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, TO>(g, pl, st);
-  return launch_3m_cfg<1, 1, 32, TO>(g, pl, st);
+  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, 1, TO>(g, pl, st);
+  return launch_3m_cfg<1, 1, 32, 2, TO>(g, pl, st);
 }
 
 
