@@ -267,19 +267,23 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
 // A and B are staged in LDS as three k-contiguous planes each (real part, imaginary part, their
 // sum, formed while staging), rows [m][k] and [n][k], in the consumption order of the fp32
 // instruction (kpos below), so that each lane fetches the operands of four instructions with one
-// 16-byte read per plane. A workgroup of KW groups of 4 waves (2 x 2, each wave WR x WC blocks of
+// 16-byte read per plane. A workgroup of KW groups of WGM x 2 waves (each wave WR x WC blocks of
 // 32 x 32 complex outputs) owns a BM x BN complex tile, double-buffered with one barrier per K
-// step of BK; with KW = 2 the two groups take the two halves of every step (two waves per SIMD,
-// so that one wave's staging and barrier wait overlap the other's matrix instructions) and their
-// partial sums meet in LDS at the end.
+// step of BK; with KW > 1 the groups take equal slices of every step (two waves per SIMD, so that
+// one wave's staging and barrier wait overlap the other's matrix instructions) and their partial
+// sums meet in LDS at the end, in group order. Tiles: 128 x 64 (one group), 64 x 64 (two groups),
+// 32 x 64 (four groups of 1 x 2 waves, BK = 64: 256 workgroups for a 256 x 2048 output without
+// splitting K).
 // Rounding: the sums carry one more rounding and Im C a difference of products, so its error
 // bound is about twice that of the expanded form, normwise.
-template <int WR, int WC, int BK_, int KW_>
+template <int WR, int WC, int BK_, int KW_, int WGM_>
 struct Tile3 {
   static constexpr int BK = BK_;               // complex K per stage
   static constexpr int KW = KW_;               // wave groups along K
-  static constexpr int NT = kThreads * KW;     // threads per workgroup
-  static constexpr int BM = 2 * WR * 32;       // complex rows per workgroup
+  static constexpr int WGM = WGM_;             // wave rows per group (2 wave columns)
+  static constexpr int GT = 128 * WGM;         // threads per wave group
+  static constexpr int NT = GT * KW;           // threads per workgroup
+  static constexpr int BM = WGM * WR * 32;     // complex rows per workgroup
   static constexpr int BN = 2 * WC * 32;       // complex columns per workgroup
   static constexpr int V = 4, KT = 2, G = KT * V;
   static constexpr int KG = BK / KW;           // complex K per wave group and stage
@@ -291,26 +295,27 @@ struct Tile3 {
   static_assert(A_ELEMS >= 4 && B_ELEMS >= 4 && A_ELEMS % 4 == 0 && B_ELEMS % 4 == 0,
                 "tile too small for the staging scheme");
   static_assert(BK % G == 0 && KG % G == 0 && ((PITCH * 4 / 16) & 1), "staging layout");
-  static_assert(KW == 1 || 2 * BM * BN <= 2 * STAGE, "LDS too small for the wave-group sum");
-  static_assert(KW == 1 || KW == 2, "one or two wave groups along K");
+  static_assert(2 * (KW - 1) * BM * BN <= 2 * STAGE, "LDS too small for the wave-group sum");
+  static_assert(NT <= 1024, "workgroup size");
   __device__ static int kpos(int k) {
     const int w = k % G;
     return k - w + (w % KT) * V + w / KT;
   }
 };
 
-template <int WR, int WC, int BK, int KW, typename TO, bool AKC, bool BNC>
-__global__ __launch_bounds__(kThreads * KW) void cgemm3m_kernel(GemmDesc g, int splits,
-                                                                int kchunk, void* part) {
-  using TT = Tile3<WR, WC, BK, KW>;
+template <int WR, int WC, int BK, int KW, int WGM, typename TO, bool AKC, bool BNC>
+__global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int splits,
+                                                                 int kchunk, void* part) {
+  using TT = Tile3<WR, WC, BK, KW, WGM>;
   using C2 = float2;
   __shared__ __attribute__((aligned(16))) float lds[2 * TT::STAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int kw = wave >> 2;  // wave group: the K slice [kw KG, (kw+1) KG) of every stage
-  const int wm = (wave >> 1) & 1, wn = wave & 1;
+  const int wq = wave % (2 * WGM);  // wave within its group
+  const int kw = wave / (2 * WGM);  // wave group: the K slice [kw KG, (kw+1) KG) of every stage
+  const int wm = wq >> 1, wn = wq & 1;
   const int bz = blockIdx.z / splits;
   const int sk = blockIdx.z - bz * splits;
   const int kbeg = sk * kchunk;
@@ -519,13 +524,15 @@ __global__ __launch_bounds__(kThreads * KW) void cgemm3m_kernel(GemmDesc g, int 
     __syncthreads();
   }
 
-  // KW = 2: wave group 1 hands its partial (Re C, Im C) to group 0 through LDS (the stage buffers
-  // are free after the last barrier of the K loop), and group 0 adds them to its own.
+  // KW > 1: wave groups 1..KW-1 hand their partial (Re C, Im C) to group 0 through LDS (the stage
+  // buffers are free after the last barrier of the K loop), and group 0 adds them to its own in
+  // group order.
+  constexpr int NR = WR * WC * 16;  // partial values per lane
   const float2* red = reinterpret_cast<const float2*>(lds);
-  const int slot = (wave & 3) * 64 + lane;
+  const int slot = wq * 64 + lane;
   if (KW > 1) {
-    if (kw == 1) {
-      float2* wr = reinterpret_cast<float2*>(lds);
+    if (kw > 0) {
+      float2* wr = reinterpret_cast<float2*>(lds) + (kw - 1) * NR * TT::GT;
 #pragma unroll
       for (int i = 0; i < WR; ++i)
 #pragma unroll
@@ -533,11 +540,11 @@ __global__ __launch_bounds__(kThreads * KW) void cgemm3m_kernel(GemmDesc g, int 
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const float a = p1[i][j][r], b = p2[i][j][r];
-            wr[((i * WC + j) * 16 + r) * 256 + slot] = float2{a - b, p3[i][j][r] - a - b};
+            wr[((i * WC + j) * 16 + r) * TT::GT + slot] = float2{a - b, p3[i][j][r] - a - b};
           }
     }
     __syncthreads();
-    if (kw == 1) return;
+    if (kw > 0) return;
   }
 #pragma unroll
   for (int i = 0; i < WR; ++i)
@@ -550,8 +557,9 @@ __global__ __launch_bounds__(kThreads * KW) void cgemm3m_kernel(GemmDesc g, int 
         if (row >= g.M || col >= g.N) continue;
         const float a = p1[i][j][r], b = p2[i][j][r];
         float re = a - b, im = p3[i][j][r] - a - b;
-        if (KW > 1) {
-          const float2 o = red[((i * WC + j) * 16 + r) * 256 + slot];
+#pragma unroll
+        for (int h = 1; h < KW; ++h) {
+          const float2 o = red[(h - 1) * NR * TT::GT + ((i * WC + j) * 16 + r) * TT::GT + slot];
           re += o.x;
           im += o.y;
         }
@@ -837,23 +845,23 @@ hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   return hipSuccess;
 }
 
-constexpr int k3mCfg[2][2] = {{128, 64}, {64, 64}};
+constexpr int k3mCfg[3][2] = {{128, 64}, {64, 64}, {32, 64}};
 
-template <int WR, int WC, int BK, int KW, typename TO>
+template <int WR, int WC, int BK, int KW, int WGM, typename TO>
 hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
-  using TT = Tile3<WR, WC, BK, KW>;
+  using TT = Tile3<WR, WC, BK, KW, WGM>;
   dim3 grid((g.N + TT::BN - 1) / TT::BN, (g.M + TT::BM - 1) / TT::BM, g.batch * pl.splits);
   const bool akc = (g.sAk == 1) || (g.K == 1);
   const bool bnc = (g.sBn == 1) || (g.N == 1);
   void* part = pl.splits > 1 ? g.ws : nullptr;
   if (akc && bnc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, true, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else if (akc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, true, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else if (bnc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, false, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, TO, false, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   MPOEVO_HIP_TRY(hipGetLastError());
   if (pl.splits > 1) {
     const long long total = (long long)g.M * g.N * g.batch;
@@ -867,9 +875,10 @@ hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
 
 template <typename TO>
 hipError_t launch_3m(const GemmDesc& g, hipStream_t st) {
-  const Plan pl = make_plan<MfmaF32>(g, k3mCfg, 2);
-  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, 1, TO>(g, pl, st);
-  return launch_3m_cfg<1, 1, 32, 2, TO>(g, pl, st);
+  const Plan pl = make_plan<MfmaF32>(g, k3mCfg, 3);
+  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, 1, 2, TO>(g, pl, st);
+  if (pl.cfg == 1) return launch_3m_cfg<1, 1, 32, 2, 2, TO>(g, pl, st);
+  return launch_3m_cfg<1, 1, 64, 4, 1, TO>(g, pl, st);
 }
 
 

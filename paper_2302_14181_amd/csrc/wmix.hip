@@ -35,17 +35,18 @@ __global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __re
   using C2 = cx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C2* Ws = reinterpret_cast<C2*>(smem_raw);
+  const int b = blockIdx.x * kThreads + threadIdx.x;
+  const int ap = blockIdx.y;
+  const int K = wl * d;
+  // the input loads are issued before W is staged, so that the two latencies overlap
+  const C2* src = Tin + (long long)ap * K * Q + min(b, Q - 1);
+  C2 in[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) in[k] = (k < K && b < Q) ? src[(long long)k * Q] : C2{T(0), T(0)};
   const int nW = wl * d * d * wr;
   for (int i = threadIdx.x; i < nW; i += kThreads) Ws[i] = W[i];
   __syncthreads();
-  const int b = blockIdx.x * kThreads + threadIdx.x;
-  const int ap = blockIdx.y;
   if (b >= Q) return;
-  const int K = wl * d;
-  const C2* src = Tin + (long long)ap * K * Q + b;
-  C2 in[KMAX];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) in[k] = (k < K) ? src[(long long)k * Q] : C2{T(0), T(0)};
   C2* dst = out + (long long)ap * d * wr * Q + b;
   // outputs o = s' wr + beta: workgroup z computes the group [z kIlp, z kIlp + kIlp) with
   // independent accumulators (more waves and independent multiply-add chains to cover latency;
@@ -85,23 +86,23 @@ __global__ __launch_bounds__(kThreads) void wmix_right_kernel(const cx_t<T>* __r
   using C2 = cx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C2* Ws = reinterpret_cast<C2*>(smem_raw);
-  const int nW = wl * d * d * wr;
-  for (int i = threadIdx.x; i < nW; i += kThreads) Ws[i] = W[i];
-  __syncthreads();
   const int cp = blockIdx.x * kThreads + threadIdx.x;
   const int b = blockIdx.y;
-  if (cp >= Pr) return;
   const int K = d * wr;
-  C2 in[KMAX];
+  C2 in[KMAX];  // loaded before W is staged (the two latencies overlap)
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     C2 v{T(0), T(0)};
-    if (k < K) {
+    if (k < K && cp < Pr) {
       const int t = k / wr, ga = k % wr;  // k = t * wr + gamma
       v = U[(((long long)b * d + t) * Pr + cp) * wr + ga];
     }
     in[k] = v;
   }
+  const int nW = wl * d * d * wr;
+  for (int i = threadIdx.x; i < nW; i += kThreads) Ws[i] = W[i];
+  __syncthreads();
+  if (cp >= Pr) return;
   // outputs o = beta d + t' (W row o: W[beta][t'][t][gamma], (t, gamma) = k): workgroup z
   // computes the group [z kIlp, z kIlp + kIlp)
   const int nout = wl * d;
