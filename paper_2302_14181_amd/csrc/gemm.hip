@@ -295,7 +295,8 @@ struct Tile3 {
   static_assert(A_ELEMS >= 4 && B_ELEMS >= 4 && A_ELEMS % 4 == 0 && B_ELEMS % 4 == 0,
                 "tile too small for the staging scheme");
   static_assert(BK % G == 0 && KG % G == 0 && ((PITCH * 4 / 16) & 1), "staging layout");
-  static_assert(2 * (KW - 1) * BM * BN <= 2 * STAGE, "LDS too small for the wave-group sum");
+  static_assert(KW == 1 || 2 * KW * BM * BN <= 2 * STAGE, "LDS too small for the wave-group sum");
+  static_assert(16 % KW == 0, "groups share out the accumulator entries");
   static_assert(NT <= 1024, "workgroup size");
   __device__ static int kpos(int k) {
     const int w = k % G;
@@ -524,27 +525,25 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
     __syncthreads();
   }
 
-  // KW > 1: wave groups 1..KW-1 hand their partial (Re C, Im C) to group 0 through LDS (the stage
-  // buffers are free after the last barrier of the K loop), and group 0 adds them to its own in
-  // group order.
+  // KW > 1: every wave group stores its partial (Re C, Im C) to LDS (the stage buffers are free
+  // after the last barrier of the K loop); group h then finishes the accumulator entries
+  // r in [h 16 / KW, (h + 1) 16 / KW) of every block, summing the groups' partials in group order,
+  // so the global stores are spread over all waves.
   constexpr int NR = WR * WC * 16;  // partial values per lane
   const float2* red = reinterpret_cast<const float2*>(lds);
   const int slot = wq * 64 + lane;
   if (KW > 1) {
-    if (kw > 0) {
-      float2* wr = reinterpret_cast<float2*>(lds) + (kw - 1) * NR * TT::GT;
+    float2* wr = reinterpret_cast<float2*>(lds);
 #pragma unroll
-      for (int i = 0; i < WR; ++i)
+    for (int i = 0; i < WR; ++i)
 #pragma unroll
-        for (int j = 0; j < WC; ++j)
+      for (int j = 0; j < WC; ++j)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const float a = p1[i][j][r], b = p2[i][j][r];
-            wr[((i * WC + j) * 16 + r) * TT::GT + slot] = float2{a - b, p3[i][j][r] - a - b};
-          }
-    }
+        for (int r = 0; r < 16; ++r) {
+          const float a = p1[i][j][r], b = p2[i][j][r];
+          wr[(kw * NR + (i * WC + j) * 16 + r) * TT::GT + slot] = float2{a - b, p3[i][j][r] - a - b};
+        }
     __syncthreads();
-    if (kw > 0) return;
   }
 #pragma unroll
   for (int i = 0; i < WR; ++i)
@@ -552,16 +551,25 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
     for (int j = 0; j < WC; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
+        if (KW > 1 && r / (16 / KW) != kw) continue;
         const int row = m0 + wm * (WR * 32) + i * 32 + MfmaF32::out_row(lane, r);
         const int col = n0 + wn * (WC * 32) + j * 32 + MfmaF32::out_col(lane);
         if (row >= g.M || col >= g.N) continue;
-        const float a = p1[i][j][r], b = p2[i][j][r];
-        float re = a - b, im = p3[i][j][r] - a - b;
+        float re, im;
+        if (KW == 1) {
+          const float a = p1[i][j][r], b = p2[i][j][r];
+          re = a - b;
+          im = p3[i][j][r] - a - b;
+        } else {
+          const float2 o = red[((i * WC + j) * 16 + r) * TT::GT + slot];
+          re = o.x;
+          im = o.y;
 #pragma unroll
-        for (int h = 1; h < KW; ++h) {
-          const float2 o = red[(h - 1) * NR * TT::GT + ((i * WC + j) * 16 + r) * TT::GT + slot];
-          re += o.x;
-          im += o.y;
+          for (int h = 1; h < KW; ++h) {
+            const float2 v = red[(h * NR + (i * WC + j) * 16 + r) * TT::GT + slot];
+            re += v.x;
+            im += v.y;
+          }
         }
         if (splits == 1) {
           TO* C = reinterpret_cast<TO*>(g.C);

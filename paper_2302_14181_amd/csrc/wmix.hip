@@ -26,16 +26,20 @@ __device__ inline cx_t<T> cmul_add(cx_t<T> acc, cx_t<T> a, cx_t<T> b) {
 constexpr int kThreads = 256;
 constexpr int kIlp = 8;  // outputs per thread computed together
 
-// grid: (ceil(Q / 256), P, ceil(d wr / kIlp)). KMAX >= wl * d.
-template <typename T, int KMAX>
-__global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __restrict__ Tin,
-                                                             const cx_t<T>* __restrict__ W,
-                                                             cx_t<T>* __restrict__ out, int Q,
-                                                             int wl, int d, int wr) {
+// Output groups per workgroup: NG groups of kThreads threads take consecutive output groups of
+// the same input columns, so that an input's second read comes from the compute unit's cache.
+template <int KMAX>
+constexpr int groups_per_wg() { return KMAX <= 16 ? 2 : 1; }
+
+// grid: (ceil(Q / 256), P, ceil(d wr / (NG kIlp))), NG kThreads threads. KMAX >= wl * d.
+template <typename T, int KMAX, int NG = groups_per_wg<KMAX>()>
+__global__ __launch_bounds__(kThreads * NG) void wmix_left_kernel(
+    const cx_t<T>* __restrict__ Tin, const cx_t<T>* __restrict__ W, cx_t<T>* __restrict__ out,
+    int Q, int wl, int d, int wr) {
   using C2 = cx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C2* Ws = reinterpret_cast<C2*>(smem_raw);
-  const int b = blockIdx.x * kThreads + threadIdx.x;
+  const int b = blockIdx.x * kThreads + threadIdx.x % kThreads;
   const int ap = blockIdx.y;
   const int K = wl * d;
   // the input loads are issued before W is staged, so that the two latencies overlap
@@ -44,7 +48,7 @@ __global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __re
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) in[k] = (k < K && b < Q) ? src[(long long)k * Q] : C2{T(0), T(0)};
   const int nW = wl * d * d * wr;
-  for (int i = threadIdx.x; i < nW; i += kThreads) Ws[i] = W[i];
+  for (int i = threadIdx.x; i < nW; i += kThreads * NG) Ws[i] = W[i];
   __syncthreads();
   if (b >= Q) return;
   C2* dst = out + (long long)ap * d * wr * Q + b;
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __re
   // the inputs are read once per group, mostly from cache)
   const int nout = d * wr;
   {
-    const int o0 = blockIdx.z * kIlp;
+    const int o0 = (blockIdx.z * NG + threadIdx.x / kThreads) * kIlp;
     C2 acc[kIlp];
     int wo[kIlp];  // offset of (s', beta) in W[alpha][s'][s][beta]
 #pragma unroll
@@ -77,16 +81,15 @@ __global__ __launch_bounds__(kThreads) void wmix_left_kernel(const cx_t<T>* __re
   }
 }
 
-// grid: (ceil(Pr / 256), Q, ceil(wl d / kIlp)). U[b][t][c'][gamma] with c' < Pr; out RB[beta][b][t'][c'].
-template <typename T, int KMAX>
-__global__ __launch_bounds__(kThreads) void wmix_right_kernel(const cx_t<T>* __restrict__ U,
-                                                              const cx_t<T>* __restrict__ W,
-                                                              cx_t<T>* __restrict__ out, int Q,
-                                                              int Pr, int wl, int d, int wr) {
+// grid: (ceil(Pr / 256), Q, ceil(wl d / (NG kIlp))), NG kThreads threads. U[b][t][c'][gamma] with c' < Pr; out RB[beta][b][t'][c'].
+template <typename T, int KMAX, int NG = groups_per_wg<KMAX>()>
+__global__ __launch_bounds__(kThreads * NG) void wmix_right_kernel(
+    const cx_t<T>* __restrict__ U, const cx_t<T>* __restrict__ W, cx_t<T>* __restrict__ out,
+    int Q, int Pr, int wl, int d, int wr) {
   using C2 = cx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C2* Ws = reinterpret_cast<C2*>(smem_raw);
-  const int cp = blockIdx.x * kThreads + threadIdx.x;
+  const int cp = blockIdx.x * kThreads + threadIdx.x % kThreads;
   const int b = blockIdx.y;
   const int K = d * wr;
   C2 in[KMAX];  // loaded before W is staged (the two latencies overlap)
@@ -100,14 +103,14 @@ __global__ __launch_bounds__(kThreads) void wmix_right_kernel(const cx_t<T>* __r
     in[k] = v;
   }
   const int nW = wl * d * d * wr;
-  for (int i = threadIdx.x; i < nW; i += kThreads) Ws[i] = W[i];
+  for (int i = threadIdx.x; i < nW; i += kThreads * NG) Ws[i] = W[i];
   __syncthreads();
   if (cp >= Pr) return;
   // outputs o = beta d + t' (W row o: W[beta][t'][t][gamma], (t, gamma) = k): workgroup z
   // computes the group [z kIlp, z kIlp + kIlp)
   const int nout = wl * d;
   {
-    const int o0 = blockIdx.z * kIlp;
+    const int o0 = (blockIdx.z * NG + threadIdx.x / kThreads) * kIlp;
     C2 acc[kIlp];
 #pragma unroll
     for (int j = 0; j < kIlp; ++j) acc[j] = C2{T(0), T(0)};
@@ -130,8 +133,9 @@ template <typename T, int KMAX>
 hipError_t launch_left(const void* Tin, const void* W, void* out, int P, int Q, int wl, int d,
                        int wr, hipStream_t st) {
   const size_t sh = sizeof(cx_t<T>) * (size_t)wl * d * d * wr;
-  dim3 grid((Q + kThreads - 1) / kThreads, P, (d * wr + kIlp - 1) / kIlp);
-  hipLaunchKernelGGL((wmix_left_kernel<T, KMAX>), grid, dim3(kThreads), sh, st,
+  constexpr int NG = groups_per_wg<KMAX>();
+  dim3 grid((Q + kThreads - 1) / kThreads, P, (d * wr + NG * kIlp - 1) / (NG * kIlp));
+  hipLaunchKernelGGL((wmix_left_kernel<T, KMAX>), grid, dim3(kThreads * NG), sh, st,
                      (const cx_t<T>*)Tin, (const cx_t<T>*)W, (cx_t<T>*)out, Q, wl, d, wr);
   return hipGetLastError();
 }
@@ -140,8 +144,9 @@ template <typename T, int KMAX>
 hipError_t launch_right(const void* U, const void* W, void* out, int Q, int Pr, int wl, int d,
                         int wr, hipStream_t st) {
   const size_t sh = sizeof(cx_t<T>) * (size_t)wl * d * d * wr;
-  dim3 grid((Pr + kThreads - 1) / kThreads, Q, (wl * d + kIlp - 1) / kIlp);
-  hipLaunchKernelGGL((wmix_right_kernel<T, KMAX>), grid, dim3(kThreads), sh, st,
+  constexpr int NG = groups_per_wg<KMAX>();
+  dim3 grid((Pr + kThreads - 1) / kThreads, Q, (wl * d + NG * kIlp - 1) / (NG * kIlp));
+  hipLaunchKernelGGL((wmix_right_kernel<T, KMAX>), grid, dim3(kThreads * NG), sh, st,
                      (const cx_t<T>*)U, (const cx_t<T>*)W, (cx_t<T>*)out, Q, Pr, wl, d, wr);
   return hipGetLastError();
 }
