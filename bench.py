@@ -33,8 +33,11 @@ D in {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up, 
 advanced together by step_batched, against the same steps taken chain by chain; the oracle checks
 and times the first step of the first four chains.
 
+With --workload env: only the left environment update at D = 256, d = 2, w = 8 (the matrix-core
+roofline case), K calls per precision (default 100) timed with HIP events on the launch stream.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched]
+                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env]
 """
 from __future__ import annotations
 
@@ -201,6 +204,31 @@ def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
     print(json.dumps(line))
 
 
+def run_env(args, torch, mp, h):
+    """The environment-update microbenchmark alone: FP32 (three real products per complex
+    multiply-add on the fp32 matrix cores), plain FP64 and split-BF16x3, K calls each."""
+    reps = max(1, args.steps)
+    res = {}
+    for name in ("fp32", "fp64", "bf16x3"):
+        ms, flop = env_microbench(mp, h, torch, prec_of(mp, name), reps=reps)
+        peak = 78.6 if name == "fp64" else 157.3
+        res[name] = {"us": ms * 1e3, "tflops": flop / ms / 1e9, "frac_of_peak": flop / ms / 1e9 / peak,
+                     "peak_tflops": peak}
+    f32 = res["fp32"]
+    print(json.dumps({
+        "metric": "env_update (left) TFLOP/s at D=256, d=2, w=8, FP32 matrix cores",
+        "value": f32["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": 3,
+        "ms_per_step": f32["us"] / 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "left environment update, E (256, 8, 256), ket/bra (256, 2, 256), "
+                               "W (8, 2, 2, 8), seeded complex normal operands",
+                   "flop_per_call": 8.0 * (2 * 256 ** 3 * 2 * 8 + 256 ** 2 * 2 ** 2 * 8 ** 2)},
+        "roofline": {"bound": "mfma", "achieved": f32["tflops"], "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": f32["frac_of_peak"], "traffic": None},
+        "precisions": res,
+    }), flush=True)
+
+
 def run_batched(args, torch, mp, wl, h):
     """K steps of 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128}, D in
     {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up: step_batched
@@ -292,7 +320,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--workload", choices=["quench", "lr3", "batched"], default="quench")
+    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env"], default="quench")
     ap.add_argument("--progress", action="store_true", help="print a line to stderr every 10 timed steps")
     args = ap.parse_args()
     if args.workload == "batched":
@@ -312,6 +340,10 @@ def main():
 
     torch.cuda.set_device(0)
     h = mp.Handle(0)
+    if args.workload == "env":
+        run_env(args, torch, mp, h)
+        h.close()
+        return
     if args.workload in ("lr3", "batched"):
         (run_lr3 if args.workload == "lr3" else run_batched)(args, torch, mp, wl, h)
         h.close()
