@@ -62,6 +62,9 @@ ENV_CASES = [  # Dbra_l, Dket_l, Dbra_r, Dket_r, d, w_l, w_r
     (130, 130, 130, 130, 2, 6, 6),
     (20, 17, 23, 19, 2, 271, 271),  # the order-3 long-range Ising MPO bond: W contraction as a product
     (9, 11, 13, 10, 2, 13, 40),     # one short (register kernel) and one long MPO leg
+    # FP32 left: E.ket on 64 x 64 tiles over several stages with a ragged last one (K = 237), the
+    # bra product with K = 1000 split in two over 64-deep stages, a partial W output group
+    (500, 237, 180, 300, 2, 4, 5),
 ]
 
 
