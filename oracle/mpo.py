@@ -297,3 +297,25 @@ def hamiltonian_mpo(H) -> np.ndarray:
     W[1:1 + chi, :, :, 1:1 + chi] = np.transpose(H.A, (0, 2, 3, 1))
     W[1:1 + chi, :, :, w - 1] = H.B
     return W
+
+
+# Splitting composites (Sec. 8.3, splitting schemes): two first-order operators at the complex
+# steps t1 tau and t2 tau, t1,2 = (1 +- i)/2, multiply to an operator accurate to second order
+# (t1 + t2 = 1 and t1 t2 = 1/2 reproduce the tau and tau^2 / 2 terms of the exponential).
+SPLIT_T1 = (1 + 1j) / 2
+SPLIT_T2 = (1 - 1j) / 2
+
+
+def compose(Wa: np.ndarray, Wb: np.ndarray) -> np.ndarray:
+    """Site tensor of the operator product O_a O_b of two MPOs (O_b acts first):
+    W[(alpha_a, alpha_b), s', s, (beta_a, beta_b)] = sum_m Wa[alpha_a, s', m, beta_a] Wb[alpha_b, m, s, beta_b];
+    the bond is the Kronecker product of the two (boundary index 0 of both is index 0)."""
+    wa, d, _, wa_r = Wa.shape
+    wb, wb_r = Wb.shape[0], Wb.shape[3]
+    X = np.einsum('apmb,cmsd->acpsbd', Wa, Wb)
+    return X.reshape(wa * wb, d, d, wa_r * wb_r)
+
+
+def split_composite(H, tau: complex, variant: str = "V2") -> np.ndarray:
+    """O1(t1 tau) O1(t2 tau) as one MPO tensor (bond (1 + chi)^2 for V2)."""
+    return compose(build_mpo(H, 1, SPLIT_T1 * tau, variant), build_mpo(H, 1, SPLIT_T2 * tau, variant))

@@ -156,3 +156,54 @@ def test_v2_more_precise_than_v1():
         e1 = _err(H, N, -0.1j, "V1", 6)
         e2 = _err(H, N, -0.1j, "V2", 6)
         assert e2 < e1, (N, e1, e2)
+
+
+# ---- splitting composites (Sec. 8.3, splitting schemes)
+
+def test_compose_is_the_operator_product():
+    """The composed site tensor contracts to the dense product of the two dense operators (brute
+    force on three sites, random tensors, boundary index 0 on both ends)."""
+    rng = np.random.default_rng(11)
+    Wa = wl.complex_normal(rng, (3, 2, 2, 3))
+    Wb = wl.complex_normal(rng, (2, 2, 2, 2))
+    L = 3
+    A = dense.contract_mpo([Wa] * L, dense.boundary(3), dense.boundary(3))
+    B = dense.contract_mpo([Wb] * L, dense.boundary(2), dense.boundary(2))
+    C = dense.contract_mpo([mpo.compose(Wa, Wb)] * L, dense.boundary(6), dense.boundary(6))
+    assert np.allclose(C, A @ B, atol=1e-12 * np.linalg.norm(A @ B))
+
+
+def test_split_step_constants():
+    """t1 + t2 = 1 and t1 t2 = 1/2: the composite's tau and tau^2 terms are those of exp."""
+    assert abs(mpo.SPLIT_T1 + mpo.SPLIT_T2 - 1) < 1e-15
+    assert abs(mpo.SPLIT_T1 * mpo.SPLIT_T2 - 0.5) < 1e-15
+
+
+@pytest.mark.parametrize("chi", [1, 2, 3])
+def test_split_composite_bond_exceeds_second_order_table(chi):
+    """Sec. 8.3: the composite of first-order operators has bond (1 + chi)^2, larger than the
+    printed second-order entry 1 + chi + chi^2 for every chi >= 1."""
+    H = wl.random_blocks(np.random.default_rng(chi), 2, chi)
+    Wc = mpo.split_composite(H, 0.1)
+    assert Wc.shape[0] == Wc.shape[3] == (1 + chi) ** 2
+    assert Wc.shape[0] > _poly(PRINTED_DIMS[2], chi) == mpo.build_mpo(H, 2, 0.1, "V2").shape[0]
+
+
+def _err_split(H, tau, variant, L):
+    Hd = dense.dense_hamiltonian(mpo.hamiltonian_mpo(H), L)
+    U = dense.expm(tau, Hd)
+    Wd = dense.dense_evolution_mpo(mpo.split_composite(H, tau, variant), L)
+    return np.linalg.norm(Wd - U, 2)
+
+
+@pytest.mark.parametrize("variant", ["V1", "V2"])
+def test_split_composite_is_second_order(variant):
+    """||O1(t1 tau) O1(t2 tau) - exp(tau H)|| ~ tau^3, against the exact exponential (TFIM real
+    time and a random non-Hermitian H); the single first-order operator only reaches tau^2."""
+    for H, L, taus in ((wl.tfim(1.0), 6, [-0.1j, -0.05j, -0.025j]),
+                       (wl.random_blocks(np.random.default_rng(7), 2, 2, a_scale=0.4), 5, [0.1, 0.05, 0.025])):
+        errs = [_err_split(H, t, variant, L) for t in taus]
+        slopes = [np.log(errs[i] / errs[i + 1]) / np.log(2) for i in range(2)]
+        assert min(slopes) >= 3 - 0.15, (errs, slopes)
+        e1 = [_err(H, 1, t, variant, L) for t in taus[1:]]
+        assert np.log(e1[0] / e1[1]) / np.log(2) < 2.6
