@@ -33,11 +33,15 @@ D in {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up, 
 advanced together by step_batched, against the same steps taken chain by chain; the oracle checks
 and times the first step of the first four chains.
 
+With --workload split: the quench above advanced by the splitting composite of Sec. 8.3 (the
+first-order MPO at t2 tau, then at t1 tau, t1,2 = (1 +- i)/2: two fits per step at MPO bond 2)
+against the order-2 MPO (one fit at bond 3), K steps each (default 20) from the same state.
+
 With --workload env: only the left environment update at D = 256, d = 2, w = 8 (the matrix-core
 roofline case), K calls per precision (default 100) timed with HIP events on the launch stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env]
+                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env|split]
 """
 from __future__ import annotations
 
@@ -229,6 +233,70 @@ def run_env(args, torch, mp, h):
     }), flush=True)
 
 
+def _overlap(a, b) -> complex:
+    """<a|b> of two open-boundary MPS given as host arrays (transfer-matrix contraction)."""
+    E = np.ones((1, 1), dtype=np.complex128)
+    for A, B in zip(a, b):
+        E = np.einsum('xy,xsu,ysv->uv', E, A.conj(), B)
+    return complex(E[0, 0])
+
+
+def run_split(args, torch, mp, wl, h):
+    """K quench steps (default 20) from the g = 0.5 ground state with the splitting composite
+    O1(t1 tau) O1(t2 tau) (Sec. 8.3) and with the order-2 MPO, each step timed with HIP events."""
+    steps = args.steps if args.steps != 100 else 20
+    prec = prec_of(mp, args.prec)
+    psi0 = load_ground()
+    H = wl.tfim(G_AFTER)
+    tau = -1j * TAU
+    W2, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, tau, mp.V2_EXTENDED)
+    Wb, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 1, mp.SPLIT_T2 * tau, mp.V2_EXTENDED)
+    Wa, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 1, mp.SPLIT_T1 * tau, mp.V2_EXTENDED)
+    d2, da, db = mp.DeviceMPO([W2] * L), mp.DeviceMPO([Wa] * L), mp.DeviceMPO([Wb] * L)
+
+    def advance(dm, split, k, ws):
+        if split:
+            mp.split_step(h, dm, db, da, prec=prec, input_right_canonical=k > 0, workspace=ws)
+        else:
+            mp.step(h, dm, d2, prec=prec, input_right_canonical=k > 0, workspace=ws)
+
+    def run(split):
+        ws = mp.step_workspace(mp.DeviceMPS(psi0, Dmax=D), d2, prec)  # bond 3 covers bond 2
+        warm = mp.DeviceMPS(psi0, Dmax=D)
+        advance(warm, split, 0, ws)
+        torch.cuda.synchronize()
+        dm = mp.DeviceMPS(psi0, Dmax=D)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for k in range(steps):
+            advance(dm, split, k, ws)
+            ev[k + 1].record()
+            if args.progress and k % 10 == 9:
+                print(f"[bench] {'split' if split else 'order 2'} step {k + 1}/{steps}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)], dm
+
+    ms2, dm2 = run(False)
+    mss, dms = run(True)
+    a, b = dms.to_numpy(), dm2.to_numpy()
+    fid = abs(_overlap(a, b)) ** 2 / (abs(_overlap(a, a)) * abs(_overlap(b, b)))
+    s_split, s_o2 = float(np.sum(mss)) / 1e3 / steps, float(np.sum(ms2)) / 1e3 / steps
+    print(json.dumps({
+        "metric": "s per time step, splitting composite O1(t1 tau) O1(t2 tau) vs order-2 MPO",
+        "value": s_split, "unit": "s per time step", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": s_split * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPES[args.prec], "data": "synthetic",
+        "config": {"workload": f"TFIM quench L={L} from the g=0.5 ground state to g={G_AFTER}, tau={TAU}, "
+                               f"D<={D}, 2 sweeps per fit, steps 1..{steps}: splitting composite "
+                               f"(first-order MPO, bond 2, at t2 tau then t1 tau) vs the order-2 MPO (bond 3)",
+                   "L": L, "D": D, "tau": TAU},
+        "order2_s_per_step": s_o2,
+        "split_over_order2": s_split / s_o2,
+        "trajectory_infidelity": 1.0 - fid,
+        "max_bond_split": max(dms.bond), "max_bond_order2": max(dm2.bond),
+    }), flush=True)
+
+
 def run_batched(args, torch, mp, wl, h):
     """K steps of 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128}, D in
     {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up: step_batched
@@ -320,7 +388,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env"], default="quench")
+    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env", "split"], default="quench")
     ap.add_argument("--progress", action="store_true", help="print a line to stderr every 10 timed steps")
     args = ap.parse_args()
     if args.workload == "batched":
@@ -342,6 +410,10 @@ def main():
     h = mp.Handle(0)
     if args.workload == "env":
         run_env(args, torch, mp, h)
+        h.close()
+        return
+    if args.workload == "split":
+        run_split(args, torch, mp, wl, h)
         h.close()
         return
     if args.workload in ("lr3", "batched"):

@@ -342,6 +342,28 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
 
 PROFILE_JACOBI = 2  # step option: time the Jacobi kernel only (least host overhead)
 
+# Splitting composite (Sec. 8.3, splitting schemes): first-order operators at the complex steps
+# t1 tau and t2 tau, t1,2 = (1 +- i)/2, applied one after the other are accurate to second order.
+SPLIT_T1 = (1 + 1j) / 2
+SPLIT_T2 = (1 - 1j) / 2
+
+
+def split_step(h: Handle, mps: DeviceMPS, first: DeviceMPO, second: DeviceMPO, nsweeps: int = 2,
+               prec: int = FP64, cutoff: float = 1e-14, input_right_canonical: bool = False,
+               workspace=None, stream=None) -> tuple:
+    """One step of a splitting composite: the fit of `first` applied to mps, then the fit of
+    `second` applied to the result (two step calls; the first leaves mps right-canonical). For the
+    second-order composite pass the first-order MPOs at SPLIT_T2 * tau and SPLIT_T1 * tau (their
+    product is the same operator to second order in either order). Returns both StepStats; the
+    product of their norms is the norm of the composite applied to mps."""
+    if workspace is None:
+        workspace = step_workspace(mps, first if max(first.w) >= max(second.w) else second, prec)
+    a = step(h, mps, first, nsweeps=nsweeps, prec=prec, cutoff=cutoff,
+             input_right_canonical=input_right_canonical, workspace=workspace, stream=stream)
+    b = step(h, mps, second, nsweeps=nsweeps, prec=prec, cutoff=cutoff, input_right_canonical=True,
+             workspace=workspace, stream=stream)
+    return a, b
+
 
 def _profile_code(profile) -> int:
     if profile is True or profile == 1:

@@ -476,3 +476,37 @@ def test_step_parity_long_range_order3(mp, handle, prec):
     infid = 1 - abs(ofit.overlap(out, ref)) ** 2
     assert infid < (1e-12 if prec == 0 else 1e-9), infid
     assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_split_composite_step(mp, handle, prec):
+    """Splitting composite (Sec. 8.3): the first-order MPO at t2 tau, then at t1 tau, through two
+    step calls on the GPU, against the oracle's two fits with its own first-order MPOs (same
+    order), and against the exact exp(tau H) psi: the unnormalised result (output times the two
+    fitted norms) differs from it by O(dt^3), where one first-order step alone is O(dt^2)."""
+    L, D = 8, 16
+    _say("split composite L=8 D=16", "fp64" if prec == 0 else "fp32")
+    H = wl.tfim(1.0)
+    rng = np.random.default_rng(5)
+    psi = _normalise(wl.random_mps(rng, L, 2, 4))
+    v0 = dense.mps_to_dense(psi)
+    Hd = dense.dense_hamiltonian(ompo.hamiltonian_mpo(H), L)
+    errs = []
+    for dt in (0.1, 0.05):
+        tau = -1j * dt
+        Wb, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 1, mp.SPLIT_T2 * tau, mp.V2_EXTENDED)
+        Wa, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 1, mp.SPLIT_T1 * tau, mp.V2_EXTENDED)
+        assert Wa.shape[0] == Wb.shape[0] == 2
+        dm = mp.DeviceMPS(psi, Dmax=D)
+        s1, s2 = mp.split_step(handle, dm, mp.DeviceMPO([Wb] * L), mp.DeviceMPO([Wa] * L), prec=prec)
+        out = dm.to_numpy()
+        mid, r1 = ofit.fit_step(psi, ompo.build_mpo(H, 1, ompo.SPLIT_T2 * tau, "V2"), Dmax=D)
+        ref, r2 = ofit.fit_step(mid, ompo.build_mpo(H, 1, ompo.SPLIT_T1 * tau, "V2"), Dmax=D)
+        infid = 1 - abs(ofit.overlap(out, ref)) ** 2
+        assert infid < (1e-12 if prec == 0 else 1e-9), (dt, infid)
+        tol = 1e-10 if prec == 0 else 1e-6
+        assert abs(s1.norm - r1["norm"]) < tol * r1["norm"] and abs(s2.norm - r2["norm"]) < tol * r2["norm"]
+        exact = dense.expm_hermitian(tau, Hd) @ v0
+        errs.append(np.linalg.norm(dense.mps_to_dense(out) * (s1.norm * s2.norm) - exact))
+    slope = np.log(errs[0] / errs[1]) / np.log(2)
+    assert slope > 3 - 0.2, (errs, slope)
