@@ -319,3 +319,14 @@ def compose(Wa: np.ndarray, Wb: np.ndarray) -> np.ndarray:
 def split_composite(H, tau: complex, variant: str = "V2") -> np.ndarray:
     """O1(t1 tau) O1(t2 tau) as one MPO tensor (bond (1 + chi)^2 for V2)."""
     return compose(build_mpo(H, 1, SPLIT_T1 * tau, variant), build_mpo(H, 1, SPLIT_T2 * tau, variant))
+
+
+# Finite temperature on a finite chain by purification: each site carries a physical and an
+# ancilla leg, combined as s d + a (ancilla fastest); exp(-beta H / 2) acting on the physical legs
+# of the product of maximally entangled pairs gives a state whose expectation values are thermal
+# averages at inverse temperature beta (the finite-chain counterpart of the density matrix
+# exp(-beta H) built in Sec. 8.4 for the thermodynamic limit).
+def purify(W: np.ndarray) -> np.ndarray:
+    """Site tensor of O (x) I: W'[alpha, (s', a'), (s, a), beta] = W[alpha, s', s, beta] delta(a', a)."""
+    w, d, _, w2 = W.shape
+    return np.einsum('apqb,xy->apxqyb', W, np.eye(d)).reshape(w, d * d, d * d, w2)

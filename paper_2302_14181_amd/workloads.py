@@ -119,6 +119,14 @@ def all_up(L: int, d: int = 2) -> list[np.ndarray]:
     return product_state(L, e)
 
 
+def infinite_temperature(L: int, d: int = 2) -> list[np.ndarray]:
+    """Purified chain at beta = 0: on every site the normalised maximally entangled pair of a
+    physical and an ancilla leg, sum_s |s>|s> / sqrt(d), local index s d + a (bond 1)."""
+    local = np.zeros(d * d, dtype=np.complex128)
+    local[[s * d + s for s in range(d)]] = 1 / np.sqrt(d)
+    return [local.reshape(1, d * d, 1).copy() for _ in range(L)]
+
+
 def bond_dims(L: int, d: int, D: int) -> list[int]:
     """Largest useful bond dimensions of an open chain capped at D: min(D, d^i, d^(L-i))."""
     out = []
