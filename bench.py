@@ -37,11 +37,16 @@ With --workload split: the quench above advanced by the splitting composite of S
 first-order MPO at t2 tau, then at t1 tau, t1,2 = (1 +- i)/2: two fits per step at MPO bond 2)
 against the order-2 MPO (one fit at bond 3), K steps each (default 20) from the same state.
 
+With --workload thermal: finite temperature by purification on the L = 64 TFIM at g = 1 (physical
+and ancilla leg per site, d = 4): the order-2 MPO at tau = -0.05 on the physical legs, K steps
+(default 20) from beta = 0 (maximally entangled pairs) to beta = 2 K 0.05, D <= 128; FP32 and
+FP64 paths, energy per site at the end from the device expectation.
+
 With --workload env: only the left environment update at D = 256, d = 2, w = 8 (the matrix-core
 roofline case), K calls per precision (default 100) timed with HIP events on the launch stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env|split]
+                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env|split|thermal]
 """
 from __future__ import annotations
 
@@ -297,6 +302,53 @@ def run_split(args, torch, mp, wl, h):
     }), flush=True)
 
 
+def run_thermal(args, torch, mp, wl, h):
+    """Imaginary-time steps of the purified L = 64 TFIM (g = 1) from beta = 0, FP32 and FP64."""
+    steps = args.steps if args.steps != 100 else 20
+    delta, g = 0.05, 1.0
+    H = wl.tfim(g)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -delta, mp.V2_EXTENDED)
+    dw = mp.DeviceMPO([mp.purify_mpo(W)] * L)
+    Hm = np.zeros((3, 2, 2, 3), dtype=np.complex128)
+    Hm[0, :, :, 0] = Hm[2, :, :, 2] = np.eye(2)
+    Hm[0, :, :, 1], Hm[1, :, :, 2], Hm[0, :, :, 2] = H.C[0], H.B[0], H.Dloc
+    dH = mp.DeviceMPO([mp.purify_mpo(Hm)] * L)
+    psi0 = wl.infinite_temperature(L)
+
+    def run(prec):
+        ws = mp.step_workspace(mp.DeviceMPS(psi0, Dmax=D), dw, prec)
+        warm = mp.DeviceMPS(psi0, Dmax=D)
+        mp.step(h, warm, dw, prec=prec, workspace=ws)
+        torch.cuda.synchronize()
+        dm = mp.DeviceMPS(psi0, Dmax=D)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for k in range(steps):
+            mp.step(h, dm, dw, prec=prec, input_right_canonical=k > 0, workspace=ws)
+            ev[k + 1].record()
+            if args.progress and k % 10 == 9:
+                print(f"[bench] thermal prec {prec} step {k + 1}/{steps}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+        return float(np.sum(ms)) / 1e3 / steps, mp.expectation(h, dm, dH, 0, 2).real / L, max(dm.bond)
+
+    s32, e32, b32 = run(mp.FP32)
+    s64, e64, b64 = run(mp.FP64)
+    print(json.dumps({
+        "metric": "s per imaginary-time step, purified TFIM (finite temperature)",
+        "value": s32, "unit": "s per time step", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": s32 * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPES["fp32"], "data": "synthetic",
+        "config": {"workload": f"TFIM L={L}, g={g}, purified (d=4), order-{ORDER} extended MPO at tau=-{delta} "
+                               f"on the physical legs, D<={D}, beta 0 -> {2 * delta * steps:g}",
+                   "L": L, "D": D, "order": ORDER, "delta": delta},
+        "beta_end": 2 * delta * steps,
+        "energy_per_site_fp32": e32, "energy_per_site_fp64": e64,
+        "fp64_s_per_step": s64, "fp32_speedup": s64 / s32,
+        "max_bond_fp32": b32, "max_bond_fp64": b64,
+    }), flush=True)
+
+
 def run_batched(args, torch, mp, wl, h):
     """K steps of 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128}, D in
     {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up: step_batched
@@ -388,7 +440,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env", "split"], default="quench")
+    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env", "split", "thermal"], default="quench")
     ap.add_argument("--progress", action="store_true", help="print a line to stderr every 10 timed steps")
     args = ap.parse_args()
     if args.workload == "batched":
@@ -412,8 +464,8 @@ def main():
         run_env(args, torch, mp, h)
         h.close()
         return
-    if args.workload == "split":
-        run_split(args, torch, mp, wl, h)
+    if args.workload in ("split", "thermal"):
+        (run_split if args.workload == "split" else run_thermal)(args, torch, mp, wl, h)
         h.close()
         return
     if args.workload in ("lr3", "batched"):

@@ -348,6 +348,18 @@ SPLIT_T1 = (1 + 1j) / 2
 SPLIT_T2 = (1 - 1j) / 2
 
 
+def purify_mpo(W: np.ndarray) -> np.ndarray:
+    """MPO site tensor of O acting on the physical leg of a purified chain (finite temperature:
+    the state exp(-beta H / 2) applied to the beta = 0 product of maximally entangled pairs gives
+    thermal averages; cf. the exp(-beta H) construction of Sec. 8.4). Local index s d + a, the
+    ancilla a fastest: W'[alpha, s' d + a, s d + a, beta] = W[alpha, s', s, beta]."""
+    w, d, _, w2 = W.shape
+    out = np.zeros((w, d * d, d * d, w2), dtype=np.complex128)
+    for a in range(d):
+        out[:, a::d, a::d, :] = W
+    return out
+
+
 def split_step(h: Handle, mps: DeviceMPS, first: DeviceMPO, second: DeviceMPO, nsweeps: int = 2,
                prec: int = FP64, cutoff: float = 1e-14, input_right_canonical: bool = False,
                workspace=None, stream=None) -> tuple:

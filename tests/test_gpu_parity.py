@@ -510,3 +510,44 @@ def test_split_composite_step(mp, handle, prec):
         errs.append(np.linalg.norm(dense.mps_to_dense(out) * (s1.norm * s2.norm) - exact))
     slope = np.log(errs[0] / errs[1]) / np.log(2)
     assert slope > 3 - 0.2, (errs, slope)
+
+
+def _tfim_h_mpo(H):
+    """Hamiltonian MPO over levels (1, 2, 3) of a chi = 1 chain, written out (product-side input)."""
+    Hm = np.zeros((3, 2, 2, 3), dtype=np.complex128)
+    Hm[0, :, :, 0] = Hm[2, :, :, 2] = np.eye(2)
+    Hm[0, :, :, 1], Hm[1, :, :, 2], Hm[0, :, :, 2] = H.C[0], H.B[0], H.Dloc
+    return Hm
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_thermal_purification(mp, handle, prec):
+    """Finite temperature by purification (d = 4 sites: physical and ancilla legs): the order-2
+    MPO at tau = -delta on the physical legs, 10 steps from beta = 0 to beta = 1, each against the
+    oracle's fit from the same input; the device energy (FP64 expectation of H on the physical
+    legs) against the oracle's trajectory and the exact thermal energy of the dense Hamiltonian."""
+    L, D, delta, K = 8, 32, 0.05, 10
+    _say("thermal purification L=8 d=4 D=32", "fp64" if prec == 0 else "fp32")
+    H = wl.tfim(1.0)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -delta, mp.V2_EXTENDED)
+    Wo = ompo.purify(ompo.build_mpo(H, 2, -delta, "V2"))
+    dm = mp.DeviceMPS(wl.infinite_temperature(L), Dmax=D)
+    dw = mp.DeviceMPO([mp.purify_mpo(W)] * L)
+    traj = wl.infinite_temperature(L)
+    for k in range(K):
+        same, _ = ofit.fit_step(dm.to_numpy(), Wo, Dmax=D)
+        mp.step(handle, dm, dw, prec=prec, input_right_canonical=k > 0)
+        infid = 1 - abs(ofit.overlap(dm.to_numpy(), same)) ** 2
+        assert infid < (1e-12 if prec == 0 else 1e-9), (k, infid)
+        traj, _ = ofit.fit_step(traj, Wo, Dmax=D)
+    Hp = mp.purify_mpo(_tfim_h_mpo(H))
+    e_gpu = mp.expectation(handle, dm, mp.DeviceMPO([Hp] * L), 0, Hp.shape[0] - 1).real
+    Ho = ompo.purify(ompo.hamiltonian_mpo(H))
+    w = Ho.shape[0]
+    e_or = (ofit.mpo_expectation(traj, [Ho] * L, dense.boundary(w, 0), dense.boundary(w, w - 1))
+            / ofit.overlap(traj, traj)).real
+    lam = np.linalg.eigvalsh(dense.dense_hamiltonian(ompo.hamiltonian_mpo(H), L))
+    p = np.exp(-1.0 * (lam - lam.min()))
+    e_ex = float((lam * p).sum() / p.sum())
+    assert abs(e_gpu - e_or) < (1e-10 if prec == 0 else 1e-5) * abs(e_ex), (e_gpu, e_or)
+    assert abs(e_gpu - e_ex) < 3e-3, (e_gpu, e_ex)
