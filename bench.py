@@ -42,11 +42,16 @@ and ancilla leg per site, d = 4): the order-2 MPO at tau = -0.05 on the physical
 (default 20) from beta = 0 (maximally entangled pairs) to beta = 2 K 0.05, D <= 128; FP32 and
 FP64 paths, energy per site at the end from the device expectation.
 
+With --workload cylinder: the efficiency set-up of Sec. 8.2 on a finite W = 4 spiral cylinder
+(TFIM, h = 2, 8 x 4 = 32 sites, D <= 64): a ground state by imaginary-time steps, a spin flip on
+the middle site, evolution to T = 1 with orders 1-3 at dt = 0.2, 0.1, 0.05, and the fidelity
+density against an order-3 run at dt = 0.0125 (standing in for the TDVP reference).
+
 With --workload env: only the left environment update at D = 256, d = 2, w = 8 (the matrix-core
 roofline case), K calls per precision (default 100) timed with HIP events on the launch stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env|split|thermal]
+                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env|split|thermal|cylinder]
 """
 from __future__ import annotations
 
@@ -349,6 +354,68 @@ def run_thermal(args, torch, mp, wl, h):
     }), flush=True)
 
 
+def run_cylinder(args, torch, mp, wl, h):
+    """Fidelity density after T = 1 against the time step for orders 1-3 on a W = 4 cylinder."""
+    Ly, Lx, hx, Dc, T = 4, 8, 2.0, 64, 1.0
+    N = Ly * Lx
+    prec = prec_of(mp, args.prec)
+    H = wl.tfim_cylinder(Ly, hx)
+
+    def evolve(psi, order, tau, steps, canonical=False):
+        W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, order, tau, mp.V2_EXTENDED)
+        dw = mp.DeviceMPO([W] * N)
+        dm = mp.DeviceMPS(psi, Dmax=Dc)
+        ws = mp.step_workspace(dm, dw, prec)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for k in range(steps):
+            mp.step(h, dm, dw, prec=prec, input_right_canonical=canonical or k > 0, workspace=ws)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        return dm.to_numpy(), float(sum(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))) / 1e3
+
+    # ground state: imaginary-time steps of the order-2 MPO from all-up (beta / 2 = 6)
+    gs, t_gs = evolve(wl.all_up(N), 2, -0.1, 60)
+    if args.progress:
+        print(f"[bench] cylinder ground state {t_gs:.1f} s", file=sys.stderr, flush=True)
+    flipped = [m.copy() for m in gs]
+    mid = N // 2
+    flipped[mid] = np.einsum('st,atb->asb', wl.SX, flipped[mid])
+
+    def unit(ms):
+        n = np.sqrt(abs(_overlap(ms, ms)))
+        out = [m.copy() for m in ms]
+        out[0] = out[0] / n
+        return out
+
+    ref, t_ref = evolve(flipped, 3, -1j * 0.0125, 80)
+    ref = unit(ref)
+    rows = []
+    for order in (1, 2, 3):
+        for dt in (0.2, 0.1, 0.05):
+            steps = int(round(T / dt))
+            out, t = evolve(flipped, order, -1j * dt, steps)
+            f = float(np.log(abs(_overlap(ref, unit(out))))) / N
+            rows.append({"order": order, "dt": dt, "steps": steps, "fidelity_density": f,
+                         "gpu_s": t, "s_per_step": t / steps})
+            if args.progress:
+                print(f"[bench] cylinder order {order} dt {dt}: f = {f:.3e}, {t:.2f} s", file=sys.stderr, flush=True)
+    o2 = [r for r in rows if r["order"] == 2 and r["dt"] == 0.1][0]
+    print(json.dumps({
+        "metric": "fidelity density after T=1 vs time step, orders 1-3, W=4 spiral cylinder",
+        "value": o2["s_per_step"], "unit": "s per time step (order 2, dt = 0.1)", "n_gpus": 1,
+        "steps": o2["steps"], "warmup": 0, "ms_per_step": o2["s_per_step"] * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"TFIM on a W={Ly} spiral cylinder, {Lx}x{Ly}={N} sites, h={hx}, D<={Dc}, "
+                               "ground state by 60 imaginary-time steps (order 2, tau=-0.1), spin flip "
+                               "(X) on the middle site, evolution to T=1; reference: order 3, dt=0.0125",
+                   "Ly": Ly, "Lx": Lx, "h": hx, "D": Dc, "T": T},
+        "reference_gpu_s": t_ref, "ground_state_gpu_s": t_gs,
+        "runs": rows,
+    }), flush=True)
+
+
 def run_batched(args, torch, mp, wl, h):
     """K steps of 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128}, D in
     {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up: step_batched
@@ -440,7 +507,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env", "split", "thermal"], default="quench")
+    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env", "split", "thermal", "cylinder"], default="quench")
     ap.add_argument("--progress", action="store_true", help="print a line to stderr every 10 timed steps")
     args = ap.parse_args()
     if args.workload == "batched":
@@ -464,8 +531,8 @@ def main():
         run_env(args, torch, mp, h)
         h.close()
         return
-    if args.workload in ("split", "thermal"):
-        (run_split if args.workload == "split" else run_thermal)(args, torch, mp, wl, h)
+    if args.workload in ("split", "thermal", "cylinder"):
+        {"split": run_split, "thermal": run_thermal, "cylinder": run_cylinder}[args.workload](args, torch, mp, wl, h)
         h.close()
         return
     if args.workload in ("lr3", "batched"):

@@ -51,6 +51,23 @@ def tfim(g: float, J: float = 1.0) -> JordanBlocks:
     )
 
 
+def tfim_cylinder(Ly: int, h: float, J: float = 1.0) -> JordanBlocks:
+    """Transverse-field Ising model on a cylinder of circumference Ly with spiral boundary
+    conditions, as a chain along the spiral (Sec. 2.3, the cylinder example):
+    H = -J sum (Z_i Z_{i+1} + Z_i Z_{i+Ly}) + h sum X_i.
+    The middle level is a shift register of Ly steps (chi = Ly): a Z placed r sites back sits in
+    register r - 1 and closes at distance 1 or Ly."""
+    A = np.zeros((Ly, Ly, 2, 2), dtype=np.complex128)
+    for j in range(Ly - 1):
+        A[j, j + 1] = ID2
+    C = np.zeros((Ly, 2, 2), dtype=np.complex128)
+    C[0] = -J * SZ
+    B = np.zeros((Ly, 2, 2), dtype=np.complex128)
+    B[0] += SZ
+    B[Ly - 1] += SZ  # (Ly = 1: both couplings close at distance 1)
+    return JordanBlocks(A=A, B=B, C=C, Dloc=h * SX)
+
+
 def lr_ising(coeffs, lambdas, g: float) -> JordanBlocks:
     """Ising chain with couplings J(r) = sum_k c_k lambda_k^(r-1) plus transverse field.
 

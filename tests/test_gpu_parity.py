@@ -551,3 +551,22 @@ def test_thermal_purification(mp, handle, prec):
     e_ex = float((lam * p).sum() / p.sum())
     assert abs(e_gpu - e_or) < (1e-10 if prec == 0 else 1e-5) * abs(e_ex), (e_gpu, e_or)
     assert abs(e_gpu - e_ex) < 3e-3, (e_gpu, e_ex)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_cylinder_step_parity(mp, handle, N, prec):
+    """TFIM on a W = 4 spiral cylinder (12 sites, h = 2): one step of the order-N MPO (bond 5,
+    21, 93: register and product paths of the W contraction) against the oracle's fit with its own
+    MPO from the same random state."""
+    L, D, dt = 12, 16, 0.1
+    _say("cylinder W=4 step", N, "fp64" if prec == 0 else "fp32")
+    H = wl.tfim_cylinder(4, 2.0)
+    psi = _normalise(wl.random_mps(np.random.default_rng(40 + N), L, 2, 6))
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, N, -1j * dt, mp.V2_EXTENDED)
+    assert W.shape[0] == {1: 5, 2: 21, 3: 93}[N]
+    ref, rst = ofit.fit_step(psi, ompo.build_mpo(H, N, -1j * dt, "V2"), Dmax=D)
+    out, st = _gpu_step(mp, handle, psi, W, D, prec)
+    infid = 1 - abs(ofit.overlap(out, ref)) ** 2
+    assert infid < (1e-12 if prec == 0 else 1e-9), infid
+    assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]

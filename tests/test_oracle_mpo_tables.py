@@ -15,7 +15,8 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import mpo
+from oracle import dense, mpo
+from paper_2302_14181_amd import workloads as wl
 from paper_2302_14181_amd.workloads import JordanBlocks
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -165,3 +166,22 @@ def test_fixture_parser_rejects_wrong_formula():
     assert np.max(np.abs(good - _expr("1/2 t^2 BD", mats, TAU))) > 1e-3
     assert np.max(np.abs(good - _expr("1/3 t^2 DB", mats, TAU))) > 1e-3
     assert np.max(np.abs(_expr("{ABB}", mats, TAU) - (mats["A"] @ mats["B"] @ mats["B"] + mats["B"] @ mats["A"] @ mats["B"] + mats["B"] @ mats["B"] @ mats["A"]))) < 1e-12
+
+
+@pytest.mark.parametrize("Ly,N", [(2, 6), (3, 7), (4, 9)])
+def test_cylinder_hamiltonian_is_the_spiral_lattice(Ly, N):
+    """The spiral-cylinder TFIM generator (chi = Ly shift register) against the dense Hamiltonian
+    built term by term: -Z_i Z_{i+1} - Z_i Z_{i+Ly} + h X_i on the chain along the spiral."""
+    h = 0.7
+    H = wl.tfim_cylinder(Ly, h)
+    Hd = dense.dense_hamiltonian(mpo.hamiltonian_mpo(H), N)
+    ref = np.zeros((2 ** N, 2 ** N), dtype=np.complex128)
+    for i in range(N):
+        ref += h * dense.local_op(wl.SX, i, N)
+        for r in (1, Ly):
+            if i + r < N:
+                ref -= dense.local_op(wl.SZ, i, N) @ dense.local_op(wl.SZ, i + r, N)
+    assert np.abs(Hd - ref).max() < 1e-14
+    # bond dimensions of the printed table at chi = Ly (W = 4: 5, 21, 93)
+    for n, coeffs in ((1, [1, 1]), (2, [1, 1, 1]), (3, [1, 3, 1, 1])):
+        assert mpo.build_mpo(H, n, -0.1j, "V2").shape[0] == sum(c * Ly ** p for p, c in enumerate(coeffs))
