@@ -253,7 +253,7 @@ def _gpu_step(mp, handle, psi, W, D, prec, nsweeps=2, canonical=False):
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("case", [(6, 4, 2, 8), (9, 6, 3, 16), (12, 8, 2, 24)], ids=str)
+@pytest.mark.parametrize("case", [(6, 4, 2, 8), (9, 6, 3, 16), (12, 8, 2, 24), (8, 4, 1, 16)], ids=str)
 def test_step_parity_random_state(mp, handle, case, prec):
     L, D0, N, D = case
     _say("step random", case, "fp64" if prec == 0 else "fp32")
@@ -570,3 +570,39 @@ def test_cylinder_step_parity(mp, handle, N, prec):
     infid = 1 - abs(ofit.overlap(out, ref)) ** 2
     assert infid < (1e-12 if prec == 0 else 1e-9), infid
     assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_xxz_step_conserves_charge(mp, handle, prec):
+    """Spin-1/2 XXZ chain (Delta = 0.5), order-2 MPO (bond 13), from the Neel state (5 up spins
+    of 10): two steps against the oracle's fits, and the U(1) charge conserved by the device
+    path: <sum Sz> = 0 and its variance <(sum Sz)^2> - <sum Sz>^2 = 0 after each step."""
+    L, D, dt = 10, 16, 0.1
+    _say("xxz step L=10 D=16", "fp64" if prec == 0 else "fp32")
+    H = wl.xxz(0.5)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -1j * dt, mp.V2_EXTENDED)
+    assert W.shape[0] == 13
+    Wo = ompo.build_mpo(H, 2, -1j * dt, "V2")
+    up, dn = np.array([1, 0], dtype=np.complex128), np.array([0, 1], dtype=np.complex128)
+    psi = [(up if i % 2 == 0 else dn).reshape(1, 2, 1) for i in range(L)]
+    sz = 0.5 * wl.SZ
+    I2 = np.eye(2, dtype=np.complex128)
+    S1 = np.zeros((2, 2, 2, 2), dtype=np.complex128)  # sum Sz: [[I, Sz], [0, I]]
+    S1[0, :, :, 0] = S1[1, :, :, 1] = I2
+    S1[0, :, :, 1] = sz
+    S2 = np.zeros((3, 2, 2, 3), dtype=np.complex128)  # (sum Sz)^2: [[I, 2Sz, Sz^2], [0, I, Sz], [0, 0, I]]
+    S2[0, :, :, 0] = S2[1, :, :, 1] = S2[2, :, :, 2] = I2
+    S2[0, :, :, 1], S2[0, :, :, 2], S2[1, :, :, 2] = 2 * sz, sz @ sz, sz
+    dm = mp.DeviceMPS(psi, Dmax=D)
+    dw = mp.DeviceMPO([W] * L)
+    d1, d2 = mp.DeviceMPO([S1] * L), mp.DeviceMPO([S2] * L)
+    ref = psi
+    for k in range(2):
+        ref, _ = ofit.fit_step(ref, Wo, Dmax=D)
+        mp.step(handle, dm, dw, prec=prec, input_right_canonical=k > 0)
+        infid = 1 - abs(ofit.overlap(dm.to_numpy(), ref)) ** 2
+        assert infid < (1e-12 if prec == 0 else 1e-9), (k, infid)
+        m1 = mp.expectation(handle, dm, d1, 0, 1).real
+        m2 = mp.expectation(handle, dm, d2, 0, 2).real
+        tol = 1e-10 if prec == 0 else 1e-6
+        assert abs(m1) < tol and abs(m2 - m1 * m1) < tol, (k, m1, m2)
