@@ -52,6 +52,7 @@ roofline case), K calls per precision (default 100) timed with HIP events on the
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
                        [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env|split|thermal|cylinder]
+                       [--order 1|2|3|4] [--tau T] [--progress]
 """
 from __future__ import annotations
 
@@ -499,6 +500,7 @@ def run_batched(args, torch, mp, wl, h):
 
 
 def main():
+    global ORDER, TAU
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
@@ -509,7 +511,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env", "split", "thermal", "cylinder"], default="quench")
     ap.add_argument("--progress", action="store_true", help="print a line to stderr every 10 timed steps")
+    ap.add_argument("--order", type=int, default=ORDER, choices=[1, 2, 3, 4],
+                    help="MPO order of the TFIM workloads (quench, split reference, thermal)")
+    ap.add_argument("--tau", type=float, default=TAU, help="time step of the quench and split workloads")
     args = ap.parse_args()
+    ORDER, TAU = args.order, args.tau
     if args.workload == "batched":
         # more hardware queues and worker streams let more chains' truncations overlap (read by
         # the HIP runtime at initialisation and by the library at each batched step)
