@@ -329,8 +329,9 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
   const float sgnA = g.conjA ? -1.f : 1.f;
   const float sgnB = g.conjB ? -1.f : 1.f;
 
-  // An operand whose rows are not contiguous in k (A not k-contiguous, B not n-major) is
-  // staged in quads: a thread loads k = kb, kb + 2, kb + 4, kb + 6 of one row (each load
+  // An operand whose LDS rows ([m][k] for A, [n][k] for B) are not contiguous in memory along k
+  // (A with unit stride in m, B with unit stride in n) is staged in quads: a thread loads
+  // k = kb, kb + 2, kb + 4, kb + 6 of one row (each load
   // coalesced across the lanes, which take consecutive rows) and writes them, adjacent in the
   // instruction order, with one 16-byte LDS store per plane (conflict-free: the row pitch is an
   // odd number of 16-byte units). A k-contiguous operand is staged element by element, the lanes
