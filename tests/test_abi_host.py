@@ -108,3 +108,16 @@ def test_device_calls_reject_null_handle():
     assert lib.env_update(None, 0, 0, None, None, None, None, None, None, None, 0, None) == mpoevo.EINVAL
     assert lib.truncate(None, None, 1, 1, 1, 0.0, 0, None, None, None, None, None, None, None, 0, None) == mpoevo.EINVAL
     assert lib.step(None, None, None, None, None, None, 0, None) == mpoevo.EINVAL
+
+
+def test_host_helpers_match_oracle():
+    """The binding's purified MPO and splitting constants (host side, no GPU) against the
+    oracle's own: the physical-leg operator of a purified chain and t1,2 = (1 +- i)/2."""
+    rng = np.random.default_rng(21)
+    for d in (2, 3):
+        W = wl.complex_normal(rng, (3, d, d, 4))
+        assert np.array_equal(mpoevo.purify_mpo(W), omp.purify(W))
+    assert mpoevo.SPLIT_T1 == omp.SPLIT_T1 and mpoevo.SPLIT_T2 == omp.SPLIT_T2
+    Wc, _ = mpoevo.mpo_build(*[getattr(wl.tfim_cylinder(4, 2.0), k) for k in ("A", "B", "C", "Dloc")], 2,
+                             -0.1j, mpoevo.V2_EXTENDED)
+    assert np.allclose(Wc, omp.build_mpo(wl.tfim_cylinder(4, 2.0), 2, -0.1j, "V2"), atol=1e-13)
