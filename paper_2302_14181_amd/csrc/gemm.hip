@@ -627,59 +627,143 @@ __global__ __launch_bounds__(kThreads) void cgemm_bf16x3_kernel(GemmDesc g, int 
   const float sgnA = g.conjA ? -1.f : 1.f;
   const float sgnB = g.conjB ? -1.f : 1.f;
 
+  // Staging: a thread takes single elements, or, for an operand whose LDS rows are not
+  // contiguous in memory along k (A with unit stride in m, B with unit stride in n) and that gives
+  // every thread a multiple of 4 elements, quads of consecutive k of one row (each load coalesced
+  // across the lanes, which take consecutive rows), stored with 16-byte LDS writes (the four
+  // complex values are 8 adjacent bf16 of a row). Load addresses are set up once and advanced by
+  // one stage per load_tiles call; a row past the edge addresses the last row (never read).
+  constexpr bool QA = !AKC && A_ELEMS % 4 == 0;
+  constexpr bool QB = BNC && B_ELEMS % 4 == 0;
   C2 ra[A_ELEMS];
   C2 rb[B_ELEMS];
-  auto load_tiles = [&](int k0) {
+  const C2* pa[A_ELEMS];
+  const C2* pb[B_ELEMS];
+  int ka[A_ELEMS], kbv[B_ELEMS];
+  bool va[A_ELEMS], vb[B_ELEMS];
+  auto a_pos = [&](int i, int& m, int& k) {  // row and k of A element i of this thread
+    if (QA) {
+      const int q = tid + (i / 4) * kThreads;
+      m = q % BM; k = 4 * (q / BM) + i % 4;
+    } else {
+      const int e = tid + i * kThreads;
+      if (AKC) { m = e / BK; k = e % BK; } else { k = e / BM; m = e % BM; }
+    }
+  };
+  auto b_pos = [&](int i, int& n, int& k) {
+    if (QB) {
+      const int q = tid + (i / 4) * kThreads;
+      n = q % BN; k = 4 * (q / BN) + i % 4;
+    } else {
+      const int e = tid + i * kThreads;
+      if (BNC) { k = e / BN; n = e % BN; } else { n = e / BK; k = e % BK; }
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < A_ELEMS; ++i) {
+    int m, k;
+    a_pos(i, m, k);
+    va[i] = m0 + m < g.M;
+    ka[i] = k;
+    pa[i] = A + (long long)min(m0 + m, g.M - 1) * g.sAm + (long long)(kbeg + k) * g.sAk;
+  }
+#pragma unroll
+  for (int i = 0; i < B_ELEMS; ++i) {
+    int n, k;
+    b_pos(i, n, k);
+    vb[i] = n0 + n < g.N;
+    kbv[i] = k;
+    pb[i] = B + (long long)(kbeg + k) * g.sBk + (long long)min(n0 + n, g.N - 1) * g.sBn;
+  }
+  const long long stepA = (long long)BK * g.sAk, stepB = (long long)BK * g.sBk;
+  int krem = kend - kbeg;
+  auto load_tiles = [&]() {
 #pragma unroll
     for (int i = 0; i < A_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int m, k;
-      if (AKC) { m = e / BK; k = e % BK; } else { k = e / BM; m = e % BM; }
-      const int gm = m0 + m, gk = k0 + k;
       C2 v{0.f, 0.f};
-      if (gm < g.M && gk < kend) v = A[gm * g.sAm + gk * g.sAk];
+      if (va[i] && ka[i] < krem) v = *pa[i];
       ra[i] = v;
+      pa[i] += stepA;
     }
 #pragma unroll
     for (int i = 0; i < B_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int k, n;
-      if (BNC) { k = e / BN; n = e % BN; } else { n = e / BK; k = e % BK; }
-      const int gk = k0 + k, gn = n0 + n;
       C2 v{0.f, 0.f};
-      if (gk < kend && gn < g.N) v = B[gk * g.sBk + gn * g.sBn];
+      if (vb[i] && kbv[i] < krem) v = *pb[i];
       rb[i] = v;
+      pb[i] += stepB;
     }
+    krem -= BK;
   };
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
   auto store_tiles = [&](int buf) {
     __bf16* Ah = lds + buf * STAGE;
     __bf16* Al = Ah + A_PLANE;
     __bf16* Bh = Al + A_PLANE;
     __bf16* Bl = Bh + B_PLANE;
+    if (QA) {
 #pragma unroll
-    for (int i = 0; i < A_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int m, k;
-      if (AKC) { m = e / BK; k = e % BK; } else { k = e / BM; m = e % BM; }
-      __bf16 h0, l0, h1, l1;
-      split_bf16(ra[i].x, h0, l0);
-      split_bf16(sgnA * ra[i].y, h1, l1);
-      *reinterpret_cast<unsigned*>(Ah + m * PITCH + 2 * k) = pack_bf16(h0, h1);
-      *reinterpret_cast<unsigned*>(Al + m * PITCH + 2 * k) = pack_bf16(l0, l1);
+      for (int i = 0; i < A_ELEMS; i += 4) {
+        int m, k;
+        a_pos(i, m, k);
+        u32x4 hv, lv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          __bf16 h0, l0, h1, l1;
+          split_bf16(ra[i + j].x, h0, l0);
+          split_bf16(sgnA * ra[i + j].y, h1, l1);
+          hv[j] = pack_bf16(h0, h1);
+          lv[j] = pack_bf16(l0, l1);
+        }
+        *reinterpret_cast<u32x4*>(Ah + m * PITCH + 2 * k) = hv;
+        *reinterpret_cast<u32x4*>(Al + m * PITCH + 2 * k) = lv;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < A_ELEMS; ++i) {
+        int m, k;
+        a_pos(i, m, k);
+        __bf16 h0, l0, h1, l1;
+        split_bf16(ra[i].x, h0, l0);
+        split_bf16(sgnA * ra[i].y, h1, l1);
+        *reinterpret_cast<unsigned*>(Ah + m * PITCH + 2 * k) = pack_bf16(h0, h1);
+        *reinterpret_cast<unsigned*>(Al + m * PITCH + 2 * k) = pack_bf16(l0, l1);
+      }
     }
+    // real column 2n: (re, -im) at k' = 2k, 2k+1; real column 2n+1: (im, re)
+    if (QB) {
 #pragma unroll
-    for (int i = 0; i < B_ELEMS; ++i) {
-      const int e = tid + i * kThreads;
-      int k, n;
-      if (BNC) { k = e / BN; n = e % BN; } else { n = e / BK; k = e % BK; }
-      __bf16 hr, lr, hi_, li;
-      split_bf16(rb[i].x, hr, lr);
-      split_bf16(sgnB * rb[i].y, hi_, li);
-      // real column 2n: (re, -im) at k' = 2k, 2k+1; real column 2n+1: (im, re)
-      *reinterpret_cast<unsigned*>(Bh + (2 * n) * PITCH + 2 * k) = pack_bf16(hr, -hi_);
-      *reinterpret_cast<unsigned*>(Bl + (2 * n) * PITCH + 2 * k) = pack_bf16(lr, -li);
-      *reinterpret_cast<unsigned*>(Bh + (2 * n + 1) * PITCH + 2 * k) = pack_bf16(hi_, hr);
-      *reinterpret_cast<unsigned*>(Bl + (2 * n + 1) * PITCH + 2 * k) = pack_bf16(li, lr);
+      for (int i = 0; i < B_ELEMS; i += 4) {
+        int n, k;
+        b_pos(i, n, k);
+        u32x4 h0v, l0v, h1v, l1v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          __bf16 hr, lr, hi_, li;
+          split_bf16(rb[i + j].x, hr, lr);
+          split_bf16(sgnB * rb[i + j].y, hi_, li);
+          h0v[j] = pack_bf16(hr, -hi_);
+          l0v[j] = pack_bf16(lr, -li);
+          h1v[j] = pack_bf16(hi_, hr);
+          l1v[j] = pack_bf16(li, lr);
+        }
+        *reinterpret_cast<u32x4*>(Bh + (2 * n) * PITCH + 2 * k) = h0v;
+        *reinterpret_cast<u32x4*>(Bl + (2 * n) * PITCH + 2 * k) = l0v;
+        *reinterpret_cast<u32x4*>(Bh + (2 * n + 1) * PITCH + 2 * k) = h1v;
+        *reinterpret_cast<u32x4*>(Bl + (2 * n + 1) * PITCH + 2 * k) = l1v;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < B_ELEMS; ++i) {
+        int n, k;
+        b_pos(i, n, k);
+        __bf16 hr, lr, hi_, li;
+        split_bf16(rb[i].x, hr, lr);
+        split_bf16(sgnB * rb[i].y, hi_, li);
+        *reinterpret_cast<unsigned*>(Bh + (2 * n) * PITCH + 2 * k) = pack_bf16(hr, -hi_);
+        *reinterpret_cast<unsigned*>(Bl + (2 * n) * PITCH + 2 * k) = pack_bf16(lr, -li);
+        *reinterpret_cast<unsigned*>(Bh + (2 * n + 1) * PITCH + 2 * k) = pack_bf16(hi_, hr);
+        *reinterpret_cast<unsigned*>(Bl + (2 * n + 1) * PITCH + 2 * k) = pack_bf16(li, lr);
+      }
     }
   };
 
@@ -691,14 +775,20 @@ __global__ __launch_bounds__(kThreads) void cgemm_bf16x3_kernel(GemmDesc g, int 
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
+  // software pipeline as in the three-product kernel: the tile of stage kt + 1 (in registers
+  // since stage kt - 1) is stored at the top of stage kt, then stage kt + 2 is loaded
   const int nk = (kend - kbeg + BK - 1) / BK;
-  load_tiles(kbeg);
+  load_tiles();
   store_tiles(0);
+  if (nk > 1) load_tiles();
   __syncthreads();
   const int lrow = lane & 31, lk = 8 * (lane >> 5);
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
+    if (kt + 1 < nk) {
+      store_tiles(cur ^ 1);
+      if (kt + 2 < nk) load_tiles();
+    }
     const __bf16* Ah = lds + cur * STAGE;
     const __bf16* Al = Ah + A_PLANE;
     const __bf16* Bh = Al + A_PLANE;
@@ -727,7 +817,6 @@ __global__ __launch_bounds__(kThreads) void cgemm_bf16x3_kernel(GemmDesc g, int 
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
     }
-    if (kt + 1 < nk) store_tiles(cur ^ 1);
     __syncthreads();
   }
 
