@@ -52,9 +52,9 @@ __global__ __launch_bounds__(kThreads * NG) void wmix_left_kernel(
   __syncthreads();
   if (b >= Q) return;
   C2* dst = out + (long long)ap * d * wr * Q + b;
-  // outputs o = s' wr + beta: workgroup z computes the group [z kIlp, z kIlp + kIlp) with
-  // independent accumulators (more waves and independent multiply-add chains to cover latency;
-  // the inputs are read once per group, mostly from cache)
+  // outputs o = s' wr + beta: thread group h = z NG + threadIdx.x / kThreads computes the output
+  // group [h kIlp, h kIlp + kIlp) with independent accumulators (more waves and independent
+  // multiply-add chains to cover latency; the inputs are read once per group, mostly from cache)
   const int nout = d * wr;
   {
     const int o0 = (blockIdx.z * NG + threadIdx.x / kThreads) * kIlp;
@@ -106,8 +106,8 @@ __global__ __launch_bounds__(kThreads * NG) void wmix_right_kernel(
   for (int i = threadIdx.x; i < nW; i += kThreads * NG) Ws[i] = W[i];
   __syncthreads();
   if (cp >= Pr) return;
-  // outputs o = beta d + t' (W row o: W[beta][t'][t][gamma], (t, gamma) = k): workgroup z
-  // computes the group [z kIlp, z kIlp + kIlp)
+  // outputs o = beta d + t' (W row o: W[beta][t'][t][gamma], (t, gamma) = k): thread group
+  // h = z NG + threadIdx.x / kThreads computes the output group [h kIlp, h kIlp + kIlp)
   const int nout = wl * d;
   {
     const int o0 = (blockIdx.z * NG + threadIdx.x / kThreads) * kIlp;
