@@ -63,6 +63,7 @@ ENV_CASES = [  # Dbra_l, Dket_l, Dbra_r, Dket_r, d, w_l, w_r
     (130, 130, 130, 130, 2, 6, 6),      # several tiles, ragged tail
     (256, 256, 256, 256, 2, 8, 8),      # the D = 256 environment shape
     (20, 17, 23, 19, 2, 271, 271),      # long MPO bonds: the W contraction as a product
+    (500, 237, 180, 300, 2, 4, 5),      # several stages with a ragged last one, split K
 ]
 
 
