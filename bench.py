@@ -247,8 +247,9 @@ def run_env(args, torch, mp, h):
 def _overlap(a, b) -> complex:
     """<a|b> of two open-boundary MPS given as host arrays (transfer-matrix contraction)."""
     E = np.ones((1, 1), dtype=np.complex128)
-    for A, B in zip(a, b):
-        E = np.einsum('xy,xsu,ysv->uv', E, A.conj(), B)
+    for A, B in zip(a, b):  # pairwise contractions: O(D^3 d) per site
+        E = np.tensordot(E, A.conj(), axes=([0], [0]))      # [y, s, u]
+        E = np.tensordot(E, B, axes=([0, 1], [0, 1]))       # [u, v]
     return complex(E[0, 0])
 
 
@@ -630,10 +631,17 @@ def main():
     fp64 = None
     if not args.no_fp64 and prec == mp.FP32:
         n64 = max(1, min(args.fp64_steps, args.steps))
-        ms64, _, _, _ = quench(mp.FP64, n64, 0, profile=True)
+        ms64, _, _, dm64 = quench(mp.FP64, n64, 0, profile=True)
         fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
                 "fp32_s_per_step": float(np.sum(ms[:n64])) / 1e3 / n64}
         fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / fp64["fp32_s_per_step"]
+        # the FP32 and FP64 trajectories after the same n64 steps from psi0
+        _, _, _, dm32n = quench(mp.FP32, n64, 0)
+        a, b = dm32n.to_numpy(), dm64.to_numpy()
+        fp64["trajectory_infidelity_fp32_vs_fp64"] = 1.0 - abs(_overlap(a, b)) ** 2 / (
+            abs(_overlap(a, a)) * abs(_overlap(b, b)))
+        fp64["Z32_after_steps_fp32"] = mp.expectation(h, dm32n, dZ).real
+        fp64["Z32_after_steps_fp64"] = mp.expectation(h, dm64, dZ).real
 
     # one step at saturated bond dimension (seeded random MPS, D = 128 on every bulk bond), after
     # two steps that leave the truncations' preconditioners in the workspace
