@@ -14,7 +14,11 @@ Modules
 
 Parity status: every function is pinned by a test that does not re-type its own
 formula (printed tables, the bond-dimension table, error scaling, closed forms,
-brute force), except the order-(N+1) coefficients of the extended MPO for N >= 3,
-which no printed table fixes ("parity partly unpinned": only the bond-dimension
-table, the error-order test and the on-site closed form constrain them).
+brute force). The order-(N+1) terms that the extension step (Alg. 3) adds are pinned
+at every order N = 1..4 against a brute-force sum over products of Hamiltonian terms
+(Sec. 5: every term of order N+1 whose N+1 actions overlap at most N times); the
+compressions that follow it on the extended operator (Alg. 2, Alg. 4) are pinned by
+the printed tables for N <= 2 and, for N >= 3, only through the bond-dimension
+table, the error order, Alg. 2's exactness on the unextended operator and the
+coefficient-wise exactness of the orders 0..N of the finished operator.
 """

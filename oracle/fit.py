@@ -23,34 +23,26 @@ from __future__ import annotations
 import numpy as np
 
 
+# numpy's default einsum planner allows no intermediate larger than the largest operand, which
+# for these networks leaves a single many-operand step that never reaches BLAS; the greedy
+# planner with room for pairwise intermediates evaluates the same expression through BLAS.
+_EINSUM = ("greedy", 2 ** 40)
+
+
 def env_left(Lenv, bra, W, ket):
-    """L'[b', beta, b] = sum conj(bra[a', s', b']) L[a', alpha, a] W[alpha, s', s, beta] ket[a, s, b],
-    evaluated as three pairwise contractions (sum over a, then over alpha and s, then a' and s')."""
-    T = np.tensordot(Lenv, ket, axes=([2], [0]))             # [a', alpha, s, b]
-    T = np.tensordot(T, W, axes=([1, 2], [0, 2]))             # [a', b, s', beta]
-    T = np.tensordot(bra.conj(), T, axes=([0, 1], [0, 2]))    # [b', b, beta]
-    return np.ascontiguousarray(T.transpose(0, 2, 1))
+    """L'[b', beta, b] = sum conj(bra[a', s', b']) L[a', alpha, a] W[alpha, s', s, beta] ket[a, s, b]."""
+    return np.einsum('xay,xpu,apsb,ysv->ubv', Lenv, bra.conj(), W, ket, optimize=_EINSUM)
 
 
 def env_right(Renv, bra, W, ket):
-    """R'[a', alpha, a] = sum conj(bra[a', s', b']) W[alpha, s', s, beta] ket[a, s, b] R[b', beta, b],
-    evaluated as three pairwise contractions (sum over b, then over s and beta, then s' and b')."""
-    T = np.tensordot(ket, Renv, axes=([2], [2]))              # [a, s, b', beta]
-    T = np.tensordot(T, W, axes=([1, 3], [2, 3]))             # [a, b', alpha, s']
-    T = np.tensordot(bra.conj(), T, axes=([1, 2], [3, 1]))    # [a', a, alpha]
-    return np.ascontiguousarray(T.transpose(0, 2, 1))
+    """R'[a', alpha, a] = sum conj(bra[a', s', b']) W[alpha, s', s, beta] ket[a, s, b] R[b', beta, b]."""
+    return np.einsum('xpu,apsb,ysv,ubv->xay', bra.conj(), W, ket, Renv, optimize=_EINSUM)
 
 
 def theta_two_site(Lenv, M1, W1, M2, W2, Renv):
     """Projected two-site tensor Theta[a', s', t', c'] =
-    sum L[a', alpha, a] M1[a, s, b] W1[alpha, s', s, beta] M2[b, t, c] W2[beta, t', t, gamma] R[c', gamma, c],
-    evaluated as the left half (L M1 W1), the right half (M2 W2 R) and their contraction over b, beta."""
-    left = np.tensordot(Lenv, M1, axes=([2], [0]))            # [a', alpha, s, b]
-    left = np.tensordot(left, W1, axes=([1, 2], [0, 2]))      # [a', b, s', beta]
-    right = np.tensordot(M2, Renv, axes=([2], [2]))           # [b, t, c', gamma]
-    right = np.tensordot(right, W2, axes=([1, 3], [2, 3]))    # [b, c', beta, t']
-    th = np.tensordot(left, right, axes=([1, 3], [0, 2]))     # [a', s', c', t']
-    return np.ascontiguousarray(th.transpose(0, 1, 3, 2))
+    sum L[a', alpha, a] M1[a, s, b] W1[alpha, s', s, beta] M2[b, t, c] W2[beta, t', t, gamma] R[c', gamma, c]."""
+    return np.einsum('xay,ysb,apsg,btc,gqtz,uzc->xpqu', Lenv, M1, W1, M2, W2, Renv, optimize=_EINSUM)
 
 
 def svd_truncate(mat, Dmax: int, cutoff: float):
