@@ -215,6 +215,18 @@ typedef struct {
                          that finds every pair below the rounding tolerance. */
 } mpoevo_step_opts;
 
+#define MPOEVO_MAX_KERNEL_STATS 16
+typedef struct {
+  char name[224];   /* the kernel's name as the HIP runtime reports it, demangled (as profilers
+                       list it); truncated to 223 characters */
+  int kind;         /* 0: Jacobi kernel, 1: complex matrix product, 2: short-leg W contraction */
+  int split_k;      /* 1: each timed interval also holds the sum of the split-K partial tiles */
+  int launches;
+  double ms;        /* summed durations (HIP events around each launch, on the step's stream) */
+  double work;      /* algorithmic GFLOP (kinds 0 and 1; 8 flop per complex multiply-add for the
+                       products) or GB read and written (kind 2) */
+} mpoevo_kernel_stat;
+
 typedef struct {
   double norm;              /* |<phi_hat|W psi>| = ||S|| at the last bond visit */
   double discarded_max;     /* largest discarded weight of any bond visit */
@@ -233,6 +245,11 @@ typedef struct {
   int n_wmix;
   int svd_sweeps_total;     /* Jacobi sweeps summed over the bond truncations of the step */
   int svd_sweeps_hist[32];  /* number of bond truncations that took s sweeps (index min(s, 31)) */
+  /* filled when opts->profile == 1: the timed launches grouped by kernel instance, longest summed
+     duration first (at most MPOEVO_MAX_KERNEL_STATS; the rest are counted only in the class
+     totals above) */
+  int n_kernel_stats;
+  mpoevo_kernel_stat kernel_stats[MPOEVO_MAX_KERNEL_STATS];
 } mpoevo_step_stats;
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
@@ -279,6 +296,36 @@ int step_batched(mpoevo_handle h, int n, mpoevo_mps* mps, const mpoevo_mpo* mpo,
  */
 int expectation(mpoevo_handle h, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
                 void* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Tile choice of the complex matrix products (a property of the handle; host calls, no GPU work).
+ * MPOEVO_TUNE_OFF (the default): every product takes the fixed planner rule -- the largest tile of
+ *   the precision's table that gives at least one workgroup per compute unit, else the smallest
+ *   tile with K split across workgroups and the partial tiles summed in a fixed order.
+ * MPOEVO_TUNE_ON: the first product of each shape (precision, M, N, K, batch, output precision,
+ *   operand layout) issued through this handle outside stream capture times every candidate plan
+ *   (each tile of the table, unsplit and with the rule's split count; three runs after one warm-up,
+ *   HIP events on the call's stream, which is synchronised: such a call blocks) and keeps the
+ *   fastest for every later product of that shape. Shapes met during stream capture take the rule.
+ * MPOEVO_TUNE_FROZEN: tuned shapes keep their plan; new shapes take the rule and are not tuned.
+ * Every plan sums in a fixed order, so results are reproducible for a fixed table, but the rounding
+ * of a product depends on the plan it takes. step_batched's chains use the handle's table and
+ * never tune. clear != 0 empties the table before setting the mode.
+ * Errors: EINVAL (NULL handle, unknown mode).
+ */
+enum { MPOEVO_TUNE_OFF = 0, MPOEVO_TUNE_ON = 1, MPOEVO_TUNE_FROZEN = 2 };
+int mpoevo_set_tuning(mpoevo_handle h, int mode, int clear);
+
+/*
+ * The plan a product of M x N x K complex multiply-adds (times batch) in precision prec takes on
+ * this handle, for operands contiguous along k (first factor) and n (second factor):
+ *   plan[0] tile rows, plan[1] tile columns, plan[2] number of K splits, plan[3] 1 if the plan
+ *   comes from the handle's tuned table, else 0 (the fixed rule).
+ *   entries (nullable): number of shapes in the tuned table.
+ * Errors: EINVAL (NULL handle or plan, unknown precision), ESHAPE (non-positive sizes).
+ */
+int mpoevo_product_plan(mpoevo_handle h, int prec, int M, int N, int K, int batch, int* plan,
+                        int* entries);
 
 /* Workspace sizes in bytes for the device calls (dims as documented for each call). */
 enum { MPOEVO_CALL_ENV_UPDATE = 0, MPOEVO_CALL_LOCAL_APPLY = 1, MPOEVO_CALL_TRUNCATE = 2,

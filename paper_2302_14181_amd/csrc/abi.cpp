@@ -67,6 +67,28 @@ int mpo_build(int d, int chi, const double* A, const double* B, const double* C,
   return rc;
 }
 
+int mpoevo_set_tuning(mpoevo_handle h, int mode, int clear) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_set_tuning: h is NULL");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (mode != MPOEVO_TUNE_OFF && mode != MPOEVO_TUNE_ON && mode != MPOEVO_TUNE_FROZEN)
+    return fail(ctx, MPOEVO_EINVAL, "mpoevo_set_tuning: unknown mode");
+  if (clear) mpoevo::gemm_tuner_clear(ctx->tuner);
+  mpoevo::gemm_tuner_mode(ctx->tuner, mode);
+  return MPOEVO_OK;
+}
+
+int mpoevo_product_plan(mpoevo_handle h, int prec, int M, int N, int K, int batch, int* plan,
+                        int* entries) {
+  if (!h || !plan) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_product_plan: NULL argument");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (!valid_prec(prec)) return fail(ctx, MPOEVO_EINVAL, "mpoevo_product_plan: unknown precision");
+  if (M < 1 || N < 1 || K < 1 || batch < 1)
+    return fail(ctx, MPOEVO_ESHAPE, "mpoevo_product_plan: non-positive size");
+  mpoevo::gemm_plan_query(ctx->tuner, prec, M, N, K, batch, plan);
+  if (entries) *entries = (int)mpoevo::gemm_tuner_entries(ctx->tuner);
+  return MPOEVO_OK;
+}
+
 int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes) {
   if (!dims || !bytes) return fail(nullptr, MPOEVO_EINVAL, "mpoevo_workspace_size: NULL argument");
   if (!valid_prec(prec)) return fail(nullptr, MPOEVO_EINVAL, "unknown precision");

@@ -36,6 +36,15 @@ constexpr size_t kGemmScratchBytes = size_t(32) << 20;
 // arithmetic. out_fp64: store C as complex128 even when T = float. Returns a hipError_t.
 hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st);
 
+// Host function of the kernel this thread launched last among the timed kernel classes (the
+// products' main kernel, the W contractions, the Jacobi kernel) and whether a split-K sum
+// followed it: a profiled step names each timed launch by it.
+struct LaunchRecord {
+  const void* kernel = nullptr;
+  bool split = false;
+};
+LaunchRecord& last_launch();
+
 #define MPOEVO_HIP_TRY(expr)                                  \
   do {                                                        \
     hipError_t e_ = (expr);                                   \

@@ -18,9 +18,12 @@
 // is decided on the device, discarded directions are exact zeros), so no visit waits for the
 // host; the host reads the kept ranks once at the end of the step and compacts the result.
 
+#include <cxxabi.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -33,6 +36,11 @@
 #include "wmix.h"
 
 namespace mpoevo {
+
+LaunchRecord& last_launch() {
+  static thread_local LaunchRecord r;
+  return r;
+}
 
 struct DeviceState {
   int* status = nullptr;  // sticky status words (device ints)
@@ -56,7 +64,7 @@ struct Prof {
   DeviceState* ds = nullptr;
   hipStream_t st = nullptr;
   bool all = true;  // time the products and W contractions too (else the Jacobi kernel only)
-  struct Rec { int kind; size_t e0; double work; };
+  struct Rec { int kind; size_t e0; double work; LaunchRecord launch; };
   std::vector<Rec> recs;
   size_t next = 0;
   hipError_t event(size_t i, hipEvent_t* out) {
@@ -81,7 +89,7 @@ struct Prof {
   }
   hipError_t end(int kind, size_t first, double work) {
     MPOEVO_HIP_TRY(hipEventRecord(ds->events[first + 1], st));
-    recs.push_back({kind, first, work});
+    recs.push_back({kind, first, work, last_launch()});
     return hipSuccess;
   }
 };
@@ -355,7 +363,7 @@ size_t wcontract_xws(long long ket_rows, long long bra_cols, int d, int wl, int 
 // ------------------------------------------------------------------------- step workspace map
 struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
-  size_t off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
+  size_t off_token_front, off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
       off_cplt, off_blocks, off_basis, basiscap, off_token, off_gemm, off_xws, total;
 };
@@ -372,6 +380,9 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.thetacap = (size_t)d * Dmax * d * Dmax;
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o += a256(bytes); return at; };
+  // the step token is kept at both ends of the region it guards (an allocation that reused the
+  // front of a freed workspace overwrites the first, one that reused its tail the second)
+  s.off_token_front = take(sizeof(unsigned long long));
   s.off_phi = take(sizeof(double2) * s.sitecap * L);
   s.off_ketc = take(f32 ? sizeof(float2) * s.sitecap * L : 0);
   s.off_brac = take(f32 ? sizeof(float2) * s.sitecap * L : 0);
@@ -428,6 +439,16 @@ int device_init(Context& ctx) {
   e = hipMemset(ds->status, 0, 4 * sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) { (void)hipFree(ds->status); delete ds; return hip_fail(ctx, e, "status init"); }
+  if (!ctx.tuner) {
+    ctx.tuner = gemm_tuner_new();
+    if (!ctx.tuner) {
+      (void)hipFree(ds->status);
+      delete ds;
+      ctx.err = "out of host memory (tuner)";
+      return MPOEVO_ENOMEM;
+    }
+    ctx.owns_tuner = true;
+  }
   ctx.dev = ds;
   return MPOEVO_OK;
 }
@@ -435,6 +456,9 @@ int device_init(Context& ctx) {
 void device_fini(Context& ctx) {
   for (auto& c : ctx.chains) device_fini(*c);
   ctx.chains.clear();
+  if (ctx.owns_tuner) gemm_tuner_free(ctx.tuner);
+  ctx.tuner = nullptr;
+  ctx.owns_tuner = false;
   if (!ctx.dev) return;
   (void)hipSetDevice(ctx.device);
   for (void* s : ctx.streams) (void)hipStreamDestroy(static_cast<hipStream_t>(s));
@@ -519,6 +543,7 @@ int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const voi
                    const void* W, const void* ket, void* E_out, const int* dims, void* ws,
                    size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
   const int Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4], wl = dims[5],
             wr = dims[6];
   const Arith ar = arith_of(prec);
@@ -548,6 +573,7 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
                     const void* M1, const void* M2, const void* R, void* Theta, const int* dims,
                     void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
   const int Dbl = dims[0], Dkl = dims[1], Dkm = dims[2], Dkr = dims[3], Dbr = dims[4], d = dims[5],
             wl = dims[6], wm = dims[7], wr = dims[8];
   const Arith ar = arith_of(prec);
@@ -571,6 +597,7 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
                  int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
                  double* norm_dev, double* sigma_dev, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
   // up to 512: Jacobi on R^dag of the column-pivoted QR (a cold start needs few sweeps that way)
   const SvdPlan p = svd_qr_ok(m, n, direction) ? svd_plan_qr(m, n, direction) : svd_plan(m, n, direction);
   hipError_t e = svd_truncate(p, static_cast<const double2*>(Theta), Dmax, cutoff,
@@ -592,6 +619,7 @@ size_t expectation_ws(int L, int d, int Dmax, int wmax) {
 int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
                     void* out, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
   const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
   int wmax = 0;
   for (int i = 0; i <= L; ++i) wmax = std::max(wmax, mpo->w[i]);
@@ -628,6 +656,7 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
 int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
              mpoevo_step_stats* stats, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
   const int L = mps->L, d = mps->d, Dmax = mps->Dmax, prec = opts->prec;
   const bool fp64 = prec == MPOEVO_FP64;
   const Arith ar = arith_of(prec);
@@ -673,14 +702,16 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   const bool warm_on = opts->svd_cold_start == 0;
   const int sig[5] = {L, d, Dmax, wmax, prec};
   unsigned long long* token_dev = reinterpret_cast<unsigned long long*>(base + lay.off_token);
+  unsigned long long* token_front = reinterpret_cast<unsigned long long*>(base + lay.off_token_front);
   bool reuse = warm_on && ctx.warm_ws == ws && std::equal(sig, sig + 5, ctx.warm_sig) &&
                (int)ctx.warm_dim.size() == L - 1 && (int)ctx.warm_deficient.size() == L - 1;
   if (reuse) {  // the workspace must still hold what this handle's last step left there
-    unsigned long long tok = 0;
-    hipError_t et = hipMemcpyAsync(&tok, token_dev, sizeof(tok), hipMemcpyDeviceToHost, st);
+    unsigned long long tok[2] = {0, 0};
+    hipError_t et = hipMemcpyAsync(&tok[0], token_front, sizeof(tok[0]), hipMemcpyDeviceToHost, st);
+    if (et == hipSuccess) et = hipMemcpyAsync(&tok[1], token_dev, sizeof(tok[1]), hipMemcpyDeviceToHost, st);
     if (et == hipSuccess) et = hipStreamSynchronize(st);
     if (et != hipSuccess) return hip_fail(ctx, et, "step: reading the workspace token");
-    reuse = tok == ctx.warm_token;
+    reuse = tok[0] == ctx.warm_token && tok[1] == ctx.warm_token;
   }
   if (!reuse) {
     ctx.warm_dim.assign(std::max(L - 1, 0), 0);
@@ -724,7 +755,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   int* sweeps_buf = reinterpret_cast<int*>(base + lay.off_sweeps);
   int* cplt_buf = reinterpret_cast<int*>(base + lay.off_cplt);
   int* blocks_buf = reinterpret_cast<int*>(base + lay.off_blocks);
-  struct JacRec { size_t ev; SvdPlan plan; int slot; };
+  struct JacRec { size_t ev; SvdPlan plan; int slot; const void* kernel; };
   std::vector<JacRec> jac_recs;
   double gflop = 0.0;
   auto flop_gemm = [&](double M, double N, double K) { gflop += 8.0 * M * N * K * 1e-9; };
@@ -825,7 +856,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
                               j1, sweeps_buf + visit, qr ? nullptr : wb, wb, ctx.coop_jacobi,
                               cplt_buf + visit, blocks_buf + visit));
-        if (prof) jac_recs.push_back({jf, sp, visit});
+        if (prof) jac_recs.push_back({jf, sp, visit, svd_jacobi_kernel_ptr(sp)});
       }
       P[i + 1] = kcap;
       k_slot_of_bond[i + 1] = visit;
@@ -868,7 +899,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                               dbuf + visit, nbuf + visit, nullptr, svdws, ctx.dev->status, st, j0,
                               j1, sweeps_buf + visit, qr ? nullptr : wb, last ? nullptr : wb,
                               ctx.coop_jacobi, cplt_buf + visit, blocks_buf + visit));
-        if (prof) jac_recs.push_back({jf, sp, visit});
+        if (prof) jac_recs.push_back({jf, sp, visit, svd_jacobi_kernel_ptr(sp)});
       }
       P[i + 1] = kcap;
       k_slot_of_bond[i + 1] = visit;
@@ -940,14 +971,27 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     stats->t_jacobi_ms = stats->jacobi_gflop = stats->t_gemm_ms = stats->gemm_gflop = 0.0;
     stats->t_wmix_ms = stats->wmix_gbyte = 0.0;
     stats->n_jacobi = stats->n_gemm = stats->n_wmix = 0;
+    stats->n_kernel_stats = 0;
     if (prof) {
       const std::vector<int>& sw = swh;
+      struct Agg { int kind; int split; int n; double ms, work; };
+      std::map<std::pair<const void*, int>, Agg> per_kernel;
+      auto add = [&](const void* k, int kind, bool split, double ms, double work) {
+        Agg& a = per_kernel[{k, split ? 1 : 0}];
+        a.kind = kind;
+        a.split = split ? 1 : 0;
+        a.n += 1;
+        a.ms += ms;
+        a.work += work;
+      };
       for (const auto& r : jac_recs) {
         float ms = 0.f;
         STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.ev], ctx.dev->events[r.ev + 1]));
+        const double gf = sw[r.slot] * svd_sweep_flop(svd_jacobi_plan(r.plan), bh[r.slot]) * 1e-9;
         stats->t_jacobi_ms += ms;
-        stats->jacobi_gflop += sw[r.slot] * svd_sweep_flop(svd_jacobi_plan(r.plan), bh[r.slot]) * 1e-9;
+        stats->jacobi_gflop += gf;
         stats->n_jacobi += 1;
+        add(r.kernel, 0, false, ms, gf);
       }
       for (const auto& r : prof->recs) {
         float ms = 0.f;
@@ -956,11 +1000,33 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
           stats->t_gemm_ms += ms;
           stats->gemm_gflop += r.work * 1e-9;
           stats->n_gemm += 1;
+          add(r.launch.kernel, 1, r.launch.split, ms, r.work * 1e-9);
         } else {
           stats->t_wmix_ms += ms;
           stats->wmix_gbyte += r.work * 1e-9;
           stats->n_wmix += 1;
+          add(r.launch.kernel, 2, false, ms, r.work * 1e-9);
         }
+      }
+      std::vector<std::pair<std::pair<const void*, int>, Agg>> order(per_kernel.begin(), per_kernel.end());
+      std::stable_sort(order.begin(), order.end(),
+                       [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
+      for (const auto& kv : order) {
+        if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
+        mpoevo_kernel_stat& o = stats->kernel_stats[stats->n_kernel_stats++];
+        std::memset(&o, 0, sizeof(o));
+        const char* raw = kv.first.first ? hipKernelNameRefByPtr(kv.first.first, st) : nullptr;
+        std::string name = raw ? raw : "unknown kernel";
+        int dst = 0;
+        char* dem = raw ? abi::__cxa_demangle(raw, nullptr, nullptr, &dst) : nullptr;
+        if (dem && dst == 0) name = dem;
+        std::free(dem);
+        std::strncpy(o.name, name.c_str(), sizeof(o.name) - 1);
+        o.kind = kv.second.kind;
+        o.split_k = kv.second.split;
+        o.launches = kv.second.n;
+        o.ms = kv.second.ms;
+        o.work = kv.second.work;
       }
     }
   }
@@ -968,6 +1034,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   if (warm_on) {
     static std::atomic<unsigned long long> next_token{1};
     ctx.warm_token = next_token.fetch_add(1);
+    STEP_TRY(hipMemcpyAsync(token_front, &ctx.warm_token, sizeof(ctx.warm_token), hipMemcpyHostToDevice, st));
     STEP_TRY(hipMemcpyAsync(token_dev, &ctx.warm_token, sizeof(ctx.warm_token), hipMemcpyHostToDevice, st));
     STEP_TRY(hipStreamSynchronize(st));
     ctx.warm_ws = ws;
@@ -1014,6 +1081,8 @@ int step_batched_dev(Context& ctx, int n, mpoevo_mps* mps, const mpoevo_mpo* mpo
     auto c = std::make_unique<Context>();
     c->device = ctx.device;
     c->coop_jacobi = false;
+    c->tuner = ctx.tuner;  // borrowed: the chains use the handle's tuned plans and tune nothing
+    c->owns_tuner = false;
     const int rc = device_init(*c);
     if (rc != MPOEVO_OK) {
       ctx.err = "step_batched: " + c->err;

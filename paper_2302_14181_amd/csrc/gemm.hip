@@ -36,8 +36,13 @@
 // scheduling).
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "dev_common.h"
+#include "internal.h"
 
 namespace mpoevo {
 namespace {
@@ -931,6 +936,14 @@ hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
     hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, BK, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
   else
     hipLaunchKernelGGL((cgemm_kernel<Mf, WR, WC, BK, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  {
+    const void* k = nullptr;
+    if (akc && bnc) k = reinterpret_cast<const void*>(cgemm_kernel<Mf, WR, WC, BK, TO, true, true>);
+    else if (akc) k = reinterpret_cast<const void*>(cgemm_kernel<Mf, WR, WC, BK, TO, true, false>);
+    else if (bnc) k = reinterpret_cast<const void*>(cgemm_kernel<Mf, WR, WC, BK, TO, false, true>);
+    else k = reinterpret_cast<const void*>(cgemm_kernel<Mf, WR, WC, BK, TO, false, false>);
+    last_launch() = LaunchRecord{k, pl.splits > 1};
+  }
   MPOEVO_HIP_TRY(hipGetLastError());
   if (pl.splits > 1) {
     using T = typename Mf::T;
@@ -960,6 +973,14 @@ hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
     hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else
     hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+  {
+    const void* k = nullptr;
+    if (akc && bnc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, true>);
+    else if (akc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, false>);
+    else if (bnc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, true>);
+    else k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, false>);
+    last_launch() = LaunchRecord{k, pl.splits > 1};
+  }
   MPOEVO_HIP_TRY(hipGetLastError());
   if (pl.splits > 1) {
     const long long total = (long long)g.M * g.N * g.batch;
@@ -970,15 +991,6 @@ hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   }
   return hipSuccess;
 }
-
-template <typename TO>
-hipError_t launch_3m(const GemmDesc& g, hipStream_t st) {
-  const Plan pl = make_plan<MfmaF32>(g, k3mCfg, 3);
-  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, 1, 2, TO>(g, pl, st);
-  if (pl.cfg == 1) return launch_3m_cfg<1, 1, 32, 2, 2, TO>(g, pl, st);
-  return launch_3m_cfg<1, 1, 64, 4, 1, TO>(g, pl, st);
-}
-
 
 template <int WR, int WC, int BK, typename TO>
 hipError_t launch_bf16x3_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
@@ -995,6 +1007,14 @@ hipError_t launch_bf16x3_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) 
     hipLaunchKernelGGL((cgemm_bf16x3_kernel<WR, WC, BK, TO, false, true>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
   else
     hipLaunchKernelGGL((cgemm_bf16x3_kernel<WR, WC, BK, TO, false, false>), grid, dim3(kThreads), 0, st, g, pl.splits, pl.kchunk, part);
+  {
+    const void* k = nullptr;
+    if (akc && bnc) k = reinterpret_cast<const void*>(cgemm_bf16x3_kernel<WR, WC, BK, TO, true, true>);
+    else if (akc) k = reinterpret_cast<const void*>(cgemm_bf16x3_kernel<WR, WC, BK, TO, true, false>);
+    else if (bnc) k = reinterpret_cast<const void*>(cgemm_bf16x3_kernel<WR, WC, BK, TO, false, true>);
+    else k = reinterpret_cast<const void*>(cgemm_bf16x3_kernel<WR, WC, BK, TO, false, false>);
+    last_launch() = LaunchRecord{k, pl.splits > 1};
+  }
   MPOEVO_HIP_TRY(hipGetLastError());
   if (pl.splits > 1) {
     const long long total = (long long)g.M * g.N * g.batch;
@@ -1006,9 +1026,108 @@ hipError_t launch_bf16x3_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) 
   return hipSuccess;
 }
 
+// ------------------------------------------------------------------------------ tile tuner
+// The fixed rule above (largest tile with a workgroup per compute unit, else split K) is the
+// default. A handle can instead time the candidate plans of each product shape the first time
+// it meets it (every tile of the precision's table, unsplit and with the rule's split count) and
+// keep the fastest for every later product of that shape.
+enum Kind : int { kKind3m = 0, kKindBf16x3 = 1, kKindF64 = 2 };
+
+struct TuneKey {
+  int kind, out64, akc, bnc, M, N, K, batch;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kind, out64, akc, bnc, M, N, K, batch) <
+           std::tie(o.kind, o.out64, o.akc, o.bnc, o.M, o.N, o.K, o.batch);
+  }
+};
+
+struct Tuner {
+  std::mutex mu;
+  int mode = MPOEVO_TUNE_OFF;
+  std::map<TuneKey, Plan> table;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~Tuner() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+thread_local Tuner* t_tuner = nullptr;
+thread_local bool t_tune_allowed = false;
+
+template <class Mf>
+std::vector<Plan> candidate_plans(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
+  std::vector<Plan> out;
+  for (int c = 0; c < ncfg; ++c) {
+    const long long t = (long long)((g.M + cfgs[c][0] - 1) / cfgs[c][0]) *
+                        ((g.N + cfgs[c][1] - 1) / cfgs[c][1]) * g.batch;
+    out.push_back(Plan{c, cfgs[c][0], cfgs[c][1], 1, g.K});
+    if (!g.ws || t >= kTargetWgs) continue;
+    int s = (int)std::min<long long>((kTargetWgs + t - 1) / t, kMaxSplits);
+    s = std::min(s, g.K / kMinSplitK);
+    const size_t per = sizeof(typename Mf::T) * 2 * (size_t)g.M * g.N * g.batch;
+    s = (int)std::min<size_t>((size_t)s, per ? g.ws_bytes / per : 0);
+    if (s < 2) continue;
+    const int kc = ((g.K + s - 1) / s + kKGrain - 1) / kKGrain * kKGrain;
+    out.push_back(Plan{c, cfgs[c][0], cfgs[c][1], (g.K + kc - 1) / kc, kc});
+  }
+  return out;
+}
+
+TuneKey key_of(const GemmDesc& g, int kind, bool out64) {
+  return TuneKey{kind, out64 ? 1 : 0, (g.sAk == 1 || g.K == 1) ? 1 : 0, (g.sBn == 1 || g.N == 1) ? 1 : 0,
+                 g.M, g.N, g.K, g.batch};
+}
+
+// The plan a product takes: the tuned one, a freshly tuned one (tuning allowed, stream not being
+// captured), or the rule.
+template <class Mf, class Run>
+hipError_t plan_and_run(const GemmDesc& g, const int (*cfgs)[2], int ncfg, int kind, bool out64,
+                        hipStream_t st, Run run) {
+  const Plan rule = make_plan<Mf>(g, cfgs, ncfg);
+  Tuner* t = t_tuner;
+  if (!t) return run(g, rule, st);
+  const TuneKey key = key_of(g, kind, out64);
+  {
+    std::lock_guard<std::mutex> lk(t->mu);
+    if (t->mode == MPOEVO_TUNE_OFF) return run(g, rule, st);
+    auto it = t->table.find(key);
+    if (it != t->table.end()) return run(g, it->second, st);
+    if (t->mode != MPOEVO_TUNE_ON || !t_tune_allowed) return run(g, rule, st);
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  MPOEVO_HIP_TRY(hipStreamIsCapturing(st, &cap));
+  if (cap != hipStreamCaptureStatusNone) return run(g, rule, st);
+  std::lock_guard<std::mutex> lk(t->mu);
+  for (hipEvent_t& e : t->ev)
+    if (!e) MPOEVO_HIP_TRY(hipEventCreate(&e));
+  MPOEVO_HIP_TRY(hipStreamSynchronize(st));
+  Plan best = rule;
+  float best_ms = 0.f;
+  bool have = false;
+  for (const Plan& p : candidate_plans<Mf>(g, cfgs, ncfg)) {
+    MPOEVO_HIP_TRY(run(g, p, st));  // warm-up (and instruction cache)
+    MPOEVO_HIP_TRY(hipEventRecord(t->ev[0], st));
+    for (int r = 0; r < 3; ++r) MPOEVO_HIP_TRY(run(g, p, st));
+    MPOEVO_HIP_TRY(hipEventRecord(t->ev[1], st));
+    MPOEVO_HIP_TRY(hipEventSynchronize(t->ev[1]));
+    float ms = 0.f;
+    MPOEVO_HIP_TRY(hipEventElapsedTime(&ms, t->ev[0], t->ev[1]));
+    if (!have || ms < best_ms) { best = p; best_ms = ms; have = true; }
+  }
+  t->table[key] = best;
+  return run(g, best, st);  // the output of the kept plan
+}
+
 template <typename TO>
-hipError_t launch_bf16x3(const GemmDesc& g, hipStream_t st) {
-  const Plan pl = make_plan<MfmaF32>(g, kF32Cfg, 3);
+hipError_t run_3m(const GemmDesc& g, const Plan& pl, hipStream_t st) {
+  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, 1, 2, TO>(g, pl, st);
+  if (pl.cfg == 1) return launch_3m_cfg<1, 1, 32, 2, 2, TO>(g, pl, st);
+  return launch_3m_cfg<1, 1, 64, 4, 1, TO>(g, pl, st);
+}
+
+template <typename TO>
+hipError_t run_bf16x3(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   switch (pl.cfg) {
     case 0: return launch_bf16x3_cfg<2, 2, 16, TO>(g, pl, st);
     case 1: return launch_bf16x3_cfg<1, 2, 16, TO>(g, pl, st);
@@ -1016,20 +1135,78 @@ hipError_t launch_bf16x3(const GemmDesc& g, hipStream_t st) {
   }
 }
 
-hipError_t launch_f64(const GemmDesc& g, hipStream_t st) {
-  const Plan pl = make_plan<MfmaF64>(g, kF64Cfg, 2);
+hipError_t run_f64(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   if (pl.cfg == 0) return launch_cfg<MfmaF64, 2, 4, 8, double>(g, pl, st);
   return launch_cfg<MfmaF64, 1, 2, 16, double>(g, pl, st);
 }
 
 }  // namespace
 
+void* gemm_tuner_new() { return new (std::nothrow) Tuner(); }
+void gemm_tuner_free(void* t) { delete static_cast<Tuner*>(t); }
+
+int gemm_tuner_mode(void* t, int set) {
+  auto* tu = static_cast<Tuner*>(t);
+  std::lock_guard<std::mutex> lk(tu->mu);
+  if (set >= 0) tu->mode = set;
+  return tu->mode;
+}
+
+size_t gemm_tuner_entries(void* t) {
+  auto* tu = static_cast<Tuner*>(t);
+  std::lock_guard<std::mutex> lk(tu->mu);
+  return tu->table.size();
+}
+
+void gemm_tuner_clear(void* t) {
+  auto* tu = static_cast<Tuner*>(t);
+  std::lock_guard<std::mutex> lk(tu->mu);
+  tu->table.clear();
+}
+
+TunerScope::TunerScope(void* t, bool allow) : prev_(t_tuner), prev_allow_(t_tune_allowed) {
+  t_tuner = static_cast<Tuner*>(t);
+  t_tune_allowed = allow;
+}
+TunerScope::~TunerScope() {
+  t_tuner = static_cast<Tuner*>(prev_);
+  t_tune_allowed = prev_allow_;
+}
+
+int gemm_plan_query(void* t, int prec, int M, int N, int K, int batch, int* out) {
+  GemmDesc g{};
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  g.sAk = 1; g.sBn = 1;
+  static char sentinel;
+  g.ws = &sentinel;  // the split-K scratch of every caller
+  g.ws_bytes = kGemmScratchBytes;
+  Plan p{};
+  int kind = 0;
+  if (prec == MPOEVO_FP64) { p = make_plan<MfmaF64>(g, kF64Cfg, 2); kind = kKindF64; }
+  else if (prec == MPOEVO_BF16X3) { p = make_plan<MfmaF32>(g, kF32Cfg, 3); kind = kKindBf16x3; }
+  else { p = make_plan<MfmaF32>(g, k3mCfg, 3); kind = kKind3m; }
+  int tuned = 0;
+  if (t) {
+    auto* tu = static_cast<Tuner*>(t);
+    std::lock_guard<std::mutex> lk(tu->mu);
+    for (int o64 = 0; o64 < 2 && !tuned; ++o64) {
+      auto it = tu->table.find(key_of(g, kind, o64 != 0));
+      if (tu->mode != MPOEVO_TUNE_OFF && it != tu->table.end()) { p = it->second; tuned = 1; }
+    }
+  }
+  out[0] = p.bm; out[1] = p.bn; out[2] = p.splits; out[3] = tuned;
+  return 0;
+}
+
 hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
-  if (fp64) return launch_f64(g, st);
-  if (g.bf16x3) return out_fp64 ? launch_bf16x3<double>(g, st) : launch_bf16x3<float>(g, st);
-  return out_fp64 ? launch_3m<double>(g, st) : launch_3m<float>(g, st);
+  if (fp64) return plan_and_run<MfmaF64>(g, kF64Cfg, 2, kKindF64, true, st, run_f64);
+  if (g.bf16x3)
+    return out_fp64 ? plan_and_run<MfmaF32>(g, kF32Cfg, 3, kKindBf16x3, true, st, run_bf16x3<double>)
+                    : plan_and_run<MfmaF32>(g, kF32Cfg, 3, kKindBf16x3, false, st, run_bf16x3<float>);
+  return out_fp64 ? plan_and_run<MfmaF32>(g, k3mCfg, 3, kKind3m, true, st, run_3m<double>)
+                  : plan_and_run<MfmaF32>(g, k3mCfg, 3, kKind3m, false, st, run_3m<float>);
 }
 
 }  // namespace mpoevo

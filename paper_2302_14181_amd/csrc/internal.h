@@ -39,6 +39,33 @@ struct Context {
   // the worker streams (hipStream_t, default priority), created on first use.
   std::vector<std::unique_ptr<Context>> chains;
   std::vector<void*> streams;
+  // product tile tuner (owned by the handle; the per-chain contexts of step_batched borrow the
+  // handle's and never tune)
+  void* tuner = nullptr;
+  bool owns_tuner = false;
+};
+
+// Product tile tuner (gemm.hip): per-handle table of the plan chosen for each product shape.
+void* gemm_tuner_new();
+void gemm_tuner_free(void* t);
+int gemm_tuner_mode(void* t, int set);  // set < 0: query only; returns the mode
+size_t gemm_tuner_entries(void* t);
+void gemm_tuner_clear(void* t);
+// The plan a product of this shape (operands contiguous along k and n) takes with tuner t
+// (nullable): out = {tile rows, tile columns, K splits, 1 if tuned else 0}.
+int gemm_plan_query(void* t, int prec, int M, int N, int K, int batch, int* out);
+// Makes t the tuner of the products launched by this thread while the scope lives; allow:
+// new shapes may be tuned (otherwise they take the rule).
+class TunerScope {
+ public:
+  TunerScope(void* t, bool allow);
+  ~TunerScope();
+  TunerScope(const TunerScope&) = delete;
+  TunerScope& operator=(const TunerScope&) = delete;
+
+ private:
+  void* prev_;
+  bool prev_allow_;
 };
 
 int device_init(Context& ctx);

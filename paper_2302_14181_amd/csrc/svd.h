@@ -103,5 +103,7 @@ double svd_sweep_flop(const SvdPlan& p, int nb = 0);
 // The plan the Jacobi iteration of a truncation runs on: the plan itself, or for the pivoted-QR
 // plan that of R^dag (nx x min(mx, nx)).
 SvdPlan svd_jacobi_plan(const SvdPlan& p);
+// Host function of the Jacobi kernel instance a plan launches (names profiled launches).
+const void* svd_jacobi_kernel_ptr(const SvdPlan& p);
 
 }  // namespace mpoevo

@@ -1283,6 +1283,8 @@ SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap) {
 
 SvdPlan svd_jacobi_plan(const SvdPlan& p) { return p.qr ? rdag_plan(p) : p; }
 
+const void* svd_jacobi_kernel_ptr(const SvdPlan& p) { return jacobi_for(svd_jacobi_plan(p)); }
+
 double svd_sweep_flop(const SvdPlan& p, int nb) {
   // one full round (every pair inside a block pair) and nb - 2 cross rounds (b x b pairs)
   if (nb <= 0) nb = p.nb;

@@ -137,6 +137,7 @@ hipError_t launch_left(const void* Tin, const void* W, void* out, int P, int Q, 
   dim3 grid((Q + kThreads - 1) / kThreads, P, (d * wr + NG * kIlp - 1) / (NG * kIlp));
   hipLaunchKernelGGL((wmix_left_kernel<T, KMAX>), grid, dim3(kThreads * NG), sh, st,
                      (const cx_t<T>*)Tin, (const cx_t<T>*)W, (cx_t<T>*)out, Q, wl, d, wr);
+  last_launch() = LaunchRecord{reinterpret_cast<const void*>(wmix_left_kernel<T, KMAX>), false};
   return hipGetLastError();
 }
 
@@ -148,6 +149,7 @@ hipError_t launch_right(const void* U, const void* W, void* out, int Q, int Pr, 
   dim3 grid((Pr + kThreads - 1) / kThreads, Q, (wl * d + NG * kIlp - 1) / (NG * kIlp));
   hipLaunchKernelGGL((wmix_right_kernel<T, KMAX>), grid, dim3(kThreads * NG), sh, st,
                      (const cx_t<T>*)U, (const cx_t<T>*)W, (cx_t<T>*)out, Q, Pr, wl, d, wr);
+  last_launch() = LaunchRecord{reinterpret_cast<const void*>(wmix_right_kernel<T, KMAX>), false};
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 V1_EXACT, V2_EXTENDED = 0, 1
 LEFT, RIGHT = 0, 1
 CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP, CALL_EXPECTATION, CALL_STEP_BATCHED = 0, 1, 2, 3, 4, 5
+TUNE_OFF, TUNE_ON, TUNE_FROZEN = 0, 1, 2
 MAX_CHAINS = 4096
 SVD_MAX_DIM = 1024
 
@@ -47,6 +48,15 @@ class _Opts(ctypes.Structure):
                 ("svd_cold_start", ctypes.c_int)]
 
 
+MAX_KERNEL_STATS = 16
+KERNEL_KINDS = ("jacobi_svd", "complex_gemm", "w_contraction")
+
+
+class _KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 224), ("kind", ctypes.c_int), ("split_k", ctypes.c_int),
+                ("launches", ctypes.c_int), ("ms", ctypes.c_double), ("work", ctypes.c_double)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_double), ("discarded_max", ctypes.c_double),
                 ("discarded_sum", ctypes.c_double), ("visits", ctypes.c_int),
@@ -54,7 +64,8 @@ class _Stats(ctypes.Structure):
                 ("t_jacobi_ms", ctypes.c_double), ("jacobi_gflop", ctypes.c_double), ("n_jacobi", ctypes.c_int),
                 ("t_gemm_ms", ctypes.c_double), ("gemm_gflop", ctypes.c_double), ("n_gemm", ctypes.c_int),
                 ("t_wmix_ms", ctypes.c_double), ("wmix_gbyte", ctypes.c_double), ("n_wmix", ctypes.c_int),
-                ("svd_sweeps_total", ctypes.c_int), ("svd_sweeps_hist", ctypes.c_int * 32)]
+                ("svd_sweeps_total", ctypes.c_int), ("svd_sweeps_hist", ctypes.c_int * 32),
+                ("n_kernel_stats", ctypes.c_int), ("kernel_stats", _KernelStat * MAX_KERNEL_STATS)]
 
 
 _lib = None
@@ -88,9 +99,12 @@ def load(path: str = LIB_PATH):
                                 vp, vp, sz, vp]
     lib.step_batched.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO),
                                  ctypes.POINTER(_Opts), ctypes.POINTER(_Stats), vp, sz, vp]
+    lib.mpoevo_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.mpoevo_product_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ip, ip]
     for name in ("mpoevo_create", "mpoevo_destroy", "mpoevo_check_solver", "mpo_build",
                  "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step", "expectation",
-                 "step_batched"):
+                 "step_batched", "mpoevo_set_tuning", "mpoevo_product_plan"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -99,7 +113,8 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     return ["mpoevo_create", "mpoevo_destroy", "mpoevo_last_error", "mpoevo_version", "mpo_build",
             "env_update", "local_apply", "truncate", "mpoevo_check_solver", "step",
-            "expectation", "step_batched", "mpoevo_workspace_size"]
+            "expectation", "step_batched", "mpoevo_workspace_size", "mpoevo_set_tuning",
+            "mpoevo_product_plan"]
 
 
 def _check(rc: int, handle=None):
@@ -201,6 +216,18 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+    def set_tuning(self, mode: int, clear: bool = False):
+        """Tile choice of the products (TUNE_OFF: fixed rule; TUNE_ON: time the candidate plans
+        of each new shape; TUNE_FROZEN: keep the tuned shapes, tune no more)."""
+        _check(load().mpoevo_set_tuning(self.ptr, int(mode), int(bool(clear))), self)
+
+    def product_plan(self, prec: int, M: int, N: int, K: int, batch: int = 1) -> dict:
+        """Plan of a product of that shape on this handle: tile, K splits, tuned or not."""
+        out = (ctypes.c_int * 4)()
+        n = ctypes.c_int(0)
+        _check(load().mpoevo_product_plan(self.ptr, prec, M, N, K, batch, out, ctypes.byref(n)), self)
+        return {"tile": (out[0], out[1]), "splits": out[2], "tuned": bool(out[3]), "entries": n.value}
 
     def check_solver(self) -> int:
         """Raise if an SVD since the last check failed; return the largest Jacobi sweep count."""
@@ -319,13 +346,27 @@ def step_workspace(mps: DeviceMPS, mpo: DeviceMPO, prec: int):
     return _workspace(workspace_size(CALL_STEP, dims, prec), mps.buf[0].device)
 
 
+def _default_step_workspace(h: "Handle", mps: DeviceMPS, mpo: DeviceMPO, prec: int):
+    """The workspace of step calls made without one: kept alive on the MPS object per handle,
+    precision and MPO bond, so that the truncation preconditioners a step leaves in it stay
+    intact until the next step (a temporary would return to the allocator and be handed out
+    again between the calls)."""
+    cache = mps.__dict__.setdefault("_step_ws", {})
+    key = (h.ptr.value, prec, max(mpo.w))
+    ws = cache.get(key)
+    if ws is None:
+        ws = cache[key] = step_workspace(mps, mpo, prec)
+    return ws
+
+
 def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int = FP64,
          cutoff: float = 1e-14, input_right_canonical: bool = False, workspace=None,
          stream=None, profile=False, svd_cold_start: bool = False) -> StepStats:
     """One time step of the variational fit; mps is updated in place (see include/mpoevo.h).
-    profile: False, True (time every kernel class) or PROFILE_JACOBI (the Jacobi kernel only)."""
+    profile: False, True (time every kernel class) or PROFILE_JACOBI (the Jacobi kernel only).
+    Without a workspace the MPS object's own default workspace is used (kept between calls)."""
     if workspace is None:
-        workspace = step_workspace(mps, mpo, prec)
+        workspace = _default_step_workspace(h, mps, mpo, prec)
     bond = _iarr(mps.bond)
     sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
     wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
@@ -369,7 +410,7 @@ def split_step(h: Handle, mps: DeviceMPS, first: DeviceMPO, second: DeviceMPO, n
     product is the same operator to second order in either order). Returns both StepStats; the
     product of their norms is the norm of the composite applied to mps."""
     if workspace is None:
-        workspace = step_workspace(mps, first if max(first.w) >= max(second.w) else second, prec)
+        workspace = _default_step_workspace(h, mps, first if max(first.w) >= max(second.w) else second, prec)
     a = step(h, mps, first, nsweeps=nsweeps, prec=prec, cutoff=cutoff,
              input_right_canonical=input_right_canonical, workspace=workspace, stream=stream)
     b = step(h, mps, second, nsweeps=nsweeps, prec=prec, cutoff=cutoff, input_right_canonical=True,
@@ -392,6 +433,9 @@ def _stats_of(st, profile) -> StepStats:
     if profile:
         prof = {k: getattr(st, k) for k in ("t_jacobi_ms", "jacobi_gflop", "n_jacobi", "t_gemm_ms",
                                             "gemm_gflop", "n_gemm", "t_wmix_ms", "wmix_gbyte", "n_wmix")}
+        prof["kernels"] = [{"name": k.name.decode(errors="replace"), "kind": KERNEL_KINDS[k.kind],
+                            "split_k": bool(k.split_k), "launches": k.launches, "ms": k.ms, "work": k.work}
+                           for k in st.kernel_stats[:st.n_kernel_stats]]
     return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
                      st.svd_sweeps_max, prof, st.svd_sweeps_total, tuple(st.svd_sweeps_hist))
 

@@ -7,6 +7,7 @@ and through it the oracle's step (infidelity <= 1e-12 FP64 / 1e-9 FP32, as for `
 import numpy as np
 import pytest
 
+from gpu_helpers import mpo_pair
 from oracle import fit as ofit
 from paper_2302_14181_amd import workloads as wl
 
@@ -46,15 +47,16 @@ CHAINS = [(0.7, 6, 4, 8), (1.3, 9, 6, 16), (1.0, 12, 8, 12), (0.55, 7, 3, 6), (1
           (0.9, 8, 8, 8), (1.2, 5, 2, 4), (0.6, 11, 6, 10), (1.1, 13, 4, 14), (0.8, 6, 5, 24)]
 
 
-def _inputs(mp, chains, seed):
+def _inputs(mp, chains, seed, oracle_mpos=False):
+    """Random states and the chains' MPOs (device side; with oracle_mpos also the oracle's own)."""
     rng = np.random.default_rng(seed)
-    psis, Ws = [], []
+    psis, Ws, Wos = [], [], []
     for g, L, D0, _ in chains:
         psis.append(_normalise(wl.random_mps(rng, L, 2, D0)))
-        H = wl.tfim(g)
-        W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+        W, Wo = mpo_pair(mp, wl.tfim(g), 2, -0.1j)
         Ws.append(W)
-    return psis, Ws
+        Wos.append(Wo)
+    return (psis, Ws, Wos) if oracle_mpos else (psis, Ws)
 
 
 def _max_diff(a, b):
@@ -66,7 +68,7 @@ def _max_diff(a, b):
 def test_batched_equals_one_by_one_and_oracle(mp, handle, prec):
     chains = CHAINS[:6]
     _say("step_batched", len(chains), "chains", "fp64" if prec == 0 else "fp32")
-    psis, Ws = _inputs(mp, chains, 41)
+    psis, Ws, Wos = _inputs(mp, chains, 41, oracle_mpos=True)
     dms = [mp.DeviceMPS(p, Dmax=c[3]) for p, c in zip(psis, chains)]
     dws = [mp.DeviceMPO([W] * c[1]) for W, c in zip(Ws, chains)]
     stats = mp.step_batched(handle, dms, dws, nsweeps=2, prec=prec)
@@ -80,7 +82,7 @@ def test_batched_equals_one_by_one_and_oracle(mp, handle, prec):
         assert abs(stats[c].norm - st1.norm) <= 1e-12 * st1.norm
         assert stats[c].visits == 4 * (chain[1] - 1)
         if c < 3:  # the oracle on the first chains
-            ref, rst = ofit.fit_step(psi, W, Dmax=chain[3], nsweeps=2)
+            ref, rst = ofit.fit_step(psi, Wos[c], Dmax=chain[3], nsweeps=2)
             infid = 1 - abs(ofit.overlap(out_b, ref)) ** 2
             assert infid < (1e-12 if prec == 0 else 1e-9), (c, infid)
 

@@ -8,14 +8,16 @@ and the t t term is dropped (at most 2^-16 |x y|). Every real product therefore 
 error of a product stays near 2^-16 * O(1), whatever K is. A contraction chains at most three
 products (environment times site, times W, times the bra or the other block), which gives the
 tolerances below:
-  contractions: relative Frobenius error <= 2e-4 (and, as a sanity check on the mode, >= 1e-9:
-                the result is not an FP64 product);
+  contractions: element-wise error <= 2e-4 of the largest oracle entry, and relative Frobenius
+                error <= 2e-4 (and, as a sanity check on the mode, >= 1e-9: the result is not an
+                FP64 product);
   time step:    infidelity against the oracle step from the same input <= 1e-7 (the state error
                 is ~1e-5 relative and enters the infidelity squared); norm within 1e-4 relative.
 """
 import numpy as np
 import pytest
 
+from gpu_helpers import assert_close, mpo_pair
 from oracle import fit as ofit
 from paper_2302_14181_amd import workloads as wl
 
@@ -85,9 +87,8 @@ def test_env_update_bf16x3(mp, handle, dims, side):
         out = torch.zeros((Dbl, wl_, Dkl), dtype=torch.complex64, device="cuda")
         mp.env_update(handle, mp.RIGHT, _dev64(E), _dev64(bra), _dev64(W), _dev64(ket), out, prec=mp.BF16X3)
     torch.cuda.synchronize()
-    err = _rel(out.cpu().numpy().astype(np.complex128), ref)
-    print(f"  relative error {err:.3e}", flush=True)
-    assert 1e-9 < err < TOL_CONTRACT, err
+    _, err = assert_close(out.cpu().numpy(), ref, TOL_CONTRACT, "env_update bf16x3")
+    assert err > 1e-9, err
 
 
 LA_CASES = [  # Dbra_l, Dket_l, Dket_m, Dket_r, Dbra_r, d, w_l, w_m, w_r
@@ -112,9 +113,8 @@ def test_local_apply_bf16x3(mp, handle, dims):
     mp.local_apply(handle, _dev64(L), _dev64(W1), _dev64(W2), _dev64(M1), _dev64(M2), _dev64(R), th,
                    prec=mp.BF16X3)
     torch.cuda.synchronize()
-    err = _rel(th.cpu().numpy(), ref)
-    print(f"  relative error {err:.3e}", flush=True)
-    assert 1e-9 < err < TOL_CONTRACT, err
+    _, err = assert_close(th.cpu().numpy(), ref, TOL_CONTRACT, "local_apply bf16x3")
+    assert err > 1e-9, err
 
 
 def test_bf16x3_needs_complex64(mp, handle):
@@ -139,8 +139,8 @@ def test_step_bf16x3_random_state(mp, handle, case):
     _say("step bf16x3 random", case)
     rng = np.random.default_rng(L * 7 + D)
     psi = _normalise(wl.random_mps(rng, L, 2, D0))
-    W, _ = mp.mpo_build(*[getattr(wl.tfim(1.0), k) for k in ("A", "B", "C", "Dloc")], N, -0.1j, mp.V2_EXTENDED)
-    ref, rst = ofit.fit_step(psi, W, Dmax=D, nsweeps=2)
+    W, Wo = mpo_pair(mp, wl.tfim(1.0), N, -0.1j)
+    ref, rst = ofit.fit_step(psi, Wo, Dmax=D, nsweeps=2)
     dm = mp.DeviceMPS(psi, Dmax=D)
     dw = mp.DeviceMPO([W] * L)
     st = mp.step(handle, dm, dw, nsweeps=2, prec=mp.BF16X3)
@@ -150,3 +150,26 @@ def test_step_bf16x3_random_state(mp, handle, case):
     assert infid < 1e-7, infid
     assert abs(st.norm - rst["norm"]) < 1e-4 * rst["norm"]
     assert abs(ofit.norm(out) - 1) < 1e-12
+
+
+def test_step_bf16x3_long_range_order3_d64(mp, handle):
+    """Split-BF16x3 step with the order-3 long-range MPO (w = 271) at L = 14, D = 64: the products
+    take the bf16x3 128 x 64 tile. Against the oracle's fit from the same random state."""
+    import json
+    import os
+    L, D = 14, 64
+    _say("step bf16x3 long-range order 3 L=14 D=64")
+    plan = handle.product_plan(mp.BF16X3, D * 271, 2 * D, D)
+    print("  plan of the E ket product:", plan, flush=True)
+    assert plan["tile"] == (128, 64)
+    fit = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lr_fit_K6.json")))
+    H = wl.lr_ising(np.array(fit["coeffs"]), np.array(fit["lambdas"]), 1.0)
+    W, Wo = mpo_pair(mp, H, 3, -0.1j)
+    psi = _normalise(wl.random_mps(np.random.default_rng(1464), L, 2, D))
+    ref, rst = ofit.fit_step(psi, Wo, Dmax=D, nsweeps=2)
+    dm = mp.DeviceMPS(psi, Dmax=D)
+    st = mp.step(handle, dm, mp.DeviceMPO([W] * L), nsweeps=2, prec=mp.BF16X3)
+    infid = 1 - abs(ofit.overlap(dm.to_numpy(), ref)) ** 2
+    print(f"  infidelity {infid:.3e}", flush=True)
+    assert infid < 1e-7, infid
+    assert abs(st.norm - rst["norm"]) < 1e-4 * rst["norm"]

@@ -1,8 +1,12 @@
 """GPU parity of the C ABI device calls against the CPU oracle (MI355X only).
 
 Every case prints its name, seed and shape before touching the GPU. Tolerances:
-  FP64 contractions: relative Frobenius error <= 1e-12;
-  FP32 contractions: relative Frobenius error <= 2e-5 (float accumulation over K <= 2048 terms);
+  FP64 contractions: element-wise error <= 1e-12 of the largest oracle entry (and relative
+            Frobenius error <= 1e-12);
+  FP32 contractions: the same with 2e-5: three chained float products, each rounding its
+            output (2^-24 relative) and summing K <= 2048 terms whose rounding errors add with
+            random signs (about sqrt(K) 2^-24 of the summed magnitudes, a few 1e-7 of the largest
+            output); the three-product complex form adds up to two such terms to Im;
   FP64 SVD: singular values to 1e-12 relative to sigma_1, factors orthonormal to 1e-12,
             the rank-k product equal to the optimal rank-k approximation to 1e-11.
   Time step (gauge-invariant): infidelity against the oracle step from the same input
@@ -12,6 +16,7 @@ Every case prints its name, seed and shape before touching the GPU. Tolerances:
 import numpy as np
 import pytest
 
+from gpu_helpers import assert_close, mpo_pair, say
 from oracle import dense, fit as ofit, mpo as ompo
 from paper_2302_14181_amd import workloads as wl
 
@@ -35,8 +40,7 @@ def handle(mp):
     h.close()
 
 
-def _say(*a):
-    print("[case]", *a, flush=True)
+_say = say
 
 
 def _dev(x, prec64=True):
@@ -87,8 +91,7 @@ def test_env_update_parity(mp, handle, dims, side, prec64):
         out = torch.zeros((Dbl, wl_, Dkl), dtype=torch.complex128 if prec64 else torch.complex64, device="cuda")
         mp.env_update(handle, mp.RIGHT, _dev(E, prec64), _dev(bra, prec64), _dev(W, prec64), _dev(ket, prec64), out)
     torch.cuda.synchronize()
-    err = _rel(out.cpu().numpy().astype(np.complex128), ref)
-    assert err < (1e-12 if prec64 else 2e-5), err
+    assert_close(out.cpu().numpy(), ref, 1e-12 if prec64 else 2e-5, "env_update")
 
 
 @pytest.mark.parametrize("prec64", [True, False], ids=["fp64", "fp32"])
@@ -100,11 +103,74 @@ def test_env_update_microbench_shape(mp, handle, prec64):
     out = torch.zeros((256, 8, 256), dtype=torch.complex128 if prec64 else torch.complex64, device="cuda")
     mp.env_update(handle, mp.LEFT, _dev(E, prec64), _dev(N, prec64), _dev(W, prec64), _dev(M, prec64), out)
     torch.cuda.synchronize()
-    assert _rel(out.cpu().numpy().astype(np.complex128), ref) < (1e-12 if prec64 else 2e-5)
+    assert_close(out.cpu().numpy(), ref, 1e-12 if prec64 else 2e-5, "left")
     ref = ofit.env_right(E, N, W, M)
     mp.env_update(handle, mp.RIGHT, _dev(E, prec64), _dev(N, prec64), _dev(W, prec64), _dev(M, prec64), out)
     torch.cuda.synchronize()
-    assert _rel(out.cpu().numpy().astype(np.complex128), ref) < (1e-12 if prec64 else 2e-5)
+    assert_close(out.cpu().numpy(), ref, 1e-12 if prec64 else 2e-5, "right")
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
+def test_env_update_large_bond_tiles(mp, handle, prec):
+    """D = 64, w = 271 (the order-3 long-range MPO bond): the W contraction runs as batched
+    products of 542 x 64 outputs over 64 batches, which the planner puts on the largest tile
+    (128 x 64: 5 x 1 x 64 = 320 workgroups) -- the tile of the D = 256, w = 271 products. Both
+    sides, element-wise against the oracle."""
+    dims = (64, 64, 64, 64, 2, 271, 271)
+    _say("env_update large-bond tile", dims, ["fp64", "fp32", "bf16x3"][prec])
+    plan = handle.product_plan(prec, 2 * 271, 64, 2 * 271, 64)
+    print("  plan of the W contraction product:", plan, flush=True)
+    if prec != mp.FP64:
+        assert plan["tile"] == (128, 64) and plan["splits"] == 1
+    rng = np.random.default_rng(271)
+    Dbl, Dkl, Dbr, Dkr, d, wl_, wr = dims
+    bra, ket, W = _cn(rng, Dbl, d, Dbr), _cn(rng, Dkl, d, Dkr), _cn(rng, wl_, d, d, wr)
+    E = _cn(rng, Dbl, wl_, Dkl)
+    f64 = prec == mp.FP64
+    tol = {0: 1e-12, 1: 2e-5, 2: 2e-4}[prec]
+    for side, ref in ((mp.LEFT, ofit.env_left(E, bra, W, ket)), (mp.RIGHT, ofit.env_right(E, bra, W, ket))):
+        out = torch.zeros(ref.shape, dtype=torch.complex128 if f64 else torch.complex64, device="cuda")
+        mp.env_update(handle, side, _dev(E, f64), _dev(bra, f64), _dev(W, f64), _dev(ket, f64), out, prec=prec)
+        torch.cuda.synchronize()
+        assert_close(out.cpu().numpy(), ref, tol, "left" if side == mp.LEFT else "right")
+
+
+@pytest.mark.parametrize("prec", [1, 2, 0], ids=["fp32", "bf16x3", "fp64"])
+def test_env_update_d256_w271_sampled(mp, handle, prec):
+    """The environment update at the full size of the long-range workload (D = 256, d = 2,
+    w = 271, both sides, on the 128 x 64 tiles): 48 sampled outputs, each computed by the oracle
+    from the definition restricted to that output index (the oracle cannot afford all 17.8 M)."""
+    D, d, w = 256, 2, 271
+    _say("env_update full size D=256 w=271 sampled", ["fp64", "fp32", "bf16x3"][prec])
+    rng = np.random.default_rng(2562)
+    bra, ket, W = _cn(rng, D, d, D), _cn(rng, D, d, D), _cn(rng, w, d, d, w)
+    E = _cn(rng, D, w, D)
+    f64 = prec == mp.FP64
+    tol = {0: 1e-12, 1: 2e-5, 2: 2e-4}[prec]
+    idx = [(int(rng.integers(D)), int(rng.integers(w)), int(rng.integers(D))) for _ in range(48)]
+    idx += [(0, 0, 0), (D - 1, w - 1, D - 1)]
+    out = torch.zeros((D, w, D), dtype=torch.complex128 if f64 else torch.complex64, device="cuda")
+    dE, dbra, dW, dket = _dev(E, f64), _dev(bra, f64), _dev(W, f64), _dev(ket, f64)
+    for side in (mp.LEFT, mp.RIGHT):
+        mp.env_update(handle, side, dE, dbra, dW, dket, out, prec=prec)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        # a reference scale for the element-wise bound: every output entry is a sum of
+        # D^2 d^2 w terms of unit variance, so |entry| ~ D d sqrt(w)
+        gs, rs = [], []
+        for (x, y, z) in idx:
+            if side == mp.LEFT:  # E_out[b', beta, b]: restrict bra to b', W to beta, ket to b
+                r = ofit.env_left(E, bra[:, :, [x]], W[:, :, :, [y]], ket[:, :, [z]])[0, 0, 0]
+            else:                # E_out[a', alpha, a]: restrict bra to a', W to alpha, ket to a
+                r = ofit.env_right(E, bra[[x]], W[[y]], ket[[z]])[0, 0, 0]
+            gs.append(got[x, y, z])
+            rs.append(r)
+        gs, rs = np.array(gs), np.array(rs)
+        scale = D * d * np.sqrt(w)
+        err = float(np.abs(gs - rs).max()) / scale
+        print(f"  side {side}: max sampled error {err:.3e} of D d sqrt(w); largest sample "
+              f"{np.abs(rs).max() / scale:.2f}", flush=True)
+        assert err <= tol, (side, err)
 
 
 LA_CASES = [  # Dbra_l, Dket_l, Dket_m, Dket_r, Dbra_r, d, w_l, w_m, w_r
@@ -131,8 +197,7 @@ def test_local_apply_parity(mp, handle, dims, prec64):
     mp.local_apply(handle, _dev(L, prec64), _dev(W1, prec64), _dev(W2, prec64), _dev(M1, prec64),
                    _dev(M2, prec64), _dev(R, prec64), th)
     torch.cuda.synchronize()
-    err = _rel(th.cpu().numpy(), ref)
-    assert err < (1e-12 if prec64 else 2e-5), err
+    assert_close(th.cpu().numpy(), ref, 1e-12 if prec64 else 2e-5, "theta")
 
 
 TR_CASES = [(1, 1), (2, 2), (2, 7), (9, 3), (32, 32), (64, 40), (40, 64), (130, 127), (256, 256), (300, 200),
@@ -259,8 +324,8 @@ def test_step_parity_random_state(mp, handle, case, prec):
     _say("step random", case, "fp64" if prec == 0 else "fp32")
     rng = np.random.default_rng(L * 7 + D)
     psi = _normalise(wl.random_mps(rng, L, 2, D0))
-    W, _ = mp.mpo_build(*[getattr(wl.tfim(1.0), k) for k in ("A", "B", "C", "Dloc")], N, -0.1j, mp.V2_EXTENDED)
-    ref, rst = ofit.fit_step(psi, W, Dmax=D, nsweeps=2)
+    W, Wo = mpo_pair(mp, wl.tfim(1.0), N, -0.1j)
+    ref, rst = ofit.fit_step(psi, Wo, Dmax=D, nsweeps=2)
     out, st = _gpu_step(mp, handle, psi, W, D, prec)
     infid = 1 - abs(ofit.overlap(out, ref)) ** 2
     assert infid < (1e-12 if prec == 0 else 1e-9), infid
@@ -278,19 +343,19 @@ def test_config1_trajectory(mp, handle, prec):
     _say("config1 trajectory", "fp64" if prec == 0 else "fp32")
     L, D, dt = 10, 16, 0.05
     H = wl.tfim(1.0)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -1j * dt, mp.V2_EXTENDED)
+    W, Wo = mpo_pair(mp, H, 2, -1j * dt)
     psi_gpu = wl.all_up(L)
     psi_or = wl.all_up(L)
     Hd = dense.dense_hamiltonian(ompo.hamiltonian_mpo(H), L)
     v0 = dense.mps_to_dense(wl.all_up(L))
     for step in range(20):
-        ref_same, _ = ofit.fit_step(psi_gpu, W, Dmax=D, nsweeps=2)
+        ref_same, _ = ofit.fit_step(psi_gpu, Wo, Dmax=D, nsweeps=2)
         out, st = _gpu_step(mp, handle, psi_gpu, W, D, prec, canonical=step > 0)
         print(f"  step {step}: bonds {max(st.max_bond, 1)} sweeps {st.svd_sweeps_max}", flush=True)
         delta = 1 - abs(ofit.overlap(out, ref_same)) ** 2
         assert delta < (1e-12 if prec == 0 else 1e-9), (step, delta)
         psi_gpu = out
-        psi_or, _ = ofit.fit_step(psi_or, W, Dmax=D, nsweeps=2)
+        psi_or, _ = ofit.fit_step(psi_or, Wo, Dmax=D, nsweeps=2)
     assert 1 - abs(ofit.overlap(psi_gpu, psi_or)) ** 2 < (1e-11 if prec == 0 else 1e-8)
     exact = dense.expm_hermitian(-1j * dt * 20, Hd) @ v0
     assert 1 - abs(np.vdot(dense.mps_to_dense(psi_gpu), exact)) ** 2 < 1e-5
@@ -338,7 +403,7 @@ def test_step_warm_started_truncations_match_cold_and_oracle(mp, handle):
     rng = np.random.default_rng(11)
     psi = _normalise(wl.random_mps(rng, L, 2, D))
     H = wl.tfim(1.5)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    W, Wo = mpo_pair(mp, H, 2, -0.1j)
     dw = mp.DeviceMPO([W] * L)
     warm = mp.DeviceMPS(psi, Dmax=D)
     cold = mp.DeviceMPS(psi, Dmax=D)
@@ -350,7 +415,7 @@ def test_step_warm_started_truncations_match_cold_and_oracle(mp, handle):
         sw = mp.step(handle, warm, dw, prec=mp.FP64, input_right_canonical=s > 0, workspace=ws_w)
         sc = mp.step(handle, cold, dw, prec=mp.FP64, input_right_canonical=s > 0, workspace=ws_c,
                      svd_cold_start=True)
-        ref, _ = ofit.fit_step(ref, W, Dmax=D, nsweeps=2)
+        ref, _ = ofit.fit_step(ref, Wo, Dmax=D, nsweeps=2)
         a, b = warm.to_numpy(), cold.to_numpy()
         assert 1 - abs(ofit.overlap(a, b)) ** 2 < 1e-12, s
         assert 1 - abs(ofit.overlap(a, ref)) ** 2 < 1e-10, s
@@ -373,7 +438,7 @@ def test_fp32_step_sweep_end_keeps_fidelity_and_isometries(mp, handle):
     rng = np.random.default_rng(23)
     psi = _normalise(wl.random_mps(rng, L, 2, D))
     H = wl.tfim(1.5)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    W, Wo = mpo_pair(mp, H, 2, -0.1j)
     dw = mp.DeviceMPO([W] * L)
     d32 = mp.DeviceMPS(psi, Dmax=D)
     ws32 = mp.step_workspace(d32, dw, mp.FP32)
@@ -385,9 +450,13 @@ def test_fp32_step_sweep_end_keeps_fidelity_and_isometries(mp, handle):
         st64 = mp.step(handle, d64, dw, prec=mp.FP64, input_right_canonical=s > 0)
         a, b = d32.to_numpy(), d64.to_numpy()
         infid = 1 - abs(ofit.overlap(a, b)) ** 2
+        ref, rst = ofit.fit_step(before, Wo, Dmax=D, nsweeps=2)
+        infid_or = 1 - abs(ofit.overlap(a, ref)) ** 2
+        assert infid_or < 1e-9, (s, infid_or)
+        assert abs(st32.norm - rst["norm"]) < 1e-6 * rst["norm"]
         iso = max(float(np.max(np.abs(B.reshape(B.shape[0], -1) @ B.reshape(B.shape[0], -1).conj().T
                                       - np.eye(B.shape[0])))) for B in a[1:])
-        print(f"  step {s}: infidelity {infid:.2e} isometry {iso:.1e} sweeps fp32 {st32.svd_sweeps_total}"
+        print(f"  step {s}: infidelity {infid:.2e} (oracle {infid_or:.2e}) isometry {iso:.1e} sweeps fp32 {st32.svd_sweeps_total}"
               f" fp64 {st64.svd_sweeps_total}", flush=True)
         assert infid < 1e-10, (s, infid)
         assert iso < 1e-9, (s, iso)
@@ -437,10 +506,10 @@ def test_expectation_energy_local_norm(mp, handle, L, D):
     assert abs(got - ref) < 1e-12 * abs(nrm)
     got = mp.expectation(handle, dm, mp.DeviceMPO([Id] * L))
     assert abs(got - nrm) < 1e-12 * abs(nrm)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 2, -0.1j, mp.V2_EXTENDED)
+    W, Wo = mpo_pair(mp, H, 2, -0.1j)
     l0 = np.zeros(W.shape[0], complex)
     l0[0] = 1.0
-    ref = ofit.mpo_expectation(psi, [W] * L, l0, l0)
+    ref = ofit.mpo_expectation(psi, [Wo] * L, l0, l0)
     got = mp.expectation(handle, dm, mp.DeviceMPO([W] * L))
     assert abs(got - ref) < 1e-12 * abs(nrm)
 
@@ -467,11 +536,11 @@ def test_step_parity_long_range_order3(mp, handle, prec):
     one step against the oracle from the same random state."""
     _say("step long-range order 3 w=271 L=6 D=8", "fp64" if prec == 0 else "fp32")
     H = _lr_blocks(1.0)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, 3, -0.1j, mp.V2_EXTENDED)
+    W, Wo = mpo_pair(mp, H, 3, -0.1j)
     assert W.shape[0] == 271
     rng = np.random.default_rng(31)
     psi = _normalise(wl.random_mps(rng, 6, 2, 4))
-    ref, rst = ofit.fit_step(psi, W, Dmax=8, nsweeps=2)
+    ref, rst = ofit.fit_step(psi, Wo, Dmax=8, nsweeps=2)
     out, st = _gpu_step(mp, handle, psi, W, 8, prec)
     infid = 1 - abs(ofit.overlap(out, ref)) ** 2
     assert infid < (1e-12 if prec == 0 else 1e-9), infid
@@ -606,3 +675,82 @@ def test_xxz_step_conserves_charge(mp, handle, prec):
         m2 = mp.expectation(handle, dm, d2, 0, 2).real
         tol = 1e-10 if prec == 0 else 1e-6
         assert abs(m1) < tol and abs(m2 - m1 * m1) < tol, (k, m1, m2)
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp32", "fp64"])
+def test_step_long_range_order3_d64(mp, handle, prec):
+    """The order-3 long-range MPO (w = 271) on L = 14 at D = 64 (middle bonds saturated): the
+    products of the step run on the 128 x 64 tile (E ket: 17344 x 128 outputs). One step against
+    the oracle's fit (its own MPO) from the same random state."""
+    L, D = 14, 64
+    _say("step long-range order 3 w=271 L=14 D=64", "fp64" if prec == 0 else "fp32")
+    plan = handle.product_plan(prec, D * 271, 2 * D, D)
+    print("  plan of the E ket product:", plan, flush=True)
+    if prec == mp.FP32:
+        assert plan["tile"] == (128, 64)
+    H = _lr_blocks(1.0)
+    W, Wo = mpo_pair(mp, H, 3, -0.1j)
+    psi = _normalise(wl.random_mps(np.random.default_rng(1464), L, 2, D))
+    ref, rst = ofit.fit_step(psi, Wo, Dmax=D, nsweeps=2)
+    out, st = _gpu_step(mp, handle, psi, W, D, prec)
+    infid = 1 - abs(ofit.overlap(out, ref)) ** 2
+    print(f"  infidelity {infid:.3e}, norm {st.norm:.12f} vs {rst['norm']:.12f}", flush=True)
+    assert infid < (1e-12 if prec == 0 else 1e-9), infid
+    assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]
+    assert abs(st.discarded_sum - sum(rst["discarded"])) < (1e-11 if prec == 0 else 1e-7)
+
+
+def test_default_workspace_survives_other_allocations(mp, handle):
+    """step() without a workspace keeps one per MPS object: the truncation preconditioners it
+    leaves there survive other allocations made between two steps (which would otherwise reuse a
+    freed temporary and overwrite them), so two such steps match the oracle's two fits."""
+    L, D = 12, 8
+    _say("default workspace L=12 D=8, scribbled allocations between two steps")
+    psi = _normalise(wl.random_mps(np.random.default_rng(77), L, 2, D))
+    W, Wo = mpo_pair(mp, wl.tfim(1.5), 2, -0.1j)
+    dm = mp.DeviceMPS(psi, Dmax=D)
+    dw = mp.DeviceMPO([W] * L)
+    mp.step(handle, dm, dw, prec=mp.FP64)
+    nbytes = mp.step_workspace(dm, dw, mp.FP64).numel()
+    junk = [torch.full((nbytes,), 0x5a, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    st = mp.step(handle, dm, dw, prec=mp.FP64, input_right_canonical=True)
+    del junk
+    ref, _ = ofit.fit_step(psi, Wo, Dmax=D)
+    ref, rst = ofit.fit_step(ref, Wo, Dmax=D)
+    infid = 1 - abs(ofit.overlap(dm.to_numpy(), ref)) ** 2
+    assert infid < 1e-12, infid
+    assert abs(st.norm - rst["norm"]) < 1e-10 * rst["norm"]
+
+
+def test_tile_tuner(mp, handle):
+    """The tile tuner: with tuning on, the first environment update of a shape times the
+    candidate plans and keeps one (the plan query then reports it as tuned); the tuned product
+    still matches the oracle element-wise; frozen mode keeps the table; clearing restores the
+    fixed rule."""
+    dims = (200, 200, 200, 200, 2, 6, 6)
+    _say("tile tuner", dims)
+    Dbl, Dkl, Dbr, Dkr, d, wl_, wr = dims
+    rng = np.random.default_rng(5151)
+    bra, ket, W = _cn(rng, Dbl, d, Dbr), _cn(rng, Dkl, d, Dkr), _cn(rng, wl_, d, d, wr)
+    E = _cn(rng, Dbl, wl_, Dkl)
+    ref = ofit.env_left(E, bra, W, ket)
+    shape = (Dbl * wl_, d * Dkr, Dkl)  # the E ket product
+    try:
+        assert not handle.product_plan(mp.FP32, *shape)["tuned"]
+        handle.set_tuning(mp.TUNE_ON, clear=True)
+        for _ in range(2):
+            out = torch.zeros(ref.shape, dtype=torch.complex64, device="cuda")
+            mp.env_update(handle, mp.LEFT, _dev(E, False), _dev(bra, False), _dev(W, False), _dev(ket, False), out)
+            torch.cuda.synchronize()
+            assert_close(out.cpu().numpy(), ref, 2e-5, "tuned env_update")
+        plan = handle.product_plan(mp.FP32, *shape)
+        print("  tuned plan", plan, flush=True)
+        assert plan["tuned"] and plan["entries"] >= 2
+        handle.set_tuning(mp.TUNE_FROZEN)
+        assert handle.product_plan(mp.FP32, *shape)["tuned"]
+        handle.set_tuning(mp.TUNE_OFF, clear=True)
+        p = handle.product_plan(mp.FP32, *shape)
+        assert not p["tuned"] and p["entries"] == 0
+    finally:
+        handle.set_tuning(mp.TUNE_OFF, clear=True)
