@@ -178,3 +178,63 @@ def applied_norm2(psi, Ws) -> float:
         E = np.tensordot(A.conj(), T, axes=([0, 1], [0, 3]))       # [u, v, b, r]
         E = E.transpose(0, 3, 2, 1)
     return float(E[0, 0, 0, 0].real)
+
+
+def local_one_site(Lenv, M, W, Renv):
+    """Projected one-site tensor  M'[a', s', b'] = sum L[a', alpha, a] M[a, s, b] W[alpha, s', s, beta] R[b', beta, b]:
+    the optimal site of the variational fit at fixed bonds, given the other sites (Sec. 2.2, Table 1
+    "variational" row)."""
+    return np.einsum('xay,ysb,apsg,ugb->xpu', Lenv, M, W, Renv, optimize=_EINSUM)
+
+
+def fit_step_one_site(psi, Ws, nsweeps: int = 2, guess=None):
+    """One time step by the one-site variational fit at the fixed bond dimensions of psi
+    (Sec. 2.2; Sec. 8.2 keeps the bond dimension fixed). Readings (the paper leaves them open):
+      * guess phi = psi brought to right-canonical form (as for the two-site fit);
+      * a sweep is a left-to-right pass over the sites 0 .. L-2, where each site's optimal tensor
+        (local_one_site) is replaced by the Q factor of its QR decomposition (rows (a', s'),
+        columns b'; FP64), followed by a right-to-left pass over the sites L-1 .. 1, where it is
+        replaced by the adjoint Q factor of the QR of its adjoint (rows a', columns (s', b'));
+        the triangular factors are dropped (the next site is recomputed from the new environment);
+      * after the last sweep the optimal tensor of site 0 completes phi; its norm is
+        |<phi_hat|W psi>| and phi is normalised.
+    Bonds must satisfy bond[i+1] <= d bond[i] after the guess (they do for the states a two-site
+    fit produces). Returns (phi, stats) with stats = dict(norm, norms (of every local tensor, in
+    visiting order), bond_dims). guess: another starting state (default psi) of the same length,
+    whose bonds the result keeps."""
+    L = len(psi)
+    if not isinstance(Ws, (list, tuple)):
+        Ws = [Ws] * L
+    phi = right_canonicalize(psi if guess is None else guess)
+    d = psi[0].shape[1]
+    for i in range(L - 1):
+        if phi[i].shape[2] > d * phi[i].shape[0]:
+            raise ValueError("one-site fit: bond %d exceeds d times bond %d" % (i + 1, i))
+    Lenv = [None] * (L + 1)
+    Renv = [None] * (L + 1)
+    Lenv[0] = boundary_env(Ws[0].shape[0])
+    Renv[L] = boundary_env(Ws[-1].shape[3])
+    for i in range(L - 1, 0, -1):
+        Renv[i] = env_right(Renv[i + 1], phi[i], Ws[i], psi[i])
+    norms = []
+    for _ in range(nsweeps):
+        for i in range(0, L - 1):  # left to right
+            M = local_one_site(Lenv[i], psi[i], Ws[i], Renv[i + 1])
+            norms.append(float(np.linalg.norm(M)))
+            a, p, b = M.shape
+            Q, _ = np.linalg.qr(M.reshape(a * p, b))
+            phi[i] = Q.reshape(a, p, b)
+            Lenv[i + 1] = env_left(Lenv[i], phi[i], Ws[i], psi[i])
+        for i in range(L - 1, 0, -1):  # right to left
+            M = local_one_site(Lenv[i], psi[i], Ws[i], Renv[i + 1])
+            norms.append(float(np.linalg.norm(M)))
+            a, p, b = M.shape
+            Q, _ = np.linalg.qr(M.reshape(a, p * b).conj().T)
+            phi[i] = Q.conj().T.reshape(a, p, b)
+            Renv[i] = env_right(Renv[i + 1], phi[i], Ws[i], psi[i])
+    M = local_one_site(Lenv[0], psi[0], Ws[0], Renv[1])
+    norm = float(np.linalg.norm(M))
+    norms.append(norm)
+    phi[0] = M / norm if norm > 0 else M
+    dims = [1] + [phi[i].shape[2] for i in range(L)]
+    return phi, dict(norm=norm, norms=norms, bond_dims=dims)
