@@ -114,6 +114,26 @@ int env_update(mpoevo_handle h, int side, int prec, const void* E_in, const void
                void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * env_update_noalloc -- DEVICE, async on `stream`. For callers that cannot allocate device
+ * memory (code under stream/graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operation, arguments and results as env_update, without a workspace argument. Its
+ * intermediates live in a scratch array the library holds on each device from its load until
+ * the process ends (MPOEVO_NOALLOC_SCRATCH_BYTES = 64 MiB per device); the call itself allocates
+ * nothing, host or device, and never synchronises. Dimensions whose intermediates need more than
+ * that (mpoevo_workspace_size(MPOEVO_CALL_ENV_UPDATE) minus its 32 MiB split-K share, e.g.
+ * D = 256, w = 8 needs 17 MB in FP32 and 34 MB in FP64) are rejected with ENOMEM before any GPU
+ * work. What the intermediates leave of the array serves as split-K scratch, so a product may be
+ * split fewer ways than under env_update (same result within rounding). All calls on one device
+ * share the array: calls that overlap in time on one device (different streams, or handles in
+ * different threads) race and give wrong results; serialise them. Nothing in the array needs
+ * clearing between calls (every byte read is written first in the same call).
+ * Errors: as env_update; ENOMEM for oversized dimensions.
+ */
+#define MPOEVO_NOALLOC_SCRATCH_BYTES (64u << 20)
+int env_update_noalloc(mpoevo_handle h, int side, int prec, const void* E_in, const void* bra,
+                       const void* W, const void* ket, void* E_out, const int* dims, void* stream);
+
+/*
  * local_apply -- DEVICE, async on `stream`.
  * Projected two-site tensor of the fit at bond (i, i+1) (the optimal two-site update):
  *   Theta[a'][s'][t'][c'] = sum L[a'][alpha][a] M1[a][s][b] W1[alpha][s'][s][beta]

@@ -152,6 +152,19 @@ int env_update(mpoevo_handle h, int side, int prec, const void* E_in, const void
                                 workspace_bytes, stream);
 }
 
+int env_update_noalloc(mpoevo_handle h, int side, int prec, const void* E_in, const void* bra,
+                       const void* W, const void* ket, void* E_out, const int* dims, void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "env_update_noalloc: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (side != MPOEVO_LEFT && side != MPOEVO_RIGHT) return fail(ctx, MPOEVO_EINVAL, "env_update_noalloc: unknown side");
+  if (!valid_prec(prec)) return fail(ctx, MPOEVO_EINVAL, "env_update_noalloc: unknown precision");
+  if (!E_in || !bra || !W || !ket || !E_out || !dims)
+    return fail(ctx, MPOEVO_EINVAL, "env_update_noalloc: NULL pointer");
+  for (int i = 0; i < 7; ++i)
+    if (dims[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "env_update_noalloc: non-positive dimension");
+  return mpoevo::env_update_noalloc_dev(*ctx, side, prec, E_in, bra, W, ket, E_out, dims, stream);
+}
+
 int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void* W1,
                 const void* W2, const void* M1, const void* M2, const void* R, void* Theta,
                 const int* dims, void* workspace, size_t workspace_bytes, void* stream) {

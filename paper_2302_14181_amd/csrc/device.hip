@@ -24,6 +24,7 @@
 #include <atomic>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -217,11 +218,12 @@ hipError_t gemm_timed(const GemmDesc& g, Arith ar, bool out_fp64, hipStream_t st
 
 hipError_t left_block(Arith ar, const void* E, const void* ket, const void* W, void* tmp,
                       void* LB, int P, int wl, int Qa, int d, int Qb, int wr, hipStream_t st,
-                      Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr) {
+                      Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr,
+                      size_t gws_bytes = kGemmScratchBytes) {
   const bool fp64 = ar.fp64;
   GemmDesc g{};
   g.ws = gws;
-  g.ws_bytes = gws ? kGemmScratchBytes : 0;
+  g.ws_bytes = gws ? gws_bytes : 0;
   g.A = E; g.B = ket; g.C = tmp;
   g.M = P * wl; g.N = d * Qb; g.K = Qa; g.batch = 1;
   g.sAm = Qa; g.sAk = 1; g.sBk = (long long)d * Qb; g.sBn = 1; g.sCm = (long long)d * Qb; g.sCn = 1;
@@ -243,7 +245,7 @@ hipError_t left_block(Arith ar, const void* E, const void* ket, const void* W, v
   MPOEVO_HIP_TRY(hipGetLastError());
   GemmDesc h{};
   h.ws = gws;
-  h.ws_bytes = gws ? kGemmScratchBytes : 0;
+  h.ws_bytes = gws ? gws_bytes : 0;
   h.A = xws; h.B = tmp; h.C = LB;
   h.M = d * wr; h.N = Qb; h.K = wl * d; h.batch = P;
   h.sAm = (long long)wl * d; h.sAk = 1; h.bA = 0;
@@ -256,11 +258,12 @@ hipError_t left_block(Arith ar, const void* E, const void* ket, const void* W, v
 // ket: (Qa, d, Qb), E: (Pr, wr, Qb), W: (wl, d, d, wr). tmp holds Qa*d*Pr*wr complex.
 hipError_t right_block(Arith ar, const void* ket, const void* E, const void* W, void* tmp,
                        void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st,
-                       Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr) {
+                       Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr,
+                       size_t gws_bytes = kGemmScratchBytes) {
   const bool fp64 = ar.fp64;
   GemmDesc g{};
   g.ws = gws;
-  g.ws_bytes = gws ? kGemmScratchBytes : 0;
+  g.ws_bytes = gws ? gws_bytes : 0;
   g.A = ket; g.B = E; g.C = tmp;
   g.M = Qa * d; g.N = Pr * wr; g.K = Qb; g.batch = 1;
   g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sBn = Qb; g.sCm = (long long)Pr * wr; g.sCn = 1;
@@ -285,7 +288,7 @@ hipError_t right_block(Arith ar, const void* ket, const void* E, const void* W, 
   for (int tp = 0; tp < d; ++tp) {
     GemmDesc h{};
     h.ws = gws;
-    h.ws_bytes = gws ? kGemmScratchBytes : 0;
+    h.ws_bytes = gws ? gws_bytes : 0;
     h.A = static_cast<const unsigned char*>(W) + cs * (size_t)tp * d * wr;
     h.B = xws;
     h.C = static_cast<unsigned char*>(RB) + cs * (size_t)tp * Pr;
@@ -301,10 +304,11 @@ hipError_t right_block(Arith ar, const void* ket, const void* E, const void* W, 
 // Lnew[b'][beta][b] = sum conj(bra[a'][s'][b']) LB[a'][s'][beta][b]; bra: (Pa, d, Pb).
 hipError_t left_env_from_block(Arith ar, const void* bra, const void* LB, void* Lnew, int Pa,
                                int d, int Pb, int wr, int Qb, hipStream_t st,
-                         Prof* pr = nullptr, void* gws = nullptr) {
+                         Prof* pr = nullptr, void* gws = nullptr,
+                         size_t gws_bytes = kGemmScratchBytes) {
   GemmDesc g{};
   g.ws = gws;
-  g.ws_bytes = gws ? kGemmScratchBytes : 0;
+  g.ws_bytes = gws ? gws_bytes : 0;
   g.A = bra; g.B = LB; g.C = Lnew;
   g.M = Pb; g.N = wr * Qb; g.K = Pa * d; g.batch = 1;
   g.sAm = 1; g.sAk = Pb; g.conjA = true;
@@ -315,10 +319,11 @@ hipError_t left_env_from_block(Arith ar, const void* bra, const void* LB, void* 
 // Rnew[a'][alpha][a] = sum conj(bra[a'][t'][c']) RB[alpha][a][t'][c']; bra: (Pa, d, Pb).
 hipError_t right_env_from_block(Arith ar, const void* bra, const void* RB, void* Rnew, int Pa,
                                 int d, int Pb, int wl, int Qa, hipStream_t st,
-                         Prof* pr = nullptr, void* gws = nullptr) {
+                         Prof* pr = nullptr, void* gws = nullptr,
+                         size_t gws_bytes = kGemmScratchBytes) {
   GemmDesc g{};
   g.ws = gws;
-  g.ws_bytes = gws ? kGemmScratchBytes : 0;
+  g.ws_bytes = gws ? gws_bytes : 0;
   g.A = bra; g.B = RB; g.C = Rnew;
   g.M = Pa; g.N = wl * Qa; g.K = d * Pb; g.batch = 1;
   g.sAm = (long long)d * Pb; g.sAk = 1; g.conjA = true;
@@ -415,6 +420,10 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
 }  // namespace
 
 // ------------------------------------------------------------------------------ init / sizes
+namespace {
+int noalloc_scratch_init(Context& ctx);
+}  // namespace
+
 int device_init(Context& ctx) {
   hipError_t e = hipSetDevice(ctx.device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
@@ -450,6 +459,11 @@ int device_init(Context& ctx) {
     ctx.owns_tuner = true;
   }
   ctx.dev = ds;
+  const int rc = noalloc_scratch_init(ctx);
+  if (rc != MPOEVO_OK) {
+    device_fini(ctx);
+    return rc;
+  }
   return MPOEVO_OK;
 }
 
@@ -539,34 +553,98 @@ int check_solver_dev(Context& ctx) {
 }
 
 // ------------------------------------------------------------------------------- ABI calls
+namespace {
+// The environment update on a scratch region: base holds the intermediate and the block
+// (env_update_core bytes), then the large-bond W scratch (env_update_xws bytes); gws / gws_bytes
+// is the split-K scratch of the products.
+hipError_t env_update_run(int side, int prec, const void* E_in, const void* bra, const void* W,
+                          const void* ket, void* E_out, const int* dims, unsigned char* base,
+                          void* gws, size_t gws_bytes, hipStream_t st) {
+  const int Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4], wl = dims[5],
+            wr = dims[6];
+  const Arith ar = arith_of(prec);
+  const size_t cs = csize(prec);
+  void* xws = base + env_update_core(dims, prec);
+  if (side == MPOEVO_LEFT) {
+    void* tmp = base;
+    void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
+    MPOEVO_HIP_TRY(left_block(ar, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws, xws,
+                              gws_bytes));
+    return left_env_from_block(ar, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st, nullptr, gws, gws_bytes);
+  }
+  void* tmp = base;
+  void* RB = base + a256(cs * (size_t)Dkl * d * Dbr * wr);
+  MPOEVO_HIP_TRY(right_block(ar, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st, nullptr, gws, xws,
+                             gws_bytes));
+  return right_env_from_block(ar, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st, nullptr, gws, gws_bytes);
+}
+
+// Scratch of env_update_noalloc: one copy per device, held from the library's load until the
+// process ends. Host code never passes the array's own name to a kernel (that is a host-side
+// stand-in): its device address on each device comes from hipGetSymbolAddress, taken once per
+// device at handle creation with that device current.
+__device__ __align__(256) unsigned char scratch[MPOEVO_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch_init(Context& ctx) {
+  if (ctx.device < 0 || ctx.device >= kMaxDevices) {
+    ctx.err = "device index beyond the library's table of per-device scratch addresses";
+    return MPOEVO_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[ctx.device]) return MPOEVO_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                               "hipGetSymbolAddress(scratch)");
+  g_scratch_ptr[ctx.device] = ptr;
+  return MPOEVO_OK;
+}
+}  // namespace
+
 int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
                    const void* W, const void* ket, void* E_out, const int* dims, void* ws,
                    size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
-  const int Dbl = dims[0], Dkl = dims[1], Dbr = dims[2], Dkr = dims[3], d = dims[4], wl = dims[5],
-            wr = dims[6];
-  const Arith ar = arith_of(prec);
-  const size_t cs = csize(prec);
-  hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned char* base = static_cast<unsigned char*>(ws);
-  void* xws = base + env_update_core(dims, prec);
-  void* gws = static_cast<unsigned char*>(xws) + env_update_xws(dims, prec);
-  hipError_t e;
-  if (side == MPOEVO_LEFT) {
-    void* tmp = base;
-    void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
-    e = left_block(ar, E_in, ket, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws, xws);
-    if (e == hipSuccess)
-      e = left_env_from_block(ar, bra, LB, E_out, Dbl, d, Dbr, wr, Dkr, st, nullptr, gws);
-  } else {
-    void* tmp = base;
-    void* RB = base + a256(cs * (size_t)Dkl * d * Dbr * wr);
-    e = right_block(ar, ket, E_in, W, tmp, RB, Dkl, d, Dkr, Dbr, wl, wr, st, nullptr, gws, xws);
-    if (e == hipSuccess)
-      e = right_env_from_block(ar, bra, RB, E_out, Dbl, d, Dbr, wl, Dkl, st, nullptr, gws);
-  }
+  void* gws = base + env_update_core(dims, prec) + env_update_xws(dims, prec);
+  const hipError_t e = env_update_run(side, prec, E_in, bra, W, ket, E_out, dims, base, gws,
+                                      kGemmScratchBytes, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "env_update");
+}
+
+size_t env_update_noalloc_need(const int* dims, int prec) {
+  return env_update_core(dims, prec) + env_update_xws(dims, prec);
+}
+
+int env_update_noalloc_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
+                           const void* W, const void* ket, void* E_out, const int* dims, void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  TunerScope tuner_scope(ctx.tuner, false);  // tuning would synchronise the stream
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ptr = (ctx.device >= 0 && ctx.device < kMaxDevices) ? g_scratch_ptr[ctx.device] : nullptr;
+  }
+  if (!ptr) { ctx.err = "env_update_noalloc: no scratch address for this device"; return MPOEVO_EUNSUPPORTED; }
+  const size_t need = env_update_noalloc_need(dims, prec);
+  if (need > MPOEVO_NOALLOC_SCRATCH_BYTES) {
+    ctx.err = "env_update_noalloc: these dimensions need " + std::to_string(need) +
+              " bytes of scratch, more than the library's " +
+              std::to_string((size_t)MPOEVO_NOALLOC_SCRATCH_BYTES) + " (use env_update with a workspace)";
+    return MPOEVO_ENOMEM;
+  }
+  unsigned char* base = static_cast<unsigned char*>(ptr);
+  // what the intermediates leave over serves as the products' split-K scratch (a planner given
+  // less scratch splits K fewer ways)
+  const size_t gws_bytes = MPOEVO_NOALLOC_SCRATCH_BYTES - need;
+  void* gws = gws_bytes > 0 ? base + need : nullptr;
+  const hipError_t e = env_update_run(side, prec, E_in, bra, W, ket, E_out, dims, base, gws, gws_bytes,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "env_update_noalloc");
 }
 
 int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const void* W2,

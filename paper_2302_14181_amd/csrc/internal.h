@@ -80,6 +80,10 @@ size_t expectation_ws(int L, int d, int Dmax, int wmax);
 int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
                    const void* W, const void* ket, void* E_out, const int* dims, void* ws,
                    size_t ws_bytes, void* stream);
+// env_update on the library's per-device static scratch (no allocation, no workspace argument)
+size_t env_update_noalloc_need(const int* dims, int prec);
+int env_update_noalloc_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
+                           const void* W, const void* ket, void* E_out, const int* dims, void* stream);
 int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const void* W2,
                     const void* M1, const void* M2, const void* R, void* Theta, const int* dims,
                     void* ws, size_t ws_bytes, void* stream);

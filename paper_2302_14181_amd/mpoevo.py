@@ -99,12 +99,13 @@ def load(path: str = LIB_PATH):
                                 vp, vp, sz, vp]
     lib.step_batched.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO),
                                  ctypes.POINTER(_Opts), ctypes.POINTER(_Stats), vp, sz, vp]
+    lib.env_update_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, ip, vp]
     lib.mpoevo_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.mpoevo_product_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ip, ip]
     for name in ("mpoevo_create", "mpoevo_destroy", "mpoevo_check_solver", "mpo_build",
                  "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step", "expectation",
-                 "step_batched", "mpoevo_set_tuning", "mpoevo_product_plan"):
+                 "step_batched", "mpoevo_set_tuning", "mpoevo_product_plan", "env_update_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -114,7 +115,7 @@ def exported_symbols():
     return ["mpoevo_create", "mpoevo_destroy", "mpoevo_last_error", "mpoevo_version", "mpo_build",
             "env_update", "local_apply", "truncate", "mpoevo_check_solver", "step",
             "expectation", "step_batched", "mpoevo_workspace_size", "mpoevo_set_tuning",
-            "mpoevo_product_plan"]
+            "mpoevo_product_plan", "env_update_noalloc"]
 
 
 def _check(rc: int, handle=None):
@@ -250,6 +251,21 @@ def env_update(h: Handle, side: int, E_in, bra, W, ket, E_out, workspace=None, s
         workspace = _workspace(workspace_size(CALL_ENV_UPDATE, dims, prec), E_in.device)
     _check(load().env_update(h.ptr, side, prec, _ptr(E_in), _ptr(bra), _ptr(W), _ptr(ket), _ptr(E_out),
                              _iarr(dims), _ptr(workspace), workspace.numel(), _stream(stream)), h)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def env_update_noalloc(h: Handle, side: int, E_in, bra, W, ket, E_out, stream=None, prec=None):
+    """env_update without a workspace: the library's per-device scratch holds the intermediates
+    (for callers that cannot allocate; calls overlapping on one device race)."""
+    prec = _prec_of(E_in, prec)
+    Dbl, d, Dbr = bra.shape
+    Dkl, _, Dkr = ket.shape
+    wl, _, _, wr = W.shape
+    dims = [Dbl, Dkl, Dbr, Dkr, d, wl, wr]
+    _check(load().env_update_noalloc(h.ptr, side, prec, _ptr(E_in), _ptr(bra), _ptr(W), _ptr(ket),
+                                     _ptr(E_out), _iarr(dims), _stream(stream)), h)
 
 
 def local_apply(h: Handle, Lenv, W1, W2, M1, M2, Renv, Theta, workspace=None, stream=None,
