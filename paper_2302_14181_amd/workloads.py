@@ -198,3 +198,62 @@ def batched_tfim_chains(seed: int = 2, n: int = 64):
         D = int(rng.choice([32, 64, 128, 256]))
         out.append((g, L, D))
     return out
+
+
+def u1_sector_tables(L: int, n_up: int, D: int, nsec: int = 15, seed: int = 1, width: float = 3.0):
+    """Sector tables {charge: dimension} of the L + 1 bonds of a U(1) MPS with n_up up spins
+    (charge = number of up spins to the left of the bond): on bond b the nsec charges nearest the
+    mean filling b n_up / L that the chain can reach, with dimensions proportional to
+    exp(-(q - qbar)^2 / (2 width^2)) (1 + 0.2 xi), xi ~ N(0, 1) from `seed`, rounded by largest
+    remainder to a total of at most D, each at least 1 and at most the exact sector dimension
+    min(C(b, q), C(L - b, n_up - q)). Bonds 0 and L are {0: 1} and {n_up: 1}."""
+    from math import comb
+    rng = np.random.default_rng(seed)
+    tables = [{0: 1}]
+    for b in range(1, L):
+        lo, hi = max(0, n_up - (L - b)), min(b, n_up)
+        qbar = b * n_up / L
+        qs = sorted(range(lo, hi + 1), key=lambda q: (abs(q - qbar), q))[:nsec]
+        qs.sort()
+        exact = {q: min(comb(b, q), comb(L - b, n_up - q)) for q in qs}
+        wgt = np.array([np.exp(-(q - qbar) ** 2 / (2 * width ** 2)) * max(0.05, 1 + 0.2 * rng.standard_normal())
+                        for q in qs])
+        total = min(D, sum(exact.values()))
+        raw = wgt / wgt.sum() * total
+        dims = {q: max(1, min(exact[q], int(np.floor(r)))) for q, r in zip(qs, raw)}
+        rem = sorted(zip(qs, raw - np.floor(raw)), key=lambda t: -t[1])
+        while sum(dims.values()) < total:
+            grown = False
+            for q, _ in rem:
+                if sum(dims.values()) >= total:
+                    break
+                if dims[q] < exact[q]:
+                    dims[q] += 1
+                    grown = True
+            if not grown:
+                break
+        while sum(dims.values()) > total:
+            q = max(dims, key=lambda x: dims[x])
+            dims[q] -= 1
+        tables.append({q: d for q, d in dims.items() if d > 0})
+    tables.append({n_up: 1})
+    return tables
+
+
+def random_u1_mps(rng: np.random.Generator, tables, phys_charge):
+    """Random U(1) MPS as blocks {(q_left, s): array (dim q_left, dim q_left + phys_charge[s])}
+    with complex-normal entries scaled by 1 / sqrt(d dim(right bond)); blocks only where both
+    charges exist. Returns the list of site dicts."""
+    d = len(phys_charge)
+    sites = []
+    for i in range(len(tables) - 1):
+        left, right = tables[i], tables[i + 1]
+        scale = 1.0 / np.sqrt(d * sum(right.values()))
+        site = {}
+        for qa, da in left.items():
+            for s in range(d):
+                qb = qa + int(phys_charge[s])
+                if qb in right:
+                    site[(qa, s)] = complex_normal(rng, (da, right[qb])) * scale
+        sites.append(site)
+    return sites
