@@ -233,13 +233,27 @@ typedef struct {
                          relative inner product is at most 3e-5 (the next would leave about its
                          square, far below the contraction rounding); with FP64, after a sweep
                          that finds every pair below the rounding tolerance. */
+  int nsites;   /* 2 (or 0): two-site updates, bonds adapt up to Dmax by SVD truncation (above).
+                   1: one-site updates at the fixed bond dimensions of psi (Sec. 2.2, Table 1 (ii);
+                   Sec. 8.2 keeps the bond dimension fixed): each site's projected tensor
+                   L_i M_i W_i R_{i+1} becomes its FP64 Householder QR factor (column-pivoted; the
+                   left-to-right pass keeps Q of the (D_i d) x D_{i+1} matrix, the right-to-left
+                   pass the adjoint Q of the transposed problem), no SVD and no truncation;
+                   a sweep is a left-to-right pass over the sites 0..L-2 and a right-to-left pass
+                   over L-1..1, and after the last sweep the projected tensor of site 0 completes
+                   phi (its norm is the fitted norm). Needs bond[i+1] <= d bond[i] after the guess
+                   and d Dmax <= 512 (ESHAPE otherwise); stats: discarded weights 0, visits =
+                   2 (L-1) nsweeps + 1 local updates, no Jacobi sweeps.
+                   -1: automatic -- one-site when every bond of psi equals its largest possible
+                   value min(Dmax, d^i, d^(L-i)) (and d Dmax <= 512), else two-site. */
 } mpoevo_step_opts;
 
 #define MPOEVO_MAX_KERNEL_STATS 16
 typedef struct {
   char name[224];   /* the kernel's name as the HIP runtime reports it, demangled (as profilers
                        list it); truncated to 223 characters */
-  int kind;         /* 0: Jacobi kernel, 1: complex matrix product, 2: short-leg W contraction */
+  int kind;         /* 0: Jacobi kernel, 1: complex matrix product, 2: short-leg W contraction,
+                       3: Householder QR with the explicit Q (one-site updates; work = its GFLOP) */
   int split_k;      /* 1: each timed interval also holds the sum of the split-K partial tiles */
   int launches;
   double ms;        /* summed durations (HIP events around each launch, on the step's stream) */

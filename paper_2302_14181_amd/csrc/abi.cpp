@@ -235,6 +235,7 @@ int check_opts(mpoevo::Context* ctx, const std::string& who, const mpoevo_step_o
   if (opts->nsweeps < 1 || opts->nsweeps > 4) return fail(ctx, MPOEVO_EINVAL, who + ": nsweeps must be 1..4");
   if (!(opts->cutoff >= 0.0) || opts->cutoff >= 1.0) return fail(ctx, MPOEVO_EINVAL, who + ": cutoff must be in [0, 1)");
   if (opts->profile < 0 || opts->profile > 2) return fail(ctx, MPOEVO_EINVAL, who + ": profile must be 0, 1 or 2");
+  if (opts->nsites < -1 || opts->nsites > 2) return fail(ctx, MPOEVO_EINVAL, who + ": nsites must be -1, 0, 1 or 2");
   return MPOEVO_OK;
 }
 }  // namespace

@@ -61,7 +61,7 @@ int hip_fail(Context& ctx, hipError_t e, const char* what) {
 
 // Optional per-kernel-class timing of a step with HIP events on its stream.
 struct Prof {
-  enum Kind { kJacobi = 0, kGemm = 1, kWmix = 2 };
+  enum Kind { kJacobi = 0, kGemm = 1, kWmix = 2, kQr = 3 };
   DeviceState* ds = nullptr;
   hipStream_t st = nullptr;
   bool all = true;  // time the products and W contractions too (else the Jacobi kernel only)
@@ -345,6 +345,78 @@ hipError_t theta_product(Arith ar, const void* LB, const void* RB, void* theta, 
   return gemm_timed(g, ar, true, st, pr);
 }
 
+// One row of the per-kernel statistics of a profiled step: the kernel's name as the runtime
+// reports it (demangled) and its summed launches, time and work.
+void fill_kernel_stat(mpoevo_kernel_stat& o, const void* kernel, int kind, bool split, int n, double ms,
+                      double work, hipStream_t st) {
+  std::memset(&o, 0, sizeof(o));
+  const char* raw = kernel ? hipKernelNameRefByPtr(kernel, st) : nullptr;
+  std::string name = raw ? raw : "unknown kernel";
+  int dst = 0;
+  char* dem = raw ? abi::__cxa_demangle(raw, nullptr, nullptr, &dst) : nullptr;
+  if (dem && dst == 0) name = dem;
+  std::free(dem);
+  std::strncpy(o.name, name.c_str(), sizeof(o.name) - 1);
+  o.kind = kind;
+  o.split_k = split ? 1 : 0;
+  o.launches = n;
+  o.ms = ms;
+  o.work = work;
+}
+
+// dst = src / ||src|| and *norm_out = ||src|| (one workgroup, fixed summation order).
+__global__ __launch_bounds__(256) void norm_scale_kernel(const double2* __restrict__ src,
+                                                         double2* __restrict__ dst, long long n,
+                                                         double* __restrict__ norm_out) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) acc = fma(src[i].x, src[i].x, fma(src[i].y, src[i].y, acc));
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double nr = sqrt(part[0]);
+  if (threadIdx.x == 0) *norm_out = nr;
+  const double f = (nr > 0.0 && isfinite(nr)) ? 1.0 / nr : 1.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = double2{src[i].x * f, src[i].y * f};
+}
+
+// One-site projected tensor from the left block (left-to-right pass):
+// M[(a',s')][b'] = sum_{(beta,b)} LB[(a',s')][(beta,b)] R[b'][(beta,b)], complex128 out.
+hipError_t local_left(Arith ar, const void* LB, const void* R, double2* M, int Pa, int d, int wr,
+                      int Qb, int Pb, hipStream_t st, Prof* pr, void* gws) {
+  GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
+  g.A = LB; g.B = R; g.C = M;
+  g.M = Pa * d; g.N = Pb; g.K = wr * Qb; g.batch = 1;
+  g.sAm = (long long)wr * Qb; g.sAk = 1; g.sBk = 1; g.sBn = (long long)wr * Qb;
+  g.sCm = Pb; g.sCn = 1;
+  return gemm_timed(g, ar, true, st, pr);
+}
+
+// One-site projected tensor from the right block (right-to-left pass):
+// M[a'][(s',b')] = sum_{(alpha,a)} L[a'][(alpha,a)] RB[(alpha,a)][(s',b')], complex128 out.
+hipError_t local_right(Arith ar, const void* L, const void* RB, double2* M, int Pa, int wl, int Qa,
+                       int d, int Pb, hipStream_t st, Prof* pr, void* gws) {
+  GemmDesc g{};
+  g.ws = gws;
+  g.ws_bytes = gws ? kGemmScratchBytes : 0;
+  g.A = L; g.B = RB; g.C = M;
+  g.M = Pa; g.N = d * Pb; g.K = wl * Qa; g.batch = 1;
+  g.sAm = (long long)wl * Qa; g.sAk = 1; g.sBk = (long long)d * Pb; g.sBn = 1;
+  g.sCm = (long long)d * Pb; g.sCn = 1;
+  return gemm_timed(g, ar, true, st, pr);
+}
+
+// Algorithmic flops of a Householder QR of an m x n complex matrix (m >= n) with the thin Q formed.
+double qr_flop(int m, int n) {
+  const double mm = m, nn = n;
+  return 2.0 * (8.0 * mm * nn * nn - 8.0 / 3.0 * nn * nn * nn);
+}
+
 // Site product site[a][s][b] <- sum_c site_in[a][s][c] R[c][b] (complex128), used to absorb
 // the U S factor of the right-canonicalisation into the site on the left.
 hipError_t absorb_right(const void* site_in, const void* R, void* site_out, int Pa, int d, int Pc,
@@ -368,7 +440,7 @@ size_t wcontract_xws(long long ket_rows, long long bra_cols, int d, int wl, int 
 // ------------------------------------------------------------------------- step workspace map
 struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
-  size_t off_token_front, off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
+  size_t off_blk, off_token_front, off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
       off_cplt, off_blocks, off_basis, basiscap, off_token, off_gemm, off_xws, total;
 };
@@ -404,6 +476,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_nbuf = take(sizeof(double) * (size_t)8 * L);
   s.off_site_tmp = take(sizeof(double2) * s.sitecap);
   s.off_site_tmp2 = take(sizeof(double2) * s.sitecap);
+  s.off_blk = take(cs * s.lbcap);  // one-site updates: the block of the current site
   s.off_sweeps = take(sizeof(int) * (size_t)8 * L);
   s.off_cplt = take(sizeof(int) * (size_t)8 * L);  // per visit: the bond matrix had full rank
   s.off_blocks = take(sizeof(int) * (size_t)8 * L);  // per visit: column blocks of the Jacobi rounds
@@ -877,6 +950,137 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   }
   for (int i = 0; i < L; ++i) STEP_TRY(bra_refresh(i));
 
+  // ------------------------------------------------------------------ one-site updates
+  // at the bonds of the guess (fixed): each site's projected tensor becomes its FP64 QR factor
+  auto cap_of = [&](int b) {
+    long long c = 1;
+    for (int k = 0; k < std::min(b, L - b) && c < Dmax; ++k) c *= d;
+    return (int)std::min<long long>(c, Dmax);
+  };
+  bool one_site = opts->nsites == 1;
+  if (opts->nsites == -1) {
+    one_site = d * Dmax <= 512;
+    for (int b = 1; b < L && one_site; ++b) one_site = P[b] == cap_of(b);
+  }
+  if (one_site) {
+    if (d * Dmax > 512) { ctx.err = "step: one-site updates need d Dmax <= 512"; return MPOEVO_ESHAPE; }
+    for (int i = 0; i + 1 < L; ++i)
+      if (P[i + 1] > d * P[i]) {
+        ctx.err = "step: one-site updates need bond[i+1] <= d bond[i] (bond " + std::to_string(i + 1) + ")";
+        return MPOEVO_ESHAPE;
+      }
+    // Lenv_i (i = 0..L-1) live in the left-block slots, Renv_i (i = 1..L) in the right-block slots
+    auto envL = [&](int i) -> void* { return LB(i); };
+    auto envR = [&](int i) -> void* { return RB(i - 1); };
+    void* blk = base + lay.off_blk;
+    auto qr_visit = [&](int m, int n, bool left_to_right, double2* out) -> hipError_t {
+      // left to right: Q of the (D_i d) x D_{i+1} tensor; right to left: Q^dag of the transposed
+      const SvdPlan qp = svd_plan_qr(m, n, left_to_right ? MPOEVO_RIGHT : MPOEVO_LEFT);
+      PROF_BEGIN(prof, qt);
+      MPOEVO_HIP_TRY(qr_isometry(qp, theta, out, !left_to_right, svdws, ctx.dev->status, st, ctx.coop_jacobi));
+      PROF_END(prof, qt, Prof::kQr, qr_flop(std::max(m, n), std::min(m, n)));
+      return hipSuccess;
+    };
+    STEP_TRY(set_boundary(envR(L), w[L], fp64, st));
+    for (int i = L - 1; i >= 1; --i) {
+      STEP_TRY(right_block(ar, ket(i), envR(i + 1), wsite(i), tmp, blk, Q[i], d, Q[i + 1], P[i + 1], w[i],
+                           w[i + 1], st, prof, gws, xws));
+      flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
+      flop_gemm((double)w[i] * d * Q[i], P[i + 1], (double)d * w[i + 1]);
+      STEP_TRY(right_env_from_block(ar, bra(i), blk, envR(i), P[i], d, P[i + 1], w[i], Q[i], st, prof, gws));
+      flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
+    }
+    STEP_TRY(set_boundary(envL(0), w[0], fp64, st));
+    int updates = 0;
+    for (int sw = 0; sw < opts->nsweeps; ++sw) {
+      for (int i = 0; i <= L - 2; ++i, ++updates) {
+        STEP_TRY(left_block(ar, envL(i), ket(i), wsite(i), tmp, blk, P[i], w[i], Q[i], d, Q[i + 1],
+                            w[i + 1], st, prof, gws, xws));
+        flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
+        flop_gemm((double)P[i] * d * w[i + 1], Q[i + 1], (double)w[i] * d);
+        STEP_TRY(local_left(ar, blk, envR(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 1], st, prof, gws));
+        flop_gemm((double)P[i] * d, P[i + 1], (double)w[i + 1] * Q[i + 1]);
+        STEP_TRY(qr_visit(P[i] * d, P[i + 1], true, phi(i)));
+        STEP_TRY(bra_refresh(i));
+        STEP_TRY(left_env_from_block(ar, bra(i), blk, envL(i + 1), P[i], d, P[i + 1], w[i + 1], Q[i + 1], st,
+                                     prof, gws));
+        flop_gemm(P[i + 1], (double)w[i + 1] * Q[i + 1], (double)P[i] * d);
+      }
+      for (int i = L - 1; i >= 1; --i, ++updates) {
+        STEP_TRY(right_block(ar, ket(i), envR(i + 1), wsite(i), tmp, blk, Q[i], d, Q[i + 1], P[i + 1], w[i],
+                             w[i + 1], st, prof, gws, xws));
+        flop_gemm((double)Q[i] * d, (double)P[i + 1] * w[i + 1], Q[i + 1]);
+        flop_gemm((double)w[i] * d * Q[i], P[i + 1], (double)d * w[i + 1]);
+        STEP_TRY(local_right(ar, envL(i), blk, theta, P[i], w[i], Q[i], d, P[i + 1], st, prof, gws));
+        flop_gemm(P[i], (double)d * P[i + 1], (double)w[i] * Q[i]);
+        STEP_TRY(qr_visit(P[i], d * P[i + 1], false, phi(i)));
+        STEP_TRY(bra_refresh(i));
+        STEP_TRY(right_env_from_block(ar, bra(i), blk, envR(i), P[i], d, P[i + 1], w[i], Q[i], st, prof, gws));
+        flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
+      }
+    }
+    // site 0: its projected tensor completes phi; its norm is the fitted norm
+    STEP_TRY(right_block(ar, ket(0), envR(1), wsite(0), tmp, blk, Q[0], d, Q[1], P[1], w[0], w[1], st, prof,
+                         gws, xws));
+    flop_gemm((double)Q[0] * d, (double)P[1] * w[1], Q[1]);
+    flop_gemm((double)w[0] * d * Q[0], P[1], (double)d * w[1]);
+    STEP_TRY(local_right(ar, envL(0), blk, theta, P[0], w[0], Q[0], d, P[1], st, prof, gws));
+    flop_gemm(P[0], (double)d * P[1], (double)w[0] * Q[0]);
+    ++updates;
+    STEP_TRY([&] {
+      hipLaunchKernelGGL(norm_scale_kernel, dim3(1), dim3(256), 0, st, theta, phi(0),
+                         (long long)P[0] * d * P[1], nbuf);
+      return hipGetLastError();
+    }());
+    double norm = 0.0;
+    STEP_TRY(hipMemcpyAsync(&norm, nbuf, sizeof(double), hipMemcpyDeviceToHost, st));
+    for (int i = 0; i < L; ++i) {  // the bonds are the guess's: copy phi back whole
+      STEP_TRY(hipMemcpyAsync(mps->site[i], phi(i), sizeof(double2) * (size_t)P[i] * d * P[i + 1],
+                              hipMemcpyDeviceToDevice, st));
+    }
+    STEP_TRY(hipStreamSynchronize(st));
+    const int sres = check_solver_dev(ctx);
+    if (sres != MPOEVO_OK) return sres;
+    int maxb = 1;
+    for (int b = 0; b <= L; ++b) {
+      mps->bond_dim[b] = P[b];
+      maxb = std::max(maxb, P[b]);
+    }
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->norm = norm;
+      stats->visits = updates;
+      stats->max_bond = maxb;
+      stats->gflop = gflop;
+      if (prof) {
+        struct Agg { int kind; int n; double ms, work; };
+        std::map<const void*, Agg> per_kernel;
+        for (const auto& r : prof->recs) {
+          float ms = 0.f;
+          STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.e0], ctx.dev->events[r.e0 + 1]));
+          const int kind = r.kind == Prof::kGemm ? 1 : r.kind == Prof::kQr ? 3 : 2;
+          if (kind == 1) { stats->t_gemm_ms += ms; stats->gemm_gflop += r.work * 1e-9; stats->n_gemm += 1; }
+          if (kind == 2) { stats->t_wmix_ms += ms; stats->wmix_gbyte += r.work * 1e-9; stats->n_wmix += 1; }
+          Agg& a = per_kernel[r.launch.kernel];
+          a.kind = kind;
+          a.n += 1;
+          a.ms += ms;
+          a.work += r.work * 1e-9;
+        }
+        std::vector<std::pair<const void*, Agg>> order(per_kernel.begin(), per_kernel.end());
+        std::stable_sort(order.begin(), order.end(),
+                         [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
+        for (const auto& kv : order) {
+          if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
+          fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first, kv.second.kind, false,
+                           kv.second.n, kv.second.ms, kv.second.work, st);
+        }
+      }
+    }
+    if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
+    return MPOEVO_OK;
+  }
+
   // right blocks RB_i, i = L-1 .. 1, from the canonical guess
   STEP_TRY(set_boundary(env1, w[L], fp64, st));  // Renv_L
   for (int i = L - 1; i >= 1; --i) {
@@ -1079,6 +1283,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
           stats->gemm_gflop += r.work * 1e-9;
           stats->n_gemm += 1;
           add(r.launch.kernel, 1, r.launch.split, ms, r.work * 1e-9);
+        } else if (r.kind == Prof::kQr) {
+          add(r.launch.kernel, 3, false, ms, r.work * 1e-9);
         } else {
           stats->t_wmix_ms += ms;
           stats->wmix_gbyte += r.work * 1e-9;
@@ -1091,20 +1297,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                        [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
       for (const auto& kv : order) {
         if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
-        mpoevo_kernel_stat& o = stats->kernel_stats[stats->n_kernel_stats++];
-        std::memset(&o, 0, sizeof(o));
-        const char* raw = kv.first.first ? hipKernelNameRefByPtr(kv.first.first, st) : nullptr;
-        std::string name = raw ? raw : "unknown kernel";
-        int dst = 0;
-        char* dem = raw ? abi::__cxa_demangle(raw, nullptr, nullptr, &dst) : nullptr;
-        if (dem && dst == 0) name = dem;
-        std::free(dem);
-        std::strncpy(o.name, name.c_str(), sizeof(o.name) - 1);
-        o.kind = kv.second.kind;
-        o.split_k = kv.second.split;
-        o.launches = kv.second.n;
-        o.ms = kv.second.ms;
-        o.work = kv.second.work;
+        fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first.first, kv.second.kind,
+                         kv.second.split != 0, kv.second.n, kv.second.ms, kv.second.work, st);
       }
     }
   }

@@ -69,6 +69,8 @@ struct SvdWs {  // carved from the caller's workspace
   double* qrefl;        // [2][kMaxGrid][8] (qr) each candidate's reflector: tau, 1 / (alpha - beta), beta
   double2* qcol;        // [2][nb / 2][mx] (qr) each workgroup's candidate column
   int* qsteps;          // [1] (qr) steps taken (fewer than min(mx, nx) when the rest is exactly zero)
+  double2* qtau;        // [2 nx] (qr) tau and 1 / (alpha - beta) of every step's reflector (in aux,
+                        // which the Jacobi phase overwrites with R^dag afterwards)
   void* gemm;           // split-K scratch of the products (kGemmScratchBytes)
 };
 
@@ -115,8 +117,10 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   w.qrefl = nullptr;
   w.qcol = nullptr;
   w.qsteps = nullptr;
+  w.qtau = nullptr;
   if (p.qr) {
     w.aux = reinterpret_cast<double2*>(base + off);
+    w.qtau = w.aux;
     off += align256(sizeof(double2) * p.aux_elems);
     w.qperm = reinterpret_cast<int*>(base + off);
     off += align256(sizeof(int) * p.np);
@@ -1047,11 +1051,13 @@ __global__ __launch_bounds__(kQrThreads) void svd_qrcp_grid_kernel(SvdPlan p, Sv
     const int k = wave;
     const bool mine_pivot = gg == g && c - c_lo == k;
     const double* r = w.qrefl + ((long long)par * kMaxGrid + gg) * 8;
-    if (mine_pivot) {  // R(j, j) and the pivot
+    if (mine_pivot) {  // R(j, j), the pivot and the reflector's scalars (for the explicit Q)
       if (lane == 0) {
         slab[(long long)k * m + j] = double2{r[4], 0.0};
         done[k] = 1;
         w.qperm[j] = c;
+        w.qtau[2 * j] = double2{r[0], r[1]};
+        w.qtau[2 * j + 1] = double2{r[2], r[3]};
       }
       continue;
     }
@@ -1130,6 +1136,61 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const int q = w.qperm[j];
     if (q >= 0 && q < n) w.pinv[q] = j;
+  }
+}
+
+// Thin Q of the column-pivoted QR X Pi = Q R of an mx x nx matrix (svd_qrcp_grid_kernel, with the
+// pivot column of step j kept in X below row j and tau_j, sc_j kept per step): Q = H_0 H_1 ...
+// H_{r-1} [I; 0] with H_j = I - tau_j v_j v_j^dag, v_j = e_j + sc_j x_j (x_j the pivot column of
+// step j below row j), r the steps taken. Column t of Q is H_0 (H_1 (... H_{r-1} e_t)); one wave
+// per column, the rows in registers. out (adjoint 0): Q row-major (mx x nx), out[row nx + t];
+// (adjoint 1): Q^dag row-major (nx x mx), out[t mx + row] = conj(Q(row, t)).
+template <int RM>
+__global__ __launch_bounds__(256) void qr_formq_kernel(SvdPlan p, SvdWs w, double2* __restrict__ out,
+                                                       int adjoint) {
+  const int m = p.mx, n = p.nx;
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (t >= n) return;
+  const int r = min(max(*w.qsteps, 0), min(m, n));
+  double2 q[RM];
+#pragma unroll
+  for (int k = 0; k < RM; ++k) q[k] = double2{lane + 64 * k == t ? 1.0 : 0.0, 0.0};
+  for (int j = r - 1; j >= 0; --j) {
+    const double2 tv = w.qtau[2 * j], sc = w.qtau[2 * j + 1];
+    const double2* x = w.X + (long long)w.qperm[j] * m;
+    double2 xv[RM];
+    double dr = 0.0, di = 0.0, qr = 0.0, qi = 0.0;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+      const int row = lane + 64 * k;
+      xv[k] = (row > j && row < m) ? x[row] : double2{0.0, 0.0};
+      dr = fma(xv[k].x, q[k].x, fma(xv[k].y, q[k].y, dr));   // Re conj(x) q
+      di = fma(xv[k].x, q[k].y, fma(-xv[k].y, q[k].x, di));  // Im conj(x) q
+      if (row == j) { qr = q[k].x; qi = q[k].y; }
+    }
+    wave_sum2(dr, di);
+    wave_sum2(qr, qi);
+    // s = v^dag q = q_j + conj(sc) sum_{i>j} conj(x_i) q_i ;  H_j q = q - v (tau s)
+    const double2 s{qr + sc.x * dr + sc.y * di, qi + sc.x * di - sc.y * dr};
+    const double2 f = cmul(tv, s);
+    const double2 fs = cmul(sc, f);
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+      const int row = lane + 64 * k;
+      if (row == j) q[k] = double2{q[k].x - f.x, q[k].y - f.y};
+      else if (row > j && row < m) {
+        const double2 d = cmul(xv[k], fs);
+        q[k] = double2{q[k].x - d.x, q[k].y - d.y};
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RM; ++k) {
+    const int row = lane + 64 * k;
+    if (row >= m) continue;
+    if (adjoint) out[(long long)t * m + row] = double2{q[k].x, -q[k].y};
+    else out[(long long)row * n + t] = q[k];
   }
 }
 
@@ -1423,6 +1484,46 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
     g.sCm = kcap; g.sCn = 1;
   }
   return gemm_launch(g, true, true, st);
+}
+
+hipError_t qr_isometry(const SvdPlan& p, const double2* theta, double2* out, bool adjoint, void* ws,
+                       int* status, hipStream_t st, bool coop) {
+  if (!p.qr || p.acc || p.mx < p.nx || std::max(p.mx, p.nx) > kQrMaxDim || p.nb / 2 > kMaxGrid ||
+      2 * p.b > kQrThreads / 64)
+    return hipErrorInvalidConfiguration;
+  SvdWs w = carve(p, ws);
+  {
+    const long long total = (long long)p.mx * p.np;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
+    hipLaunchKernelGGL(svd_init_kernel, dim3(blocks), dim3(256), 0, st, theta, p, w, 1, nullptr);
+    MPOEVO_HIP_TRY(hipGetLastError());
+  }
+  {  // squared column norms of X for the factorisation's stopping test
+    const int wpb0 = 4;
+    hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb0 - 1) / wpb0), dim3(64 * wpb0), 0, st, p, w,
+                       status, 1);
+    MPOEVO_HIP_TRY(hipGetLastError());
+  }
+  {
+    SvdPlan pp = p;
+    SvdWs ww = w;
+    int* stp = status;
+    void* args[] = {&pp, &ww, &stp};
+    const size_t lds = sizeof(double2) * (size_t)(2 * p.b) * p.mx;
+    const void* fn = p.mx <= 256 ? reinterpret_cast<const void*>(svd_qrcp_grid_kernel<4>)
+                                 : reinterpret_cast<const void*>(svd_qrcp_grid_kernel<8>);
+    if (coop)
+      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.nb / 2), dim3(kQrThreads), args, (unsigned)lds, st));
+    else
+      MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(p.nb / 2), dim3(kQrThreads), args, lds, st));
+    last_launch() = LaunchRecord{fn, false};
+  }
+  const int blocks = (p.nx + 3) / 4;
+  if (p.mx <= 256)
+    hipLaunchKernelGGL(qr_formq_kernel<4>, dim3(blocks), dim3(256), 0, st, p, w, out, adjoint ? 1 : 0);
+  else
+    hipLaunchKernelGGL(qr_formq_kernel<8>, dim3(blocks), dim3(256), 0, st, p, w, out, adjoint ? 1 : 0);
+  return hipGetLastError();
 }
 
 }  // namespace mpoevo

@@ -45,11 +45,11 @@ class _MPO(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("nsweeps", ctypes.c_int), ("prec", ctypes.c_int), ("cutoff", ctypes.c_double),
                 ("input_right_canonical", ctypes.c_int), ("profile", ctypes.c_int),
-                ("svd_cold_start", ctypes.c_int)]
+                ("svd_cold_start", ctypes.c_int), ("nsites", ctypes.c_int)]
 
 
 MAX_KERNEL_STATS = 16
-KERNEL_KINDS = ("jacobi_svd", "complex_gemm", "w_contraction")
+KERNEL_KINDS = ("jacobi_svd", "complex_gemm", "w_contraction", "householder_qr")
 
 
 class _KernelStat(ctypes.Structure):
@@ -375,9 +375,12 @@ def _default_step_workspace(h: "Handle", mps: DeviceMPS, mpo: DeviceMPO, prec: i
     return ws
 
 
+NSITES_AUTO = -1  # step option: one-site updates once every bond is at its largest value
+
+
 def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int = FP64,
          cutoff: float = 1e-14, input_right_canonical: bool = False, workspace=None,
-         stream=None, profile=False, svd_cold_start: bool = False) -> StepStats:
+         stream=None, profile=False, svd_cold_start: bool = False, nsites: int = 2) -> StepStats:
     """One time step of the variational fit; mps is updated in place (see include/mpoevo.h).
     profile: False, True (time every kernel class) or PROFILE_JACOBI (the Jacobi kernel only).
     Without a workspace the MPS object's own default workspace is used (kept between calls)."""
@@ -389,7 +392,7 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
     cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
     opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
-                 int(bool(svd_cold_start)))
+                 int(bool(svd_cold_start)), int(nsites))
     st = _Stats()
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
                        _ptr(workspace), workspace.numel(), _stream(stream)), h)
@@ -465,7 +468,7 @@ def step_batched_workspace(chains, mpos, prec: int):
 
 def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cutoff: float = 1e-14,
                  input_right_canonical: bool = False, workspace=None, stream=None, profile: bool = False,
-                 svd_cold_start: bool = False):
+                 svd_cold_start: bool = False, nsites: int = 2):
     """One time step of every chain (lists of DeviceMPS and DeviceMPO of equal length), advanced
     concurrently by the library; each MPS is updated in place. Returns one StepStats per chain."""
     if len(chains) != len(mpos) or not chains:
@@ -485,7 +488,7 @@ def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cu
         cms[c] = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
         cws[c] = _MPO(mpo.L, mpo.d, w, wsites)
     opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
-                 int(bool(svd_cold_start)))
+                 int(bool(svd_cold_start)), int(nsites))
     st = (_Stats * n)()
     _check(load().step_batched(h.ptr, n, cms, cws, ctypes.byref(opts), st, _ptr(workspace),
                                workspace.numel(), _stream(stream)), h)

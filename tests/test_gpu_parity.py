@@ -754,3 +754,75 @@ def test_tile_tuner(mp, handle):
         assert not p["tuned"] and p["entries"] == 0
     finally:
         handle.set_tuning(mp.TUNE_OFF, clear=True)
+
+
+ONE_SITE_CASES = [(8, 8, 2), (12, 16, 2), (10, 32, 3), (9, 256, 1)]  # L, Dmax (bonds at their cap), order
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", ONE_SITE_CASES, ids=str)
+def test_one_site_step_parity(mp, handle, case, prec):
+    """One-site updates at fixed bonds (FP64 Householder QR of each projected site tensor) against
+    the oracle's one-site fit from the same state: gauge-invariant overlap and the fitted norm."""
+    L, D, N = case
+    _say("one-site step", case, "fp64" if prec == 0 else "fp32")
+    psi = _normalise(wl.random_mps(np.random.default_rng(300 + L + D), L, 2, D))
+    W, Wo = mpo_pair(mp, wl.tfim(1.2), N, -0.1j)
+    ref, rst = ofit.fit_step_one_site(psi, Wo, nsweeps=2)
+    dm = mp.DeviceMPS(psi, Dmax=D)
+    st = mp.step(handle, dm, mp.DeviceMPO([W] * L), prec=prec, nsites=1)
+    out = dm.to_numpy()
+    infid = 1 - abs(ofit.overlap(out, ref)) ** 2
+    print(f"  infidelity {infid:.3e} norm {st.norm:.14f} vs {rst['norm']:.14f}", flush=True)
+    assert [m.shape for m in out] == [m.shape for m in ref]
+    assert infid < (1e-12 if prec == 0 else 1e-9), infid
+    assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]
+    assert abs(ofit.norm(out) - 1) < 1e-12
+    assert st.visits == 4 * (L - 1) + 1 and st.discarded_sum == 0.0 and st.svd_sweeps_max == 0
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp32", "fp64"])
+def test_one_site_step_long_range_d64(mp, handle, prec):
+    """One-site updates with the order-3 long-range MPO (w = 271) at L = 14, D = 64."""
+    L, D = 14, 64
+    _say("one-site step long-range w=271 L=14 D=64", "fp64" if prec == 0 else "fp32")
+    W, Wo = mpo_pair(mp, _lr_blocks(1.0), 3, -0.1j)
+    psi = _normalise(wl.random_mps(np.random.default_rng(1465), L, 2, D))
+    ref, rst = ofit.fit_step_one_site(psi, Wo, nsweeps=2)
+    dm = mp.DeviceMPS(psi, Dmax=D)
+    st = mp.step(handle, dm, mp.DeviceMPO([W] * L), prec=prec, nsites=1, profile=True)
+    infid = 1 - abs(ofit.overlap(dm.to_numpy(), ref)) ** 2
+    print(f"  infidelity {infid:.3e}; kernels: " +
+          ", ".join(f"{k['kind']} {k['ms']:.2f} ms" for k in st.profile["kernels"][:4]), flush=True)
+    assert infid < (1e-12 if prec == 0 else 1e-9), infid
+    assert abs(st.norm - rst["norm"]) < (1e-10 if prec == 0 else 1e-6) * rst["norm"]
+    assert any(k["kind"] == "householder_qr" for k in st.profile["kernels"])
+
+
+def test_auto_update_picks_by_bond_saturation(mp, handle):
+    """nsites = -1: one-site updates when every bond is at its largest value, else two-site."""
+    L, D = 10, 16
+    _say("automatic one-/two-site choice L=10 D=16")
+    W, Wo = mpo_pair(mp, wl.tfim(0.8), 2, -0.1j)
+    dw = mp.DeviceMPO([W] * L)
+    full = _normalise(wl.random_mps(np.random.default_rng(21), L, 2, D))  # bonds at the cap
+    part = _normalise(wl.random_mps(np.random.default_rng(22), L, 2, 6))  # bonds below it
+    for psi, fit in ((full, ofit.fit_step_one_site), (part, lambda p, W_: ofit.fit_step(p, W_, Dmax=D))):
+        ref, _ = fit(psi, Wo)
+        dm = mp.DeviceMPS(psi, Dmax=D)
+        st = mp.step(handle, dm, dw, prec=mp.FP64, nsites=mp.NSITES_AUTO)
+        assert 1 - abs(ofit.overlap(dm.to_numpy(), ref)) ** 2 < 1e-12
+        assert st.visits == (4 * (L - 1) + 1 if fit is ofit.fit_step_one_site else 4 * (L - 1))
+
+
+def test_one_site_rejects_unsupported_shapes(mp, handle):
+    _say("one-site shape errors")
+    L = 6
+    W, _ = mpo_pair(mp, wl.tfim(1.0), 2, -0.1j)
+    dm = mp.DeviceMPS(wl.all_up(L), Dmax=512)  # d Dmax = 1024 > 512
+    with pytest.raises(mp.MpoevoError) as e:
+        mp.step(handle, dm, mp.DeviceMPO([W] * L), nsites=1)
+    assert e.value.code == mp.ESHAPE
+    with pytest.raises(mp.MpoevoError) as e:
+        mp.step(handle, dm, mp.DeviceMPO([W] * L), nsites=3)
+    assert e.value.code == mp.EINVAL
