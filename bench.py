@@ -1,58 +1,53 @@
 """Benchmark: seconds per time step of the variational higher-order MPO evolution on one MI355X.
 
-Workload (default): the quench of the open transverse-field Ising chain H = -sum Z Z - g sum X,
-L = 64, from the ground state at g = 0.5 (tests/golden/tfim_g05_L64_ground.npz, prepared by the
-oracle) to g = 1.5, with the order-2 extended MPO (w = 3) of exp(-i tau H), tau = 0.1, bond
-dimension D <= 128, truncation cutoff 1e-14 sigma_1, two sweeps per step: K time steps from t = 0
-(default K = 100, the whole run). The bond dimension grows from about 24 to 128 during the first
-twenty steps and stays at 128 afterwards. Contractions run on the FP32 matrix cores, the SVD
-truncation in FP64. `value` is the mean seconds per step over the K timed steps (HIP events on
-the launch stream, bracketed by device synchronisation); W untimed warm-up steps run first on a
-separate copy of the initial state.
+Workload (default, --workload lr3): the long-range Ising chain H = -sum_{i<j} J(j-i) Z_i Z_j - g sum X_i
+with J(r) = r^-2 fitted as six exponentials (tests/golden/lr_fit_K6.json), g = 1, L = 100, the
+order-3 extended MPO (w = 271) of exp(-i tau H), tau = 0.1, bond dimension D <= 256, cutoff
+1e-14 sigma_1, two sweeps of two-site updates per step, from the all-up product state: K time steps
+from t = 0 (default K = 20) after W untimed warm-up steps of the same trajectory on their own state
+(default W = 2). Contractions on the FP32 matrix cores (--prec), the SVD truncation in FP64. The
+bonds reach D = 256 at step 3. `value` is the mean seconds per step over the K timed steps (HIP
+events on the launch stream around each step; every step ends with a synchronisation).
 
-Also reported: the same opening steps on the plain FP64 path (FP32/FP64 time ratio on identical
-steps), one step at saturated bond dimension on a seeded random MPS (D = 128 on every bulk bond;
-also on the FP64 path, for the ratio at saturation),
-one step of the long-range chain at D = 256 with the w = 271 order-3 MPO on the FP32, FP64 and
-split-BF16x3 paths (step time and matrix-core rate of the contractions: the "TFLOP/s at D = 256"
-part of the metric),
-the environment-update microbenchmark at D = 256, d = 2, w = 8 (the matrix-core roofline target),
-the Jacobi kernel's time summed over the timed steps (HIP events around its launches only, the
-roofline line) and every kernel class on one extra saturated step, per-step parity of the first step against the
-oracle from the same initial state on each path (infidelity and <Z_32> error), and the CPU oracle timed on one
-saturated-bond step (the cpu_baseline).
+Also on the line: the plain FP64 path on the same K opening steps (time ratio, and the two
+trajectories' infidelity and <Z_50> after them); per-step parity against the CPU oracle on the
+opening steps: step 1 from all-up on every precision (R17-A infidelity 1 - |<phi_gpu|phi_oracle>|^2
+and R17-B |eps_gpu - eps_oracle|, eps = 1 - |<phi|W psi>|^2 / ||W psi||^2) and step 2 restarted from
+the oracle's state after step 1; the timed launches of the K steps per kernel instance with their
+algorithmic rates, the dominant one as the roofline line (with the HBM traffic per launch from
+profiles/hbm_traffic_lr3.md while the measured source is unchanged); the CPU oracle timed on
+saturated bond visits and scaled to a step (cpu_baseline); side fields: the L = 64 TFIM quench
+(configuration 2, steps 1-20, FP32 and FP64, first-step parity) and the environment-update
+microbenchmark at D = 256, d = 2, w = 8.
 
-With --workload lr3: the long-range Ising chain of the configuration with the largest MPO bond,
-J(r) = r^-2 as six exponentials (tests/golden/lr_fit_K6.json), g = 1, L = 100, order-3 extended MPO
-(w = 271), tau = 0.1, at saturated bond dimension D = 256 (seeded random MPS), K timed steps after
-W warm-up steps of the same trajectory (defaults K = 2, W = 1), FP32 and FP64 paths; the CPU oracle
-is timed on one bond visit of that workload and scaled to a step (labelled extrapolated).
+--workload quench: the L = 64 TFIM quench g = 0.5 -> 1.5 from the ground state at g = 0.5
+(tests/golden/tfim_g05_L64_ground.npz, prepared by the oracle), order-2 extended MPO (w = 3; --order),
+tau = 0.1 (--tau), D <= 128, K steps (default 100) with the FP64 comparison and first-step parity.
 
-With --workload batched: 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128},
+--workload batched: 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128},
 D in {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up, K steps (default 3)
 advanced together by step_batched, against the same steps taken chain by chain; the oracle checks
 and times the first step of the first four chains.
 
-With --workload split: the quench above advanced by the splitting composite of Sec. 8.3 (the
-first-order MPO at t2 tau, then at t1 tau, t1,2 = (1 +- i)/2: two fits per step at MPO bond 2)
-against the order-2 MPO (one fit at bond 3), K steps each (default 20) from the same state.
+--workload split: the quench advanced by the splitting composite of Sec. 8.3 (the first-order MPO at
+t2 tau, then at t1 tau, t1,2 = (1 +- i)/2: two fits per step at MPO bond 2) against the order-2 MPO
+(one fit at bond 3), K steps each (default 20) from the same state.
 
-With --workload thermal: finite temperature by purification on the L = 64 TFIM at g = 1 (physical
-and ancilla leg per site, d = 4): the order-2 MPO at tau = -0.05 on the physical legs, K steps
-(default 20) from beta = 0 (maximally entangled pairs) to beta = 2 K 0.05, D <= 128; FP32 and
-FP64 paths, energy per site at the end from the device expectation.
+--workload thermal: finite temperature by purification on the L = 64 TFIM at g = 1 (physical and
+ancilla leg per site, d = 4): the order-2 MPO at tau = -0.05 on the physical legs, K steps (default
+20) from beta = 0 to beta = 2 K 0.05, D <= 128; FP32 and FP64 paths.
 
-With --workload cylinder: the efficiency set-up of Sec. 8.2 on a finite W = 4 spiral cylinder
-(TFIM, h = 2, 8 x 4 = 32 sites, D <= 64): a ground state by imaginary-time steps, a spin flip on
-the middle site, evolution to T = 1 with orders 1-3 at dt = 0.2, 0.1, 0.05, and the fidelity
-density against an order-3 run at dt = 0.0125 (standing in for the TDVP reference).
+--workload cylinder: the efficiency set-up of Sec. 8.2 on a finite W = 4 spiral cylinder (TFIM, h = 2,
+8 x 4 = 32 sites, D <= 64): fidelity density after T = 1 against the time step for orders 1-3
+against an order-3 run at dt = 0.0125 (standing in for the TDVP reference).
 
-With --workload env: only the left environment update at D = 256, d = 2, w = 8 (the matrix-core
-roofline case), K calls per precision (default 100) timed with HIP events on the launch stream.
+--workload env: only the left environment update at D = 256, d = 2, w = 8, K calls per precision
+(default 100) timed with HIP events on the launch stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64] [--workload quench|lr3|batched|env|split|thermal|cylinder]
-                       [--order 1|2|3|4] [--tau T] [--progress]
+                       [--no-cpu] [--no-fp64] [--no-delta2] [--no-side]
+                       [--workload lr3|quench|batched|env|split|thermal|cylinder] [--order N] [--tau T]
+                       [--progress]
 """
 from __future__ import annotations
 
@@ -113,116 +108,295 @@ def load_ground():
     return [z[f"site_{i:03d}"] for i in range(L)]
 
 
-def run_lr3(args, torch, mp, wl, h, steps=None, warmup=None, embedded=False):
-    """K steps of the order-3 long-range Ising chain at D = 256 (w = 271): the chosen path, and
-    with an FP32 path also plain FP64 and split-BF16x3 on the same steps.
-    embedded: return a summary dict (FP32 vs FP64 vs BF16X3 step time and product rate)."""
-    import json as _json
-    Llr, Dlr, order, tau = 100, 256, 3, 0.1
-    if steps is None:
-        steps = args.steps if args.steps != 100 else 2
-    if warmup is None:
-        warmup = args.warmup
-    fit = _json.load(open(os.path.join(ROOT, "tests", "golden", "lr_fit_K6.json")))
-    H = wl.lr_ising(np.array(fit["coeffs"]), np.array(fit["lambdas"]), 1.0)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, order, -1j * tau, mp.V2_EXTENDED)
-    w = W.shape[0]
-    dw = mp.DeviceMPO([W] * Llr)
-    psi = wl.random_mps(np.random.default_rng(0), Llr, 2, Dlr)
+LR_L, LR_D, LR_ORDER, LR_TAU, LR_SITE = 100, 256, 3, 0.1, 49  # <Z> on site 50 (counted from 1)
+NSITES_DESC = {2: "two-site updates", 1: "one-site updates at fixed bonds",
+               -1: "two-site updates while the bonds grow, one-site once every bond is at its largest value"}
 
-    def run(p, n):
-        dm = mp.DeviceMPS(psi, Dmax=Dlr)
-        ws = mp.step_workspace(dm, dw, p)
-        for k in range(warmup):
-            mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=ws)
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
-        ev[0].record()
-        st = []
-        for k in range(n):
-            st.append(mp.step(h, dm, dw, prec=p, input_right_canonical=(warmup + k) > 0, workspace=ws,
-                              profile=True))
-            ev[k + 1].record()
-        torch.cuda.synchronize()
-        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(n)]
-        del ws, dm
-        torch.cuda.empty_cache()
-        return ms, st
 
-    prec = mp.FP32 if embedded else prec_of(mp, args.prec)
-    ms, st = run(prec, steps)
-    sec = float(np.sum(ms)) / 1e3 / steps
-    prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile}
-    peak = {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA, mp.BF16X3: CEIL_BF16X3}[prec]
-    gemm_tf = prof["gemm_gflop"] / prof["t_gemm_ms"] if prof["t_gemm_ms"] > 0 else 0.0
-    fp64 = bf = None
-    if (embedded or not args.no_fp64) and prec == mp.FP32:
-        ms64, st64 = run(mp.FP64, steps)
-        p64 = {k: float(sum(x.profile[k] for x in st64)) for k in st64[0].profile}
-        fp64 = {"fp64_s_per_step": float(np.sum(ms64)) / 1e3 / steps,
-                "fp64_gemm_tflops": p64["gemm_gflop"] / p64["t_gemm_ms"] if p64["t_gemm_ms"] > 0 else 0.0}
-        fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / sec
-        msb, stb = run(mp.BF16X3, steps)
-        pb = {k: float(sum(x.profile[k] for x in stb)) for k in stb[0].profile}
-        bf = {"bf16x3_s_per_step": float(np.sum(msb)) / 1e3 / steps,
-              "bf16x3_gemm_tflops": pb["gemm_gflop"] / pb["t_gemm_ms"] if pb["t_gemm_ms"] > 0 else 0.0}
-        bf["bf16x3_frac_of_ceiling"] = bf["bf16x3_gemm_tflops"] * 1e12 / CEIL_BF16X3
-        bf["bf16x3_speedup_vs_fp64"] = fp64["fp64_s_per_step"] / bf["bf16x3_s_per_step"]
-    if embedded:
-        return {"workload": f"long-range Ising L={Llr}, order-{order} extended MPO (w={w}), tau={tau}, "
-                            f"D={Dlr} saturated random MPS, {steps} step(s) after {warmup} warm-up",
-                "fp32_s_per_step": sec, "fp64_s_per_step": fp64["fp64_s_per_step"],
-                "fp32_speedup": fp64["fp32_speedup"], "step_tflop": float(np.mean([x.gflop for x in st])) / 1e3,
-                "fp32_gemm_tflops": gemm_tf, "fp32_gemm_frac_of_mfma_peak": gemm_tf * 1e12 / PEAK_FP32_MFMA,
-                "fp64_gemm_tflops": fp64["fp64_gemm_tflops"],
-                "fp64_gemm_frac_of_mfma_peak": fp64["fp64_gemm_tflops"] * 1e12 / PEAK_FP64_MFMA,
-                "jacobi_share_fp32": prof["t_jacobi_ms"] / max(float(np.sum(ms)), 1e-9),
-                "bf16x3": bf}
-    cpu = None
-    if not args.no_cpu:
-        from oracle import fit as ofit
-        import threadpoolctl
-        rng = np.random.default_rng(1)
-        Lenv = wl.complex_normal(rng, (Dlr, w, Dlr))
-        M1, M2 = wl.complex_normal(rng, (Dlr, 2, Dlr)), wl.complex_normal(rng, (Dlr, 2, Dlr))
+def lr_blocks(wl):
+    """J(r) = r^-2 as six exponentials (tests/golden/lr_fit_K6.json), transverse field g = 1."""
+    fit = json.load(open(os.path.join(ROOT, "tests", "golden", "lr_fit_K6.json")))
+    return wl.lr_ising(np.array(fit["coeffs"]), np.array(fit["lambdas"]), 1.0)
+
+
+def trajectory(torch, mp, h, psi0, dw, prec, steps, Dmax, profile=False, progress=None, nsites=2):
+    """`steps` time steps from psi0 on a fresh MPS and workspace; HIP events on the launch stream
+    around every step. Returns (ms per step, StepStats per step, the final DeviceMPS)."""
+    dm = mp.DeviceMPS(psi0, Dmax=Dmax)
+    ws = mp.step_workspace(dm, dw, prec)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    st = []
+    torch.cuda.synchronize()
+    ev[0].record()
+    for k in range(steps):
+        st.append(mp.step(h, dm, dw, prec=prec, input_right_canonical=k > 0, workspace=ws, profile=profile,
+                          nsites=nsites))
+        ev[k + 1].record()
+        if progress:
+            print(f"[bench] {progress} step {k + 1}/{steps}: bond {st[-1].max_bond}, "
+                  f"{'one' if st[-1].discarded_sum == 0 and st[-1].visits % 2 == 1 else 'two'}-site",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    del ws
+    torch.cuda.empty_cache()
+    return ms, st, dm
+
+
+PEAKS = {  # by kernel class and contraction precision: (bound, peak, unit)
+    ("jacobi_svd", None): ("alu", PEAK_FP64_VALU / 1e12, "TFLOP/s"),
+    ("complex_gemm", "fp32"): ("mfma", PEAK_FP32_MFMA / 1e12, "TFLOP/s"),
+    ("complex_gemm", "fp64"): ("mfma", PEAK_FP64_MFMA / 1e12, "TFLOP/s"),
+    ("complex_gemm", "bf16x3"): ("mfma", PEAK_BF16_MFMA / 1e12, "TFLOP/s"),
+    ("w_contraction", None): ("hbm", PEAK_HBM / 1e9, "GB/s"),
+    ("householder_qr", None): ("alu", PEAK_FP64_VALU / 1e12, "TFLOP/s"),
+}
+
+
+def kernel_table(stats, prec_name):
+    """The profiled launches of a set of steps grouped by kernel instance, longest first, each
+    with its algorithmic rate against its roofline (products: 8 flop per complex multiply-add;
+    the three-product FP32 kernel issues 6 of them on the matrix cores: `executed_frac`)."""
+    agg = {}
+    for s in stats:
+        for k in s.profile["kernels"]:
+            a = agg.setdefault((k["name"], k["split_k"]), {"name": k["name"], "kind": k["kind"],
+                                                           "split_k": k["split_k"], "launches": 0,
+                                                           "ms": 0.0, "work": 0.0})
+            a["launches"] += k["launches"]
+            a["ms"] += k["ms"]
+            a["work"] += k["work"]
+    rows = sorted(agg.values(), key=lambda r: -r["ms"])
+    for r in rows:
+        bound, peak, unit = PEAKS[(r["kind"], prec_name if r["kind"] == "complex_gemm" else None)]
+        scale = 1e3 if unit == "TFLOP/s" else 1.0  # work in GFLOP or GB
+        r["avg_launch_us"] = 1e3 * r["ms"] / max(r["launches"], 1)
+        r["work_per_launch"] = r["work"] / max(r["launches"], 1)
+        r["work_unit"] = "GFLOP" if unit == "TFLOP/s" else "GB"
+        r["achieved"] = r["work"] / (r["ms"] * 1e-3) / scale if r["ms"] > 0 else 0.0
+        r.update(bound=bound, peak=peak, unit=unit, frac=r["achieved"] / peak)
+        if "cgemm3m_kernel" in r["name"]:
+            r["executed_frac"] = 0.75 * r["frac"]
+    return rows
+
+
+def roofline_of(row):
+    out = {"bound": row["bound"], "kernel": row["name"], "achieved": row["achieved"], "peak": row["peak"],
+           "unit": row["unit"], "frac": row["frac"], "avg_launch_us": row["avg_launch_us"],
+           "work_per_launch": row["work_per_launch"], "work_unit": row["work_unit"],
+           "launches": row["launches"], "traffic": traffic_of(row["name"])}
+    if "executed_frac" in row:
+        out["executed_frac"] = row["executed_frac"]
+    return out
+
+
+def traffic_of(kernel_name):
+    """HBM bytes per launch of a kernel instance from the committed counter summary
+    (profiles/hbm_traffic_lr3.md: FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel factors),
+    valid only while the source file it was measured on is unchanged; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_lr3.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("| traffic |"):
+            continue
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        _, name, src, sha, fetch, write = cells[:6]
+        if name != kernel_name:
+            continue
+        cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        if cur != sha:
+            return None
+        return float(fetch) + float(write)
+    return None
+
+
+def lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, Dmax, delta2=True):
+    """Per-step parity against the oracle on the opening steps of the trajectory from all-up:
+    step 1 from psi0 (R17-A: 1 - |<phi_gpu|phi_oracle>|^2; R17-B: |eps_gpu - eps_oracle| with
+    eps = 1 - |<phi|W psi>|^2 / ||W psi||^2, ||W psi0||^2 from the oracle's double-layer
+    contraction) on every contraction precision, and step 2 restarted from the oracle's state
+    after step 1 (delta_2, R17-A; the norm error in place of R17-B, whose ||W psi1||^2 is beyond the
+    oracle's budget)."""
+    from oracle import fit as ofit
+    t0 = time.perf_counter()
+    ref1, r1 = ofit.fit_step(psi0, Wo, Dmax=Dmax)
+    n2 = ofit.applied_norm2(psi0, Wo)
+    eps_or = 1.0 - r1["norm"] ** 2 / n2
+    z_or = ofit.expect_local(ref1, wl.SZ, LR_SITE).real
+    out = {"step1": {"oracle_norm": r1["norm"], "oracle_eps": eps_or, "W_psi0_norm2": n2,
+                     "oracle_max_bond": max(r1["bond_dims"])}}
+    for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64), ("bf16x3", mp.BF16X3)):
+        dm = mp.DeviceMPS(psi0, Dmax=Dmax)
+        s = mp.step(h, dm, dw, prec=p)
+        phi = dm.to_numpy()
+        eps = 1.0 - s.norm ** 2 / n2
+        out["step1"][name] = {"infidelity_R17A": float(1.0 - abs(ofit.overlap(phi, ref1)) ** 2),
+                              "eps_excess_R17B": float(abs(eps - eps_or)),
+                              "Z50_error": float(abs(ofit.expect_local(phi, wl.SZ, LR_SITE).real - z_or)),
+                              "norm_rel_error": float(abs(s.norm - r1["norm"]) / r1["norm"])}
+        del dm
+    if delta2:
+        ref2, r2 = ofit.fit_step(ref1, Wo, Dmax=Dmax)
+        z2 = ofit.expect_local(ref2, wl.SZ, LR_SITE).real
+        out["step2_from_oracle_state"] = {"oracle_norm": r2["norm"], "oracle_max_bond": max(r2["bond_dims"]),
+                                          "oracle_discarded_sum": float(sum(r2["discarded"]))}
+        for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64)):
+            dm = mp.DeviceMPS(ref1, Dmax=Dmax)
+            s = mp.step(h, dm, dw, prec=p)
+            phi = dm.to_numpy()
+            out["step2_from_oracle_state"][name] = {
+                "infidelity_R17A": float(1.0 - abs(ofit.overlap(phi, ref2)) ** 2),
+                "norm_rel_error": float(abs(s.norm - r2["norm"]) / r2["norm"]),
+                "discarded_sum_abs_error": float(abs(s.discarded_sum - sum(r2["discarded"]))),
+                "Z50_error": float(abs(ofit.expect_local(phi, wl.SZ, LR_SITE).real - z2))}
+            del dm
+    out["oracle_wall_s"] = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    return out
+
+
+def lr3_cpu_baseline(Wo, wl, Dmax, visits=4):
+    """The oracle timed on a bounded sample of the workload: `visits` bond visits at saturated
+    bond dimension (seeded random environments and sites, D = 256, w = 271): the projected
+    two-site tensor, its FP64 SVD truncation and one environment update, scaled to the
+    4 (L - 1) visits of a step (extrapolated)."""
+    from oracle import fit as ofit
+    import threadpoolctl
+    rng = np.random.default_rng(1)
+    w = Wo.shape[0]
+    t = 0.0
+    for _ in range(visits):
+        Lenv = wl.complex_normal(rng, (Dmax, w, Dmax))
+        Renv = wl.complex_normal(rng, (Dmax, w, Dmax))
+        M1, M2 = wl.complex_normal(rng, (Dmax, 2, Dmax)), wl.complex_normal(rng, (Dmax, 2, Dmax))
         t0 = time.perf_counter()
-        ofit.env_left(Lenv, M1, W, M1)
-        ofit.theta_two_site(Lenv, M1, W, M2, W, Lenv)
-        visit = time.perf_counter() - t0
-        info = threadpoolctl.threadpool_info()
-        threads = max([i.get("num_threads", 1) for i in info] + [1])
-        cpu = {"value": visit * 4 * (Llr - 1), "unit": "s per time step (extrapolated)", "cores": int(threads),
-               "kind": "oracle",
-               "sample": f"one bond visit's contractions (one environment update and the projected two-site "
-                         f"tensor, D={Dlr}, w={w}) timed in the oracle ({visit:.2f} s, numpy complex128, "
-                         f"{threads} BLAS threads), times the {4 * (Llr - 1)} visits of a step; the SVDs "
-                         f"are not included"}
+        th = ofit.theta_two_site(Lenv, M1, Wo, M2, Wo, Renv)
+        U, S, Vh, _ = ofit.svd_truncate(th.reshape(2 * Dmax, 2 * Dmax), Dmax, 1e-14)
+        ofit.env_left(Lenv, U.reshape(Dmax, 2, -1), Wo, M1)
+        t += time.perf_counter() - t0
+    per_visit = t / visits
+    info = threadpoolctl.threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info] + [1])
+    nv = 4 * (LR_L - 1)
+    return {"value": per_visit * nv, "unit": "s per time step (extrapolated, saturated bonds)",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"{visits} bond visits of the oracle at saturated bond dimension (D={Dmax}, w={w}, seeded "
+                      f"random environments and sites): projected two-site tensor, FP64 SVD truncation of the "
+                      f"{2 * Dmax}x{2 * Dmax} matrix, one environment update; {per_visit:.2f} s per visit "
+                      f"(numpy complex128, {threads} BLAS threads), times the {nv} visits of a step",
+            "sample_wall_s": t}
+
+
+def run_lr3(args, torch, mp, wl, h):
+    """The default line: K steps of the long-range Ising chain from all-up (see the module
+    docstring), FP32 products against plain FP64 on the same opening steps."""
+    from oracle import mpo as ompo
+    K, Wm = args.steps, args.warmup
+    prec = prec_of(mp, args.prec)
+    H = lr_blocks(wl)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, LR_ORDER, -1j * LR_TAU, mp.V2_EXTENDED)
+    w = W.shape[0]
+    dw = mp.DeviceMPO([W] * LR_L)
+    psi0 = wl.all_up(LR_L)
+    prog = "lr3" if args.progress else None
+    ns = args.nsites
+    if Wm:  # untimed warm-up steps of the same trajectory on their own state and workspace
+        trajectory(torch, mp, h, psi0, dw, prec, Wm, LR_D, progress=prog and prog + " warm-up", nsites=ns)
+    ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, K, LR_D, profile=True, progress=prog, nsites=ns)
+    sec = float(np.sum(ms)) / 1e3 / K
+    kt = kernel_table(st, args.prec)
+    prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile if k != "kernels"}
+    gemm_tf = prof["gemm_gflop"] / prof["t_gemm_ms"] if prof["t_gemm_ms"] > 0 else 0.0
+    Id = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
+    zops = [Id] * LR_L
+    zops[LR_SITE] = wl.SZ.reshape(1, 2, 2, 1)
+    dZ = mp.DeviceMPO(zops)
+    z_end = mp.expectation(h, dm, dZ).real
+    sat = [i for i, x in enumerate(st) if x.max_bond >= LR_D]
+    fp64 = None
+    if not args.no_fp64 and prec != mp.FP64:
+        n64 = max(1, min(args.fp64_steps or K, K))
+        ms64, st64, dm64 = trajectory(torch, mp, h, psi0, dw, mp.FP64, n64, LR_D, profile=True,
+                                      progress=prog and prog + " fp64", nsites=ns)
+        p64 = {k: float(sum(x.profile[k] for x in st64)) for k in st64[0].profile if k != "kernels"}
+        fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
+                "fp32_s_per_step_same_steps": float(np.sum(ms[:n64])) / 1e3 / n64,
+                "fp64_gemm_tflops": p64["gemm_gflop"] / p64["t_gemm_ms"] if p64["t_gemm_ms"] > 0 else 0.0,
+                "fp64_jacobi_share": p64["t_jacobi_ms"] / max(float(np.sum(ms64)), 1e-9),
+                "fp64_dominant_kernel": roofline_of(kernel_table(st64, "fp64")[0])}
+        fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / fp64["fp32_s_per_step_same_steps"]
+        if n64 == K:  # the two trajectories after the same K steps from psi0
+            a, b = dm.to_numpy(), dm64.to_numpy()
+            fp64["trajectory_infidelity_fp32_vs_fp64"] = float(1.0 - abs(_overlap(a, b)) ** 2 / (
+                abs(_overlap(a, a)) * abs(_overlap(b, b))))
+            fp64["Z50_end_fp32"] = z_end
+            fp64["Z50_end_fp64"] = mp.expectation(h, dm64, dZ).real
+            fp64["Z50_abs_diff"] = abs(fp64["Z50_end_fp32"] - fp64["Z50_end_fp64"])
+        del dm64
+        torch.cuda.empty_cache()
+    del dm
+    torch.cuda.empty_cache()
+    parity = cpu = None
+    if not args.no_cpu:
+        Wo = ompo.build_mpo(H, LR_ORDER, -1j * LR_TAU, "V2")
+        parity = lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, LR_D, delta2=not args.no_delta2)
+        cpu = lr3_cpu_baseline(Wo, wl, LR_D)
+    side = {} if args.no_side else {"quench_L64_D128": run_quench(args, torch, mp, wl, h, side=True),
+                                    "env_microbench": env_microbench_summary(mp, h, torch)}
     line = {
         "metric": "s per time step & TFLOP/s at D=256: FP32-MFMA grouped vs plain FP64, fidelity",
-        "value": sec, "unit": "s per time step", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "value": sec, "unit": "s per time step", "n_gpus": 1, "steps": K, "warmup": Wm,
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPES[args.prec], "data": "synthetic",
-        "config": {"workload": f"long-range Ising L={Llr}, J(r)=r^-2 as 6 exponentials, g=1, order-{order} "
-                               f"extended MPO (w={w}), tau={tau}, D={Dlr} saturated random MPS",
-                   "L": Llr, "D": Dlr, "order": order, "tau": tau},
-        "step_gflop": float(np.mean([x.gflop for x in st])),
-        "kernel_classes_timed_steps": {
-            "jacobi_svd_ms": prof["t_jacobi_ms"], "n_jacobi": prof["n_jacobi"],
-            "complex_gemm_ms": prof["t_gemm_ms"], "complex_gemm_gflop": prof["gemm_gflop"],
-            "complex_gemm_tflops": gemm_tf, "complex_gemm_frac_of_peak": gemm_tf * 1e12 / peak,
-            "w_contraction_ms": prof["t_wmix_ms"]},
+        "config": {"workload": f"long-range Ising L={LR_L}, J(r)=r^-2 as 6 exponentials, g=1, order-{LR_ORDER} "
+                               f"extended MPO (w={w}), tau={LR_TAU} (real time), D<={LR_D}, all-up start, "
+                               f"2 sweeps per step ({NSITES_DESC[ns]}), steps 1..{K} from t=0",
+                   "L": LR_L, "D": LR_D, "order": LR_ORDER, "tau": LR_TAU, "w": w},
+        "step_ms": ms,
+        "max_bond_per_step": [x.max_bond for x in st],
+        "one_site_steps": [i + 1 for i, x in enumerate(st) if x.visits == 4 * (LR_L - 1) + 1],
+        "discarded_sum_per_step": [x.discarded_sum for x in st],
+        "saturated_steps": len(sat),
+        "saturated_s_per_step": float(np.mean([ms[i] for i in sat])) / 1e3 if sat else None,
+        "step_tflop_mean": float(np.mean([x.gflop for x in st])) / 1e3,
+        "products_tflops": gemm_tf,
+        "products_frac_of_peak": gemm_tf * 1e12 / {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA,
+                                                   mp.BF16X3: PEAK_BF16_MFMA}[prec],
+        "class_ms_timed_steps": {"jacobi_svd": prof["t_jacobi_ms"], "complex_gemm": prof["t_gemm_ms"],
+                                 "w_contraction": prof["t_wmix_ms"], "all_steps": float(np.sum(ms))},
         "svd_sweeps_mean": float(np.mean([x.svd_sweeps_total / max(x.visits, 1) for x in st])),
+        "Z50_end": z_end,
+        "roofline": roofline_of(kt[0]),
+        "kernels_timed_steps": kt[:8],
         "fp64_path": fp64,
-        "bf16x3_path": bf,
+        "parity_vs_oracle": parity,
+        **side,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line))
+    print(json.dumps(line), flush=True)
+
+
+def env_microbench_summary(mp, h, torch):
+    mb32_ms, mb_flop = env_microbench(mp, h, torch, mp.FP32)
+    mb64_ms, _ = env_microbench(mp, h, torch, mp.FP64)
+    mbbf_ms, _ = env_microbench(mp, h, torch, mp.BF16X3)
+    tf32 = mb_flop / (mb32_ms * 1e-3) / 1e12
+    return {"D": 256, "d": 2, "w": 8, "flop_per_call": mb_flop,
+            "fp32_ms": mb32_ms, "fp32_tflops": tf32,
+            "fp32_frac_of_mfma_peak": tf32 * 1e12 / PEAK_FP32_MFMA,
+            "fp32_executed_frac_of_mfma_peak": 0.75 * tf32 * 1e12 / PEAK_FP32_MFMA,
+            "fp64_ms": mb64_ms, "fp64_tflops": mb_flop / (mb64_ms * 1e-3) / 1e12,
+            "fp64_frac_of_mfma_peak": mb_flop / (mb64_ms * 1e-3) / PEAK_FP64_MFMA,
+            "bf16x3_ms": mbbf_ms, "bf16x3_tflops": mb_flop / (mbbf_ms * 1e-3) / 1e12,
+            "bf16x3_frac_of_ceiling": mb_flop / (mbbf_ms * 1e-3) / CEIL_BF16X3}
 
 
 def run_env(args, torch, mp, h):
     """The environment-update microbenchmark alone: FP32 (three real products per complex
     multiply-add on the fp32 matrix cores), plain FP64 and split-BF16x3, K calls each."""
-    reps = max(1, args.steps)
+    reps = max(1, args.steps or 100)
     res = {}
     for name in ("fp32", "fp64", "bf16x3"):
         ms, flop = env_microbench(mp, h, torch, prec_of(mp, name), reps=reps)
@@ -256,7 +430,7 @@ def _overlap(a, b) -> complex:
 def run_split(args, torch, mp, wl, h):
     """K quench steps (default 20) from the g = 0.5 ground state with the splitting composite
     O1(t1 tau) O1(t2 tau) (Sec. 8.3) and with the order-2 MPO, each step timed with HIP events."""
-    steps = args.steps if args.steps != 100 else 20
+    steps = args.steps or 20
     prec = prec_of(mp, args.prec)
     psi0 = load_ground()
     H = wl.tfim(G_AFTER)
@@ -311,7 +485,7 @@ def run_split(args, torch, mp, wl, h):
 
 def run_thermal(args, torch, mp, wl, h):
     """Imaginary-time steps of the purified L = 64 TFIM (g = 1) from beta = 0, FP32 and FP64."""
-    steps = args.steps if args.steps != 100 else 20
+    steps = args.steps or 20
     delta, g = 0.05, 1.0
     H = wl.tfim(g)
     W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -delta, mp.V2_EXTENDED)
@@ -423,7 +597,7 @@ def run_batched(args, torch, mp, wl, h):
     {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up: step_batched
     against the same chains stepped one by one, and the oracle on the first chains' first step."""
     chains = wl.batched_tfim_chains(2, 64)
-    steps = args.steps if args.steps != 100 else 3
+    steps = args.steps or 3
     prec = prec_of(mp, args.prec)
     mpos = {}
     for g, Lc, _ in chains:
@@ -463,12 +637,14 @@ def run_batched(args, torch, mp, wl, h):
     parity, cpu = None, None
     if not args.no_cpu:
         from oracle import fit as ofit
+        from oracle import mpo as ompo
         import threadpoolctl
         parity = []
         t0 = time.perf_counter()
         for c in range(4):
             g, Lc, Dc = chains[c]
-            ref, _ = ofit.fit_step(wl.all_up(Lc), mpos[g], Dmax=Dc, nsweeps=2)
+            ref, _ = ofit.fit_step(wl.all_up(Lc), ompo.build_mpo(wl.tfim(g), 2, -1j * TAU, "V2"), Dmax=Dc,
+                                   nsweeps=2)
             parity.append({"chain": c, "L": Lc, "D": Dc, "g": g,
                            "step1_infidelity": float(1.0 - abs(ofit.overlap(first_b[c], ref)) ** 2),
                            "batched_vs_one_by_one_max_abs": float(max(np.max(np.abs(a - b)) for a, b in
@@ -500,23 +676,101 @@ def run_batched(args, torch, mp, wl, h):
     print(json.dumps(line))
 
 
+def run_quench(args, torch, mp, wl, h, side=False):
+    """The L = 64 TFIM quench (g = 0.5 -> 1.5) from t = 0: K steps on the chosen path and the same
+    steps on the plain FP64 path, first-step parity against the oracle (R17-A and R17-B), the
+    dominant kernel. side=True: steps 1..20 on the FP32 path, returned as a dict."""
+    from oracle import fit as ofit
+    from oracle import mpo as ompo
+    steps = 20 if side else (args.steps or 100)
+    prec = mp.FP32 if side else prec_of(mp, args.prec)
+    pname = "fp32" if side else args.prec
+    psi0 = load_ground()
+    H = wl.tfim(G_AFTER)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -1j * TAU, mp.V2_EXTENDED)
+    dw = mp.DeviceMPO([W] * L)
+    prog = ("quench" if args.progress else None)
+    if not side and args.warmup:
+        trajectory(torch, mp, h, psi0, dw, prec, args.warmup, D)
+    ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, steps, D, profile=True, progress=prog)
+    sec = float(np.sum(ms)) / 1e3 / steps
+    kt = kernel_table(st, pname)
+    Id = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
+    zops = [Id] * L
+    zops[31] = wl.SZ.reshape(1, 2, 2, 1)
+    dZ = mp.DeviceMPO(zops)
+    out = {"workload": f"TFIM quench L={L} from the g=0.5 ground state to g={G_AFTER}, order-{ORDER} extended "
+                       f"MPO (w={W.shape[0]}), tau={TAU}, D<={D}, steps 1..{steps} from t=0",
+           "s_per_step": sec, "steps": steps, "max_bond_last_step": st[-1].max_bond,
+           "dominant_kernel": roofline_of(kt[0])}
+    if (side or not args.no_fp64) and prec != mp.FP64:
+        ms64, _, dm64 = trajectory(torch, mp, h, psi0, dw, mp.FP64, steps, D)
+        a, b = dm.to_numpy(), dm64.to_numpy()
+        out["fp64_s_per_step"] = float(np.sum(ms64)) / 1e3 / steps
+        out["fp32_speedup"] = out["fp64_s_per_step"] / sec
+        out["trajectory_infidelity_fp32_vs_fp64"] = float(1.0 - abs(_overlap(a, b)) ** 2 / (
+            abs(_overlap(a, a)) * abs(_overlap(b, b))))
+        out["Z32_abs_diff_fp32_vs_fp64"] = abs(mp.expectation(h, dm, dZ).real - mp.expectation(h, dm64, dZ).real)
+        del dm64
+    del dm
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        Wo = ompo.build_mpo(H, ORDER, -1j * TAU, "V2")
+        ref, rinfo = ofit.fit_step(psi0, Wo, Dmax=D)
+        n2 = ofit.applied_norm2(psi0, Wo)
+        eps_or = 1.0 - rinfo["norm"] ** 2 / n2
+        z_or = ofit.expect_local(ref, wl.SZ, 31).real
+        par = {}
+        for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64), ("bf16x3", mp.BF16X3)):
+            dm1 = mp.DeviceMPS(psi0, Dmax=D)
+            s1 = mp.step(h, dm1, dw, prec=p)
+            o = dm1.to_numpy()
+            par[name] = {"infidelity_R17A": float(1.0 - abs(ofit.overlap(o, ref)) ** 2),
+                         "eps_excess_R17B": float(abs(1.0 - s1.norm ** 2 / n2 - eps_or)),
+                         "Z32_error": float(abs(ofit.expect_local(o, wl.SZ, 31).real - z_or)),
+                         "norm_rel_error": float(abs(s1.norm - rinfo["norm"]) / rinfo["norm"])}
+        out["step1_parity_vs_oracle"] = par
+    if side:
+        return out
+    print(json.dumps({
+        "metric": "s per time step, TFIM quench L=64 (configuration 2)",
+        "value": sec, "unit": "s per time step", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[args.prec], "data": "synthetic",
+        "config": {"workload": out["workload"], "L": L, "D": D, "order": ORDER, "tau": TAU},
+        "step_ms": ms, "roofline": out["dominant_kernel"], "kernels_timed_steps": kt[:8],
+        **{k: v for k, v in out.items() if k not in ("workload", "dominant_kernel")}}), flush=True)
+
+
 def main():
     global ORDER, TAU
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 for lr3, 100 for quench, 3 for batched, 20 for split/thermal, "
+                         "100 calls for env)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed warm-up steps (default 2; 1 for quench)")
     ap.add_argument("--prec", choices=["fp32", "fp64", "bf16x3"], default="fp32")
-    ap.add_argument("--fp64-steps", type=int, default=20, help="opening steps run on the FP64 path too")
+    ap.add_argument("--fp64-steps", type=int, default=None, help="opening steps run on the FP64 path too (default: all)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--workload", choices=["quench", "lr3", "batched", "env", "split", "thermal", "cylinder"], default="quench")
-    ap.add_argument("--progress", action="store_true", help="print a line to stderr every 10 timed steps")
+    ap.add_argument("--no-delta2", action="store_true", help="lr3: skip the step-2 parity from the oracle state")
+    ap.add_argument("--no-side", action="store_true", help="lr3: skip the quench and microbenchmark side fields")
+    ap.add_argument("--nsites", type=int, default=-1, choices=[-1, 1, 2],
+                    help="lr3: local update (2: two-site; 1: one-site at fixed bonds; -1: two-site while the "
+                         "bonds grow, one-site once all are at their largest value)")
+    ap.add_argument("--workload", choices=["lr3", "quench", "batched", "env", "split", "thermal", "cylinder"],
+                    default="lr3")
+    ap.add_argument("--progress", action="store_true", help="print a line to stderr after every timed step")
     ap.add_argument("--order", type=int, default=ORDER, choices=[1, 2, 3, 4],
                     help="MPO order of the TFIM workloads (quench, split reference, thermal)")
     ap.add_argument("--tau", type=float, default=TAU, help="time step of the quench and split workloads")
     args = ap.parse_args()
     ORDER, TAU = args.order, args.tau
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "quench" else 2
+    if args.workload == "lr3" and args.steps is None:
+        args.steps = 20
     if args.workload == "batched":
         # more hardware queues and worker streams let more chains' truncations overlap (read by
         # the HIP runtime at initialisation and by the library at each batched step)
@@ -536,225 +790,11 @@ def main():
     h = mp.Handle(0)
     if args.workload == "env":
         run_env(args, torch, mp, h)
-        h.close()
-        return
-    if args.workload in ("split", "thermal", "cylinder"):
-        {"split": run_split, "thermal": run_thermal, "cylinder": run_cylinder}[args.workload](args, torch, mp, wl, h)
-        h.close()
-        return
-    if args.workload in ("lr3", "batched"):
-        (run_lr3 if args.workload == "lr3" else run_batched)(args, torch, mp, wl, h)
-        h.close()
-        return
-    prec = prec_of(mp, args.prec)
-    psi0 = load_ground()
-    H = wl.tfim(G_AFTER)
-    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -1j * TAU, mp.V2_EXTENDED)
-    dw = mp.DeviceMPO([W] * L)
-
-    def quench(p, steps, warmup, profile=False):
-        """Per-step milliseconds of `steps` quench steps from psi0 (events on the default stream);
-        with `profile` every step also times its kernel classes with HIP events."""
-        if warmup:
-            dm = mp.DeviceMPS(psi0, Dmax=D)
-            wsw = mp.step_workspace(dm, dw, p)
-            for k in range(warmup):
-                mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=wsw)
-            torch.cuda.synchronize()
-            del wsw
-        dm = mp.DeviceMPS(psi0, Dmax=D)
-        ws = torch.empty_like(mp.step_workspace(dm, dw, p))
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-        st = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev[0].record()
-        for k in range(steps):
-            st.append(mp.step(h, dm, dw, prec=p, input_right_canonical=k > 0, workspace=ws,
-                              profile=profile))
-            ev[k + 1].record()
-            if args.progress and k % 10 == 9:
-                print(f"[bench] step {k + 1}/{steps}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
-        return ms, wall, st, dm
-
-    # the timed steps time the Jacobi kernel only (HIP events around each launch, on its stream):
-    # events around every kernel class would add a few per cent of host work to the steps
-    ms, wall, st, dm_end = quench(prec, args.steps, args.warmup, profile=mp.PROFILE_JACOBI)
-    sec_step = float(np.sum(ms)) / 1e3 / args.steps
-    gflop = float(np.mean([x.gflop for x in st]))
-
-    def class_table(prof):
-        classes = {
-            "jacobi_svd": {"ms": prof["t_jacobi_ms"], "launches": prof["n_jacobi"], "work": prof["jacobi_gflop"],
-                           "work_unit": "GFLOP", "bound": "alu", "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"},
-            "complex_gemm": {"ms": prof["t_gemm_ms"], "launches": prof["n_gemm"], "work": prof["gemm_gflop"],
-                             "work_unit": "GFLOP", "bound": "mfma",
-                             "peak": {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA,
-                                      mp.BF16X3: CEIL_BF16X3}[prec] / 1e12, "unit": "TFLOP/s"},
-            "w_contraction": {"ms": prof["t_wmix_ms"], "launches": prof["n_wmix"], "work": prof["wmix_gbyte"],
-                              "work_unit": "GB", "bound": "hbm", "peak": PEAK_HBM / 1e9, "unit": "GB/s"},
-        }
-        for c in classes.values():
-            c["achieved"] = c["work"] / (c["ms"] * 1e-3) / (1e3 if c["unit"] == "TFLOP/s" else 1.0) if c["ms"] > 0 else 0.0
-            c["frac"] = c["achieved"] / c["peak"] if c["peak"] else 0.0
-            c["avg_launch_us"] = 1e3 * c["ms"] / max(c["launches"], 1)
-        return classes
-
-    # the Jacobi kernel summed over the timed steps (the dominant kernel: the roofline below)
-    prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile}
-    classes = {"jacobi_svd": class_table(prof)["jacobi_svd"]}
-    dominant = "jacobi_svd"
-
-    # diagnostics of the trajectory on the device (FP64): energy of H(g = 1.5), conserved by the
-    # exact evolution, and <Z_32>, at t = 0 and after the last timed step
-    Hm = np.zeros((3, 2, 2, 3), dtype=np.complex128)
-    Hm[0, :, :, 0] = Hm[2, :, :, 2] = np.eye(2)
-    Hm[0, :, :, 1], Hm[1, :, :, 2], Hm[0, :, :, 2] = H.C[0], H.B[0], H.Dloc
-    dH = mp.DeviceMPO([Hm] * L)
-    Id = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
-    zops = [Id] * L
-    zops[31] = wl.SZ.reshape(1, 2, 2, 1)
-    dZ = mp.DeviceMPO(zops)
-    dm0 = mp.DeviceMPS(psi0, Dmax=D)
-    diag = {"energy_t0": mp.expectation(h, dm0, dH, 0, 2).real,
-            "energy_end": mp.expectation(h, dm_end, dH, 0, 2).real,
-            "Z32_t0": mp.expectation(h, dm0, dZ).real,
-            "Z32_end": mp.expectation(h, dm_end, dZ).real,
-            "t_end": TAU * args.steps}
-    diag["energy_drift_per_site"] = (diag["energy_end"] - diag["energy_t0"]) / L
-    del dm0, dm_end
-
-    # the plain FP64 path on the same opening steps
-    fp64 = None
-    if not args.no_fp64 and prec == mp.FP32:
-        n64 = max(1, min(args.fp64_steps, args.steps))
-        ms64, _, _, dm64 = quench(mp.FP64, n64, 0, profile=True)
-        fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
-                "fp32_s_per_step": float(np.sum(ms[:n64])) / 1e3 / n64}
-        fp64["fp32_speedup"] = fp64["fp64_s_per_step"] / fp64["fp32_s_per_step"]
-        # the FP32 and FP64 trajectories after the same n64 steps from psi0
-        _, _, _, dm32n = quench(mp.FP32, n64, 0)
-        a, b = dm32n.to_numpy(), dm64.to_numpy()
-        fp64["trajectory_infidelity_fp32_vs_fp64"] = 1.0 - abs(_overlap(a, b)) ** 2 / (
-            abs(_overlap(a, a)) * abs(_overlap(b, b)))
-        fp64["Z32_after_steps_fp32"] = mp.expectation(h, dm32n, dZ).real
-        fp64["Z32_after_steps_fp64"] = mp.expectation(h, dm64, dZ).real
-
-    # one step at saturated bond dimension (seeded random MPS, D = 128 on every bulk bond), after
-    # two steps that leave the truncations' preconditioners in the workspace
-    # (a fourth step, timing every kernel class, gives the breakdown of a saturated step)
-    rnd = wl.random_mps(np.random.default_rng(0), L, 2, D)
-
-    def saturated_step(p, breakdown=False):
-        dmr = mp.DeviceMPS(rnd, Dmax=D)
-        wsr = mp.step_workspace(dmr, dw, p)
-        mp.step(h, dmr, dw, prec=p, workspace=wsr)
-        mp.step(h, dmr, dw, prec=p, input_right_canonical=True, workspace=wsr)
-        torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        mp.step(h, dmr, dw, prec=p, input_right_canonical=True, workspace=wsr)
-        e.record()
-        torch.cuda.synchronize()
-        t = s.elapsed_time(e) / 1e3
-        if not breakdown:
-            return t, None
-        sp = mp.step(h, dmr, dw, prec=p, input_right_canonical=True, workspace=wsr, profile=True)
-        torch.cuda.synchronize()
-        return t, class_table(sp.profile)
-
-    sat_s, sat_classes = saturated_step(prec, breakdown=True)
-    if fp64 is not None:  # the same saturated step on the plain FP64 path
-        fp64["saturated_fp64_s_per_step"] = saturated_step(mp.FP64)[0]
-        fp64["saturated_fp32_s_per_step"] = sat_s
-        fp64["saturated_fp32_speedup"] = fp64["saturated_fp64_s_per_step"] / sat_s
-
-    mb32_ms, mb_flop = env_microbench(mp, h, torch, mp.FP32)
-    mb64_ms, _ = env_microbench(mp, h, torch, mp.FP64)
-    mbbf_ms, _ = env_microbench(mp, h, torch, mp.BF16X3)
-    d256 = None if args.no_fp64 else run_lr3(args, torch, mp, wl, h, steps=1, warmup=1, embedded=True)
-
-    # parity of the first step from psi0 against the oracle, and the CPU baseline
-    cpu = None
-    parity = None
-    if not args.no_cpu:
-        from oracle import fit as ofit
-        import threadpoolctl
-        ref, rinfo = ofit.fit_step(psi0, W, Dmax=D, nsweeps=2)
-        parity = {}
-        for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64), ("bf16x3", mp.BF16X3)):
-            dm1 = mp.DeviceMPS(psi0, Dmax=D)
-            s1 = mp.step(h, dm1, dw, prec=p)
-            out = dm1.to_numpy()
-            parity[name] = {
-                "step1_infidelity": float(1.0 - abs(ofit.overlap(out, ref)) ** 2),
-                "step1_Z32_error": float(abs(ofit.expect_local(out, wl.SZ, 31) - ofit.expect_local(ref, wl.SZ, 31))),
-                "step1_norm_rel_error": float(abs(s1.norm - rinfo["norm"]) / rinfo["norm"]),
-            }
-        info = threadpoolctl.threadpool_info()
-        threads = max([i.get("num_threads", 1) for i in info] + [1])
-        t0 = time.perf_counter()
-        ofit.fit_step(rnd, W, Dmax=D, nsweeps=2)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": cpu_s, "unit": "s per time step", "cores": int(threads), "kind": "oracle",
-               "sample": f"one time step at saturated bond dimension (seeded random MPS, L={L}, D={D} on "
-                         f"every bulk bond, order {ORDER}, 2 sweeps, including its right-canonicalisation), "
-                         f"numpy complex128 with {threads} BLAS threads on {os.cpu_count()} host cores; "
-                         f"the GPU takes gpu_saturated_step_s for the same step",
-               "gpu_saturated_step_s": sat_s}
-
-    mb_tflops = mb_flop / (mb32_ms * 1e-3) / 1e12
-    phases = {}
-    for lo, hi in ((0, 20), (20, 40), (40, args.steps)):
-        if hi > lo and lo < args.steps:
-            seg = ms[lo:min(hi, args.steps)]
-            phases[f"steps_{lo + 1}_{min(hi, args.steps)}_ms"] = float(np.mean(seg))
-    line = {
-        "metric": "s per time step & TFLOP/s at D=256: FP32-MFMA grouped vs plain FP64, fidelity",
-        "value": sec_step,
-        "unit": "s per time step",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec_step * 1e3,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": DTYPES[args.prec],
-        "data": "synthetic",
-        "config": {"workload": f"TFIM quench L={L} from the g=0.5 ground state to g={G_AFTER}, order-{ORDER} "
-                               f"extended MPO (w={W.shape[0]}), tau={TAU}, D<={D}, 2 sweeps per step, "
-                               f"steps 1..{args.steps} from t=0",
-                   "L": L, "D": D, "order": ORDER, "tau": TAU},
-        "wall_s_per_step": wall / args.steps,
-        "phase_ms_per_step": phases,
-        "max_bond_last_step": int(st[-1].max_bond),
-        "discarded_sum_last_step": float(st[-1].discarded_sum),
-        "step_gflop_mean": gflop,
-        "svd_sweeps_mean": float(np.mean([x.svd_sweeps_total / max(x.visits, 1) for x in st])),
-        "fp64_path": fp64,
-        "diagnostics_device": diag,
-        "gpu_saturated_step_s": sat_s,
-        "parity_vs_oracle": parity,
-        "d256_long_range": d256,
-        "env_microbench": {"D": 256, "d": 2, "w": 8, "fp32_ms": mb32_ms, "fp64_ms": mb64_ms,
-                           "fp32_tflops": mb_tflops, "fp64_tflops": mb_flop / (mb64_ms * 1e-3) / 1e12,
-                           "fp32_frac_of_mfma_peak": mb_tflops * 1e12 / PEAK_FP32_MFMA,
-                           "fp64_frac_of_mfma_peak": mb_flop / (mb64_ms * 1e-3) / PEAK_FP64_MFMA,
-                           "bf16x3_ms": mbbf_ms, "bf16x3_tflops": mb_flop / (mbbf_ms * 1e-3) / 1e12,
-                           "bf16x3_frac_of_ceiling": mb_flop / (mbbf_ms * 1e-3) / CEIL_BF16X3},
-        "roofline": {"bound": classes[dominant]["bound"], "kernel": dominant,
-                     "achieved": classes[dominant]["achieved"], "peak": classes[dominant]["peak"],
-                     "unit": classes[dominant]["unit"], "frac": classes[dominant]["frac"],
-                     "avg_launch_us": classes[dominant]["avg_launch_us"], "traffic": None},
-        "kernel_classes_timed_steps": classes,
-        "kernel_classes_saturated_step": sat_classes,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line))
+    elif args.workload == "quench":
+        run_quench(args, torch, mp, wl, h)
+    else:
+        {"lr3": run_lr3, "batched": run_batched, "split": run_split, "thermal": run_thermal,
+         "cylinder": run_cylinder}[args.workload](args, torch, mp, wl, h)
     h.close()
 
 
