@@ -202,6 +202,20 @@ typedef struct {
   int L, d, Dmax;
   int* bond_dim;
   void** site;
+  /* U(1) symmetry (nullable; both or neither): sector_table[b * Dmax + j], j < bond_dim[b], is the
+     charge of index j of bond b, nondecreasing in j (the site tensors' bond indices sorted by
+     charge), and phys_charge[s] that of physical index s. The site tensors must vanish unless
+     q(b) = q(a) + phys_charge[s] (a U(1)-symmetric MPS stored densely in charge order) and the MPO
+     must conserve the charge (W[alpha][s'][s][beta] = 0 unless l(alpha) + q(s') = q(s) + l(beta)
+     for some level charges l, as mpo_build's level_charge_out gives). step then runs the U(1)
+     two-site fit (Sec. 2.4 example; symmetric tensors): every truncation, and the canonical
+     guess, factorises each charge block of the bond matrix by its own FP64 SVD and keeps the
+     Dmax largest singular values over all blocks (k = min(Dmax, #{sigma > cutoff sigma_max}),
+     ties to the lower charge), so the new bond's indices come sorted by charge; the contractions
+     are the dense ones (they keep the vanishing blocks exactly zero). The tables of bonds 1..L-1
+     are rewritten in place. Two-site updates only (nsites 1 gives EUNSUPPORTED, -1 means 2). */
+  int* sector_table;
+  const int* phys_charge;
 } mpoevo_mps;
 
 typedef struct {
@@ -360,6 +374,20 @@ int mpoevo_set_tuning(mpoevo_handle h, int mode, int clear);
  */
 int mpoevo_product_plan(mpoevo_handle h, int prec, int M, int N, int K, int batch, int* plan,
                         int* entries);
+
+/*
+ * overlap -- <bra| O |ket> for an MPO O = l . O_1 ... O_L . r (boundary levels as for expectation)
+ * and two MPS on the same chain (their bond dimensions may differ): FP64 throughout, by the left
+ * environment recursion E <- E . ket_i . O_i . conj(bra_i). The norms and overlaps of the method
+ * (Sec. 8.2: fidelities of the evolved state) in double precision whatever the contraction
+ * precision of the step that produced the states: with O the evolution MPO, ket = psi and bra the
+ * normalised fitted phi, |<phi|W psi>|^2 / ||W psi||^2 = 1 - the step's truncation error.
+ *   out   device complex128 (two doubles), written on `stream`; no synchronisation.
+ * Workspace: mpoevo_workspace_size(MPOEVO_CALL_EXPECTATION, dims = {L, d, max(bra Dmax, ket Dmax),
+ * wmax}, FP64). Errors: as expectation (either MPS).
+ */
+int overlap(mpoevo_handle h, const mpoevo_mps* bra, const mpoevo_mpo* mpo, const mpoevo_mps* ket, int left,
+            int right, void* out, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Workspace sizes in bytes for the device calls (dims as documented for each call). */
 enum { MPOEVO_CALL_ENV_UPDATE = 0, MPOEVO_CALL_LOCAL_APPLY = 1, MPOEVO_CALL_TRUNCATE = 2,

@@ -2,6 +2,7 @@
 // This translation unit includes no HIP or POSIX headers (the ABI exports a function named
 // `truncate`, which must not meet the libc declaration of the same name).
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -226,6 +227,14 @@ int check_chain(mpoevo::Context* ctx, const std::string& who, const mpoevo_mps* 
   }
   for (int i = 0; i < L; ++i)
     if (!mps->site[i] || !mpo->site[i]) return fail(ctx, MPOEVO_EINVAL, who + ": NULL site pointer");
+  if ((mps->sector_table == nullptr) != (mps->phys_charge == nullptr))
+    return fail(ctx, MPOEVO_EINVAL, who + ": give both sector_table and phys_charge or neither");
+  if (mps->sector_table) {
+    for (int b = 0; b <= L; ++b)
+      for (int j = 1; j < mps->bond_dim[b]; ++j)
+        if (mps->sector_table[(size_t)b * Dmax + j] < mps->sector_table[(size_t)b * Dmax + j - 1])
+          return fail(ctx, MPOEVO_EINVAL, who + ": sector_table must be nondecreasing within each bond");
+  }
   return MPOEVO_OK;
 }
 
@@ -249,6 +258,8 @@ int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_s
   if (int rc = check_chain(ctx, "step", mps, mpo, &wmax); rc != MPOEVO_OK) return rc;
   if (workspace_bytes < mpoevo::step_ws(mps->L, mps->d, mps->Dmax, wmax, opts->prec) || !workspace)
     return fail(ctx, MPOEVO_ENOMEM, "step: workspace too small");
+  if (mps->sector_table && opts->nsites == 1)
+    return fail(ctx, MPOEVO_EUNSUPPORTED, "step: one-site updates of U(1) chains are not built");
   return mpoevo::step_dev(*ctx, mps, mpo, opts, stats, workspace, workspace_bytes, stream);
 }
 
@@ -301,6 +312,45 @@ int expectation(mpoevo_handle h, const mpoevo_mps* mps, const mpoevo_mpo* mpo, i
   if (!workspace || workspace_bytes < mpoevo::expectation_ws(L, d, Dmax, wmax))
     return fail(ctx, MPOEVO_ENOMEM, "expectation: workspace too small");
   return mpoevo::expectation_dev(*ctx, mps, mpo, left, right, out, workspace, workspace_bytes, stream);
+}
+
+namespace {
+int check_measured(mpoevo::Context* ctx, const char* who, const mpoevo_mps* mps, const mpoevo_mpo* mpo,
+                   int* wmax) {
+  const std::string w_ = who;
+  if (!mps || !mpo || !mps->bond_dim || !mps->site || !mpo->w || !mpo->site)
+    return fail(ctx, MPOEVO_EINVAL, w_ + ": NULL argument");
+  const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
+  if (L < 1 || d < 1 || Dmax < 1 || mpo->L != L || mpo->d != d)
+    return fail(ctx, MPOEVO_ESHAPE, w_ + ": need L >= 1 and matching L, d of MPS and MPO");
+  if (mps->bond_dim[0] != 1 || mps->bond_dim[L] != 1) return fail(ctx, MPOEVO_ESHAPE, w_ + ": boundary bonds must be 1");
+  *wmax = 0;
+  for (int i = 0; i <= L; ++i) {
+    if (i > 0 && i < L && (mps->bond_dim[i] < 1 || mps->bond_dim[i] > Dmax))
+      return fail(ctx, MPOEVO_ESHAPE, w_ + ": MPS bond dimension outside 1..Dmax");
+    if (mpo->w[i] < 1) return fail(ctx, MPOEVO_ESHAPE, w_ + ": MPO bond dimension < 1");
+    if (mpo->w[i] > *wmax) *wmax = mpo->w[i];
+  }
+  for (int i = 0; i < L; ++i)
+    if (!mps->site[i] || !mpo->site[i]) return fail(ctx, MPOEVO_EINVAL, w_ + ": NULL site pointer");
+  return MPOEVO_OK;
+}
+}  // namespace
+
+int overlap(mpoevo_handle h, const mpoevo_mps* bra, const mpoevo_mpo* mpo, const mpoevo_mps* ket, int left,
+            int right, void* out, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!h) return fail(nullptr, MPOEVO_EINVAL, "overlap: NULL handle");
+  auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
+  if (!out) return fail(ctx, MPOEVO_EINVAL, "overlap: NULL argument");
+  int wb = 0, wk = 0;
+  if (int rc = check_measured(ctx, "overlap", bra, mpo, &wb); rc != MPOEVO_OK) return rc;
+  if (int rc = check_measured(ctx, "overlap", ket, mpo, &wk); rc != MPOEVO_OK) return rc;
+  if (left < 0 || left >= mpo->w[0] || right < 0 || right >= mpo->w[ket->L])
+    return fail(ctx, MPOEVO_EINVAL, "overlap: boundary level out of range");
+  const int Dmax = std::max(bra->Dmax, ket->Dmax);
+  if (!workspace || workspace_bytes < mpoevo::expectation_ws(ket->L, ket->d, Dmax, wk))
+    return fail(ctx, MPOEVO_ENOMEM, "overlap: workspace too small");
+  return mpoevo::overlap_dev(*ctx, bra, mpo, ket, left, right, out, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

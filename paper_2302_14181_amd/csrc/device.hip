@@ -417,6 +417,169 @@ double qr_flop(int m, int n) {
   return 2.0 * (8.0 * mm * nn * nn - 8.0 / 3.0 * nn * nn * nn);
 }
 
+// ------------------------------------------------------------- U(1): truncation per charge block
+// out (mq x nq, row-major) = X[rows[i]][cols[j]] (X row pitch n).
+__global__ void gather_block(const double2* __restrict__ X, int n, const int* __restrict__ rows, int mq,
+                             const int* __restrict__ cols, int nq, double2* __restrict__ out) {
+  const long long total = (long long)mq * nq;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / nq), j = (int)(idx % nq);
+    out[idx] = X[(long long)rows[i] * n + cols[j]];
+  }
+}
+
+// A[rows[i]][off + j] = AQ[i][j], i < mq, j < kq (AQ row pitch pa, A row pitch lda).
+__global__ void scatter_block_cols(const double2* __restrict__ AQ, int pa, int mq, int kq,
+                                   const int* __restrict__ rows, double2* __restrict__ A, int lda, int off) {
+  const long long total = (long long)mq * kq;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / kq), j = (int)(idx % kq);
+    A[(long long)rows[i] * lda + off + j] = AQ[(long long)i * pa + j];
+  }
+}
+
+// B[off + j][cols[c]] = BQ[j][c], j < kq, c < nq (BQ row pitch nq, B row pitch ldb).
+__global__ void scatter_block_rows(const double2* __restrict__ BQ, int nq, int kq,
+                                   const int* __restrict__ cols, double2* __restrict__ B, int ldb, int off) {
+  const long long total = (long long)kq * nq;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / nq), c = (int)(idx % nq);
+    B[(long long)(off + j) * ldb + cols[c]] = BQ[idx];
+  }
+}
+
+__global__ void fill_zero_c128(double2* x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = double2{0.0, 0.0};
+}
+
+// Scratch of a blocked truncation of an m x n matrix with m, n <= dim.
+size_t blocked_scratch_bytes(int dim) {
+  const size_t mn = (size_t)dim * dim;
+  return 3 * a256(sizeof(double2) * mn) + a256(sizeof(int) * 2 * (size_t)dim) + a256(sizeof(double) * dim) +
+         a256((sizeof(int) + 2 * sizeof(double)) * (size_t)dim);
+}
+
+struct BlockedResult {
+  int k = 0;
+  double disc = 0.0, norm = 0.0;
+  std::vector<int> charges;  // of the kept indices, nondecreasing
+};
+
+// X (m x n, row-major, complex128) vanishes unless rq[r] == cq[c]: block diagonal by charge. Each
+// charge block gets its own FP64 SVD (the truncation kernels, keeping everything above the
+// rounding floor); the Dmax largest singular values over all blocks are kept (k = min(Dmax,
+// #{sigma > cutoff sigma_max}) >= 1, ties to the lower charge, then the earlier value), and the
+// factors are written densely with the kept indices in charge order: direction LEFT A = U
+// (m x k), B = S V^dag (k x n); RIGHT A = U S, B = V^dag. One stream synchronisation (the host
+// selects the kept values).
+hipError_t blocked_truncate(Context& ctx, const double2* X, int m, int n, const std::vector<int>& rq,
+                            const std::vector<int>& cq, int Dmax, double cutoff, int direction,
+                            double2* A, double2* B, unsigned char* scratch, int dim, void* svdws,
+                            hipStream_t st, BlockedResult& res) {
+  std::map<int, std::vector<int>> rows, cols;
+  for (int r = 0; r < m; ++r) rows[rq[r]].push_back(r);
+  for (int c = 0; c < n; ++c) cols[cq[c]].push_back(c);
+  struct Blk { int q, mq, nq, kcap; size_t xo, ao, bo, so, io; int kq = 0, off = 0; };
+  std::vector<Blk> blks;
+  std::vector<int> idx;
+  size_t xo = 0, ao = 0, bo = 0, so = 0;
+  for (const auto& kv : rows) {
+    auto it = cols.find(kv.first);
+    if (it == cols.end()) continue;
+    Blk b{kv.first, (int)kv.second.size(), (int)it->second.size(), 0, xo, ao, bo, so, idx.size()};
+    b.kcap = std::min(b.mq, b.nq);
+    idx.insert(idx.end(), kv.second.begin(), kv.second.end());
+    idx.insert(idx.end(), it->second.begin(), it->second.end());
+    xo += (size_t)b.mq * b.nq;
+    ao += (size_t)b.mq * b.kcap;
+    bo += (size_t)b.kcap * b.nq;
+    so += b.kcap;
+    blks.push_back(b);
+  }
+  if (blks.empty()) return hipErrorInvalidValue;
+  const size_t mn = (size_t)dim * dim;
+  double2* xq = reinterpret_cast<double2*>(scratch);
+  double2* aq = reinterpret_cast<double2*>(scratch + a256(sizeof(double2) * mn));
+  double2* bq = reinterpret_cast<double2*>(scratch + 2 * a256(sizeof(double2) * mn));
+  unsigned char* rest = scratch + 3 * a256(sizeof(double2) * mn);
+  int* idx_dev = reinterpret_cast<int*>(rest);
+  double* sig = reinterpret_cast<double*>(rest + a256(sizeof(int) * 2 * (size_t)dim));
+  unsigned char* tail = rest + a256(sizeof(int) * 2 * (size_t)dim) + a256(sizeof(double) * dim);
+  int* kd = reinterpret_cast<int*>(tail);
+  double* dd = reinterpret_cast<double*>(tail + a256(sizeof(int) * (size_t)dim));
+  double* nd = dd + dim;
+  MPOEVO_HIP_TRY(hipMemcpyAsync(idx_dev, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, st));
+  for (size_t t = 0; t < blks.size(); ++t) {
+    const Blk& b = blks[t];
+    const int* r_dev = idx_dev + b.io;
+    const int* c_dev = r_dev + b.mq;
+    hipLaunchKernelGGL(gather_block, dim3(grid_for((long long)b.mq * b.nq)), dim3(256), 0, st, X, n, r_dev, b.mq,
+                       c_dev, b.nq, xq + b.xo);
+    MPOEVO_HIP_TRY(hipGetLastError());
+    const SvdPlan pl = svd_qr_ok(b.mq, b.nq, direction) ? svd_plan_qr(b.mq, b.nq, direction)
+                                                         : svd_plan(b.mq, b.nq, direction);
+    MPOEVO_HIP_TRY(svd_truncate(pl, xq + b.xo, b.kcap, 0.0, aq + b.ao, bq + b.bo, kd + t, dd + t, nd + t,
+                                sig + b.so, svdws, ctx.dev->status, st, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, ctx.coop_jacobi));
+  }
+  std::vector<double> sh(so);
+  MPOEVO_HIP_TRY(hipMemcpyAsync(sh.data(), sig, sizeof(double) * so, hipMemcpyDeviceToHost, st));
+  MPOEVO_HIP_TRY(hipStreamSynchronize(st));
+  struct Cand { double s; int t, j; };
+  std::vector<Cand> cand;
+  double tot = 0.0;
+  for (size_t t = 0; t < blks.size(); ++t)
+    for (int j = 0; j < blks[t].kcap; ++j) {
+      cand.push_back({sh[blks[t].so + j], (int)t, j});
+      tot += sh[blks[t].so + j] * sh[blks[t].so + j];
+    }
+  std::stable_sort(cand.begin(), cand.end(), [&](const Cand& a, const Cand& b) {
+    if (a.s != b.s) return a.s > b.s;
+    if (blks[a.t].q != blks[b.t].q) return blks[a.t].q < blks[b.t].q;
+    return a.j < b.j;
+  });
+  const double smax = cand.empty() ? 0.0 : cand[0].s;
+  int above = 0;
+  for (const Cand& c : cand) above += c.s > cutoff * smax ? 1 : 0;
+  const int k = std::max(1, std::min<int>({Dmax, (int)cand.size(), std::max(above, 1)}));
+  double kept2 = 0.0;
+  for (int i = 0; i < k; ++i) {
+    blks[cand[i].t].kq += 1;
+    kept2 += cand[i].s * cand[i].s;
+  }
+  res.k = k;
+  res.norm = std::sqrt(kept2);
+  res.disc = tot > 0.0 ? std::max(0.0, tot - kept2) / tot : 0.0;
+  res.charges.clear();
+  int off = 0;
+  for (Blk& b : blks) {  // blocks come in ascending charge (std::map order)
+    b.off = off;
+    off += b.kq;
+    res.charges.insert(res.charges.end(), b.kq, b.q);
+  }
+  hipLaunchKernelGGL(fill_zero_c128, dim3(grid_for((long long)m * k)), dim3(256), 0, st, A, (long long)m * k);
+  MPOEVO_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(fill_zero_c128, dim3(grid_for((long long)k * n)), dim3(256), 0, st, B, (long long)k * n);
+  MPOEVO_HIP_TRY(hipGetLastError());
+  for (const Blk& b : blks) {
+    if (b.kq == 0) continue;
+    const int* r_dev = idx_dev + b.io;
+    const int* c_dev = r_dev + b.mq;
+    hipLaunchKernelGGL(scatter_block_cols, dim3(grid_for((long long)b.mq * b.kq)), dim3(256), 0, st, aq + b.ao,
+                       b.kcap, b.mq, b.kq, r_dev, A, k, b.off);
+    MPOEVO_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(scatter_block_rows, dim3(grid_for((long long)b.kq * b.nq)), dim3(256), 0, st, bq + b.bo,
+                       b.nq, b.kq, c_dev, B, n, b.off);
+    MPOEVO_HIP_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
 // Site product site[a][s][b] <- sum_c site_in[a][s][c] R[c][b] (complex128), used to absorb
 // the U S factor of the right-canonicalisation into the site on the left.
 hipError_t absorb_right(const void* site_in, const void* R, void* site_out, int Pa, int d, int Pc,
@@ -440,7 +603,7 @@ size_t wcontract_xws(long long ket_rows, long long bra_cols, int d, int wl, int 
 // ------------------------------------------------------------------------- step workspace map
 struct StepLayout {
   size_t sitecap, lbcap, envcap, tmpcap, wcap, thetacap;
-  size_t off_blk, off_token_front, off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
+  size_t off_u1, off_blk, off_token_front, off_phi, off_ketc, off_brac, off_wc, off_lb, off_rb, off_env0, off_env1, off_tmp,
       off_theta, off_svd, off_kbuf, off_dbuf, off_nbuf, off_site_tmp, off_site_tmp2, off_sweeps,
       off_cplt, off_blocks, off_basis, basiscap, off_token, off_gemm, off_xws, total;
 };
@@ -477,6 +640,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_site_tmp = take(sizeof(double2) * s.sitecap);
   s.off_site_tmp2 = take(sizeof(double2) * s.sitecap);
   s.off_blk = take(cs * s.lbcap);  // one-site updates: the block of the current site
+  s.off_u1 = take(blocked_scratch_bytes(d * Dmax));  // U(1) chains: per-charge truncations
   s.off_sweeps = take(sizeof(int) * (size_t)8 * L);
   s.off_cplt = take(sizeof(int) * (size_t)8 * L);  // per visit: the bond matrix had full rank
   s.off_blocks = take(sizeof(int) * (size_t)8 * L);  // per visit: column blocks of the Jacobi rounds
@@ -766,12 +930,12 @@ size_t expectation_ws(int L, int d, int Dmax, int wmax) {
   return 2 * env + 2 * blk + wcontract_xws(Dmax, Dmax, d, wmax, wmax, sizeof(double2)) + kGemmScratchBytes;
 }
 
-// E <- E . psi_i . O_i . conj(psi_i), i = 0 .. L-1, from E = e_left; out = E[right].
-int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
-                    void* out, void* ws, size_t, void* stream) {
+// E <- E . ket_i . O_i . conj(bra_i), i = 0 .. L-1, from E = e_left; out = E[right] = <bra| O |ket>.
+int overlap_dev(Context& ctx, const mpoevo_mps* bra, const mpoevo_mpo* mpo, const mpoevo_mps* ket, int left,
+                int right, void* out, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
   TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
-  const int L = mps->L, d = mps->d, Dmax = mps->Dmax;
+  const int L = ket->L, d = ket->d, Dmax = std::max(bra->Dmax, ket->Dmax);
   int wmax = 0;
   for (int i = 0; i <= L; ++i) wmax = std::max(wmax, mpo->w[i]);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -783,24 +947,30 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
   void* LB = base + 2 * env + blk;
   void* xws = base + 2 * env + 2 * blk;
   void* gws = static_cast<unsigned char*>(xws) + wcontract_xws(Dmax, Dmax, d, wmax, wmax, sizeof(double2));
-  const int* D = mps->bond_dim;
+  const int* P = bra->bond_dim;
+  const int* Q = ket->bond_dim;
   const int* w = mpo->w;
   hipLaunchKernelGGL(boundary_level, dim3((w[0] + 255) / 256), dim3(256), 0, st, E[0], w[0], left);
   hipError_t e = hipGetLastError();
   int cur = 0;
   for (int i = 0; i < L && e == hipSuccess; ++i) {
-    e = left_block(Arith{true, false}, E[cur], mps->site[i], mpo->site[i], tmp, LB, D[i], w[i], D[i], d, D[i + 1],
+    e = left_block(Arith{true, false}, E[cur], ket->site[i], mpo->site[i], tmp, LB, P[i], w[i], Q[i], d, Q[i + 1],
                    w[i + 1], st, nullptr, gws, xws);
     if (e == hipSuccess)
-      e = left_env_from_block(Arith{true, false}, mps->site[i], LB, E[cur ^ 1], D[i], d, D[i + 1], w[i + 1],
-                              D[i + 1], st, nullptr, gws);
+      e = left_env_from_block(Arith{true, false}, bra->site[i], LB, E[cur ^ 1], P[i], d, P[i + 1], w[i + 1],
+                              Q[i + 1], st, nullptr, gws);
     cur ^= 1;
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(copy_entry, dim3(1), dim3(64), 0, st, E[cur] + right, static_cast<double2*>(out));
     e = hipGetLastError();
   }
-  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "expectation");
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "overlap");
+}
+
+int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
+                    void* out, void* ws, size_t bytes, void* stream) {
+  return overlap_dev(ctx, mps, mpo, mps, left, right, out, ws, bytes, stream);
 }
 
 // ---------------------------------------------------------------------------------- the step
@@ -850,7 +1020,17 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   // Jacobi preconditioners: kept in the workspace between steps of the same handle, valid while
   // the workspace and the chain's shape stay the same; otherwise every bond restarts from the
   // identity. warm_dim[i] is the order of the unitary stored for bond i (0: none).
-  const bool warm_on = opts->svd_cold_start == 0;
+  // U(1) chains: host copies of the charges of the bra bonds (the ket's are fixed during the step)
+  const bool u1 = mps->sector_table != nullptr;
+  std::vector<std::vector<int>> qch(L + 1);
+  std::vector<int> qp(u1 ? d : 0);
+  if (u1) {
+    for (int s_ = 0; s_ < d; ++s_) qp[s_] = mps->phys_charge[s_];
+    for (int b = 0; b <= L; ++b)
+      qch[b].assign(mps->sector_table + (size_t)b * Dmax, mps->sector_table + (size_t)b * Dmax + mps->bond_dim[b]);
+  }
+  unsigned char* u1ws = base + lay.off_u1;
+  const bool warm_on = opts->svd_cold_start == 0 && !u1;
   const int sig[5] = {L, d, Dmax, wmax, prec};
   unsigned long long* token_dev = reinterpret_cast<unsigned long long*>(base + lay.off_token);
   unsigned long long* token_front = reinterpret_cast<unsigned long long*>(base + lay.off_token_front);
@@ -929,8 +1109,35 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       STEP_TRY(cast_to_c64(mpo->site[i], (void*)wsite(i), (long long)w[i] * d * d * w[i + 1], st));
     }
   }
+  // row charges of a bond matrix with rows (a', s') and column charges of one with columns
+  // (t', c') (the charge of the bond between them)
+  auto row_charges = [&](int bond) {
+    std::vector<int> r((size_t)P[bond] * d);
+    for (int a = 0; a < P[bond]; ++a)
+      for (int s_ = 0; s_ < d; ++s_) r[(size_t)a * d + s_] = qch[bond][a] + qp[s_];
+    return r;
+  };
+  auto col_charges = [&](int bond) {
+    std::vector<int> c((size_t)d * P[bond]);
+    for (int t = 0; t < d; ++t)
+      for (int b = 0; b < P[bond]; ++b) c[(size_t)t * P[bond] + b] = qch[bond][b] - qp[t];
+    return c;
+  };
   // right-canonical guess: SVD of each site from the last to the second
-  if (!opts->input_right_canonical) {
+  if (!opts->input_right_canonical && u1) {
+    for (int i = L - 1; i >= 1; --i) {  // per charge block: the rows a carry q(a), columns (s, b) q(b) - q(s)
+      const int m = P[i], n = d * P[i + 1];
+      BlockedResult br;
+      STEP_TRY(blocked_truncate(ctx, phi(i), m, n, qch[i], col_charges(i + 1), std::min(m, n), opts->cutoff,
+                                MPOEVO_RIGHT, theta, site_tmp, u1ws, d * Dmax, svdws, st, br));
+      STEP_TRY(hipMemcpyAsync(phi(i), site_tmp, sizeof(double2) * (size_t)br.k * n, hipMemcpyDeviceToDevice, st));
+      STEP_TRY(absorb_right(phi(i - 1), theta, site_tmp2, P[i - 1], d, m, br.k, st, gws));
+      STEP_TRY(hipMemcpyAsync(phi(i - 1), site_tmp2, sizeof(double2) * (size_t)P[i - 1] * d * br.k,
+                              hipMemcpyDeviceToDevice, st));
+      P[i] = br.k;
+      qch[i] = br.charges;
+    }
+  } else if (!opts->input_right_canonical) {
     for (int i = L - 1; i >= 1; --i) {
       const int m = P[i], n = d * P[i + 1];
       const SvdPlan pl = svd_plan(m, n, MPOEVO_RIGHT);
@@ -959,7 +1166,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   };
   bool one_site = opts->nsites == 1;
   if (opts->nsites == -1) {
-    one_site = d * Dmax <= 512;
+    one_site = d * Dmax <= 512 && !u1;
     for (int b = 1; b < L && one_site; ++b) one_site = P[b] == cap_of(b);
   }
   if (one_site) {
@@ -1096,6 +1303,19 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
 
   int visit = 0;
   const int nvis = opts->nsweeps * 2 * (L - 1);
+  // U(1): the truncation of a visit per charge block (kept rank, weight and norm known on the host)
+  std::vector<int> u1_k(u1 ? nvis : 0);
+  std::vector<double> u1_d(u1 ? nvis : 0), u1_n(u1 ? nvis : 0);
+  auto u1_visit = [&](int i, int m, int n, int dir, int vis) -> hipError_t {
+    BlockedResult br;
+    MPOEVO_HIP_TRY(blocked_truncate(ctx, theta, m, n, row_charges(i), col_charges(i + 2), Dmax, opts->cutoff, dir,
+                                    phi(i), phi(i + 1), u1ws, d * Dmax, svdws, st, br));
+    u1_k[vis] = br.k;
+    u1_d[vis] = br.disc;
+    u1_n[vis] = br.norm;
+    qch[i + 1] = br.charges;
+    return hipSuccess;
+  };
   int last_visit_k_slot = 0;
   std::vector<int> k_slot_of_bond(L, -1);
   std::vector<int> bond_of_visit(nvis, 0);
@@ -1115,8 +1335,12 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       const int m = P[i] * d, n = d * P[i + 2];
       STEP_TRY(theta_product(ar, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
-      const int kcap = std::min(Dmax, std::min(m, n));
-      {
+      int kcap = std::min(Dmax, std::min(m, n));
+      if (u1) {
+        bond_of_visit[visit] = i;
+        STEP_TRY(u1_visit(i, m, n, MPOEVO_LEFT, visit));
+        kcap = u1_k[visit];
+      } else {
         // the first visit of a bond in a step has no fresh preconditioner (Theta moved by a
         // whole time step since the last one), and a bond below Dmax, or one whose matrix the
         // last step found numerically rank-deficient, would need its basis completed: square
@@ -1160,8 +1384,12 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       const int m = P[i] * d, n = d * P[i + 2];
       STEP_TRY(theta_product(ar, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
-      const int kcap = std::min(Dmax, std::min(m, n));
-      {
+      int kcap = std::min(Dmax, std::min(m, n));
+      if (u1) {
+        bond_of_visit[visit] = i;
+        STEP_TRY(u1_visit(i, m, n, MPOEVO_RIGHT, visit));
+        kcap = u1_k[visit];
+      } else {
         const bool deficient = !saturated[i + 1] || ctx.warm_deficient[i];
         const bool qr = warm_on && svd_qr_ok(m, n, MPOEVO_RIGHT) &&
                         (m == n ? (ctx.warm_dim[i] != m || deficient)
@@ -1189,6 +1417,15 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       STEP_TRY(bra_refresh(i));
       STEP_TRY(bra_refresh(i + 1));
     }
+  }
+  std::vector<int> u1_zero(u1 ? nvis : 0, 0), u1_one(u1 ? nvis : 0, 1);
+  if (u1) {  // the visit slots the dense truncation fills on the device
+    STEP_TRY(hipMemcpyAsync(kbuf, u1_k.data(), sizeof(int) * nvis, hipMemcpyHostToDevice, st));
+    STEP_TRY(hipMemcpyAsync(dbuf, u1_d.data(), sizeof(double) * nvis, hipMemcpyHostToDevice, st));
+    STEP_TRY(hipMemcpyAsync(nbuf, u1_n.data(), sizeof(double) * nvis, hipMemcpyHostToDevice, st));
+    STEP_TRY(hipMemcpyAsync(sweeps_buf, u1_zero.data(), sizeof(int) * nvis, hipMemcpyHostToDevice, st));
+    STEP_TRY(hipMemcpyAsync(cplt_buf, u1_one.data(), sizeof(int) * nvis, hipMemcpyHostToDevice, st));
+    STEP_TRY(hipMemcpyAsync(blocks_buf, u1_zero.data(), sizeof(int) * nvis, hipMemcpyHostToDevice, st));
   }
   // normalise with the norm of the last visit (phi_0 holds U S)
   STEP_TRY([&] {
@@ -1232,6 +1469,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     mps->bond_dim[b] = Pact[b];
     maxb = std::max(maxb, Pact[b]);
   }
+  if (u1)
+    for (int b = 1; b < L; ++b) std::copy(qch[b].begin(), qch[b].end(), mps->sector_table + (size_t)b * Dmax);
   if (stats) {
     stats->norm = norm;
     stats->discarded_max = 0.0;

@@ -93,6 +93,8 @@ int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double
 int check_solver_dev(Context& ctx);
 int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
              mpoevo_step_stats* stats, void* ws, size_t ws_bytes, void* stream);
+int overlap_dev(Context& ctx, const mpoevo_mps* bra, const mpoevo_mpo* mpo, const mpoevo_mps* ket, int left,
+                int right, void* out, void* ws, size_t ws_bytes, void* stream);
 int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, int left, int right,
                     void* out, void* ws, size_t ws_bytes, void* stream);
 size_t step_batched_ws(int n, const int* dims, int prec);  // dims: {L, d, Dmax, wmax} per chain

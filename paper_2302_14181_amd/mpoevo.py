@@ -34,7 +34,8 @@ class MpoevoError(RuntimeError):
 
 class _MPS(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("d", ctypes.c_int), ("Dmax", ctypes.c_int),
-                ("bond_dim", ctypes.POINTER(ctypes.c_int)), ("site", ctypes.POINTER(ctypes.c_void_p))]
+                ("bond_dim", ctypes.POINTER(ctypes.c_int)), ("site", ctypes.POINTER(ctypes.c_void_p)),
+                ("sector_table", ctypes.POINTER(ctypes.c_int)), ("phys_charge", ctypes.POINTER(ctypes.c_int))]
 
 
 class _MPO(ctypes.Structure):
@@ -99,13 +100,15 @@ def load(path: str = LIB_PATH):
                                 vp, vp, sz, vp]
     lib.step_batched.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO),
                                  ctypes.POINTER(_Opts), ctypes.POINTER(_Stats), vp, sz, vp]
+    lib.overlap.argtypes = [vp, ctypes.POINTER(_MPS), ctypes.POINTER(_MPO), ctypes.POINTER(_MPS), ctypes.c_int,
+                            ctypes.c_int, vp, vp, sz, vp]
     lib.env_update_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, ip, vp]
     lib.mpoevo_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.mpoevo_product_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ip, ip]
     for name in ("mpoevo_create", "mpoevo_destroy", "mpoevo_check_solver", "mpo_build",
                  "mpoevo_workspace_size", "env_update", "local_apply", "truncate", "step", "expectation",
-                 "step_batched", "mpoevo_set_tuning", "mpoevo_product_plan", "env_update_noalloc"):
+                 "step_batched", "mpoevo_set_tuning", "mpoevo_product_plan", "env_update_noalloc", "overlap"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -115,7 +118,7 @@ def exported_symbols():
     return ["mpoevo_create", "mpoevo_destroy", "mpoevo_last_error", "mpoevo_version", "mpo_build",
             "env_update", "local_apply", "truncate", "mpoevo_check_solver", "step",
             "expectation", "step_batched", "mpoevo_workspace_size", "mpoevo_set_tuning",
-            "mpoevo_product_plan", "env_update_noalloc"]
+            "mpoevo_product_plan", "env_update_noalloc", "overlap"]
 
 
 def _check(rc: int, handle=None):
@@ -314,14 +317,26 @@ class StepStats:
 
 
 class DeviceMPS:
-    """MPS on the device: complex128 site buffers of capacity Dmax * d * Dmax, bonds on the host."""
+    """MPS on the device: complex128 site buffers of capacity Dmax * d * Dmax, bonds on the host.
+    U(1) chains: charges[b] lists the charge of every index of bond b (nondecreasing; the sites'
+    bond indices in charge order) and phys_charge that of every physical index; a step then runs
+    the U(1) fit and updates self.charges."""
 
-    def __init__(self, sites, Dmax: int, device="cuda"):
+    def __init__(self, sites, Dmax: int, device="cuda", charges=None, phys_charge=None):
         torch = _torch()
         self.L = len(sites)
         self.d = sites[0].shape[1]
         self.Dmax = Dmax
         self.bond = [1] + [int(s.shape[2]) for s in sites]
+        self.charges = None
+        self.phys_charge = None
+        if charges is not None:
+            if phys_charge is None or len(charges) != self.L + 1:
+                raise MpoevoError(EINVAL, "charges need L + 1 bonds and phys_charge")
+            self.charges = [list(map(int, c)) for c in charges]
+            self.phys_charge = list(map(int, phys_charge))
+            if [len(c) for c in self.charges] != self.bond:
+                raise MpoevoError(ESHAPE, "charges must list every bond index")
         cap = Dmax * self.d * Dmax
         self.buf = []
         for s in sites:
@@ -357,6 +372,26 @@ class DeviceMPO:
             self.buf.append(cache[key])
 
 
+def _c_mps(mps: DeviceMPS):
+    """ctypes view of a DeviceMPS: (structure, bond array, sector table array or None, keep-alive)."""
+    bond = _iarr(mps.bond)
+    sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
+    table = qp = None
+    if mps.charges is not None:
+        flat = [0] * ((mps.L + 1) * mps.Dmax)
+        for b, c in enumerate(mps.charges):
+            flat[b * mps.Dmax:b * mps.Dmax + len(c)] = c
+        table = _iarr(flat)
+        qp = _iarr(mps.phys_charge)
+    return _MPS(mps.L, mps.d, mps.Dmax, bond, sites, table, qp), bond, table, (sites, qp)
+
+
+def _c_mps_update(mps: DeviceMPS, bond, table):
+    mps.bond = [bond[i] for i in range(mps.L + 1)]
+    if table is not None:
+        mps.charges = [[table[b * mps.Dmax + j] for j in range(mps.bond[b])] for b in range(mps.L + 1)]
+
+
 def step_workspace(mps: DeviceMPS, mpo: DeviceMPO, prec: int):
     dims = [mps.L, mps.d, mps.Dmax, max(mpo.w)]
     return _workspace(workspace_size(CALL_STEP, dims, prec), mps.buf[0].device)
@@ -386,17 +421,15 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     Without a workspace the MPS object's own default workspace is used (kept between calls)."""
     if workspace is None:
         workspace = _default_step_workspace(h, mps, mpo, prec)
-    bond = _iarr(mps.bond)
-    sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
+    cm, bond, table, _keep = _c_mps(mps)
     wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
-    cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
     cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
     opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
                  int(bool(svd_cold_start)), int(nsites))
     st = _Stats()
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
                        _ptr(workspace), workspace.numel(), _stream(stream)), h)
-    mps.bond = [bond[i] for i in range(mps.L + 1)]
+    _c_mps_update(mps, bond, table)
     return _stats_of(st, profile)
 
 
@@ -479,13 +512,14 @@ def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cu
     keep = []  # ctypes arrays referenced by the structures
     cms = (_MPS * n)()
     cws = (_MPO * n)()
+    tables = []
     for c, (mps, mpo) in enumerate(zip(chains, mpos)):
-        bond = _iarr(mps.bond)
-        sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
+        cm, bond, table, k2 = _c_mps(mps)
         w = _iarr(mpo.w)
         wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
-        keep += [bond, sites, w, wsites]
-        cms[c] = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
+        keep += [bond, k2, w, wsites]
+        tables.append(table)
+        cms[c] = cm
         cws[c] = _MPO(mpo.L, mpo.d, w, wsites)
     opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
                  int(bool(svd_cold_start)), int(nsites))
@@ -493,7 +527,7 @@ def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cu
     _check(load().step_batched(h.ptr, n, cms, cws, ctypes.byref(opts), st, _ptr(workspace),
                                workspace.numel(), _stream(stream)), h)
     for c, mps in enumerate(chains):
-        mps.bond = [keep[4 * c][i] for i in range(mps.L + 1)]
+        _c_mps_update(mps, keep[4 * c], tables[c])
     return [_stats_of(st[c], profile) for c in range(n)]
 
 
@@ -504,14 +538,32 @@ def expectation(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, left: int = 0, right:
     dev = mps.buf[0].device
     if workspace is None:
         workspace = _workspace(workspace_size(CALL_EXPECTATION, [mps.L, mps.d, mps.Dmax, max(mpo.w)], FP64), dev)
-    bond = _iarr(mps.bond)
-    sites = (ctypes.c_void_p * mps.L)(*[t.data_ptr() for t in mps.buf])
+    cm, bond, table, _keep = _c_mps(mps)
     wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
-    cm = _MPS(mps.L, mps.d, mps.Dmax, bond, sites)
     cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
     out = torch.zeros(2, dtype=torch.float64, device=dev)
     _check(load().expectation(h.ptr, ctypes.byref(cm), ctypes.byref(cw), left, right, _ptr(out),
                               _ptr(workspace), workspace.numel(), _stream(stream)), h)
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+    v = out.cpu().numpy()
+    return complex(v[0], v[1])
+
+
+def overlap(h: Handle, bra: DeviceMPS, mpo: DeviceMPO, ket: DeviceMPS, left: int = 0, right: int = 0,
+            workspace=None, stream=None) -> complex:
+    """<bra| l.O_1...O_L.r |ket> on the device in FP64 (see include/mpoevo.h); waits for the result."""
+    torch = _torch()
+    dev = ket.buf[0].device
+    Dm = max(bra.Dmax, ket.Dmax)
+    if workspace is None:
+        workspace = _workspace(workspace_size(CALL_EXPECTATION, [ket.L, ket.d, Dm, max(mpo.w)], FP64), dev)
+    cb, _, _, kb = _c_mps(bra)
+    ck, _, _, kk = _c_mps(ket)
+    wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
+    cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    _check(load().overlap(h.ptr, ctypes.byref(cb), ctypes.byref(cw), ctypes.byref(ck), left, right, _ptr(out),
+                          _ptr(workspace), workspace.numel(), _stream(stream)), h)
     (stream if stream is not None else torch.cuda.current_stream()).synchronize()
     v = out.cpu().numpy()
     return complex(v[0], v[1])

@@ -242,18 +242,45 @@ def u1_sector_tables(L: int, n_up: int, D: int, nsec: int = 15, seed: int = 1, w
 
 def random_u1_mps(rng: np.random.Generator, tables, phys_charge):
     """Random U(1) MPS as blocks {(q_left, s): array (dim q_left, dim q_left + phys_charge[s])}
-    with complex-normal entries scaled by 1 / sqrt(d dim(right bond)); blocks only where both
-    charges exist. Returns the list of site dicts."""
+    with complex-normal entries, blocks only where both charges exist; the entries of a left index
+    of charge q are scaled by 1 / sqrt(its number of entries, sum_s dim(q + phys_charge[s])), so
+    that every row has unit expected norm and the state's norm stays of order one on long chains.
+    Returns the list of site dicts."""
     d = len(phys_charge)
     sites = []
     for i in range(len(tables) - 1):
         left, right = tables[i], tables[i + 1]
-        scale = 1.0 / np.sqrt(d * sum(right.values()))
         site = {}
         for qa, da in left.items():
+            nrow = sum(right.get(qa + int(phys_charge[s]), 0) for s in range(d))
             for s in range(d):
                 qb = qa + int(phys_charge[s])
                 if qb in right:
-                    site[(qa, s)] = complex_normal(rng, (da, right[qb])) * scale
+                    site[(qa, s)] = complex_normal(rng, (da, right[qb])) / np.sqrt(nrow)
         sites.append(site)
     return sites
+
+
+def u1_dense(sites, tables, phys_charge):
+    """A U(1) MPS given as blocks laid out densely with every bond's indices in ascending charge:
+    (list of (D_left, d, D_right) arrays, list of L + 1 per-index charge lists)."""
+    d = len(phys_charge)
+    out, charges = [], []
+    for b, t in enumerate(tables):
+        charges.append([q for q in sorted(t) for _ in range(t[q])])
+    for i, site in enumerate(sites):
+        left, right = tables[i], tables[i + 1]
+        lo, ro, o = {}, {}, 0
+        for q in sorted(left):
+            lo[q] = o
+            o += left[q]
+        o = 0
+        for q in sorted(right):
+            ro[q] = o
+            o += right[q]
+        M = np.zeros((sum(left.values()), d, sum(right.values())), dtype=np.complex128)
+        for (qa, s), blk in site.items():
+            qb = qa + int(phys_charge[s])
+            M[lo[qa]:lo[qa] + left[qa], s, ro[qb]:ro[qb] + right[qb]] = blk
+        out.append(M)
+    return out, charges
