@@ -24,6 +24,11 @@ microbenchmark at D = 256, d = 2, w = 8.
 (tests/golden/tfim_g05_L64_ground.npz, prepared by the oracle), order-2 extended MPO (w = 3; --order),
 tau = 0.1 (--tau), D <= 128, K steps (default 100) with the FP64 comparison and first-step parity.
 
+--workload xxz: the XXZ chain with U(1) charges (configuration 4): L = 128, 64 up spins, Delta = 0.5,
+order-2 extended MPO (w = 13), tau = 0.1, D <= 512 over about 15 charge sectors per bond (seeded
+sector tables), K steps (default 20) from a seeded random U(1) state, FP32 and FP64, parity of step 1
+against the block-sparse oracle.
+
 --workload batched: 64 independent TFIM chains (g ~ U(0.5, 1.5), L in {32, 64, 96, 128},
 D in {32, 64, 128, 256}, seed 2), order-2 extended MPO, tau = 0.1, from all-up, K steps (default 3)
 advanced together by step_batched, against the same steps taken chain by chain; the oracle checks
@@ -215,8 +220,8 @@ def traffic_of(kernel_name):
 def lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, Dmax, delta2=True):
     """Per-step parity against the oracle on the opening steps of the trajectory from all-up:
     step 1 from psi0 (R17-A: 1 - |<phi_gpu|phi_oracle>|^2; R17-B: |eps_gpu - eps_oracle| with
-    eps = 1 - |<phi|W psi>|^2 / ||W psi||^2, ||W psi0||^2 from the oracle's double-layer
-    contraction) on every contraction precision, and step 2 restarted from the oracle's state
+    eps = 1 - |<phi|W psi>|^2 / ||W psi||^2, the device state's overlap with W psi0 taken in FP64 on
+    the device, ||W psi0||^2 from the oracle's double-layer contraction) on every contraction precision, and step 2 restarted from the oracle's state
     after step 1 (delta_2, R17-A; the norm error in place of R17-B, whose ||W psi1||^2 is beyond the
     oracle's budget)."""
     from oracle import fit as ofit
@@ -227,13 +232,16 @@ def lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, Dmax, delta2=True):
     z_or = ofit.expect_local(ref1, wl.SZ, LR_SITE).real
     out = {"step1": {"oracle_norm": r1["norm"], "oracle_eps": eps_or, "W_psi0_norm2": n2,
                      "oracle_max_bond": max(r1["bond_dims"])}}
+    dpsi0 = mp.DeviceMPS(psi0, Dmax=Dmax)
     for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64), ("bf16x3", mp.BF16X3)):
         dm = mp.DeviceMPS(psi0, Dmax=Dmax)
         s = mp.step(h, dm, dw, prec=p)
         phi = dm.to_numpy()
-        eps = 1.0 - s.norm ** 2 / n2
+        # eps of the device state from its FP64 overlap with W psi0 (the norms and overlaps in FP64)
+        eps = 1.0 - abs(mp.overlap(h, dm, dw, dpsi0)) ** 2 / n2
         out["step1"][name] = {"infidelity_R17A": float(1.0 - abs(ofit.overlap(phi, ref1)) ** 2),
                               "eps_excess_R17B": float(abs(eps - eps_or)),
+                              "eps_excess_from_step_norm": float(abs(1.0 - s.norm ** 2 / n2 - eps_or)),
                               "Z50_error": float(abs(ofit.expect_local(phi, wl.SZ, LR_SITE).real - z_or)),
                               "norm_rel_error": float(abs(s.norm - r1["norm"]) / r1["norm"])}
         del dm
@@ -676,6 +684,104 @@ def run_batched(args, torch, mp, wl, h):
     print(json.dumps(line))
 
 
+XXZ_L, XXZ_UP, XXZ_D, XXZ_ORDER, XXZ_TAU, XXZ_DELTA = 128, 64, 512, 2, 0.1, 0.5
+
+
+def run_xxz(args, torch, mp, wl, h, side=False):
+    """The XXZ chain with U(1) charges (configuration 4): L = 128, 64 up spins, Delta = 0.5, the
+    order-2 extended MPO (w = 13), tau = 0.1, D <= 512 over about 15 charge sectors per bond (the
+    seeded sector tables of the input recipe, seed 1), K steps (default 20; side=True: 3) from
+    the seeded random U(1) state, FP32 and FP64; the oracle's block-sparse step 1 for parity."""
+    K = 3 if side else (args.steps or 20)
+    H = wl.xxz(XXZ_DELTA)
+    qp = H.phys_charge
+    W, lc = mp.mpo_build(H.A, H.B, H.C, H.Dloc, XXZ_ORDER, -1j * XXZ_TAU, mp.V2_EXTENDED, H.inner_charge, qp)
+    tables = wl.u1_sector_tables(XXZ_L, XXZ_UP, XXZ_D, nsec=15, seed=1)
+    psi = wl.random_u1_mps(np.random.default_rng(1), tables, qp)
+    dense, charges = wl.u1_dense(psi, tables, qp)
+    dw = mp.DeviceMPO([W] * XXZ_L)
+    prog = "xxz" if args.progress else None
+
+    def run(prec, n, profile=False):
+        dm = mp.DeviceMPS(dense, Dmax=XXZ_D, charges=charges, phys_charge=qp)
+        ws = mp.step_workspace(dm, dw, prec)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        st = []
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(n):
+            st.append(mp.step(h, dm, dw, prec=prec, input_right_canonical=k > 0, workspace=ws, profile=profile))
+            ev[k + 1].record()
+            if prog:
+                print(f"[bench] {prog} prec {prec} step {k + 1}/{n}: bond {st[-1].max_bond}", file=sys.stderr,
+                      flush=True)
+        torch.cuda.synchronize()
+        del ws
+        torch.cuda.empty_cache()
+        return [ev[k].elapsed_time(ev[k + 1]) for k in range(n)], st, dm
+
+    prec = mp.FP32 if side else prec_of(mp, args.prec)
+    if not side and args.warmup:
+        run(prec, min(args.warmup, 2))
+    ms, st, dm = run(prec, K, profile=True)
+    sec = float(np.sum(ms)) / 1e3 / K
+    kt = kernel_table(st, "fp32" if side else args.prec)
+    nsec = [len(set(c)) for c in dm.charges[1:-1]]
+    out = {"workload": f"XXZ chain (Delta={XXZ_DELTA}) with U(1) charges, L={XXZ_L}, {XXZ_UP} up spins, order-"
+                       f"{XXZ_ORDER} extended MPO (w={W.shape[0]}), tau={XXZ_TAU}, D<={XXZ_D} over charge sectors "
+                       f"(seeded tables, seed 1), steps 1..{K} from the seeded random U(1) state",
+           "s_per_step": sec, "step_ms": ms, "max_bond_end": max(dm.bond), "sectors_per_bond_end_max": max(nsec),
+           "discarded_sum_per_step": [x.discarded_sum for x in st],
+           "products_ms": float(sum(x.profile["t_gemm_ms"] for x in st)),
+           "dominant_kernel": roofline_of(kt[0]) if kt else None}
+    if not (side or args.no_fp64) and prec != mp.FP64:
+        ms64, _, dm64 = run(mp.FP64, K)
+        a, b = dm.to_numpy(), dm64.to_numpy()
+        out["fp64_s_per_step"] = float(np.sum(ms64)) / 1e3 / K
+        out["fp32_speedup"] = out["fp64_s_per_step"] / sec
+        out["trajectory_infidelity_fp32_vs_fp64"] = float(1.0 - abs(_overlap(a, b)) ** 2 / (
+            abs(_overlap(a, a)) * abs(_overlap(b, b))))
+        del dm64
+    del dm
+    torch.cuda.empty_cache()
+    if not side and not args.no_cpu:
+        from oracle import mpo as ompo
+        from oracle import u1 as ou1
+        Wo = ompo.build_mpo(H, XXZ_ORDER, -1j * XXZ_TAU, "V2")
+        lco = ompo.level_charges(H, XXZ_ORDER, -1j * XXZ_TAU, "V2")
+        t0 = time.perf_counter()
+        ref, rb, rst = ou1.fit_step(psi, tables, Wo, lco, qp, Dmax=XXZ_D)
+        t_or = time.perf_counter() - t0
+        refd = ou1.to_dense(ref, rb, qp)
+        par = {}
+        for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64)):
+            dm1 = mp.DeviceMPS(dense, Dmax=XXZ_D, charges=charges, phys_charge=qp)
+            s1 = mp.step(h, dm1, dw, prec=p)
+            par[name] = {"step1_infidelity_R17A": float(1.0 - abs(_overlap(dm1.to_numpy(), refd)) ** 2),
+                         "step1_norm_rel_error": float(abs(s1.norm - rst["norm"]) / rst["norm"]),
+                         "step1_discarded_abs_error": float(abs(s1.discarded_sum - sum(rst["discarded"]))),
+                         "bond_charges_equal": all(sorted(dm1.charges[b]) ==
+                                                   [q for q in sorted(rb[b]) for _ in range(rb[b][q])]
+                                                   for b in range(XXZ_L + 1))}
+            del dm1
+        out["parity_vs_block_oracle"] = par
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+        out["cpu_baseline"] = {"value": t_or, "unit": "s per time step", "cores": int(threads), "kind": "oracle",
+                               "sample": "the block-sparse oracle's step 1 from the same state (dictionaries of "
+                                         f"blocks, numpy complex128, {threads} BLAS threads)"}
+    if side:
+        return out
+    print(json.dumps({
+        "metric": "s per time step, U(1) XXZ chain (configuration 4)",
+        "value": sec, "unit": "s per time step", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[args.prec], "data": "synthetic",
+        "config": {"workload": out["workload"], "L": XXZ_L, "D": XXZ_D, "order": XXZ_ORDER, "tau": XXZ_TAU},
+        "roofline": out["dominant_kernel"], "kernels_timed_steps": kt[:8],
+        **{k: v for k, v in out.items() if k not in ("workload", "dominant_kernel")}}), flush=True)
+
+
 def run_quench(args, torch, mp, wl, h, side=False):
     """The L = 64 TFIM quench (g = 0.5 -> 1.5) from t = 0: K steps on the chosen path and the same
     steps on the plain FP64 path, first-step parity against the oracle (R17-A and R17-B), the
@@ -721,12 +827,15 @@ def run_quench(args, torch, mp, wl, h, side=False):
         eps_or = 1.0 - rinfo["norm"] ** 2 / n2
         z_or = ofit.expect_local(ref, wl.SZ, 31).real
         par = {}
+        dpsi0 = mp.DeviceMPS(psi0, Dmax=D)
         for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64), ("bf16x3", mp.BF16X3)):
             dm1 = mp.DeviceMPS(psi0, Dmax=D)
             s1 = mp.step(h, dm1, dw, prec=p)
             o = dm1.to_numpy()
+            eps = 1.0 - abs(mp.overlap(h, dm1, dw, dpsi0)) ** 2 / n2
             par[name] = {"infidelity_R17A": float(1.0 - abs(ofit.overlap(o, ref)) ** 2),
-                         "eps_excess_R17B": float(abs(1.0 - s1.norm ** 2 / n2 - eps_or)),
+                         "eps_excess_R17B": float(abs(eps - eps_or)),
+                         "eps_excess_from_step_norm": float(abs(1.0 - s1.norm ** 2 / n2 - eps_or)),
                          "Z32_error": float(abs(ofit.expect_local(o, wl.SZ, 31).real - z_or)),
                          "norm_rel_error": float(abs(s1.norm - rinfo["norm"]) / rinfo["norm"])}
         out["step1_parity_vs_oracle"] = par
@@ -759,8 +868,8 @@ def main():
     ap.add_argument("--nsites", type=int, default=-1, choices=[-1, 1, 2],
                     help="lr3: local update (2: two-site; 1: one-site at fixed bonds; -1: two-site while the "
                          "bonds grow, one-site once all are at their largest value)")
-    ap.add_argument("--workload", choices=["lr3", "quench", "batched", "env", "split", "thermal", "cylinder"],
-                    default="lr3")
+    ap.add_argument("--workload", choices=["lr3", "quench", "xxz", "batched", "env", "split", "thermal",
+                                           "cylinder"], default="lr3")
     ap.add_argument("--progress", action="store_true", help="print a line to stderr after every timed step")
     ap.add_argument("--order", type=int, default=ORDER, choices=[1, 2, 3, 4],
                     help="MPO order of the TFIM workloads (quench, split reference, thermal)")
@@ -793,7 +902,7 @@ def main():
     elif args.workload == "quench":
         run_quench(args, torch, mp, wl, h)
     else:
-        {"lr3": run_lr3, "batched": run_batched, "split": run_split, "thermal": run_thermal,
+        {"lr3": run_lr3, "xxz": run_xxz, "batched": run_batched, "split": run_split, "thermal": run_thermal,
          "cylinder": run_cylinder}[args.workload](args, torch, mp, wl, h)
     h.close()
 

@@ -156,9 +156,14 @@ def expect_local(ms, op, site: int) -> complex:
 
 def mpo_expectation(ms, Wsites, left, right) -> complex:
     """<psi| O |psi> for an MPO O = l . W_1 ... W_L . r."""
+    return mpo_overlap(ms, Wsites, ms, left, right)
+
+
+def mpo_overlap(bra, Wsites, ket, left, right) -> complex:
+    """<bra| O |ket> for an MPO O = l . W_1 ... W_L . r (left environments from the left end)."""
     E = np.einsum('a,xy->xay', left, np.ones((1, 1), dtype=np.complex128))
-    for A, W in zip(ms, Wsites):
-        E = env_left(E, A, W, A)
+    for A, W, B in zip(bra, Wsites, ket):
+        E = env_left(E, A, W, B)
     return complex(np.einsum('xay,a->', E, right))
 
 

@@ -826,3 +826,17 @@ def test_one_site_rejects_unsupported_shapes(mp, handle):
     with pytest.raises(mp.MpoevoError) as e:
         mp.step(handle, dm, mp.DeviceMPO([W] * L), nsites=3)
     assert e.value.code == mp.EINVAL
+
+
+@pytest.mark.parametrize("L,Db,Dk", [(7, 4, 9), (10, 16, 6)], ids=str)
+def test_overlap_fp64(mp, handle, L, Db, Dk):
+    """<bra| W |ket> on the device in FP64 against the oracle, bra and ket with different bonds."""
+    _say("overlap", L, Db, Dk)
+    rng = np.random.default_rng(L * 31 + Db)
+    bra, ket = wl.random_mps(rng, L, 2, Db), wl.random_mps(rng, L, 2, Dk)
+    W, Wo = mpo_pair(mp, wl.tfim(1.1), 2, -0.2j)
+    e0 = np.zeros(W.shape[0], complex)
+    e0[0] = 1.0
+    ref = ofit.mpo_overlap(bra, [Wo] * L, ket, e0, e0)
+    got = mp.overlap(handle, mp.DeviceMPS(bra, Dmax=Db), mp.DeviceMPO([W] * L), mp.DeviceMPS(ket, Dmax=Dk))
+    assert abs(got - ref) < 1e-12 * abs(ref), (got, ref)

@@ -163,3 +163,15 @@ def test_fit_observables_gauge_invariant():
     for j in (0, 3, 5):
         ref = np.vdot(v, dense.local_op(wl.SZ, j, 6) @ v).real
         assert abs(fit.expect_local(psi, wl.SZ, j).real - ref) < 1e-13
+
+
+def test_mpo_overlap_equals_dense():
+    """<bra| O |ket> through the environments equals the dense bra^dag O ket (different bonds)."""
+    rng = np.random.default_rng(12)
+    L = 6
+    bra, ket = wl.random_mps(rng, L, 2, 3), wl.random_mps(rng, L, 2, 5)
+    W = mpo.build_mpo(wl.random_blocks(rng, 2, 2), 2, 0.1 + 0.2j, "V2")
+    e0 = dense.boundary(W.shape[0])
+    got = fit.mpo_overlap(bra, [W] * L, ket, e0, e0)
+    ref = np.vdot(dense.mps_to_dense(bra), dense.dense_evolution_mpo(W, L) @ dense.mps_to_dense(ket))
+    assert abs(got - ref) < 1e-12 * abs(ref)
