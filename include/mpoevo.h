@@ -260,6 +260,19 @@ typedef struct {
                    2 (L-1) nsweeps + 1 local updates, no Jacobi sweeps.
                    -1: automatic -- one-site when every bond of psi equals its largest possible
                    value min(Dmax, d^i, d^(L-i)) (and d Dmax <= 512), else two-site. */
+  int use_graph; /* 1: the step's device work (everything between the opening check of the
+                   workspace and the closing read-back of ranks and statistics) is captured into a
+                   HIP graph the second time a step with the same plan runs on this handle (the
+                   first runs uncaptured, so that the tile tuner can time new product shapes) --
+                   the plan being the shapes, options, buffers (workspace, site and MPO pointers),
+                   the truncations' preconditioner state and the tuner's mode -- and replayed by
+                   every later step with that plan (one launch instead of thousands). The handle
+                   keeps the last 8 graphs; mpoevo_set_tuning starts new ones.
+                   Not with profile or U(1) charges (ignored there). In a graph the Jacobi and QR
+                   kernels are ordinary launches that need their workgroups resident together (the
+                   graph runs one node at a time; other work on the device meanwhile can delay them
+                   to their bounded-wait timeout, ESOLVER); the arithmetic is that of the
+                   uncaptured step, so the results are the same bit for bit. 0: no graph. */
 } mpoevo_step_opts;
 
 #define MPOEVO_MAX_KERNEL_STATS 16
@@ -298,6 +311,8 @@ typedef struct {
      totals above) */
   int n_kernel_stats;
   mpoevo_kernel_stat kernel_stats[MPOEVO_MAX_KERNEL_STATS];
+  int graph;                /* opts->use_graph: 0 the work was issued launch by launch, 1 it was
+                               captured into a new graph (then launched), 2 a graph replayed it */
 } mpoevo_step_stats;
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,

@@ -245,6 +245,7 @@ int check_opts(mpoevo::Context* ctx, const std::string& who, const mpoevo_step_o
   if (!(opts->cutoff >= 0.0) || opts->cutoff >= 1.0) return fail(ctx, MPOEVO_EINVAL, who + ": cutoff must be in [0, 1)");
   if (opts->profile < 0 || opts->profile > 2) return fail(ctx, MPOEVO_EINVAL, who + ": profile must be 0, 1 or 2");
   if (opts->nsites < -1 || opts->nsites > 2) return fail(ctx, MPOEVO_EINVAL, who + ": nsites must be -1, 0, 1 or 2");
+  if (opts->use_graph < 0 || opts->use_graph > 1) return fail(ctx, MPOEVO_EINVAL, who + ": use_graph must be 0 or 1");
   return MPOEVO_OK;
 }
 }  // namespace

@@ -26,6 +26,7 @@
 #include <map>
 #include <mutex>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -43,10 +44,26 @@ LaunchRecord& last_launch() {
   return r;
 }
 
+// A step's device work captured into a HIP graph, with the plan it was captured for and the host
+// state the work leaves behind (restored whenever the graph replays it).
+struct GraphEntry {
+  std::vector<long long> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> P, bond_of_visit, k_slot_of_bond, warm_dim;
+  int last_visit_k_slot = 0, updates = 0;
+  double gflop = 0.0;
+  bool one_site = false;
+};
+constexpr size_t kMaxGraphs = 8;
+
 struct DeviceState {
   int* status = nullptr;  // sticky status words (device ints)
   int lds_max = 0;
   std::vector<hipEvent_t> events;  // reused by profiled steps
+  std::vector<GraphEntry> graphs;  // captured steps, oldest first
+  std::vector<std::vector<long long>> seen;  // plans run once, uncaptured
+  hipStream_t capture_stream = nullptr;
 };
 
 namespace {
@@ -715,6 +732,11 @@ void device_fini(Context& ctx) {
   for (void* s : ctx.streams) (void)hipStreamDestroy(static_cast<hipStream_t>(s));
   ctx.streams.clear();
   for (hipEvent_t ev : ctx.dev->events) (void)hipEventDestroy(ev);
+  for (GraphEntry& g : ctx.dev->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  if (ctx.dev->capture_stream) (void)hipStreamDestroy(ctx.dev->capture_stream);
   (void)hipFree(ctx.dev->status);
   delete ctx.dev;
   ctx.dev = nullptr;
@@ -974,6 +996,130 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
 }
 
 // ---------------------------------------------------------------------------------- the step
+// Host state the device work of a step leaves behind.
+struct StepPost {
+  std::vector<int>* P;
+  std::vector<int>* bond_of_visit;
+  std::vector<int>* k_slot_of_bond;
+  int* last_visit_k_slot;
+  double* gflop;
+  bool* one_site;
+  int* updates;
+  int* graph_use;  // 0 issued, 1 captured, 2 replayed
+};
+
+// Issues the device work of a step (body). With opts->use_graph (and neither profiling nor U(1)
+// charges, whose truncations wait for the device) the work is captured into a HIP graph the second
+// time a step with the same plan runs on the handle -- the plan being everything the launches
+// depend on: shapes, options, the buffers, the truncations' preconditioner state and the tile
+// tuner's state -- and every later step with that plan replays the graph instead of issuing its
+// launches.
+// Inside a graph the Jacobi and QR kernels are ordinary launches (the graph runs its nodes one at
+// a time, so their workgroups are resident together), not cooperative ones; the arithmetic is
+// the same, so replays reproduce the uncaptured step bit for bit.
+template <class Body>
+int run_step_body(Context& ctx, const mpoevo_step_opts* opts, const mpoevo_mps* mps, const mpoevo_mpo* mpo,
+                  const void* ws, const std::vector<int>& Q, bool profiling, bool u1, bool warm_on,
+                  hipStream_t& st, Body& body, StepPost post) {
+  *post.graph_use = 0;
+  if (!opts->use_graph || profiling || u1) return body();
+  const int L = mps->L;
+  std::vector<long long> key = {L, mps->d, mps->Dmax, opts->prec, opts->nsweeps, opts->nsites,
+                                opts->input_right_canonical, opts->svd_cold_start, warm_on ? 1 : 0,
+                                (long long)(uintptr_t)ws, ctx.tuner ? gemm_tuner_mode(ctx.tuner, -1) : -1,
+                                ctx.tuner ? (long long)gemm_tuner_generation(ctx.tuner) : -1};
+  long long cut = 0;
+  std::memcpy(&cut, &opts->cutoff, sizeof(cut));
+  key.push_back(cut);
+  for (int i = 0; i < L; ++i) {
+    key.push_back((long long)(uintptr_t)mps->site[i]);
+    key.push_back((long long)(uintptr_t)mpo->site[i]);
+  }
+  for (int i = 0; i <= L; ++i) {
+    key.push_back(Q[i]);
+    key.push_back(mpo->w[i]);
+  }
+  for (size_t i = 0; i < ctx.warm_dim.size(); ++i) {
+    key.push_back(ctx.warm_dim[i]);
+    key.push_back(ctx.warm_deficient[i]);
+  }
+  DeviceState& ds = *ctx.dev;
+  // a plan is captured the second time it is seen: the first step with it runs uncaptured, which
+  // lets the tile tuner time the products it has not seen (it cannot while a stream is captured)
+  if (std::find(ds.seen.begin(), ds.seen.end(), key) == ds.seen.end()) {
+    bool cached = false;
+    for (const GraphEntry& g : ds.graphs) cached = cached || g.key == key;
+    if (!cached) {
+      if (ds.seen.size() >= 2 * kMaxGraphs) ds.seen.erase(ds.seen.begin());
+      ds.seen.push_back(key);
+      return body();
+    }
+  }
+  for (GraphEntry& g : ds.graphs) {
+    if (g.key != key) continue;
+    const hipError_t e = hipGraphLaunch(g.exec, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step: replaying the captured graph");
+    *post.P = g.P;
+    *post.bond_of_visit = g.bond_of_visit;
+    *post.k_slot_of_bond = g.k_slot_of_bond;
+    *post.last_visit_k_slot = g.last_visit_k_slot;
+    *post.gflop = g.gflop;
+    *post.one_site = g.one_site;
+    *post.updates = g.updates;
+    *post.graph_use = 2;
+    ctx.warm_dim = g.warm_dim;
+    return MPOEVO_OK;
+  }
+  if (!ds.capture_stream) {
+    const hipError_t e = hipStreamCreateWithFlags(&ds.capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step: creating the capture stream");
+  }
+  const hipStream_t orig = st;
+  st = ds.capture_stream;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    st = orig;
+    return hip_fail(ctx, e, "step: beginning the graph capture");
+  }
+  const bool coop = ctx.coop_jacobi;
+  ctx.coop_jacobi = false;
+  const int rc = body();
+  ctx.coop_jacobi = coop;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(st, &graph);
+  st = orig;
+  if (rc != MPOEVO_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "step: ending the graph capture");
+  GraphEntry g;
+  g.key = std::move(key);
+  g.graph = graph;
+  e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(ctx, e, "step: instantiating the captured graph");
+  }
+  g.P = *post.P;
+  g.bond_of_visit = *post.bond_of_visit;
+  g.k_slot_of_bond = *post.k_slot_of_bond;
+  g.last_visit_k_slot = *post.last_visit_k_slot;
+  g.gflop = *post.gflop;
+  g.one_site = *post.one_site;
+  g.updates = *post.updates;
+  g.warm_dim = ctx.warm_dim;
+  if (ds.graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(ds.graphs.front().exec);
+    (void)hipGraphDestroy(ds.graphs.front().graph);
+    ds.graphs.erase(ds.graphs.begin());
+  }
+  ds.graphs.push_back(std::move(g));
+  *post.graph_use = 1;
+  e = hipGraphLaunch(ds.graphs.back().exec, st);
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "step: launching the captured graph");
+}
+
 int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
              mpoevo_step_stats* stats, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
@@ -1100,6 +1246,20 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     if (e != hipSuccess) return hip_fail(ctx, e, "step"); \
   } while (0)
 
+  // ---------------------------------------------------------------- the step's device work
+  // Everything from here to the final normalisation is issued without waiting for the device, so
+  // that it can be captured into a HIP graph once and replayed by later steps with the same plan.
+  int visit = 0;
+  const int nvis = opts->nsweeps * 2 * (L - 1);
+  int last_visit_k_slot = 0;
+  std::vector<int> k_slot_of_bond(L, -1);
+  std::vector<int> bond_of_visit(nvis, 0);
+  bool one_site = false;
+  int updates = 0;
+  std::vector<int> u1_k(u1 ? nvis : 0);
+  std::vector<double> u1_d(u1 ? nvis : 0), u1_n(u1 ? nvis : 0);
+  std::vector<int> u1_zero(u1 ? nvis : 0, 0), u1_one(u1 ? nvis : 0, 1);
+  auto body = [&]() -> int {
   // inputs in contraction precision; phi <- psi
   for (int i = 0; i < L; ++i) {
     const long long ns = (long long)Q[i] * d * Q[i + 1];
@@ -1164,7 +1324,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     for (int k = 0; k < std::min(b, L - b) && c < Dmax; ++k) c *= d;
     return (int)std::min<long long>(c, Dmax);
   };
-  bool one_site = opts->nsites == 1;
+  one_site = opts->nsites == 1;
   if (opts->nsites == -1) {
     one_site = d * Dmax <= 512 && !u1;
     for (int b = 1; b < L && one_site; ++b) one_site = P[b] == cap_of(b);
@@ -1198,7 +1358,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       flop_gemm(P[i], (double)w[i] * Q[i], (double)d * P[i + 1]);
     }
     STEP_TRY(set_boundary(envL(0), w[0], fp64, st));
-    int updates = 0;
+    updates = 0;
     for (int sw = 0; sw < opts->nsweeps; ++sw) {
       for (int i = 0; i <= L - 2; ++i, ++updates) {
         STEP_TRY(left_block(ar, envL(i), ket(i), wsite(i), tmp, blk, P[i], w[i], Q[i], d, Q[i + 1],
@@ -1239,52 +1399,6 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                          (long long)P[0] * d * P[1], nbuf);
       return hipGetLastError();
     }());
-    double norm = 0.0;
-    STEP_TRY(hipMemcpyAsync(&norm, nbuf, sizeof(double), hipMemcpyDeviceToHost, st));
-    for (int i = 0; i < L; ++i) {  // the bonds are the guess's: copy phi back whole
-      STEP_TRY(hipMemcpyAsync(mps->site[i], phi(i), sizeof(double2) * (size_t)P[i] * d * P[i + 1],
-                              hipMemcpyDeviceToDevice, st));
-    }
-    STEP_TRY(hipStreamSynchronize(st));
-    const int sres = check_solver_dev(ctx);
-    if (sres != MPOEVO_OK) return sres;
-    int maxb = 1;
-    for (int b = 0; b <= L; ++b) {
-      mps->bond_dim[b] = P[b];
-      maxb = std::max(maxb, P[b]);
-    }
-    if (stats) {
-      std::memset(stats, 0, sizeof(*stats));
-      stats->norm = norm;
-      stats->visits = updates;
-      stats->max_bond = maxb;
-      stats->gflop = gflop;
-      if (prof) {
-        struct Agg { int kind; int n; double ms, work; };
-        std::map<const void*, Agg> per_kernel;
-        for (const auto& r : prof->recs) {
-          float ms = 0.f;
-          STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.e0], ctx.dev->events[r.e0 + 1]));
-          const int kind = r.kind == Prof::kGemm ? 1 : r.kind == Prof::kQr ? 3 : 2;
-          if (kind == 1) { stats->t_gemm_ms += ms; stats->gemm_gflop += r.work * 1e-9; stats->n_gemm += 1; }
-          if (kind == 2) { stats->t_wmix_ms += ms; stats->wmix_gbyte += r.work * 1e-9; stats->n_wmix += 1; }
-          Agg& a = per_kernel[r.launch.kernel];
-          a.kind = kind;
-          a.n += 1;
-          a.ms += ms;
-          a.work += r.work * 1e-9;
-        }
-        std::vector<std::pair<const void*, Agg>> order(per_kernel.begin(), per_kernel.end());
-        std::stable_sort(order.begin(), order.end(),
-                         [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
-        for (const auto& kv : order) {
-          if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
-          fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first, kv.second.kind, false,
-                           kv.second.n, kv.second.ms, kv.second.work, st);
-        }
-      }
-    }
-    if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
     return MPOEVO_OK;
   }
 
@@ -1301,11 +1415,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     }
   }
 
-  int visit = 0;
-  const int nvis = opts->nsweeps * 2 * (L - 1);
   // U(1): the truncation of a visit per charge block (kept rank, weight and norm known on the host)
-  std::vector<int> u1_k(u1 ? nvis : 0);
-  std::vector<double> u1_d(u1 ? nvis : 0), u1_n(u1 ? nvis : 0);
   auto u1_visit = [&](int i, int m, int n, int dir, int vis) -> hipError_t {
     BlockedResult br;
     MPOEVO_HIP_TRY(blocked_truncate(ctx, theta, m, n, row_charges(i), col_charges(i + 2), Dmax, opts->cutoff, dir,
@@ -1316,9 +1426,6 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     qch[i + 1] = br.charges;
     return hipSuccess;
   };
-  int last_visit_k_slot = 0;
-  std::vector<int> k_slot_of_bond(L, -1);
-  std::vector<int> bond_of_visit(nvis, 0);
   for (int sw = 0; sw < opts->nsweeps; ++sw) {
     // left to right
     for (int i = 0; i <= L - 2; ++i, ++visit) {
@@ -1418,7 +1525,6 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       STEP_TRY(bra_refresh(i + 1));
     }
   }
-  std::vector<int> u1_zero(u1 ? nvis : 0, 0), u1_one(u1 ? nvis : 0, 1);
   if (u1) {  // the visit slots the dense truncation fills on the device
     STEP_TRY(hipMemcpyAsync(kbuf, u1_k.data(), sizeof(int) * nvis, hipMemcpyHostToDevice, st));
     STEP_TRY(hipMemcpyAsync(dbuf, u1_d.data(), sizeof(double) * nvis, hipMemcpyHostToDevice, st));
@@ -1433,6 +1539,67 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                        st, phi(0), (long long)P[0] * d * P[1], nbuf + last_visit_k_slot);
     return hipGetLastError();
   }());
+    return MPOEVO_OK;
+  };
+
+  int graph_use = 0;
+  if (const int rc = run_step_body(ctx, opts, mps, mpo, ws, Q, prof != nullptr, u1, warm_on, st, body,
+                                   StepPost{&P, &bond_of_visit, &k_slot_of_bond, &last_visit_k_slot, &gflop,
+                                            &one_site, &updates, &graph_use});
+      rc != MPOEVO_OK)
+    return rc;
+
+  if (one_site) {
+    double norm = 0.0;
+    STEP_TRY(hipMemcpyAsync(&norm, nbuf, sizeof(double), hipMemcpyDeviceToHost, st));
+    for (int i = 0; i < L; ++i) {  // the bonds are the guess's: copy phi back whole
+      STEP_TRY(hipMemcpyAsync(mps->site[i], phi(i), sizeof(double2) * (size_t)P[i] * d * P[i + 1],
+                              hipMemcpyDeviceToDevice, st));
+    }
+    STEP_TRY(hipStreamSynchronize(st));
+    const int sres = check_solver_dev(ctx);
+    if (sres != MPOEVO_OK) return sres;
+    int maxb = 1;
+    for (int b = 0; b <= L; ++b) {
+      mps->bond_dim[b] = P[b];
+      maxb = std::max(maxb, P[b]);
+    }
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->norm = norm;
+      stats->visits = updates;
+      stats->max_bond = maxb;
+      stats->gflop = gflop;
+      stats->graph = graph_use;
+      if (prof) {
+        struct Agg { int kind; int n; double ms, work; };
+        std::map<const void*, Agg> per_kernel;
+        for (const auto& r : prof->recs) {
+          float ms = 0.f;
+          STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.e0], ctx.dev->events[r.e0 + 1]));
+          const int kind = r.kind == Prof::kGemm ? 1 : r.kind == Prof::kQr ? 3 : 2;
+          if (kind == 1) { stats->t_gemm_ms += ms; stats->gemm_gflop += r.work * 1e-9; stats->n_gemm += 1; }
+          if (kind == 2) { stats->t_wmix_ms += ms; stats->wmix_gbyte += r.work * 1e-9; stats->n_wmix += 1; }
+          Agg& a = per_kernel[r.launch.kernel];
+          a.kind = kind;
+          a.n += 1;
+          a.ms += ms;
+          a.work += r.work * 1e-9;
+        }
+        std::vector<std::pair<const void*, Agg>> order(per_kernel.begin(), per_kernel.end());
+        std::stable_sort(order.begin(), order.end(),
+                         [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
+        for (const auto& kv : order) {
+          if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
+          fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first, kv.second.kind, false,
+                           kv.second.n, kv.second.ms, kv.second.work, st);
+        }
+      }
+    }
+    if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
+    return MPOEVO_OK;
+  }
+
   // read back the kept ranks and statistics (one synchronisation per step)
   std::vector<int> kh(nvis), swh(nvis), ch(nvis);
   std::vector<double> dh(nvis), nh(nvis);
@@ -1493,6 +1660,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     stats->t_wmix_ms = stats->wmix_gbyte = 0.0;
     stats->n_jacobi = stats->n_gemm = stats->n_wmix = 0;
     stats->n_kernel_stats = 0;
+    stats->graph = graph_use;
     if (prof) {
       const std::vector<int>& sw = swh;
       struct Agg { int kind; int split; int n; double ms, work; };

@@ -1045,6 +1045,7 @@ struct Tuner {
   std::mutex mu;
   int mode = MPOEVO_TUNE_OFF;
   std::map<TuneKey, Plan> table;
+  unsigned long long generation = 0;  // bumped when the mode changes or the table is cleared
   hipEvent_t ev[2] = {nullptr, nullptr};
   ~Tuner() {
     for (hipEvent_t e : ev)
@@ -1148,8 +1149,17 @@ void gemm_tuner_free(void* t) { delete static_cast<Tuner*>(t); }
 int gemm_tuner_mode(void* t, int set) {
   auto* tu = static_cast<Tuner*>(t);
   std::lock_guard<std::mutex> lk(tu->mu);
-  if (set >= 0) tu->mode = set;
+  if (set >= 0 && set != tu->mode) {
+    tu->mode = set;
+    ++tu->generation;
+  }
   return tu->mode;
+}
+
+unsigned long long gemm_tuner_generation(void* t) {
+  auto* tu = static_cast<Tuner*>(t);
+  std::lock_guard<std::mutex> lk(tu->mu);
+  return tu->generation;
 }
 
 size_t gemm_tuner_entries(void* t) {
@@ -1162,6 +1172,7 @@ void gemm_tuner_clear(void* t) {
   auto* tu = static_cast<Tuner*>(t);
   std::lock_guard<std::mutex> lk(tu->mu);
   tu->table.clear();
+  ++tu->generation;
 }
 
 TunerScope::TunerScope(void* t, bool allow) : prev_(t_tuner), prev_allow_(t_tune_allowed) {

@@ -51,6 +51,7 @@ void gemm_tuner_free(void* t);
 int gemm_tuner_mode(void* t, int set);  // set < 0: query only; returns the mode
 size_t gemm_tuner_entries(void* t);
 void gemm_tuner_clear(void* t);
+unsigned long long gemm_tuner_generation(void* t);  // changes with the mode and on every clear
 // The plan a product of this shape (operands contiguous along k and n) takes with tuner t
 // (nullable): out = {tile rows, tile columns, K splits, 1 if tuned else 0}.
 int gemm_plan_query(void* t, int prec, int M, int N, int K, int batch, int* out);
