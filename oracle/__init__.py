@@ -8,7 +8,11 @@ Modules
   mpo    -- level bookkeeping, powers of the Hamiltonian MPO and the construction of
             the order-N time-evolution MPO (Sec. 2.5, Alg. 1, Alg. 2, Alg. 3, Alg. 4).
   fit    -- environments, projected two-site tensor, FP64 SVD truncation and the
-            variational sweeping fit of W|psi> at fixed maximal bond dimension (Sec. 2.2).
+            variational sweeping fit of W|psi> at fixed maximal bond dimension (Sec. 2.2):
+            two-site and one-site, from a right-canonical or a zip-up guess; overlaps and
+            MPO expectation values.
+  u1     -- the two-site fit with U(1)-symmetric tensors stored as dictionaries of charge
+            blocks (Sec. 2.4 XXZ example).
   dense  -- dense references for tiny chains: contracted operators, exact exponentials,
             MPS <-> state vectors.
 

@@ -81,12 +81,45 @@ def boundary_env(w: int):
     return E
 
 
-def fit_step(psi, Ws, Dmax: int, nsweeps: int = 2, cutoff: float = 1e-14):
+def zipup_guess(psi, Ws, Dmax: int, cutoff: float = 1e-14):
+    """Zip-up application of W to psi (Sec. 2.2, Table 1 zip-up row): W|psi> compressed site by
+    site with SVDs, without bringing psi into canonical form first. Readings (the paper only
+    names the method): the zip runs from the right end to the left, so that its sites come out
+    right-orthonormal, as the two-site fit wants its guess. A carry C[k, beta, b] (k: the new bond
+    to the right, beta: the MPO bond, b: psi's bond) starts as the right boundary (level 0); at
+    site i = L-1 .. 1 the matrix
+        X[(alpha, a), (s', k)] = sum_{s, b, beta} W_i[alpha, s', s, beta] psi_i[a, s, b] C[k, beta, b]
+    is split by an FP64 SVD truncated like every bond of the fit (svd_truncate: k' = min(Dmax,
+    #{sigma > cutoff sigma_1}) >= 1), the site becomes V^dag (k', s', k) and the carry (U S)^T
+    (k', alpha, a). Site 0 is X at the left boundary level alpha = 0; it holds the norm.
+    Returns (sites, stats) with stats = dict(discarded (per bond L-1 .. 1), bond_dims)."""
+    L = len(psi)
+    if not isinstance(Ws, (list, tuple)):
+        Ws = [Ws] * L
+    C = boundary_env(Ws[-1].shape[3])
+    out = [None] * L
+    discarded = []
+    for i in range(L - 1, 0, -1):
+        X = np.einsum('ypsz,asb,kzb->yapk', Ws[i], psi[i], C)
+        y, a, p, k = X.shape
+        U, S, Vh, disc = svd_truncate(X.reshape(y * a, p * k), Dmax, cutoff)
+        discarded.append(disc)
+        kk = S.size
+        out[i] = Vh.reshape(kk, p, k)
+        C = (U * S[None, :]).T.reshape(kk, y, a)
+    X = np.einsum('ypsz,asb,kzb->yapk', Ws[0], psi[0], C)
+    out[0] = X[0].reshape(psi[0].shape[0], X.shape[2], X.shape[3])
+    dims = [1] + [out[i].shape[2] for i in range(L)]
+    return out, dict(discarded=discarded, bond_dims=dims)
+
+
+def fit_step(psi, Ws, Dmax: int, nsweeps: int = 2, cutoff: float = 1e-14, guess=None):
     """One time step: variational two-site fit of W|psi> at bonds <= Dmax (module docstring).
 
-    psi: list of L site tensors; Ws: one MPO tensor or a list of L; returns (phi, stats) with phi
-    normalised (unless W|psi> projects to zero) and stats = dict(norm, discarded (per visit),
-    bond_dims)."""
+    psi: list of L site tensors; Ws: one MPO tensor or a list of L; guess: the starting phi, whose
+    sites 1 .. L-1 must be right-orthonormal (default: psi right-canonicalised; zipup_guess gives
+    another); returns (phi, stats) with phi normalised (unless W|psi> projects to zero) and
+    stats = dict(norm, discarded (per visit), bond_dims)."""
     L = len(psi)
     if not isinstance(Ws, (list, tuple)):
         Ws = [Ws] * L
@@ -94,7 +127,7 @@ def fit_step(psi, Ws, Dmax: int, nsweeps: int = 2, cutoff: float = 1e-14):
         phi0 = np.einsum('apsb,xsy->xpy', Ws[0][:1, :, :, :1], psi[0])  # boundary level 0 in and out
         n = np.linalg.norm(phi0)
         return [phi0 / n if n > 0 else phi0], dict(norm=float(n), discarded=[], bond_dims=[1, 1])
-    phi = right_canonicalize(psi)
+    phi = right_canonicalize(psi) if guess is None else [m.copy() for m in guess]
     Lenv = [None] * (L + 1)
     Renv = [None] * (L + 1)
     Lenv[0] = boundary_env(Ws[0].shape[0])
