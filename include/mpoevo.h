@@ -273,7 +273,24 @@ typedef struct {
                    graph runs one node at a time; other work on the device meanwhile can delay them
                    to their bounded-wait timeout, ESOLVER); the arithmetic is that of the
                    uncaptured step, so the results are the same bit for bit. 0: no graph. */
+  int guess;     /* the MPS the sweeps start from. MPOEVO_GUESS_CANONICAL (0): psi, brought to
+                   right-canonical form unless input_right_canonical. MPOEVO_GUESS_ZIPUP (1): the
+                   zip-up application of W to psi (Sec. 2.2, Table 1 zip-up row), from the right
+                   end, in FP64 whatever prec: at site i = L-1 .. 1 the matrix
+                   X[(alpha, a), (s', k)] = sum W_i[alpha, s', s, beta] psi_i[a, s, b] C[k, beta, b]
+                   (C: the carry, the right boundary level at the start) is split by the FP64 SVD
+                   truncation of every bond (Dmax, cutoff), the site becomes V^dag and the carry
+                   (U S)^T; site 0 is X at the left boundary level. The guess then has bonds up to
+                   Dmax at once instead of growing from psi's during the sweeps (psi need not be
+                   canonical). Two-site updates only, no U(1) charges, and every X must have at most
+                   d Dmax rows, i.e. bond[i] w[i] <= d Dmax (EUNSUPPORTED otherwise): the zip-up
+                   is for states with small bonds (a product state, the first steps of a quench).
+                   MPOEVO_GUESS_AUTO (-1): the zip-up where it applies, nsites is not 1 and some
+                   bond of psi is below its largest value min(Dmax, d^i, d^(L-i)) (the step then
+                   runs two-site updates), else 0. */
 } mpoevo_step_opts;
+
+enum { MPOEVO_GUESS_AUTO = -1, MPOEVO_GUESS_CANONICAL = 0, MPOEVO_GUESS_ZIPUP = 1 };
 
 #define MPOEVO_MAX_KERNEL_STATS 16
 typedef struct {
@@ -313,6 +330,7 @@ typedef struct {
   mpoevo_kernel_stat kernel_stats[MPOEVO_MAX_KERNEL_STATS];
   int graph;                /* opts->use_graph: 0 the work was issued launch by launch, 1 it was
                                captured into a new graph (then launched), 2 a graph replayed it */
+  int guess;                /* the guess the sweeps started from: 0 psi, 1 the zip-up */
 } mpoevo_step_stats;
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,

@@ -246,6 +246,9 @@ int check_opts(mpoevo::Context* ctx, const std::string& who, const mpoevo_step_o
   if (opts->profile < 0 || opts->profile > 2) return fail(ctx, MPOEVO_EINVAL, who + ": profile must be 0, 1 or 2");
   if (opts->nsites < -1 || opts->nsites > 2) return fail(ctx, MPOEVO_EINVAL, who + ": nsites must be -1, 0, 1 or 2");
   if (opts->use_graph < 0 || opts->use_graph > 1) return fail(ctx, MPOEVO_EINVAL, who + ": use_graph must be 0 or 1");
+  if (opts->guess < -1 || opts->guess > 1) return fail(ctx, MPOEVO_EINVAL, who + ": guess must be -1, 0 or 1");
+  if (opts->guess == MPOEVO_GUESS_ZIPUP && opts->nsites == 1)
+    return fail(ctx, MPOEVO_EUNSUPPORTED, who + ": the zip-up guess is followed by two-site updates only");
   return MPOEVO_OK;
 }
 }  // namespace
@@ -261,6 +264,8 @@ int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_s
     return fail(ctx, MPOEVO_ENOMEM, "step: workspace too small");
   if (mps->sector_table && opts->nsites == 1)
     return fail(ctx, MPOEVO_EUNSUPPORTED, "step: one-site updates of U(1) chains are not built");
+  if (mps->sector_table && opts->guess == MPOEVO_GUESS_ZIPUP)
+    return fail(ctx, MPOEVO_EUNSUPPORTED, "step: the zip-up guess of U(1) chains is not built");
   return mpoevo::step_dev(*ctx, mps, mpo, opts, stats, workspace, workspace_bytes, stream);
 }
 

@@ -198,6 +198,17 @@ __global__ void compact_site(const double2* __restrict__ src, double2* __restric
   }
 }
 
+// E[c][r] = A[r][c] for an m x k matrix A (the zip-up's carry (U S)^T).
+__global__ void transpose_c128(const double2* __restrict__ A, double2* __restrict__ E, int m, int k) {
+  const long long n = (long long)m * k;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(i % m);
+    const long long c = i / m;
+    E[i] = A[(long long)r * k + c];
+  }
+}
+
 int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
 
 hipError_t cast_to_c64(const void* in, void* out, long long n, hipStream_t st) {
@@ -996,6 +1007,43 @@ int expectation_dev(Context& ctx, const mpoevo_mps* mps, const mpoevo_mpo* mpo, 
 }
 
 // ---------------------------------------------------------------------------------- the step
+// The zip-up guess: bond bounds K (K[i] = min(Dmax, rows, columns) of the SVD at site i, the
+// carry's bond) and its buffers inside the region of the environment blocks (free until the
+// sweeps build them): X and the contraction's temporaries, all FP64, U S and two carries.
+struct ZipPlan {
+  bool ok = false;
+  std::vector<int> K;
+  size_t offX = 0, offT = 0, offXws = 0, offA = 0, offE0 = 0, offE1 = 0;
+};
+
+ZipPlan zip_plan(int L, int d, int Dmax, const std::vector<int>& Q, const int* w, size_t region) {
+  ZipPlan z;
+  z.K.assign(L + 1, 1);
+  const size_t c16 = sizeof(double2);
+  size_t xb = 0, tb = 0, xwb = 0, ab = 0, eb = c16 * (size_t)w[L];
+  for (int i = L - 1; i >= 0; --i) {
+    const long long m = (long long)w[i] * Q[i], n = (long long)d * z.K[i + 1];
+    xb = std::max(xb, c16 * (size_t)(m * n));
+    tb = std::max(tb, c16 * (size_t)Q[i] * d * z.K[i + 1] * w[i + 1]);
+    xwb = std::max(xwb, wcontract_xws(Q[i], z.K[i + 1], d, w[i], w[i + 1], c16));
+    if (i == 0) break;
+    if (m > (long long)d * Dmax) return z;  // beyond the SVD's workspace
+    z.K[i] = (int)std::min<long long>(Dmax, std::min(m, n));
+    ab = std::max(ab, c16 * (size_t)(m * z.K[i]));
+    eb = std::max(eb, c16 * (size_t)(m * z.K[i]));
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += a256(bytes); return at; };
+  z.offX = take(xb);
+  z.offT = take(tb);
+  z.offXws = take(xwb);
+  z.offA = take(ab);
+  z.offE0 = take(eb);
+  z.offE1 = take(eb);
+  z.ok = o <= region;
+  return z;
+}
+
 // Host state the device work of a step leaves behind.
 struct StepPost {
   std::vector<int>* P;
@@ -1024,7 +1072,7 @@ int run_step_body(Context& ctx, const mpoevo_step_opts* opts, const mpoevo_mps* 
   *post.graph_use = 0;
   if (!opts->use_graph || profiling || u1) return body();
   const int L = mps->L;
-  std::vector<long long> key = {L, mps->d, mps->Dmax, opts->prec, opts->nsweeps, opts->nsites,
+  std::vector<long long> key = {L, mps->d, mps->Dmax, opts->prec, opts->nsweeps, opts->nsites, opts->guess,
                                 opts->input_right_canonical, opts->svd_cold_start, warm_on ? 1 : 0,
                                 (long long)(uintptr_t)ws, ctx.tuner ? gemm_tuner_mode(ctx.tuner, -1) : -1,
                                 ctx.tuner ? (long long)gemm_tuner_generation(ctx.tuner) : -1};
@@ -1246,6 +1294,24 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     if (e != hipSuccess) return hip_fail(ctx, e, "step"); \
   } while (0)
 
+  // the guess: psi, or the zip-up of W psi (bonds up to Dmax at once)
+  auto cap_of = [&](int b) {
+    long long c = 1;
+    for (int k = 0; k < std::min(b, L - b) && c < Dmax; ++k) c *= d;
+    return (int)std::min<long long>(c, Dmax);
+  };
+  const ZipPlan zp = zip_plan(L, d, Dmax, Q, w, lay.off_env0 - lay.off_lb);
+  bool zip = false;
+  if (opts->guess == MPOEVO_GUESS_ZIPUP) {
+    if (!zp.ok) {
+      ctx.err = "step: the zip-up guess needs bond[i] w[i] <= d Dmax at every site i >= 1";
+      return MPOEVO_EUNSUPPORTED;
+    }
+    zip = true;
+  } else if (opts->guess == MPOEVO_GUESS_AUTO && !u1 && zp.ok && opts->nsites != 1) {
+    for (int b = 1; b < L && !zip; ++b) zip = Q[b] < cap_of(b);
+  }
+
   // ---------------------------------------------------------------- the step's device work
   // Everything from here to the final normalisation is issued without waiting for the device, so
   // that it can be captured into a HIP graph once and replayed by later steps with the same plan.
@@ -1283,8 +1349,43 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       for (int b = 0; b < P[bond]; ++b) c[(size_t)t * P[bond] + b] = qch[bond][b] - qp[t];
     return c;
   };
-  // right-canonical guess: SVD of each site from the last to the second
-  if (!opts->input_right_canonical && u1) {
+  if (zip) {
+    // zip-up from the right end in FP64: X_i = W_i psi_i C_{i+1}, rows (alpha, a), columns
+    // (s', k); its truncated SVD gives phi_i = V^dag and the next carry C_i = (U S)^T
+    const Arith ar64{true, false};
+    unsigned char* zb = base + lay.off_lb;
+    double2* X = reinterpret_cast<double2*>(zb + zp.offX);
+    void* T = zb + zp.offT;
+    void* XW = zb + zp.offXws;
+    double2* A = reinterpret_cast<double2*>(zb + zp.offA);
+    double2* Ec = reinterpret_cast<double2*>(zb + zp.offE0);
+    double2* En = reinterpret_cast<double2*>(zb + zp.offE1);
+    const std::vector<int>& K = zp.K;
+    STEP_TRY(set_boundary(Ec, w[L], true, st));
+    for (int i = L - 1; i >= 0; --i) {
+      STEP_TRY(right_block(ar64, mps->site[i], Ec, mpo->site[i], T, X, Q[i], d, Q[i + 1], K[i + 1], w[i],
+                           w[i + 1], st, prof, gws, XW));
+      flop_gemm((double)Q[i] * d, (double)K[i + 1] * w[i + 1], Q[i + 1]);
+      flop_gemm((double)w[i] * d * Q[i], K[i + 1], (double)d * w[i + 1]);
+      if (i == 0) {  // the left boundary level: the first d K[1] entries of X
+        STEP_TRY(hipMemcpyAsync(phi(0), X, sizeof(double2) * (size_t)Q[0] * d * K[1], hipMemcpyDeviceToDevice,
+                                st));
+        P[0] = Q[0];
+        break;
+      }
+      const int m = w[i] * Q[i], n = d * K[i + 1];
+      const SvdPlan sp = svd_qr_ok(m, n, MPOEVO_RIGHT) ? svd_plan_qr(m, n, MPOEVO_RIGHT)
+                                                       : svd_plan(m, n, MPOEVO_RIGHT);
+      STEP_TRY(svd_truncate(sp, X, Dmax, opts->cutoff, A, phi(i), nullptr, nullptr, nullptr, nullptr, svdws,
+                            ctx.dev->status, st, nullptr, nullptr, nullptr, nullptr, nullptr, ctx.coop_jacobi));
+      STEP_TRY([&] {
+        hipLaunchKernelGGL(transpose_c128, dim3(grid_for((long long)m * K[i])), dim3(256), 0, st, A, En, m, K[i]);
+        return hipGetLastError();
+      }());
+      std::swap(Ec, En);
+      P[i] = K[i];
+    }
+  } else if (!opts->input_right_canonical && u1) {  // right-canonical guess: SVD of each site from the last to the second
     for (int i = L - 1; i >= 1; --i) {  // per charge block: the rows a carry q(a), columns (s, b) q(b) - q(s)
       const int m = P[i], n = d * P[i + 1];
       BlockedResult br;
@@ -1319,13 +1420,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
 
   // ------------------------------------------------------------------ one-site updates
   // at the bonds of the guess (fixed): each site's projected tensor becomes its FP64 QR factor
-  auto cap_of = [&](int b) {
-    long long c = 1;
-    for (int k = 0; k < std::min(b, L - b) && c < Dmax; ++k) c *= d;
-    return (int)std::min<long long>(c, Dmax);
-  };
   one_site = opts->nsites == 1;
-  if (opts->nsites == -1) {
+  if (opts->nsites == -1 && !zip) {
     one_site = d * Dmax <= 512 && !u1;
     for (int b = 1; b < L && one_site; ++b) one_site = P[b] == cap_of(b);
   }
@@ -1661,6 +1757,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     stats->n_jacobi = stats->n_gemm = stats->n_wmix = 0;
     stats->n_kernel_stats = 0;
     stats->graph = graph_use;
+    stats->guess = zip ? 1 : 0;
     if (prof) {
       const std::vector<int>& sw = swh;
       struct Agg { int kind; int split; int n; double ms, work; };

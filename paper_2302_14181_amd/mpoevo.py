@@ -46,7 +46,8 @@ class _MPO(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("nsweeps", ctypes.c_int), ("prec", ctypes.c_int), ("cutoff", ctypes.c_double),
                 ("input_right_canonical", ctypes.c_int), ("profile", ctypes.c_int),
-                ("svd_cold_start", ctypes.c_int), ("nsites", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("svd_cold_start", ctypes.c_int), ("nsites", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("guess", ctypes.c_int)]
 
 
 MAX_KERNEL_STATS = 16
@@ -67,7 +68,7 @@ class _Stats(ctypes.Structure):
                 ("t_wmix_ms", ctypes.c_double), ("wmix_gbyte", ctypes.c_double), ("n_wmix", ctypes.c_int),
                 ("svd_sweeps_total", ctypes.c_int), ("svd_sweeps_hist", ctypes.c_int * 32),
                 ("n_kernel_stats", ctypes.c_int), ("kernel_stats", _KernelStat * MAX_KERNEL_STATS),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("guess", ctypes.c_int)]
 
 
 _lib = None
@@ -316,6 +317,7 @@ class StepStats:
     svd_sweeps_total: int = 0
     svd_sweeps_hist: tuple = ()
     graph: int = 0  # use_graph: 0 issued launch by launch, 1 captured into a new graph, 2 replayed
+    guess: int = 0  # the guess the sweeps started from: 0 psi, 1 the zip-up
 
 
 class DeviceMPS:
@@ -413,12 +415,14 @@ def _default_step_workspace(h: "Handle", mps: DeviceMPS, mpo: DeviceMPO, prec: i
 
 
 NSITES_AUTO = -1  # step option: one-site updates once every bond is at its largest value
+# step option guess: psi (right-canonicalised), the zip-up of W psi, or the zip-up while bonds grow
+GUESS_AUTO, GUESS_CANONICAL, GUESS_ZIPUP = -1, 0, 1
 
 
 def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int = FP64,
          cutoff: float = 1e-14, input_right_canonical: bool = False, workspace=None,
          stream=None, profile=False, svd_cold_start: bool = False, nsites: int = 2,
-         use_graph: bool = False) -> StepStats:
+         use_graph: bool = False, guess: int = 0) -> StepStats:
     """One time step of the variational fit; mps is updated in place (see include/mpoevo.h).
     profile: False, True (time every kernel class) or PROFILE_JACOBI (the Jacobi kernel only).
     Without a workspace the MPS object's own default workspace is used (kept between calls)."""
@@ -428,7 +432,8 @@ def step(h: Handle, mps: DeviceMPS, mpo: DeviceMPO, nsweeps: int = 2, prec: int 
     wsites = (ctypes.c_void_p * mpo.L)(*[t.data_ptr() for t in mpo.buf])
     cw = _MPO(mpo.L, mpo.d, _iarr(mpo.w), wsites)
     opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
-                 int(bool(svd_cold_start)), int(nsites), int(bool(use_graph)))
+                 int(bool(svd_cold_start)), int(nsites), int(bool(use_graph)),
+                 int(guess))
     st = _Stats()
     _check(load().step(h.ptr, ctypes.byref(cm), ctypes.byref(cw), ctypes.byref(opts), ctypes.byref(st),
                        _ptr(workspace), workspace.numel(), _stream(stream)), h)
@@ -492,7 +497,8 @@ def _stats_of(st, profile) -> StepStats:
                             "split_k": bool(k.split_k), "launches": k.launches, "ms": k.ms, "work": k.work}
                            for k in st.kernel_stats[:st.n_kernel_stats]]
     return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
-                     st.svd_sweeps_max, prof, st.svd_sweeps_total, tuple(st.svd_sweeps_hist), st.graph)
+                     st.svd_sweeps_max, prof, st.svd_sweeps_total, tuple(st.svd_sweeps_hist), st.graph,
+                     st.guess)
 
 
 def step_batched_workspace(chains, mpos, prec: int):
@@ -504,7 +510,7 @@ def step_batched_workspace(chains, mpos, prec: int):
 
 def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cutoff: float = 1e-14,
                  input_right_canonical: bool = False, workspace=None, stream=None, profile: bool = False,
-                 svd_cold_start: bool = False, nsites: int = 2, use_graph: bool = False):
+                 svd_cold_start: bool = False, nsites: int = 2, use_graph: bool = False, guess: int = 0):
     """One time step of every chain (lists of DeviceMPS and DeviceMPO of equal length), advanced
     concurrently by the library; each MPS is updated in place. Returns one StepStats per chain."""
     if len(chains) != len(mpos) or not chains:
@@ -525,7 +531,8 @@ def step_batched(h: Handle, chains, mpos, nsweeps: int = 2, prec: int = FP64, cu
         cms[c] = cm
         cws[c] = _MPO(mpo.L, mpo.d, w, wsites)
     opts = _Opts(nsweeps, prec, cutoff, int(bool(input_right_canonical)), _profile_code(profile),
-                 int(bool(svd_cold_start)), int(nsites), int(bool(use_graph)))
+                 int(bool(svd_cold_start)), int(nsites), int(bool(use_graph)),
+                 int(guess))
     st = (_Stats * n)()
     _check(load().step_batched(h.ptr, n, cms, cws, ctypes.byref(opts), st, _ptr(workspace),
                                workspace.numel(), _stream(stream)), h)
