@@ -124,7 +124,16 @@ def lr_blocks(wl):
     return wl.lr_ising(np.array(fit["coeffs"]), np.array(fit["lambdas"]), 1.0)
 
 
-def trajectory(torch, mp, h, psi0, dw, prec, steps, Dmax, profile=False, progress=None, nsites=2):
+GUESS_DESC = {"canonical": "", "zipup": ", each step from the zip-up of W psi",
+              "auto": ", from the zip-up of W psi while the bonds grow"}
+
+
+def guess_of(mp, args):
+    return {"canonical": mp.GUESS_CANONICAL, "zipup": mp.GUESS_ZIPUP, "auto": mp.GUESS_AUTO}[args.guess]
+
+
+def trajectory(torch, mp, h, psi0, dw, prec, steps, Dmax, profile=False, progress=None, nsites=2, guess=0,
+               use_graph=False):
     """`steps` time steps from psi0 on a fresh MPS and workspace; HIP events on the launch stream
     around every step. Returns (ms per step, StepStats per step, the final DeviceMPS)."""
     dm = mp.DeviceMPS(psi0, Dmax=Dmax)
@@ -135,11 +144,12 @@ def trajectory(torch, mp, h, psi0, dw, prec, steps, Dmax, profile=False, progres
     ev[0].record()
     for k in range(steps):
         st.append(mp.step(h, dm, dw, prec=prec, input_right_canonical=k > 0, workspace=ws, profile=profile,
-                          nsites=nsites))
+                          nsites=nsites, guess=guess, use_graph=use_graph))
         ev[k + 1].record()
         if progress:
             print(f"[bench] {progress} step {k + 1}/{steps}: bond {st[-1].max_bond}, "
-                  f"{'one' if st[-1].discarded_sum == 0 and st[-1].visits % 2 == 1 else 'two'}-site",
+                  f"{'one' if st[-1].discarded_sum == 0 and st[-1].visits % 2 == 1 else 'two'}-site"
+                  f"{', zip-up guess' if st[-1].guess else ''}{', graph' if st[-1].graph else ''}",
                   file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
@@ -245,6 +255,21 @@ def lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, Dmax, delta2=True):
                               "Z50_error": float(abs(ofit.expect_local(phi, wl.SZ, LR_SITE).real - z_or)),
                               "norm_rel_error": float(abs(s.norm - r1["norm"]) / r1["norm"])}
         del dm
+    # step 1 from the zip-up of W psi0 (bonds up to Dmax before the sweeps; its oracle parity is a
+    # GPU test at L = 8, the oracle's zip-up fit at this size takes a minute)
+    zs = {}
+    for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64)):
+        dm = mp.DeviceMPS(psi0, Dmax=Dmax)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s = mp.step(h, dm, dw, prec=p, guess=mp.GUESS_ZIPUP)
+        torch.cuda.synchronize()
+        zs[name] = {"ms": (time.perf_counter() - t1) * 1e3, "max_bond": s.max_bond,
+                    "eps": float(1.0 - abs(mp.overlap(h, dm, dw, dpsi0)) ** 2 / n2),
+                    "norm": s.norm}
+        del dm
+    zs["oracle_eps_canonical_guess"] = eps_or
+    out["step1_zipup_guess"] = zs
     if delta2:
         ref2, r2 = ofit.fit_step(ref1, Wo, Dmax=Dmax)
         z2 = ofit.expect_local(ref2, wl.SZ, LR_SITE).real
@@ -310,9 +335,15 @@ def run_lr3(args, torch, mp, wl, h):
     psi0 = wl.all_up(LR_L)
     prog = "lr3" if args.progress else None
     ns = args.nsites
+    gs, gr = guess_of(mp, args), args.graph
     if Wm:  # untimed warm-up steps of the same trajectory on their own state and workspace
-        trajectory(torch, mp, h, psi0, dw, prec, Wm, LR_D, progress=prog and prog + " warm-up", nsites=ns)
-    ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, K, LR_D, profile=True, progress=prog, nsites=ns)
+        trajectory(torch, mp, h, psi0, dw, prec, Wm, LR_D, progress=prog and prog + " warm-up", nsites=ns,
+                   guess=gs, use_graph=gr)
+    ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, K, LR_D, profile=not gr, progress=prog, nsites=ns,
+                            guess=gs, use_graph=gr)
+    if gr:  # the kernel table from the same steps profiled launch by launch (untimed)
+        _, st, dmp = trajectory(torch, mp, h, psi0, dw, prec, K, LR_D, profile=True, nsites=ns, guess=gs)
+        del dmp
     sec = float(np.sum(ms)) / 1e3 / K
     kt = kernel_table(st, args.prec)
     prof = {k: float(sum(x.profile[k] for x in st)) for k in st[0].profile if k != "kernels"}
@@ -327,7 +358,7 @@ def run_lr3(args, torch, mp, wl, h):
     if not args.no_fp64 and prec != mp.FP64:
         n64 = max(1, min(args.fp64_steps or K, K))
         ms64, st64, dm64 = trajectory(torch, mp, h, psi0, dw, mp.FP64, n64, LR_D, profile=True,
-                                      progress=prog and prog + " fp64", nsites=ns)
+                                      progress=prog and prog + " fp64", nsites=ns, guess=gs)
         p64 = {k: float(sum(x.profile[k] for x in st64)) for k in st64[0].profile if k != "kernels"}
         fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
                 "fp32_s_per_step_same_steps": float(np.sum(ms[:n64])) / 1e3 / n64,
@@ -360,7 +391,8 @@ def run_lr3(args, torch, mp, wl, h):
         "dtype": DTYPES[args.prec], "data": "synthetic",
         "config": {"workload": f"long-range Ising L={LR_L}, J(r)=r^-2 as 6 exponentials, g=1, order-{LR_ORDER} "
                                f"extended MPO (w={w}), tau={LR_TAU} (real time), D<={LR_D}, all-up start, "
-                               f"2 sweeps per step ({NSITES_DESC[ns]}), steps 1..{K} from t=0",
+                               f"2 sweeps per step ({NSITES_DESC[ns]}){GUESS_DESC[args.guess]}"
+                               f"{', steps replayed from HIP graphs' if gr else ''}, steps 1..{K} from t=0",
                    "L": LR_L, "D": LR_D, "order": LR_ORDER, "tau": LR_TAU, "w": w},
         "step_ms": ms,
         "max_bond_per_step": [x.max_bond for x in st],
@@ -796,9 +828,14 @@ def run_quench(args, torch, mp, wl, h, side=False):
     W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, ORDER, -1j * TAU, mp.V2_EXTENDED)
     dw = mp.DeviceMPO([W] * L)
     prog = ("quench" if args.progress else None)
+    gs, gr = (0, False) if side else (guess_of(mp, args), args.graph)
     if not side and args.warmup:
-        trajectory(torch, mp, h, psi0, dw, prec, args.warmup, D)
-    ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, steps, D, profile=True, progress=prog)
+        trajectory(torch, mp, h, psi0, dw, prec, args.warmup, D, guess=gs, use_graph=gr)
+    ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, steps, D, profile=not gr, progress=prog, guess=gs,
+                            use_graph=gr)
+    if gr:  # the kernel table from the same steps profiled launch by launch (untimed)
+        _, st, dmp = trajectory(torch, mp, h, psi0, dw, prec, steps, D, profile=True, guess=gs)
+        del dmp
     sec = float(np.sum(ms)) / 1e3 / steps
     kt = kernel_table(st, pname)
     Id = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
@@ -806,11 +843,13 @@ def run_quench(args, torch, mp, wl, h, side=False):
     zops[31] = wl.SZ.reshape(1, 2, 2, 1)
     dZ = mp.DeviceMPO(zops)
     out = {"workload": f"TFIM quench L={L} from the g=0.5 ground state to g={G_AFTER}, order-{ORDER} extended "
-                       f"MPO (w={W.shape[0]}), tau={TAU}, D<={D}, steps 1..{steps} from t=0",
+                       f"MPO (w={W.shape[0]}), tau={TAU}, D<={D}"
+                       f"{'' if side else GUESS_DESC[args.guess]}"
+                       f"{', steps replayed from HIP graphs' if gr else ''}, steps 1..{steps} from t=0",
            "s_per_step": sec, "steps": steps, "max_bond_last_step": st[-1].max_bond,
            "dominant_kernel": roofline_of(kt[0])}
     if (side or not args.no_fp64) and prec != mp.FP64:
-        ms64, _, dm64 = trajectory(torch, mp, h, psi0, dw, mp.FP64, steps, D)
+        ms64, _, dm64 = trajectory(torch, mp, h, psi0, dw, mp.FP64, steps, D, guess=gs, use_graph=gr)
         a, b = dm.to_numpy(), dm64.to_numpy()
         out["fp64_s_per_step"] = float(np.sum(ms64)) / 1e3 / steps
         out["fp32_speedup"] = out["fp64_s_per_step"] / sec
@@ -871,6 +910,11 @@ def main():
     ap.add_argument("--workload", choices=["lr3", "quench", "xxz", "batched", "env", "split", "thermal",
                                            "cylinder"], default="lr3")
     ap.add_argument("--progress", action="store_true", help="print a line to stderr after every timed step")
+    ap.add_argument("--guess", choices=["canonical", "zipup", "auto"], default="canonical",
+                    help="lr3 and quench: the sweeps' starting point (psi, the zip-up of W psi, or the zip-up "
+                         "while the bonds grow)")
+    ap.add_argument("--graph", action="store_true",
+                    help="lr3 and quench: replay each step's launches from a captured HIP graph once its plan repeats")
     ap.add_argument("--order", type=int, default=ORDER, choices=[1, 2, 3, 4],
                     help="MPO order of the TFIM workloads (quench, split reference, thermal)")
     ap.add_argument("--tau", type=float, default=TAU, help="time step of the quench and split workloads")
