@@ -47,12 +47,16 @@ ancilla leg per site, d = 4): the order-2 MPO at tau = -0.05 on the physical leg
 against an order-3 run at dt = 0.0125 (standing in for the TDVP reference).
 
 --workload env: only the left environment update at D = 256, d = 2, w = 8, K calls per precision
-(default 100) timed with HIP events on the launch stream.
+(default 100) timed with HIP events on the launch stream; --env-w 271: the same at the long-range
+chain's MPO (w = 271, default 10 calls), whose products are the default line's dominant kernel.
+
+--workload copy: a plain 256 MiB device copy, K times (the calibration of the HBM counters).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
-                       [--no-cpu] [--no-fp64] [--no-delta2] [--no-side]
-                       [--workload lr3|quench|batched|env|split|thermal|cylinder] [--order N] [--tau T]
-                       [--progress]
+                       [--no-cpu] [--no-fp64] [--no-delta2] [--no-side] [--nsites -1|1|2]
+                       [--guess canonical|zipup|auto] [--graph] [--env-w 8|271]
+                       [--workload lr3|quench|xxz|batched|env|split|thermal|cylinder|copy]
+                       [--order N] [--tau T] [--quiet]
 """
 from __future__ import annotations
 
@@ -84,14 +88,32 @@ def prec_of(mp, name: str) -> int:
     return {"fp32": mp.FP32, "fp64": mp.FP64, "bf16x3": mp.BF16X3}[name]
 
 
-def env_microbench(mp, h, torch, prec: int, reps: int = 50):
-    """Time env_update (left) at D = 256, d = 2, w = 8 with HIP events on the launch stream."""
+def env_inputs(mp, wl, w: int):
+    """Operands of the environment microbenchmark: w = 8, the seeded complex-normal set of
+    workloads.env_microbench_inputs; w = 271, the long-range chain's order-3 MPO with E, ket and
+    bra (256, 271, 256), (256, 2, 256) x 2 complex normal from default_rng(0) in that order."""
+    if w == 8:
+        return wl.env_microbench_inputs(0)
+    H = lr_blocks(wl)
+    W, _ = mp.mpo_build(H.A, H.B, H.C, H.Dloc, LR_ORDER, -1j * LR_TAU, mp.V2_EXTENDED)
+    if W.shape[0] != w:
+        raise SystemExit(f"--env-w {w}: the long-range MPO has w = {W.shape[0]}")
+    rng = np.random.default_rng(0)
+    E = wl.complex_normal(rng, (256, w, 256))
+    M = wl.complex_normal(rng, (256, 2, 256))
+    N = wl.complex_normal(rng, (256, 2, 256))
+    return E, M, N, W
+
+
+def env_microbench(mp, h, torch, prec: int, reps: int = 50, w: int = 8):
+    """Time env_update (left) at D = 256, d = 2 and MPO bond w with HIP events on the launch stream."""
     from paper_2302_14181_amd import workloads as wl
-    E, M, N, W = wl.env_microbench_inputs(0)
+    E, M, N, W = env_inputs(mp, wl, w)
     dt = torch.complex128 if prec == mp.FP64 else torch.complex64
     t = {k: torch.from_numpy(v).to(dt).cuda() for k, v in dict(E=E, M=M, N=N, W=W).items()}
-    out = torch.empty((256, 8, 256), dtype=dt, device="cuda")
-    ws = torch.empty(mp.workspace_size(mp.CALL_ENV_UPDATE, [256, 256, 256, 256, 2, 8, 8], prec),
+    del E, M, N
+    out = torch.empty((256, w, 256), dtype=dt, device="cuda")
+    ws = torch.empty(mp.workspace_size(mp.CALL_ENV_UPDATE, [256, 256, 256, 256, 2, w, w], prec),
                      dtype=torch.uint8, device="cuda")
     for _ in range(3):
         mp.env_update(h, mp.LEFT, t["E"], t["N"], t["W"], t["M"], out, workspace=ws, prec=prec)
@@ -103,8 +125,10 @@ def env_microbench(mp, h, torch, prec: int, reps: int = 50):
     e.record()
     torch.cuda.synchronize()
     ms = s.elapsed_time(e) / reps
-    Dm, d, w = 256, 2, 8
+    Dm, d = 256, 2
     flop = 8.0 * (2 * Dm ** 3 * d * w + Dm ** 2 * d ** 2 * w ** 2)
+    del t, out, ws
+    torch.cuda.empty_cache()
     return ms, flop
 
 
@@ -380,8 +404,14 @@ def run_lr3(args, torch, mp, wl, h):
     parity = cpu = None
     if not args.no_cpu:
         Wo = ompo.build_mpo(H, LR_ORDER, -1j * LR_TAU, "V2")
+        if prog:
+            print("[bench] lr3 parity against the oracle (steps 1 and 2)", file=sys.stderr, flush=True)
         parity = lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, LR_D, delta2=not args.no_delta2)
+        if prog:
+            print("[bench] lr3 CPU oracle baseline", file=sys.stderr, flush=True)
         cpu = lr3_cpu_baseline(Wo, wl, LR_D)
+    if prog and not args.no_side:
+        print("[bench] side fields: quench steps 1-20, environment microbenchmark", file=sys.stderr, flush=True)
     side = {} if args.no_side else {"quench_L64_D128": run_quench(args, torch, mp, wl, h, side=True),
                                     "env_microbench": env_microbench_summary(mp, h, torch)}
     line = {
@@ -436,26 +466,53 @@ def env_microbench_summary(mp, h, torch):
 def run_env(args, torch, mp, h):
     """The environment-update microbenchmark alone: FP32 (three real products per complex
     multiply-add on the fp32 matrix cores), plain FP64 and split-BF16x3, K calls each."""
-    reps = max(1, args.steps or 100)
+    reps = max(1, args.steps or (100 if args.env_w == 8 else 10))
+    w = args.env_w
     res = {}
     for name in ("fp32", "fp64", "bf16x3"):
-        ms, flop = env_microbench(mp, h, torch, prec_of(mp, name), reps=reps)
+        ms, flop = env_microbench(mp, h, torch, prec_of(mp, name), reps=reps, w=w)
         peak = 78.6 if name == "fp64" else 157.3
         res[name] = {"us": ms * 1e3, "tflops": flop / ms / 1e9, "frac_of_peak": flop / ms / 1e9 / peak,
                      "peak_tflops": peak}
     f32 = res["fp32"]
+    opd = ("W (8, 2, 2, 8), seeded complex normal operands" if w == 8 else
+           f"W the long-range chain's order-3 MPO ({w}, 2, 2, {w}), seeded complex normal E and sites")
     print(json.dumps({
-        "metric": "env_update (left) TFLOP/s at D=256, d=2, w=8, FP32 matrix cores",
+        "metric": f"env_update (left) TFLOP/s at D=256, d=2, w={w}, FP32 matrix cores",
         "value": f32["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": 3,
         "ms_per_step": f32["us"] / 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "left environment update, E (256, 8, 256), ket/bra (256, 2, 256), "
-                               "W (8, 2, 2, 8), seeded complex normal operands",
-                   "flop_per_call": 8.0 * (2 * 256 ** 3 * 2 * 8 + 256 ** 2 * 2 ** 2 * 8 ** 2)},
+        "config": {"workload": f"left environment update, E (256, {w}, 256), ket/bra (256, 2, 256), " + opd,
+                   "flop_per_call": 8.0 * (2 * 256 ** 3 * 2 * w + 256 ** 2 * 2 ** 2 * w ** 2)},
         "roofline": {"bound": "mfma", "achieved": f32["tflops"], "peak": 157.3, "unit": "TFLOP/s",
                      "frac": f32["frac_of_peak"], "traffic": None},
         "precisions": res,
     }), flush=True)
+
+
+def run_copy(args, torch):
+    """Calibration of the HBM counters: a plain device copy of 256 MiB, K times (torch's copy
+    kernel); FETCH_SIZE and WRITE_SIZE per dispatch against the 256 MiB it reads and writes give
+    the scale factors of the counter tables in profiles/."""
+    n = 256 * 2 ** 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    reps = max(1, args.steps or 10)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    print(json.dumps({"metric": "device copy bandwidth (counter calibration)", "value": 2 * n / ms / 1e6,
+                      "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 0, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+                      "data": "synthetic", "config": {"workload": "device copy of 256 MiB", "bytes": n},
+                      "roofline": {"bound": "hbm", "achieved": 2 * n / ms / 1e6, "peak": PEAK_HBM / 1e9,
+                                   "unit": "GB/s", "frac": 2 * n / ms / 1e6 / (PEAK_HBM / 1e9),
+                                   "traffic": 2 * n}}), flush=True)
 
 
 def _overlap(a, b) -> complex:
@@ -908,8 +965,12 @@ def main():
                     help="lr3: local update (2: two-site; 1: one-site at fixed bonds; -1: two-site while the "
                          "bonds grow, one-site once all are at their largest value)")
     ap.add_argument("--workload", choices=["lr3", "quench", "xxz", "batched", "env", "split", "thermal",
-                                           "cylinder"], default="lr3")
-    ap.add_argument("--progress", action="store_true", help="print a line to stderr after every timed step")
+                                           "cylinder", "copy"], default="lr3")
+    ap.add_argument("--progress", action="store_true", default=True,
+                    help="print a line to stderr after every timed step and phase (the default)")
+    ap.add_argument("--quiet", dest="progress", action="store_false", help="no progress lines on stderr")
+    ap.add_argument("--env-w", type=int, default=8, choices=[8, 271],
+                    help="env workload: the MPO bond (8: the microbenchmark; 271: the long-range chain's MPO)")
     ap.add_argument("--guess", choices=["canonical", "zipup", "auto"], default="canonical",
                     help="lr3 and quench: the sweeps' starting point (psi, the zip-up of W psi, or the zip-up "
                          "while the bonds grow)")
@@ -940,6 +1001,9 @@ def main():
     from paper_2302_14181_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.workload == "copy":
+        run_copy(args, torch)
+        return
     h = mp.Handle(0)
     if args.workload == "env":
         run_env(args, torch, mp, h)

@@ -64,6 +64,11 @@ struct DeviceState {
   std::vector<GraphEntry> graphs;  // captured steps, oldest first
   std::vector<std::vector<long long>> seen;  // plans run once, uncaptured
   hipStream_t capture_stream = nullptr;
+  int cus = 0;  // compute units
+  // U(1) truncations: the charge blocks' SVDs fork from the step's stream to worker streams
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  std::vector<hipStream_t> block_streams;
 };
 
 namespace {
@@ -504,11 +509,15 @@ struct BlockedResult {
 // #{sigma > cutoff sigma_max}) >= 1, ties to the lower charge, then the earlier value), and the
 // factors are written densely with the kept indices in charge order: direction LEFT A = U
 // (m x k), B = S V^dag (k x n); RIGHT A = U S, B = V^dag. One stream synchronisation (the host
-// selects the kept values).
+// selects the kept values). The blocks' SVDs run side by side on up to four worker streams
+// (forked from st and joined back) when their workspaces (without split-K scratch) fit next to
+// each other in svdws (svd_bytes) and their grids fit on three quarters of the compute units
+// together (ordinary launches: the device must hold every running grid at once) and the step has
+// the device to itself; otherwise one after the other on st.
 hipError_t blocked_truncate(Context& ctx, const double2* X, int m, int n, const std::vector<int>& rq,
                             const std::vector<int>& cq, int Dmax, double cutoff, int direction,
                             double2* A, double2* B, unsigned char* scratch, int dim, void* svdws,
-                            hipStream_t st, BlockedResult& res) {
+                            size_t svd_bytes, hipStream_t st, BlockedResult& res) {
   std::map<int, std::vector<int>> rows, cols;
   for (int r = 0; r < m; ++r) rows[rq[r]].push_back(r);
   for (int c = 0; c < n; ++c) cols[cq[c]].push_back(c);
@@ -542,18 +551,53 @@ hipError_t blocked_truncate(Context& ctx, const double2* X, int m, int n, const 
   double* dd = reinterpret_cast<double*>(tail + a256(sizeof(int) * (size_t)dim));
   double* nd = dd + dim;
   MPOEVO_HIP_TRY(hipMemcpyAsync(idx_dev, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, st));
+  std::vector<SvdPlan> plans;
+  size_t wsmax = 0;
+  int gmax = 1;
+  for (const Blk& b : blks) {
+    plans.push_back(svd_plan_unsplit(svd_qr_ok(b.mq, b.nq, direction) ? svd_plan_qr(b.mq, b.nq, direction)
+                                                                      : svd_plan(b.mq, b.nq, direction)));
+    wsmax = std::max(wsmax, a256(plans.back().ws));
+    gmax = std::max(gmax, svd_grid(plans.back()));
+  }
+  DeviceState& ds = *ctx.dev;
+  const int nstreams = (int)std::min<size_t>({size_t(4), blks.size(), svd_bytes / std::max<size_t>(wsmax, 1),
+                                              size_t(std::max(1, (3 * ds.cus / 4) / gmax))});
+  // (only where this step has the device to itself: not for the chains of step_batched, whose
+  // streams already share it)
+  const bool par = nstreams > 1 && ctx.coop_jacobi;
+  if (par) {
+    while ((int)ds.block_streams.size() < nstreams) {
+      hipStream_t bs = nullptr;
+      MPOEVO_HIP_TRY(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+      ds.block_streams.push_back(bs);
+      hipEvent_t ev = nullptr;
+      MPOEVO_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      ds.joins.push_back(ev);
+    }
+    if (!ds.fork) MPOEVO_HIP_TRY(hipEventCreateWithFlags(&ds.fork, hipEventDisableTiming));
+    MPOEVO_HIP_TRY(hipEventRecord(ds.fork, st));
+    for (int s_ = 0; s_ < nstreams; ++s_) MPOEVO_HIP_TRY(hipStreamWaitEvent(ds.block_streams[s_], ds.fork, 0));
+  }
   for (size_t t = 0; t < blks.size(); ++t) {
     const Blk& b = blks[t];
+    const int lane = (int)(t % (size_t)nstreams);
+    hipStream_t bst = par ? ds.block_streams[lane] : st;
+    void* bws = par ? static_cast<unsigned char*>(svdws) + wsmax * lane : svdws;
     const int* r_dev = idx_dev + b.io;
     const int* c_dev = r_dev + b.mq;
-    hipLaunchKernelGGL(gather_block, dim3(grid_for((long long)b.mq * b.nq)), dim3(256), 0, st, X, n, r_dev, b.mq,
+    hipLaunchKernelGGL(gather_block, dim3(grid_for((long long)b.mq * b.nq)), dim3(256), 0, bst, X, n, r_dev, b.mq,
                        c_dev, b.nq, xq + b.xo);
     MPOEVO_HIP_TRY(hipGetLastError());
-    const SvdPlan pl = svd_qr_ok(b.mq, b.nq, direction) ? svd_plan_qr(b.mq, b.nq, direction)
-                                                         : svd_plan(b.mq, b.nq, direction);
-    MPOEVO_HIP_TRY(svd_truncate(pl, xq + b.xo, b.kcap, 0.0, aq + b.ao, bq + b.bo, kd + t, dd + t, nd + t,
-                                sig + b.so, svdws, ctx.dev->status, st, nullptr, nullptr, nullptr, nullptr,
-                                nullptr, ctx.coop_jacobi));
+    MPOEVO_HIP_TRY(svd_truncate(plans[t], xq + b.xo, b.kcap, 0.0, aq + b.ao, bq + b.bo, kd + t, dd + t, nd + t,
+                                sig + b.so, bws, ctx.dev->status, bst, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, par ? false : ctx.coop_jacobi));
+  }
+  if (par) {
+    for (int s_ = 0; s_ < nstreams; ++s_) {
+      MPOEVO_HIP_TRY(hipEventRecord(ds.joins[s_], ds.block_streams[s_]));
+      MPOEVO_HIP_TRY(hipStreamWaitEvent(st, ds.joins[s_], 0));
+    }
   }
   std::vector<double> sh(so);
   MPOEVO_HIP_TRY(hipMemcpyAsync(sh.data(), sig, sizeof(double) * so, hipMemcpyDeviceToHost, st));
@@ -708,6 +752,8 @@ int device_init(Context& ctx) {
   if (e != hipSuccess) return hip_fail(ctx, e, "svd_configure");
   auto* ds = new DeviceState();
   ds->lds_max = lds;
+  e = hipDeviceGetAttribute(&ds->cus, hipDeviceAttributeMultiprocessorCount, ctx.device);
+  if (e != hipSuccess) { delete ds; return hip_fail(ctx, e, "hipDeviceGetAttribute(compute units)"); }
   e = hipMalloc(&ds->status, 4 * sizeof(int));
   if (e != hipSuccess) { delete ds; return hip_fail(ctx, e, "hipMalloc(status)"); }
   e = hipMemset(ds->status, 0, 4 * sizeof(int));
@@ -748,6 +794,9 @@ void device_fini(Context& ctx) {
     if (g.graph) (void)hipGraphDestroy(g.graph);
   }
   if (ctx.dev->capture_stream) (void)hipStreamDestroy(ctx.dev->capture_stream);
+  if (ctx.dev->fork) (void)hipEventDestroy(ctx.dev->fork);
+  for (hipEvent_t ev : ctx.dev->joins) (void)hipEventDestroy(ev);
+  for (hipStream_t bs : ctx.dev->block_streams) (void)hipStreamDestroy(bs);
   (void)hipFree(ctx.dev->status);
   delete ctx.dev;
   ctx.dev = nullptr;
@@ -1390,7 +1439,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       const int m = P[i], n = d * P[i + 1];
       BlockedResult br;
       STEP_TRY(blocked_truncate(ctx, phi(i), m, n, qch[i], col_charges(i + 1), std::min(m, n), opts->cutoff,
-                                MPOEVO_RIGHT, theta, site_tmp, u1ws, d * Dmax, svdws, st, br));
+                                MPOEVO_RIGHT, theta, site_tmp, u1ws, d * Dmax, svdws, svd_ws_bound(d * Dmax), st,
+                                br));
       STEP_TRY(hipMemcpyAsync(phi(i), site_tmp, sizeof(double2) * (size_t)br.k * n, hipMemcpyDeviceToDevice, st));
       STEP_TRY(absorb_right(phi(i - 1), theta, site_tmp2, P[i - 1], d, m, br.k, st, gws));
       STEP_TRY(hipMemcpyAsync(phi(i - 1), site_tmp2, sizeof(double2) * (size_t)P[i - 1] * d * br.k,
@@ -1515,7 +1565,8 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   auto u1_visit = [&](int i, int m, int n, int dir, int vis) -> hipError_t {
     BlockedResult br;
     MPOEVO_HIP_TRY(blocked_truncate(ctx, theta, m, n, row_charges(i), col_charges(i + 2), Dmax, opts->cutoff, dir,
-                                    phi(i), phi(i + 1), u1ws, d * Dmax, svdws, st, br));
+                                    phi(i), phi(i + 1), u1ws, d * Dmax, svdws, svd_ws_bound(d * Dmax), st,
+                                    br));
     u1_k[vis] = br.k;
     u1_d[vis] = br.disc;
     u1_n[vis] = br.norm;

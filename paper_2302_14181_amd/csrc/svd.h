@@ -27,6 +27,7 @@ struct SvdPlan {
   int threads;     // threads per Jacobi workgroup (one pair per wave)
   size_t lds;      // dynamic LDS bytes of the Jacobi kernel
   size_t ws;       // workspace bytes
+  int split_ok;    // the products of the truncation may split K (their scratch ends the workspace)
 };
 
 // Early end of the Jacobi iteration for bond matrices formed by FP32 contractions (relative
@@ -55,6 +56,10 @@ SvdPlan svd_plan(int m, int n, int direction, bool want_basis = false,
 SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap = kSvdLdsBytes);
 // Whether the pivoted-QR plan applies: max(m, n) <= 512.
 bool svd_qr_ok(int m, int n, int direction);
+
+// The plan with products that never split K: its workspace drops the split-K scratch
+// (kGemmScratchBytes), so that several small truncations can run side by side in one buffer.
+SvdPlan svd_plan_unsplit(SvdPlan p);
 
 // Largest workspace of any plan with m, n <= maxdim (memoised).
 size_t svd_ws_bound(int maxdim);

@@ -1300,6 +1300,7 @@ void finish_plan(SvdPlan& p, size_t lds_cap) {
   p.np_alloc = p.np;
   p.aux_elems = 0;
   p.ws = ws_bytes(p.mx, p.nx, p.np, p.acc != 0, false, p.np_alloc, 0);
+  p.split_ok = 1;
 }
 
 bool svd_qr_ok(int m, int n, int direction) {
@@ -1339,10 +1340,19 @@ SvdPlan svd_plan_qr(int m, int n, int direction, size_t lds_cap) {
   p.np_alloc = std::max(p.np, q.np);
   p.aux_elems = std::max((size_t)p.mx * p.np, (size_t)q.mx * q.np);
   p.ws = ws_bytes(p.mx, p.nx, p.np, false, true, p.np_alloc, p.aux_elems);
+  p.split_ok = 1;
   return p;
 }
 
 SvdPlan svd_jacobi_plan(const SvdPlan& p) { return p.qr ? rdag_plan(p) : p; }
+
+SvdPlan svd_plan_unsplit(SvdPlan p) {
+  if (p.split_ok) {
+    p.split_ok = 0;
+    p.ws -= kGemmScratchBytes;
+  }
+  return p;
+}
 
 const void* svd_jacobi_kernel_ptr(const SvdPlan& p) { return jacobi_for(svd_jacobi_plan(p)); }
 
@@ -1379,7 +1389,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   if (warm) {  // X = Theta P (xconj 0) or Theta^dag P (xconj 1), column-major
     GemmDesc g{};
     g.batch = 1;
-    g.ws = w.gemm; g.ws_bytes = kGemmScratchBytes;
+    g.ws = p.split_ok ? w.gemm : nullptr; g.ws_bytes = p.split_ok ? kGemmScratchBytes : 0;
     g.A = theta; g.B = warm; g.C = w.X;
     g.M = p.mx; g.N = p.nx; g.K = p.nx;
     if (p.xconj == 0) { g.sAm = p.n; g.sAk = 1; }
@@ -1470,7 +1480,7 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
   }
   GemmDesc g{};
   g.batch = 1;
-  g.ws = w.gemm; g.ws_bytes = kGemmScratchBytes;
+  g.ws = p.split_ok ? w.gemm : nullptr; g.ws_bytes = p.split_ok ? kGemmScratchBytes : 0;
   if (p.direction == 0) {  // B_out = U_k^dag Theta  (kcap x n)
     g.A = A_out; g.B = theta; g.C = B_out;
     g.M = kcap; g.N = p.n; g.K = p.m;
