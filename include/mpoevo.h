@@ -250,9 +250,10 @@ typedef struct {
   int nsites;   /* 2 (or 0): two-site updates, bonds adapt up to Dmax by SVD truncation (above).
                    1: one-site updates at the fixed bond dimensions of psi (Sec. 2.2, Table 1 (ii);
                    Sec. 8.2 keeps the bond dimension fixed): each site's projected tensor
-                   L_i M_i W_i R_{i+1} becomes its FP64 Householder QR factor (column-pivoted; the
-                   left-to-right pass keeps Q of the (D_i d) x D_{i+1} matrix, the right-to-left
-                   pass the adjoint Q of the transposed problem), no SVD and no truncation;
+                   L_i M_i W_i R_{i+1} becomes its FP64 Householder QR factor (blocked, without
+                   pivoting; the left-to-right pass keeps Q of the (D_i d) x D_{i+1} matrix, the
+                   right-to-left pass the adjoint Q of the transposed problem), no SVD and no
+                   truncation;
                    a sweep is a left-to-right pass over the sites 0..L-2 and a right-to-left pass
                    over L-1..1, and after the last sweep the projected tensor of site 0 completes
                    phi (its norm is the fitted norm). Needs bond[i+1] <= d bond[i] after the guess

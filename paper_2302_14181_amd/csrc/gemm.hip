@@ -276,9 +276,10 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
 // 32 x 32 complex outputs) owns a BM x BN complex tile, double-buffered with one barrier per K
 // step of BK; with KW > 1 the groups take equal slices of every step (two waves per SIMD, so that
 // one wave's staging and barrier wait overlap the other's matrix instructions) and their partial
-// sums meet in LDS at the end, in group order. Tiles: 128 x 64 (one group), 64 x 64 (two groups),
-// 32 x 64 (four groups of 1 x 2 waves, BK = 64: 256 workgroups for a 256 x 2048 output without
-// splitting K).
+// sums meet in LDS at the end, in group order. Tiles: 128 x 128 (one group of 2 x 2 waves, each
+// 64 x 64: half the operand traffic per flop of 128 x 64, for the large products of wide MPO bonds),
+// 128 x 64 (one group), 64 x 64 (two groups), 32 x 64 (four groups of 1 x 2 waves, BK = 64: 256
+// workgroups for a 256 x 2048 output without splitting K).
 // Rounding: the sums carry one more rounding and Im C a difference of products, so its error
 // bound is about twice that of the expanded form, normwise.
 template <int WR, int WC, int BK_, int KW_, int WGM_>
@@ -901,7 +902,7 @@ Plan make_plan(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
   };
   Plan p{ncfg - 1, cfgs[ncfg - 1][0], cfgs[ncfg - 1][1], 1, g.K};
   for (int c = 0; c < ncfg; ++c)
-    if (tiles(c) >= kMinWgs) {
+    if (tiles(c) >= kMinWgs && cfgs[c][1] <= std::max(g.N, 64)) {  // no tile twice as wide as C
       p.cfg = c; p.bm = cfgs[c][0]; p.bn = cfgs[c][1];
       return p;
     }
@@ -956,7 +957,7 @@ hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   return hipSuccess;
 }
 
-constexpr int k3mCfg[3][2] = {{128, 64}, {64, 64}, {32, 64}};
+constexpr int k3mCfg[4][2] = {{128, 128}, {128, 64}, {64, 64}, {32, 64}};
 
 template <int WR, int WC, int BK, int KW, int WGM, typename TO>
 hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
@@ -1122,8 +1123,9 @@ hipError_t plan_and_run(const GemmDesc& g, const int (*cfgs)[2], int ncfg, int k
 
 template <typename TO>
 hipError_t run_3m(const GemmDesc& g, const Plan& pl, hipStream_t st) {
-  if (pl.cfg == 0) return launch_3m_cfg<2, 1, 16, 1, 2, TO>(g, pl, st);
-  if (pl.cfg == 1) return launch_3m_cfg<1, 1, 32, 2, 2, TO>(g, pl, st);
+  if (pl.cfg == 0) return launch_3m_cfg<2, 2, 16, 1, 2, TO>(g, pl, st);
+  if (pl.cfg == 1) return launch_3m_cfg<2, 1, 16, 1, 2, TO>(g, pl, st);
+  if (pl.cfg == 2) return launch_3m_cfg<1, 1, 32, 2, 2, TO>(g, pl, st);
   return launch_3m_cfg<1, 1, 64, 4, 1, TO>(g, pl, st);
 }
 
@@ -1195,7 +1197,7 @@ int gemm_plan_query(void* t, int prec, int M, int N, int K, int batch, int* out)
   int kind = 0;
   if (prec == MPOEVO_FP64) { p = make_plan<MfmaF64>(g, kF64Cfg, 2); kind = kKindF64; }
   else if (prec == MPOEVO_BF16X3) { p = make_plan<MfmaF32>(g, kF32Cfg, 3); kind = kKindBf16x3; }
-  else { p = make_plan<MfmaF32>(g, k3mCfg, 3); kind = kKind3m; }
+  else { p = make_plan<MfmaF32>(g, k3mCfg, 4); kind = kKind3m; }
   int tuned = 0;
   if (t) {
     auto* tu = static_cast<Tuner*>(t);
@@ -1216,8 +1218,8 @@ hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t 
   if (g.bf16x3)
     return out_fp64 ? plan_and_run<MfmaF32>(g, kF32Cfg, 3, kKindBf16x3, true, st, run_bf16x3<double>)
                     : plan_and_run<MfmaF32>(g, kF32Cfg, 3, kKindBf16x3, false, st, run_bf16x3<float>);
-  return out_fp64 ? plan_and_run<MfmaF32>(g, k3mCfg, 3, kKind3m, true, st, run_3m<double>)
-                  : plan_and_run<MfmaF32>(g, k3mCfg, 3, kKind3m, false, st, run_3m<float>);
+  return out_fp64 ? plan_and_run<MfmaF32>(g, k3mCfg, 4, kKind3m, true, st, run_3m<double>)
+                  : plan_and_run<MfmaF32>(g, k3mCfg, 4, kKind3m, false, st, run_3m<float>);
 }
 
 }  // namespace mpoevo

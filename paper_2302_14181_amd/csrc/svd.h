@@ -98,14 +98,15 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
                         double2* basis_out = nullptr, bool coop = true, int* complete_dev = nullptr,
                         int* blocks_dev = nullptr);
 
-// FP64 Householder QR with column pivoting of X = Theta (plan of svd_plan_qr with direction 1:
-// Theta m x n, m >= n) or X = Theta^dag (direction 0: Theta m x n, n >= m), written out as the
-// explicit thin Q (mx x nx, orthonormal columns spanning X's column space; where the
-// factorisation stops early at the rounding floor the remaining columns complete the basis):
-// adjoint false: out = Q row-major (mx x nx); adjoint true: out = Q^dag row-major (nx x mx).
-// For the one-site fit: Theta = its local tensor (rows (a', s'), columns b') with direction 1
-// gives the left-orthonormal site; Theta (rows a', columns (s', b')) with direction 0 and
-// adjoint true gives the right-orthonormal site. ws: the plan's workspace (p.ws bytes).
+// FP64 Householder QR of X = Theta (plan of svd_plan_qr with direction 1: Theta m x n, m >= n) or
+// X = Theta^dag (direction 0: Theta m x n, n >= m), without pivoting, blocked in panels of 16
+// columns (one workgroup per panel, compact-WY block reflectors), written out as the explicit thin
+// Q (mx x nx, orthonormal columns spanning X's column space when X has full column rank; an
+// orthonormal completion otherwise): adjoint false: out = Q row-major (mx x nx); adjoint true:
+// out = Q^dag row-major (nx x mx). For the one-site fit: Theta = its local tensor (rows (a', s'),
+// columns b') with direction 1 gives the left-orthonormal site; Theta (rows a', columns (s', b'))
+// with direction 0 and adjoint true gives the right-orthonormal site. ws: the plan's workspace
+// (p.ws bytes). coop: cooperative launch (the panels' workgroups wait on each other).
 hipError_t qr_isometry(const SvdPlan& p, const double2* theta, double2* out, bool adjoint, void* ws,
                        int* status, hipStream_t st, bool coop);
 

@@ -69,8 +69,6 @@ struct SvdWs {  // carved from the caller's workspace
   double* qrefl;        // [2][kMaxGrid][8] (qr) each candidate's reflector: tau, 1 / (alpha - beta), beta
   double2* qcol;        // [2][nb / 2][mx] (qr) each workgroup's candidate column
   int* qsteps;          // [1] (qr) steps taken (fewer than min(mx, nx) when the rest is exactly zero)
-  double2* qtau;        // [2 nx] (qr) tau and 1 / (alpha - beta) of every step's reflector (in aux,
-                        // which the Jacobi phase overwrites with R^dag afterwards)
   void* gemm;           // split-K scratch of the products (kGemmScratchBytes)
 };
 
@@ -117,10 +115,8 @@ SvdWs carve(const SvdPlan& p, void* ws) {
   w.qrefl = nullptr;
   w.qcol = nullptr;
   w.qsteps = nullptr;
-  w.qtau = nullptr;
   if (p.qr) {
     w.aux = reinterpret_cast<double2*>(base + off);
-    w.qtau = w.aux;
     off += align256(sizeof(double2) * p.aux_elems);
     w.qperm = reinterpret_cast<int*>(base + off);
     off += align256(sizeof(int) * p.np);
@@ -1051,13 +1047,11 @@ __global__ __launch_bounds__(kQrThreads) void svd_qrcp_grid_kernel(SvdPlan p, Sv
     const int k = wave;
     const bool mine_pivot = gg == g && c - c_lo == k;
     const double* r = w.qrefl + ((long long)par * kMaxGrid + gg) * 8;
-    if (mine_pivot) {  // R(j, j), the pivot and the reflector's scalars (for the explicit Q)
+    if (mine_pivot) {  // R(j, j) and the pivot
       if (lane == 0) {
         slab[(long long)k * m + j] = double2{r[4], 0.0};
         done[k] = 1;
         w.qperm[j] = c;
-        w.qtau[2 * j] = double2{r[0], r[1]};
-        w.qtau[2 * j + 1] = double2{r[2], r[3]};
       }
       continue;
     }
@@ -1139,59 +1133,308 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
   }
 }
 
-// Thin Q of the column-pivoted QR X Pi = Q R of an mx x nx matrix (svd_qrcp_grid_kernel, with the
-// pivot column of step j kept in X below row j and tau_j, sc_j kept per step): Q = H_0 H_1 ...
-// H_{r-1} [I; 0] with H_j = I - tau_j v_j v_j^dag, v_j = e_j + sc_j x_j (x_j the pivot column of
-// step j below row j), r the steps taken. Column t of Q is H_0 (H_1 (... H_{r-1} e_t)); one wave
-// per column, the rows in registers. out (adjoint 0): Q row-major (mx x nx), out[row nx + t];
-// (adjoint 1): Q^dag row-major (nx x mx), out[t mx + row] = conj(Q(row, t)).
-template <int RM>
-__global__ __launch_bounds__(256) void qr_formq_kernel(SvdPlan p, SvdWs w, double2* __restrict__ out,
-                                                       int adjoint) {
-  const int m = p.mx, n = p.nx;
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (t >= n) return;
-  const int r = min(max(*w.qsteps, 0), min(m, n));
-  double2 q[RM];
-#pragma unroll
-  for (int k = 0; k < RM; ++k) q[k] = double2{lane + 64 * k == t ? 1.0 : 0.0, 0.0};
-  for (int j = r - 1; j >= 0; --j) {
-    const double2 tv = w.qtau[2 * j], sc = w.qtau[2 * j + 1];
-    const double2* x = w.X + (long long)w.qperm[j] * m;
-    double2 xv[RM];
-    double dr = 0.0, di = 0.0, qr = 0.0, qi = 0.0;
-#pragma unroll
-    for (int k = 0; k < RM; ++k) {
-      const int row = lane + 64 * k;
-      xv[k] = (row > j && row < m) ? x[row] : double2{0.0, 0.0};
-      dr = fma(xv[k].x, q[k].x, fma(xv[k].y, q[k].y, dr));   // Re conj(x) q
-      di = fma(xv[k].x, q[k].y, fma(-xv[k].y, q[k].x, di));  // Im conj(x) q
-      if (row == j) { qr = q[k].x; qi = q[k].y; }
-    }
-    wave_sum2(dr, di);
-    wave_sum2(qr, qi);
-    // s = v^dag q = q_j + conj(sc) sum_{i>j} conj(x_i) q_i ;  H_j q = q - v (tau s)
-    const double2 s{qr + sc.x * dr + sc.y * di, qi + sc.x * di - sc.y * dr};
-    const double2 f = cmul(tv, s);
-    const double2 fs = cmul(sc, f);
-#pragma unroll
-    for (int k = 0; k < RM; ++k) {
-      const int row = lane + 64 * k;
-      if (row == j) q[k] = double2{q[k].x - f.x, q[k].y - f.y};
-      else if (row > j && row < m) {
-        const double2 d = cmul(xv[k], fs);
-        q[k] = double2{q[k].x - d.x, q[k].y - d.y};
+// Blocked Householder QR without pivoting of X (mx x nx, column-major in q.X, nx <= mx <= 512),
+// written out as the explicit thin Q (one-site updates: only the column space matters, any
+// orthonormal basis of it gives the same fitted state). Workgroup g owns the panel of columns
+// [16 g, 16 g + 16), one wave per column, held in LDS. Phase 1: for k = 0 .. g - 1 it waits for
+// panel k (flag), applies B_k^dag = I - V_k T_k^dag V_k^dag to its columns, then factorises its
+// own panel with 16 Householder steps (H_j = I - tau_j v_j v_j^dag, v_j(j) = 1, H_j^dag zeroes
+// column j below row j), forms the compact-WY T_g (B_g = H_0 ... H_15 = I - V_g T_g V_g^dag, T_g
+// upper triangular, column j: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^dag v_j),
+// publishes V_g (into its own columns of q.X: zeros above the diagonal, 1 on it) and T_g (q.T),
+// and raises its flag (release). The panels factorise one after the other, each as soon as the
+// panel before it has reached its columns. Phase 2: column block g of Q = B_0 ... B_{G-1} [I; 0]
+// is B_0 (B_1 (... B_g E_g)) (B_k leaves E_g alone for k > g): the workgroup starts from E_g and
+// applies B_g, B_{g-1}, ..., B_0. out (adjoint 0): Q row-major (mx x nx); (adjoint 1): Q^dag
+// row-major (nx x mx). Waits are bounded (barrier-timeout status).
+constexpr int kQbThreads = 1024;
+// Workspace of the blocked QR: X (mx x 16 G, column-major, the columns past nx zero), the panels'
+// T (G x 16 x 16) and G panel flags followed by an abort word.
+struct QbWs {
+  double2* X;
+  double2* T;
+  unsigned* flags;
+};
+size_t qb_bytes(int mx, int G) {
+  return align256(sizeof(double2) * (size_t)mx * 16 * G) + align256(sizeof(double2) * 256 * (size_t)G) +
+         align256(sizeof(unsigned) * (size_t)(G + 1));
+}
+QbWs qb_carve(int mx, int G, void* ws) {
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  QbWs q;
+  q.X = reinterpret_cast<double2*>(base);
+  base += align256(sizeof(double2) * (size_t)mx * 16 * G);
+  q.T = reinterpret_cast<double2*>(base);
+  base += align256(sizeof(double2) * 256 * (size_t)G);
+  q.flags = reinterpret_cast<unsigned*>(base);
+  return q;
+}
+
+// X = Theta (xconj 0) or Theta^dag (xconj 1) into the blocked QR's workspace; flags cleared.
+__global__ void qb_init_kernel(const double2* __restrict__ theta, SvdPlan p, QbWs q, int G) {
+  const long long total = (long long)p.mx * 16 * G;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / p.mx), row = (int)(idx % p.mx);
+    double2 v{0.0, 0.0};
+    if (j < p.nx) {
+      if (p.xconj == 0) v = theta[(long long)row * p.n + j];
+      else {
+        const double2 t = theta[(long long)j * p.n + row];
+        v = double2{t.x, -t.y};
       }
     }
+    q.X[idx] = v;
   }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i <= G; i += blockDim.x) q.flags[i] = 0u;
+}
+
+__global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs q, double2* __restrict__ out,
+                                                               int adjoint, int* status) {
+  extern __shared__ double2 cs[];  // [16][mx] the panel's columns
+  __shared__ double2 Ts[16][16], Ws[16][16];
+  __shared__ double2 tau_s[16], zs[2][16];
+  __shared__ int abort_s;
+  const int m = p.mx, n = p.nx, g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c0 = 16 * g;
+  double2* X = q.X;
+  double2* Tall = q.T;
+  unsigned* flags = q.flags;
+  unsigned* abort_word = q.flags + gridDim.x;
+  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
+    const int k = idx / m, r = idx % m;
+    cs[idx] = c0 + k < n ? X[(long long)(c0 + k) * m + r] : double2{0.0, 0.0};
+  }
+  if (tid == 0) abort_s = 0;
+  __syncthreads();
+
+  // C <- C - V_k (T_k^(dag) (V_k^dag C)) on the panel in LDS; V_k from w.X, rows from 16 k on
+  auto apply = [&](int k, bool adj) {
+    const double2* V = X + (long long)(16 * k) * m;
+    const int r0 = 16 * k;
+    for (int idx = tid; idx < 256; idx += kQbThreads) Ts[idx >> 4][idx & 15] = Tall[(long long)k * 256 + idx];
+    // W = V^dag C: 32 blocks of 2 x 4 entries (a in [2 ab, 2 ab + 2), c in [4 cb, 4 cb + 4)), two per
+    // wave, each summed over the rows by the wave's lanes
+    for (int blk = wv; blk < 32; blk += 16) {
+      const int ab = blk >> 2, cb = blk & 3;
+      double acc[2][4][2];
 #pragma unroll
-  for (int k = 0; k < RM; ++k) {
-    const int row = lane + 64 * k;
-    if (row >= m) continue;
-    if (adjoint) out[(long long)t * m + row] = double2{q[k].x, -q[k].y};
-    else out[(long long)row * n + t] = q[k];
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j][0] = acc[i][j][1] = 0.0;
+      for (int r = r0 + lane; r < m; r += 64) {
+        double2 v[2], x[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) v[i] = V[(long long)(2 * ab + i) * m + r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = cs[(4 * cb + j) * m + r];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {  // conj(v) x
+            acc[i][j][0] = fma(v[i].x, x[j].x, fma(v[i].y, x[j].y, acc[i][j][0]));
+            acc[i][j][1] = fma(v[i].x, x[j].y, fma(-v[i].y, x[j].x, acc[i][j][1]));
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          wave_sum2(acc[i][j][0], acc[i][j][1]);
+          if (lane == 0) Ws[2 * ab + i][4 * cb + j] = double2{acc[i][j][0], acc[i][j][1]};
+        }
+    }
+    __syncthreads();
+    double2 y{0.0, 0.0};
+    if (tid < 256) {  // Y = T W (B_k) or T^dag W (B_k^dag); T upper triangular
+      const int a = tid >> 4, c = tid & 15;
+      if (adj) {
+        for (int b = 0; b <= a; ++b) {
+          const double2 t = Ts[b][a], x = Ws[b][c];
+          y.x = fma(t.x, x.x, fma(t.y, x.y, y.x));
+          y.y = fma(t.x, x.y, fma(-t.y, x.x, y.y));
+        }
+      } else {
+        for (int b = a; b < 16; ++b) {
+          const double2 t = Ts[a][b], x = Ws[b][c];
+          y.x = fma(t.x, x.x, fma(-t.y, x.y, y.x));
+          y.y = fma(t.x, x.y, fma(t.y, x.x, y.y));
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 256) Ws[tid >> 4][tid & 15] = y;
+    __syncthreads();
+    // C(r, c) -= sum_a V(r, a) Y(a, c): two threads per row (m <= 512), eight columns each
+    const int half = tid >= 512 ? 1 : 0;
+    if (const int r = r0 + (tid & 511); r < m) {
+      double2 x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = cs[(8 * half + j) * m + r];
+      for (int a = 0; a < 16; ++a) {
+        const double2 v = V[(long long)a * m + r];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const double2 yy = Ws[a][8 * half + j];
+          x[j].x -= v.x * yy.x - v.y * yy.y;
+          x[j].y -= v.x * yy.y + v.y * yy.x;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cs[(8 * half + j) * m + r] = x[j];
+    }
+    __syncthreads();
+  };
+  auto wait_panel = [&](int k) -> bool {
+    if (tid == 0) {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(&flags[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+        if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > kBarrierTimeoutTicks) {
+          __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          abort_s = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return abort_s == 0;
+  };
+
+  // phase 1: the earlier panels' reflectors, then this panel's factorisation
+  for (int k = 0; k < g; ++k) {
+    if (!wait_panel(k)) {
+      if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
+      return;
+    }
+    apply(k, true);
   }
+  // the reflector of column j = c0 + jj (wave jj, its column up to date): beta = -sign(Re alpha) |x|,
+  // tau = (beta - alpha) / beta, v = x / (alpha - beta) below row j (stored in place), R(j, j) = beta
+  auto form = [&](int jj) {
+    const int j = c0 + jj;
+    double2* cj = cs + jj * m;
+    double sq = 0.0, dummy = 0.0;
+    for (int r = j + 1 + lane; r < m; r += 64) sq = fma(cj[r].x, cj[r].x, fma(cj[r].y, cj[r].y, sq));
+    wave_sum2(sq, dummy);
+    const double2 al = cj[j];
+    double2 tv{0.0, 0.0}, sc{0.0, 0.0};
+    double beta = al.x;
+    if (sq > 0.0 || al.y != 0.0) {
+      const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
+      beta = al.x >= 0.0 ? -xn : xn;
+      const double rb = 1.0 / beta;
+      tv = double2{(beta - al.x) * rb, -al.y * rb};
+      const double2 d{al.x - beta, al.y};
+      const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
+      sc = double2{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
+    }
+    for (int r = j + 1 + lane; r < m; r += 64) cj[r] = cmul(cj[r], sc);
+    if (lane == 0) {
+      cj[j] = double2{beta, 0.0};
+      tau_s[jj] = tv;
+    }
+  };
+  // column jj of T from the products z(l) = v_l^dag v_jj (l < jj), one entry per thread of wave 0
+  auto t_column = [&](int jj) {
+    if (tid < 16) {
+      const int i = tid;
+      const double2 t = tau_s[jj];
+      const double2* z = zs[jj & 1];
+      double2 v{0.0, 0.0};
+      if (i == jj) v = t;
+      else if (i < jj) {
+        double2 acc{0.0, 0.0};
+        for (int l = i; l < jj; ++l) {
+          const double2 pr = cmul(Ts[i][l], z[l]);
+          acc = double2{acc.x + pr.x, acc.y + pr.y};
+        }
+        const double2 q = cmul(t, acc);
+        v = double2{-q.x, -q.y};
+      }
+      Ts[i][jj] = v;
+    }
+  };
+  const int ncol = min(16, n - c0);  // columns of this panel
+  if (wv == 0) form(0);
+  __syncthreads();
+  // step jj: the later columns take H_jj^dag (column jj + 1 then forms the next reflector at once),
+  // the earlier ones give z for T's column jj, and T's column jj - 1 is completed meanwhile
+  for (int jj = 0; jj < ncol; ++jj) {
+    const int j = c0 + jj;
+    const double2* cj = cs + jj * m;
+    if (jj > 0) t_column(jj - 1);
+    if (wv != jj && wv < ncol) {
+      double2* ck = cs + wv * m;
+      const bool later = wv > jj;
+      double dr = 0.0, di = 0.0;
+      for (int r = j + 1 + lane; r < m; r += 64) {
+        const double2 a = later ? cj[r] : ck[r], b = later ? ck[r] : cj[r];  // conj(a) b
+        dr = fma(a.x, b.x, fma(a.y, b.y, dr));
+        di = fma(a.x, b.y, fma(-a.y, b.x, di));
+      }
+      wave_sum2(dr, di);
+      const double2 cjk = ck[j];
+      if (later) {  // s = v^dag col (v(j) = 1), col -= v conj(tau) s
+        const double2 sv{cjk.x + dr, cjk.y + di};
+        const double2 t = tau_s[jj];
+        const double2 f = cmul(double2{t.x, -t.y}, sv);
+        if (lane == 0) ck[j] = double2{cjk.x - f.x, cjk.y - f.y};
+        for (int r = j + 1 + lane; r < m; r += 64) {
+          const double2 d = cmul(cj[r], f);
+          ck[r] = double2{ck[r].x - d.x, ck[r].y - d.y};
+        }
+        if (wv == jj + 1) form(jj + 1);
+      } else if (lane == 0) {  // z = conj(v_wv(j)) + sum conj(v_wv) v_j
+        zs[jj & 1][wv] = double2{cjk.x + dr, -cjk.y + di};
+      }
+    }
+    __syncthreads();
+  }
+  t_column(ncol - 1);
+  for (int jj = ncol; jj < 16; ++jj)  // columns past nx: identity reflectors (tau 0)
+    if (tid < 16) Ts[tid][jj] = double2{0.0, 0.0};
+  __syncthreads();
+  // publish V_g (zeros above the diagonal, 1 on it) and T_g
+  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
+    const int k = idx / m, r = idx % m, j = c0 + k;
+    if (j >= n) continue;
+    double2 v{0.0, 0.0};
+    if (r == j) v = double2{1.0, 0.0};
+    else if (r > j) v = cs[idx];
+    X[(long long)j * m + r] = v;
+  }
+  if (tid < 256) Tall[(long long)g * 256 + tid] = Ts[tid >> 4][tid & 15];
+  __syncthreads();
+  if (tid == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&flags[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the compute unit's cache may still hold this panel's input columns, now V_g
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  // phase 2: column block g of Q
+  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
+    const int k = idx / m, r = idx % m;
+    cs[idx] = double2{r == c0 + k ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int k = g; k >= 0; --k) apply(k, false);
+  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
+    const int k = idx % 16, r = idx / 16, c = c0 + k;  // row-major runs of 16 columns
+    if (c >= n || adjoint) continue;
+    out[(long long)r * n + c] = cs[k * m + r];
+  }
+  if (adjoint)
+    for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
+      const int k = idx / m, r = idx % m, c = c0 + k;
+      if (c >= n) continue;
+      const double2 q = cs[idx];
+      out[(long long)c * m + r] = double2{q.x, -q.y};
+    }
 }
 
 // Y = R^dag into dst (q.mx = nx rows, q.np columns, column-major, columns from q.nx = min(mx, nx)
@@ -1249,6 +1492,8 @@ hipError_t svd_configure() {
   for (const void* f : {reinterpret_cast<const void*>(svd_qrcp_grid_kernel<4>),
                         reinterpret_cast<const void*>(svd_qrcp_grid_kernel<8>)})
     MPOEVO_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsBytes));
+  MPOEVO_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(qr_blocked_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsBytes));
   return hipSuccess;
 }
 
@@ -1498,42 +1743,30 @@ hipError_t svd_truncate(const SvdPlan& p, const double2* theta, int Dmax, double
 
 hipError_t qr_isometry(const SvdPlan& p, const double2* theta, double2* out, bool adjoint, void* ws,
                        int* status, hipStream_t st, bool coop) {
-  if (!p.qr || p.acc || p.mx < p.nx || std::max(p.mx, p.nx) > kQrMaxDim || p.nb / 2 > kMaxGrid ||
-      2 * p.b > kQrThreads / 64)
+  const int G = (p.nx + 15) / 16;
+  if (!p.qr || p.acc || p.mx < p.nx || p.mx > kQrMaxDim || G > kMaxGrid || qb_bytes(p.mx, G) > p.ws)
     return hipErrorInvalidConfiguration;
-  SvdWs w = carve(p, ws);
+  const QbWs q = qb_carve(p.mx, G, ws);
   {
-    const long long total = (long long)p.mx * p.np;
+    const long long total = (long long)p.mx * 16 * G;
     const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
-    hipLaunchKernelGGL(svd_init_kernel, dim3(blocks), dim3(256), 0, st, theta, p, w, 1, nullptr);
+    hipLaunchKernelGGL(qb_init_kernel, dim3(blocks), dim3(256), 0, st, theta, p, q, G);
     MPOEVO_HIP_TRY(hipGetLastError());
   }
-  {  // squared column norms of X for the factorisation's stopping test
-    const int wpb0 = 4;
-    hipLaunchKernelGGL(svd_norms_kernel, dim3((p.nx + wpb0 - 1) / wpb0), dim3(64 * wpb0), 0, st, p, w,
-                       status, 1);
-    MPOEVO_HIP_TRY(hipGetLastError());
-  }
-  {
-    SvdPlan pp = p;
-    SvdWs ww = w;
-    int* stp = status;
-    void* args[] = {&pp, &ww, &stp};
-    const size_t lds = sizeof(double2) * (size_t)(2 * p.b) * p.mx;
-    const void* fn = p.mx <= 256 ? reinterpret_cast<const void*>(svd_qrcp_grid_kernel<4>)
-                                 : reinterpret_cast<const void*>(svd_qrcp_grid_kernel<8>);
-    if (coop)
-      MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p.nb / 2), dim3(kQrThreads), args, (unsigned)lds, st));
-    else
-      MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(p.nb / 2), dim3(kQrThreads), args, lds, st));
-    last_launch() = LaunchRecord{fn, false};
-  }
-  const int blocks = (p.nx + 3) / 4;
-  if (p.mx <= 256)
-    hipLaunchKernelGGL(qr_formq_kernel<4>, dim3(blocks), dim3(256), 0, st, p, w, out, adjoint ? 1 : 0);
+  SvdPlan pp = p;
+  QbWs qq = q;
+  double2* o = out;
+  int adj = adjoint ? 1 : 0;
+  int* stp = status;
+  void* args[] = {&pp, &qq, &o, &adj, &stp};
+  const size_t lds = sizeof(double2) * 16 * (size_t)p.mx;
+  const void* fn = reinterpret_cast<const void*>(qr_blocked_kernel);
+  if (coop)
+    MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kQbThreads), args, (unsigned)lds, st));
   else
-    hipLaunchKernelGGL(qr_formq_kernel<8>, dim3(blocks), dim3(256), 0, st, p, w, out, adjoint ? 1 : 0);
-  return hipGetLastError();
+    MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(G), dim3(kQbThreads), args, lds, st));
+  last_launch() = LaunchRecord{fn, false};
+  return hipSuccess;
 }
 
 }  // namespace mpoevo

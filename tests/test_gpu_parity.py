@@ -113,8 +113,8 @@ def test_env_update_microbench_shape(mp, handle, prec64):
 @pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
 def test_env_update_large_bond_tiles(mp, handle, prec):
     """D = 64, w = 271 (the order-3 long-range MPO bond): the W contraction runs as batched
-    products of 542 x 64 outputs over 64 batches, which the planner puts on the largest tile
-    (128 x 64: 5 x 1 x 64 = 320 workgroups) -- the tile of the D = 256, w = 271 products. Both
+    products of 542 x 64 outputs over 64 batches, which the planner puts on the 128 x 64 tile
+    (5 x 1 x 64 = 320 workgroups; the 128 x 128 tile would be half empty at 64 columns). Both
     sides, element-wise against the oracle."""
     dims = (64, 64, 64, 64, 2, 271, 271)
     _say("env_update large-bond tile", dims, ["fp64", "fp32", "bf16x3"][prec])
@@ -138,10 +138,14 @@ def test_env_update_large_bond_tiles(mp, handle, prec):
 @pytest.mark.parametrize("prec", [1, 2, 0], ids=["fp32", "bf16x3", "fp64"])
 def test_env_update_d256_w271_sampled(mp, handle, prec):
     """The environment update at the full size of the long-range workload (D = 256, d = 2,
-    w = 271, both sides, on the 128 x 64 tiles): 48 sampled outputs, each computed by the oracle
-    from the definition restricted to that output index (the oracle cannot afford all 17.8 M)."""
+    w = 271, both sides; FP32 on the 128 x 128 three-product tiles, split-BF16x3 on 128 x 64): 48
+    sampled outputs, each computed by the oracle from the definition restricted to that output
+    index (the oracle cannot afford all 17.8 M)."""
     D, d, w = 256, 2, 271
     _say("env_update full size D=256 w=271 sampled", ["fp64", "fp32", "bf16x3"][prec])
+    if prec == mp.FP32:  # E . ket and the W contraction (batch D)
+        assert handle.product_plan(prec, D * w, d * D, D, 1)["tile"] == (128, 128)
+        assert handle.product_plan(prec, d * w, D, d * w, D)["tile"] == (128, 128)
     rng = np.random.default_rng(2562)
     bra, ket, W = _cn(rng, D, d, D), _cn(rng, D, d, D), _cn(rng, w, d, d, w)
     E = _cn(rng, D, w, D)
