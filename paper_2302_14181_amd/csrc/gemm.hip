@@ -310,7 +310,20 @@ struct Tile3 {
   }
 };
 
-template <int WR, int WC, int BK, int KW, int WGM, typename TO, bool AKC, bool BNC>
+// Tile of a workgroup when the grid is renumbered for the eight XCDs (each with its own L2), which
+// take the workgroups in turn: XCD x runs the x-th contiguous run of tiles (x fastest, then y,
+// then z), so the tiles sharing an operand row (or batch) meet in one L2 instead of eight.
+__device__ inline void xcd_tile(int& bx, int& by, int& bz) {
+  const unsigned gx = gridDim.x, gy = gridDim.y, total = gx * gy * gridDim.z;
+  const unsigned id = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const unsigned xcd = id % 8u, k = id / 8u, q = total / 8u, r = total % 8u;
+  const unsigned nid = xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+  bx = (int)(nid % gx);
+  by = (int)((nid / gx) % gy);
+  bz = (int)(nid / (gx * gy));
+}
+
+template <int WR, int WC, int BK, int KW, int WGM, typename TO, bool AKC, bool BNC, bool XCD = false>
 __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int splits,
                                                                  int kchunk, void* part) {
   using TT = Tile3<WR, WC, BK, KW, WGM>;
@@ -323,12 +336,14 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
   const int wq = wave % (2 * WGM);  // wave within its group
   const int kw = wave / (2 * WGM);  // wave group: the K slice [kw KG, (kw+1) KG) of every stage
   const int wm = wq >> 1, wn = wq & 1;
-  const int bz = blockIdx.z / splits;
-  const int sk = blockIdx.z - bz * splits;
+  int tx = blockIdx.x, ty = blockIdx.y, tz = blockIdx.z;
+  if (XCD) xcd_tile(tx, ty, tz);
+  const int bz = tz / splits;
+  const int sk = tz - bz * splits;
   const int kbeg = sk * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
-  const int m0 = blockIdx.y * TT::BM;
-  const int n0 = blockIdx.x * TT::BN;
+  const int m0 = ty * TT::BM;
+  const int n0 = tx * TT::BN;
 
   const C2* A = reinterpret_cast<const C2*>(g.A) + bz * g.bA;
   const C2* B = reinterpret_cast<const C2*>(g.B) + bz * g.bB;
@@ -959,7 +974,7 @@ hipError_t launch_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
 
 constexpr int k3mCfg[4][2] = {{128, 128}, {128, 64}, {64, 64}, {32, 64}};
 
-template <int WR, int WC, int BK, int KW, int WGM, typename TO>
+template <int WR, int WC, int BK, int KW, int WGM, typename TO, bool XCD = false>
 hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   using TT = Tile3<WR, WC, BK, KW, WGM>;
   dim3 grid((g.N + TT::BN - 1) / TT::BN, (g.M + TT::BM - 1) / TT::BM, g.batch * pl.splits);
@@ -967,19 +982,19 @@ hipError_t launch_3m_cfg(const GemmDesc& g, const Plan& pl, hipStream_t st) {
   const bool bnc = (g.sBn == 1) || (g.N == 1);
   void* part = pl.splits > 1 ? g.ws : nullptr;
   if (akc && bnc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, true, XCD>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else if (akc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, false, XCD>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else if (bnc)
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, true>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, true, XCD>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   else
-    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, false>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
+    hipLaunchKernelGGL((cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, false, XCD>), grid, dim3(TT::NT), 0, st, g, pl.splits, pl.kchunk, part);
   {
     const void* k = nullptr;
-    if (akc && bnc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, true>);
-    else if (akc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, false>);
-    else if (bnc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, true>);
-    else k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, false>);
+    if (akc && bnc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, true, XCD>);
+    else if (akc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, true, false, XCD>);
+    else if (bnc) k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, true, XCD>);
+    else k = reinterpret_cast<const void*>(cgemm3m_kernel<WR, WC, BK, KW, WGM, TO, false, false, XCD>);
     last_launch() = LaunchRecord{k, pl.splits > 1};
   }
   MPOEVO_HIP_TRY(hipGetLastError());
@@ -1123,7 +1138,7 @@ hipError_t plan_and_run(const GemmDesc& g, const int (*cfgs)[2], int ncfg, int k
 
 template <typename TO>
 hipError_t run_3m(const GemmDesc& g, const Plan& pl, hipStream_t st) {
-  if (pl.cfg == 0) return launch_3m_cfg<2, 2, 16, 1, 2, TO>(g, pl, st);
+  if (pl.cfg == 0) return launch_3m_cfg<2, 2, 16, 1, 2, TO, true>(g, pl, st);
   if (pl.cfg == 1) return launch_3m_cfg<2, 1, 16, 1, 2, TO>(g, pl, st);
   if (pl.cfg == 2) return launch_3m_cfg<1, 1, 32, 2, 2, TO>(g, pl, st);
   return launch_3m_cfg<1, 1, 64, 4, 1, TO>(g, pl, st);
