@@ -712,14 +712,16 @@ def run_batched(args, torch, mp, wl, h):
         else:
             ws = [mp.step_workspace(dm, dw, prec) for dm, dw in zip(dms, dws)]
         torch.cuda.synchronize()
-        ms, first = [], None
+        ms, first, graphs = [], None, []
         for k in range(steps):
             t0 = time.perf_counter()
             if batched:
-                st = mp.step_batched(h, dms, dws, prec=prec, workspace=ws, input_right_canonical=k > 0)
+                st = mp.step_batched(h, dms, dws, prec=prec, workspace=ws, input_right_canonical=k > 0,
+                                     use_graph=args.graph)
             else:
                 st = [mp.step(h, dm, dw, prec=prec, workspace=w_, input_right_canonical=k > 0)
                       for dm, dw, w_ in zip(dms, dws, ws)]
+            graphs.append(sum(1 for x in st if x.graph == 2))
             torch.cuda.synchronize()
             ms.append((time.perf_counter() - t0) * 1e3)
             if k == 0:
@@ -728,10 +730,10 @@ def run_batched(args, torch, mp, wl, h):
         gflop = sum(x.gflop for x in st)
         del ws, dms
         torch.cuda.empty_cache()
-        return ms, first, bonds, gflop
+        return ms, first, bonds, gflop, graphs
 
-    ms_b, first_b, bonds, gflop = trajectory(True)
-    ms_1, first_1, _, _ = trajectory(False)
+    ms_b, first_b, bonds, gflop, graphs_b = trajectory(True)
+    ms_1, first_1, _, _, _ = trajectory(False)
     sec = float(np.sum(ms_b)) / 1e3 / steps
     parity, cpu = None, None
     if not args.no_cpu:
@@ -761,9 +763,11 @@ def run_batched(args, torch, mp, wl, h):
         "dtype": DTYPES[args.prec], "data": "synthetic",
         "config": {"workload": "64 independent TFIM chains, g ~ U(0.5,1.5), L in {32,64,96,128}, "
                                "D in {32,64,128,256} (seed 2), order-2 extended MPO (w=3), tau=0.1, "
-                               f"2 sweeps, all-up start, steps 1..{steps}",
+                               f"2 sweeps, all-up start, steps 1..{steps}"
+                               f"{', each chain replaying its captured step graph once its plan repeats' if args.graph else ''}",
                    "chains": len(chains), "tau": TAU, "order": 2},
         "steps_ms_batched": ms_b, "steps_ms_one_by_one": ms_1,
+        "graph_replays_per_step": graphs_b if args.graph else None,
         "batched_speedup": float(np.sum(ms_1) / np.sum(ms_b)),
         "chain_steps_per_s": len(chains) * steps / (float(np.sum(ms_b)) / 1e3),
         "worker_streams_requested": int(os.environ.get("MPOEVO_BATCH_STREAMS", "4")),
@@ -977,7 +981,8 @@ def main():
                     help="lr3 and quench: the sweeps' starting point (psi, the zip-up of W psi, or the zip-up "
                          "while the bonds grow)")
     ap.add_argument("--graph", action="store_true",
-                    help="lr3 and quench: replay each step's launches from a captured HIP graph once its plan repeats")
+                    help="lr3, quench and batched: replay each step's launches from a captured HIP graph once its "
+                         "plan repeats")
     ap.add_argument("--order", type=int, default=ORDER, choices=[1, 2, 3, 4],
                     help="MPO order of the TFIM workloads (quench, split reference, thermal)")
     ap.add_argument("--tau", type=float, default=TAU, help="time step of the quench and split workloads")

@@ -848,15 +848,21 @@ size_t step_ws(int L, int d, int Dmax, int wmax, int prec) {
   return step_layout(L, d, Dmax, wmax, prec).total;
 }
 
-int check_solver_dev(Context& ctx) {
+int check_solver_dev(Context& ctx, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  // on the given stream (a step's: no dependence on the legacy stream, which another thread's graph
+  // capture would forbid), else on the legacy stream
+  const hipStream_t sq = static_cast<hipStream_t>(stream);
   int stv[4] = {0, 0, 0, 0};
-  hipError_t e = hipMemcpy(stv, ctx.dev->status, sizeof(stv), hipMemcpyDeviceToHost);
+  hipError_t e = sq ? hipMemcpyAsync(stv, ctx.dev->status, sizeof(stv), hipMemcpyDeviceToHost, sq)
+                    : hipMemcpy(stv, ctx.dev->status, sizeof(stv), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && sq) e = hipStreamSynchronize(sq);
   if (e != hipSuccess) return hip_fail(ctx, e, "reading the solver status");
   ctx.max_sweeps = std::max(ctx.max_sweeps, stv[1]);
   const int st = stv[0];
   if (st || stv[1] || stv[2]) {
-    e = hipMemset(ctx.dev->status, 0, sizeof(stv));
+    e = sq ? hipMemsetAsync(ctx.dev->status, 0, sizeof(stv), sq) : hipMemset(ctx.dev->status, 0, sizeof(stv));
+    if (e == hipSuccess && sq) e = hipStreamSynchronize(sq);
     if (e != hipSuccess) return hip_fail(ctx, e, "clearing the solver status");
   }
   if (st) {
@@ -1217,9 +1223,22 @@ int run_step_body(Context& ctx, const mpoevo_step_opts* opts, const mpoevo_mps* 
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "step: launching the captured graph");
 }
 
+// The calling thread's stream-capture mode set to relaxed while it lives. A thread's own mode
+// decides whether its synchronous calls (the read-back of a step, the solver check) are refused
+// while another thread captures a graph, and the runtime counts every thread's capture there
+// (step_batched's workers capture and synchronise side by side); relaxed lets both proceed.
+struct RelaxedCaptureMode {
+  hipStreamCaptureMode prev = hipStreamCaptureModeRelaxed;
+  RelaxedCaptureMode() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+  ~RelaxedCaptureMode() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+  RelaxedCaptureMode(const RelaxedCaptureMode&) = delete;
+  RelaxedCaptureMode& operator=(const RelaxedCaptureMode&) = delete;
+};
+
 int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
              mpoevo_step_stats* stats, void* ws, size_t, void* stream) {
   if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  const RelaxedCaptureMode capture_mode;
   TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
   const int L = mps->L, d = mps->d, Dmax = mps->Dmax, prec = opts->prec;
   const bool fp64 = prec == MPOEVO_FP64;
@@ -1704,7 +1723,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                               hipMemcpyDeviceToDevice, st));
     }
     STEP_TRY(hipStreamSynchronize(st));
-    const int sres = check_solver_dev(ctx);
+    const int sres = check_solver_dev(ctx, st);
     if (sres != MPOEVO_OK) return sres;
     int maxb = 1;
     for (int b = 0; b <= L; ++b) {
@@ -1758,7 +1777,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   STEP_TRY(hipMemcpyAsync(dh.data(), dbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipMemcpyAsync(nh.data(), nbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
   STEP_TRY(hipStreamSynchronize(st));
-  const int sres = check_solver_dev(ctx);
+  const int sres = check_solver_dev(ctx, st);
   if (sres != MPOEVO_OK) return sres;
   std::vector<int> Pact(L + 1, 1);
   for (int b = 1; b < L; ++b) Pact[b] = kh[k_slot_of_bond[b]];

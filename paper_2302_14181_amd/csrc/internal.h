@@ -91,7 +91,7 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
 int truncate_dev(Context& ctx, const void* Theta, int m, int n, int Dmax, double cutoff,
                  int direction, void* A_out, void* B_out, int* k_dev, double* discarded_dev,
                  double* norm_dev, double* sigma_dev, void* ws, size_t ws_bytes, void* stream);
-int check_solver_dev(Context& ctx);
+int check_solver_dev(Context& ctx, void* stream = nullptr);
 int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,
              mpoevo_step_stats* stats, void* ws, size_t ws_bytes, void* stream);
 int overlap_dev(Context& ctx, const mpoevo_mps* bra, const mpoevo_mpo* mpo, const mpoevo_mps* ket, int left,

@@ -97,10 +97,12 @@ def test_graph_not_used_with_profile(mp):
 
 def test_graph_batched_chains_bitwise(mp):
     """step_batched with use_graph: every chain captures and replays its own graph on its worker
-    stream; the chains match the uncaptured batched steps bit for bit."""
-    say("graph replay step_batched, 3 chains")
+    stream while the other workers run and synchronise their own steps; the chains match the
+    uncaptured batched steps bit for bit."""
+    say("graph replay step_batched, 12 chains")
     W, _ = mpo_pair(mp, wl.tfim(1.2), 2, -0.1j)
-    shapes = [(10, 8), (12, 8), (9, 4)]
+    shapes = [(10, 8), (12, 8), (9, 4), (14, 16), (8, 8), (11, 4), (16, 16), (10, 16), (13, 8), (9, 8),
+              (12, 4), (15, 8)]
     hg, hp = mp.Handle(0), mp.Handle(0)
     try:
         G, P, M = [], [], []
