@@ -54,7 +54,7 @@ chain's MPO (w = 271, default 10 calls), whose products are the default line's d
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
                        [--no-cpu] [--no-fp64] [--no-delta2] [--no-side] [--nsites -1|1|2]
-                       [--guess canonical|zipup|auto] [--graph] [--env-w 8|271]
+                       [--guess canonical|zipup|auto] [--graph] [--tune] [--env-w 8|271]
                        [--workload lr3|quench|xxz|batched|env|split|thermal|cylinder|copy]
                        [--order N] [--tau T] [--quiet]
 """
@@ -362,9 +362,16 @@ def run_lr3(args, torch, mp, wl, h):
     gs, gr = guess_of(mp, args), args.graph
     # the environment microbenchmark first, on a device that has not yet run minutes of work
     envmb = None if args.no_side else env_microbench_summary(mp, h, torch)
+    # the tile tuner times the products of the shapes the warm-up steps meet and keeps the fastest
+    # plan; frozen for the timed steps (shapes it has not seen take the planner's rule)
+    tune = args.tune
+    if tune:
+        h.set_tuning(mp.TUNE_ON)
     if Wm:  # untimed warm-up steps of the same trajectory on their own state and workspace
         trajectory(torch, mp, h, psi0, dw, prec, Wm, LR_D, progress=prog and prog + " warm-up", nsites=ns,
                    guess=gs, use_graph=gr)
+    if tune:
+        h.set_tuning(mp.TUNE_FROZEN)
     ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, K, LR_D, profile=not gr, progress=prog, nsites=ns,
                             guess=gs, use_graph=gr)
     if gr:  # the kernel table from the same steps profiled launch by launch (untimed)
@@ -383,6 +390,12 @@ def run_lr3(args, torch, mp, wl, h):
     fp64 = None
     if not args.no_fp64 and prec != mp.FP64:
         n64 = max(1, min(args.fp64_steps or K, K))
+        if tune:  # the same warm-up and tuning for the FP64 path's products
+            h.set_tuning(mp.TUNE_ON)
+            if Wm:
+                trajectory(torch, mp, h, psi0, dw, mp.FP64, Wm, LR_D, progress=prog and prog + " fp64 warm-up",
+                           nsites=ns, guess=gs)
+            h.set_tuning(mp.TUNE_FROZEN)
         ms64, st64, dm64 = trajectory(torch, mp, h, psi0, dw, mp.FP64, n64, LR_D, profile=True,
                                       progress=prog and prog + " fp64", nsites=ns, guess=gs)
         p64 = {k: float(sum(x.profile[k] for x in st64)) for k in st64[0].profile if k != "kernels"}
@@ -427,6 +440,9 @@ def run_lr3(args, torch, mp, wl, h):
                                f"{', steps replayed from HIP graphs' if gr else ''}, steps 1..{K} from t=0",
                    "L": LR_L, "D": LR_D, "order": LR_ORDER, "tau": LR_TAU, "w": w},
         "step_ms": ms,
+        "tile_tuner": ({"mode": "timed the product plans of the warm-up steps' shapes (FP32 and FP64 each), "
+                                "frozen for the timed steps", "entries": h.product_plan(prec, 1, 1, 1)["entries"]}
+                       if tune else None),
         "max_bond_per_step": [x.max_bond for x in st],
         "one_site_steps": [i + 1 for i, x in enumerate(st) if x.visits == 4 * (LR_L - 1) + 1],
         "discarded_sum_per_step": [x.discarded_sum for x in st],
@@ -967,6 +983,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-delta2", action="store_true", help="lr3: skip the step-2 parity from the oracle state")
     ap.add_argument("--no-side", action="store_true", help="lr3: skip the quench and microbenchmark side fields")
+    ap.add_argument("--tune", action="store_true",
+                    help="lr3: tune the product plans on the warm-up steps, frozen for the timed steps (default: the "
+                         "planner's rule)")
     ap.add_argument("--nsites", type=int, default=-1, choices=[-1, 1, 2],
                     help="lr3: local update (2: two-site; 1: one-site at fixed bonds; -1: two-site while the "
                          "bonds grow, one-site once all are at their largest value)")
