@@ -269,15 +269,16 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
 //   Re C = P1 - P2,  Im C = P3 - P1 - P2,
 // three v_mfma_f32_32x32x2f32 accumulators per 32 x 32 complex block instead of the four real
 // products of the expanded form (the algorithmic count stays 8 flops per complex multiply-add).
-// A and B are staged in LDS as three k-contiguous planes each (real part, imaginary part, their
-// sum, formed while staging), rows [m][k] and [n][k], in the consumption order of the fp32
-// instruction (kpos below), so that each lane fetches the operands of four instructions with one
-// 16-byte read per plane. A workgroup of KW groups of WGM x 2 waves (each wave WR x WC blocks of
+// A and B are staged in LDS as two k-contiguous planes each (real and imaginary part; the sum the
+// third product takes is formed in registers after the read), rows [m][k] and [n][k], in the
+// consumption order of the fp32 instruction (kpos below), so that each lane fetches the operands
+// of four instructions with one 16-byte read per plane. A workgroup of KW groups of WGM x 2 waves (each wave WR x WC blocks of
 // 32 x 32 complex outputs) owns a BM x BN complex tile, double-buffered with one barrier per K
 // step of BK; with KW > 1 the groups take equal slices of every step (two waves per SIMD, so that
 // one wave's staging and barrier wait overlap the other's matrix instructions) and their partial
 // sums meet in LDS at the end, in group order. Tiles: 128 x 128 (one group of 2 x 2 waves, each
-// 64 x 64: half the operand traffic per flop of 128 x 64, for the large products of wide MPO bonds),
+// 64 x 64: half the operand traffic per flop of 128 x 64, for the large products of wide MPO
+// bonds),
 // 128 x 64 (one group), 64 x 64 (two groups), 32 x 64 (four groups of 1 x 2 waves, BK = 64: 256
 // workgroups for a 256 x 2048 output without splitting K).
 // Rounding: the sums carry one more rounding and Im C a difference of products, so its error
@@ -297,7 +298,7 @@ struct Tile3 {
   static constexpr int A_ELEMS = BM * BK / NT;
   static constexpr int B_ELEMS = BN * BK / NT;
   static constexpr int PLANE_A = BM * PITCH, PLANE_B = BN * PITCH;
-  static constexpr int STAGE = 3 * (PLANE_A + PLANE_B);
+  static constexpr int STAGE = 2 * (PLANE_A + PLANE_B);  // real and imaginary planes
   static_assert(A_ELEMS >= 4 && B_ELEMS >= 4 && A_ELEMS % 4 == 0 && B_ELEMS % 4 == 0,
                 "tile too small for the staging scheme");
   static_assert(BK % G == 0 && KG % G == 0 && ((PITCH * 4 / 16) & 1), "staging layout");
@@ -425,10 +426,8 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
   auto store_tiles = [&](int buf) {
     float* Ar = lds + buf * TT::STAGE;
     float* Ai = Ar + TT::PLANE_A;
-    float* As = Ai + TT::PLANE_A;
-    float* Br = As + TT::PLANE_A;
+    float* Br = Ai + TT::PLANE_A;
     float* Bi = Br + TT::PLANE_B;
-    float* Bs = Bi + TT::PLANE_B;
     if (AKC) {
 #pragma unroll
       for (int i = 0; i < TT::A_ELEMS; ++i) {
@@ -437,7 +436,6 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
         const float re = ra[i].x, im = sgnA * ra[i].y;
         Ar[pp] = re;
         Ai[pp] = im;
-        As[pp] = re + im;
       }
     } else {
 #pragma unroll
@@ -453,7 +451,6 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
         }
         *reinterpret_cast<V4*>(Ar + pp) = re;
         *reinterpret_cast<V4*>(Ai + pp) = im;
-        *reinterpret_cast<V4*>(As + pp) = re + im;
       }
     }
     if (!BNC) {
@@ -464,7 +461,6 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
         const float re = rb[i].x, im = sgnB * rb[i].y;
         Br[pp] = re;
         Bi[pp] = im;
-        Bs[pp] = re + im;
       }
     } else {
 #pragma unroll
@@ -480,7 +476,6 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
         }
         *reinterpret_cast<V4*>(Br + pp) = re;
         *reinterpret_cast<V4*>(Bi + pp) = im;
-        *reinterpret_cast<V4*>(Bs + pp) = re + im;
       }
     }
   };
@@ -512,10 +507,8 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
     }
     const float* Ar = lds + cur * TT::STAGE;
     const float* Ai = Ar + TT::PLANE_A;
-    const float* As = Ai + TT::PLANE_A;
-    const float* Br = As + TT::PLANE_A;
+    const float* Br = Ai + TT::PLANE_A;
     const float* Bi = Br + TT::PLANE_B;
-    const float* Bs = Bi + TT::PLANE_B;
 #pragma unroll
     for (int kg = kw * TT::KG; kg < (kw + 1) * TT::KG; kg += TT::G) {
       VecT ar_[WR], ai_[WR], as_[WR], br_[WC], bi_[WC], bs_[WC];
@@ -524,14 +517,14 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
         const int o = (wm * (WR * 32) + i * 32 + arow) * TT::PITCH + kg + ak * TT::V;
         ar_[i] = *reinterpret_cast<const VecT*>(Ar + o);
         ai_[i] = *reinterpret_cast<const VecT*>(Ai + o);
-        as_[i] = *reinterpret_cast<const VecT*>(As + o);
+        as_[i] = ar_[i] + ai_[i];  // the summed operand of the third product, formed in registers
       }
 #pragma unroll
       for (int j = 0; j < WC; ++j) {
         const int o = (wn * (WC * 32) + j * 32 + arow) * TT::PITCH + kg + ak * TT::V;
         br_[j] = *reinterpret_cast<const VecT*>(Br + o);
         bi_[j] = *reinterpret_cast<const VecT*>(Bi + o);
-        bs_[j] = *reinterpret_cast<const VecT*>(Bs + o);
+        bs_[j] = br_[j] + bi_[j];
       }
 #pragma unroll
       for (int q = 0; q < TT::V; ++q)
