@@ -914,12 +914,24 @@ Plan make_plan(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
       p.cfg = c; p.bm = cfgs[c][0]; p.bn = cfgs[c][1];
       return p;
     }
-  const long long t = tiles(p.cfg);
-  if (!g.ws || t >= kTargetWgs) return p;
-  int s = (int)std::min<long long>((kTargetWgs + t - 1) / t, kMaxSplits);
-  s = std::min(s, g.K / kMinSplitK);
+  if (!g.ws || tiles(p.cfg) >= kTargetWgs) return p;
+  // split K: the largest tile whose splits (at most kMaxSplits, of at least kMinSplitK each, their
+  // partial tiles within the scratch) bring the workgroups to kTargetWgs, else the smallest tile
+  // with as many splits as allowed
   const size_t per = sizeof(typename Mf::T) * 2 * (size_t)g.M * g.N * g.batch;
-  s = (int)std::min<size_t>((size_t)s, per ? g.ws_bytes / per : 0);
+  const int smax = (int)std::min<size_t>({(size_t)kMaxSplits, (size_t)std::max(g.K / kMinSplitK, 1),
+                                          per ? g.ws_bytes / per : 0});
+  int s = 0;
+  for (int c = 0; c < ncfg && s == 0; ++c) {
+    if (cfgs[c][1] > std::max(g.N, 64)) continue;
+    const long long t = tiles(c);
+    const long long need = (kTargetWgs + t - 1) / t;
+    if (need <= smax) {
+      p.cfg = c; p.bm = cfgs[c][0]; p.bn = cfgs[c][1];
+      s = (int)need;
+    }
+  }
+  if (s == 0) s = std::min<int>(smax, (int)((kTargetWgs + tiles(p.cfg) - 1) / tiles(p.cfg)));
   if (s < 2) return p;
   const int kc = ((g.K + s - 1) / s + kKGrain - 1) / kKGrain * kKGrain;
   p.kchunk = kc;
