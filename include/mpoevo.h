@@ -135,15 +135,23 @@ int env_update_noalloc(mpoevo_handle h, int side, int prec, const void* E_in, co
 
 /*
  * local_apply -- DEVICE, async on `stream`.
- * Projected two-site tensor of the fit at bond (i, i+1) (the optimal two-site update):
+ * nsites = 2: projected two-site tensor of the fit at bond (i, i+1) (the optimal two-site update):
  *   Theta[a'][s'][t'][c'] = sum L[a'][alpha][a] M1[a][s][b] W1[alpha][s'][s][beta]
  *                               M2[b][t][c] W2[beta][t'][t][gamma] R[c'][gamma][c]
- * nsites must be 2. dims: [0] Dbra_l, [1] Dket_l, [2] Dket_m, [3] Dket_r, [4] Dbra_r, [5] d,
- * [6] w_l, [7] w_m, [8] w_r.  L (Dbra_l, w_l, Dket_l), M1 (Dket_l, d, Dket_m),
- * W1 (w_l, d, d, w_m), M2 (Dket_m, d, Dket_r), W2 (w_m, d, d, w_r), R (Dbra_r, w_r, Dket_r).
+ * dims: [0] Dbra_l, [1] Dket_l, [2] Dket_m, [3] Dket_r, [4] Dbra_r, [5] d, [6] w_l, [7] w_m,
+ * [8] w_r.  L (Dbra_l, w_l, Dket_l), M1 (Dket_l, d, Dket_m), W1 (w_l, d, d, w_m),
+ * M2 (Dket_m, d, Dket_r), W2 (w_m, d, d, w_r), R (Dbra_r, w_r, Dket_r); Theta shaped
+ * (Dbra_l*d) x (d*Dbra_r). Workspace: mpoevo_workspace_size(MPOEVO_CALL_LOCAL_APPLY, dims).
+ * nsites = 1: projected one-site tensor at site i (the optimal site at fixed bonds, Sec. 2.2,
+ * Table 1 (ii)):
+ *   Theta[a'][s'][b'] = sum L[a'][alpha][a] M1[a][s][b] W1[alpha][s'][s][beta] R[b'][beta][b]
+ * dims: [0] Dbra_l, [1] Dket_l, [2] Dket_r, [3] Dbra_r, [4] d, [5] w_l, [6] w_r.
+ * L (Dbra_l, w_l, Dket_l), M1 (Dket_l, d, Dket_r), W1 (w_l, d, d, w_r), R (Dbra_r, w_r, Dket_r);
+ * W2 and M2 are not read (may be NULL); Theta shaped (Dbra_l*d) x Dbra_r. Workspace:
+ * mpoevo_workspace_size(MPOEVO_CALL_LOCAL_APPLY1, dims).
  * Inputs complex128 (FP64) or complex64 (FP32); Theta is ALWAYS complex128 (the FP32 path
- * accumulates in float and widens on store), shaped (Dbra_l*d) x (d*Dbra_r).
- * Errors: EINVAL, ESHAPE, ENOMEM, EHIP.
+ * accumulates in float and widens on store).
+ * Errors: EINVAL (nsites not 1 or 2, NULL pointers), ESHAPE, ENOMEM, EHIP.
  */
 int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void* W1,
                 const void* W2, const void* M1, const void* M2, const void* R, void* Theta,
@@ -425,7 +433,8 @@ int overlap(mpoevo_handle h, const mpoevo_mps* bra, const mpoevo_mpo* mpo, const
 
 /* Workspace sizes in bytes for the device calls (dims as documented for each call). */
 enum { MPOEVO_CALL_ENV_UPDATE = 0, MPOEVO_CALL_LOCAL_APPLY = 1, MPOEVO_CALL_TRUNCATE = 2,
-       MPOEVO_CALL_STEP = 3, MPOEVO_CALL_EXPECTATION = 4, MPOEVO_CALL_STEP_BATCHED = 5 };
+       MPOEVO_CALL_STEP = 3, MPOEVO_CALL_EXPECTATION = 4, MPOEVO_CALL_STEP_BATCHED = 5,
+       MPOEVO_CALL_LOCAL_APPLY1 = 6 };
 /* dims: ENV_UPDATE -> the 7 env_update dims; LOCAL_APPLY -> the 9 local_apply dims;
  * TRUNCATE -> {m, n}; STEP and EXPECTATION -> {L, d, Dmax, wmax};
  * STEP_BATCHED -> {n, L_0, d_0, Dmax_0, wmax_0, ..., L_{n-1}, d_{n-1}, Dmax_{n-1}, wmax_{n-1}}. */

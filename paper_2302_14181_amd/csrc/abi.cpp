@@ -102,6 +102,10 @@ int mpoevo_workspace_size(int call_id, const int* dims, int prec, size_t* bytes)
       for (int i = 0; i < 9; ++i) if (dims[i] < 1) return fail(nullptr, MPOEVO_ESHAPE, "non-positive dimension");
       *bytes = mpoevo::local_apply_ws(dims, prec);
       return MPOEVO_OK;
+    case MPOEVO_CALL_LOCAL_APPLY1:
+      for (int i = 0; i < 7; ++i) if (dims[i] < 1) return fail(nullptr, MPOEVO_ESHAPE, "non-positive dimension");
+      *bytes = mpoevo::local_apply1_ws(dims, prec);
+      return MPOEVO_OK;
     case MPOEVO_CALL_TRUNCATE:
       if (dims[0] < 1 || dims[1] < 1 || dims[0] > MPOEVO_SVD_MAX_DIM || dims[1] > MPOEVO_SVD_MAX_DIM)
         return fail(nullptr, MPOEVO_ESHAPE, "truncate: m, n must be in 1..MPOEVO_SVD_MAX_DIM");
@@ -171,8 +175,15 @@ int local_apply(mpoevo_handle h, int nsites, int prec, const void* L, const void
                 const int* dims, void* workspace, size_t workspace_bytes, void* stream) {
   if (!h) return fail(nullptr, MPOEVO_EINVAL, "local_apply: NULL handle");
   auto* ctx = reinterpret_cast<mpoevo::Context*>(h);
-  if (nsites != 2) return fail(ctx, MPOEVO_EUNSUPPORTED, "local_apply: only the two-site tensor is built");
+  if (nsites != 1 && nsites != 2) return fail(ctx, MPOEVO_EINVAL, "local_apply: nsites must be 1 or 2");
   if (!valid_prec(prec)) return fail(ctx, MPOEVO_EINVAL, "local_apply: unknown precision");
+  if (nsites == 1) {  // L, W1, M1, R; W2 and M2 unused
+    if (!L || !W1 || !M1 || !R || !Theta || !dims) return fail(ctx, MPOEVO_EINVAL, "local_apply: NULL pointer");
+    for (int i = 0; i < 7; ++i) if (dims[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "local_apply: non-positive dimension");
+    if (workspace_bytes < mpoevo::local_apply1_ws(dims, prec) || (!workspace && workspace_bytes))
+      return fail(ctx, MPOEVO_ENOMEM, "local_apply: workspace too small");
+    return mpoevo::local_apply1_dev(*ctx, prec, L, W1, M1, R, Theta, dims, workspace, workspace_bytes, stream);
+  }
   if (!L || !W1 || !W2 || !M1 || !M2 || !R || !Theta || !dims) return fail(ctx, MPOEVO_EINVAL, "local_apply: NULL pointer");
   for (int i = 0; i < 9; ++i) if (dims[i] < 1) return fail(ctx, MPOEVO_ESHAPE, "local_apply: non-positive dimension");
   if (workspace_bytes < mpoevo::local_apply_ws(dims, prec) || (!workspace && workspace_bytes))

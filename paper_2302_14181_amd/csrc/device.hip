@@ -837,6 +837,15 @@ size_t local_apply_ws(const int* dims, int prec) {
   return local_apply_core(dims, prec) + local_apply_xws(dims, prec) + kGemmScratchBytes;
 }
 
+// One-site local tensor: dims = {Dbra_l, Dket_l, Dket_r, Dbra_r, d, w_l, w_r}; the left block's
+// temporary and the block itself, the large-bond contraction scratch, split-K scratch.
+size_t local_apply1_ws(const int* dims, int prec) {
+  const size_t Dbl = dims[0], Dkr = dims[2], d = dims[4], wl = dims[5], wr = dims[6];
+  const size_t cs = csize(prec);
+  return a256(cs * Dbl * wl * d * Dkr) + a256(cs * Dbl * d * wr * Dkr) +
+         wcontract_xws(dims[1], dims[2], dims[4], dims[5], dims[6], cs) + kGemmScratchBytes;
+}
+
 size_t truncate_ws(int m, int n) {
   size_t ws = 0;
   for (int dir : {MPOEVO_LEFT, MPOEVO_RIGHT})
@@ -993,6 +1002,26 @@ int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const
   if (e == hipSuccess)
     e = right_block(ar, M2, R, W2, tmp, RB, Dkm, d, Dkr, Dbr, wm, wr, st, nullptr, gws, xws);
   if (e == hipSuccess) e = theta_product(ar, LB, RB, Theta, Dbl, d, wm, Dkm, Dbr, st, nullptr, gws);
+  return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "local_apply");
+}
+
+// Theta[a'][s'][b'] = sum L[a'][alpha][a] M[a][s][b] W[alpha][s'][s][beta] R[b'][beta][b]: the left
+// block LB = L M W (as in a left-to-right one-site update), then LB R.
+int local_apply1_dev(Context& ctx, int prec, const void* L, const void* W, const void* M, const void* R,
+                     void* Theta, const int* dims, void* ws, size_t, void* stream) {
+  if (hipError_t e0 = hipSetDevice(ctx.device); e0 != hipSuccess) return hip_fail(ctx, e0, "hipSetDevice");
+  TunerScope tuner_scope(ctx.tuner, ctx.owns_tuner);
+  const int Dbl = dims[0], Dkl = dims[1], Dkr = dims[2], Dbr = dims[3], d = dims[4], wl = dims[5], wr = dims[6];
+  const Arith ar = arith_of(prec);
+  const size_t cs = csize(prec);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  void* tmp = base;
+  void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
+  void* xws = static_cast<unsigned char*>(LB) + a256(cs * (size_t)Dbl * d * wr * Dkr);
+  void* gws = static_cast<unsigned char*>(xws) + wcontract_xws(Dkl, Dkr, d, wl, wr, cs);
+  hipError_t e = left_block(ar, L, M, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws, xws);
+  if (e == hipSuccess) e = local_left(ar, LB, R, static_cast<double2*>(Theta), Dbl, d, wr, Dkr, Dbr, st, nullptr, gws);
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "local_apply");
 }
 

@@ -74,6 +74,7 @@ void device_fini(Context& ctx);
 
 size_t env_update_ws(const int* dims, int prec);
 size_t local_apply_ws(const int* dims, int prec);
+size_t local_apply1_ws(const int* dims, int prec);  // one-site: dims {Dbl, Dkl, Dkr, Dbr, d, wl, wr}
 size_t truncate_ws(int m, int n);
 size_t step_ws(int L, int d, int Dmax, int wmax, int prec);
 size_t expectation_ws(int L, int d, int Dmax, int wmax);
@@ -85,6 +86,8 @@ int env_update_dev(Context& ctx, int side, int prec, const void* E_in, const voi
 size_t env_update_noalloc_need(const int* dims, int prec);
 int env_update_noalloc_dev(Context& ctx, int side, int prec, const void* E_in, const void* bra,
                            const void* W, const void* ket, void* E_out, const int* dims, void* stream);
+int local_apply1_dev(Context& ctx, int prec, const void* L, const void* W, const void* M, const void* R,
+                     void* Theta, const int* dims, void* ws, size_t ws_bytes, void* stream);
 int local_apply_dev(Context& ctx, int prec, const void* L, const void* W1, const void* W2,
                     const void* M1, const void* M2, const void* R, void* Theta, const int* dims,
                     void* ws, size_t ws_bytes, void* stream);

@@ -21,6 +21,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 V1_EXACT, V2_EXTENDED = 0, 1
 LEFT, RIGHT = 0, 1
 CALL_ENV_UPDATE, CALL_LOCAL_APPLY, CALL_TRUNCATE, CALL_STEP, CALL_EXPECTATION, CALL_STEP_BATCHED = 0, 1, 2, 3, 4, 5
+CALL_LOCAL_APPLY1 = 6
 TUNE_OFF, TUNE_ON, TUNE_FROZEN = 0, 1, 2
 MAX_CHAINS = 4096
 SVD_MAX_DIM = 1024
@@ -290,6 +291,20 @@ def local_apply(h: Handle, Lenv, W1, W2, M1, M2, Renv, Theta, workspace=None, st
     _check(load().local_apply(h.ptr, 2, prec, _ptr(Lenv), _ptr(W1), _ptr(W2), _ptr(M1), _ptr(M2),
                               _ptr(Renv), _ptr(Theta), _iarr(dims), _ptr(workspace), workspace.numel(),
                               _stream(stream)), h)
+
+
+def local_apply_one_site(h: Handle, Lenv, W, M, Renv, Theta, workspace=None, stream=None, prec=None):
+    """Projected one-site tensor into Theta (complex128, (Dbra_l*d) x Dbra_r); prec as for
+    env_update."""
+    prec = _prec_of(Lenv, prec)
+    Dbl, wl, Dkl = Lenv.shape
+    Dbr, wr, Dkr = Renv.shape
+    d = M.shape[1]
+    dims = [Dbl, Dkl, Dkr, Dbr, d, wl, wr]
+    if workspace is None:
+        workspace = _workspace(workspace_size(CALL_LOCAL_APPLY1, dims, prec), Lenv.device)
+    _check(load().local_apply(h.ptr, 1, prec, _ptr(Lenv), _ptr(W), None, _ptr(M), None, _ptr(Renv),
+                              _ptr(Theta), _iarr(dims), _ptr(workspace), workspace.numel(), _stream(stream)), h)
 
 
 def truncate(h: Handle, Theta, Dmax: int, cutoff: float, direction: int, A_out, B_out,

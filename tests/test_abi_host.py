@@ -101,6 +101,14 @@ def test_workspace_queries():
     with pytest.raises(mpoevo.MpoevoError) as e:
         mpoevo.workspace_size(mpoevo.CALL_TRUNCATE, [2000, 5], mpoevo.FP64)
     assert e.value.code == mpoevo.ESHAPE
+    # the one-site local tensor: its left block (Dbra_l d w_r Dket_r complex) and temporary at least
+    one = [64, 64, 64, 64, 2, 6, 6]
+    assert mpoevo.workspace_size(mpoevo.CALL_LOCAL_APPLY1, one, mpoevo.FP64) >= 2 * 64 * 2 * 6 * 64 * 16
+    assert (mpoevo.workspace_size(mpoevo.CALL_LOCAL_APPLY1, one, mpoevo.FP32)
+            < mpoevo.workspace_size(mpoevo.CALL_LOCAL_APPLY1, one, mpoevo.FP64))
+    with pytest.raises(mpoevo.MpoevoError) as e:
+        mpoevo.workspace_size(mpoevo.CALL_LOCAL_APPLY1, [64, 64, 0, 64, 2, 6, 6], mpoevo.FP32)
+    assert e.value.code == mpoevo.ESHAPE
 
 
 def test_device_calls_reject_null_handle():

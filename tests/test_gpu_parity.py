@@ -204,6 +204,45 @@ def test_local_apply_parity(mp, handle, dims, prec64):
     assert_close(th.cpu().numpy(), ref, 1e-12 if prec64 else 2e-5, "theta")
 
 
+LA1_CASES = [  # Dbra_l, Dket_l, Dket_r, Dbra_r, d, w_l, w_r
+    (1, 1, 2, 2, 2, 3, 3),
+    (33, 40, 29, 35, 2, 3, 3),
+    (64, 64, 64, 64, 2, 6, 6),
+    (20, 31, 18, 22, 3, 4, 5),
+    (10, 12, 11, 9, 2, 271, 271),
+    (128, 128, 128, 128, 2, 271, 271),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("dims", LA1_CASES, ids=[str(c) for c in LA1_CASES])
+def test_local_apply_one_site_parity(mp, handle, dims, prec):
+    """The one-site projected tensor L M W R (the optimal site at fixed bonds) through local_apply
+    with nsites = 1, element-wise against the oracle's definition."""
+    Dbl, Dkl, Dkr, Dbr, d, wl_, wr = dims
+    rng = np.random.default_rng(11 + sum(dims))
+    _say("local_apply one-site", ["fp64", "fp32", "bf16x3"][prec], dims)
+    L, M, W, R = _cn(rng, Dbl, wl_, Dkl), _cn(rng, Dkl, d, Dkr), _cn(rng, wl_, d, d, wr), _cn(rng, Dbr, wr, Dkr)
+    ref = ofit.local_one_site(L, M, W, R).reshape(Dbl * d, Dbr)
+    th = torch.zeros((Dbl * d, Dbr), dtype=torch.complex128, device="cuda")
+    f64 = prec == mp.FP64
+    mp.local_apply_one_site(handle, _dev(L, f64), _dev(W, f64), _dev(M, f64), _dev(R, f64), th, prec=prec)
+    torch.cuda.synchronize()
+    assert_close(th.cpu().numpy(), ref, {0: 1e-12, 1: 2e-5, 2: 2e-4}[prec], "theta")
+
+
+def test_local_apply_rejects_bad_nsites(mp, handle):
+    _say("local_apply nsites argument")
+    import ctypes
+    t = torch.zeros(8, dtype=torch.complex128, device="cuda")
+    lib = mp.load()
+    arr = (ctypes.c_int * 9)(*([2] * 9))
+    rc = lib.local_apply(handle.ptr, 3, mp.FP64, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                         ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                         ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(t.data_ptr()), arr, None, 0, None)
+    assert rc == mp.EINVAL
+
+
 TR_CASES = [(1, 1), (2, 2), (2, 7), (9, 3), (32, 32), (64, 40), (40, 64), (130, 127), (256, 256), (300, 200),
             (384, 384), (512, 512)]
 
