@@ -150,21 +150,6 @@ __global__ void permute_w_left(const C2* __restrict__ W, C2* __restrict__ Wt, in
   }
 }
 
-// Up[b][t][gamma][c'] = U[b][t][c'][gamma] (Qt = Qa d leading pairs (b, t)).
-template <typename C2>
-__global__ void permute_u_right(const C2* __restrict__ U, C2* __restrict__ Up, long long Qt, int Pr,
-                                int wr) {
-  const long long n = Qt * Pr * wr;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(i % Pr);
-    long long r = i / Pr;
-    const int gamma = (int)(r % wr);
-    const long long bt = r / wr;
-    Up[i] = U[(bt * Pr + c) * wr + gamma];
-  }
-}
-
 // E (1 x w x 1) = e_level.
 __global__ void boundary_level(double2* E, int w, int level) {
   const int i = threadIdx.x + blockIdx.x * blockDim.x;
@@ -291,39 +276,41 @@ hipError_t left_block(Arith ar, const void* E, const void* ket, const void* W, v
 // ket: (Qa, d, Qb), E: (Pr, wr, Qb), W: (wl, d, d, wr). tmp holds Qa*d*Pr*wr complex.
 hipError_t right_block(Arith ar, const void* ket, const void* E, const void* W, void* tmp,
                        void* RB, int Qa, int d, int Qb, int Pr, int wl, int wr, hipStream_t st,
-                       Prof* pr = nullptr, void* gws = nullptr, void* xws = nullptr,
+                       Prof* pr = nullptr, void* gws = nullptr, void* /*xws*/ = nullptr,
                        size_t gws_bytes = kGemmScratchBytes) {
   const bool fp64 = ar.fp64;
   GemmDesc g{};
   g.ws = gws;
   g.ws_bytes = gws ? gws_bytes : 0;
   g.A = ket; g.B = E; g.C = tmp;
-  g.M = Qa * d; g.N = Pr * wr; g.K = Qb; g.batch = 1;
-  g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sBn = Qb; g.sCm = (long long)Pr * wr; g.sCn = 1;
-  MPOEVO_HIP_TRY(gemm_timed(g, ar, false, st, pr));
+  g.M = Qa * d; g.K = Qb;
+  g.sAm = Qb; g.sAk = 1; g.sBk = 1; g.sCn = 1;
   if (wmix_supported(wl, d, wr)) {
+    // U[b][t][c'][gamma] = sum_c ket[b][t][c] E[c'][gamma][c]: one product over the rows (c', gamma)
+    g.N = Pr * wr; g.batch = 1;
+    g.sBn = Qb; g.sCm = (long long)Pr * wr;
+    MPOEVO_HIP_TRY(gemm_timed(g, ar, false, st, pr));
     PROF_BEGIN(pr, tok);
     MPOEVO_HIP_TRY(wmix_right(fp64, tmp, W, RB, Qa, Pr, wl, d, wr, st));
     const double cs = fp64 ? 16.0 : 8.0;
     PROF_END(pr, tok, Prof::kWmix, cs * ((double)Qa * d * Pr * wr + (double)wl * Qa * d * Pr + wl * d * d * wr));
     return hipSuccess;
   }
-  // large MPO bond: Up[b][t][gamma][c'] = U[b][t][c'][gamma], then for each t':
-  // RB[beta][b][t'][c'] = sum_{(t, gamma)} W[beta][t'][t][gamma] Up_b[(t, gamma)][c']
-  if (!xws) return hipErrorInvalidValue;
-  const long long nU = (long long)Qa * d * Pr * wr;
-  if (fp64) hipLaunchKernelGGL(permute_u_right<double2>, dim3(grid_for(nU)), dim3(256), 0, st,
-                               (const double2*)tmp, (double2*)xws, (long long)Qa * d, Pr, wr);
-  else hipLaunchKernelGGL(permute_u_right<float2>, dim3(grid_for(nU)), dim3(256), 0, st,
-                          (const float2*)tmp, (float2*)xws, (long long)Qa * d, Pr, wr);
-  MPOEVO_HIP_TRY(hipGetLastError());
+  // large MPO bond: the same contraction batched over gamma, written as Up[b][t][gamma][c'] (batch
+  // gamma reads rows c' of E at stride wr Qb from offset gamma Qb), so that for each t'
+  // RB[beta][b][t'][c'] = sum_{(t, gamma)} W[beta][t'][t][gamma] Up_b[(t, gamma)][c'] reads its
+  // operand at one stride per index
+  g.N = Pr; g.batch = wr;
+  g.sBn = (long long)wr * Qb; g.bA = 0; g.bB = Qb;
+  g.sCm = (long long)wr * Pr; g.bC = Pr;
+  MPOEVO_HIP_TRY(gemm_timed(g, ar, false, st, pr));
   const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
   for (int tp = 0; tp < d; ++tp) {
     GemmDesc h{};
     h.ws = gws;
     h.ws_bytes = gws ? gws_bytes : 0;
     h.A = static_cast<const unsigned char*>(W) + cs * (size_t)tp * d * wr;
-    h.B = xws;
+    h.B = tmp;
     h.C = static_cast<unsigned char*>(RB) + cs * (size_t)tp * Pr;
     h.M = wl; h.N = Pr; h.K = d * wr; h.batch = Qa;
     h.sAm = (long long)d * d * wr; h.sAk = 1; h.bA = 0;
@@ -666,10 +653,10 @@ hipError_t absorb_right(const void* site_in, const void* R, void* site_out, int 
 }
 
 // Scratch of the short-leg contraction done as a product (MPO bonds beyond the register kernels):
-// W permuted for the left side, the right intermediate transposed for the right side.
-size_t wcontract_xws(long long ket_rows, long long bra_cols, int d, int wl, int wr, size_t cs) {
+// W permuted for the left side (the right side needs none).
+size_t wcontract_xws(int d, int wl, int wr, size_t cs) {
   if (wmix_supported(wl, d, wr)) return 0;
-  return std::max(a256(cs * (size_t)d * wr * wl * d), a256(cs * (size_t)(ket_rows * d * bra_cols * wr)));
+  return a256(cs * (size_t)d * wr * wl * d);
 }
 
 // ------------------------------------------------------------------------- step workspace map
@@ -721,7 +708,7 @@ StepLayout step_layout(int L, int d, int Dmax, int wmax, int prec) {
   s.off_basis = take(sizeof(double2) * s.basiscap * (size_t)std::max(L - 1, 1));
   s.off_token = take(sizeof(unsigned long long));  // which step last wrote the unitaries
   s.off_gemm = take(kGemmScratchBytes);             // split-K partial products
-  s.off_xws = take(wcontract_xws(Dmax, Dmax, d, wmax, wmax, cs));  // large MPO bonds
+  s.off_xws = take(wcontract_xws(d, wmax, wmax, cs));  // large MPO bonds
   s.total = o;
   return s;
 }
@@ -812,7 +799,7 @@ size_t env_update_core(const int* dims, int prec) {
 }
 
 size_t env_update_xws(const int* dims, int prec) {
-  return wcontract_xws(dims[1], dims[2], dims[4], dims[5], dims[6], csize(prec));
+  return wcontract_xws(dims[4], dims[5], dims[6], csize(prec));
 }
 
 size_t env_update_ws(const int* dims, int prec) {
@@ -829,8 +816,7 @@ size_t local_apply_core(const int* dims, int prec) {
 
 size_t local_apply_xws(const int* dims, int prec) {
   const size_t cs = csize(prec);
-  return std::max(wcontract_xws(dims[1], dims[2], dims[5], dims[6], dims[7], cs),
-                  wcontract_xws(dims[2], dims[4], dims[5], dims[7], dims[8], cs));
+  return std::max(wcontract_xws(dims[5], dims[6], dims[7], cs), wcontract_xws(dims[5], dims[7], dims[8], cs));
 }
 
 size_t local_apply_ws(const int* dims, int prec) {
@@ -843,7 +829,7 @@ size_t local_apply1_ws(const int* dims, int prec) {
   const size_t Dbl = dims[0], Dkr = dims[2], d = dims[4], wl = dims[5], wr = dims[6];
   const size_t cs = csize(prec);
   return a256(cs * Dbl * wl * d * Dkr) + a256(cs * Dbl * d * wr * Dkr) +
-         wcontract_xws(dims[1], dims[2], dims[4], dims[5], dims[6], cs) + kGemmScratchBytes;
+         wcontract_xws(dims[4], dims[5], dims[6], cs) + kGemmScratchBytes;
 }
 
 size_t truncate_ws(int m, int n) {
@@ -1019,7 +1005,7 @@ int local_apply1_dev(Context& ctx, int prec, const void* L, const void* W, const
   void* tmp = base;
   void* LB = base + a256(cs * (size_t)Dbl * wl * d * Dkr);
   void* xws = static_cast<unsigned char*>(LB) + a256(cs * (size_t)Dbl * d * wr * Dkr);
-  void* gws = static_cast<unsigned char*>(xws) + wcontract_xws(Dkl, Dkr, d, wl, wr, cs);
+  void* gws = static_cast<unsigned char*>(xws) + wcontract_xws(d, wl, wr, cs);
   hipError_t e = left_block(ar, L, M, W, tmp, LB, Dbl, wl, Dkl, d, Dkr, wr, st, nullptr, gws, xws);
   if (e == hipSuccess) e = local_left(ar, LB, R, static_cast<double2*>(Theta), Dbl, d, wr, Dkr, Dbr, st, nullptr, gws);
   return e == hipSuccess ? MPOEVO_OK : hip_fail(ctx, e, "local_apply");
@@ -1044,7 +1030,7 @@ size_t expectation_ws(int L, int d, int Dmax, int wmax) {
   (void)L;
   const size_t env = a256(sizeof(double2) * (size_t)Dmax * wmax * Dmax);
   const size_t blk = a256(sizeof(double2) * (size_t)Dmax * wmax * d * Dmax);
-  return 2 * env + 2 * blk + wcontract_xws(Dmax, Dmax, d, wmax, wmax, sizeof(double2)) + kGemmScratchBytes;
+  return 2 * env + 2 * blk + wcontract_xws(d, wmax, wmax, sizeof(double2)) + kGemmScratchBytes;
 }
 
 // E <- E . ket_i . O_i . conj(bra_i), i = 0 .. L-1, from E = e_left; out = E[right] = <bra| O |ket>.
@@ -1063,7 +1049,7 @@ int overlap_dev(Context& ctx, const mpoevo_mps* bra, const mpoevo_mpo* mpo, cons
   void* tmp = base + 2 * env;
   void* LB = base + 2 * env + blk;
   void* xws = base + 2 * env + 2 * blk;
-  void* gws = static_cast<unsigned char*>(xws) + wcontract_xws(Dmax, Dmax, d, wmax, wmax, sizeof(double2));
+  void* gws = static_cast<unsigned char*>(xws) + wcontract_xws(d, wmax, wmax, sizeof(double2));
   const int* P = bra->bond_dim;
   const int* Q = ket->bond_dim;
   const int* w = mpo->w;
@@ -1109,7 +1095,7 @@ ZipPlan zip_plan(int L, int d, int Dmax, const std::vector<int>& Q, const int* w
     const long long m = (long long)w[i] * Q[i], n = (long long)d * z.K[i + 1];
     xb = std::max(xb, c16 * (size_t)(m * n));
     tb = std::max(tb, c16 * (size_t)Q[i] * d * z.K[i + 1] * w[i + 1]);
-    xwb = std::max(xwb, wcontract_xws(Q[i], z.K[i + 1], d, w[i], w[i + 1], c16));
+    xwb = std::max(xwb, wcontract_xws(d, w[i], w[i + 1], c16));
     if (i == 0) break;
     if (m > (long long)d * Dmax) return z;  // beyond the SVD's workspace
     z.K[i] = (int)std::min<long long>(Dmax, std::min(m, n));
