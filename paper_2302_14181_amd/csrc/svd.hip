@@ -1135,19 +1135,26 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
 
 // Blocked Householder QR without pivoting of X (mx x nx, column-major in q.X, nx <= mx <= 512),
 // written out as the explicit thin Q (one-site updates: only the column space matters, any
-// orthonormal basis of it gives the same fitted state). Workgroup g owns the panel of columns
-// [16 g, 16 g + 16), one wave per column, held in LDS. Phase 1: for k = 0 .. g - 1 it waits for
-// panel k (flag), applies B_k^dag = I - V_k T_k^dag V_k^dag to its columns, then factorises its
-// own panel with 16 Householder steps (H_j = I - tau_j v_j v_j^dag, v_j(j) = 1, H_j^dag zeroes
-// column j below row j), forms the compact-WY T_g (B_g = H_0 ... H_15 = I - V_g T_g V_g^dag, T_g
-// upper triangular, column j: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^dag v_j),
-// publishes V_g (into its own columns of q.X: zeros above the diagonal, 1 on it) and T_g (q.T),
-// and raises its flag (release). The panels factorise one after the other, each as soon as the
-// panel before it has reached its columns. Phase 2: column block g of Q = B_0 ... B_{G-1} [I; 0]
-// is B_0 (B_1 (... B_g E_g)) (B_k leaves E_g alone for k > g): the workgroup starts from E_g and
-// applies B_g, B_{g-1}, ..., B_0. out (adjoint 0): Q row-major (mx x nx); (adjoint 1): Q^dag
-// row-major (nx x mx). Waits are bounded (barrier-timeout status).
+// orthonormal basis of it gives the same fitted state). One launch of G = ceil(nx / 16) panel
+// workgroups followed by ceil(mx / 16) row workgroups.
+// Panel workgroup g owns the columns [16 g, 16 g + 16), one wave per column, each column in its
+// wave's registers (lane l, register i: row l + 64 i). For k = 0 .. g - 1 it waits for panel k
+// (flag) and applies B_k^dag = I - V_k T_k^dag V_k^dag to its columns (V_k staged in LDS), then
+// factorises its panel with 16 Householder steps (H_j = I - tau_j v_j v_j^dag, v_j(j) = 1, H_j^dag
+// zeroes column j below row j): at step j the wave of column j + 1 takes H_j^dag and forms the next
+// reflector at once, handing it to the other waves through LDS (two buffers, one barrier per
+// column), while the waves of the earlier columns give the inner products for T's column j. The
+// compact-WY T_g (B_g = H_0 ... H_15 = I - V_g T_g V_g^dag, T_g upper triangular, column j:
+// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^dag v_j) and V_g (in the panel's own
+// columns of q.X: zeros above the diagonal, 1 on it) are published and the flag raised (release).
+// Row workgroup b owns rows [16 b, 16 b + 16) of P = B_0 B_1 ... B_{G-1} (one wave per row, the row
+// in registers: lane l, register i: column l + 64 i). It starts from the identity and, as panel k
+// is published, takes P <- P - (P V_k) T_k V_k^dag; Q = P [I; 0] is P's first nx columns. The rows
+// follow the panels one update behind, so Q is complete one update after the last panel.
+// out (adjoint 0): Q row-major (mx x nx); (adjoint 1): Q^dag row-major (nx x mx). Waits are
+// bounded (barrier-timeout status).
 constexpr int kQbThreads = 1024;
+constexpr int kQbRows = 8;  // entries of a 512-long column (or row) per lane
 // Workspace of the blocked QR: X (mx x 16 G, column-major, the columns past nx zero), the panels'
 // T (G x 16 x 16) and G panel flags followed by an abort word.
 struct QbWs {
@@ -1192,101 +1199,19 @@ __global__ void qb_init_kernel(const double2* __restrict__ theta, SvdPlan p, QbW
 
 __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs q, double2* __restrict__ out,
                                                                int adjoint, int* status) {
-  extern __shared__ double2 cs[];  // [16][mx] the panel's columns
-  __shared__ double2 Ts[16][16], Ws[16][16];
+  // vs: a panel's V (16 x 512) staged for an update; during a factorisation its first 1024 entries
+  // hold the two reflector buffers; at the end of a row workgroup, the transposed rows
+  extern __shared__ double2 vs[];
+  __shared__ double2 Ts[16][16], Ws[16][16], Ys[16][16];
   __shared__ double2 tau_s[16], zs[2][16];
   __shared__ int abort_s;
-  const int m = p.mx, n = p.nx, g = blockIdx.x;
+  const int m = p.mx, n = p.nx, G = (n + 15) / 16;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int c0 = 16 * g;
   double2* X = q.X;
-  double2* Tall = q.T;
   unsigned* flags = q.flags;
-  unsigned* abort_word = q.flags + gridDim.x;
-  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
-    const int k = idx / m, r = idx % m;
-    cs[idx] = c0 + k < n ? X[(long long)(c0 + k) * m + r] : double2{0.0, 0.0};
-  }
+  unsigned* abort_word = q.flags + G;
   if (tid == 0) abort_s = 0;
-  __syncthreads();
 
-  // C <- C - V_k (T_k^(dag) (V_k^dag C)) on the panel in LDS; V_k from w.X, rows from 16 k on
-  auto apply = [&](int k, bool adj) {
-    const double2* V = X + (long long)(16 * k) * m;
-    const int r0 = 16 * k;
-    for (int idx = tid; idx < 256; idx += kQbThreads) Ts[idx >> 4][idx & 15] = Tall[(long long)k * 256 + idx];
-    // W = V^dag C: 32 blocks of 2 x 4 entries (a in [2 ab, 2 ab + 2), c in [4 cb, 4 cb + 4)), two per
-    // wave, each summed over the rows by the wave's lanes
-    for (int blk = wv; blk < 32; blk += 16) {
-      const int ab = blk >> 2, cb = blk & 3;
-      double acc[2][4][2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j][0] = acc[i][j][1] = 0.0;
-      for (int r = r0 + lane; r < m; r += 64) {
-        double2 v[2], x[4];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) v[i] = V[(long long)(2 * ab + i) * m + r];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = cs[(4 * cb + j) * m + r];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {  // conj(v) x
-            acc[i][j][0] = fma(v[i].x, x[j].x, fma(v[i].y, x[j].y, acc[i][j][0]));
-            acc[i][j][1] = fma(v[i].x, x[j].y, fma(-v[i].y, x[j].x, acc[i][j][1]));
-          }
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          wave_sum2(acc[i][j][0], acc[i][j][1]);
-          if (lane == 0) Ws[2 * ab + i][4 * cb + j] = double2{acc[i][j][0], acc[i][j][1]};
-        }
-    }
-    __syncthreads();
-    double2 y{0.0, 0.0};
-    if (tid < 256) {  // Y = T W (B_k) or T^dag W (B_k^dag); T upper triangular
-      const int a = tid >> 4, c = tid & 15;
-      if (adj) {
-        for (int b = 0; b <= a; ++b) {
-          const double2 t = Ts[b][a], x = Ws[b][c];
-          y.x = fma(t.x, x.x, fma(t.y, x.y, y.x));
-          y.y = fma(t.x, x.y, fma(-t.y, x.x, y.y));
-        }
-      } else {
-        for (int b = a; b < 16; ++b) {
-          const double2 t = Ts[a][b], x = Ws[b][c];
-          y.x = fma(t.x, x.x, fma(-t.y, x.y, y.x));
-          y.y = fma(t.x, x.y, fma(t.y, x.x, y.y));
-        }
-      }
-    }
-    __syncthreads();
-    if (tid < 256) Ws[tid >> 4][tid & 15] = y;
-    __syncthreads();
-    // C(r, c) -= sum_a V(r, a) Y(a, c): two threads per row (m <= 512), eight columns each
-    const int half = tid >= 512 ? 1 : 0;
-    if (const int r = r0 + (tid & 511); r < m) {
-      double2 x[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) x[j] = cs[(8 * half + j) * m + r];
-      for (int a = 0; a < 16; ++a) {
-        const double2 v = V[(long long)a * m + r];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const double2 yy = Ws[a][8 * half + j];
-          x[j].x -= v.x * yy.x - v.y * yy.y;
-          x[j].y -= v.x * yy.y + v.y * yy.x;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) cs[(8 * half + j) * m + r] = x[j];
-    }
-    __syncthreads();
-  };
   auto wait_panel = [&](int k) -> bool {
     if (tid == 0) {
       const unsigned long long t0 = wall_clock64();
@@ -1304,137 +1229,260 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
     __syncthreads();
     return abort_s == 0;
   };
+  // V_k (rows from 16 k on; the rows above are zero) into vs[a][r], T_k into Ts
+  auto stage = [&](int k) {
+    const double2* V = X + (long long)(16 * k) * m;
+#pragma unroll
+    for (int s = 0; s < kQbRows; ++s) {
+      const int idx = tid + kQbThreads * s;
+      const int a = idx >> 9, r = idx & 511;
+      vs[idx] = (r < m && r >= 16 * k) ? V[(long long)a * m + r] : double2{0.0, 0.0};
+    }
+    if (tid < 256) Ts[tid >> 4][tid & 15] = q.T[(long long)k * 256 + tid];
+    __syncthreads();
+  };
 
-  // phase 1: the earlier panels' reflectors, then this panel's factorisation
-  for (int k = 0; k < g; ++k) {
+  if ((int)blockIdx.x < G) {
+    // ------------------------------------------------------------------ panel workgroup
+    const int g = blockIdx.x, c0 = 16 * g;
+    const int ncol = min(16, n - c0);
+    const bool mine = wv < ncol;  // this wave holds one of the panel's columns
+    double2 x[kQbRows];
+#pragma unroll
+    for (int i = 0; i < kQbRows; ++i) {
+      const int r = lane + 64 * i;
+      x[i] = (mine && r < m) ? X[(long long)(c0 + wv) * m + r] : double2{0.0, 0.0};
+    }
+    for (int k = 0; k < g; ++k) {
+      if (!wait_panel(k)) {
+        if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
+        return;
+      }
+      stage(k);
+      const int ilo = (16 * k) >> 6;  // registers below it hold rows above 16 k
+      if (mine)  // W(a, w) = v_a^dag x_w
+        for (int a = 0; a < 16; ++a) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int i = 0; i < kQbRows; ++i) {
+            if (i < ilo) continue;
+            const double2 v = vs[a * 512 + lane + 64 * i];
+            sr = fma(v.x, x[i].x, fma(v.y, x[i].y, sr));
+            si = fma(v.x, x[i].y, fma(-v.y, x[i].x, si));
+          }
+          wave_sum2(sr, si);
+          if (lane == 0) Ws[wv][a] = double2{sr, si};
+        }
+      __syncthreads();
+      if (tid < 16 * ncol) {  // Y(a, w) = sum_{b <= a} conj(T(b, a)) W(b, w)
+        const int w = tid >> 4, a = tid & 15;
+        double2 y{0.0, 0.0};
+        for (int b = 0; b <= a; ++b) {
+          const double2 t = Ts[b][a], wb = Ws[w][b];
+          y.x = fma(t.x, wb.x, fma(t.y, wb.y, y.x));
+          y.y = fma(t.x, wb.y, fma(-t.y, wb.x, y.y));
+        }
+        Ys[w][a] = y;
+      }
+      __syncthreads();
+      if (mine)  // x_w -= V Y(:, w)
+        for (int a = 0; a < 16; ++a) {
+          const double2 y = Ys[wv][a];
+#pragma unroll
+          for (int i = 0; i < kQbRows; ++i) {
+            if (i < ilo) continue;
+            const double2 v = vs[a * 512 + lane + 64 * i];
+            x[i].x -= v.x * y.x - v.y * y.y;
+            x[i].y -= v.x * y.y + v.y * y.x;
+          }
+        }
+      __syncthreads();  // vs is staged again
+    }
+
+    double2* vb = vs;  // vb[0 .. 511], vb[512 .. 1023]: this step's reflector and the next one
+    // reflector of column j = c0 + w from the wave's column: beta = -sign(Re alpha) |x|, tau =
+    // (beta - alpha) / beta, v = x / (alpha - beta) below row j; the column becomes v (0 above row
+    // j, 1 on it), also written to vb[buf]
+    auto form = [&](int w, int buf) {
+      const int j = c0 + w, ij = j >> 6;
+      double2 al{0.0, 0.0};
+      double sq = 0.0, dummy = 0.0;
+#pragma unroll
+      for (int i = 0; i < kQbRows; ++i) {
+        const int r = lane + 64 * i;
+        if (r > j) sq = fma(x[i].x, x[i].x, fma(x[i].y, x[i].y, sq));
+        if (i == ij) al = x[i];
+      }
+      wave_sum2(sq, dummy);
+      al.x = __shfl(al.x, j & 63);
+      al.y = __shfl(al.y, j & 63);
+      double2 tv{0.0, 0.0}, sc{0.0, 0.0};
+      if (sq > 0.0 || al.y != 0.0) {
+        const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
+        const double beta = al.x >= 0.0 ? -xn : xn;
+        const double rb = 1.0 / beta;
+        tv = double2{(beta - al.x) * rb, -al.y * rb};
+        const double2 d{al.x - beta, al.y};
+        const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
+        sc = double2{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
+      }
+#pragma unroll
+      for (int i = 0; i < kQbRows; ++i) {
+        const int r = lane + 64 * i;
+        x[i] = r < j ? double2{0.0, 0.0} : r == j ? double2{1.0, 0.0} : cmul(x[i], sc);
+        vb[buf * 512 + r] = x[i];
+      }
+      if (lane == 0) tau_s[w] = tv;
+    };
+    // column jj of T from z(l) = v_l^dag v_jj (l < jj), one entry per thread of wave 0
+    auto t_column = [&](int jj) {
+      if (tid < 16) {
+        const int i = tid;
+        const double2 t = tau_s[jj];
+        const double2* z = zs[jj & 1];
+        double2 v{0.0, 0.0};
+        if (i == jj) v = t;
+        else if (i < jj) {
+          double2 acc{0.0, 0.0};
+          for (int l = i; l < jj; ++l) {
+            const double2 pr = cmul(Ts[i][l], z[l]);
+            acc = double2{acc.x + pr.x, acc.y + pr.y};
+          }
+          const double2 qv = cmul(t, acc);
+          v = double2{-qv.x, -qv.y};
+        }
+        Ts[i][jj] = v;
+      }
+    };
+    if (wv == 0) form(0, 0);
+    __syncthreads();
+    for (int jj = 0; jj < ncol; ++jj) {
+      const int j = c0 + jj, buf = jj & 1, ilo = j >> 6;
+      if (jj > 0) t_column(jj - 1);
+      if (mine && wv != jj) {
+        double2 v[kQbRows];
+#pragma unroll
+        for (int i = 0; i < kQbRows; ++i) v[i] = i < ilo ? double2{0.0, 0.0} : vb[buf * 512 + lane + 64 * i];
+        double dr = 0.0, di = 0.0;
+        if (wv > jj) {  // s = v^dag x, x -= v conj(tau) s
+#pragma unroll
+          for (int i = 0; i < kQbRows; ++i) {
+            dr = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, dr));
+            di = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, di));
+          }
+          wave_sum2(dr, di);
+          const double2 t = tau_s[jj];
+          const double2 f = cmul(double2{t.x, -t.y}, double2{dr, di});
+#pragma unroll
+          for (int i = 0; i < kQbRows; ++i) {
+            if (i < ilo) continue;
+            const double2 d = cmul(v[i], f);
+            x[i] = double2{x[i].x - d.x, x[i].y - d.y};
+          }
+          if (wv == jj + 1) form(wv, buf ^ 1);
+        } else {  // z(w) = v_w^dag v_jj (x holds v_w)
+#pragma unroll
+          for (int i = 0; i < kQbRows; ++i) {
+            dr = fma(x[i].x, v[i].x, fma(x[i].y, v[i].y, dr));
+            di = fma(x[i].x, v[i].y, fma(-x[i].y, v[i].x, di));
+          }
+          wave_sum2(dr, di);
+          if (lane == 0) zs[buf][wv] = double2{dr, di};
+        }
+      }
+      __syncthreads();
+    }
+    t_column(ncol - 1);
+    for (int jj = ncol; jj < 16; ++jj)  // columns past nx: identity reflectors (tau 0)
+      if (tid < 16) Ts[tid][jj] = double2{0.0, 0.0};
+    __syncthreads();
+    // publish V_g and T_g, then the flag
+    if (mine)
+#pragma unroll
+      for (int i = 0; i < kQbRows; ++i) {
+        const int r = lane + 64 * i;
+        if (r < m) X[(long long)(c0 + wv) * m + r] = x[i];
+      }
+    if (tid < 256) q.T[(long long)g * 256 + tid] = Ts[tid >> 4][tid & 15];
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&flags[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+
+  // -------------------------------------------------------------------- row workgroup
+  const int rb = blockIdx.x - G, row = 16 * rb + wv;
+  const bool live = row < m;
+  double2 pr[kQbRows];
+#pragma unroll
+  for (int i = 0; i < kQbRows; ++i) pr[i] = double2{lane + 64 * i == row ? 1.0 : 0.0, 0.0};
+  for (int k = 0; k < G; ++k) {
     if (!wait_panel(k)) {
       if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
       return;
     }
-    apply(k, true);
-  }
-  // the reflector of column j = c0 + jj (wave jj, its column up to date): beta = -sign(Re alpha) |x|,
-  // tau = (beta - alpha) / beta, v = x / (alpha - beta) below row j (stored in place), R(j, j) = beta
-  auto form = [&](int jj) {
-    const int j = c0 + jj;
-    double2* cj = cs + jj * m;
-    double sq = 0.0, dummy = 0.0;
-    for (int r = j + 1 + lane; r < m; r += 64) sq = fma(cj[r].x, cj[r].x, fma(cj[r].y, cj[r].y, sq));
-    wave_sum2(sq, dummy);
-    const double2 al = cj[j];
-    double2 tv{0.0, 0.0}, sc{0.0, 0.0};
-    double beta = al.x;
-    if (sq > 0.0 || al.y != 0.0) {
-      const double xn = sqrt(fma(al.x, al.x, fma(al.y, al.y, sq)));
-      beta = al.x >= 0.0 ? -xn : xn;
-      const double rb = 1.0 / beta;
-      tv = double2{(beta - al.x) * rb, -al.y * rb};
-      const double2 d{al.x - beta, al.y};
-      const double dn = 1.0 / fma(d.x, d.x, d.y * d.y);
-      sc = double2{d.x * dn, -d.y * dn};  // 1 / (alpha - beta)
-    }
-    for (int r = j + 1 + lane; r < m; r += 64) cj[r] = cmul(cj[r], sc);
-    if (lane == 0) {
-      cj[j] = double2{beta, 0.0};
-      tau_s[jj] = tv;
-    }
-  };
-  // column jj of T from the products z(l) = v_l^dag v_jj (l < jj), one entry per thread of wave 0
-  auto t_column = [&](int jj) {
-    if (tid < 16) {
-      const int i = tid;
-      const double2 t = tau_s[jj];
-      const double2* z = zs[jj & 1];
-      double2 v{0.0, 0.0};
-      if (i == jj) v = t;
-      else if (i < jj) {
-        double2 acc{0.0, 0.0};
-        for (int l = i; l < jj; ++l) {
-          const double2 pr = cmul(Ts[i][l], z[l]);
-          acc = double2{acc.x + pr.x, acc.y + pr.y};
+    stage(k);
+    const int ilo = (16 * k) >> 6;  // registers below it hold columns where V_k is zero
+    if (live)  // S(row, a) = sum_c P(row, c) V(c, a)
+      for (int a = 0; a < 16; ++a) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int i = 0; i < kQbRows; ++i) {
+          if (i < ilo) continue;
+          const double2 v = vs[a * 512 + lane + 64 * i];
+          sr = fma(pr[i].x, v.x, fma(-pr[i].y, v.y, sr));
+          si = fma(pr[i].x, v.y, fma(pr[i].y, v.x, si));
         }
-        const double2 q = cmul(t, acc);
-        v = double2{-q.x, -q.y};
+        wave_sum2(sr, si);
+        if (lane == 0) Ws[wv][a] = double2{sr, si};
       }
-      Ts[i][jj] = v;
-    }
-  };
-  const int ncol = min(16, n - c0);  // columns of this panel
-  if (wv == 0) form(0);
-  __syncthreads();
-  // step jj: the later columns take H_jj^dag (column jj + 1 then forms the next reflector at once),
-  // the earlier ones give z for T's column jj, and T's column jj - 1 is completed meanwhile
-  for (int jj = 0; jj < ncol; ++jj) {
-    const int j = c0 + jj;
-    const double2* cj = cs + jj * m;
-    if (jj > 0) t_column(jj - 1);
-    if (wv != jj && wv < ncol) {
-      double2* ck = cs + wv * m;
-      const bool later = wv > jj;
-      double dr = 0.0, di = 0.0;
-      for (int r = j + 1 + lane; r < m; r += 64) {
-        const double2 a = later ? cj[r] : ck[r], b = later ? ck[r] : cj[r];  // conj(a) b
-        dr = fma(a.x, b.x, fma(a.y, b.y, dr));
-        di = fma(a.x, b.y, fma(-a.y, b.x, di));
+    __syncthreads();
+    if (tid < 256 && 16 * rb + (tid >> 4) < m) {  // Y(row, b) = sum_{a <= b} S(row, a) T(a, b)
+      const int w = tid >> 4, bcol = tid & 15;
+      double2 y{0.0, 0.0};
+      for (int a = 0; a <= bcol; ++a) {
+        const double2 pv = cmul(Ws[w][a], Ts[a][bcol]);
+        y = double2{y.x + pv.x, y.y + pv.y};
       }
-      wave_sum2(dr, di);
-      const double2 cjk = ck[j];
-      if (later) {  // s = v^dag col (v(j) = 1), col -= v conj(tau) s
-        const double2 sv{cjk.x + dr, cjk.y + di};
-        const double2 t = tau_s[jj];
-        const double2 f = cmul(double2{t.x, -t.y}, sv);
-        if (lane == 0) ck[j] = double2{cjk.x - f.x, cjk.y - f.y};
-        for (int r = j + 1 + lane; r < m; r += 64) {
-          const double2 d = cmul(cj[r], f);
-          ck[r] = double2{ck[r].x - d.x, ck[r].y - d.y};
-        }
-        if (wv == jj + 1) form(jj + 1);
-      } else if (lane == 0) {  // z = conj(v_wv(j)) + sum conj(v_wv) v_j
-        zs[jj & 1][wv] = double2{cjk.x + dr, -cjk.y + di};
-      }
+      Ys[w][bcol] = y;
     }
     __syncthreads();
+    if (live)  // P(row, c) -= sum_b Y(row, b) conj(V(c, b))
+      for (int bcol = 0; bcol < 16; ++bcol) {
+        const double2 y = Ys[wv][bcol];
+#pragma unroll
+        for (int i = 0; i < kQbRows; ++i) {
+          if (i < ilo) continue;
+          const double2 v = vs[bcol * 512 + lane + 64 * i];
+          pr[i].x -= fma(y.x, v.x, y.y * v.y);
+          pr[i].y -= fma(y.y, v.x, -y.x * v.y);
+        }
+      }
+    __syncthreads();  // vs is staged again
   }
-  t_column(ncol - 1);
-  for (int jj = ncol; jj < 16; ++jj)  // columns past nx: identity reflectors (tau 0)
-    if (tid < 16) Ts[tid][jj] = double2{0.0, 0.0};
+  if (!adjoint) {
+    if (live)
+#pragma unroll
+      for (int i = 0; i < kQbRows; ++i) {
+        const int c = lane + 64 * i;
+        if (c < n) out[(long long)row * n + c] = pr[i];
+      }
+    return;
+  }
+  // Q^dag: the 16 rows transposed through LDS (entry (c, w) at c 16 + (w xor (c mod 16)))
+#pragma unroll
+  for (int i = 0; i < kQbRows; ++i) {
+    const int c = lane + 64 * i;
+    if (c < n) vs[c * 16 + (wv ^ (c & 15))] = double2{pr[i].x, -pr[i].y};
+  }
   __syncthreads();
-  // publish V_g (zeros above the diagonal, 1 on it) and T_g
-  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
-    const int k = idx / m, r = idx % m, j = c0 + k;
-    if (j >= n) continue;
-    double2 v{0.0, 0.0};
-    if (r == j) v = double2{1.0, 0.0};
-    else if (r > j) v = cs[idx];
-    X[(long long)j * m + r] = v;
+  const int nrow = min(16, m - 16 * rb);
+  for (int idx = tid; idx < 16 * n; idx += kQbThreads) {
+    const int c = idx >> 4, w = idx & 15;
+    if (w < nrow) out[(long long)c * m + 16 * rb + w] = vs[c * 16 + (w ^ (c & 15))];
   }
-  if (tid < 256) Tall[(long long)g * 256 + tid] = Ts[tid >> 4][tid & 15];
-  __syncthreads();
-  if (tid == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&flags[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // the compute unit's cache may still hold this panel's input columns, now V_g
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  // phase 2: column block g of Q
-  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
-    const int k = idx / m, r = idx % m;
-    cs[idx] = double2{r == c0 + k ? 1.0 : 0.0, 0.0};
-  }
-  __syncthreads();
-  for (int k = g; k >= 0; --k) apply(k, false);
-  for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
-    const int k = idx % 16, r = idx / 16, c = c0 + k;  // row-major runs of 16 columns
-    if (c >= n || adjoint) continue;
-    out[(long long)r * n + c] = cs[k * m + r];
-  }
-  if (adjoint)
-    for (int idx = tid; idx < 16 * m; idx += kQbThreads) {
-      const int k = idx / m, r = idx % m, c = c0 + k;
-      if (c >= n) continue;
-      const double2 q = cs[idx];
-      out[(long long)c * m + r] = double2{q.x, -q.y};
-    }
 }
 
 // Y = R^dag into dst (q.mx = nx rows, q.np columns, column-major, columns from q.nx = min(mx, nx)
@@ -1759,12 +1807,13 @@ hipError_t qr_isometry(const SvdPlan& p, const double2* theta, double2* out, boo
   int adj = adjoint ? 1 : 0;
   int* stp = status;
   void* args[] = {&pp, &qq, &o, &adj, &stp};
-  const size_t lds = sizeof(double2) * 16 * (size_t)p.mx;
+  const size_t lds = kQrLdsBytes;  // vs: 16 x 512 complex
+  const int wgs = G + (p.mx + 15) / 16;  // the panels, then the row blocks of Q
   const void* fn = reinterpret_cast<const void*>(qr_blocked_kernel);
   if (coop)
-    MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kQbThreads), args, (unsigned)lds, st));
+    MPOEVO_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(wgs), dim3(kQbThreads), args, (unsigned)lds, st));
   else
-    MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(G), dim3(kQbThreads), args, lds, st));
+    MPOEVO_HIP_TRY(hipLaunchKernel(fn, dim3(wgs), dim3(kQbThreads), args, lds, st));
   last_launch() = LaunchRecord{fn, false};
   return hipSuccess;
 }
