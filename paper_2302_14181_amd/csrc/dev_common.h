@@ -27,6 +27,8 @@ struct GemmDesc {
   void* ws;         // optional scratch for split-K partial tiles (null: never split)
   size_t ws_bytes;
   bool bf16x3;      // fp32 operands: split-BF16x3 products on the bf16 matrix cores
+  bool row_tail;    // the rows past another launch's whole row blocks: the smallest tile that
+                    // holds them in one row block, K unsplit
 };
 
 // Scratch a caller gives gemm_launch for split-K partial results (the planner never needs more).
@@ -35,6 +37,11 @@ constexpr size_t kGemmScratchBytes = size_t(32) << 20;
 // Launch a complex product with real fp32 (T = float) or fp64 (T = double) matrix-core
 // arithmetic. out_fp64: store C as complex128 even when T = float. Returns a hipError_t.
 hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st);
+
+// Rows to launch apart from a product's whole row blocks: M mod the rule's tile rows when that
+// tile's last row block would be at most half filled and a smaller tile (32 or 64 rows) holds
+// them, else 0. Only the FP32 three-product path splits.
+int gemm_row_tail(const GemmDesc& g, bool fp64);
 
 // Host function of the kernel this thread launched last among the timed kernel classes (the
 // products' main kernel, the W contractions, the Jacobi kernel) and whether a split-K sum

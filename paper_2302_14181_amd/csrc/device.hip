@@ -228,9 +228,25 @@ Arith arith_of(int prec) { return Arith{prec == MPOEVO_FP64, prec == MPOEVO_BF16
 hipError_t gemm_timed(const GemmDesc& g, Arith ar, bool out_fp64, hipStream_t st, Prof* pr) {
   GemmDesc h = g;
   h.bf16x3 = ar.bf16x3 && !ar.fp64;
+  // rows that would leave the tile's last row block mostly empty (an MPO bond of 271 on 128-row
+  // tiles) go to a second product on a tile of 32 or 64 rows
+  const int tail = gemm_row_tail(h, ar.fp64);
+  GemmDesc t = h;
+  if (tail > 0) {
+    h.M -= tail;
+    t.M = tail;
+    t.row_tail = true;
+    t.A = static_cast<const unsigned char*>(g.A) + sizeof(float2) * (size_t)h.M * g.sAm;
+    t.C = static_cast<unsigned char*>(g.C) + (out_fp64 ? sizeof(double2) : sizeof(float2)) * (size_t)h.M * g.sCm;
+  }
   PROF_BEGIN(pr, tok);
   MPOEVO_HIP_TRY(gemm_launch(h, ar.fp64, out_fp64, st));
   PROF_END(pr, tok, Prof::kGemm, gemm_flop(h));
+  if (tail > 0) {
+    PROF_BEGIN(pr, tok2);
+    MPOEVO_HIP_TRY(gemm_launch(t, ar.fp64, out_fp64, st));
+    PROF_END(pr, tok2, Prof::kGemm, gemm_flop(t));
+  }
   return hipSuccess;
 }
 

@@ -909,6 +909,14 @@ Plan make_plan(const GemmDesc& g, const int (*cfgs)[2], int ncfg) {
     return (long long)((g.M + cfgs[c][0] - 1) / cfgs[c][0]) * ((g.N + cfgs[c][1] - 1) / cfgs[c][1]) * g.batch;
   };
   Plan p{ncfg - 1, cfgs[ncfg - 1][0], cfgs[ncfg - 1][1], 1, g.K};
+  if (g.row_tail) {  // the smallest tile rows that hold M (the table lists tiles by falling rows)
+    for (int c = ncfg - 1; c >= 0; --c)
+      if (cfgs[c][0] >= g.M) {
+        p.cfg = c; p.bm = cfgs[c][0]; p.bn = cfgs[c][1];
+        return p;
+      }
+    return p;
+  }
   for (int c = 0; c < ncfg; ++c)
     if (tiles(c) >= kMinWgs && cfgs[c][1] <= std::max(g.N, 64)) {  // no tile twice as wide as C
       p.cfg = c; p.bm = cfgs[c][0]; p.bn = cfgs[c][1];
@@ -1229,6 +1237,14 @@ int gemm_plan_query(void* t, int prec, int M, int N, int K, int batch, int* out)
   }
   out[0] = p.bm; out[1] = p.bn; out[2] = p.splits; out[3] = tuned;
   return 0;
+}
+
+int gemm_row_tail(const GemmDesc& g, bool fp64) {
+  if (fp64 || g.bf16x3 || g.row_tail || g.M <= 0 || g.N <= 0 || g.batch <= 0) return 0;
+  const Plan p = make_plan<MfmaF32>(g, k3mCfg, 4);
+  const int rem = g.M % p.bm;
+  const int tail_rows = rem <= 32 ? 32 : 64;  // the tile the rows past the whole blocks would take
+  return (g.M > p.bm && rem > 0 && 2 * rem <= p.bm && rem <= 64 && tail_rows < p.bm) ? rem : 0;
 }
 
 hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st) {
