@@ -276,3 +276,107 @@ def fit_step_one_site(psi, Ws, nsweeps: int = 2, guess=None):
     phi[0] = M / norm if norm > 0 else M
     dims = [1] + [phi[i].shape[2] for i in range(L)]
     return phi, dict(norm=norm, norms=norms, bond_dims=dims)
+
+
+def frozen_bonds(bond_dims, d: int, Dmax: int):
+    """frozen[b] (b = 0 .. L): bond b is at its largest value min(Dmax, d^b, d^(L-b)) (the two ends
+    always)."""
+    L = len(bond_dims) - 1
+    out = [True] * (L + 1)
+    for b in range(1, L):
+        out[b] = bond_dims[b] == min(Dmax, d ** min(b, L - b))
+    return out
+
+
+def fit_step_mixed(psi, Ws, Dmax: int, nsweeps: int = 2, cutoff: float = 1e-14):
+    """One time step with the update chosen per position (our reading for states whose bonds are
+    still growing; Sec. 2.2 gives both fits, Sec. 8.2 keeps the bond dimension fixed): the bonds
+    at their largest value in the right-canonicalised guess are frozen; the sweeps visit the
+    positions of the two-site fit (fit_step), and a position whose site has both bonds frozen --
+    site i going left to right, site i + 1 going right to left -- takes the one-site update of
+    that site (fit_step_one_site: QR of its projected tensor), every other position the two-site
+    update (SVD truncation at Dmax, which may grow its bond). When the last visit is a one-site
+    update, site 0's projected tensor completes phi as in the one-site fit. If a two-site update
+    leaves a frozen bond below its starting value, the one-site updates next to it would no longer
+    see the bond they were planned for: the step is then the plain two-site fit instead.
+    With every bond frozen this is fit_step_one_site, with none fit_step. Returns (phi, stats)
+    with stats = dict(norm, discarded (per visit, 0 for one-site visits), bond_dims, kinds (1 or 2
+    per visit), fallback)."""
+    L = len(psi)
+    if not isinstance(Ws, (list, tuple)):
+        Ws = [Ws] * L
+    d = psi[0].shape[1]
+    phi = right_canonicalize(psi)
+    start = [1] + [phi[i].shape[2] for i in range(L)]
+    fz = frozen_bonds(start, d, Dmax)
+    if L == 1 or not any(fz[i] and fz[i + 1] for i in range(L)):
+        ref, st = fit_step(psi, Ws, Dmax, nsweeps, cutoff)
+        return ref, dict(st, kinds=[2] * len(st["discarded"]), fallback=False)
+    Lenv = [None] * (L + 1)
+    Renv = [None] * (L + 1)
+    Lenv[0] = boundary_env(Ws[0].shape[0])
+    Renv[L] = boundary_env(Ws[-1].shape[3])
+    for i in range(L - 1, 0, -1):
+        Renv[i] = env_right(Renv[i + 1], phi[i], Ws[i], psi[i])
+    discarded, kinds = [], []
+    S = None
+    last_one = False
+
+    def shrunk(b, k):  # a two-site update left the frozen bond b below its starting value
+        return fz[b] and k < start[b]
+
+    for _ in range(nsweeps):
+        for i in range(0, L - 1):  # left to right
+            if fz[i] and fz[i + 1]:
+                M = local_one_site(Lenv[i], psi[i], Ws[i], Renv[i + 1])
+                a, p, b = M.shape
+                Q, _ = np.linalg.qr(M.reshape(a * p, b))
+                phi[i] = Q.reshape(a, p, b)
+                discarded.append(0.0)
+                kinds.append(1)
+            else:
+                th = theta_two_site(Lenv[i], psi[i], Ws[i], psi[i + 1], Ws[i + 1], Renv[i + 2])
+                a, p, q, c = th.shape
+                U, S, Vh, disc = svd_truncate(th.reshape(a * p, q * c), Dmax, cutoff)
+                k = S.size
+                if shrunk(i + 1, k):
+                    ref, st = fit_step(psi, Ws, Dmax, nsweeps, cutoff)
+                    return ref, dict(st, kinds=[2] * len(st["discarded"]), fallback=True)
+                discarded.append(disc)
+                kinds.append(2)
+                phi[i] = U.reshape(a, p, k)
+                phi[i + 1] = (S[:, None] * Vh).reshape(k, q, c)
+            Lenv[i + 1] = env_left(Lenv[i], phi[i], Ws[i], psi[i])
+        for i in range(L - 2, -1, -1):  # right to left
+            if fz[i + 1] and fz[i + 2]:
+                M = local_one_site(Lenv[i + 1], psi[i + 1], Ws[i + 1], Renv[i + 2])
+                a, p, b = M.shape
+                Q, _ = np.linalg.qr(M.reshape(a, p * b).conj().T)
+                phi[i + 1] = Q.conj().T.reshape(a, p, b)
+                discarded.append(0.0)
+                kinds.append(1)
+                last_one = True
+            else:
+                th = theta_two_site(Lenv[i], psi[i], Ws[i], psi[i + 1], Ws[i + 1], Renv[i + 2])
+                a, p, q, c = th.shape
+                U, S, Vh, disc = svd_truncate(th.reshape(a * p, q * c), Dmax, cutoff)
+                k = S.size
+                if shrunk(i + 1, k):
+                    ref, st = fit_step(psi, Ws, Dmax, nsweeps, cutoff)
+                    return ref, dict(st, kinds=[2] * len(st["discarded"]), fallback=True)
+                discarded.append(disc)
+                kinds.append(2)
+                phi[i] = (U * S[None, :]).reshape(a, p, k)
+                phi[i + 1] = Vh.reshape(k, q, c)
+                last_one = False
+            Renv[i + 1] = env_right(Renv[i + 2], phi[i + 1], Ws[i + 1], psi[i + 1])
+    if last_one:  # site 0's projected tensor completes phi (one-site fit)
+        M = local_one_site(Lenv[0], psi[0], Ws[0], Renv[1])
+        norm = float(np.linalg.norm(M))
+        phi[0] = M / norm if norm > 0 else M
+    else:
+        norm = float(np.linalg.norm(S))
+        if norm > 0:
+            phi[0] = phi[0] / norm
+    dims = [1] + [phi[i].shape[2] for i in range(L)]
+    return phi, dict(norm=norm, discarded=discarded, bond_dims=dims, kinds=kinds, fallback=False)
