@@ -268,7 +268,15 @@ typedef struct {
                    and d Dmax <= 512 (ESHAPE otherwise); stats: discarded weights 0, visits =
                    2 (L-1) nsweeps + 1 local updates, no Jacobi sweeps.
                    -1: automatic -- one-site when every bond of psi equals its largest possible
-                   value min(Dmax, d^i, d^(L-i)) (and d Dmax <= 512), else two-site. */
+                   value min(Dmax, d^i, d^(L-i)) (and d Dmax <= 512); else, when some site has
+                   both bonds at that value ("frozen" at the start of the step; d Dmax <= 512,
+                   no zip-up guess, no U(1) charges), a mixed sweep: the visits of the two-site
+                   sweep, where a position whose site (i going left to right, i + 1 going right
+                   to left) has both bonds frozen takes that site's one-site update and the other
+                   positions the two-site update; when the last visit is a one-site update, the
+                   projected tensor of site 0 completes phi. If a two-site update leaves a frozen
+                   bond below its value, the step is redone with two-site updates throughout
+                   (stats->two_site_redo). Otherwise two-site. */
   int use_graph; /* 1: the step's device work (everything between the opening check of the
                    workspace and the closing read-back of ranks and statistics) is captured into a
                    HIP graph the second time a step with the same plan runs on this handle (the
@@ -340,6 +348,10 @@ typedef struct {
   int graph;                /* opts->use_graph: 0 the work was issued launch by launch, 1 it was
                                captured into a new graph (then launched), 2 a graph replayed it */
   int guess;                /* the guess the sweeps started from: 0 psi, 1 the zip-up */
+  int one_site_visits;      /* visits that took the one-site update (all of them with nsites 1;
+                               with nsites -1 those at sites whose two bonds were frozen) */
+  int two_site_redo;        /* 1: the automatic mode's mixed sweep found a frozen bond shrunk by a
+                               two-site update and the step was redone with two-site updates */
 } mpoevo_step_stats;
 
 int step(mpoevo_handle h, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_step_opts* opts,

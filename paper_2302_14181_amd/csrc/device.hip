@@ -51,9 +51,10 @@ struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int> P, bond_of_visit, k_slot_of_bond, warm_dim;
+  std::vector<char> visit_kind, frozen;
   int last_visit_k_slot = 0, updates = 0;
   double gflop = 0.0;
-  bool one_site = false;
+  bool one_site = false, mixed = false;
 };
 constexpr size_t kMaxGraphs = 8;
 
@@ -147,6 +148,20 @@ __global__ void permute_w_left(const C2* __restrict__ W, C2* __restrict__ Wt, in
     const int sp = (int)(r % d);
     const int alpha = (int)(r / d);
     Wt[((long long)sp * wr + beta) * (wl * d) + alpha * d + s] = W[i];
+  }
+}
+
+// The statistics slots of a visit that takes the one-site update: bond k kept, nothing discarded,
+// no Jacobi sweeps, a complete basis.
+__global__ void one_site_visit_slots(int* kbuf, double* dbuf, double* nbuf, int* sweeps, int* cplt, int* blocks,
+                                     int k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *kbuf = k;
+    *dbuf = 0.0;
+    *nbuf = 0.0;
+    *sweeps = 0;
+    *cplt = 1;
+    *blocks = 0;
   }
 }
 
@@ -1140,6 +1155,9 @@ struct StepPost {
   bool* one_site;
   int* updates;
   int* graph_use;  // 0 issued, 1 captured, 2 replayed
+  std::vector<char>* visit_kind;  // per visit: 1 one-site, 2 two-site update
+  std::vector<char>* frozen;      // per bond: at its largest value when the step started
+  bool* mixed;
 };
 
 // Issues the device work of a step (body). With opts->use_graph (and neither profiling nor U(1)
@@ -1154,11 +1172,12 @@ struct StepPost {
 template <class Body>
 int run_step_body(Context& ctx, const mpoevo_step_opts* opts, const mpoevo_mps* mps, const mpoevo_mpo* mpo,
                   const void* ws, const std::vector<int>& Q, bool profiling, bool u1, bool warm_on,
-                  hipStream_t& st, Body& body, StepPost post) {
+                  hipStream_t& st, Body& body, StepPost post, bool two_site_only) {
   *post.graph_use = 0;
   if (!opts->use_graph || profiling || u1) return body();
   const int L = mps->L;
   std::vector<long long> key = {L, mps->d, mps->Dmax, opts->prec, opts->nsweeps, opts->nsites, opts->guess,
+                                two_site_only ? 1 : 0,
                                 opts->input_right_canonical, opts->svd_cold_start, warm_on ? 1 : 0,
                                 (long long)(uintptr_t)ws, ctx.tuner ? gemm_tuner_mode(ctx.tuner, -1) : -1,
                                 ctx.tuner ? (long long)gemm_tuner_generation(ctx.tuner) : -1};
@@ -1200,6 +1219,9 @@ int run_step_body(Context& ctx, const mpoevo_step_opts* opts, const mpoevo_mps* 
     *post.gflop = g.gflop;
     *post.one_site = g.one_site;
     *post.updates = g.updates;
+    *post.visit_kind = g.visit_kind;
+    *post.frozen = g.frozen;
+    *post.mixed = g.mixed;
     *post.graph_use = 2;
     ctx.warm_dim = g.warm_dim;
     return MPOEVO_OK;
@@ -1242,6 +1264,9 @@ int run_step_body(Context& ctx, const mpoevo_step_opts* opts, const mpoevo_mps* 
   g.gflop = *post.gflop;
   g.one_site = *post.one_site;
   g.updates = *post.updates;
+  g.visit_kind = *post.visit_kind;
+  g.frozen = *post.frozen;
+  g.mixed = *post.mixed;
   g.warm_dim = ctx.warm_dim;
   if (ds.graphs.size() >= kMaxGraphs) {
     (void)hipGraphExecDestroy(ds.graphs.front().exec);
@@ -1421,10 +1446,23 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   std::vector<int> bond_of_visit(nvis, 0);
   bool one_site = false;
   int updates = 0;
+  // automatic mode with bonds still growing: the bonds at their largest value when the step starts
+  // are frozen, and a position whose site has both bonds frozen takes that site's one-site update
+  std::vector<char> frozen(L + 1, 1), visit_kind(nvis, 2);
+  bool mixed = false, two_site_only = false;
   std::vector<int> u1_k(u1 ? nvis : 0);
   std::vector<double> u1_d(u1 ? nvis : 0), u1_n(u1 ? nvis : 0);
   std::vector<int> u1_zero(u1 ? nvis : 0, 0), u1_one(u1 ? nvis : 0, 1);
+  const std::vector<int> P0(P);
+  std::vector<int> P_guess;  // the guess's bonds (the one-site visits keep them)
   auto body = [&]() -> int {
+  P = P0;
+  visit = 0;
+  last_visit_k_slot = 0;
+  std::fill(k_slot_of_bond.begin(), k_slot_of_bond.end(), -1);
+  std::fill(visit_kind.begin(), visit_kind.end(), 2);
+  gflop = 0.0;
+  jac_recs.clear();
   // inputs in contraction precision; phi <- psi
   for (int i = 0; i < L; ++i) {
     const long long ns = (long long)Q[i] * d * Q[i + 1];
@@ -1525,6 +1563,31 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     one_site = d * Dmax <= 512 && !u1;
     for (int b = 1; b < L && one_site; ++b) one_site = P[b] == cap_of(b);
   }
+  auto qr_visit = [&](int m, int n, bool left_to_right, double2* out) -> hipError_t {
+    // left to right: Q of the (D_i d) x D_{i+1} tensor; right to left: Q^dag of the transposed
+    const SvdPlan qp = svd_plan_qr(m, n, left_to_right ? MPOEVO_RIGHT : MPOEVO_LEFT);
+    PROF_BEGIN(prof, qt);
+    MPOEVO_HIP_TRY(qr_isometry(qp, theta, out, !left_to_right, svdws, ctx.dev->status, st, ctx.coop_jacobi));
+    PROF_END(prof, qt, Prof::kQr, qr_flop(std::max(m, n), std::min(m, n)));
+    return hipSuccess;
+  };
+  mixed = false;
+  P_guess = P;
+  std::fill(frozen.begin(), frozen.end(), 1);
+  if (opts->nsites == -1 && !zip && !u1 && !one_site && !two_site_only && d * Dmax <= 512) {
+    for (int b = 1; b < L; ++b) frozen[b] = P[b] == cap_of(b) ? 1 : 0;
+    for (int i = 0; i < L && !mixed; ++i) mixed = frozen[i] && frozen[i + 1];
+  }
+  // a one-site visit of site i: both its bonds frozen and still at their starting values (a
+  // two-site update that shrank one makes the step fall back to two-site updates, see below)
+  auto one_site_at = [&](int i) {
+    return mixed && frozen[i] && frozen[i + 1] && P[i] == P_guess[i] && P[i + 1] == P_guess[i + 1];
+  };
+  auto one_site_slots = [&](int v, int k) -> hipError_t {
+    hipLaunchKernelGGL(one_site_visit_slots, dim3(1), dim3(64), 0, st, kbuf + v, dbuf + v, nbuf + v,
+                       sweeps_buf + v, cplt_buf + v, blocks_buf + v, k);
+    return hipGetLastError();
+  };
   if (one_site) {
     if (d * Dmax > 512) { ctx.err = "step: one-site updates need d Dmax <= 512"; return MPOEVO_ESHAPE; }
     for (int i = 0; i + 1 < L; ++i)
@@ -1536,14 +1599,6 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     auto envL = [&](int i) -> void* { return LB(i); };
     auto envR = [&](int i) -> void* { return RB(i - 1); };
     void* blk = base + lay.off_blk;
-    auto qr_visit = [&](int m, int n, bool left_to_right, double2* out) -> hipError_t {
-      // left to right: Q of the (D_i d) x D_{i+1} tensor; right to left: Q^dag of the transposed
-      const SvdPlan qp = svd_plan_qr(m, n, left_to_right ? MPOEVO_RIGHT : MPOEVO_LEFT);
-      PROF_BEGIN(prof, qt);
-      MPOEVO_HIP_TRY(qr_isometry(qp, theta, out, !left_to_right, svdws, ctx.dev->status, st, ctx.coop_jacobi));
-      PROF_END(prof, qt, Prof::kQr, qr_flop(std::max(m, n), std::min(m, n)));
-      return hipSuccess;
-    };
     STEP_TRY(set_boundary(envR(L), w[L], fp64, st));
     for (int i = L - 1; i >= 1; --i) {
       STEP_TRY(right_block(ar, ket(i), envR(i + 1), wsite(i), tmp, blk, Q[i], d, Q[i + 1], P[i + 1], w[i],
@@ -1636,6 +1691,22 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
                           w[i + 1], st, prof, gws, xws));
       flop_gemm((double)P[i] * w[i], (double)d * Q[i + 1], Q[i]);
       flop_gemm((double)P[i] * d * w[i + 1], Q[i + 1], (double)w[i] * d);  // the W contraction
+      if (one_site_at(i)) {
+        // site i's projected tensor against the right environment of bond i + 1 (from the right
+        // block of site i + 1), replaced by its QR factor
+        STEP_TRY(right_env_from_block(ar, bra(i + 1), RB(i + 1), env1, P[i + 1], d, P[i + 2], w[i + 1], Q[i + 1],
+                                      st, prof, gws));
+        flop_gemm(P[i + 1], (double)w[i + 1] * Q[i + 1], (double)d * P[i + 2]);
+        STEP_TRY(local_left(ar, LB(i), env1, theta, P[i], d, w[i + 1], Q[i + 1], P[i + 1], st, prof, gws));
+        flop_gemm((double)P[i] * d, P[i + 1], (double)w[i + 1] * Q[i + 1]);
+        STEP_TRY(qr_visit(P[i] * d, P[i + 1], true, phi(i)));
+        STEP_TRY(one_site_slots(visit, P[i + 1]));
+        visit_kind[visit] = 1;
+        bond_of_visit[visit] = i;
+        last_visit_k_slot = visit;
+        STEP_TRY(bra_refresh(i));
+        continue;
+      }
       const int m = P[i] * d, n = d * P[i + 2];
       STEP_TRY(theta_product(ar, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
@@ -1685,6 +1756,22 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
         flop_gemm((double)Q[i + 1] * d, (double)P[i + 2] * w[i + 2], Q[i + 2]);
         flop_gemm((double)w[i + 1] * d * Q[i + 1], P[i + 2], (double)d * w[i + 2]);  // the W contraction
       }
+      if (one_site_at(i + 1)) {
+        // site i + 1's projected tensor against the left environment of bond i + 1 (from the left
+        // block of site i), replaced by the adjoint QR factor of its adjoint
+        STEP_TRY(left_env_from_block(ar, bra(i), LB(i), env0, P[i], d, P[i + 1], w[i + 1], Q[i + 1], st, prof,
+                                     gws));
+        flop_gemm(P[i + 1], (double)w[i + 1] * Q[i + 1], (double)P[i] * d);
+        STEP_TRY(local_right(ar, env0, RB(i + 1), theta, P[i + 1], w[i + 1], Q[i + 1], d, P[i + 2], st, prof, gws));
+        flop_gemm(P[i + 1], (double)d * P[i + 2], (double)w[i + 1] * Q[i + 1]);
+        STEP_TRY(qr_visit(P[i + 1], d * P[i + 2], false, phi(i + 1)));
+        STEP_TRY(one_site_slots(visit, P[i + 1]));
+        visit_kind[visit] = 1;
+        bond_of_visit[visit] = i;
+        last_visit_k_slot = visit;
+        STEP_TRY(bra_refresh(i + 1));
+        continue;
+      }
       const int m = P[i] * d, n = d * P[i + 2];
       STEP_TRY(theta_product(ar, LB(i), RB(i + 1), theta, P[i], d, w[i + 1], Q[i + 1], P[i + 2], st, prof, gws));
       flop_gemm(m, n, (double)w[i + 1] * Q[i + 1]);
@@ -1730,19 +1817,42 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     STEP_TRY(hipMemcpyAsync(cplt_buf, u1_one.data(), sizeof(int) * nvis, hipMemcpyHostToDevice, st));
     STEP_TRY(hipMemcpyAsync(blocks_buf, u1_zero.data(), sizeof(int) * nvis, hipMemcpyHostToDevice, st));
   }
-  // normalise with the norm of the last visit (phi_0 holds U S)
-  STEP_TRY([&] {
-    hipLaunchKernelGGL(scale_by_inverse_norm, dim3(grid_for((long long)P[0] * d * P[1])), dim3(256), 0,
-                       st, phi(0), (long long)P[0] * d * P[1], nbuf + last_visit_k_slot);
-    return hipGetLastError();
-  }());
+  if (mixed && visit_kind[visit - 1] == 1) {
+    // the last visit updated site 1: site 0's projected tensor completes phi (its norm is the
+    // fitted norm, kept in that visit's slot)
+    STEP_TRY(right_env_from_block(ar, bra(1), RB(1), env1, P[1], d, P[2], w[1], Q[1], st, prof, gws));
+    flop_gemm(P[1], (double)w[1] * Q[1], (double)d * P[2]);
+    STEP_TRY(right_block(ar, ket(0), env1, wsite(0), tmp, LB(0), Q[0], d, Q[1], P[1], w[0], w[1], st, prof, gws,
+                         xws));
+    flop_gemm((double)Q[0] * d, (double)P[1] * w[1], Q[1]);
+    flop_gemm((double)w[0] * d * Q[0], P[1], (double)d * w[1]);
+    STEP_TRY(set_boundary(env0, w[0], fp64, st));
+    STEP_TRY(local_right(ar, env0, LB(0), theta, P[0], w[0], Q[0], d, P[1], st, prof, gws));
+    flop_gemm(P[0], (double)d * P[1], (double)w[0] * Q[0]);
+    STEP_TRY([&] {
+      hipLaunchKernelGGL(norm_scale_kernel, dim3(1), dim3(256), 0, st, theta, phi(0),
+                         (long long)P[0] * d * P[1], nbuf + (visit - 1));
+      return hipGetLastError();
+    }());
+    last_visit_k_slot = visit - 1;
+  } else {
+    // normalise with the norm of the last visit (phi_0 holds U S)
+    STEP_TRY([&] {
+      hipLaunchKernelGGL(scale_by_inverse_norm, dim3(grid_for((long long)P[0] * d * P[1])), dim3(256), 0,
+                         st, phi(0), (long long)P[0] * d * P[1], nbuf + last_visit_k_slot);
+      return hipGetLastError();
+    }());
+  }
     return MPOEVO_OK;
   };
 
   int graph_use = 0;
+  // a second pass (two-site updates throughout) when the mixed step's check below fails
+  for (int pass = 0;; ++pass) {
   if (const int rc = run_step_body(ctx, opts, mps, mpo, ws, Q, prof != nullptr, u1, warm_on, st, body,
                                    StepPost{&P, &bond_of_visit, &k_slot_of_bond, &last_visit_k_slot, &gflop,
-                                            &one_site, &updates, &graph_use});
+                                            &one_site, &updates, &graph_use, &visit_kind, &frozen, &mixed},
+                                   two_site_only);
       rc != MPOEVO_OK)
     return rc;
 
@@ -1765,6 +1875,7 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       std::memset(stats, 0, sizeof(*stats));
       stats->norm = norm;
       stats->visits = updates;
+      stats->one_site_visits = updates;
       stats->max_bond = maxb;
       stats->gflop = gflop;
       stats->graph = graph_use;
@@ -1810,8 +1921,25 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   STEP_TRY(hipStreamSynchronize(st));
   const int sres = check_solver_dev(ctx, st);
   if (sres != MPOEVO_OK) return sres;
+  if (mixed && pass == 0) {
+    // a two-site update that left a frozen bond below its value changed a bond that the one-site
+    // updates next to it took as fixed: the step is redone with two-site updates throughout
+    bool shrunk = false;
+    for (int v = 0; v < nvis && !shrunk; ++v) {
+      const int b = bond_of_visit[v] + 1;
+      shrunk = visit_kind[v] == 2 && frozen[b] && kh[v] < cap_of(b);
+    }
+    if (shrunk) {
+      two_site_only = true;
+      if (prof) {
+        prof->recs.clear();
+        prof->next = 0;
+      }
+      continue;
+    }
+  }
   std::vector<int> Pact(L + 1, 1);
-  for (int b = 1; b < L; ++b) Pact[b] = kh[k_slot_of_bond[b]];
+  for (int b = 1; b < L; ++b) Pact[b] = k_slot_of_bond[b] >= 0 ? kh[k_slot_of_bond[b]] : P[b];
   // a bond is taken as rank-deficient when any of its truncations in this step was (near the
   // onset of the rank deficiency the visits of one bond disagree, and a needless QR costs less
   // than a completion)
@@ -1844,6 +1972,9 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
       stats->discarded_sum += dh[v];
     }
     stats->visits = nvis;
+    stats->one_site_visits = 0;
+    for (int v = 0; v < nvis; ++v) stats->one_site_visits += mixed && visit_kind[v] == 1 ? 1 : 0;
+    stats->two_site_redo = two_site_only ? 1 : 0;
     stats->max_bond = maxb;
     stats->gflop = gflop;
     stats->svd_sweeps_max = ctx.max_sweeps;
@@ -1917,8 +2048,9 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
     ctx.warm_ws = ws;
     std::copy(sig, sig + 5, ctx.warm_sig);
   }
-#undef STEP_TRY
   return MPOEVO_OK;
+  }
+#undef STEP_TRY
 }
 
 // ------------------------------------------------------------------------- batched chains

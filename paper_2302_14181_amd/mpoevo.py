@@ -69,7 +69,8 @@ class _Stats(ctypes.Structure):
                 ("t_wmix_ms", ctypes.c_double), ("wmix_gbyte", ctypes.c_double), ("n_wmix", ctypes.c_int),
                 ("svd_sweeps_total", ctypes.c_int), ("svd_sweeps_hist", ctypes.c_int * 32),
                 ("n_kernel_stats", ctypes.c_int), ("kernel_stats", _KernelStat * MAX_KERNEL_STATS),
-                ("graph", ctypes.c_int), ("guess", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("guess", ctypes.c_int), ("one_site_visits", ctypes.c_int),
+                ("two_site_redo", ctypes.c_int)]
 
 
 _lib = None
@@ -333,6 +334,8 @@ class StepStats:
     svd_sweeps_hist: tuple = ()
     graph: int = 0  # use_graph: 0 issued launch by launch, 1 captured into a new graph, 2 replayed
     guess: int = 0  # the guess the sweeps started from: 0 psi, 1 the zip-up
+    one_site_visits: int = 0  # visits that took the one-site update
+    two_site_redo: int = 0  # 1: the automatic mode's mixed sweep was redone with two-site updates
 
 
 class DeviceMPS:
@@ -513,7 +516,7 @@ def _stats_of(st, profile) -> StepStats:
                            for k in st.kernel_stats[:st.n_kernel_stats]]
     return StepStats(st.norm, st.discarded_max, st.discarded_sum, st.visits, st.max_bond, st.gflop,
                      st.svd_sweeps_max, prof, st.svd_sweeps_total, tuple(st.svd_sweeps_hist), st.graph,
-                     st.guess)
+                     st.guess, st.one_site_visits, st.two_site_redo)
 
 
 def step_batched_workspace(chains, mpos, prec: int):
