@@ -156,6 +156,15 @@ def guess_of(mp, args):
     return {"canonical": mp.GUESS_CANONICAL, "zipup": mp.GUESS_ZIPUP, "auto": mp.GUESS_AUTO}[args.guess]
 
 
+def update_kind(st):
+    """The updates a step took: one-site, two-site or mixed (with its count of one-site visits)."""
+    if st.one_site_visits == st.visits:
+        return "one-site"
+    if st.one_site_visits == 0:
+        return "two-site" + (" (redone)" if st.two_site_redo else "")
+    return f"mixed, {st.one_site_visits}/{st.visits} one-site"
+
+
 def trajectory(torch, mp, h, psi0, dw, prec, steps, Dmax, profile=False, progress=None, nsites=2, guess=0,
                use_graph=False):
     """`steps` time steps from psi0 on a fresh MPS and workspace; HIP events on the launch stream
@@ -172,7 +181,7 @@ def trajectory(torch, mp, h, psi0, dw, prec, steps, Dmax, profile=False, progres
         ev[k + 1].record()
         if progress:
             print(f"[bench] {progress} step {k + 1}/{steps}: bond {st[-1].max_bond}, "
-                  f"{'one' if st[-1].discarded_sum == 0 and st[-1].visits % 2 == 1 else 'two'}-site"
+                  f"{update_kind(st[-1])}"
                   f"{', zip-up guess' if st[-1].guess else ''}{', graph' if st[-1].graph else ''}",
                   file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -251,13 +260,15 @@ def traffic_of(kernel_name):
     return None
 
 
-def lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, Dmax, delta2=True):
+def lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, Dmax, delta2=True, nsites=-1):
     """Per-step parity against the oracle on the opening steps of the trajectory from all-up:
     step 1 from psi0 (R17-A: 1 - |<phi_gpu|phi_oracle>|^2; R17-B: |eps_gpu - eps_oracle| with
     eps = 1 - |<phi|W psi>|^2 / ||W psi||^2, the device state's overlap with W psi0 taken in FP64 on
     the device, ||W psi0||^2 from the oracle's double-layer contraction) on every contraction precision, and step 2 restarted from the oracle's state
     after step 1 (delta_2, R17-A; the norm error in place of R17-B, whose ||W psi1||^2 is beyond the
-    oracle's budget)."""
+    oracle's budget) with the trajectory's update mode: from the oracle's step-1 state the edge
+    bonds are already at their largest values, so the automatic mode runs a mixed sweep there,
+    against the oracle's fit_step_mixed."""
     from oracle import fit as ofit
     t0 = time.perf_counter()
     ref1, r1 = ofit.fit_step(psi0, Wo, Dmax=Dmax)
@@ -295,15 +306,24 @@ def lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, Dmax, delta2=True):
     zs["oracle_eps_canonical_guess"] = eps_or
     out["step1_zipup_guess"] = zs
     if delta2:
-        ref2, r2 = ofit.fit_step(ref1, Wo, Dmax=Dmax)
+        if nsites == -1:
+            ref2, r2 = ofit.fit_step_mixed(ref1, Wo, Dmax=Dmax)
+        elif nsites == 1:
+            ref2, r2 = ofit.fit_step_one_site(ref1, Wo)
+            r2["discarded"] = [0.0]
+        else:
+            ref2, r2 = ofit.fit_step(ref1, Wo, Dmax=Dmax)
         z2 = ofit.expect_local(ref2, wl.SZ, LR_SITE).real
         out["step2_from_oracle_state"] = {"oracle_norm": r2["norm"], "oracle_max_bond": max(r2["bond_dims"]),
-                                          "oracle_discarded_sum": float(sum(r2["discarded"]))}
+                                          "oracle_discarded_sum": float(sum(r2["discarded"])),
+                                          "nsites": nsites,
+                                          "oracle_one_site_visits": r2.get("kinds", []).count(1)}
         for name, p in (("fp32", mp.FP32), ("fp64", mp.FP64)):
             dm = mp.DeviceMPS(ref1, Dmax=Dmax)
-            s = mp.step(h, dm, dw, prec=p)
+            s = mp.step(h, dm, dw, prec=p, nsites=nsites)
             phi = dm.to_numpy()
             out["step2_from_oracle_state"][name] = {
+                "one_site_visits": s.one_site_visits,
                 "infidelity_R17A": float(1.0 - abs(ofit.overlap(phi, ref2)) ** 2),
                 "norm_rel_error": float(abs(s.norm - r2["norm"]) / r2["norm"]),
                 "discarded_sum_abs_error": float(abs(s.discarded_sum - sum(r2["discarded"]))),
@@ -421,7 +441,7 @@ def run_lr3(args, torch, mp, wl, h):
         Wo = ompo.build_mpo(H, LR_ORDER, -1j * LR_TAU, "V2")
         if prog:
             print("[bench] lr3 parity against the oracle (steps 1 and 2)", file=sys.stderr, flush=True)
-        parity = lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, LR_D, delta2=not args.no_delta2)
+        parity = lr3_parity(torch, mp, h, wl, W, Wo, dw, psi0, LR_D, delta2=not args.no_delta2, nsites=ns)
         if prog:
             print("[bench] lr3 CPU oracle baseline", file=sys.stderr, flush=True)
         cpu = lr3_cpu_baseline(Wo, wl, LR_D)
@@ -444,7 +464,9 @@ def run_lr3(args, torch, mp, wl, h):
                                 "frozen for the timed steps", "entries": h.product_plan(prec, 1, 1, 1)["entries"]}
                        if tune else None),
         "max_bond_per_step": [x.max_bond for x in st],
-        "one_site_steps": [i + 1 for i, x in enumerate(st) if x.visits == 4 * (LR_L - 1) + 1],
+        "one_site_steps": [i + 1 for i, x in enumerate(st) if x.one_site_visits == x.visits],
+        "mixed_steps": {i + 1: f"{x.one_site_visits}/{x.visits} one-site visits" for i, x in enumerate(st)
+                        if 0 < x.one_site_visits < x.visits},
         "discarded_sum_per_step": [x.discarded_sum for x in st],
         "saturated_steps": len(sat),
         "saturated_s_per_step": float(np.mean([ms[i] for i in sat])) / 1e3 if sat else None,
