@@ -276,10 +276,12 @@ __global__ __launch_bounds__(kThreads) void cgemm_kernel(GemmDesc g, int splits,
 // 32 x 32 complex outputs) owns a BM x BN complex tile, double-buffered with one barrier per K
 // step of BK; with KW > 1 the groups take equal slices of every step (two waves per SIMD, so that
 // one wave's staging and barrier wait overlap the other's matrix instructions) and their partial
-// sums meet in LDS at the end, in group order. Tiles: 128 x 128 (one group of 2 x 2 waves, each
-// 64 x 64: half the operand traffic per flop of 128 x 64, for the large products of wide MPO
-// bonds),
-// 128 x 64 (one group), 64 x 64 (two groups), 32 x 64 (four groups of 1 x 2 waves, BK = 64: 256
+// sums meet in LDS at the end, in group order. Tiles: 128 x 128 (one group of 4 x 2 waves, each
+// 32 x 64: half the operand traffic per flop of 128 x 64, for the large products of wide MPO
+// bonds; eight waves of 96 accumulator registers leave room for two waves per SIMD, which hide
+// each other's staging and barrier waits -- four waves of 64 x 64 held one per SIMD and ran the
+// long-range one-site step 5 % slower), 128 x 64 (one group of 4 x 2 waves of 32 x 32, BK = 32,
+// for the same reason), 64 x 64 (two groups), 32 x 64 (four groups of 1 x 2 waves, BK = 64: 256
 // workgroups for a 256 x 2048 output without splitting K).
 // Rounding: the sums carry one more rounding and Im C a difference of products, so its error
 // bound is about twice that of the expanded form, normwise.
@@ -1151,8 +1153,8 @@ hipError_t plan_and_run(const GemmDesc& g, const int (*cfgs)[2], int ncfg, int k
 
 template <typename TO>
 hipError_t run_3m(const GemmDesc& g, const Plan& pl, hipStream_t st) {
-  if (pl.cfg == 0) return launch_3m_cfg<2, 2, 16, 1, 2, TO, true>(g, pl, st);
-  if (pl.cfg == 1) return launch_3m_cfg<2, 1, 16, 1, 2, TO>(g, pl, st);
+  if (pl.cfg == 0) return launch_3m_cfg<1, 2, 16, 1, 4, TO, true>(g, pl, st);
+  if (pl.cfg == 1) return launch_3m_cfg<1, 1, 32, 1, 4, TO>(g, pl, st);
   if (pl.cfg == 2) return launch_3m_cfg<1, 1, 32, 2, 2, TO>(g, pl, st);
   return launch_3m_cfg<1, 1, 64, 4, 1, TO>(g, pl, st);
 }
