@@ -1139,31 +1139,33 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
 // workgroups followed by ceil(mx / 16) row workgroups.
 // Panel workgroup g owns the columns [16 g, 16 g + 16), one wave per column, each column in its
 // wave's registers (lane l, register i: row l + 64 i). For k = 0 .. g - 1 it waits for panel k
-// (flag) and applies B_k^dag = I - V_k T_k^dag V_k^dag to its columns (V_k staged in LDS), then
+// (flag) and applies B_k^dag = H_15^dag ... H_0^dag to its columns, reflector by reflector (V_k
+// staged in LDS: one pass over V, where the compact-WY form B_k^dag = I - V_k T_k^dag V_k^dag
+// takes two and an exchange between the waves), then
 // factorises its panel with 16 Householder steps (H_j = I - tau_j v_j v_j^dag, v_j(j) = 1, H_j^dag
 // zeroes column j below row j): at step j the wave of column j + 1 takes H_j^dag and forms the next
 // reflector at once, handing it to the other waves through LDS (two buffers, one barrier per
-// column), while the waves of the earlier columns give the inner products for T's column j. The
-// compact-WY T_g (B_g = H_0 ... H_15 = I - V_g T_g V_g^dag, T_g upper triangular, column j:
-// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^dag v_j) and V_g (in the panel's own
-// columns of q.X: zeros above the diagonal, 1 on it) are published and the flag raised (release).
+// column). V_g (in the panel's own columns of q.X: zeros above the diagonal, 1 on it) and its 16
+// taus (q.tau, 0 for the columns past nx: identity reflectors) are published and the flag raised
+// (release).
 // Row workgroup b owns rows [16 b, 16 b + 16) of P = B_0 B_1 ... B_{G-1} (one wave per row, the row
 // in registers: lane l, register i: column l + 64 i). It starts from the identity and, as panel k
-// is published, takes P <- P - (P V_k) T_k V_k^dag; Q = P [I; 0] is P's first nx columns. The rows
+// is published, takes P <- P B_k = P H_0 ... H_15 (reflector by reflector: P -= tau (P v) v^dag);
+// Q = P [I; 0] is P's first nx columns. The rows
 // follow the panels one update behind, so Q is complete one update after the last panel.
 // out (adjoint 0): Q row-major (mx x nx); (adjoint 1): Q^dag row-major (nx x mx). Waits are
 // bounded (barrier-timeout status).
 constexpr int kQbThreads = 1024;
 constexpr int kQbRows = 8;  // entries of a 512-long column (or row) per lane
 // Workspace of the blocked QR: X (mx x 16 G, column-major, the columns past nx zero), the panels'
-// T (G x 16 x 16) and G panel flags followed by an abort word.
+// taus (G x 16) and G panel flags followed by an abort word.
 struct QbWs {
   double2* X;
-  double2* T;
+  double2* tau;
   unsigned* flags;
 };
 size_t qb_bytes(int mx, int G) {
-  return align256(sizeof(double2) * (size_t)mx * 16 * G) + align256(sizeof(double2) * 256 * (size_t)G) +
+  return align256(sizeof(double2) * (size_t)mx * 16 * G) + align256(sizeof(double2) * 16 * (size_t)G) +
          align256(sizeof(unsigned) * (size_t)(G + 1));
 }
 QbWs qb_carve(int mx, int G, void* ws) {
@@ -1171,8 +1173,8 @@ QbWs qb_carve(int mx, int G, void* ws) {
   QbWs q;
   q.X = reinterpret_cast<double2*>(base);
   base += align256(sizeof(double2) * (size_t)mx * 16 * G);
-  q.T = reinterpret_cast<double2*>(base);
-  base += align256(sizeof(double2) * 256 * (size_t)G);
+  q.tau = reinterpret_cast<double2*>(base);
+  base += align256(sizeof(double2) * 16 * (size_t)G);
   q.flags = reinterpret_cast<unsigned*>(base);
   return q;
 }
@@ -1202,8 +1204,8 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
   // vs: a panel's V (16 x 512) staged for an update; during a factorisation its first 1024 entries
   // hold the two reflector buffers; at the end of a row workgroup, the transposed rows
   extern __shared__ double2 vs[];
-  __shared__ double2 Ts[16][16], Ws[16][16], Ys[16][16];
-  __shared__ double2 tau_s[16], zs[2][16];
+  __shared__ double2 tk[16];  // a staged panel's taus
+  __shared__ double2 tau_s[16];
   __shared__ int abort_s;
   const int m = p.mx, n = p.nx, G = (n + 15) / 16;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1229,7 +1231,7 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
     __syncthreads();
     return abort_s == 0;
   };
-  // V_k (rows from 16 k on; the rows above are zero) into vs[a][r], T_k into Ts
+  // V_k (rows from 16 k on; the rows above are zero) into vs[a][r], its taus into tk
   auto stage = [&](int k) {
     const double2* V = X + (long long)(16 * k) * m;
 #pragma unroll
@@ -1238,7 +1240,7 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
       const int a = idx >> 9, r = idx & 511;
       vs[idx] = (r < m && r >= 16 * k) ? V[(long long)a * m + r] : double2{0.0, 0.0};
     }
-    if (tid < 256) Ts[tid >> 4][tid & 15] = q.T[(long long)k * 256 + tid];
+    if (tid < 16) tk[tid] = q.tau[16 * k + tid];
     __syncthreads();
   };
 
@@ -1260,40 +1262,26 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
       }
       stage(k);
       const int ilo = (16 * k) >> 6;  // registers below it hold rows above 16 k
-      if (mine)  // W(a, w) = v_a^dag x_w
+      // B_k^dag x_w = H_15^dag ... H_0^dag x_w, one reflector after the other (one pass over V,
+      // where the compact-WY form takes two): x -= v_a conj(tau_a) (v_a^dag x)
+      if (mine)
         for (int a = 0; a < 16; ++a) {
+          double2 v[kQbRows];
           double sr = 0.0, si = 0.0;
 #pragma unroll
           for (int i = 0; i < kQbRows; ++i) {
-            if (i < ilo) continue;
-            const double2 v = vs[a * 512 + lane + 64 * i];
-            sr = fma(v.x, x[i].x, fma(v.y, x[i].y, sr));
-            si = fma(v.x, x[i].y, fma(-v.y, x[i].x, si));
+            v[i] = i < ilo ? double2{0.0, 0.0} : vs[a * 512 + lane + 64 * i];
+            sr = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, sr));
+            si = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, si));
           }
           wave_sum2(sr, si);
-          if (lane == 0) Ws[wv][a] = double2{sr, si};
-        }
-      __syncthreads();
-      if (tid < 16 * ncol) {  // Y(a, w) = sum_{b <= a} conj(T(b, a)) W(b, w)
-        const int w = tid >> 4, a = tid & 15;
-        double2 y{0.0, 0.0};
-        for (int b = 0; b <= a; ++b) {
-          const double2 t = Ts[b][a], wb = Ws[w][b];
-          y.x = fma(t.x, wb.x, fma(t.y, wb.y, y.x));
-          y.y = fma(t.x, wb.y, fma(-t.y, wb.x, y.y));
-        }
-        Ys[w][a] = y;
-      }
-      __syncthreads();
-      if (mine)  // x_w -= V Y(:, w)
-        for (int a = 0; a < 16; ++a) {
-          const double2 y = Ys[wv][a];
+          const double2 t = tk[a];
+          const double2 f = cmul(double2{t.x, -t.y}, double2{sr, si});
 #pragma unroll
           for (int i = 0; i < kQbRows; ++i) {
             if (i < ilo) continue;
-            const double2 v = vs[a * 512 + lane + 64 * i];
-            x[i].x -= v.x * y.x - v.y * y.y;
-            x[i].y -= v.x * y.y + v.y * y.x;
+            const double2 dd = cmul(v[i], f);
+            x[i] = double2{x[i].x - dd.x, x[i].y - dd.y};
           }
         }
       __syncthreads();  // vs is staged again
@@ -1334,76 +1322,41 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
       }
       if (lane == 0) tau_s[w] = tv;
     };
-    // column jj of T from z(l) = v_l^dag v_jj (l < jj), one entry per thread of wave 0
-    auto t_column = [&](int jj) {
-      if (tid < 16) {
-        const int i = tid;
-        const double2 t = tau_s[jj];
-        const double2* z = zs[jj & 1];
-        double2 v{0.0, 0.0};
-        if (i == jj) v = t;
-        else if (i < jj) {
-          double2 acc{0.0, 0.0};
-          for (int l = i; l < jj; ++l) {
-            const double2 pr = cmul(Ts[i][l], z[l]);
-            acc = double2{acc.x + pr.x, acc.y + pr.y};
-          }
-          const double2 qv = cmul(t, acc);
-          v = double2{-qv.x, -qv.y};
-        }
-        Ts[i][jj] = v;
-      }
-    };
     if (wv == 0) form(0, 0);
     __syncthreads();
     for (int jj = 0; jj < ncol; ++jj) {
       const int j = c0 + jj, buf = jj & 1, ilo = j >> 6;
-      if (jj > 0) t_column(jj - 1);
-      if (mine && wv != jj) {
+      if (mine && wv > jj) {  // s = v^dag x, x -= v conj(tau) s
         double2 v[kQbRows];
 #pragma unroll
         for (int i = 0; i < kQbRows; ++i) v[i] = i < ilo ? double2{0.0, 0.0} : vb[buf * 512 + lane + 64 * i];
         double dr = 0.0, di = 0.0;
-        if (wv > jj) {  // s = v^dag x, x -= v conj(tau) s
 #pragma unroll
-          for (int i = 0; i < kQbRows; ++i) {
-            dr = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, dr));
-            di = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, di));
-          }
-          wave_sum2(dr, di);
-          const double2 t = tau_s[jj];
-          const double2 f = cmul(double2{t.x, -t.y}, double2{dr, di});
-#pragma unroll
-          for (int i = 0; i < kQbRows; ++i) {
-            if (i < ilo) continue;
-            const double2 d = cmul(v[i], f);
-            x[i] = double2{x[i].x - d.x, x[i].y - d.y};
-          }
-          if (wv == jj + 1) form(wv, buf ^ 1);
-        } else {  // z(w) = v_w^dag v_jj (x holds v_w)
-#pragma unroll
-          for (int i = 0; i < kQbRows; ++i) {
-            dr = fma(x[i].x, v[i].x, fma(x[i].y, v[i].y, dr));
-            di = fma(x[i].x, v[i].y, fma(-x[i].y, v[i].x, di));
-          }
-          wave_sum2(dr, di);
-          if (lane == 0) zs[buf][wv] = double2{dr, di};
+        for (int i = 0; i < kQbRows; ++i) {
+          dr = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, dr));
+          di = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, di));
         }
+        wave_sum2(dr, di);
+        const double2 t = tau_s[jj];
+        const double2 f = cmul(double2{t.x, -t.y}, double2{dr, di});
+#pragma unroll
+        for (int i = 0; i < kQbRows; ++i) {
+          if (i < ilo) continue;
+          const double2 d = cmul(v[i], f);
+          x[i] = double2{x[i].x - d.x, x[i].y - d.y};
+        }
+        if (wv == jj + 1) form(wv, buf ^ 1);
       }
       __syncthreads();
     }
-    t_column(ncol - 1);
-    for (int jj = ncol; jj < 16; ++jj)  // columns past nx: identity reflectors (tau 0)
-      if (tid < 16) Ts[tid][jj] = double2{0.0, 0.0};
-    __syncthreads();
-    // publish V_g and T_g, then the flag
+    // publish V_g and its taus, then the flag
     if (mine)
 #pragma unroll
       for (int i = 0; i < kQbRows; ++i) {
         const int r = lane + 64 * i;
         if (r < m) X[(long long)(c0 + wv) * m + r] = x[i];
       }
-    if (tid < 256) q.T[(long long)g * 256 + tid] = Ts[tid >> 4][tid & 15];
+    if (tid < 16) q.tau[16 * g + tid] = tid < ncol ? tau_s[tid] : double2{0.0, 0.0};
     __syncthreads();
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1425,39 +1378,24 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
     }
     stage(k);
     const int ilo = (16 * k) >> 6;  // registers below it hold columns where V_k is zero
-    if (live)  // S(row, a) = sum_c P(row, c) V(c, a)
+    // P_row B_k = P_row H_0 ... H_15, one reflector after the other: P -= tau_a (P v_a) v_a^dag
+    if (live)
       for (int a = 0; a < 16; ++a) {
+        double2 v[kQbRows];
         double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int i = 0; i < kQbRows; ++i) {
-          if (i < ilo) continue;
-          const double2 v = vs[a * 512 + lane + 64 * i];
-          sr = fma(pr[i].x, v.x, fma(-pr[i].y, v.y, sr));
-          si = fma(pr[i].x, v.y, fma(pr[i].y, v.x, si));
+          v[i] = i < ilo ? double2{0.0, 0.0} : vs[a * 512 + lane + 64 * i];
+          sr = fma(pr[i].x, v[i].x, fma(-pr[i].y, v[i].y, sr));
+          si = fma(pr[i].x, v[i].y, fma(pr[i].y, v[i].x, si));
         }
         wave_sum2(sr, si);
-        if (lane == 0) Ws[wv][a] = double2{sr, si};
-      }
-    __syncthreads();
-    if (tid < 256 && 16 * rb + (tid >> 4) < m) {  // Y(row, b) = sum_{a <= b} S(row, a) T(a, b)
-      const int w = tid >> 4, bcol = tid & 15;
-      double2 y{0.0, 0.0};
-      for (int a = 0; a <= bcol; ++a) {
-        const double2 pv = cmul(Ws[w][a], Ts[a][bcol]);
-        y = double2{y.x + pv.x, y.y + pv.y};
-      }
-      Ys[w][bcol] = y;
-    }
-    __syncthreads();
-    if (live)  // P(row, c) -= sum_b Y(row, b) conj(V(c, b))
-      for (int bcol = 0; bcol < 16; ++bcol) {
-        const double2 y = Ys[wv][bcol];
+        const double2 f = cmul(tk[a], double2{sr, si});
 #pragma unroll
         for (int i = 0; i < kQbRows; ++i) {
           if (i < ilo) continue;
-          const double2 v = vs[bcol * 512 + lane + 64 * i];
-          pr[i].x -= fma(y.x, v.x, y.y * v.y);
-          pr[i].y -= fma(y.y, v.x, -y.x * v.y);
+          pr[i].x -= fma(f.x, v[i].x, f.y * v[i].y);
+          pr[i].y -= fma(f.y, v[i].x, -f.x * v[i].y);
         }
       }
     __syncthreads();  // vs is staged again
