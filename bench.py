@@ -475,8 +475,12 @@ def run_lr3(args, torch, mp, wl, h):
         "products_frac_of_peak": gemm_tf * 1e12 / {mp.FP32: PEAK_FP32_MFMA, mp.FP64: PEAK_FP64_MFMA,
                                                    mp.BF16X3: PEAK_BF16_MFMA}[prec],
         "class_ms_timed_steps": {"jacobi_svd": prof["t_jacobi_ms"], "complex_gemm": prof["t_gemm_ms"],
-                                 "w_contraction": prof["t_wmix_ms"], "all_steps": float(np.sum(ms))},
-        "svd_sweeps_mean": float(np.mean([x.svd_sweeps_total / max(x.visits, 1) for x in st])),
+                                 "w_contraction": prof["t_wmix_ms"],
+                                 "householder_qr": float(sum(r["ms"] for r in kt if r["kind"] == "householder_qr")),
+                                 "all_steps": float(np.sum(ms))},
+        # Jacobi sweeps per two-site truncation (one-site visits take none)
+        "svd_sweeps_mean": float(sum(x.svd_sweeps_total for x in st) /
+                                 max(sum(x.visits - x.one_site_visits for x in st), 1)),
         "Z50_end": z_end,
         "roofline": roofline_of(kt[0]),
         "kernels_timed_steps": kt[:8],
