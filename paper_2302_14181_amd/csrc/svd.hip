@@ -1158,7 +1158,8 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
 constexpr int kQbThreads = 1024;
 constexpr int kQbRows = 8;  // entries of a 512-long column (or row) per lane
 // Workspace of the blocked QR: X (mx x 16 G, column-major, the columns past nx zero), the panels'
-// taus (G x 16) and G panel flags followed by an abort word.
+// taus (G x 16), G panel flags, an abort word, then 4 G quarter flags (panel g's reflectors
+// 4 q .. 4 q + 3 published).
 struct QbWs {
   double2* X;
   double2* tau;
@@ -1166,7 +1167,7 @@ struct QbWs {
 };
 size_t qb_bytes(int mx, int G) {
   return align256(sizeof(double2) * (size_t)mx * 16 * G) + align256(sizeof(double2) * 16 * (size_t)G) +
-         align256(sizeof(unsigned) * (size_t)(G + 1));
+         align256(sizeof(unsigned) * (size_t)(5 * G + 1));
 }
 QbWs qb_carve(int mx, int G, void* ws) {
   unsigned char* base = static_cast<unsigned char*>(ws);
@@ -1196,7 +1197,7 @@ __global__ void qb_init_kernel(const double2* __restrict__ theta, SvdPlan p, QbW
     q.X[idx] = v;
   }
   if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i <= G; i += blockDim.x) q.flags[i] = 0u;
+    for (int i = threadIdx.x; i < 5 * G + 1; i += blockDim.x) q.flags[i] = 0u;
 }
 
 __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs q, double2* __restrict__ out,
@@ -1212,12 +1213,13 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
   double2* X = q.X;
   unsigned* flags = q.flags;
   unsigned* abort_word = q.flags + G;
+  unsigned* qflags = q.flags + G + 1;
   if (tid == 0) abort_s = 0;
 
-  auto wait_panel = [&](int k) -> bool {
+  auto wait_flag = [&](unsigned* f) -> bool {
     if (tid == 0) {
       const unsigned long long t0 = wall_clock64();
-      while (__hip_atomic_load(&flags[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
         if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
             wall_clock64() - t0 > kBarrierTimeoutTicks) {
           __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1231,16 +1233,16 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
     __syncthreads();
     return abort_s == 0;
   };
-  // V_k (rows from 16 k on; the rows above are zero) into vs[a][r], its taus into tk
-  auto stage = [&](int k) {
+  // reflectors a0 .. a0 + na - 1 of panel k (rows from 16 k on; the rows above are zero) into
+  // vs[a][r], their taus into tk[a] (na = 4 or 16)
+  auto stage = [&](int k, int a0, int na) {
     const double2* V = X + (long long)(16 * k) * m;
-#pragma unroll
-    for (int s = 0; s < kQbRows; ++s) {
-      const int idx = tid + kQbThreads * s;
+    for (int s = 0; s < na / 2; ++s) {
+      const int idx = 512 * a0 + tid + kQbThreads * s;
       const int a = idx >> 9, r = idx & 511;
       vs[idx] = (r < m && r >= 16 * k) ? V[(long long)a * m + r] : double2{0.0, 0.0};
     }
-    if (tid < 16) tk[tid] = q.tau[16 * k + tid];
+    if (tid < na) tk[a0 + tid] = q.tau[16 * k + a0 + tid];
     __syncthreads();
   };
 
@@ -1256,35 +1258,40 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
       x[i] = (mine && r < m) ? X[(long long)(c0 + wv) * m + r] : double2{0.0, 0.0};
     }
     for (int k = 0; k < g; ++k) {
-      if (!wait_panel(k)) {
-        if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
-        return;
-      }
-      stage(k);
-      const int ilo = (16 * k) >> 6;  // registers below it hold rows above 16 k
-      // B_k^dag x_w = H_15^dag ... H_0^dag x_w, one reflector after the other (one pass over V,
-      // where the compact-WY form takes two): x -= v_a conj(tau_a) (v_a^dag x)
-      if (mine)
-        for (int a = 0; a < 16; ++a) {
-          double2 v[kQbRows];
-          double sr = 0.0, si = 0.0;
-#pragma unroll
-          for (int i = 0; i < kQbRows; ++i) {
-            v[i] = i < ilo ? double2{0.0, 0.0} : vs[a * 512 + lane + 64 * i];
-            sr = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, sr));
-            si = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, si));
-          }
-          wave_sum2(sr, si);
-          const double2 t = tk[a];
-          const double2 f = cmul(double2{t.x, -t.y}, double2{sr, si});
-#pragma unroll
-          for (int i = 0; i < kQbRows; ++i) {
-            if (i < ilo) continue;
-            const double2 dd = cmul(v[i], f);
-            x[i] = double2{x[i].x - dd.x, x[i].y - dd.y};
-          }
+      // the panel just before this one is taken a quarter at a time, as its reflectors appear
+      const int nq = k == g - 1 ? 4 : 1, na = 16 / nq;
+      for (int qd = 0; qd < nq; ++qd) {
+        if (!wait_flag(nq == 4 ? &qflags[4 * k + qd] : &flags[k])) {
+          if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
+          return;
         }
-      __syncthreads();  // vs is staged again
+        const int a0 = qd * na;
+        stage(k, a0, na);
+        const int ilo = (16 * k) >> 6;  // registers below it hold rows above 16 k
+        // H_a^dag x for a = a0 .. a0 + na - 1, one reflector after the other (one pass over V,
+        // where the compact-WY form takes two): x -= v_a conj(tau_a) (v_a^dag x)
+        if (mine)
+          for (int a = a0; a < a0 + na; ++a) {
+            double2 v[kQbRows];
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int i = 0; i < kQbRows; ++i) {
+              v[i] = i < ilo ? double2{0.0, 0.0} : vs[a * 512 + lane + 64 * i];
+              sr = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, sr));
+              si = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, si));
+            }
+            wave_sum2(sr, si);
+            const double2 t = tk[a];
+            const double2 f = cmul(double2{t.x, -t.y}, double2{sr, si});
+#pragma unroll
+            for (int i = 0; i < kQbRows; ++i) {
+              if (i < ilo) continue;
+              const double2 dd = cmul(v[i], f);
+              x[i] = double2{x[i].x - dd.x, x[i].y - dd.y};
+            }
+          }
+        __syncthreads();  // vs is staged again
+      }
     }
 
     double2* vb = vs;  // vb[0 .. 511], vb[512 .. 1023]: this step's reflector and the next one
@@ -1319,6 +1326,7 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
         const int r = lane + 64 * i;
         x[i] = r < j ? double2{0.0, 0.0} : r == j ? double2{1.0, 0.0} : cmul(x[i], sc);
         vb[buf * 512 + r] = x[i];
+        if (r < m) X[(long long)j * m + r] = x[i];  // v_j is final: published at once
       }
       if (lane == 0) tau_s[w] = tv;
     };
@@ -1348,14 +1356,15 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
         if (wv == jj + 1) form(wv, buf ^ 1);
       }
       __syncthreads();
-    }
-    // publish V_g and its taus, then the flag
-    if (mine)
-#pragma unroll
-      for (int i = 0; i < kQbRows; ++i) {
-        const int r = lane + 64 * i;
-        if (r < m) X[(long long)(c0 + wv) * m + r] = x[i];
+      // reflectors jj - 2 .. jj + 1 formed (their columns written above): a quarter for the next
+      // panel, which has one only if this panel is full
+      if (g + 1 < G && (jj & 3) == 2 && tid == 0) {
+        for (int t = jj - 2; t <= jj + 1; ++t) q.tau[16 * g + t] = tau_s[t];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&qflags[4 * g + (jj >> 2)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+    }
+    // publish the taus of V_g (its columns are written), then the flag
     if (tid < 16) q.tau[16 * g + tid] = tid < ncol ? tau_s[tid] : double2{0.0, 0.0};
     __syncthreads();
     if (tid == 0) {
@@ -1372,11 +1381,11 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
 #pragma unroll
   for (int i = 0; i < kQbRows; ++i) pr[i] = double2{lane + 64 * i == row ? 1.0 : 0.0, 0.0};
   for (int k = 0; k < G; ++k) {
-    if (!wait_panel(k)) {
+    if (!wait_flag(&flags[k])) {
       if (tid == 0) atomicOr(status, kStatusBarrierTimeout);
       return;
     }
-    stage(k);
+    stage(k, 0, 16);
     const int ilo = (16 * k) >> 6;  // registers below it hold columns where V_k is zero
     // P_row B_k = P_row H_0 ... H_15, one reflector after the other: P -= tau_a (P v_a) v_a^dag
     if (live)
