@@ -1141,13 +1141,15 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
 // wave's registers (lane l, register i: row l + 64 i). For k = 0 .. g - 1 it waits for panel k
 // (flag) and applies B_k^dag = H_15^dag ... H_0^dag to its columns, reflector by reflector (V_k
 // staged in LDS: one pass over V, where the compact-WY form B_k^dag = I - V_k T_k^dag V_k^dag
-// takes two and an exchange between the waves), then
-// factorises its panel with 16 Householder steps (H_j = I - tau_j v_j v_j^dag, v_j(j) = 1, H_j^dag
-// zeroes column j below row j): at step j the wave of column j + 1 takes H_j^dag and forms the next
-// reflector at once, handing it to the other waves through LDS (two buffers, one barrier per
-// column). V_g (in the panel's own columns of q.X: zeros above the diagonal, 1 on it) and its 16
-// taus (q.tau, 0 for the columns past nx: identity reflectors) are published and the flag raised
-// (release).
+// takes two and an exchange between the waves); panel g - 1 it takes a quarter (4 reflectors) at a
+// time, as that panel publishes them, so that most of this update overlaps its factorisation. Then
+// it factorises its panel with 16 Householder steps (H_j = I - tau_j v_j v_j^dag, v_j(j) = 1,
+// H_j^dag zeroes column j below row j): at step j the wave of column j + 1 takes H_j^dag and forms
+// the next reflector at once, handing it to the other waves through LDS (two buffers, one barrier
+// per column) and writing it to the panel's column of q.X (zeros above the diagonal, 1 on it);
+// after every fourth reflector the quarter's taus are written and its flag raised (release, only
+// when a next panel exists), at the end all 16 taus (q.tau, 0 for the columns past nx: identity
+// reflectors) and the panel flag.
 // Row workgroup b owns rows [16 b, 16 b + 16) of P = B_0 B_1 ... B_{G-1} (one wave per row, the row
 // in registers: lane l, register i: column l + 64 i). It starts from the identity and, as panel k
 // is published, takes P <- P B_k = P H_0 ... H_15 (reflector by reflector: P -= tau (P v) v^dag);
