@@ -528,6 +528,10 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
         bi_[j] = *reinterpret_cast<const VecT*>(Bi + o);
         bs_[j] = br_[j] + bi_[j];
       }
+      // a wave issuing its matrix instructions goes first (the other wave on the SIMD is then
+      // staging or reading fragments): 1 % on the long-range one-site step, 3 % on its
+      // environment update
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int q = 0; q < TT::V; ++q)
 #pragma unroll
@@ -538,6 +542,7 @@ __global__ __launch_bounds__(128 * WGM * KW) void cgemm3m_kernel(GemmDesc g, int
             p2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai_[i][q], bi_[j][q], p2[i][j], 0, 0, 0);
             p3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as_[i][q], bs_[j][q], p3[i][j], 0, 0, 0);
           }
+      __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
   }
