@@ -1849,206 +1849,206 @@ int step_dev(Context& ctx, mpoevo_mps* mps, const mpoevo_mpo* mpo, const mpoevo_
   int graph_use = 0;
   // a second pass (two-site updates throughout) when the mixed step's check below fails
   for (int pass = 0;; ++pass) {
-  if (const int rc = run_step_body(ctx, opts, mps, mpo, ws, Q, prof != nullptr, u1, warm_on, st, body,
-                                   StepPost{&P, &bond_of_visit, &k_slot_of_bond, &last_visit_k_slot, &gflop,
-                                            &one_site, &updates, &graph_use, &visit_kind, &frozen, &mixed},
-                                   two_site_only);
-      rc != MPOEVO_OK)
-    return rc;
+    if (const int rc = run_step_body(ctx, opts, mps, mpo, ws, Q, prof != nullptr, u1, warm_on, st, body,
+                                     StepPost{&P, &bond_of_visit, &k_slot_of_bond, &last_visit_k_slot, &gflop,
+                                              &one_site, &updates, &graph_use, &visit_kind, &frozen, &mixed},
+                                     two_site_only);
+        rc != MPOEVO_OK)
+      return rc;
 
-  if (one_site) {
-    double norm = 0.0;
-    STEP_TRY(hipMemcpyAsync(&norm, nbuf, sizeof(double), hipMemcpyDeviceToHost, st));
-    for (int i = 0; i < L; ++i) {  // the bonds are the guess's: copy phi back whole
-      STEP_TRY(hipMemcpyAsync(mps->site[i], phi(i), sizeof(double2) * (size_t)P[i] * d * P[i + 1],
-                              hipMemcpyDeviceToDevice, st));
+    if (one_site) {
+      double norm = 0.0;
+      STEP_TRY(hipMemcpyAsync(&norm, nbuf, sizeof(double), hipMemcpyDeviceToHost, st));
+      for (int i = 0; i < L; ++i) {  // the bonds are the guess's: copy phi back whole
+        STEP_TRY(hipMemcpyAsync(mps->site[i], phi(i), sizeof(double2) * (size_t)P[i] * d * P[i + 1],
+                                hipMemcpyDeviceToDevice, st));
+      }
+      STEP_TRY(hipStreamSynchronize(st));
+      const int sres = check_solver_dev(ctx, st);
+      if (sres != MPOEVO_OK) return sres;
+      int maxb = 1;
+      for (int b = 0; b <= L; ++b) {
+        mps->bond_dim[b] = P[b];
+        maxb = std::max(maxb, P[b]);
+      }
+      if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->norm = norm;
+        stats->visits = updates;
+        stats->one_site_visits = updates;
+        stats->max_bond = maxb;
+        stats->gflop = gflop;
+        stats->graph = graph_use;
+        if (prof) {
+          struct Agg { int kind; int n; double ms, work; };
+          std::map<const void*, Agg> per_kernel;
+          for (const auto& r : prof->recs) {
+            float ms = 0.f;
+            STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.e0], ctx.dev->events[r.e0 + 1]));
+            const int kind = r.kind == Prof::kGemm ? 1 : r.kind == Prof::kQr ? 3 : 2;
+            if (kind == 1) { stats->t_gemm_ms += ms; stats->gemm_gflop += r.work * 1e-9; stats->n_gemm += 1; }
+            if (kind == 2) { stats->t_wmix_ms += ms; stats->wmix_gbyte += r.work * 1e-9; stats->n_wmix += 1; }
+            Agg& a = per_kernel[r.launch.kernel];
+            a.kind = kind;
+            a.n += 1;
+            a.ms += ms;
+            a.work += r.work * 1e-9;
+          }
+          std::vector<std::pair<const void*, Agg>> order(per_kernel.begin(), per_kernel.end());
+          std::stable_sort(order.begin(), order.end(),
+                           [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
+          for (const auto& kv : order) {
+            if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
+            fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first, kv.second.kind, false,
+                             kv.second.n, kv.second.ms, kv.second.work, st);
+          }
+        }
+      }
+      if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
+      return MPOEVO_OK;
     }
+
+    // read back the kept ranks and statistics (one synchronisation per step)
+    std::vector<int> kh(nvis), swh(nvis), ch(nvis);
+    std::vector<double> dh(nvis), nh(nvis);
+    STEP_TRY(hipMemcpyAsync(swh.data(), sweeps_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
+    STEP_TRY(hipMemcpyAsync(ch.data(), cplt_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
+    std::vector<int> bh(nvis, 0);
+    if (prof) STEP_TRY(hipMemcpyAsync(bh.data(), blocks_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
+    STEP_TRY(hipMemcpyAsync(kh.data(), kbuf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
+    STEP_TRY(hipMemcpyAsync(dh.data(), dbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
+    STEP_TRY(hipMemcpyAsync(nh.data(), nbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
     STEP_TRY(hipStreamSynchronize(st));
     const int sres = check_solver_dev(ctx, st);
     if (sres != MPOEVO_OK) return sres;
+    if (mixed && pass == 0) {
+      // a two-site update that left a frozen bond below its value changed a bond that the one-site
+      // updates next to it took as fixed: the step is redone with two-site updates throughout
+      bool shrunk = false;
+      for (int v = 0; v < nvis && !shrunk; ++v) {
+        const int b = bond_of_visit[v] + 1;
+        shrunk = visit_kind[v] == 2 && frozen[b] && kh[v] < cap_of(b);
+      }
+      if (shrunk) {
+        two_site_only = true;
+        if (prof) {
+          prof->recs.clear();
+          prof->next = 0;
+        }
+        continue;
+      }
+    }
+    std::vector<int> Pact(L + 1, 1);
+    for (int b = 1; b < L; ++b) Pact[b] = k_slot_of_bond[b] >= 0 ? kh[k_slot_of_bond[b]] : P[b];
+    // a bond is taken as rank-deficient when any of its truncations in this step was (near the
+    // onset of the rank deficiency the visits of one bond disagree, and a needless QR costs less
+    // than a completion)
+    std::fill(ctx.warm_deficient.begin(), ctx.warm_deficient.end(), 0);
+    for (int v = 0; v < nvis; ++v)
+      if (ch[v] == 0) ctx.warm_deficient[bond_of_visit[v]] = 1;
+    // compact phi into the caller's site buffers
+    for (int i = 0; i < L; ++i) {
+      const long long n = (long long)Pact[i] * d * Pact[i + 1];
+      // rows beyond Pact[i] are zero; keep a' < Pact[i], b < Pact[i+1] of the padded (P[i], d, P[i+1])
+      hipLaunchKernelGGL(compact_site, dim3(grid_for(n)), dim3(256), 0, st, phi(i),
+                         static_cast<double2*>(mps->site[i]), Pact[i], d, Pact[i + 1], P[i + 1]);
+      STEP_TRY(hipGetLastError());
+    }
+    STEP_TRY(hipStreamSynchronize(st));
+    const double norm = nh[last_visit_k_slot];
     int maxb = 1;
     for (int b = 0; b <= L; ++b) {
-      mps->bond_dim[b] = P[b];
-      maxb = std::max(maxb, P[b]);
+      mps->bond_dim[b] = Pact[b];
+      maxb = std::max(maxb, Pact[b]);
     }
+    if (u1)
+      for (int b = 1; b < L; ++b) std::copy(qch[b].begin(), qch[b].end(), mps->sector_table + (size_t)b * Dmax);
     if (stats) {
-      std::memset(stats, 0, sizeof(*stats));
       stats->norm = norm;
-      stats->visits = updates;
-      stats->one_site_visits = updates;
+      stats->discarded_max = 0.0;
+      stats->discarded_sum = 0.0;
+      for (int v = 0; v < nvis; ++v) {
+        stats->discarded_max = std::max(stats->discarded_max, dh[v]);
+        stats->discarded_sum += dh[v];
+      }
+      stats->visits = nvis;
+      stats->one_site_visits = 0;
+      for (int v = 0; v < nvis; ++v) stats->one_site_visits += mixed && visit_kind[v] == 1 ? 1 : 0;
+      stats->two_site_redo = two_site_only ? 1 : 0;
       stats->max_bond = maxb;
       stats->gflop = gflop;
+      stats->svd_sweeps_max = ctx.max_sweeps;
+      stats->svd_sweeps_total = 0;
+      for (int& c : stats->svd_sweeps_hist) c = 0;
+      for (int v = 0; v < nvis; ++v) {
+        stats->svd_sweeps_total += swh[v];
+        stats->svd_sweeps_hist[std::min(std::max(swh[v], 0), 31)] += 1;
+      }
+      stats->t_jacobi_ms = stats->jacobi_gflop = stats->t_gemm_ms = stats->gemm_gflop = 0.0;
+      stats->t_wmix_ms = stats->wmix_gbyte = 0.0;
+      stats->n_jacobi = stats->n_gemm = stats->n_wmix = 0;
+      stats->n_kernel_stats = 0;
       stats->graph = graph_use;
+      stats->guess = zip ? 1 : 0;
       if (prof) {
-        struct Agg { int kind; int n; double ms, work; };
-        std::map<const void*, Agg> per_kernel;
+        const std::vector<int>& sw = swh;
+        struct Agg { int kind; int split; int n; double ms, work; };
+        std::map<std::pair<const void*, int>, Agg> per_kernel;
+        auto add = [&](const void* k, int kind, bool split, double ms, double work) {
+          Agg& a = per_kernel[{k, split ? 1 : 0}];
+          a.kind = kind;
+          a.split = split ? 1 : 0;
+          a.n += 1;
+          a.ms += ms;
+          a.work += work;
+        };
+        for (const auto& r : jac_recs) {
+          float ms = 0.f;
+          STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.ev], ctx.dev->events[r.ev + 1]));
+          const double gf = sw[r.slot] * svd_sweep_flop(svd_jacobi_plan(r.plan), bh[r.slot]) * 1e-9;
+          stats->t_jacobi_ms += ms;
+          stats->jacobi_gflop += gf;
+          stats->n_jacobi += 1;
+          add(r.kernel, 0, false, ms, gf);
+        }
         for (const auto& r : prof->recs) {
           float ms = 0.f;
           STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.e0], ctx.dev->events[r.e0 + 1]));
-          const int kind = r.kind == Prof::kGemm ? 1 : r.kind == Prof::kQr ? 3 : 2;
-          if (kind == 1) { stats->t_gemm_ms += ms; stats->gemm_gflop += r.work * 1e-9; stats->n_gemm += 1; }
-          if (kind == 2) { stats->t_wmix_ms += ms; stats->wmix_gbyte += r.work * 1e-9; stats->n_wmix += 1; }
-          Agg& a = per_kernel[r.launch.kernel];
-          a.kind = kind;
-          a.n += 1;
-          a.ms += ms;
-          a.work += r.work * 1e-9;
+          if (r.kind == Prof::kGemm) {
+            stats->t_gemm_ms += ms;
+            stats->gemm_gflop += r.work * 1e-9;
+            stats->n_gemm += 1;
+            add(r.launch.kernel, 1, r.launch.split, ms, r.work * 1e-9);
+          } else if (r.kind == Prof::kQr) {
+            add(r.launch.kernel, 3, false, ms, r.work * 1e-9);
+          } else {
+            stats->t_wmix_ms += ms;
+            stats->wmix_gbyte += r.work * 1e-9;
+            stats->n_wmix += 1;
+            add(r.launch.kernel, 2, false, ms, r.work * 1e-9);
+          }
         }
-        std::vector<std::pair<const void*, Agg>> order(per_kernel.begin(), per_kernel.end());
+        std::vector<std::pair<std::pair<const void*, int>, Agg>> order(per_kernel.begin(), per_kernel.end());
         std::stable_sort(order.begin(), order.end(),
                          [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
         for (const auto& kv : order) {
           if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
-          fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first, kv.second.kind, false,
-                           kv.second.n, kv.second.ms, kv.second.work, st);
+          fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first.first, kv.second.kind,
+                           kv.second.split != 0, kv.second.n, kv.second.ms, kv.second.work, st);
         }
       }
     }
     if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
+    if (warm_on) {
+      static std::atomic<unsigned long long> next_token{1};
+      ctx.warm_token = next_token.fetch_add(1);
+      STEP_TRY(hipMemcpyAsync(token_front, &ctx.warm_token, sizeof(ctx.warm_token), hipMemcpyHostToDevice, st));
+      STEP_TRY(hipMemcpyAsync(token_dev, &ctx.warm_token, sizeof(ctx.warm_token), hipMemcpyHostToDevice, st));
+      STEP_TRY(hipStreamSynchronize(st));
+      ctx.warm_ws = ws;
+      std::copy(sig, sig + 5, ctx.warm_sig);
+    }
     return MPOEVO_OK;
-  }
-
-  // read back the kept ranks and statistics (one synchronisation per step)
-  std::vector<int> kh(nvis), swh(nvis), ch(nvis);
-  std::vector<double> dh(nvis), nh(nvis);
-  STEP_TRY(hipMemcpyAsync(swh.data(), sweeps_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
-  STEP_TRY(hipMemcpyAsync(ch.data(), cplt_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
-  std::vector<int> bh(nvis, 0);
-  if (prof) STEP_TRY(hipMemcpyAsync(bh.data(), blocks_buf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
-  STEP_TRY(hipMemcpyAsync(kh.data(), kbuf, sizeof(int) * nvis, hipMemcpyDeviceToHost, st));
-  STEP_TRY(hipMemcpyAsync(dh.data(), dbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
-  STEP_TRY(hipMemcpyAsync(nh.data(), nbuf, sizeof(double) * nvis, hipMemcpyDeviceToHost, st));
-  STEP_TRY(hipStreamSynchronize(st));
-  const int sres = check_solver_dev(ctx, st);
-  if (sres != MPOEVO_OK) return sres;
-  if (mixed && pass == 0) {
-    // a two-site update that left a frozen bond below its value changed a bond that the one-site
-    // updates next to it took as fixed: the step is redone with two-site updates throughout
-    bool shrunk = false;
-    for (int v = 0; v < nvis && !shrunk; ++v) {
-      const int b = bond_of_visit[v] + 1;
-      shrunk = visit_kind[v] == 2 && frozen[b] && kh[v] < cap_of(b);
-    }
-    if (shrunk) {
-      two_site_only = true;
-      if (prof) {
-        prof->recs.clear();
-        prof->next = 0;
-      }
-      continue;
-    }
-  }
-  std::vector<int> Pact(L + 1, 1);
-  for (int b = 1; b < L; ++b) Pact[b] = k_slot_of_bond[b] >= 0 ? kh[k_slot_of_bond[b]] : P[b];
-  // a bond is taken as rank-deficient when any of its truncations in this step was (near the
-  // onset of the rank deficiency the visits of one bond disagree, and a needless QR costs less
-  // than a completion)
-  std::fill(ctx.warm_deficient.begin(), ctx.warm_deficient.end(), 0);
-  for (int v = 0; v < nvis; ++v)
-    if (ch[v] == 0) ctx.warm_deficient[bond_of_visit[v]] = 1;
-  // compact phi into the caller's site buffers
-  for (int i = 0; i < L; ++i) {
-    const long long n = (long long)Pact[i] * d * Pact[i + 1];
-    // rows beyond Pact[i] are zero; keep a' < Pact[i], b < Pact[i+1] of the padded (P[i], d, P[i+1])
-    hipLaunchKernelGGL(compact_site, dim3(grid_for(n)), dim3(256), 0, st, phi(i),
-                       static_cast<double2*>(mps->site[i]), Pact[i], d, Pact[i + 1], P[i + 1]);
-    STEP_TRY(hipGetLastError());
-  }
-  STEP_TRY(hipStreamSynchronize(st));
-  const double norm = nh[last_visit_k_slot];
-  int maxb = 1;
-  for (int b = 0; b <= L; ++b) {
-    mps->bond_dim[b] = Pact[b];
-    maxb = std::max(maxb, Pact[b]);
-  }
-  if (u1)
-    for (int b = 1; b < L; ++b) std::copy(qch[b].begin(), qch[b].end(), mps->sector_table + (size_t)b * Dmax);
-  if (stats) {
-    stats->norm = norm;
-    stats->discarded_max = 0.0;
-    stats->discarded_sum = 0.0;
-    for (int v = 0; v < nvis; ++v) {
-      stats->discarded_max = std::max(stats->discarded_max, dh[v]);
-      stats->discarded_sum += dh[v];
-    }
-    stats->visits = nvis;
-    stats->one_site_visits = 0;
-    for (int v = 0; v < nvis; ++v) stats->one_site_visits += mixed && visit_kind[v] == 1 ? 1 : 0;
-    stats->two_site_redo = two_site_only ? 1 : 0;
-    stats->max_bond = maxb;
-    stats->gflop = gflop;
-    stats->svd_sweeps_max = ctx.max_sweeps;
-    stats->svd_sweeps_total = 0;
-    for (int& c : stats->svd_sweeps_hist) c = 0;
-    for (int v = 0; v < nvis; ++v) {
-      stats->svd_sweeps_total += swh[v];
-      stats->svd_sweeps_hist[std::min(std::max(swh[v], 0), 31)] += 1;
-    }
-    stats->t_jacobi_ms = stats->jacobi_gflop = stats->t_gemm_ms = stats->gemm_gflop = 0.0;
-    stats->t_wmix_ms = stats->wmix_gbyte = 0.0;
-    stats->n_jacobi = stats->n_gemm = stats->n_wmix = 0;
-    stats->n_kernel_stats = 0;
-    stats->graph = graph_use;
-    stats->guess = zip ? 1 : 0;
-    if (prof) {
-      const std::vector<int>& sw = swh;
-      struct Agg { int kind; int split; int n; double ms, work; };
-      std::map<std::pair<const void*, int>, Agg> per_kernel;
-      auto add = [&](const void* k, int kind, bool split, double ms, double work) {
-        Agg& a = per_kernel[{k, split ? 1 : 0}];
-        a.kind = kind;
-        a.split = split ? 1 : 0;
-        a.n += 1;
-        a.ms += ms;
-        a.work += work;
-      };
-      for (const auto& r : jac_recs) {
-        float ms = 0.f;
-        STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.ev], ctx.dev->events[r.ev + 1]));
-        const double gf = sw[r.slot] * svd_sweep_flop(svd_jacobi_plan(r.plan), bh[r.slot]) * 1e-9;
-        stats->t_jacobi_ms += ms;
-        stats->jacobi_gflop += gf;
-        stats->n_jacobi += 1;
-        add(r.kernel, 0, false, ms, gf);
-      }
-      for (const auto& r : prof->recs) {
-        float ms = 0.f;
-        STEP_TRY(hipEventElapsedTime(&ms, ctx.dev->events[r.e0], ctx.dev->events[r.e0 + 1]));
-        if (r.kind == Prof::kGemm) {
-          stats->t_gemm_ms += ms;
-          stats->gemm_gflop += r.work * 1e-9;
-          stats->n_gemm += 1;
-          add(r.launch.kernel, 1, r.launch.split, ms, r.work * 1e-9);
-        } else if (r.kind == Prof::kQr) {
-          add(r.launch.kernel, 3, false, ms, r.work * 1e-9);
-        } else {
-          stats->t_wmix_ms += ms;
-          stats->wmix_gbyte += r.work * 1e-9;
-          stats->n_wmix += 1;
-          add(r.launch.kernel, 2, false, ms, r.work * 1e-9);
-        }
-      }
-      std::vector<std::pair<std::pair<const void*, int>, Agg>> order(per_kernel.begin(), per_kernel.end());
-      std::stable_sort(order.begin(), order.end(),
-                       [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
-      for (const auto& kv : order) {
-        if (stats->n_kernel_stats >= MPOEVO_MAX_KERNEL_STATS) break;
-        fill_kernel_stat(stats->kernel_stats[stats->n_kernel_stats++], kv.first.first, kv.second.kind,
-                         kv.second.split != 0, kv.second.n, kv.second.ms, kv.second.work, st);
-      }
-    }
-  }
-  if (!std::isfinite(norm)) { ctx.err = "step: fitted norm is not finite"; return MPOEVO_ENONFINITE; }
-  if (warm_on) {
-    static std::atomic<unsigned long long> next_token{1};
-    ctx.warm_token = next_token.fetch_add(1);
-    STEP_TRY(hipMemcpyAsync(token_front, &ctx.warm_token, sizeof(ctx.warm_token), hipMemcpyHostToDevice, st));
-    STEP_TRY(hipMemcpyAsync(token_dev, &ctx.warm_token, sizeof(ctx.warm_token), hipMemcpyHostToDevice, st));
-    STEP_TRY(hipStreamSynchronize(st));
-    ctx.warm_ws = ws;
-    std::copy(sig, sig + 5, ctx.warm_sig);
-  }
-  return MPOEVO_OK;
   }
 #undef STEP_TRY
 }
