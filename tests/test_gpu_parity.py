@@ -799,7 +799,8 @@ def test_tile_tuner(mp, handle):
         handle.set_tuning(mp.TUNE_OFF, clear=True)
 
 
-ONE_SITE_CASES = [(8, 8, 2), (12, 16, 2), (10, 32, 3), (9, 256, 1)]  # L, Dmax (bonds at their cap), order
+ONE_SITE_CASES = [(8, 8, 2), (12, 16, 2), (10, 32, 3), (9, 256, 1),
+                  (18, 256, 2)]  # L, Dmax (bonds at their cap), order; the last at the full QR width (512 x 256)
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
