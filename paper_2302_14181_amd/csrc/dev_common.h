@@ -43,6 +43,13 @@ hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t 
 // them, else 0. Only the FP32 three-product path splits.
 int gemm_row_tail(const GemmDesc& g, bool fp64);
 
+// Where to cut a product so that its whole rounds of workgroups (kMinWgs tiles each) run in one
+// launch and the few tiles of a last, mostly empty round in a second one, which the planner then
+// gives a smaller tile or split K: dim 0 no cut, 1 rows [at, M), 2 columns [at, N), 3 batch
+// entries [at, batch) go to the second launch. Only the FP32 three-product path on its own tile
+// rule (no K split) is cut, when the last round would hold at most half of its tiles.
+void gemm_round_tail(const GemmDesc& g, bool fp64, int& dim, long long& at);
+
 // Host function of the kernel this thread launched last among the timed kernel classes (the
 // products' main kernel, the W contractions, the Jacobi kernel) and whether a split-K sum
 // followed it: a profiled step names each timed launch by it.

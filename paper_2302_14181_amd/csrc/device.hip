@@ -254,6 +254,39 @@ hipError_t gemm_timed(const GemmDesc& g, Arith ar, bool out_fp64, hipStream_t st
     t.A = static_cast<const unsigned char*>(g.A) + sizeof(float2) * (size_t)h.M * g.sAm;
     t.C = static_cast<unsigned char*>(g.C) + (out_fp64 ? sizeof(double2) : sizeof(float2)) * (size_t)h.M * g.sCm;
   }
+  // tiles that would run as a last, mostly empty round of workgroups go to a launch of their own
+  // (which then takes a smaller tile or splits K)
+  int cut = 0;
+  long long at = 0;
+  if (tail == 0) gemm_round_tail(h, ar.fp64, cut, at);
+  if (cut != 0) {
+    const size_t ci = sizeof(float2), co = out_fp64 ? sizeof(double2) : sizeof(float2);
+    GemmDesc u = h;
+    if (cut == 1) {
+      h.M = (int)at;
+      u.M -= (int)at;
+      u.A = static_cast<const unsigned char*>(g.A) + ci * (size_t)(at * g.sAm);
+      u.C = static_cast<unsigned char*>(g.C) + co * (size_t)(at * g.sCm);
+    } else if (cut == 2) {
+      h.N = (int)at;
+      u.N -= (int)at;
+      u.B = static_cast<const unsigned char*>(g.B) + ci * (size_t)(at * g.sBn);
+      u.C = static_cast<unsigned char*>(g.C) + co * (size_t)(at * g.sCn);
+    } else {
+      h.batch = (int)at;
+      u.batch -= (int)at;
+      u.A = static_cast<const unsigned char*>(g.A) + ci * (size_t)(at * g.bA);
+      u.B = static_cast<const unsigned char*>(g.B) + ci * (size_t)(at * g.bB);
+      u.C = static_cast<unsigned char*>(g.C) + co * (size_t)(at * g.bC);
+    }
+    PROF_BEGIN(pr, tok);
+    MPOEVO_HIP_TRY(gemm_launch(h, ar.fp64, out_fp64, st));
+    PROF_END(pr, tok, Prof::kGemm, gemm_flop(h));
+    PROF_BEGIN(pr, tok3);
+    MPOEVO_HIP_TRY(gemm_launch(u, ar.fp64, out_fp64, st));
+    PROF_END(pr, tok3, Prof::kGemm, gemm_flop(u));
+    return hipSuccess;
+  }
   PROF_BEGIN(pr, tok);
   MPOEVO_HIP_TRY(gemm_launch(h, ar.fp64, out_fp64, st));
   PROF_END(pr, tok, Prof::kGemm, gemm_flop(h));

@@ -1254,6 +1254,29 @@ int gemm_row_tail(const GemmDesc& g, bool fp64) {
   return (g.M > p.bm && rem > 0 && 2 * rem <= p.bm && rem <= 64 && tail_rows < p.bm) ? rem : 0;
 }
 
+void gemm_round_tail(const GemmDesc& g, bool fp64, int& dim, long long& at) {
+  dim = 0;
+  at = 0;
+  if (fp64 || g.bf16x3 || g.row_tail || g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  const Plan p = make_plan<MfmaF32>(g, k3mCfg, 4);
+  if (p.splits != 1) return;
+  const long long tm = (g.M + p.bm - 1) / p.bm, tn = (g.N + p.bn - 1) / p.bn;
+  const long long t = tm * tn * g.batch, r = t % kMinWgs;
+  if (t <= kMinWgs || r == 0 || 2 * r > kMinWgs) return;
+  // the cut removes exactly the r tiles of the last round: whole batch entries, else whole
+  // column blocks of every entry, else whole row blocks
+  if (g.batch > 1 && r % (tm * tn) == 0) {
+    dim = 3;
+    at = g.batch - r / (tm * tn);
+  } else if (r % (tm * g.batch) == 0 && r / (tm * g.batch) < tn) {
+    dim = 2;
+    at = (tn - r / (tm * g.batch)) * p.bn;
+  } else if (r % (tn * g.batch) == 0 && r / (tn * g.batch) < tm) {
+    dim = 1;
+    at = (tm - r / (tn * g.batch)) * p.bm;
+  }
+}
+
 hipError_t gemm_launch(const GemmDesc& g, bool fp64, bool out_fp64, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
