@@ -76,7 +76,7 @@ constexpr int kKGrain = 8;      // split-K chunks are multiples of this
 constexpr int kMinWgs = 256;    // a tile giving at least this many workgroups is used as is
 constexpr int kTargetWgs = 256; // split K up to this many workgroups (one per compute unit:
                                 // more splits cost more in the reduction than they gain)
-constexpr int kMaxSplits = 16;
+constexpr int kMaxSplits = 32;  // (the one-site local tensor at D = 256, w = 271: 128 x 128 tiles, 32 splits)
 constexpr int kMinSplitK = 32;  // complex K per split, at least
 
 // LDS staging: A as rows [m][k] and the expanded B as columns [n][k] (real k), each row of
