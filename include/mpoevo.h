@@ -54,7 +54,7 @@ enum {
   MPOEVO_EHIP = -4,         /* a HIP runtime call failed */
   MPOEVO_ESOLVER = -5,      /* the FP64 SVD did not converge or a device wait timed out */
   MPOEVO_ENONFINITE = -6,   /* non-finite input (H blocks, tau) or non-finite matrix in truncate */
-  MPOEVO_EUNSUPPORTED = -7  /* valid request this build does not implement */
+  MPOEVO_EUNSUPPORTED = -7  /* valid request the library does not implement */
 };
 
 enum { MPOEVO_FP64 = 0, MPOEVO_FP32 = 1, MPOEVO_BF16X3 = 2 };
