@@ -3,13 +3,17 @@
 Workload (default, --workload lr3): the long-range Ising chain H = -sum_{i<j} J(j-i) Z_i Z_j - g sum X_i
 with J(r) = r^-2 fitted as six exponentials (tests/golden/lr_fit_K6.json), g = 1, L = 100, the
 order-3 extended MPO (w = 271) of exp(-i tau H), tau = 0.1, bond dimension D <= 256, cutoff
-1e-14 sigma_1, two sweeps of two-site updates per step, from the all-up product state: K time steps
-from t = 0 (default K = 20) after W untimed warm-up steps of the same trajectory on their own state
-(default W = 2). Contractions on the FP32 matrix cores (--prec), the SVD truncation in FP64. The
-bonds reach D = 256 at step 3. `value` is the mean seconds per step over the K timed steps (HIP
-events on the launch stream around each step; every step ends with a synchronisation).
+1e-14 sigma_1, two sweeps per step (two-site updates while the bonds grow, one-site updates at the
+bonds already at their largest value; --nsites), from the all-up product state: K time steps from
+t = 0 (default K = 20) after W untimed warm-up steps of the same trajectory on their own state
+(default W = 2). Contractions on the FP32 matrix cores (--prec), the SVD truncation and the QR in
+FP64. The bonds reach D = 256 at step 3. A step whose plan the handle has seen before (the warm-up
+steps are the first sightings) is captured into a HIP graph and replayed (--no-graph: kernel by
+kernel); the kernel table comes from the same K steps run again launch by launch. `value` is the
+mean seconds per step over the K timed steps (HIP events on the launch stream around each step;
+every step ends with a synchronisation).
 
-Also on the line: the plain FP64 path on the same K opening steps (time ratio, and the two
+Also on the line: the plain FP64 path (kernel by kernel) on the same K opening steps (time ratio, and the two
 trajectories' infidelity and <Z_50> after them); per-step parity against the CPU oracle on the
 opening steps: step 1 from all-up on every precision (R17-A infidelity 1 - |<phi_gpu|phi_oracle>|^2
 and R17-B |eps_gpu - eps_oracle|, eps = 1 - |<phi|W psi>|^2 / ||W psi||^2) and step 2 restarted from
@@ -54,7 +58,7 @@ chain's MPO (w = 271, default 10 calls), whose products are the default line's d
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64|bf16x3] [--fp64-steps N]
                        [--no-cpu] [--no-fp64] [--no-delta2] [--no-side] [--nsites -1|1|2]
-                       [--guess canonical|zipup|auto] [--graph] [--tune] [--env-w 8|271]
+                       [--guess canonical|zipup|auto] [--graph] [--no-graph] [--tune] [--env-w 8|271]
                        [--workload lr3|quench|xxz|batched|env|split|thermal|cylinder|copy]
                        [--order N] [--tau T] [--quiet]
 """
@@ -386,7 +390,9 @@ def run_lr3(args, torch, mp, wl, h):
     psi0 = wl.all_up(LR_L)
     prog = "lr3" if args.progress else None
     ns = args.nsites
-    gs, gr = guess_of(mp, args), args.graph
+    # a step whose plan the handle has seen before (the warm-up steps are the first sightings) is
+    # captured into a HIP graph and replayed, unless --no-graph
+    gs, gr = guess_of(mp, args), not args.no_graph
     # the environment microbenchmark first, on a device that has not yet run minutes of work
     envmb = None if args.no_side else env_microbench_summary(mp, h, torch)
     # the tile tuner times the products of the shapes the warm-up steps meet and keeps the fastest
@@ -401,6 +407,7 @@ def run_lr3(args, torch, mp, wl, h):
         h.set_tuning(mp.TUNE_FROZEN)
     ms, st, dm = trajectory(torch, mp, h, psi0, dw, prec, K, LR_D, profile=not gr, progress=prog, nsites=ns,
                             guess=gs, use_graph=gr)
+    graph_steps = [i + 1 for i, x in enumerate(st) if x.graph]
     if gr:  # the kernel table from the same steps profiled launch by launch (untimed)
         _, st, dmp = trajectory(torch, mp, h, psi0, dw, prec, K, LR_D, profile=True, nsites=ns, guess=gs)
         del dmp
@@ -426,7 +433,8 @@ def run_lr3(args, torch, mp, wl, h):
         ms64, st64, dm64 = trajectory(torch, mp, h, psi0, dw, mp.FP64, n64, LR_D, profile=True,
                                       progress=prog and prog + " fp64", nsites=ns, guess=gs)
         p64 = {k: float(sum(x.profile[k] for x in st64)) for k in st64[0].profile if k != "kernels"}
-        fp64 = {"steps": n64, "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
+        fp64 = {"steps": n64, "launches": "kernel by kernel, each timed (no graphs)",
+                "fp64_s_per_step": float(np.sum(ms64)) / 1e3 / n64,
                 "fp32_s_per_step_same_steps": float(np.sum(ms[:n64])) / 1e3 / n64,
                 "fp64_gemm_tflops": p64["gemm_gflop"] / p64["t_gemm_ms"] if p64["t_gemm_ms"] > 0 else 0.0,
                 "fp64_jacobi_share": p64["t_jacobi_ms"] / max(float(np.sum(ms64)), 1e-9),
@@ -467,6 +475,7 @@ def run_lr3(args, torch, mp, wl, h):
                                f"{', steps replayed from HIP graphs' if gr else ''}, steps 1..{K} from t=0",
                    "L": LR_L, "D": LR_D, "order": LR_ORDER, "tau": LR_TAU, "w": w},
         "step_ms": ms,
+        "graph_steps": graph_steps if gr else None,
         "tile_tuner": ({"mode": "timed the product plans of the warm-up steps' shapes (FP32 and FP64 each), "
                                 "frozen for the timed steps", "entries": h.product_plan(prec, 1, 1, 1)["entries"]}
                        if tune else None),
@@ -1033,8 +1042,11 @@ def main():
                     help="lr3 and quench: the sweeps' starting point (psi, the zip-up of W psi, or the zip-up "
                          "while the bonds grow)")
     ap.add_argument("--graph", action="store_true",
-                    help="lr3, quench and batched: replay each step's launches from a captured HIP graph once its "
-                         "plan repeats")
+                    help="quench and batched: replay each step's launches from a captured HIP graph once its "
+                         "plan repeats (lr3 does by default)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="lr3: launch every step's kernels one by one instead of replaying a step whose plan was "
+                         "seen before from its captured HIP graph")
     ap.add_argument("--order", type=int, default=ORDER, choices=[1, 2, 3, 4],
                     help="MPO order of the TFIM workloads (quench, split reference, thermal)")
     ap.add_argument("--tau", type=float, default=TAU, help="time step of the quench and split workloads")
