@@ -1142,16 +1142,18 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
 // k = 0 .. g - 1 it waits for panel k (flag) and applies B_k^dag = H_{P-1}^dag ... H_0^dag to its
 // columns, reflector by reflector (V_k staged in LDS: one pass over V, where the compact-WY form
 // B_k^dag = I - V_k T_k^dag V_k^dag takes two and an exchange between the waves); panel g - 1 it
-// takes 4 reflectors at a time, as that panel publishes them, so that most of this update overlaps
-// its factorisation. Then it factorises its panel with P Householder steps (H_j = I - tau_j v_j
+// takes kQbGroup reflectors at a time, as that panel publishes them, so that most of this update
+// overlaps its factorisation. Then it factorises its panel with P Householder steps (H_j = I - tau_j v_j
 // v_j^dag, v_j(j) = 1, H_j^dag zeroes column j below row j): at step j the wave of column j + 1
 // takes H_j^dag and forms the next reflector at once, handing it to the other waves through LDS
 // (two buffers, one barrier per column) and writing it to the panel's column of q.X (zeros above
-// the diagonal, 1 on it); after every fourth reflector their taus are written and a flag raised
-// (release, only when a next panel exists), at the end all P taus (q.tau, 0 for the columns past
-// nx: identity reflectors) and the panel flag. Panels of 8 columns: the column step has fewer
+// the diagonal, 1 on it); after every kQbGroup-th reflector their taus are written and a flag
+// raised (release, only when a next panel exists), at the end all P taus (q.tau, 0 for the columns
+// past nx: identity reflectors) and the panel flag. Panels of 8 columns: the column step has fewer
 // waves reading each reflector and sharing the SIMDs than with 16, and the chain of panel
-// hand-offs stays short (0.45 ms per 512 x 256 QR against 0.53 ms with 16 and 0.71 ms with 4).
+// hand-offs stays short (0.45 ms per 512 x 256 QR against 0.53 ms with 16 and 0.71 ms with 4);
+// groups of 2 reflectors leave less of the previous panel for after its last flag (0.43 ms
+// against 0.45 ms with groups of 4).
 // Row workgroup b owns rows [16 b, 16 b + 16) of P_Q = B_0 B_1 ... B_{G-1} (one wave per row, the
 // row in registers: lane l, register i: column l + 64 i). It starts from the identity and, as panel
 // k is published, takes P_Q <- P_Q B_k = P_Q H_0 ... H_{P-1} (reflector by reflector: P_Q -= tau
@@ -1162,7 +1164,8 @@ __global__ __launch_bounds__(1024) void svd_qrperm_kernel(SvdPlan p, SvdWs w) {
 constexpr int kQbThreads = 1024;
 constexpr int kQbRows = 8;    // entries of a 512-long column (or row) per lane
 constexpr int kQbPanel = 8;   // columns per panel workgroup (one wave each; at most 16)
-constexpr int kQbQuarters = kQbPanel / 4;  // groups of 4 reflectors a panel publishes one by one
+constexpr int kQbGroup = 2;                 // reflectors per group a panel publishes for the next one (>= 2)
+constexpr int kQbQuarters = kQbPanel / kQbGroup;  // groups per panel
 // Workspace of the blocked QR: X (mx x kQbPanel G, column-major, the columns past nx zero), the
 // panels' taus (G x kQbPanel), G panel flags, an abort word, then kQbQuarters G flags (panel g's
 // reflectors 4 q .. 4 q + 3 published).
@@ -1240,7 +1243,7 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
     return abort_s == 0;
   };
   // reflectors a0 .. a0 + na - 1 of panel k (rows from kQbPanel k on; the rows above are zero)
-  // into vs[a][r], their taus into tk[a] (na = 4 or kQbPanel)
+  // into vs[a][r], their taus into tk[a] (na = kQbGroup or kQbPanel)
   auto stage = [&](int k, int a0, int na) {
     const double2* V = X + (long long)(kQbPanel * k) * m;
     for (int s = 0; s < na / 2; ++s) {
@@ -1363,12 +1366,13 @@ __global__ __launch_bounds__(kQbThreads) void qr_blocked_kernel(SvdPlan p, QbWs 
         if (wv == jj + 1) form(wv, buf ^ 1);
       }
       __syncthreads();
-      // reflectors jj - 2 .. jj + 1 formed (their columns written above): a quarter for the next
-      // panel, which has one only if this panel is full
-      if (g + 1 < G && (jj & 3) == 2 && tid == 0) {
-        for (int t = jj - 2; t <= jj + 1; ++t) q.tau[kQbPanel * g + t] = tau_s[t];
+      // reflectors jj + 2 - kQbGroup .. jj + 1 formed (their columns written above): a group for
+      // the next panel, which has one only if this panel is full
+      if (g + 1 < G && (jj + 2) % kQbGroup == 0 && tid == 0) {
+        for (int t = jj + 2 - kQbGroup; t <= jj + 1; ++t) q.tau[kQbPanel * g + t] = tau_s[t];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&qflags[kQbQuarters * g + (jj >> 2)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&qflags[kQbQuarters * g + (jj + 1) / kQbGroup], 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     // publish the taus of V_g (its columns are written), then the flag
